@@ -1,0 +1,629 @@
+/* CPU reference for event-driven e-prop: TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain serial FP64 C, built with -O2 -ffp-contract=off so that every
+ * multiply and add rounds on its own.  Nothing here is blocked, fused or
+ * reordered beyond what the paper's equations and algorithms state.
+ * Equation names refer to the paper's labels (Methods and Supplementary
+ * Information).  Readings of points the paper leaves open:
+ *   - a spike is emitted iff v >= threshold (the Heaviside tie spikes);
+ *   - refractoriness (not in the equations): after a spike at t_s the
+ *     neuron cannot spike and has psi = 0 at steps t_s+1 .. t_s+n_ref, while
+ *     v keeps integrating, reset included;
+ *   - the reset subtracts the current adaptive threshold v_th + beta_a a^t;
+ *   - psi multiplies both eligibility components, e = psi (eps_v - beta_a eps_a)
+ *     (eq. filtered-eligibility-trace; the brace in eq. gradient-rec is read
+ *     the same way);
+ *   - the output gradient is sum_t E_k^t F_kappa(z_j^t)
+ *     (eq. eprop-output-new-subs-rewritten with d = 0);
+ *   - the learning window multiplies E (and so L); loss terms outside it are 0;
+ *   - every synapse sees its presynaptic spike train delayed by its own
+ *     delay D >= 1; inputs enter exactly like recurrent sources;
+ *   - the input current sums the arriving input synapses in ascending source
+ *     order, then the arriving recurrent synapses in ascending source order.
+ */
+#include "eprop_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int kind;      /* 0 input, 1 recurrent */
+  int src;
+  int delay;
+  long idx;      /* index into the projection's arrays */
+} in_syn;
+
+typedef struct {
+  double alpha, kappa, rho;  /* exact-integration propagators */
+  int n_ref;
+  int max_delay;
+  long *in_ptr;              /* [J+1] incoming synapses per target, canonical order */
+  in_syn *syn;
+} prep_t;
+
+static void prep_free(prep_t *p) {
+  free(p->in_ptr);
+  free(p->syn);
+}
+
+/* Propagators of eq. lif_update, eq. spike-threshold-adaptation and
+ * eq. leaky_integrator: alpha = exp(-dt/tau_m), rho = exp(-dt/tau_a),
+ * kappa = exp(-dt/tau_out). */
+static int prep_init(const orc_net *net, prep_t *p) {
+  const int J = net->n_rec;
+  memset(p, 0, sizeof(*p));
+  p->alpha = exp(-net->dt / net->tau_m);
+  p->kappa = exp(-net->dt / net->tau_out);
+  p->rho = exp(-net->dt / net->tau_a);
+  p->n_ref = (int)lround(net->t_ref / net->dt);
+  p->in_ptr = (long *)calloc((size_t)J + 1, sizeof(long));
+  long total = net->in.nnz + net->rec.nnz;
+  p->syn = (in_syn *)malloc(sizeof(in_syn) * (size_t)(total > 0 ? total : 1));
+  long *fill = (long *)calloc((size_t)J + 1, sizeof(long));
+  if (!p->in_ptr || !p->syn || !fill) { free(fill); prep_free(p); return -1; }
+  const orc_proj *pr[2] = {&net->in, &net->rec};
+  for (int kind = 0; kind < 2; ++kind)
+    for (long q = 0; q < pr[kind]->nnz; ++q) {
+      unsigned int j = pr[kind]->col[q];
+      if ((int)j >= J || pr[kind]->delay[q] < 1) { free(fill); prep_free(p); return -1; }
+      p->in_ptr[j + 1]++;
+      if (pr[kind]->delay[q] > p->max_delay) p->max_delay = pr[kind]->delay[q];
+    }
+  for (int j = 0; j < J; ++j) p->in_ptr[j + 1] += p->in_ptr[j];
+  /* sources visited in ascending order, inputs first: lists come out canonical */
+  for (int kind = 0; kind < 2; ++kind)
+    for (int i = 0; i < pr[kind]->n_src; ++i)
+      for (unsigned long q = pr[kind]->row_ptr[i]; q < pr[kind]->row_ptr[i + 1]; ++q) {
+        unsigned int j = pr[kind]->col[q];
+        in_syn *s = &p->syn[p->in_ptr[j] + fill[j]++];
+        s->kind = kind;
+        s->src = i;
+        s->delay = pr[kind]->delay[q];
+        s->idx = (long)q;
+      }
+  free(fill);
+  return 0;
+}
+
+/* Spike records: zin[s*I + i] for emission steps s in [0, T-1];
+ * zrec[t*J + j] for t in [0, T] with row 0 all zero. */
+typedef struct {
+  int T, I, J;
+  unsigned char *zin, *zrec, *zforced;
+} spikes_t;
+
+static int spiked(const spikes_t *sp, int kind, int src, int s) {
+  if (kind == 0) return (s >= 0 && s < sp->T) ? sp->zin[(long)s * sp->I + src] : 0;
+  return (s >= 1 && s <= sp->T) ? sp->zrec[(long)s * sp->J + src] : 0;
+}
+
+static void spikes_free(spikes_t *sp) {
+  free(sp->zin);
+  free(sp->zrec);
+  free(sp->zforced);
+}
+
+static int spikes_init(const orc_net *net, const orc_trial *tr, spikes_t *sp) {
+  memset(sp, 0, sizeof(*sp));
+  sp->T = tr->n_steps;
+  sp->I = net->n_in;
+  sp->J = net->n_rec;
+  sp->zin = (unsigned char *)calloc((size_t)sp->T * (sp->I > 0 ? sp->I : 1), 1);
+  sp->zrec = (unsigned char *)calloc((size_t)(sp->T + 1) * sp->J, 1);
+  if (!sp->zin || !sp->zrec) { spikes_free(sp); return -1; }
+  for (long e = 0; e < tr->n_in_spikes; ++e) {
+    unsigned int s = tr->in_step[e], i = tr->in_src[e];
+    if ((int)s >= sp->T || (int)i >= sp->I) { spikes_free(sp); return -1; }
+    sp->zin[(long)s * sp->I + i] = 1;
+  }
+  if (tr->forced) {
+    sp->zforced = (unsigned char *)calloc((size_t)(sp->T + 1) * sp->J, 1);
+    if (!sp->zforced) { spikes_free(sp); return -1; }
+    for (long e = 0; e < tr->n_forced; ++e) {
+      unsigned int t = tr->forced_step[e], j = tr->forced_neuron[e];
+      if (t < 1 || (int)t > sp->T || (int)j >= sp->J) { spikes_free(sp); return -1; }
+      sp->zforced[(long)t * sp->J + j] = 1;
+    }
+  }
+  return 0;
+}
+
+/* Surrogate gradient: eq. piecewise-linear-surrogate-gradient or
+ * eq. exponential-surrogate-gradient, of the distance to the threshold. */
+static double surrogate(const orc_net *net, double dv) {
+  if (net->surrogate == 1) return net->sg_gamma * exp(-net->sg_beta * fabs(dv));
+  return net->sg_gamma * fmax(0.0, 1.0 - net->sg_beta * fabs(dv));
+}
+
+static double neuron_beta(const orc_net *net, int j) {
+  return (net->is_alif && net->is_alif[j]) ? net->beta_a : 0.0;
+}
+
+/* Input current of neuron j at step t: eq. lif_update's two sums, each
+ * synapse seeing its source delayed by its own delay. */
+static double input_current(const orc_net *net, const prep_t *p, const spikes_t *sp, int j, int t) {
+  double I = 0.0;
+  for (long q = p->in_ptr[j]; q < p->in_ptr[j + 1]; ++q) {
+    const in_syn *s = &p->syn[q];
+    if (spiked(sp, s->kind, s->src, t - s->delay))
+      I = I + (s->kind == 0 ? net->in.w[s->idx] : net->rec.w[s->idx]);
+  }
+  return I;
+}
+
+/* One neuron update at step t (eq. spike-threshold-adaptation, adaptive
+ * threshold, eq. lif_update, eq. binary-spike-state-variable, surrogate). */
+static int neuron_step(const orc_net *net, const prep_t *p, int j, double I, double zprev,
+                       int forced_z, double *v, double *a, int *refr, double *psi) {
+  const double beta = neuron_beta(net, j);
+  *a = p->rho * *a + zprev;
+  const double A = net->v_th + beta * *a;
+  *v = p->alpha * *v + I - zprev * A;
+  const int refractory = *refr > 0;
+  if (refractory) *refr -= 1;
+  int z;
+  if (forced_z >= 0) z = forced_z;
+  else z = (!refractory && *v >= A) ? 1 : 0;
+  *psi = refractory ? 0.0 : surrogate(net, *v - A);
+  if (z) *refr = p->n_ref;
+  return z;
+}
+
+/* One step of a synapse's e-prop recursion (eq. eligibility-vector-substituted,
+ * eq. filtered-eligibility-trace, eq. final-gradient):
+ *   eps_a^t = psi^{t-1} eps_v^{t-1} + (rho - psi^{t-1} beta) eps_a^{t-1}
+ *   eps_v^t = alpha eps_v^{t-1} + x^t                   (F_alpha of the arrivals)
+ *   e^t     = psi^t (eps_v^t - beta eps_a^t)
+ *   ebar^t  = kappa ebar^{t-1} + e^t                    (F_kappa)
+ *   g      += L^t ebar^t                                                       */
+static void syn_step(const prep_t *p, double x, double psi_prev, double psi_now, double beta,
+                     double L, double *ev, double *ea, double *eb, double *g) {
+  const double ea_new = psi_prev * *ev + (p->rho - psi_prev * beta) * *ea;
+  const double ev_new = p->alpha * *ev + x;
+  const double e = psi_now * (ev_new - beta * ea_new);
+  *eb = p->kappa * *eb + e;
+  *ev = ev_new;
+  *ea = ea_new;
+  *g += L * *eb;
+}
+
+/* Readout (eq. leaky_integrator), error signal and loss (eq. mean-squared-error
+ * or eq. softmax + eq. cross-entropy-loss), window-gated. */
+static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp,
+                         const orc_trial *tr, int t, double *y, double *E, double *loss,
+                         double *psum) {
+  const int J = net->n_rec, K = net->n_out;
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int j = 0; j < J; ++j)
+      if (sp->zrec[(long)t * J + j]) s = s + net->w_out[(long)k * J + j];
+    y[k] = p->kappa * y[k] + s;
+  }
+  const int win = tr->window ? tr->window[t - 1] : 1;
+  if (net->loss == 0) {
+    for (int k = 0; k < K; ++k) {
+      const double d = y[k] - tr->target[(long)(t - 1) * K + k];
+      E[k] = win ? d : 0.0;
+      if (win) *loss += 0.5 * d * d;
+    }
+  } else {
+    double mx = y[0];
+    for (int k = 1; k < K; ++k) mx = fmax(mx, y[k]);
+    double se = 0.0;
+    for (int k = 0; k < K; ++k) se += exp(y[k] - mx);
+    for (int k = 0; k < K; ++k) {
+      const double pi = exp(y[k] - mx) / se;
+      E[k] = win ? pi - (k == tr->label ? 1.0 : 0.0) : 0.0;
+      if (win) psum[k] += pi;
+    }
+    if (win) *loss += -(y[tr->label] - mx - log(se));
+  }
+}
+
+static int check_net(const orc_net *net, const orc_trial *tr) {
+  if (!net || !tr || net->n_rec < 1 || net->n_out < 1 || net->n_in < 0 || tr->n_steps < 1) return -1;
+  if (net->in.n_src != net->n_in || net->rec.n_src != net->n_rec) return -1;
+  if (net->loss == 0 && !tr->target) return -1;
+  if (net->loss == 1 && (tr->label < 0 || tr->label >= net->n_out)) return -1;
+  return 0;
+}
+
+int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double *g_in,
+                  double *g_rec, double *g_out, orc_trace *trace, double *loss_out, int *pred) {
+  if (check_net(net, tr)) return -1;
+  prep_t p;
+  if (prep_init(net, &p)) return -1;
+  spikes_t sp;
+  if (spikes_init(net, tr, &sp)) { prep_free(&p); return -1; }
+  const int T = tr->n_steps, I = net->n_in, J = net->n_rec, K = net->n_out;
+  const long nin = net->in.nnz, nrec = net->rec.nnz;
+  int rc = -1;
+
+  double *v = calloc(J, sizeof(double)), *a = calloc(J, sizeof(double));
+  int *refr = calloc(J, sizeof(int));
+  double *y = calloc(K, sizeof(double)), *E = calloc(K, sizeof(double));
+  double *psum = calloc(K, sizeof(double));
+  /* archived histories, row t (row 0 = zero): psi and L per neuron, E per readout */
+  double *psi_h = calloc((size_t)(T + 1) * J, sizeof(double));
+  double *L_h = calloc((size_t)(T + 1) * J, sizeof(double));
+  double *E_h = calloc((size_t)(T + 1) * K, sizeof(double));
+  /* per-synapse traces (eps_v, eps_a, ebar) and, event-driven, the pending arrival */
+  long ns = nin + nrec;
+  double *ev = calloc(ns + 1, sizeof(double)), *ea = calloc(ns + 1, sizeof(double));
+  double *eb = calloc(ns + 1, sizeof(double));
+  int *apr = calloc(ns + 1, sizeof(int));
+  double *zb = calloc(J, sizeof(double));
+  int *apr_o = calloc(J, sizeof(int));
+  int *q_src = calloc(ns + 1, sizeof(int));   /* source of each synapse */
+  if (!v || !a || !refr || !y || !E || !psum || !psi_h || !L_h || !E_h || !ev || !ea || !eb ||
+      !apr || !zb || !apr_o || !q_src)
+    goto done;
+  for (int i = 0; i < net->in.n_src; ++i)
+    for (unsigned long r = net->in.row_ptr[i]; r < net->in.row_ptr[i + 1]; ++r) q_src[r] = i;
+  for (int i = 0; i < net->rec.n_src; ++i)
+    for (unsigned long r = net->rec.row_ptr[i]; r < net->rec.row_ptr[i + 1]; ++r) q_src[nin + (long)r] = i;
+
+  double loss = 0.0;
+  /* per-synapse view: target, source kind, source, delay, weight-gradient slot */
+#define SYN_TGT(q) ((q) < nin ? (int)net->in.col[q] : (int)net->rec.col[(q)-nin])
+#define SYN_G(q) ((q) < nin ? &g_in[q] : &g_rec[(q)-nin])
+
+  for (int t = 1; t <= T; ++t) {
+    /* neurons (time-driven) */
+    for (int j = 0; j < J; ++j) {
+      const double I_t = input_current(net, &p, &sp, j, t);
+      const double zprev = sp.zrec[(long)(t - 1) * J + j] ? 1.0 : 0.0;
+      const int fz = sp.zforced ? sp.zforced[(long)t * J + j] : -1;
+      double psi;
+      const int z = neuron_step(net, &p, j, I_t, zprev, fz, &v[j], &a[j], &refr[j], &psi);
+      sp.zrec[(long)t * J + j] = (unsigned char)z;
+      psi_h[(long)t * J + j] = psi;
+      if (trace) {
+        if (trace->v) trace->v[(long)(t - 1) * J + j] = v[j];
+        if (trace->a) trace->a[(long)(t - 1) * J + j] = a[j];
+        if (trace->psi) trace->psi[(long)(t - 1) * J + j] = psi;
+        if (trace->z) trace->z[(long)(t - 1) * J + j] = (unsigned char)z;
+      }
+    }
+    /* readout, error signal, loss */
+    readout_step(net, &p, &sp, tr, t, y, E, &loss, psum);
+    for (int k = 0; k < K; ++k) E_h[(long)t * K + k] = E[k];
+    /* learning signal L_j^t = sum_k B_jk E_k^t (eq. final-gradient) */
+    for (int j = 0; j < J; ++j) {
+      double Ls = 0.0;
+      for (int k = 0; k < K; ++k) Ls = Ls + net->fb[(long)j * K + k] * E[k];
+      L_h[(long)t * J + j] = Ls;
+    }
+    if (trace) {
+      for (int k = 0; k < K; ++k) {
+        if (trace->y) trace->y[(long)(t - 1) * K + k] = y[k];
+        if (trace->err) trace->err[(long)(t - 1) * K + k] = E[k];
+      }
+      if (trace->learn)
+        for (int j = 0; j < J; ++j) trace->learn[(long)(t - 1) * J + j] = L_h[(long)t * J + j];
+    }
+
+    if (grad_mode == 1) {
+      /* Time-driven gradient computation: every synapse, every step. */
+      for (long q = 0; q < ns; ++q) {
+        const int j = SYN_TGT(q);
+        const int kind = q < nin ? 0 : 1;
+        const int D = q < nin ? net->in.delay[q] : net->rec.delay[q - nin];
+        const double x = spiked(&sp, kind, q_src[q], t - D) ? 1.0 : 0.0;
+        syn_step(&p, x, psi_h[(long)(t - 1) * J + j], psi_h[(long)t * J + j], neuron_beta(net, j),
+                 L_h[(long)t * J + j], &ev[q], &ea[q], &eb[q], SYN_G(q));
+      }
+      /* output synapses: zbar = F_kappa(z_j), g_out += E_k zbar */
+      for (int j = 0; j < J; ++j) {
+        zb[j] = p.kappa * zb[j] + (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);
+        for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E[k] * zb[j];
+      }
+    } else if (grad_mode == 2) {
+      /* Event-driven update: a synapse whose presynaptic spike arrives at t
+       * walks the archived history over its previous interval
+       * [a_prev, t-1], with the arrival counted at the interval's first step. */
+      for (int D = 1; D <= p.max_delay; ++D) {
+        const int s = t - D;
+        for (int kind = 0; kind < 2; ++kind) {
+          const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
+          const long base = kind == 0 ? 0 : nin;
+          for (int i = 0; i < pr->n_src; ++i) {
+            if (!spiked(&sp, kind, i, s)) continue;
+            for (unsigned long r = pr->row_ptr[i]; r < pr->row_ptr[i + 1]; ++r) {
+              if (pr->delay[r] != D) continue;
+              const long q = base + (long)r;
+              const int j = (int)pr->col[r];
+              if (apr[q] > 0)
+                for (int u = apr[q]; u <= t - 1; ++u)
+                  syn_step(&p, u == apr[q] ? 1.0 : 0.0, psi_h[(long)(u - 1) * J + j],
+                           psi_h[(long)u * J + j], neuron_beta(net, j), L_h[(long)u * J + j],
+                           &ev[q], &ea[q], &eb[q], SYN_G(q));
+              apr[q] = t;
+            }
+          }
+        }
+      }
+      for (int j = 0; j < J; ++j) {
+        if (!sp.zrec[(long)t * J + j]) continue;
+        if (apr_o[j] > 0)
+          for (int u = apr_o[j]; u <= t - 1; ++u) {
+            zb[j] = p.kappa * zb[j] + (u == apr_o[j] ? 1.0 : 0.0);
+            for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E_h[(long)u * K + k] * zb[j];
+          }
+        apr_o[j] = t;
+      }
+    }
+  }
+  if (grad_mode == 2) {
+    /* end of the trial: flush every open interval up to T */
+    for (long q = 0; q < ns; ++q) {
+      if (apr[q] == 0) continue;
+      const int j = SYN_TGT(q);
+      for (int u = apr[q]; u <= T; ++u)
+        syn_step(&p, u == apr[q] ? 1.0 : 0.0, psi_h[(long)(u - 1) * J + j], psi_h[(long)u * J + j],
+                 neuron_beta(net, j), L_h[(long)u * J + j], &ev[q], &ea[q], &eb[q], SYN_G(q));
+    }
+    for (int j = 0; j < J; ++j) {
+      if (apr_o[j] == 0) continue;
+      for (int u = apr_o[j]; u <= T; ++u) {
+        zb[j] = p.kappa * zb[j] + (u == apr_o[j] ? 1.0 : 0.0);
+        for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E_h[(long)u * K + k] * zb[j];
+      }
+    }
+  }
+#undef SYN_TGT
+#undef SYN_G
+  if (loss_out) *loss_out = loss;
+  if (pred) {
+    int best = 0;
+    for (int k = 1; k < K; ++k)
+      if (psum[k] > psum[best]) best = k;
+    *pred = net->loss == 1 ? best : 0;
+  }
+  rc = 0;
+  (void)I;
+done:
+  free(v); free(a); free(refr); free(y); free(E); free(psum);
+  free(psi_h); free(L_h); free(E_h); free(ev); free(ea); free(eb); free(apr); free(zb); free(apr_o);
+  free(q_src);
+  spikes_free(&sp);
+  prep_free(&p);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward-mode checks.  A dual number carries a value and its derivative
+ * with respect to one seeded weight. */
+
+typedef struct { double x, d; } dual;
+
+static dual dmul_c(double c, dual a) { dual r = {c * a.x, c * a.d}; return r; }
+static dual dadd(dual a, dual b) { dual r = {a.x + b.x, a.d + b.d}; return r; }
+static dual dsub(dual a, dual b) { dual r = {a.x - b.x, a.d - b.d}; return r; }
+static dual dstop(dual a) { dual r = {a.x, 0.0}; return r; }
+
+/* Seeded weight: kind (0 input, 1 recurrent), its source, target and delay. */
+typedef struct { int kind, src, tgt, delay; } seed_t;
+
+/* Runs the network over one trial with dual numbers.  If stop_presyn, the
+ * spikes of other neurons enter as constants (e-prop's truncation); else
+ * their derivatives propagate through the recurrent weights.  Records
+ * dz[t*J + j] (t in 0..T) and, if dloss, accumulates the loss tangent
+ * sum_t sum_k E_k^t dy_k^t through the readouts. */
+static int dual_run(const orc_net *net, const prep_t *p, const spikes_t *sp_ref, const orc_trial *tr,
+                    const double *E_rec, seed_t sd, int stop_presyn, double *dz, double *dloss) {
+  const int T = tr->n_steps, J = net->n_rec, K = net->n_out;
+  dual *v = calloc(J, sizeof(dual)), *a = calloc(J, sizeof(dual)), *y = calloc(K, sizeof(dual));
+  int *refr = calloc(J, sizeof(int));
+  if (!v || !a || !y || !refr) { free(v); free(a); free(y); free(refr); return -1; }
+  memset(dz, 0, sizeof(double) * (size_t)(T + 1) * J);
+  double dl = 0.0;
+  for (int t = 1; t <= T; ++t) {
+    for (int j = 0; j < J; ++j) {
+      /* input current with its tangent */
+      dual I = {0.0, 0.0};
+      for (long q = p->in_ptr[j]; q < p->in_ptr[j + 1]; ++q) {
+        const in_syn *s = &p->syn[q];
+        const int src_step = t - s->delay;
+        const double w = s->kind == 0 ? net->in.w[s->idx] : net->rec.w[s->idx];
+        dual zs = {(double)spiked(sp_ref, s->kind, s->src, src_step), 0.0};
+        if (s->kind == 1 && !stop_presyn && src_step >= 1) zs.d = dz[(long)src_step * J + s->src];
+        dual term = dmul_c(w, zs);
+        if (s->kind == sd.kind && s->src == sd.src && j == sd.tgt) term.d += zs.x; /* d(w z)/dw */
+        I = dadd(I, term);
+      }
+      const double beta = neuron_beta(net, j);
+      dual zprev = {sp_ref->zrec[(long)(t - 1) * J + j] ? 1.0 : 0.0, dz[(long)(t - 1) * J + j]};
+      a[j] = dadd(dmul_c(p->rho, a[j]), zprev);                 /* a^t = rho a + z^{t-1} */
+      dual A = dadd((dual){net->v_th, 0.0}, dmul_c(beta, a[j]));  /* adaptive threshold */
+      /* v^t = alpha v + I - z^{t-1} A, with the reset term's derivative stopped */
+      dual reset = dstop((dual){zprev.x * A.x, 0.0});
+      v[j] = dsub(dadd(dmul_c(p->alpha, v[j]), I), reset);
+      const int refractory = refr[j] > 0;
+      if (refractory) refr[j] -= 1;
+      const double psi = refractory ? 0.0 : surrogate(net, v[j].x - A.x);
+      const int z = sp_ref->zrec[(long)t * J + j];   /* same spikes as the reference pass */
+      if (z) refr[j] = p->n_ref;
+      /* dz/dv = psi, dz/dA = -psi */
+      dz[(long)t * J + j] = psi * (v[j].d - A.d);
+    }
+    if (dloss) {
+      for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < J; ++j) s += net->w_out[(long)k * J + j] * dz[(long)t * J + j];
+        y[k].d = p->kappa * y[k].d + s;
+        dl += E_rec[(long)(t - 1) * K + k] * y[k].d;
+      }
+    }
+  }
+  if (dloss) *dloss = dl;
+  free(v); free(a); free(y); free(refr);
+  return 0;
+}
+
+/* Runs the reference pass and returns its spikes and error signals. */
+static int reference_pass(const orc_net *net, const orc_trial *tr, spikes_t *sp, double **E_rec) {
+  const int T = tr->n_steps, J = net->n_rec, K = net->n_out;
+  unsigned char *z = calloc((size_t)T * J, 1);
+  *E_rec = calloc((size_t)T * K, sizeof(double));
+  orc_trace trc;
+  memset(&trc, 0, sizeof(trc));
+  trc.z = z;
+  trc.err = *E_rec;
+  double loss;
+  if (!z || !*E_rec || orc_run_trial(net, tr, 0, NULL, NULL, NULL, &trc, &loss, NULL) ||
+      spikes_init(net, tr, sp)) {
+    free(z); free(*E_rec); *E_rec = NULL;
+    return -1;
+  }
+  for (int t = 1; t <= T; ++t)
+    for (int j = 0; j < J; ++j) sp->zrec[(long)t * J + j] = z[(long)(t - 1) * J + j];
+  free(z);
+  return 0;
+}
+
+static void for_each_weight(const orc_net *net, int kind, long q, seed_t *sd) {
+  const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
+  int src = 0;
+  while (pr->row_ptr[src + 1] <= (unsigned long)q) ++src;
+  sd->kind = kind;
+  sd->src = src;
+  sd->tgt = (int)pr->col[q];
+  sd->delay = pr->delay[q];
+}
+
+int orc_bruteforce_eprop(const orc_net *net, const orc_trial *tr, double *g_in, double *g_rec) {
+  if (check_net(net, tr)) return -1;
+  prep_t p;
+  if (prep_init(net, &p)) return -1;
+  spikes_t sp;
+  double *E_rec = NULL;
+  if (reference_pass(net, tr, &sp, &E_rec)) { prep_free(&p); return -1; }
+  const int T = tr->n_steps, J = net->n_rec, K = net->n_out;
+  double *dz = calloc((size_t)(T + 1) * J, sizeof(double));
+  int rc = dz ? 0 : -1;
+  for (int kind = 0; kind < 2 && rc == 0; ++kind) {
+    const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
+    for (long q = 0; q < pr->nnz && rc == 0; ++q) {
+      seed_t sd;
+      for_each_weight(net, kind, q, &sd);
+      rc = dual_run(net, &p, &sp, tr, E_rec, sd, 1, dz, NULL);
+      /* eq. summation-future: sum_t' [sum_k B_jk sum_{t>=t'} E_k^t kappa^(t-t')] e^t' */
+      double g = 0.0;
+      for (int tp = 1; tp <= T; ++tp) {
+        double Ls = 0.0;
+        for (int k = 0; k < K; ++k) {
+          double fut = 0.0;
+          for (int t = tp; t <= T; ++t) fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa, t - tp);
+          Ls += net->fb[(long)sd.tgt * K + k] * fut;
+        }
+        g += Ls * dz[(long)tp * J + sd.tgt];
+      }
+      (kind == 0 ? g_in : g_rec)[q] = g;
+    }
+  }
+  free(dz);
+  free(E_rec);
+  spikes_free(&sp);
+  prep_free(&p);
+  return rc;
+}
+
+int orc_forward_mode_loss_grad(const orc_net *net, const orc_trial *tr, double *g_in, double *g_rec) {
+  if (check_net(net, tr)) return -1;
+  prep_t p;
+  if (prep_init(net, &p)) return -1;
+  spikes_t sp;
+  double *E_rec = NULL;
+  if (reference_pass(net, tr, &sp, &E_rec)) { prep_free(&p); return -1; }
+  const int T = tr->n_steps, J = net->n_rec;
+  double *dz = calloc((size_t)(T + 1) * J, sizeof(double));
+  int rc = dz ? 0 : -1;
+  for (int kind = 0; kind < 2 && rc == 0; ++kind) {
+    const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
+    for (long q = 0; q < pr->nnz && rc == 0; ++q) {
+      seed_t sd;
+      double dl = 0.0;
+      for_each_weight(net, kind, q, &sd);
+      rc = dual_run(net, &p, &sp, tr, E_rec, sd, 0, dz, &dl);
+      (kind == 0 ? g_in : g_rec)[q] = dl;
+    }
+  }
+  free(dz);
+  free(E_rec);
+  spikes_free(&sp);
+  prep_free(&p);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+
+int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, const int *targets,
+                       double *g_in, double *g_rec, double *psi_out, double *loss_out) {
+  if (check_net(net, tr) || !tr->forced) return -1;
+  prep_t p;
+  if (prep_init(net, &p)) return -1;
+  spikes_t sp;
+  if (spikes_init(net, tr, &sp)) { prep_free(&p); return -1; }
+  const int T = tr->n_steps, J = net->n_rec, K = net->n_out;
+  /* forced spikes are the recurrent spike train */
+  memcpy(sp.zrec, sp.zforced, (size_t)(T + 1) * J);
+  double *y = calloc(K, sizeof(double)), *E = calloc(K, sizeof(double)), *psum = calloc(K, sizeof(double));
+  double *E_h = calloc((size_t)(T + 1) * K, sizeof(double));
+  double *psi_h = calloc((size_t)(T + 1), sizeof(double)), *L_h = calloc((size_t)(T + 1), sizeof(double));
+  int rc = (y && E && psum && E_h && psi_h && L_h) ? 0 : -1;
+  double loss = 0.0;
+  for (int t = 1; t <= T && rc == 0; ++t) {
+    readout_step(net, &p, &sp, tr, t, y, E, &loss, psum);
+    for (int k = 0; k < K; ++k) E_h[(long)t * K + k] = E[k];
+  }
+  for (int n = 0; n < n_sample && rc == 0; ++n) {
+    const int j = targets[n];
+    if (j < 0 || j >= J) { rc = -1; break; }
+    double v = 0.0, a = 0.0;
+    int refr = 0;
+    for (int t = 1; t <= T; ++t) {
+      const double I_t = input_current(net, &p, &sp, j, t);
+      const double zprev = sp.zrec[(long)(t - 1) * J + j] ? 1.0 : 0.0;
+      double psi;
+      neuron_step(net, &p, j, I_t, zprev, sp.zrec[(long)t * J + j], &v, &a, &refr, &psi);
+      psi_h[t] = psi;
+      if (psi_out) psi_out[(long)n * T + (t - 1)] = psi;
+      double Ls = 0.0;
+      for (int k = 0; k < K; ++k) Ls = Ls + net->fb[(long)j * K + k] * E_h[(long)t * K + k];
+      L_h[t] = Ls;
+    }
+    for (long q = p.in_ptr[j]; q < p.in_ptr[j + 1]; ++q) {
+      const in_syn *s = &p.syn[q];
+      double ev = 0.0, ea = 0.0, eb = 0.0, g = 0.0;
+      for (int t = 1; t <= T; ++t)
+        syn_step(&p, spiked(&sp, s->kind, s->src, t - s->delay) ? 1.0 : 0.0, psi_h[t - 1], psi_h[t],
+                 neuron_beta(net, j), L_h[t], &ev, &ea, &eb, &g);
+      (s->kind == 0 ? g_in : g_rec)[s->idx] = g;
+    }
+  }
+  if (loss_out) *loss_out = loss;
+  free(y); free(E); free(psum); free(E_h); free(psi_h); free(L_h);
+  spikes_free(&sp);
+  prep_free(&p);
+  return rc;
+}
+
+/* Gradient descent (eq. gradient-descent) on the mini-batch mean, or Adam
+ * with eq. eta-adam-fast and eq. delta-w-adam-fast applied once per
+ * iteration to the mini-batch mean gradient. */
+void orc_apply(long n, double *w, const double *g_sum, double n_trials, int optimizer, double eta,
+               double beta1, double beta2, double eps_hat, long step, double *m, double *v) {
+  const double eta_t = eta * sqrt(1.0 - pow(beta2, (double)step)) / (1.0 - pow(beta1, (double)step));
+  for (long i = 0; i < n; ++i) {
+    const double G = g_sum[i] / n_trials;
+    if (optimizer == 0) {
+      w[i] = w[i] - eta * G;
+    } else {
+      m[i] = beta1 * m[i] + (1.0 - beta1) * G;
+      v[i] = beta2 * v[i] + (1.0 - beta2) * G * G;
+      w[i] = w[i] - eta_t * m[i] / (sqrt(v[i]) + eps_hat);
+    }
+  }
+}

@@ -1,0 +1,103 @@
+/* CPU reference for event-driven e-prop: TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, serial, FP64 implementation of what the GPU library computes,
+ * written from the paper's equations (Methods: neuron models, loss
+ * function, gradients, optimization) and its algorithms (Alg. "time-driven
+ * gradient computation"; Algs. "event-driven weight update" with a FIFO of
+ * presynaptic spikes and its optimized spike-time form).  It shares no code,
+ * header, table or helper with the HIP library; only tests, the smoke check
+ * and the benchmark's CPU-baseline leg may call it.
+ *
+ * Conventions: steps t = 1..T, state zero at t = 0; a spike emitted by a
+ * source at step s reaches a synapse with delay D at step s + D; input
+ * emission steps lie in [0, T-1]; projections are CSR by source.
+ */
+#ifndef EPROP_ORACLE_H
+#define EPROP_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int n_src, n_tgt;
+  long nnz;
+  const unsigned long *row_ptr;   /* [n_src+1] */
+  const unsigned int *col;        /* [nnz] target index */
+  const double *w;                /* [nnz] */
+  const unsigned char *delay;     /* [nnz], >= 1 */
+} orc_proj;
+
+typedef struct {
+  int n_in, n_rec, n_out;
+  const unsigned char *is_alif;   /* [n_rec] */
+  double dt, tau_m, tau_out, v_th, t_ref, tau_a, beta_a;
+  int surrogate;                  /* 0 piecewise linear, 1 exponential */
+  double sg_gamma, sg_beta;
+  int loss;                       /* 0 mean squared error, 1 softmax cross-entropy */
+  orc_proj in, rec;
+  const double *w_out;            /* [K*J], row k */
+  const double *fb;               /* [J*K], row j */
+} orc_net;
+
+typedef struct {
+  int n_steps;
+  long n_in_spikes;
+  const unsigned int *in_step, *in_src;   /* emission steps in [0, T-1] */
+  const double *target;                   /* [T*K] (MSE) or NULL */
+  int label;                              /* class (cross-entropy) */
+  const unsigned char *window;            /* [T] learning window, NULL = always open */
+  int forced;                             /* 1: recurrent spikes replaced by the list below */
+  long n_forced;
+  const unsigned int *forced_step, *forced_neuron;   /* steps in [1, T] */
+} orc_trial;
+
+typedef struct {       /* optional per-step recordings, row t-1; any may be NULL */
+  double *v, *a, *psi, *learn;    /* [T*J] */
+  double *y, *err;                /* [T*K] */
+  unsigned char *z;               /* [T*J] */
+} orc_trace;
+
+/* One trial from zero state.  grad_mode 0: dynamics and loss only;
+ * 1: time-driven gradient (per-step recursion for every synapse);
+ * 2: event-driven gradient (intervals between presynaptic arrivals, walked
+ * from archived postsynaptic history when the next arrival comes, flushed at
+ * the end of the trial).  Gradients are ADDED into g_in [nnz_in],
+ * g_rec [nnz_rec] and g_out [K*J].  Returns 0, or -1 on bad input. */
+int orc_run_trial(const orc_net *net, const orc_trial *trial, int grad_mode,
+                  double *g_in, double *g_rec, double *g_out,
+                  orc_trace *trace, double *loss, int *pred);
+
+/* e-prop gradient by forward-mode dual numbers on the neuron equations
+ * (surrogate derivative for the spike, stop-gradient on the reset term and
+ * on presynaptic spikes), combined with the learning signal in its
+ * future-sum form.  O(T^2) per weight; tiny networks only.  Writes g_in,
+ * g_rec (not accumulated). */
+int orc_bruteforce_eprop(const orc_net *net, const orc_trial *trial,
+                         double *g_in, double *g_rec);
+
+/* Forward-mode gradient of the loss through the whole network (no
+ * stop-gradient on presynaptic spikes; reset term still stopped; loss
+ * tangent through the readouts with W_out).  Tiny networks only. */
+int orc_forward_mode_loss_grad(const orc_net *net, const orc_trial *trial,
+                               double *g_in, double *g_rec);
+
+/* Teacher-forced trial: computes the loss from the forced spikes of all
+ * neurons, and for each sampled target neuron its surrogate-gradient trace
+ * psi_out [n_sample*T] and the time-driven gradient of each of its incoming
+ * synapses (written into g_in / g_rec at the synapse's index; other entries
+ * untouched).  Cost is linear in the sampled neurons' in-degrees. */
+int orc_forced_sampled(const orc_net *net, const orc_trial *trial, int n_sample,
+                       const int *targets, double *g_in, double *g_rec,
+                       double *psi_out, double *loss);
+
+/* End of iteration: G = g_sum / n_trials, then gradient descent or Adam in
+ * the TensorFlow ordering (step = iteration count, starting at 1). */
+void orc_apply(long n, double *w, const double *g_sum, double n_trials, int optimizer,
+               double eta, double beta1, double beta2, double eps_hat, long step,
+               double *m, double *v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
