@@ -1,0 +1,277 @@
+/* eprop.h -- C ABI of the MI355X event-driven e-prop library (libeprop_hip.so).
+ *
+ * The library trains recurrent spiking networks with e-prop, the online
+ * approximation of the loss gradient dL/dW_ji ~ sum_t L_j^t F_kappa(e_ji^t)
+ * (paper, Methods "Gradients", eq. final-gradient and eq.
+ * filtered-eligibility-trace), evaluated event-driven: a synapse's gradient
+ * is formed only at the arrivals of its presynaptic spikes, from the
+ * archived history of its postsynaptic neuron (Results, "Event-driven weight
+ * updates in e-prop"; Supplementary "Algorithms").  Weights stay fixed
+ * within an iteration; gradients are summed over the samples of the
+ * iteration and applied once, averaged, by gradient descent or Adam
+ * (Methods "Optimization").
+ *
+ * Model (Methods "Neuron models", "Loss function"):
+ *   a_j^t = rho a_j^{t-1} + z_j^{t-1}                 (ALIF; beta_a = 0 gives LIF)
+ *   A_j^t = v_th + beta_a a_j^t
+ *   v_j^t = alpha v_j^{t-1} + I_j^t - z_j^{t-1} A_j^t  (reset by subtraction)
+ *   z_j^t = [v_j^t >= A_j^t and not refractory]
+ *   psi_j^t = surrogate(v_j^t - A_j^t), 0 while refractory
+ *   y_k^t = kappa y_k^{t-1} + sum_j W^out_kj z_j^t
+ *   E_k^t = window^t * dL/dy_k^t  (MSE: y - y*; softmax cross-entropy: pi - pi*)
+ *   L_j^t = sum_k B_jk E_k^t
+ * with alpha = exp(-dt/tau_m), rho = exp(-dt/tau_a), kappa = exp(-dt/tau_out).
+ * Time steps are t = 1..T with zero state at t = 0.  Refractoriness lasts
+ * n_ref = round(t_ref/dt) steps after a spike.  Every presynaptic source
+ * (input channel or recurrent neuron) emits spikes at integer steps; a
+ * synapse with delay D >= 1 receives a spike emitted at step s at step
+ * s + D.  I_j^t sums the weights of the synapses receiving a spike at t.
+ *
+ * Threading: one handle must not be used by two threads at once; separate
+ * handles are independent.  Every call is synchronous with respect to the
+ * host: when it returns, its results are in the caller's buffers.  All
+ * device work is issued on the HIP stream given to eprop_create_network.
+ *
+ * Errors: every call returns an eprop_status; nothing throws across the
+ * ABI.  Arguments are validated before any device work; on
+ * EPROP_ERR_INVALID_ARGUMENT, EPROP_ERR_CAPACITY or EPROP_ERR_STATE the
+ * handle is unchanged.  After EPROP_ERR_DEVICE or EPROP_ERR_NUMERIC the
+ * handle is failed: only eprop_read_state, eprop_last_error and
+ * eprop_destroy_network remain usable.  eprop_last_error gives the message
+ * of the last failure on a handle.
+ */
+#ifndef EPROP_H
+#define EPROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPROP_ABI_VERSION 1u
+
+typedef struct eprop_network eprop_network;   /* opaque, owned by the library */
+
+typedef enum {
+  EPROP_OK = 0,
+  EPROP_ERR_INVALID_ARGUMENT = -1,
+  EPROP_ERR_OUT_OF_MEMORY = -2,
+  EPROP_ERR_DEVICE = -3,
+  EPROP_ERR_STATE = -4,
+  EPROP_ERR_CAPACITY = -5,
+  EPROP_ERR_NUMERIC = -6,
+  EPROP_ERR_UNSUPPORTED = -7
+} eprop_status;
+
+/* Arithmetic of membrane, traces, weights and gradients.  FP32 sums the
+ * per-synapse gradients with compensated (Kahan) FP32; the loss, the
+ * readout reductions and the backward filters of the learning signal are
+ * FP64 in both modes. */
+typedef enum { EPROP_FP32 = 0, EPROP_FP64 = 1 } eprop_precision;
+
+/* Pseudo-derivative: eq. piecewise-linear-surrogate-gradient
+ * psi = gamma max(0, 1 - beta |v - A|), or eq. exponential-surrogate-gradient
+ * psi = gamma exp(-beta |v - A|). */
+typedef enum { EPROP_SG_PIECEWISE_LINEAR = 0, EPROP_SG_EXPONENTIAL = 1 } eprop_surrogate;
+
+/* eq. mean-squared-error (L = 1/2 sum_t sum_k (y - y*)^2) or eq. softmax with
+ * eq. cross-entropy-loss (L = -sum_t sum_k pi* log pi), both gated by the
+ * learning window. */
+typedef enum { EPROP_LOSS_MSE = 0, EPROP_LOSS_SOFTMAX_CE = 1 } eprop_loss;
+
+/* eq. gradient-descent, or Adam in the TensorFlow ordering
+ * (eq. eta-adam-fast, eq. delta-w-adam-fast) with one step per iteration. */
+typedef enum { EPROP_OPT_GD = 0, EPROP_OPT_ADAM = 1 } eprop_optimizer;
+
+/* Spike delivery.  SCATTER: one wavefront per spiking source adds its
+ * weights into per-target delay ring buffers with atomics (order of the
+ * additions not fixed).  GATHER: every target sums its incoming synapses
+ * that receive a spike, in ascending source order, inputs first
+ * (deterministic, bitwise reproducible).  AUTO: GATHER for FP64, SCATTER
+ * for FP32. */
+typedef enum { EPROP_DELIVERY_AUTO = 0, EPROP_DELIVERY_SCATTER = 1, EPROP_DELIVERY_GATHER = 2 } eprop_delivery;
+
+/* eprop_config.flags */
+#define EPROP_FLAG_NO_GRAPH (1u << 0)   /* launch the step loop kernel by kernel, no captured HIP graph */
+
+typedef struct {
+  uint32_t abi_version;          /* EPROP_ABI_VERSION */
+  int32_t precision;             /* eprop_precision */
+  uint32_t n_in, n_rec, n_out;   /* I input channels, J recurrent neurons, K readouts */
+  const uint8_t *is_alif;        /* [n_rec] host, 1 = adaptive threshold; NULL = all LIF; copied */
+  double dt, tau_m, tau_out, v_th, t_ref, tau_a, beta_a;   /* ms; beta_a applies to ALIF neurons */
+  int32_t surrogate;             /* eprop_surrogate */
+  double sg_gamma, sg_beta;      /* surrogate height gamma and width factor beta */
+  int32_t loss;                  /* eprop_loss */
+  int32_t optimizer;             /* eprop_optimizer */
+  double eta, adam_beta1, adam_beta2, adam_eps_hat;
+  uint32_t max_delay;            /* largest synaptic delay in steps, 1..255 */
+  uint32_t max_trials;           /* largest number of trials per eprop_simulate_batch call */
+  uint32_t max_steps;            /* largest trial length T, 1..65535 */
+  int32_t delivery;              /* eprop_delivery */
+  uint32_t flags;                /* EPROP_FLAG_* */
+} eprop_config;
+
+/* A projection in CSR-by-source form (host memory, copied by the call):
+ * synapse q of source i (row_ptr[i] <= q < row_ptr[i+1]) targets col[q]
+ * with weight w[q] and delay delay[q] in 1..max_delay (delay NULL = 1).
+ * No two synapses of one projection join the same pair; the recurrent
+ * projection has no self-connections.  Weights must be finite.  The order
+ * of synapses given here is the order of every per-synapse array the
+ * library returns. */
+typedef struct {
+  uint32_t n_src, n_tgt;
+  uint64_t nnz;
+  const uint64_t *row_ptr;   /* [n_src+1] */
+  const uint32_t *col;       /* [nnz] */
+  const double *w;           /* [nnz] */
+  const uint8_t *delay;      /* [nnz] or NULL */
+} eprop_projection;
+
+/* Adam state to resume from (host, copied); NULL pointers = zero. */
+typedef struct {
+  const double *m_in, *v_in;     /* [nnz of in_rec] */
+  const double *m_rec, *v_rec;   /* [nnz of rec_rec] */
+  const double *m_out, *v_out;   /* [n_out*n_rec] */
+  uint64_t step;                 /* Adam steps taken so far */
+} eprop_optimizer_state;
+
+/* Creates a network (Methods "Network architecture"): I inputs, J LIF/ALIF
+ * recurrent neurons, K leaky readouts, weights W^in (in_rec: I -> J),
+ * W^rec (rec_rec: J -> J), W^out ([K*J] row-major, row k = weights into
+ * readout k) and fixed random feedback B ([J*K] row-major, row j) that
+ * replaces W^out^T in the learning signal (eq. replace-wkj-by-bjk).
+ * opt may be NULL.  hip_stream is a hipStream_t (NULL = default stream)
+ * that stays owned by the caller and must outlive the handle.  Device
+ * memory is owned by the handle until eprop_destroy_network.
+ * Errors: INVALID_ARGUMENT (bad sizes, NULL arrays, delay out of range,
+ * duplicate pairs, self-connections, non-finite weights, more than 2^24-1
+ * sources or targets, 2^32 or more synapses), UNSUPPORTED (ABI version),
+ * OUT_OF_MEMORY, DEVICE (no usable gfx950 device). */
+eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projection *in_rec,
+                                  const eprop_projection *rec_rec, const double *w_out,
+                                  const double *feedback, const eprop_optimizer_state *opt,
+                                  void *hip_stream, eprop_network **out_net);
+
+typedef enum { EPROP_MEM_HOST = 0, EPROP_MEM_DEVICE = 1 } eprop_memory;
+
+/* eprop_batch.flags */
+#define EPROP_BATCH_TRAIN (1u << 0)    /* accumulate e-prop gradients of these trials */
+#define EPROP_BATCH_PROFILE (1u << 1)  /* time each phase with HIP events (phase_ms) */
+
+/* A batch of independent trials (samples) of uneven lengths, simulated
+ * together from zero state with the current weights (Results, "Evidence
+ * accumulation": parallel copies equal sequential processing when state
+ * and traces are reset per sample).
+ *   n_steps, label:   host arrays [n_trials] (always host memory);
+ *   in_ptr [n_trials+1], in_step, in_src: the input spikes of trial b are
+ *       entries in_ptr[b] .. in_ptr[b+1]-1, emission steps in [0, T_b-1],
+ *       sorted by (step, source) within the trial; n_in_spikes = in_ptr[n_trials];
+ *   target [n_trials * step_stride * n_out]: MSE target, entry
+ *       ((b*step_stride) + t-1)*n_out + k is y*_k at step t;
+ *   window [n_trials * step_stride] or NULL (always open): 1 where the
+ *       learning window is open at step t (entry b*step_stride + t-1);
+ *   forced_*: teacher forcing, NULL = free running; otherwise the recurrent
+ *       spikes of trial b are exactly the (step, neuron) pairs
+ *       forced_ptr[b] .. forced_ptr[b+1]-1 with steps in [1, T_b];
+ *   memory: where in_ptr, in_step, in_src, target, window and forced_* live.
+ *       With EPROP_MEM_DEVICE they are read by kernels, which check ranges
+ *       and order and make the call fail with INVALID_ARGUMENT. */
+typedef struct {
+  uint32_t n_trials;
+  int32_t memory;                 /* eprop_memory */
+  const uint32_t *n_steps;
+  uint64_t n_in_spikes;
+  const uint64_t *in_ptr;
+  const uint32_t *in_step, *in_src;
+  uint32_t step_stride;           /* >= max n_steps */
+  const double *target;           /* MSE only */
+  const uint32_t *label;          /* cross-entropy only, < n_out */
+  const uint8_t *window;
+  uint64_t n_forced;
+  const uint64_t *forced_ptr;
+  const uint32_t *forced_step, *forced_neuron;
+  uint32_t flags;                 /* EPROP_BATCH_* */
+} eprop_batch;
+
+#define EPROP_N_PHASES 8
+/* phase_ms indices */
+#define EPROP_PHASE_STAGE 0      /* input staging */
+#define EPROP_PHASE_FORWARD 1    /* neuron updates and spike delivery, all steps */
+#define EPROP_PHASE_READOUT 2    /* readout, error signals, loss */
+#define EPROP_PHASE_ADJOINT 3    /* per-neuron archive of arrival values */
+#define EPROP_PHASE_SYNAPSE 4    /* event-driven synapse gradient */
+#define EPROP_PHASE_OUTPUT 5     /* output-synapse gradient reduction */
+
+typedef struct {
+  double *loss;                  /* [n_trials] caller-owned or NULL: per-trial loss */
+  uint32_t *predicted;           /* [n_trials] or NULL: argmax_k of the window-summed pi (CE) */
+  uint64_t n_rec_spikes, n_in_spikes;
+  uint64_t n_syn_events;         /* input + recurrent deliveries arriving within their trial */
+  uint64_t n_out_events;         /* recurrent spikes x readouts */
+  uint64_t n_eprop_updates;      /* arrival evaluations on plastic synapses (TRAIN only) */
+  double device_ms;              /* device time of the whole call (HIP events) */
+  double phase_ms[EPROP_N_PHASES];   /* with EPROP_BATCH_PROFILE */
+} eprop_batch_result;
+
+/* Simulates the batch and, with EPROP_BATCH_TRAIN, adds the e-prop gradient
+ * of every trial to the handle's accumulators (Results, "Event-driven
+ * weight updates in e-prop": gradients accumulated per sample, weights
+ * unchanged until eprop_apply_updates).  res is caller-owned.
+ * Errors: INVALID_ARGUMENT, CAPACITY (n_trials > max_trials or a trial
+ * longer than max_steps), STATE (failed handle), DEVICE, NUMERIC (a
+ * non-finite loss). */
+eprop_status eprop_simulate_batch(eprop_network *net, const eprop_batch *batch,
+                                  eprop_batch_result *res);
+
+/* Ends an iteration: divides the accumulated gradients by the number of
+ * trials trained since the last call (reading: mean over the mini-batch),
+ * applies gradient descent or one Adam step to W^in, W^rec and W^out, and
+ * clears the accumulators (Methods "Optimization").
+ * Errors: STATE (no trials trained since the last call, or failed handle),
+ * DEVICE. */
+eprop_status eprop_apply_updates(eprop_network *net);
+
+typedef enum {
+  EPROP_STATE_W_IN = 0,      /* double [nnz_in], caller's synapse order */
+  EPROP_STATE_W_REC = 1,     /* double [nnz_rec] */
+  EPROP_STATE_W_OUT = 2,     /* double [K*J] */
+  EPROP_STATE_GRAD_IN = 3,   /* double, accumulated gradient sums (not yet averaged) */
+  EPROP_STATE_GRAD_REC = 4,
+  EPROP_STATE_GRAD_OUT = 5,
+  EPROP_STATE_ADAM_M_IN = 6, EPROP_STATE_ADAM_V_IN = 7,
+  EPROP_STATE_ADAM_M_REC = 8, EPROP_STATE_ADAM_V_REC = 9,
+  EPROP_STATE_ADAM_M_OUT = 10, EPROP_STATE_ADAM_V_OUT = 11,
+  EPROP_STATE_ADAM_STEP = 12,  /* uint64 */
+  EPROP_STATE_SPIKES = 13,     /* last batch, trial `trial`: uint32 pairs (step, neuron), sorted */
+  EPROP_STATE_PSI = 14,        /* last batch, trial: double [T_b * J], row t-1 */
+  EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
+  EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
+  EPROP_STATE_V = 17           /* last batch, trial: double [J] membrane potential at T_b */
+} eprop_state_id;
+
+/* Copies one state array to host memory dst (dst_bytes large).  With
+ * dst == NULL only *bytes_needed is set.  trial selects the trial of the
+ * last simulated batch for per-trial states and is ignored otherwise.
+ * Errors: INVALID_ARGUMENT (unknown id, trial out of range, dst too small),
+ * STATE (per-trial state requested before any batch), DEVICE. */
+eprop_status eprop_read_state(const eprop_network *net, int32_t what, uint32_t trial, void *dst,
+                              size_t dst_bytes, size_t *bytes_needed);
+
+/* Releases the handle and its device memory.  NULL is allowed. */
+void eprop_destroy_network(eprop_network *net);
+
+/* Static text for a status code. */
+const char *eprop_status_string(int32_t status);
+
+/* Message of the last failure on this handle ("" if none); valid until the
+ * next call on the handle.  NULL handle: the last failure of
+ * eprop_create_network in this thread. */
+const char *eprop_last_error(const eprop_network *net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EPROP_H */

@@ -1,0 +1,943 @@
+// Host side of the C ABI declared in include/eprop.h: argument validation
+// (before any device work), graph construction in source- and target-major
+// order, device memory, the step loop (captured once into a HIP graph per
+// block of steps and replayed), the optimizer call and state read-back.
+#include "eprop.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eprop_internal.h"
+
+using eprop::DevNet;
+using eprop::Launch;
+using eprop::Shapes;
+
+namespace {
+thread_local std::string g_create_error;
+constexpr uint32_t kMaxIndex = (1u << 24) - 1u;
+
+
+inline bool is_finite(double x) { return std::isfinite(x); }
+inline uint32_t round_up(uint32_t a, uint32_t m) { return (a + m - 1) / m * m; }
+}  // namespace
+
+struct eprop_network {
+  eprop_config cfg{};
+  uint32_t I = 0, J = 0, K = 0, NS = 0, Jp = 0, Jw = 0, Iw = 0, R = 0, Tcap = 0, Tp = 0, Bcap = 0;
+  uint64_t S_in = 0, S_rec = 0, S = 0;
+  bool fp64 = false, gather = false, adam = false, use_graph = true;
+  uint32_t n_ref = 0;
+  double alpha = 0, rho = 0, kappa = 0;
+  hipStream_t stream = nullptr, cap_stream = nullptr;
+  bool failed = false;
+  std::string err;
+  std::vector<void *> allocs;
+  DevNet<float> n32{};
+  DevNet<double> n64{};
+  Shapes shapes{};
+  std::vector<uint32_t> perm;       // target-major index -> caller's synapse index
+  uint32_t trials_accum = 0;
+  uint64_t adam_step = 0;
+  // library-owned staging copies of host-memory batches
+  uint32_t *d_T = nullptr, *d_label = nullptr;
+  uint64_t *d_in_ptr = nullptr, *d_forced_ptr = nullptr;
+  uint32_t *d_in_step = nullptr, *d_in_src = nullptr, *d_forced_step = nullptr, *d_forced_neuron = nullptr;
+  double *d_target = nullptr;
+  uint8_t *d_window = nullptr;
+  size_t cap_in_step = 0, cap_in_src = 0, cap_target = 0, cap_window = 0, cap_f_step = 0, cap_f_neuron = 0;
+  bool have_forced_bits = false;
+  // step loop
+  uint32_t blk = 0;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipEvent_t ev[EPROP_N_PHASES + 1] = {};
+  // last batch
+  uint32_t last_ntr = 0;
+  std::vector<uint32_t> last_T;
+};
+
+namespace {
+
+void set_fail(eprop_network *n, const std::string &m) { n->err = m; }
+
+template <typename T>
+bool dalloc(eprop_network *n, T **p, size_t count) {
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (hipMalloc(reinterpret_cast<void **>(p), bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  n->allocs.push_back(*p);
+  return true;
+}
+
+// Grows a library-owned staging buffer; returns false on allocation failure.
+template <typename T>
+bool dgrow(eprop_network *n, T **p, size_t *cap, size_t count) {
+  if (*p && *cap >= count) return true;
+  if (*p) {
+    auto it = std::find(n->allocs.begin(), n->allocs.end(), (void *)*p);
+    if (it != n->allocs.end()) n->allocs.erase(it);
+    (void)hipFree(*p);
+    *p = nullptr;
+  }
+  const size_t want = std::max<size_t>(count, 1024);
+  if (!dalloc(n, p, want)) return false;
+  *cap = want;
+  return true;
+}
+
+const char *hip_msg(hipError_t e) { return hipGetErrorString(e); }
+
+eprop_status check_projection(const eprop_projection *p, uint32_t n_src, uint32_t n_tgt, uint32_t max_delay,
+                              bool no_self, const char *name, std::string &msg) {
+  if (!p) { msg = std::string(name) + ": NULL projection"; return EPROP_ERR_INVALID_ARGUMENT; }
+  if (p->n_src != n_src || p->n_tgt != n_tgt) {
+    msg = std::string(name) + ": n_src/n_tgt do not match the network sizes";
+    return EPROP_ERR_INVALID_ARGUMENT;
+  }
+  if (!p->row_ptr) { msg = std::string(name) + ": NULL row_ptr"; return EPROP_ERR_INVALID_ARGUMENT; }
+  if (p->row_ptr[0] != 0 || p->row_ptr[n_src] != p->nnz) {
+    msg = std::string(name) + ": row_ptr must start at 0 and end at nnz";
+    return EPROP_ERR_INVALID_ARGUMENT;
+  }
+  if (p->nnz > 0 && (!p->col || !p->w)) { msg = std::string(name) + ": NULL col or w"; return EPROP_ERR_INVALID_ARGUMENT; }
+  for (uint32_t i = 0; i < n_src; ++i) {
+    if (p->row_ptr[i] > p->row_ptr[i + 1]) {
+      msg = std::string(name) + ": row_ptr decreases";
+      return EPROP_ERR_INVALID_ARGUMENT;
+    }
+    for (uint64_t q = p->row_ptr[i]; q < p->row_ptr[i + 1]; ++q) {
+      if (p->col[q] >= n_tgt) { msg = std::string(name) + ": target index out of range"; return EPROP_ERR_INVALID_ARGUMENT; }
+      if (no_self && p->col[q] == i) { msg = std::string(name) + ": self-connection"; return EPROP_ERR_INVALID_ARGUMENT; }
+      const uint32_t d = p->delay ? p->delay[q] : 1u;
+      if (d < 1 || d > max_delay) { msg = std::string(name) + ": delay outside 1..max_delay"; return EPROP_ERR_INVALID_ARGUMENT; }
+      if (!is_finite(p->w[q])) { msg = std::string(name) + ": non-finite weight"; return EPROP_ERR_INVALID_ARGUMENT; }
+    }
+  }
+  return EPROP_OK;
+}
+
+eprop_status check_config(const eprop_config *c, std::string &msg) {
+  if (!c) { msg = "NULL config"; return EPROP_ERR_INVALID_ARGUMENT; }
+  if (c->abi_version != EPROP_ABI_VERSION) { msg = "ABI version mismatch"; return EPROP_ERR_UNSUPPORTED; }
+  auto bad = [&](const char *m) { msg = m; return EPROP_ERR_INVALID_ARGUMENT; };
+  if (c->precision != EPROP_FP32 && c->precision != EPROP_FP64) return bad("precision must be FP32 or FP64");
+  if (c->n_rec < 1) return bad("n_rec must be >= 1");
+  if (c->n_out < 1 || c->n_out > 64) return bad("n_out must be in 1..64");
+  if ((uint64_t)c->n_in + c->n_rec > kMaxIndex) return bad("n_in + n_rec must be below 2^24");
+  if (!(c->dt > 0) || !(c->tau_m > 0) || !(c->tau_out > 0) || !(c->tau_a > 0) || !is_finite(c->dt) ||
+      !is_finite(c->tau_m) || !is_finite(c->tau_out) || !is_finite(c->tau_a))
+    return bad("dt and time constants must be positive and finite");
+  if (!is_finite(c->v_th) || !is_finite(c->beta_a) || !is_finite(c->sg_gamma) || !is_finite(c->sg_beta))
+    return bad("non-finite neuron or surrogate parameter");
+  if (!(c->t_ref >= 0) || !is_finite(c->t_ref) || std::lround(c->t_ref / c->dt) > 127)
+    return bad("t_ref must give 0..127 refractory steps");
+  if (c->surrogate != EPROP_SG_PIECEWISE_LINEAR && c->surrogate != EPROP_SG_EXPONENTIAL) return bad("unknown surrogate");
+  if (c->loss != EPROP_LOSS_MSE && c->loss != EPROP_LOSS_SOFTMAX_CE) return bad("unknown loss");
+  if (c->optimizer != EPROP_OPT_GD && c->optimizer != EPROP_OPT_ADAM) return bad("unknown optimizer");
+  if (!is_finite(c->eta)) return bad("non-finite learning rate");
+  if (c->optimizer == EPROP_OPT_ADAM &&
+      (!(c->adam_beta1 >= 0 && c->adam_beta1 < 1) || !(c->adam_beta2 >= 0 && c->adam_beta2 < 1) ||
+       !(c->adam_eps_hat > 0) || !is_finite(c->adam_eps_hat)))
+    return bad("Adam parameters out of range");
+  if (c->max_delay < 1 || c->max_delay > 255) return bad("max_delay must be in 1..255");
+  if (c->max_trials < 1) return bad("max_trials must be >= 1");
+  if (c->max_steps < 1 || c->max_steps > 65535) return bad("max_steps must be in 1..65535");
+  if (c->delivery < EPROP_DELIVERY_AUTO || c->delivery > EPROP_DELIVERY_GATHER) return bad("unknown delivery");
+  return EPROP_OK;
+}
+
+// Fills a DevNet's pointers and constants from the network's allocations.
+template <typename real>
+bool alloc_state(eprop_network *n, DevNet<real> &d) {
+  const size_t B = n->Bcap, T1 = (size_t)n->Tcap + 1, T2 = (size_t)n->Tcap + 2;
+  d.I = n->I; d.J = n->J; d.K = n->K; d.NS = n->NS; d.Jp = n->Jp; d.Jw = n->Jw; d.Iw = n->Iw;
+  d.R = n->R; d.Tcap = n->Tcap; d.Tp = n->Tp; d.Bcap = n->Bcap;
+  d.spk_stride = (uint64_t)n->NS * n->Tcap;
+  d.n_ref = n->n_ref;
+  d.surrogate = n->cfg.surrogate;
+  d.loss = n->cfg.loss;
+  d.alpha = (real)n->alpha; d.rho = (real)n->rho; d.v_th = (real)n->cfg.v_th;
+  d.sg_gamma = (real)n->cfg.sg_gamma; d.sg_beta = (real)n->cfg.sg_beta;
+  d.alpha_d = n->alpha; d.rho_d = n->rho; d.kappa_d = n->kappa;
+  uint32_t *p32;
+  real *pr;
+  bool ok = true;
+  ok &= dalloc(n, &p32, n->NS + 1); d.sm_ptr = p32;
+  ok &= dalloc(n, &p32, n->S); d.sm_syn = p32;
+  ok &= dalloc(n, &d.sm_w, n->S);
+  ok &= dalloc(n, &p32, n->J + 1); d.tm_ptr = p32;
+  ok &= dalloc(n, &p32, n->S); d.tm_syn = p32;
+  ok &= dalloc(n, &p32, n->S); d.tm_perm = p32;
+  ok &= dalloc(n, &d.tm_w, n->S);
+  ok &= dalloc(n, &d.gs, n->S);
+  ok &= dalloc(n, &d.gc, n->S);
+  if (n->adam) {
+    ok &= dalloc(n, &d.adam_m, n->S);
+    ok &= dalloc(n, &d.adam_v, n->S);
+  }
+  ok &= dalloc(n, &pr, n->Jp); d.beta_j = pr;
+  const size_t KJ = (size_t)n->K * n->Jp;
+  ok &= dalloc(n, &d.w_out, KJ);
+  ok &= dalloc(n, &d.fb, KJ);
+  ok &= dalloc(n, &d.gos, KJ);
+  ok &= dalloc(n, &d.goc, KJ);
+  if (n->adam) {
+    ok &= dalloc(n, &d.adam_mo, KJ);
+    ok &= dalloc(n, &d.adam_vo, KJ);
+  }
+  ok &= dalloc(n, &d.gout_b, B * KJ);
+  ok &= dalloc(n, &d.v, B * n->Jp);
+  ok &= dalloc(n, &d.a, B * n->Jp);
+  ok &= dalloc(n, &d.nst, B * n->Jp);
+  if (!n->gather) ok &= dalloc(n, &d.ring, B * n->R * n->Jp);
+  ok &= dalloc(n, &d.psi, B * T1 * n->Jp);
+  ok &= dalloc(n, &d.phi, B * n->Jp * n->Tp);
+  ok &= dalloc(n, &d.rec_bits, B * T1 * n->Jw);
+  ok &= dalloc(n, &d.in_bits, B * n->Tcap * n->Iw);
+  ok &= dalloc(n, &d.spk_cnt, B * n->NS);
+  ok &= dalloc(n, &d.spk_t, B * d.spk_stride);
+  ok &= dalloc(n, &d.rec_cnt, B * T1);
+  ok &= dalloc(n, &d.rec_list, B * 2 * n->Jp);
+  ok &= dalloc(n, &d.in_step_ptr, B * T1);
+  ok &= dalloc(n, &d.ysum, B * T2 * n->K);
+  ok &= dalloc(n, &d.y, B * T2 * n->K);
+  ok &= dalloc(n, &d.err, B * T2 * n->K);
+  ok &= dalloc(n, &d.ebar, B * T2 * n->K);
+  ok &= dalloc(n, &d.loss_out, B);
+  ok &= dalloc(n, &d.pred_out, B);
+  ok &= dalloc(n, &d.ctl, 64);
+  ok &= dalloc(n, &d.cnt, eprop::CNT_WORDS);
+  return ok;
+}
+
+// Uploads graph, weights and optimiser state (host arrays in double).
+template <typename real>
+hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t> &sm_ptr,
+                  const std::vector<uint32_t> &sm_syn, const std::vector<double> &sm_w,
+                  const std::vector<uint32_t> &tm_ptr, const std::vector<uint32_t> &tm_syn,
+                  const std::vector<uint32_t> &tm_perm, const std::vector<double> &tm_w,
+                  const std::vector<double> &beta, const double *w_out, const double *fb,
+                  const eprop_optimizer_state *opt) {
+  hipError_t e = hipSuccess;
+  auto cp = [&](void *dst, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  auto conv = [&](const std::vector<double> &v) {
+    std::vector<real> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (real)v[i];
+    return o;
+  };
+  cp((void *)d.sm_ptr, sm_ptr.data(), sm_ptr.size() * 4);
+  cp((void *)d.sm_syn, sm_syn.data(), sm_syn.size() * 4);
+  { auto o = conv(sm_w); cp(d.sm_w, o.data(), o.size() * sizeof(real)); }
+  cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
+  cp((void *)d.tm_syn, tm_syn.data(), tm_syn.size() * 4);
+  cp((void *)d.tm_perm, tm_perm.data(), tm_perm.size() * 4);
+  { auto o = conv(tm_w); cp(d.tm_w, o.data(), o.size() * sizeof(real)); }
+  { auto o = conv(beta); cp((void *)d.beta_j, o.data(), o.size() * sizeof(real)); }
+  const size_t KJ = (size_t)n->K * n->Jp;
+  std::vector<double> wo(KJ, 0.0), fbp(KJ, 0.0);
+  for (uint32_t k = 0; k < n->K; ++k)
+    for (uint32_t j = 0; j < n->J; ++j) {
+      wo[(size_t)k * n->Jp + j] = w_out[(size_t)k * n->J + j];
+      fbp[(size_t)j * n->K + k] = fb[(size_t)j * n->K + k];
+    }
+  { auto o = conv(wo); cp(d.w_out, o.data(), o.size() * sizeof(real)); }
+  { auto o = conv(fbp); cp(d.fb, o.data(), o.size() * sizeof(real)); }
+  if (e == hipSuccess && n->S) e = hipMemset(d.gs, 0, n->S * sizeof(real));
+  if (e == hipSuccess && n->S) e = hipMemset(d.gc, 0, n->S * sizeof(real));
+  if (e == hipSuccess) e = hipMemset(d.gos, 0, KJ * sizeof(real));
+  if (e == hipSuccess) e = hipMemset(d.goc, 0, KJ * sizeof(real));
+  if (e == hipSuccess) e = hipMemset(d.cnt, 0, eprop::CNT_WORDS * 8);
+  if (n->adam && e == hipSuccess) {
+    // optimiser state: caller order -> target-major
+    std::vector<double> m(n->S, 0.0), v(n->S, 0.0), mo(KJ, 0.0), vo(KJ, 0.0);
+    if (opt) {
+      for (uint64_t q = 0; q < n->S; ++q) {
+        const uint32_t c = tm_perm[q];
+        const double *ms = c < n->S_in ? opt->m_in : opt->m_rec;
+        const double *vs = c < n->S_in ? opt->v_in : opt->v_rec;
+        const uint64_t o = c < n->S_in ? c : c - n->S_in;
+        if (ms) m[q] = ms[o];
+        if (vs) v[q] = vs[o];
+      }
+      for (uint32_t k = 0; k < n->K; ++k)
+        for (uint32_t j = 0; j < n->J; ++j) {
+          if (opt->m_out) mo[(size_t)k * n->Jp + j] = opt->m_out[(size_t)k * n->J + j];
+          if (opt->v_out) vo[(size_t)k * n->Jp + j] = opt->v_out[(size_t)k * n->J + j];
+        }
+    }
+    { auto o = conv(m); cp(d.adam_m, o.data(), o.size() * sizeof(real)); }
+    { auto o = conv(v); cp(d.adam_v, o.data(), o.size() * sizeof(real)); }
+    { auto o = conv(mo); cp(d.adam_mo, o.data(), o.size() * sizeof(real)); }
+    { auto o = conv(vo); cp(d.adam_vo, o.data(), o.size() * sizeof(real)); }
+  }
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *eprop_status_string(int32_t s) {
+  switch (s) {
+    case EPROP_OK: return "ok";
+    case EPROP_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case EPROP_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case EPROP_ERR_DEVICE: return "device error";
+    case EPROP_ERR_STATE: return "call not valid in the handle's state";
+    case EPROP_ERR_CAPACITY: return "batch exceeds the configured capacity";
+    case EPROP_ERR_NUMERIC: return "non-finite loss";
+    case EPROP_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char *eprop_last_error(const eprop_network *net) {
+  return net ? net->err.c_str() : g_create_error.c_str();
+}
+
+void eprop_destroy_network(eprop_network *net) {
+  if (!net) return;
+  (void)hipStreamSynchronize(net->stream);
+  for (auto &g : net->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto &e : net->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
+  for (void *p : net->allocs) (void)hipFree(p);
+  delete net;
+}
+
+eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projection *in_rec,
+                                  const eprop_projection *rec_rec, const double *w_out,
+                                  const double *feedback, const eprop_optimizer_state *opt,
+                                  void *hip_stream, eprop_network **out_net) {
+  g_create_error.clear();
+  std::string msg;
+  if (!out_net) { g_create_error = "NULL out_net"; return EPROP_ERR_INVALID_ARGUMENT; }
+  *out_net = nullptr;
+  eprop_status st = check_config(cfg, msg);
+  if (st == EPROP_OK) st = check_projection(in_rec, cfg->n_in, cfg->n_rec, cfg->max_delay, false, "in_rec", msg);
+  if (st == EPROP_OK) st = check_projection(rec_rec, cfg->n_rec, cfg->n_rec, cfg->max_delay, true, "rec_rec", msg);
+  if (st == EPROP_OK && (in_rec->nnz + rec_rec->nnz) >= (1ull << 32)) {
+    msg = "2^32 or more synapses";
+    st = EPROP_ERR_INVALID_ARGUMENT;
+  }
+  if (st == EPROP_OK && (!w_out || !feedback)) {
+    msg = "NULL w_out or feedback";
+    st = EPROP_ERR_INVALID_ARGUMENT;
+  }
+  if (st == EPROP_OK) {
+    for (size_t i = 0; i < (size_t)cfg->n_out * cfg->n_rec; ++i)
+      if (!is_finite(w_out[i]) || !is_finite(feedback[i])) {
+        msg = "non-finite w_out or feedback";
+        st = EPROP_ERR_INVALID_ARGUMENT;
+        break;
+      }
+  }
+  if (st != EPROP_OK) {
+    g_create_error = msg;
+    return st;
+  }
+
+  // graph in both orders (pure host work); duplicates found on the way
+  const uint32_t I = cfg->n_in, J = cfg->n_rec, NS = I + J;
+  const uint64_t S_in = in_rec->nnz, S_rec = rec_rec->nnz, S = S_in + S_rec;
+  std::vector<uint32_t> sm_ptr(NS + 1), sm_syn(S), tm_ptr(J + 1, 0), tm_syn(S), tm_perm(S);
+  std::vector<double> sm_w(S), tm_w(S);
+  for (uint32_t i = 0; i <= I; ++i) sm_ptr[i] = (uint32_t)in_rec->row_ptr[i];
+  for (uint32_t i = 1; i <= J; ++i) sm_ptr[I + i] = (uint32_t)(S_in + rec_rec->row_ptr[i]);
+  for (int kind = 0; kind < 2; ++kind) {
+    const eprop_projection *p = kind == 0 ? in_rec : rec_rec;
+    const uint64_t base = kind == 0 ? 0 : S_in;
+    for (uint64_t q = 0; q < p->nnz; ++q) {
+      const uint32_t d = p->delay ? p->delay[q] : 1u;
+      sm_syn[base + q] = p->col[q] | (d << 24);
+      sm_w[base + q] = p->w[q];
+      tm_ptr[p->col[q] + 1]++;
+    }
+  }
+  for (uint32_t j = 0; j < J; ++j) tm_ptr[j + 1] += tm_ptr[j];
+  {
+    std::vector<uint32_t> fill(J, 0);
+    for (uint32_t src = 0; src < NS; ++src)
+      for (uint32_t q = sm_ptr[src]; q < sm_ptr[src + 1]; ++q) {
+        const uint32_t tgt = sm_syn[q] & 0xFFFFFFu;
+        const uint32_t pos = tm_ptr[tgt] + fill[tgt]++;
+        if (pos > tm_ptr[tgt] && (tm_syn[pos - 1] & 0xFFFFFFu) == src) {
+          g_create_error = "duplicate synapse between one pair of neurons";
+          return EPROP_ERR_INVALID_ARGUMENT;
+        }
+        tm_syn[pos] = src | (sm_syn[q] & 0xFF000000u);
+        tm_w[pos] = sm_w[q];
+        tm_perm[pos] = q;
+      }
+  }
+
+  // device
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device";
+    return EPROP_ERR_DEVICE;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    g_create_error = "cannot query the HIP device";
+    return EPROP_ERR_DEVICE;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_error = std::string("library built for gfx950, device is ") + prop.gcnArchName;
+    return EPROP_ERR_DEVICE;
+  }
+
+  eprop_network *n = new (std::nothrow) eprop_network();
+  if (!n) { g_create_error = "host allocation failed"; return EPROP_ERR_OUT_OF_MEMORY; }
+  n->cfg = *cfg;
+  n->cfg.is_alif = nullptr;
+  n->I = I; n->J = J; n->K = cfg->n_out; n->NS = NS;
+  n->Jw = (J + 63) / 64; n->Jp = n->Jw * 64; n->Iw = std::max<uint32_t>(1, (I + 63) / 64);
+  n->R = cfg->max_delay + 1; n->Tcap = cfg->max_steps; n->Tp = round_up(n->Tcap + 1, 16);
+  n->Bcap = cfg->max_trials;
+  n->S_in = S_in; n->S_rec = S_rec; n->S = S;
+  n->fp64 = cfg->precision == EPROP_FP64;
+  n->gather = cfg->delivery == EPROP_DELIVERY_GATHER || (cfg->delivery == EPROP_DELIVERY_AUTO && n->fp64);
+  n->adam = cfg->optimizer == EPROP_OPT_ADAM;
+  n->use_graph = (cfg->flags & EPROP_FLAG_NO_GRAPH) == 0;
+  n->n_ref = (uint32_t)std::lround(cfg->t_ref / cfg->dt);
+  // exact-integration propagators (eq. lif_update, eq. spike-threshold-adaptation,
+  // eq. leaky_integrator)
+  n->alpha = std::exp(-cfg->dt / cfg->tau_m);
+  n->rho = std::exp(-cfg->dt / cfg->tau_a);
+  n->kappa = std::exp(-cfg->dt / cfg->tau_out);
+  n->stream = static_cast<hipStream_t>(hip_stream);
+  n->perm = tm_perm;
+  n->adam_step = opt ? opt->step : 0;
+  n->blk = std::min<uint32_t>(50, n->Tcap);
+  n->shapes.block = 256;
+  n->shapes.deliver_blocks_per_trial = std::max<uint32_t>(1, std::min<uint32_t>(512, 1024 / n->Bcap));
+  n->shapes.syn_blocks = std::max<uint32_t>(1, std::min<uint32_t>((J + 3) / 4, 4096));
+
+  std::vector<double> beta(n->Jp, 0.0);
+  for (uint32_t j = 0; j < J; ++j) beta[j] = (cfg->is_alif && cfg->is_alif[j]) ? cfg->beta_a : 0.0;
+
+  bool ok = n->fp64 ? alloc_state(n, n->n64) : alloc_state(n, n->n32);
+  ok = ok && dalloc(n, &n->d_T, n->Bcap) && dalloc(n, &n->d_label, n->Bcap) && dalloc(n, &n->d_in_ptr, n->Bcap + 1) &&
+       dalloc(n, &n->d_forced_ptr, n->Bcap + 1);
+  if (!ok) {
+    g_create_error = "out of device memory";
+    eprop_destroy_network(n);
+    return EPROP_ERR_OUT_OF_MEMORY;
+  }
+  hipError_t e = n->fp64 ? upload(n, n->n64, sm_ptr, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
+                                  feedback, opt)
+                         : upload(n, n->n32, sm_ptr, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
+                                  feedback, opt);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&n->cap_stream, hipStreamNonBlocking);
+  for (auto &ev : n->ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    g_create_error = std::string("device error during setup: ") + hip_msg(e);
+    eprop_destroy_network(n);
+    return EPROP_ERR_DEVICE;
+  }
+  *out_net = n;
+  return EPROP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validates a batch on the host.  Device-memory arrays are checked by the
+// staging kernels; their in_ptr / forced_ptr are copied and checked here.
+eprop_status check_batch(eprop_network *n, const eprop_batch *b, std::vector<uint64_t> &in_ptr,
+                         std::vector<uint64_t> &f_ptr, uint32_t &t_max, std::string &msg) {
+  auto bad = [&](const char *m) { msg = m; return EPROP_ERR_INVALID_ARGUMENT; };
+  if (b->n_trials < 1) return bad("n_trials must be >= 1");
+  if (b->n_trials > n->Bcap) { msg = "n_trials exceeds max_trials"; return EPROP_ERR_CAPACITY; }
+  if (b->memory != EPROP_MEM_HOST && b->memory != EPROP_MEM_DEVICE) return bad("unknown memory kind");
+  if (!b->n_steps) return bad("NULL n_steps");
+  t_max = 0;
+  for (uint32_t i = 0; i < b->n_trials; ++i) {
+    if (b->n_steps[i] < 1) return bad("trial with 0 steps");
+    if (b->n_steps[i] > n->Tcap) { msg = "trial longer than max_steps"; return EPROP_ERR_CAPACITY; }
+    t_max = std::max(t_max, b->n_steps[i]);
+  }
+  if (b->step_stride < t_max) return bad("step_stride smaller than the longest trial");
+  if (n->cfg.loss == EPROP_LOSS_MSE && !b->target) return bad("MSE needs a target");
+  if (n->cfg.loss == EPROP_LOSS_SOFTMAX_CE) {
+    if (!b->label) return bad("cross-entropy needs labels");
+    for (uint32_t i = 0; i < b->n_trials; ++i)
+      if (b->label[i] >= n->K) return bad("label out of range");
+  }
+  if (!b->in_ptr) return bad("NULL in_ptr");
+  if (b->n_in_spikes > 0 && (!b->in_step || !b->in_src)) return bad("NULL in_step or in_src");
+  if (b->n_in_spikes >= (1ull << 40)) return bad("too many input spikes");
+  const bool dev = b->memory == EPROP_MEM_DEVICE;
+  in_ptr.assign(b->n_trials + 1, 0);
+  if (dev) {
+    if (hipMemcpy(in_ptr.data(), b->in_ptr, in_ptr.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      return bad("in_ptr is not readable device memory");
+    }
+  } else {
+    std::memcpy(in_ptr.data(), b->in_ptr, in_ptr.size() * 8);
+  }
+  if (in_ptr[0] != 0 || in_ptr[b->n_trials] != b->n_in_spikes) return bad("in_ptr must span 0..n_in_spikes");
+  for (uint32_t i = 0; i < b->n_trials; ++i)
+    if (in_ptr[i] > in_ptr[i + 1]) return bad("in_ptr decreases");
+  if (!dev) {
+    for (uint32_t i = 0; i < b->n_trials; ++i)
+      for (uint64_t e = in_ptr[i]; e < in_ptr[i + 1]; ++e) {
+        if (b->in_step[e] >= b->n_steps[i] || b->in_src[e] >= n->I) return bad("input spike out of range");
+        if (e > in_ptr[i]) {
+          const uint32_t ps = b->in_step[e - 1], pi = b->in_src[e - 1];
+          if (!(ps < b->in_step[e] || (ps == b->in_step[e] && pi < b->in_src[e])))
+            return bad("input spikes not strictly sorted by (step, source)");
+        }
+      }
+  }
+  f_ptr.clear();
+  if (b->forced_ptr) {
+    if (b->n_forced > 0 && (!b->forced_step || !b->forced_neuron)) return bad("NULL forced arrays");
+    f_ptr.assign(b->n_trials + 1, 0);
+    if (dev) {
+      if (hipMemcpy(f_ptr.data(), b->forced_ptr, f_ptr.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return bad("forced_ptr is not readable device memory");
+      }
+    } else {
+      std::memcpy(f_ptr.data(), b->forced_ptr, f_ptr.size() * 8);
+    }
+    if (f_ptr[0] != 0 || f_ptr[b->n_trials] != b->n_forced) return bad("forced_ptr must span 0..n_forced");
+    for (uint32_t i = 0; i < b->n_trials; ++i) {
+      if (f_ptr[i] > f_ptr[i + 1]) return bad("forced_ptr decreases");
+      if (!dev)
+        for (uint64_t e = f_ptr[i]; e < f_ptr[i + 1]; ++e)
+          if (b->forced_step[e] < 1 || b->forced_step[e] > b->n_steps[i] || b->forced_neuron[e] >= n->J)
+            return bad("forced spike out of range");
+    }
+  }
+  return EPROP_OK;
+}
+
+template <typename real>
+void record_block(eprop_network *n, DevNet<real> &d, bool forced, hipStream_t s) {
+  for (uint32_t o = 1; o <= n->blk; ++o) {
+    Launch<real>::neuron(d, o, n->gather, forced, s);
+    if (!n->gather) Launch<real>::deliver(d, n->shapes, o, s);
+  }
+  eprop::launch_advance(d.ctl, n->blk, s);
+}
+
+template <typename real>
+hipError_t ensure_graph(eprop_network *n, DevNet<real> &d, bool forced) {
+  hipGraphExec_t &ge = n->gexec[forced ? 1 : 0];
+  if (ge) return hipSuccess;
+  hipError_t e = hipStreamBeginCapture(n->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  record_block(n, d, forced, n->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(n->cap_stream, &g);
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+template <typename real>
+eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res) {
+  std::string msg;
+  std::vector<uint64_t> in_ptr, f_ptr;
+  uint32_t t_max = 0;
+  eprop_status st = check_batch(n, b, in_ptr, f_ptr, t_max, msg);
+  if (st != EPROP_OK) {
+    set_fail(n, msg);
+    return st;
+  }
+  const uint32_t ntr = b->n_trials;
+  const bool dev = b->memory == EPROP_MEM_DEVICE;
+  const bool forced = b->forced_ptr != nullptr;
+  const bool train = (b->flags & EPROP_BATCH_TRAIN) != 0;
+  const bool prof = (b->flags & EPROP_BATCH_PROFILE) != 0;
+  hipStream_t s = n->stream;
+  hipError_t e = hipSuccess;
+  auto H2D = [&](void *dst, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  auto MS = [&](void *dst, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemsetAsync(dst, 0, bytes, s);
+  };
+
+  // batch arrays: library copies for host memory, caller's for device memory
+  if (!dev) {
+    const size_t nt = (size_t)ntr * b->step_stride;
+    bool ok = dgrow(n, &n->d_in_step, &n->cap_in_step, b->n_in_spikes) &&
+              dgrow(n, &n->d_in_src, &n->cap_in_src, b->n_in_spikes);
+    if (ok && b->target) ok = dgrow(n, &n->d_target, &n->cap_target, nt * n->K);
+    if (ok && b->window) ok = dgrow(n, &n->d_window, &n->cap_window, nt);
+    if (ok && forced)
+      ok = dgrow(n, &n->d_forced_step, &n->cap_f_step, b->n_forced) &&
+           dgrow(n, &n->d_forced_neuron, &n->cap_f_neuron, b->n_forced);
+    if (!ok) {
+      set_fail(n, "out of device memory for the batch");
+      return EPROP_ERR_OUT_OF_MEMORY;
+    }
+  }
+  if (forced && !n->have_forced_bits) {
+    if (!dalloc(n, &d.forced_bits, (size_t)n->Bcap * (n->Tcap + 1) * n->Jw)) {
+      set_fail(n, "out of device memory for forced spikes");
+      return EPROP_ERR_OUT_OF_MEMORY;
+    }
+    n->have_forced_bits = true;
+  }
+  d.T = n->d_T;
+  d.label = n->d_label;
+  d.step_stride = b->step_stride;
+  if (dev) {
+    d.in_ptr = b->in_ptr;
+    d.in_step = b->in_step;
+    d.in_src = b->in_src;
+    d.target = b->target;
+    d.window = b->window;
+    d.forced_ptr = b->forced_ptr;
+    d.forced_step = b->forced_step;
+    d.forced_neuron = b->forced_neuron;
+  } else {
+    d.in_ptr = n->d_in_ptr;
+    d.in_step = n->d_in_step;
+    d.in_src = n->d_in_src;
+    d.target = b->target ? n->d_target : nullptr;
+    d.window = b->window ? n->d_window : nullptr;
+    d.forced_ptr = n->d_forced_ptr;
+    d.forced_step = n->d_forced_step;
+    d.forced_neuron = n->d_forced_neuron;
+  }
+
+  (void)hipEventRecord(n->ev[0], s);
+  // upload
+  H2D(n->d_T, b->n_steps, ntr * 4);
+  if (b->label) H2D(n->d_label, b->label, ntr * 4);
+  if (!dev) {
+    H2D(n->d_in_ptr, in_ptr.data(), in_ptr.size() * 8);
+    H2D(n->d_in_step, b->in_step, b->n_in_spikes * 4);
+    H2D(n->d_in_src, b->in_src, b->n_in_spikes * 4);
+    const size_t nt = (size_t)ntr * b->step_stride;
+    if (b->target) H2D(n->d_target, b->target, nt * n->K * 8);
+    if (b->window) H2D(n->d_window, b->window, nt);
+    if (forced) {
+      H2D(n->d_forced_ptr, f_ptr.data(), f_ptr.size() * 8);
+      H2D(n->d_forced_step, b->forced_step, b->n_forced * 4);
+      H2D(n->d_forced_neuron, b->forced_neuron, b->n_forced * 4);
+    }
+  }
+  struct {
+    uint32_t w[eprop::CTL_WORDS];
+    const uint32_t *in_src;
+  } ctl{};
+  ctl.w[eprop::CTL_T0] = 0;
+  ctl.w[eprop::CTL_NTRIALS] = ntr;
+  ctl.w[eprop::CTL_ERR] = 0;
+  ctl.in_src = d.in_src;
+  H2D(d.ctl, &ctl, sizeof(ctl));
+  // per-batch state from zero (trials start from rest)
+  const size_t T1 = (size_t)n->Tcap + 1;
+  MS(d.v, (size_t)ntr * n->Jp * sizeof(real));
+  MS(d.a, (size_t)ntr * n->Jp * sizeof(real));
+  MS(d.nst, (size_t)ntr * n->Jp);
+  if (!n->gather) MS(d.ring, (size_t)ntr * n->R * n->Jp * sizeof(real));
+  MS(d.in_bits, (size_t)ntr * n->Tcap * n->Iw * 8);
+  MS(d.spk_cnt, (size_t)ntr * n->NS * 4);
+  MS(d.rec_cnt, (size_t)ntr * T1 * 4);
+  MS(d.cnt, eprop::CNT_WORDS * 8);
+  if (forced) MS(d.forced_bits, (size_t)ntr * T1 * n->Jw * 8);
+  if (e != hipSuccess) goto device_error;
+
+  Launch<real>::stage_inputs(d, ntr, b->n_in_spikes, dev, s);
+  if (forced) Launch<real>::stage_forced(d, ntr, b->n_forced, s);
+  if (dev) {
+    uint32_t flags = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flags, d.ctl + eprop::CTL_ERR, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) goto device_error;
+    if (flags) {
+      set_fail(n, flags & eprop::ERR_INPUT_ORDER ? "input spikes not strictly sorted by (step, source)"
+                                                 : "spike out of range");
+      return EPROP_ERR_INVALID_ARGUMENT;
+    }
+  }
+  if (prof) (void)hipEventRecord(n->ev[1], s);
+
+  // forward: spikes emitted at step 0 are delivered first, then blocks of steps
+  if (!n->gather) Launch<real>::deliver(d, n->shapes, 0, s);
+  {
+    const uint32_t nblk = (t_max + n->blk - 1) / n->blk;
+    if (n->use_graph) {
+      e = ensure_graph(n, d, forced);
+      if (e != hipSuccess) goto device_error;
+      for (uint32_t i = 0; i < nblk && e == hipSuccess; ++i) e = hipGraphLaunch(n->gexec[forced ? 1 : 0], s);
+    } else {
+      for (uint32_t i = 0; i < nblk; ++i) record_block(n, d, forced, s);
+    }
+  }
+  if (prof) (void)hipEventRecord(n->ev[2], s);
+  Launch<real>::readout(d, s);
+  if (prof) (void)hipEventRecord(n->ev[3], s);
+  if (train) {
+    Launch<real>::adjoint(d, s);
+    if (prof) (void)hipEventRecord(n->ev[4], s);
+    Launch<real>::synapse(d, n->shapes, s);
+    if (prof) (void)hipEventRecord(n->ev[5], s);
+    Launch<real>::output_reduce(d, s);
+    if (prof) (void)hipEventRecord(n->ev[6], s);
+  }
+  (void)hipEventRecord(n->ev[7], s);
+  {
+    std::vector<double> loss(ntr);
+    std::vector<uint32_t> pred(ntr);
+    unsigned long long cnt[eprop::CNT_WORDS] = {};
+    uint32_t flags = 0;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(loss.data(), d.loss_out, ntr * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(pred.data(), d.pred_out, ntr * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, d.cnt, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flags, d.ctl + eprop::CTL_ERR, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) goto device_error;
+    n->last_ntr = ntr;
+    n->last_T.assign(b->n_steps, b->n_steps + ntr);
+    if (flags) {
+      set_fail(n, "forced spike out of range");
+      return EPROP_ERR_INVALID_ARGUMENT;
+    }
+    bool finite_all = true;
+    for (uint32_t i = 0; i < ntr; ++i) finite_all = finite_all && std::isfinite(loss[i]);
+    if (train) n->trials_accum += ntr;
+    if (res) {
+      if (res->loss) std::memcpy(res->loss, loss.data(), ntr * 8);
+      if (res->predicted) std::memcpy(res->predicted, pred.data(), ntr * 4);
+      res->n_rec_spikes = cnt[eprop::CNT_REC_SPIKES];
+      res->n_in_spikes = b->n_in_spikes;
+      res->n_syn_events = cnt[eprop::CNT_EVENTS];
+      res->n_out_events = cnt[eprop::CNT_REC_SPIKES] * n->K;
+      res->n_eprop_updates = train ? cnt[eprop::CNT_EVENTS] : 0;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, n->ev[0], n->ev[7]);
+      res->device_ms = ms;
+      for (int p = 0; p < EPROP_N_PHASES; ++p) res->phase_ms[p] = 0;
+      if (prof) {
+        const int upto = train ? 6 : 3;
+        for (int p = 0; p < upto; ++p) {
+          float m = 0;
+          (void)hipEventElapsedTime(&m, n->ev[p], n->ev[p + 1]);
+          res->phase_ms[p] = m;
+        }
+      }
+    }
+    if (!finite_all) {
+      n->failed = true;
+      set_fail(n, "non-finite loss");
+      return EPROP_ERR_NUMERIC;
+    }
+  }
+  n->err.clear();
+  return EPROP_OK;
+
+device_error:
+  n->failed = true;
+  set_fail(n, std::string("device error: ") + hip_msg(e));
+  return EPROP_ERR_DEVICE;
+}
+
+template <typename real>
+eprop_status apply(eprop_network *n, DevNet<real> &d) {
+  const double b1 = n->cfg.adam_beta1, b2 = n->cfg.adam_beta2;
+  n->adam_step += 1;
+  const double step = (double)n->adam_step;
+  // eq. eta-adam-fast
+  const double eta_t = n->cfg.eta * std::sqrt(1.0 - std::pow(b2, step)) / (1.0 - std::pow(b1, step));
+  Launch<real>::apply(d, n->S, (double)n->trials_accum, n->cfg.optimizer, n->cfg.eta, eta_t, b1, b2,
+                      n->cfg.adam_eps_hat, n->stream);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+  if (e != hipSuccess) {
+    n->failed = true;
+    set_fail(n, std::string("device error: ") + hip_msg(e));
+    return EPROP_ERR_DEVICE;
+  }
+  n->trials_accum = 0;
+  n->err.clear();
+  return EPROP_OK;
+}
+
+template <typename real>
+eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t what, uint32_t trial,
+                        void *dst, size_t dst_bytes, size_t *needed) {
+  const bool per_trial = what >= EPROP_STATE_SPIKES;
+  if (what < 0 || what > EPROP_STATE_V) return EPROP_ERR_INVALID_ARGUMENT;
+  if (per_trial && n->last_ntr == 0) return EPROP_ERR_STATE;
+  if (per_trial && trial >= n->last_ntr) return EPROP_ERR_INVALID_ARGUMENT;
+  const uint32_t T = per_trial ? n->last_T[trial] : 0;
+  const size_t KJ = (size_t)n->K * n->Jp;
+  auto fetch = [&](const void *src, size_t count, std::vector<real> &out) {
+    out.resize(count);
+    return count ? hipMemcpy(out.data(), src, count * sizeof(real), hipMemcpyDeviceToHost) : hipSuccess;
+  };
+  std::vector<double> outd;
+  std::vector<uint32_t> outu;
+  uint64_t step = n->adam_step;
+  hipError_t e = hipSuccess;
+  size_t bytes = 0;
+  const void *payload = nullptr;
+  switch (what) {
+    case EPROP_STATE_W_IN:
+    case EPROP_STATE_W_REC: {
+      std::vector<real> w;
+      const bool in = what == EPROP_STATE_W_IN;
+      if (!dst) { bytes = (in ? n->S_in : n->S_rec) * 8; break; }
+      e = fetch(d.sm_w + (in ? 0 : n->S_in), in ? n->S_in : n->S_rec, w);
+      outd.assign(w.begin(), w.end());
+      break;
+    }
+    case EPROP_STATE_GRAD_IN: case EPROP_STATE_GRAD_REC:
+    case EPROP_STATE_ADAM_M_IN: case EPROP_STATE_ADAM_V_IN:
+    case EPROP_STATE_ADAM_M_REC: case EPROP_STATE_ADAM_V_REC: {
+      const bool in = what == EPROP_STATE_GRAD_IN || what == EPROP_STATE_ADAM_M_IN || what == EPROP_STATE_ADAM_V_IN;
+      const uint64_t cnt = in ? n->S_in : n->S_rec;
+      if (!dst) { bytes = cnt * 8; break; }
+      if ((what >= EPROP_STATE_ADAM_M_IN) && !n->adam) { outd.assign(cnt, 0.0); break; }
+      std::vector<real> a, c;
+      if (what == EPROP_STATE_GRAD_IN || what == EPROP_STATE_GRAD_REC) {
+        e = fetch(d.gs, n->S, a);
+        if (e == hipSuccess) e = fetch(d.gc, n->S, c);
+      } else {
+        const bool m = what == EPROP_STATE_ADAM_M_IN || what == EPROP_STATE_ADAM_M_REC;
+        e = fetch(m ? d.adam_m : d.adam_v, n->S, a);
+      }
+      outd.assign(cnt, 0.0);
+      for (uint64_t q = 0; q < n->S && e == hipSuccess; ++q) {
+        const uint32_t o = n->perm[q];
+        const bool is_in = o < n->S_in;
+        if (is_in != in) continue;
+        outd[in ? o : o - n->S_in] = (double)a[q] + (c.empty() ? 0.0 : (double)c[q]);
+      }
+      break;
+    }
+    case EPROP_STATE_W_OUT: case EPROP_STATE_GRAD_OUT: case EPROP_STATE_ADAM_M_OUT: case EPROP_STATE_ADAM_V_OUT: {
+      if (!dst) { bytes = (size_t)n->K * n->J * 8; break; }
+      std::vector<real> a, c;
+      if ((what == EPROP_STATE_ADAM_M_OUT || what == EPROP_STATE_ADAM_V_OUT) && !n->adam) {
+        outd.assign((size_t)n->K * n->J, 0.0);
+        break;
+      }
+      const real *src = what == EPROP_STATE_W_OUT ? d.w_out : what == EPROP_STATE_GRAD_OUT ? d.gos
+                        : what == EPROP_STATE_ADAM_M_OUT ? d.adam_mo : d.adam_vo;
+      e = fetch(src, KJ, a);
+      if (e == hipSuccess && what == EPROP_STATE_GRAD_OUT) e = fetch(d.goc, KJ, c);
+      outd.resize((size_t)n->K * n->J);
+      for (uint32_t k = 0; k < n->K; ++k)
+        for (uint32_t j = 0; j < n->J; ++j) {
+          const size_t i = (size_t)k * n->Jp + j;
+          outd[(size_t)k * n->J + j] = (double)a[i] + (c.empty() ? 0.0 : (double)c[i]);
+        }
+      break;
+    }
+    case EPROP_STATE_ADAM_STEP:
+      bytes = 8;
+      payload = &step;
+      break;
+    case EPROP_STATE_SPIKES: {
+      std::vector<uint64_t> bits((size_t)T * n->Jw);
+      e = hipMemcpy(bits.data(), d.rec_bits + ((size_t)trial * (n->Tcap + 1) + 1) * n->Jw, bits.size() * 8,
+                    hipMemcpyDeviceToHost);
+      for (uint32_t t = 1; t <= T && e == hipSuccess; ++t)
+        for (uint32_t w = 0; w < n->Jw; ++w) {
+          uint64_t word = bits[(size_t)(t - 1) * n->Jw + w];
+          while (word) {
+            const uint32_t bit = (uint32_t)__builtin_ctzll(word);
+            word &= word - 1;
+            outu.push_back(t);
+            outu.push_back(w * 64 + bit);
+          }
+        }
+      bytes = outu.size() * 4;
+      payload = outu.data();
+      break;
+    }
+    case EPROP_STATE_PSI: {
+      if (!dst) { bytes = (size_t)T * n->J * 8; break; }
+      std::vector<real> a;
+      e = fetch(d.psi + ((size_t)trial * (n->Tcap + 1) + 1) * n->Jp, (size_t)T * n->Jp, a);
+      outd.resize((size_t)T * n->J);
+      for (uint32_t t = 0; t < T && e == hipSuccess; ++t)
+        for (uint32_t j = 0; j < n->J; ++j) outd[(size_t)t * n->J + j] = (double)a[(size_t)t * n->Jp + j];
+      break;
+    }
+    case EPROP_STATE_Y: case EPROP_STATE_ERR: {
+      bytes = (size_t)T * n->K * 8;
+      if (!dst) break;
+      outd.resize((size_t)T * n->K);
+      const double *src = (what == EPROP_STATE_Y ? d.y : d.err) + ((size_t)trial * (n->Tcap + 2) + 1) * n->K;
+      e = hipMemcpy(outd.data(), src, bytes, hipMemcpyDeviceToHost);
+      break;
+    }
+    case EPROP_STATE_V: {
+      if (!dst) { bytes = (size_t)n->J * 8; break; }
+      std::vector<real> a;
+      e = fetch(d.v + (size_t)trial * n->Jp, n->J, a);
+      outd.assign(a.begin(), a.end());
+      break;
+    }
+  }
+  if (e != hipSuccess) return EPROP_ERR_DEVICE;
+  if (!payload && dst) {
+    payload = outd.data();
+    bytes = outd.size() * 8;
+  }
+  if (needed) *needed = bytes;
+  if (!dst) return EPROP_OK;
+  if (dst_bytes < bytes) return EPROP_ERR_INVALID_ARGUMENT;
+  if (bytes) std::memcpy(dst, payload, bytes);
+  return EPROP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+eprop_status eprop_simulate_batch(eprop_network *net, const eprop_batch *batch, eprop_batch_result *res) {
+  if (!net || !batch) return EPROP_ERR_INVALID_ARGUMENT;
+  if (net->failed) return EPROP_ERR_STATE;
+  return net->fp64 ? simulate(net, net->n64, batch, res) : simulate(net, net->n32, batch, res);
+}
+
+eprop_status eprop_apply_updates(eprop_network *net) {
+  if (!net) return EPROP_ERR_INVALID_ARGUMENT;
+  if (net->failed) return EPROP_ERR_STATE;
+  if (net->trials_accum == 0) {
+    set_fail(net, "no trials trained since the last update");
+    return EPROP_ERR_STATE;
+  }
+  return net->fp64 ? apply(net, net->n64) : apply(net, net->n32);
+}
+
+eprop_status eprop_read_state(const eprop_network *net, int32_t what, uint32_t trial, void *dst,
+                              size_t dst_bytes, size_t *bytes_needed) {
+  if (!net) return EPROP_ERR_INVALID_ARGUMENT;
+  return net->fp64 ? read_state(net, net->n64, what, trial, dst, dst_bytes, bytes_needed)
+                   : read_state(net, net->n32, what, trial, dst, dst_bytes, bytes_needed);
+}
+
+}  // extern "C"

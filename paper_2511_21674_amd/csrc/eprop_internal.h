@@ -1,0 +1,100 @@
+// Internal device-side description of one network and the launchers of
+// its kernels.  Shared by eprop_kernels.hip and eprop_host.cpp only.
+//
+// HBM layout (b = trial slot, j = neuron, t = step 1..T, Jp = J padded to 64):
+//   graph, source-major  sm_ptr[NS+1], sm_syn[S] = target | delay << 24, sm_w[S]
+//   graph, target-major  tm_ptr[J+1], tm_syn[S] = source | delay << 24, tm_w[S]
+//                        (sources: inputs 0..I-1, then recurrent I..I+J-1;
+//                        each target's list sorted by source), tm_perm[S]
+//                        (target-major index -> source-major index)
+//   gradient sums        gs[S], gc[S] (Kahan pair, target-major), Adam m, v
+//   neuron state         v[b][Jp], a[b][Jp], nst[b][Jp] (refractory count | z << 7)
+//   delay ring           ring[b][R][Jp], R = max_delay + 1 (scatter delivery)
+//   psi archive          psi[b][t][Jp]          (time-major, written per step)
+//   arrival archive      phi[b][j][t]           (neuron-major, stride Tp)
+//   spike bitsets        rec_bits[b][t][Jw], in_bits[b][s][Iw], forced_bits[b][t][Jw]
+//   spike-time lists     spk_cnt[b][NS], spk_t[b][src*Tcap + k] (uint16, ascending)
+//   per-step spikes      rec_cnt[b][t], rec_list[b][t & 1][Jp]
+//   readout (FP64)       ysum/pi[b][t][K], y[b][t][K], err[b][t][K], ebar[b][t][K]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eprop {
+
+// ctl words; the 64-bit device pointer to the batch's input-source array is
+// stored at word CTL_WORDS (byte offset 64)
+enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
+enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_LABEL = 8u };
+enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_WORDS = 8 };
+
+template <typename real>
+struct DevNet {
+  // sizes
+  uint32_t I, J, K, NS, Jp, Jw, Iw, R, Tcap, Tp, Bcap;
+  uint64_t spk_stride;          // per-slot size of spk_t (NS * Tcap)
+  uint32_t n_ref;
+  int32_t surrogate, loss;
+  uint32_t step_stride;         // batch target/window row length
+  // constants (working precision for the dynamics, FP64 for the backward filters)
+  real alpha, rho, v_th, sg_gamma, sg_beta;
+  double alpha_d, rho_d, kappa_d;
+  // graph
+  const uint32_t *sm_ptr, *sm_syn;
+  real *sm_w;
+  const uint32_t *tm_ptr, *tm_syn, *tm_perm;
+  real *tm_w, *gs, *gc, *adam_m, *adam_v;
+  const real *beta_j;           // beta_a for ALIF neurons, 0 for LIF [Jp]
+  real *w_out, *fb;             // [K][Jp], [Jp][K]
+  real *gos, *goc, *adam_mo, *adam_vo;   // [K][Jp]
+  real *gout_b;                 // [Bcap][K][Jp]
+  // per-slot state
+  real *v, *a;
+  uint8_t *nst;
+  real *ring, *psi, *phi;
+  uint64_t *rec_bits, *in_bits, *forced_bits;
+  uint32_t *spk_cnt;
+  uint16_t *spk_t;
+  uint32_t *rec_cnt, *rec_list;
+  uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
+  double *ysum, *y, *err, *ebar;  // [Bcap][Tcap+2][K]
+  double *loss_out;             // [Bcap]
+  uint32_t *pred_out;           // [Bcap]
+  // batch (device pointers)
+  const uint32_t *T, *label;
+  const uint64_t *in_ptr;
+  const uint32_t *in_step, *in_src;
+  const double *target;
+  const uint8_t *window;
+  const uint64_t *forced_ptr;
+  const uint32_t *forced_step, *forced_neuron;
+  // control
+  uint32_t *ctl;
+  unsigned long long *cnt;
+};
+
+// Launch shapes (chosen on the host; the autotuner may change them)
+struct Shapes {
+  uint32_t deliver_blocks_per_trial;
+  uint32_t syn_blocks;
+  uint32_t block;               // threads per block for grid-stride kernels
+};
+
+template <typename real>
+struct Launch {
+  static void stage_inputs(const DevNet<real> &n, uint32_t n_trials, uint64_t n_spikes, bool check_order,
+                           hipStream_t s);
+  static void stage_forced(const DevNet<real> &n, uint32_t n_trials, uint64_t n_forced, hipStream_t s);
+  static void neuron(const DevNet<real> &n, uint32_t off, bool gather, bool forced, hipStream_t s);
+  static void deliver(const DevNet<real> &n, const Shapes &sh, uint32_t off, hipStream_t s);
+  static void readout(const DevNet<real> &n, hipStream_t s);
+  static void adjoint(const DevNet<real> &n, hipStream_t s);
+  static void synapse(const DevNet<real> &n, const Shapes &sh, hipStream_t s);
+  static void output_reduce(const DevNet<real> &n, hipStream_t s);
+  static void apply(const DevNet<real> &n, uint64_t n_syn, double n_trials, int optimizer, double eta,
+                    double eta_t, double b1, double b2, double eps_hat, hipStream_t s);
+};
+
+void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s);
+
+}  // namespace eprop

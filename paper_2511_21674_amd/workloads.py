@@ -421,7 +421,7 @@ def c3_events(seed: int = SEED_BASE + 3, batch_size: int = 128, iterations: int 
 
 
 def _large_sparse(name: str, seed: int, n_rec: int, indeg_rec: int, n_in: int, indeg_in: int,
-                  rate_in_hz: float, n_steps: int, batch_size: int, gain: float,
+                  rate_in_hz: float, n_steps: int, batch_size: int, gain: float, in_gain: float,
                   alif_fraction: float, iterations: int, description: str) -> Workload:
     n_out = 10
     is_alif = np.zeros(n_rec, np.uint8)
@@ -433,7 +433,7 @@ def _large_sparse(name: str, seed: int, n_rec: int, indeg_rec: int, n_in: int, i
     rec = fixed_indegree_projection(n_rec, n_rec, indeg_rec, gain / np.sqrt(indeg_rec),
                                     rng(seed, _P_GRAPH_REC), rng(seed, _P_W_REC),
                                     rng(seed, _P_DELAY_REC), no_self=True, delay_lo=1, delay_hi=5)
-    inp = fixed_indegree_projection(n_in, n_rec, indeg_in, 1.0 / np.sqrt(indeg_in),
+    inp = fixed_indegree_projection(n_in, n_rec, indeg_in, in_gain / np.sqrt(indeg_in),
                                     rng(seed, _P_GRAPH_IN), rng(seed, _P_W_IN),
                                     rng(seed, _P_DELAY_IN), no_self=False, delay_lo=1, delay_hi=1)
     net = Network(n_in, n_rec, n_out, is_alif, prm, inp, rec,
@@ -449,33 +449,35 @@ def _large_sparse(name: str, seed: int, n_rec: int, indeg_rec: int, n_in: int, i
             trials.append((n_steps, s, c))
         return _assemble(trials, n_out, n_steps, targets=[targets] * n)
     return Workload(name, net, make_batch, batch_size, iterations, description,
-                    info={"gain": gain, "indeg_rec": indeg_rec, "indeg_in": indeg_in})
+                    info={"gain": gain, "in_gain": in_gain, "indeg_rec": indeg_rec, "indeg_in": indeg_in})
 
 
 # Recurrent gains chosen once so that the free-running recurrent rate lies near
 # the configured target (about 10 Hz for the 1e5-neuron network, about 5 Hz for
 # the 1e6-neuron one); measured rates are always reported next to results.
-C4_GAIN = 0.5
-C5_GAIN = 0.5
+C4_GAIN, C4_IN_GAIN = 0.5, 0.75
+C5_GAIN, C5_IN_GAIN = 0.5, 1.0
 
 
 def c4_sparse(seed: int = SEED_BASE + 4, n_rec: int = 100_000, n_steps: int = 1000,
               batch_size: int = 4, iterations: int = 2, gain: float = None,
-              n_in: int = 1000) -> Workload:
+              n_in: int = 1000, in_gain: float = None) -> Workload:
     """Large sparse network: fixed in-degree 1000, delays 1-5, 1000 Poisson
     inputs at 20 Hz with in-degree 100, 10 readouts (MSE on sinusoid sums)."""
     return _large_sparse("c4_sparse", seed, n_rec, min(1000, n_rec - 1), n_in, min(100, n_in),
-                         20.0, n_steps, batch_size, C4_GAIN if gain is None else gain, 0.0,
+                         20.0, n_steps, batch_size, C4_GAIN if gain is None else gain,
+                         C4_IN_GAIN if in_gain is None else in_gain, 0.0,
                          iterations, "1e5 LIF, in-degree 1000 (1e8 synapses), batch 4")
 
 
 def c5_million(seed: int = SEED_BASE + 5, n_rec: int = 1_000_000, n_steps: int = 2000,
                batch_size: int = 1, iterations: int = 1, gain: float = None,
-               n_in: int = 10_000) -> Workload:
+               n_in: int = 10_000, in_gain: float = None) -> Workload:
     """Million-neuron network: 80/20 LIF/ALIF, fixed in-degree 100, delays 1-5,
     10,000 Poisson inputs at 5 Hz with in-degree 10, 10 readouts."""
     return _large_sparse("c5_million", seed, n_rec, min(100, n_rec - 1), n_in, min(10, n_in),
-                         5.0, n_steps, batch_size, C5_GAIN if gain is None else gain, 0.2,
+                         5.0, n_steps, batch_size, C5_GAIN if gain is None else gain,
+                         C5_IN_GAIN if in_gain is None else in_gain, 0.2,
                          iterations, "1e6 LIF/ALIF, in-degree 100 (1e8 synapses), batch 1")
 
 

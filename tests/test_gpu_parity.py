@@ -1,0 +1,323 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (relative, normwise and per entry with a floor, see
+tests/helpers.rel_close):
+  * FP64: spike trains identical, gradients and weights within 1e-10;
+  * FP32 with teacher-forced spike trains: per-iteration weight change
+    within 1e-4;
+  * FP32 free running: mean loss over the last iterations within 2% of the
+    oracle's, averaged over seeds (single runs diverge by spike flips).
+"""
+import numpy as np
+import pytest
+
+from paper_2511_21674_amd import eprop as E
+from paper_2511_21674_amd import workloads as W
+import oracle as O
+from tests.helpers import rel_close, small_net, batch_from
+
+pytestmark = pytest.mark.gpu
+KEYS = ("w_in", "w_rec", "w_out")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def gpu_train(wl, precision, iterations, bs, delivery="auto", forced_rate=None, device=False,
+              max_steps=None, record=True):
+    T = max_steps or max(int(wl.make_batch(it, 0, bs).n_steps.max()) for it in range(iterations))
+    net = E.Network(wl.network, precision, max_trials=bs, max_steps=T, delivery=delivery)
+    hist = {"loss": [], "spikes": [], "grads": [], "weights": [], "dw": []}
+    w_prev = net.weights()
+    for it in range(iterations):
+        b = wl.make_batch(it, 0, bs)
+        if forced_rate:
+            b = W.forced_poisson(b, wl.network.n_rec, forced_rate, wl.network.params.dt, seed=99,
+                                 iteration=it, n_ref=2)
+        r = net.simulate(b, train=True, device=device)
+        hist["loss"].append(r.loss.copy())
+        if record:
+            hist["spikes"].append([net.spikes(i, int(b.n_steps[i])) for i in range(b.n_trials)])
+            hist["grads"].append(net.grads())
+        net.apply()
+        w = net.weights()
+        hist["weights"].append(w)
+        hist["dw"].append({k: w[k] - w_prev[k] for k in KEYS})
+        w_prev = w
+    net.close()
+    return hist
+
+
+def oracle_train(wl, iterations, bs, forced_rate=None, grad_mode=2):
+    on = O.OracleNet(wl.network)
+    hist = {"loss": [], "spikes": [], "grads": [], "weights": [], "dw": []}
+    w_prev = {k: getattr(on, k).copy() for k in KEYS}
+    for it in range(iterations):
+        b = wl.make_batch(it, 0, bs)
+        if forced_rate:
+            b = W.forced_poisson(b, wl.network.n_rec, forced_rate, wl.network.params.dt, seed=99,
+                                 iteration=it, n_ref=2)
+        g = O.zero_grads(on)
+        losses, spikes = [], []
+        for i in range(b.n_trials):
+            r = O.run_trial(on, b, i, grad_mode, g, trace=True)
+            losses.append(r.loss)
+            spikes.append(r.trace["z"])
+        hist["loss"].append(np.array(losses))
+        hist["spikes"].append(spikes)
+        hist["grads"].append({k: v.copy() for k, v in g.items()})
+        O.apply(on, g, b.n_trials)
+        w = {k: getattr(on, k).copy() for k in KEYS}
+        hist["weights"].append(w)
+        hist["dw"].append({k: w[k] - w_prev[k] for k in KEYS})
+        w_prev = w
+    return hist
+
+
+def assert_fp64_parity(gh, oh, name):
+    for it in range(len(oh["loss"])):
+        for i, (zg, zo) in enumerate(zip(gh["spikes"][it], oh["spikes"][it])):
+            assert np.array_equal(zg, zo), f"{name}: iteration {it} trial {i} spike trains differ"
+        ok, e, _ = rel_close(gh["loss"][it], oh["loss"][it], 1e-12)
+        assert ok, (name, it, "loss", e)
+        for k in KEYS:
+            ok, e, ent = rel_close(gh["grads"][it][k], oh["grads"][it][k], 1e-10)
+            assert ok, (name, it, "grad", k, e, ent)
+            ok, e, ent = rel_close(gh["weights"][it][k], oh["weights"][it][k], 1e-10)
+            assert ok, (name, it, "weights", k, e, ent)
+        log(f"{name} it {it}: spikes identical, max grad err "
+            f"{max(rel_close(gh['grads'][it][k], oh['grads'][it][k], 1)[1] for k in KEYS):.2e}")
+
+
+# ----------------------------------------------------------------- FP64: exact reproduction
+
+@pytest.mark.parametrize("loss,surrogate", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_fp64_tiny_exact(loss, surrogate):
+    wl = W.tiny(loss=loss, surrogate=surrogate)
+    gh = gpu_train(wl, "fp64", 3, 2)
+    oh = oracle_train(wl, 3, 2)
+    assert_fp64_parity(gh, oh, f"tiny loss={loss} sg={surrogate}")
+
+
+def test_fp64_c1_pattern_generation():
+    """Pattern generation as configured (GD 1e-3, 10 iterations, batch 1)."""
+    wl = W.c1_pattern()
+    gh = gpu_train(wl, "fp64", 10, 1)
+    oh = oracle_train(wl, 10, 1)
+    assert_fp64_parity(gh, oh, "c1")
+
+
+def test_fp64_c2_evidence_uneven_adam():
+    """Evidence accumulation: LIF + ALIF, softmax, learning window, Adam,
+    four trials of uneven lengths per batch."""
+    wl = W.c2_evidence(batch_size=4)
+    assert len(set(wl.make_batch(0, 0, 4).n_steps.tolist())) > 1
+    gh = gpu_train(wl, "fp64", 2, 4)
+    oh = oracle_train(wl, 2, 4)
+    assert_fp64_parity(gh, oh, "c2")
+
+
+def test_fp64_c3_events():
+    wl = W.c3_events(batch_size=4)
+    gh = gpu_train(wl, "fp64", 2, 4)
+    oh = oracle_train(wl, 2, 4)
+    assert_fp64_parity(gh, oh, "c3")
+
+
+@pytest.mark.parametrize("delivery", ["gather", "scatter"])
+def test_fp64_sparse_twin_with_delays(delivery):
+    """Twin of the 1e5-neuron network (fixed in-degree 1000, delays 1..5:
+    the delay ring wraps around); scatter adds in a free order, so spikes are
+    compared exactly only where they are reproducible (gather)."""
+    wl = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300)
+    gh = gpu_train(wl, "fp64", 2, 2, delivery=delivery)
+    oh = oracle_train(wl, 2, 2)
+    if delivery == "gather":
+        assert_fp64_parity(gh, oh, "c4twin gather")
+    else:
+        for it in range(2):
+            for k in KEYS:
+                ok, e, ent = rel_close(gh["weights"][it][k], oh["weights"][it][k], 1e-10)
+                assert ok, ("scatter weights", it, k, e, ent)
+
+
+def test_fp64_deterministic_and_batch_invariant():
+    """Two runs are bitwise equal; a trial run alone equals the same trial
+    inside a batch (parallel copies equal sequential samples)."""
+    wl = W.c2_evidence(batch_size=4)
+    b = wl.make_batch(0, 0, 4)
+    T = int(b.n_steps.max())
+    runs = []
+    for _ in range(2):
+        net = E.Network(wl.network, "fp64", max_trials=4, max_steps=T)
+        r = net.simulate(b)
+        runs.append((r.loss.copy(), net.grads(), [net.spikes(i, int(b.n_steps[i])) for i in range(4)]))
+        net.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for k in KEYS:
+        assert np.array_equal(runs[0][1][k], runs[1][1][k])
+    net = E.Network(wl.network, "fp64", max_trials=4, max_steps=T)
+    gsum = {k: 0.0 for k in KEYS}
+    for i in range(4):
+        r = net.simulate(b.trial(i))
+        assert r.loss[0] == runs[0][0][i]
+        assert np.array_equal(net.spikes(0, int(b.n_steps[i])), runs[0][2][i])
+    g = net.grads()
+    for k in KEYS:
+        assert rel_close(g[k], runs[0][1][k], 1e-13)[0]
+    net.close()
+
+
+def test_device_memory_batch_equals_host_batch():
+    wl = W.c3_events(batch_size=3)
+    b = W.forced_poisson(wl.make_batch(0, 0, 3), wl.network.n_rec, 15.0, 1.0, seed=5, n_ref=2)
+    out = []
+    for device in (False, True):
+        net = E.Network(wl.network, "fp64", max_trials=3, max_steps=300)
+        r = net.simulate(b, device=device)
+        out.append((r.loss.copy(), net.grads()))
+        net.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for k in KEYS:
+        assert np.array_equal(out[0][1][k], out[1][1][k])
+
+
+# ----------------------------------------------------------------- FP32
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4twin", "tiny"])
+def test_fp32_teacher_forced_weight_updates(name):
+    """FP32 with the oracle's (teacher-forced) spike trains: every
+    iteration's weight change within 1e-4 relative of the FP64 oracle's."""
+    if name == "c1":
+        # as configured (GD 1e-3) the loss grows to 1e9 by the third iteration;
+        # the check runs in the trained regime instead
+        wl, bs, it = W.c1_pattern(), 1, 3
+        wl.network.params.eta = 2e-5
+    elif name == "c2":
+        wl, bs, it = W.c2_evidence(batch_size=4), 4, 2
+    elif name == "c3":
+        wl, bs, it = W.c3_events(batch_size=4), 4, 2
+    elif name == "c4twin":
+        wl, bs, it = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), 2, 2
+    else:
+        wl, bs, it = W.tiny(), 2, 3
+    gh = gpu_train(wl, "fp32", it, bs, forced_rate=20.0, record=False)
+    oh = oracle_train(wl, it, bs, forced_rate=20.0)
+    for i in range(it):
+        for k in KEYS:
+            ok, e, ent = rel_close(gh["dw"][i][k], oh["dw"][i][k], 1e-4)
+            log(f"{name} it {i} dW {k}: normwise {e:.2e} worst entry {ent:.2e}")
+            assert ok, (name, i, k, e, ent)
+        assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
+
+
+def test_fp32_free_running_final_loss():
+    """Trained pattern-generation runs (learning rate lowered so that the
+    loss converges): FP32 final loss within 2% of the FP64 oracle's, as the
+    mean over the last 10 of 20 iterations and over 3 seeds."""
+    g_final, o_final = [], []
+    for s in range(3):
+        wl = W.c1_pattern(seed=W.SEED_BASE + 100 + s)
+        wl.network.params.eta = 2e-5
+        gh = gpu_train(wl, "fp32", 20, 1, record=False)
+        oh = oracle_train(wl, 20, 1)
+        g_final.append(np.mean([l.mean() for l in gh["loss"][10:]]))
+        o_final.append(np.mean([l.mean() for l in oh["loss"][10:]]))
+        log(f"seed {s}: first loss {oh['loss'][0][0]:.1f}, final gpu {g_final[-1]:.2f} oracle {o_final[-1]:.2f}")
+        assert o_final[-1] < 0.9 * oh["loss"][0][0]   # training reduced the loss
+    rel = abs(np.mean(g_final) - np.mean(o_final)) / np.mean(o_final)
+    log(f"mean final loss gpu {np.mean(g_final):.3f} oracle {np.mean(o_final):.3f} rel {rel:.3e}")
+    assert rel < 0.02
+
+
+# ----------------------------------------------------------------- edge cases
+
+def test_silent_network_and_single_step_trial():
+    """No input spikes: no recurrent spikes, all gradients of plastic synapses
+    exactly zero, loss 1/2 sum y*^2; a one-step trial runs."""
+    net_w = small_net(3, 4, 2, [(0, 1, 0.5, 1), (2, 3, 0.1, 1)], [(1, 2, 0.3, 1), (3, 0, -0.2, 2)])
+    tg = np.random.default_rng(1).normal(size=(50, 2))
+    b = batch_from(50, [], 2, target=tg)
+    net = E.Network(net_w, "fp32", max_trials=1, max_steps=50)
+    r = net.simulate(b)
+    assert r.n_rec_spikes == 0 and r.n_syn_events == 0
+    assert r.loss[0] == pytest.approx(0.5 * (tg ** 2).sum(), rel=1e-12)
+    g = net.grads()
+    assert np.all(g["w_in"] == 0) and np.all(g["w_rec"] == 0) and np.all(g["w_out"] == 0)
+    r = net.simulate(batch_from(1, [(0, 0)], 2, target=tg[:1]))
+    assert r.n_rec_spikes == 1 and r.n_syn_events == 0   # the spike at step 1 arrives at step 2 > T
+    net.close()
+
+
+def test_errors_are_reported():
+    wl = W.tiny()
+    b = wl.make_batch(0, 0, 2)
+    net = E.Network(wl.network, "fp32", max_trials=2, max_steps=100)
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(b)                               # 200-step trials > max_steps
+    assert ei.value.status == E.EPROP_ERR_CAPACITY
+    with pytest.raises(E.EpropError) as ei:
+        net.apply()                                   # nothing trained yet
+    assert ei.value.status == E.EPROP_ERR_STATE
+    with pytest.raises(E.EpropError) as ei:
+        net.read(E.EPROP_STATE_PSI, 0)                # no batch yet
+    assert ei.value.status == E.EPROP_ERR_STATE
+    net.close()
+    net = E.Network(wl.network, "fp32", max_trials=2, max_steps=200)
+    bad = wl.make_batch(0, 0, 2)
+    bad.in_step = bad.in_step[::-1].copy()            # unsorted (host memory: host check)
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(bad)
+    assert ei.value.status == E.EPROP_ERR_INVALID_ARGUMENT
+    bad = wl.make_batch(0, 0, 2)
+    bad.in_src = bad.in_src.copy()
+    bad.in_src[3] = 1000                              # out of range (device memory: kernel check)
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(bad, device=True)
+    assert ei.value.status == E.EPROP_ERR_INVALID_ARGUMENT
+    r = net.simulate(wl.make_batch(0, 0, 2))          # the handle is still usable
+    assert np.all(np.isfinite(r.loss))
+    net.apply()
+    assert net.read(E.EPROP_STATE_ADAM_STEP)[0] == 1
+    net.close()
+
+
+# ----------------------------------------------------------------- full size, sampled
+
+def test_full_size_sparse_network_sampled():
+    """1e5 neurons, in-degree 1000, delays 1..5, 4 trials per batch, FP32
+    scatter (the benchmark's launch configuration), teacher-forced at 10 Hz:
+    the gradients of every incoming synapse of 24 sampled neurons, summed
+    over the 4 trials, within 1e-4 of the oracle's per-neuron evaluation, and
+    the per-trial losses within 1e-6."""
+    wl = W.c4_sparse()
+    b = W.forced_poisson(wl.make_batch(0, 0, 4), wl.network.n_rec, 10.0, 1.0, seed=7, n_ref=2)
+    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=1000)
+    r = net.simulate(b, train=True)
+    g = net.grads()
+    net.close()
+    log(f"gpu done: {r.n_rec_spikes} spikes, {r.n_syn_events} events")
+    on = O.OracleNet(wl.network)
+    rng = np.random.default_rng(0)
+    targets = np.sort(rng.choice(wl.network.n_rec, 24, replace=False))
+    gi = np.zeros_like(on.w_in)
+    gr = np.zeros_like(on.w_rec)
+    for i in range(4):
+        loss, psi, a, c = O.forced_sampled(on, b, i, targets)
+        assert abs(r.loss[i] - loss) <= 1e-6 * abs(loss), (i, r.loss[i], loss)
+        mi, mr = ~np.isnan(a), ~np.isnan(c)
+        gi[mi] += a[mi]
+        gr[mr] += c[mr]
+    for name, gg, ref, m in (("w_in", g["w_in"], gi, mi), ("w_rec", g["w_rec"], gr, mr)):
+        ok, e, ent = rel_close(gg[m], ref[m], 1e-4)
+        log(f"full size {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
+        assert ok, (name, e, ent)
