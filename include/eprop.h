@@ -209,7 +209,7 @@ typedef struct {
   double *loss;                  /* [n_trials] caller-owned or NULL: per-trial loss */
   uint32_t *predicted;           /* [n_trials] or NULL: argmax_k of the window-summed pi (CE) */
   uint64_t n_rec_spikes, n_in_spikes;
-  uint64_t n_syn_events;         /* input + recurrent deliveries arriving within their trial */
+  uint64_t n_syn_events;         /* input + recurrent deliveries arriving within their trial (TRAIN) */
   uint64_t n_out_events;         /* recurrent spikes x readouts */
   uint64_t n_eprop_updates;      /* arrival evaluations on plastic synapses (TRAIN only) */
   double device_ms;              /* device time of the whole call (HIP events) */
@@ -249,7 +249,10 @@ typedef enum {
   EPROP_STATE_PSI = 14,        /* last batch, trial: double [T_b * J], row t-1 */
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
-  EPROP_STATE_V = 17           /* last batch, trial: double [J] membrane potential at T_b */
+  EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
+  EPROP_STATE_LAYOUT = 18      /* uint64 [8]: neurons per tile, tiles per trial, lanes per source,
+                                  threads per tile, synapse-kernel threads, trials per synapse
+                                  block, steps per forward launch, gather delivery (0/1) */
 } eprop_state_id;
 
 /* Copies one state array to host memory dst (dst_bytes large).  With

@@ -42,6 +42,9 @@ struct eprop_network {
   DevNet<double> n64{};
   Shapes shapes{};
   std::vector<uint32_t> perm;       // target-major index -> caller's synapse index
+  std::vector<uint32_t> sm2caller;  // internal source-major index -> caller's synapse index
+  size_t tile_smem = 0;             // dynamic LDS of the tiled forward kernel
+  void *partial = nullptr;          // per trial-chunk synapse sums (large batches)
   uint32_t trials_accum = 0;
   uint64_t adam_step = 0;
   // library-owned staging copies of host-memory batches
@@ -160,7 +163,9 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   const size_t B = n->Bcap, T1 = (size_t)n->Tcap + 1, T2 = (size_t)n->Tcap + 2;
   d.I = n->I; d.J = n->J; d.K = n->K; d.NS = n->NS; d.Jp = n->Jp; d.Jw = n->Jw; d.Iw = n->Iw;
   d.R = n->R; d.Tcap = n->Tcap; d.Tp = n->Tp; d.Bcap = n->Bcap;
-  d.spk_stride = (uint64_t)n->NS * n->Tcap;
+  d.Lc = round_up(n->Tcap, 8);
+  d.spk_stride = (uint64_t)n->NS * d.Lc;
+  d.S = n->S;
   d.n_ref = n->n_ref;
   d.surrogate = n->cfg.surrogate;
   d.loss = n->cfg.loss;
@@ -170,7 +175,15 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   uint32_t *p32;
   real *pr;
   bool ok = true;
+  d.TS = n->n32.TS ? n->n32.TS : n->n64.TS;
+  d.KT = n->n32.KT ? n->n32.KT : n->n64.KT;
+  d.grp = n->n32.grp ? n->n32.grp : n->n64.grp;
   ok &= dalloc(n, &p32, n->NS + 1); d.sm_ptr = p32;
+  if (!n->gather) {
+    ok &= dalloc(n, &p32, (size_t)n->NS * (d.KT + 1)); d.tseg = p32;
+  }
+  ok &= dalloc(n, &d.nspk, B * T1);
+  ok &= dalloc(n, &d.bar, B * 2);
   ok &= dalloc(n, &p32, n->S); d.sm_syn = p32;
   ok &= dalloc(n, &d.sm_w, n->S);
   ok &= dalloc(n, &p32, n->J + 1); d.tm_ptr = p32;
@@ -197,7 +210,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.v, B * n->Jp);
   ok &= dalloc(n, &d.a, B * n->Jp);
   ok &= dalloc(n, &d.nst, B * n->Jp);
-  if (!n->gather) ok &= dalloc(n, &d.ring, B * n->R * n->Jp);
+  ok &= dalloc(n, &d.ring, B * n->R * n->Jp);
   ok &= dalloc(n, &d.psi, B * T1 * n->Jp);
   ok &= dalloc(n, &d.phi, B * n->Jp * n->Tp);
   ok &= dalloc(n, &d.rec_bits, B * T1 * n->Jw);
@@ -215,12 +228,20 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.pred_out, B);
   ok &= dalloc(n, &d.ctl, 64);
   ok &= dalloc(n, &d.cnt, eprop::CNT_WORDS);
+  ok &= dalloc(n, &d.evcnt, 64);
+  const uint32_t nchunk_max = (n->Bcap + n->shapes.ginst - 1) / n->shapes.ginst;
+  if (nchunk_max > 1) {
+    real *part = nullptr;
+    ok &= dalloc(n, &part, (size_t)nchunk_max * n->S);
+    n->partial = part;
+  }
   return ok;
 }
 
 // Uploads graph, weights and optimiser state (host arrays in double).
 template <typename real>
 hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t> &sm_ptr,
+                  const std::vector<uint32_t> &tseg,
                   const std::vector<uint32_t> &sm_syn, const std::vector<double> &sm_w,
                   const std::vector<uint32_t> &tm_ptr, const std::vector<uint32_t> &tm_syn,
                   const std::vector<uint32_t> &tm_perm, const std::vector<double> &tm_w,
@@ -236,6 +257,7 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     return o;
   };
   cp((void *)d.sm_ptr, sm_ptr.data(), sm_ptr.size() * 4);
+  if (!n->gather) cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
   cp((void *)d.sm_syn, sm_syn.data(), sm_syn.size() * 4);
   { auto o = conv(sm_w); cp(d.sm_w, o.data(), o.size() * sizeof(real)); }
   cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
@@ -262,7 +284,7 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     std::vector<double> m(n->S, 0.0), v(n->S, 0.0), mo(KJ, 0.0), vo(KJ, 0.0);
     if (opt) {
       for (uint64_t q = 0; q < n->S; ++q) {
-        const uint32_t c = tm_perm[q];
+        const uint32_t c = n->perm[q];
         const double *ms = c < n->S_in ? opt->m_in : opt->m_rec;
         const double *vs = c < n->S_in ? opt->v_in : opt->v_rec;
         const uint64_t o = c < n->S_in ? c : c - n->S_in;
@@ -356,14 +378,31 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   std::vector<double> sm_w(S), tm_w(S);
   for (uint32_t i = 0; i <= I; ++i) sm_ptr[i] = (uint32_t)in_rec->row_ptr[i];
   for (uint32_t i = 1; i <= J; ++i) sm_ptr[I + i] = (uint32_t)(S_in + rec_rec->row_ptr[i]);
-  for (int kind = 0; kind < 2; ++kind) {
-    const eprop_projection *p = kind == 0 ? in_rec : rec_rec;
-    const uint64_t base = kind == 0 ? 0 : S_in;
-    for (uint64_t q = 0; q < p->nnz; ++q) {
-      const uint32_t d = p->delay ? p->delay[q] : 1u;
-      sm_syn[base + q] = p->col[q] | (d << 24);
-      sm_w[base + q] = p->w[q];
-      tm_ptr[p->col[q] + 1]++;
+  // internal source-major order: each row sorted by target (stable), so that
+  // the targets of one tile form one contiguous segment of the row
+  std::vector<uint32_t> sm2caller(S);
+  {
+    std::vector<uint32_t> idx;
+    for (uint32_t src = 0; src < NS; ++src) {
+      const bool in = src < I;
+      const eprop_projection *p = in ? in_rec : rec_rec;
+      const uint64_t lo = in ? in_rec->row_ptr[src] : rec_rec->row_ptr[src - I];
+      const uint64_t hi = in ? in_rec->row_ptr[src + 1] : rec_rec->row_ptr[src - I + 1];
+      idx.resize(hi - lo);
+      for (uint64_t q = lo; q < hi; ++q) idx[q - lo] = (uint32_t)q;
+      bool sorted = true;
+      for (size_t i = 1; i < idx.size() && sorted; ++i) sorted = p->col[idx[i - 1]] <= p->col[idx[i]];
+      if (!sorted)
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return p->col[x] < p->col[y]; });
+      const uint64_t base = in ? 0 : S_in;
+      for (size_t i = 0; i < idx.size(); ++i) {
+        const uint64_t pos = sm_ptr[src] + i, q = idx[i];
+        const uint32_t d = p->delay ? p->delay[q] : 1u;
+        sm_syn[pos] = p->col[q] | (d << 24);
+        sm_w[pos] = p->w[q];
+        sm2caller[pos] = (uint32_t)(base + q);
+        tm_ptr[p->col[q] + 1]++;
+      }
     }
   }
   for (uint32_t j = 0; j < J; ++j) tm_ptr[j + 1] += tm_ptr[j];
@@ -423,10 +462,61 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   n->stream = static_cast<hipStream_t>(hip_stream);
   n->perm = tm_perm;
   n->adam_step = opt ? opt->step : 0;
-  n->blk = std::min<uint32_t>(50, n->Tcap);
   n->shapes.block = 256;
-  n->shapes.deliver_blocks_per_trial = std::max<uint32_t>(1, std::min<uint32_t>(512, 1024 / n->Bcap));
-  n->shapes.syn_blocks = std::max<uint32_t>(1, std::min<uint32_t>((J + 3) / 4, 4096));
+  {
+    // synapse kernel: a block per (target, chunk of trials); the chunk's
+    // archive rows must fit 16 KB of LDS, and small networks with many
+    // trials use smaller chunks to fill the device
+    const size_t row = (size_t)n->Tp * (n->fp64 ? 8 : 4);
+    uint32_t g = (uint32_t)std::max<size_t>(1, 16384 / row);
+    g = std::min<uint32_t>(std::min<uint32_t>(g, n->Bcap), 8);
+    const uint64_t par = (uint64_t)n->Bcap * J / 4096;
+    g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, par));
+    n->shapes.ginst = g;
+    const double indeg = (double)S / J;
+    uint32_t sb = 64;
+    while (sb < 256 && sb < indeg) sb += 64;
+    n->shapes.syn_block = sb;
+  }
+  n->sm2caller = std::move(sm2caller);
+  for (uint64_t q = 0; q < S; ++q) n->perm[q] = n->sm2caller[tm_perm[q]];
+  // Tiles of the persistent forward kernel: as many neurons per workgroup as
+  // LDS allows, but enough tiles to spread the trials over the device; small
+  // networks keep a whole trial in one workgroup (no inter-workgroup barrier).
+  uint32_t TS = n->Jp, KT = 1, grp = 1, tile_block = 64;
+  if (!n->gather) {
+    const size_t rs = n->fp64 ? 8 : 4;
+    size_t lds = prop.sharedMemPerBlock;
+    if (prop.sharedMemPerBlockOptin > lds) lds = prop.sharedMemPerBlockOptin;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0 && lds > prop.maxSharedMemoryPerMultiProcessor)
+      lds = prop.maxSharedMemoryPerMultiProcessor;
+    const size_t fixed = 1024;  // static LDS of the kernel and slack
+    uint32_t ts_lds = (uint32_t)(((lds - fixed) / ((n->R + 3) * rs + 2)) / 64 * 64);
+    while (ts_lds > 64 && (n->fp64 ? Launch<double>::tile_smem(ts_lds, n->R) : Launch<float>::tile_smem(ts_lds, n->R)) + fixed > lds)
+      ts_lds -= 64;
+    const uint32_t cu = std::max(1, prop.multiProcessorCount);
+    const uint32_t want = std::max<uint32_t>(1, cu / n->Bcap);
+    uint32_t ts_par = round_up((J + want - 1) / want, 64);
+    ts_par = std::max<uint32_t>(ts_par, std::min<uint32_t>(n->Jp, 1024));
+    TS = std::min(std::min(ts_lds, ts_par), n->Jp);
+    TS = std::max<uint32_t>(TS, 64);
+    KT = (n->Jp + TS - 1) / TS;
+    tile_block = std::min<uint32_t>(1024, TS);
+    const double avg_seg = (double)S / ((double)NS * KT);
+    grp = 1;
+    while (grp < 64 && grp * 4 < avg_seg) grp *= 2;
+    n->tile_smem = n->fp64 ? Launch<double>::tile_smem(TS, n->R) : Launch<float>::tile_smem(TS, n->R);
+    if (ts_lds < 64) {
+      g_create_error = "not enough LDS for a tile of 64 neurons";
+      delete n;
+      return EPROP_ERR_UNSUPPORTED;
+    }
+  }
+  n->shapes.tile_block = tile_block;
+  n->n32.TS = n->n64.TS = TS;
+  n->n32.KT = n->n64.KT = KT;
+  n->n32.grp = n->n64.grp = grp;
+  n->blk = std::min<uint32_t>(n->gather ? 50 : 250, n->Tcap);
 
   std::vector<double> beta(n->Jp, 0.0);
   for (uint32_t j = 0; j < J; ++j) beta[j] = (cfg->is_alif && cfg->is_alif[j]) ? cfg->beta_a : 0.0;
@@ -439,10 +529,39 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
     eprop_destroy_network(n);
     return EPROP_ERR_OUT_OF_MEMORY;
   }
-  hipError_t e = n->fp64 ? upload(n, n->n64, sm_ptr, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
-                                  feedback, opt)
-                         : upload(n, n->n32, sm_ptr, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
-                                  feedback, opt);
+  // tile segments of every source row
+  std::vector<uint32_t> tseg;
+  if (!n->gather) {
+    tseg.resize((size_t)NS * (KT + 1));
+    for (uint32_t src = 0; src < NS; ++src) {
+      uint32_t q = sm_ptr[src];
+      const uint32_t hi = sm_ptr[src + 1];
+      for (uint32_t k = 0; k <= KT; ++k) {
+        const uint64_t lo_t = (uint64_t)k * TS;
+        while (q < hi && (sm_syn[q] & 0xFFFFFFu) < lo_t) ++q;
+        tseg[(size_t)src * (KT + 1) + k] = q;
+      }
+      tseg[(size_t)src * (KT + 1) + KT] = hi;
+    }
+  }
+  hipError_t e = hipSuccess;
+  if (!n->gather) {
+    e = n->fp64 ? Launch<double>::allow_smem(n->tile_smem) : Launch<float>::allow_smem(n->tile_smem);
+    int per_cu = 0;
+    if (e == hipSuccess)
+      e = n->fp64 ? Launch<double>::resident(tile_block, n->tile_smem, &per_cu)
+                  : Launch<float>::resident(tile_block, n->tile_smem, &per_cu);
+    if (e == hipSuccess && (uint64_t)per_cu * prop.multiProcessorCount < KT) {
+      g_create_error = "the tiles of one trial cannot be resident together on this device";
+      eprop_destroy_network(n);
+      return EPROP_ERR_UNSUPPORTED;
+    }
+  }
+  if (e == hipSuccess)
+    e = n->fp64 ? upload(n, n->n64, sm_ptr, tseg, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
+                         feedback, opt)
+                : upload(n, n->n32, sm_ptr, tseg, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
+                         feedback, opt);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&n->cap_stream, hipStreamNonBlocking);
   for (auto &ev : n->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
@@ -535,9 +654,10 @@ eprop_status check_batch(eprop_network *n, const eprop_batch *b, std::vector<uin
 
 template <typename real>
 void record_block(eprop_network *n, DevNet<real> &d, bool forced, hipStream_t s) {
-  for (uint32_t o = 1; o <= n->blk; ++o) {
-    Launch<real>::neuron(d, o, n->gather, forced, s);
-    if (!n->gather) Launch<real>::deliver(d, n->shapes, o, s);
+  if (n->gather) {
+    for (uint32_t o = 1; o <= n->blk; ++o) Launch<real>::neuron_gather(d, o, forced, s);
+  } else {
+    Launch<real>::forward_tiled(d, n->blk, forced, n->shapes.tile_block, n->tile_smem, s);
   }
   eprop::launch_advance(d.ctl, n->blk, s);
 }
@@ -657,11 +777,13 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   MS(d.v, (size_t)ntr * n->Jp * sizeof(real));
   MS(d.a, (size_t)ntr * n->Jp * sizeof(real));
   MS(d.nst, (size_t)ntr * n->Jp);
-  if (!n->gather) MS(d.ring, (size_t)ntr * n->R * n->Jp * sizeof(real));
+  MS(d.ring, (size_t)ntr * n->R * n->Jp * sizeof(real));
   MS(d.in_bits, (size_t)ntr * n->Tcap * n->Iw * 8);
   MS(d.spk_cnt, (size_t)ntr * n->NS * 4);
   MS(d.rec_cnt, (size_t)ntr * T1 * 4);
+  MS(d.bar, (size_t)ntr * 2 * 4);
   MS(d.cnt, eprop::CNT_WORDS * 8);
+  MS(d.evcnt, 64 * 8);
   if (forced) MS(d.forced_bits, (size_t)ntr * T1 * n->Jw * 8);
   if (e != hipSuccess) goto device_error;
 
@@ -680,8 +802,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   }
   if (prof) (void)hipEventRecord(n->ev[1], s);
 
-  // forward: spikes emitted at step 0 are delivered first, then blocks of steps
-  if (!n->gather) Launch<real>::deliver(d, n->shapes, 0, s);
+  // forward in blocks of steps (the tiled kernel delivers step-0 inputs first)
   {
     const uint32_t nblk = (t_max + n->blk - 1) / n->blk;
     if (n->use_graph) {
@@ -698,7 +819,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   if (train) {
     Launch<real>::adjoint(d, s);
     if (prof) (void)hipEventRecord(n->ev[4], s);
-    Launch<real>::synapse(d, n->shapes, s);
+    Launch<real>::synapse(d, n->shapes, ntr, static_cast<real *>(n->partial), s);
     if (prof) (void)hipEventRecord(n->ev[5], s);
     Launch<real>::output_reduce(d, s);
     if (prof) (void)hipEventRecord(n->ev[6], s);
@@ -707,17 +828,23 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   {
     std::vector<double> loss(ntr);
     std::vector<uint32_t> pred(ntr);
-    unsigned long long cnt[eprop::CNT_WORDS] = {};
+    unsigned long long cnt[eprop::CNT_WORDS] = {}, ev[64] = {};
     uint32_t flags = 0;
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(loss.data(), d.loss_out, ntr * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(pred.data(), d.pred_out, ntr * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(cnt, d.cnt, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ev, d.evcnt, sizeof(ev), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&flags, d.ctl + eprop::CTL_ERR, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) goto device_error;
     n->last_ntr = ntr;
     n->last_T.assign(b->n_steps, b->n_steps + ntr);
+    if (flags & eprop::ERR_BARRIER) {
+      n->failed = true;
+      set_fail(n, "tile barrier timed out: the workgroups of a trial were not resident together");
+      return EPROP_ERR_DEVICE;
+    }
     if (flags) {
       set_fail(n, "forced spike out of range");
       return EPROP_ERR_INVALID_ARGUMENT;
@@ -730,9 +857,11 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
       if (res->predicted) std::memcpy(res->predicted, pred.data(), ntr * 4);
       res->n_rec_spikes = cnt[eprop::CNT_REC_SPIKES];
       res->n_in_spikes = b->n_in_spikes;
-      res->n_syn_events = cnt[eprop::CNT_EVENTS];
+      unsigned long long events = 0;
+      for (int i = 0; i < 64; ++i) events += ev[i];
+      res->n_syn_events = events;
       res->n_out_events = cnt[eprop::CNT_REC_SPIKES] * n->K;
-      res->n_eprop_updates = train ? cnt[eprop::CNT_EVENTS] : 0;
+      res->n_eprop_updates = train ? events : 0;
       float ms = 0;
       (void)hipEventElapsedTime(&ms, n->ev[0], n->ev[7]);
       res->device_ms = ms;
@@ -785,8 +914,17 @@ eprop_status apply(eprop_network *n, DevNet<real> &d) {
 template <typename real>
 eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t what, uint32_t trial,
                         void *dst, size_t dst_bytes, size_t *needed) {
-  const bool per_trial = what >= EPROP_STATE_SPIKES;
-  if (what < 0 || what > EPROP_STATE_V) return EPROP_ERR_INVALID_ARGUMENT;
+  const bool per_trial = what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V;
+  if (what < 0 || what > EPROP_STATE_LAYOUT) return EPROP_ERR_INVALID_ARGUMENT;
+  if (what == EPROP_STATE_LAYOUT) {
+    const uint64_t lay[8] = {d.TS, d.KT, d.grp, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
+                             n->blk, n->gather ? 1u : 0u};
+    if (needed) *needed = sizeof(lay);
+    if (!dst) return EPROP_OK;
+    if (dst_bytes < sizeof(lay)) return EPROP_ERR_INVALID_ARGUMENT;
+    std::memcpy(dst, lay, sizeof(lay));
+    return EPROP_OK;
+  }
   if (per_trial && n->last_ntr == 0) return EPROP_ERR_STATE;
   if (per_trial && trial >= n->last_ntr) return EPROP_ERR_INVALID_ARGUMENT;
   const uint32_t T = per_trial ? n->last_T[trial] : 0;
@@ -807,8 +945,12 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
       std::vector<real> w;
       const bool in = what == EPROP_STATE_W_IN;
       if (!dst) { bytes = (in ? n->S_in : n->S_rec) * 8; break; }
-      e = fetch(d.sm_w + (in ? 0 : n->S_in), in ? n->S_in : n->S_rec, w);
-      outd.assign(w.begin(), w.end());
+      e = fetch(d.sm_w, n->S, w);
+      outd.assign(in ? n->S_in : n->S_rec, 0.0);
+      for (uint64_t q = 0; q < n->S && e == hipSuccess; ++q) {
+        const uint32_t o = n->sm2caller[q];
+        if ((o < n->S_in) == in) outd[in ? o : o - n->S_in] = (double)w[q];
+      }
       break;
     }
     case EPROP_STATE_GRAD_IN: case EPROP_STATE_GRAD_REC:

@@ -9,12 +9,16 @@
 //                        (target-major index -> source-major index)
 //   gradient sums        gs[S], gc[S] (Kahan pair, target-major), Adam m, v
 //   neuron state         v[b][Jp], a[b][Jp], nst[b][Jp] (refractory count | z << 7)
-//   delay ring           ring[b][R][Jp], R = max_delay + 1 (scatter delivery)
+//   delay ring           ring[b][R][Jp], R = max_delay + 1 (scatter delivery; held in
+//                        LDS by the tile that owns the targets, saved between launches)
+//   tile segments        tseg[src][k], k = 0..KT: first synapse of source src whose
+//                        target lies in tile k (source rows sorted by target)
 //   psi archive          psi[b][t][Jp]          (time-major, written per step)
 //   arrival archive      phi[b][j][t]           (neuron-major, stride Tp)
 //   spike bitsets        rec_bits[b][t][Jw], in_bits[b][s][Iw], forced_bits[b][t][Jw]
-//   spike-time lists     spk_cnt[b][NS], spk_t[b][src*Tcap + k] (uint16, ascending)
-//   per-step spikes      rec_cnt[b][t], rec_list[b][t & 1][Jp]
+//   spike-time lists     spk_cnt[b][NS], spk_t[b][src*Lc + k] (uint16, ascending)
+//   per-step spikes      rec_cnt[b][t], rec_list[b][t & 1][Jp], nspk[b][t]
+//   tile barriers        bar[b][2] (arrival count, generation)
 //   readout (FP64)       ysum/pi[b][t][K], y[b][t][K], err[b][t][K], ebar[b][t][K]
 #pragma once
 #include <hip/hip_runtime.h>
@@ -25,22 +29,25 @@ namespace eprop {
 // ctl words; the 64-bit device pointer to the batch's input-source array is
 // stored at word CTL_WORDS (byte offset 64)
 enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
-enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_LABEL = 8u };
+enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_BARRIER = 8u };
 enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_WORDS = 8 };
 
 template <typename real>
 struct DevNet {
   // sizes
   uint32_t I, J, K, NS, Jp, Jw, Iw, R, Tcap, Tp, Bcap;
-  uint64_t spk_stride;          // per-slot size of spk_t (NS * Tcap)
+  uint64_t spk_stride;          // per-slot size of spk_t (NS * Lc)
+  uint32_t Lc;                  // spike-list capacity per source (Tcap rounded up to 8)
+  uint64_t S;                   // synapses
   uint32_t n_ref;
   int32_t surrogate, loss;
   uint32_t step_stride;         // batch target/window row length
+  uint32_t TS, KT, grp;         // tile size (neurons), tiles per trial, lanes per source in delivery
   // constants (working precision for the dynamics, FP64 for the backward filters)
   real alpha, rho, v_th, sg_gamma, sg_beta;
   double alpha_d, rho_d, kappa_d;
   // graph
-  const uint32_t *sm_ptr, *sm_syn;
+  const uint32_t *sm_ptr, *sm_syn, *tseg;
   real *sm_w;
   const uint32_t *tm_ptr, *tm_syn, *tm_perm;
   real *tm_w, *gs, *gc, *adam_m, *adam_v;
@@ -55,7 +62,7 @@ struct DevNet {
   uint64_t *rec_bits, *in_bits, *forced_bits;
   uint32_t *spk_cnt;
   uint16_t *spk_t;
-  uint32_t *rec_cnt, *rec_list;
+  uint32_t *rec_cnt, *rec_list, *nspk, *bar;
   uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
   double *ysum, *y, *err, *ebar;  // [Bcap][Tcap+2][K]
   double *loss_out;             // [Bcap]
@@ -71,13 +78,15 @@ struct DevNet {
   // control
   uint32_t *ctl;
   unsigned long long *cnt;
+  unsigned long long *evcnt;    // [64] event counters (spread to avoid one hot atomic)
 };
 
 // Launch shapes (chosen on the host; the autotuner may change them)
 struct Shapes {
-  uint32_t deliver_blocks_per_trial;
-  uint32_t syn_blocks;
   uint32_t block;               // threads per block for grid-stride kernels
+  uint32_t tile_block;          // threads per block of the tiled forward kernel
+  uint32_t syn_block;           // threads per block of the synapse kernel
+  uint32_t ginst;               // trials per block of the synapse kernel
 };
 
 template <typename real>
@@ -85,11 +94,17 @@ struct Launch {
   static void stage_inputs(const DevNet<real> &n, uint32_t n_trials, uint64_t n_spikes, bool check_order,
                            hipStream_t s);
   static void stage_forced(const DevNet<real> &n, uint32_t n_trials, uint64_t n_forced, hipStream_t s);
-  static void neuron(const DevNet<real> &n, uint32_t off, bool gather, bool forced, hipStream_t s);
-  static void deliver(const DevNet<real> &n, const Shapes &sh, uint32_t off, hipStream_t s);
+  // deterministic per-step neuron update with gather delivery at step ctl[T0] + off
+  static void neuron_gather(const DevNet<real> &n, uint32_t off, bool forced, hipStream_t s);
+  // persistent tiled forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps
+  static void forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t block,
+                            size_t smem, hipStream_t s);
+  static size_t tile_smem(uint32_t TS, uint32_t R);
+  static hipError_t allow_smem(size_t smem);
+  static hipError_t resident(uint32_t block, size_t smem, int *per_cu);
   static void readout(const DevNet<real> &n, hipStream_t s);
   static void adjoint(const DevNet<real> &n, hipStream_t s);
-  static void synapse(const DevNet<real> &n, const Shapes &sh, hipStream_t s);
+  static void synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *partial, hipStream_t s);
   static void output_reduce(const DevNet<real> &n, hipStream_t s);
   static void apply(const DevNet<real> &n, uint64_t n_syn, double n_trials, int optimizer, double eta,
                     double eta_t, double b1, double b2, double eps_hat, hipStream_t s);

@@ -5,9 +5,10 @@
 // event-driven implementation computes the gradient at the first spike
 // after each sample from the archived postsynaptic history).  The path is:
 //
-//   forward, per step t     k_neuron  (time-driven neuron update, eq. lif_update,
+//   forward, per step t     neuron update (time-driven, eq. lif_update,
 //                                      eq. spike-threshold-adaptation, surrogate)
-//                           k_deliver (spike delivery into delay rings)
+//                           (k_forward_tiled: persistent, tiles of targets with
+//                            LDS delay rings; k_neuron_gather: deterministic)
 //   after the sample        k_readout_sums, k_readout_scan (eq. leaky_integrator,
 //                                      error signal, loss; backward filter of E)
 //                           k_adjoint (per-neuron arrival archive phi)
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_stage_in_lists(DevNet<real> n) {
   if (i >= n.I) return;
   const uint32_t T = n.T[b];
   const uint64_t *bits = n.in_bits + (size_t)b * n.Tcap * n.Iw + (i >> 6);
-  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)i * n.Tcap;
+  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)i * n.Lc;
   uint32_t c = 0;
   for (uint32_t s = 0; s < T; ++s)
     if ((bits[(size_t)s * n.Iw] >> (i & 63u)) & 1ull) out[c++] = (uint16_t)s;
@@ -134,61 +135,20 @@ __global__ __launch_bounds__(256) void k_stage_forced(DevNet<real> n, uint32_t n
 
 // ----------------------------------------------------------------- forward
 
-// Neuron update at step t = ctl[T0] + off for every (trial, neuron).
-// GATHER sums the arriving synapses of each target in ascending source
-// order (inputs first); otherwise the input is read from the delay ring.
-// The expression order matches the reference definition, so FP64 with
-// GATHER reproduces it bit for bit.
-template <typename real, bool GATHER, bool FORCED>
-__global__ __launch_bounds__(256) void k_neuron(DevNet<real> n, uint32_t off) {
-  const uint32_t b = blockIdx.y;
-  if (b >= n.ctl[CTL_NTRIALS]) return;
-  const uint32_t t = n.ctl[CTL_T0] + off;
-  const uint32_t Tb = n.T[b];
-  if (t == 0 || t > Tb) return;
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n.Jp) return;  // whole wavefronts: Jp is a multiple of 64
-  const bool live = j < n.J;
-  const size_t sidx = (size_t)b * n.Jp + j;
-
-  real I = 0;
-  if constexpr (GATHER) {
-    if (live) {
-      const uint64_t *inb = n.in_bits + (size_t)b * n.Tcap * n.Iw;
-      const uint64_t *rb = n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw;
-      const uint32_t q1 = n.tm_ptr[j + 1];
-      for (uint32_t q = n.tm_ptr[j]; q < q1; ++q) {
-        const uint32_t pk = n.tm_syn[q];
-        const uint32_t src = pk & 0xFFFFFFu;
-        const int s = (int)t - (int)(pk >> 24);
-        bool hit;
-        if (src < n.I) {
-          hit = s >= 0 && ((inb[(size_t)s * n.Iw + (src >> 6)] >> (src & 63u)) & 1ull);
-        } else {
-          const uint32_t r = src - n.I;
-          hit = s >= 1 && ((rb[(size_t)s * n.Jw + (r >> 6)] >> (r & 63u)) & 1ull);
-        }
-        if (hit) I = I + n.tm_w[q];
-      }
-    }
-  } else {
-    real *slot = n.ring + ((size_t)b * n.R + t % n.R) * n.Jp + j;
-    I = *slot;
-    *slot = (real)0;
-  }
-
-  const uint8_t st = n.nst[sidx];
+// One neuron update at step t (state in registers; the caller loads and
+// stores it).  The expression order is that of the model definition, so the
+// FP64 instantiation with an identically ordered input sum reproduces it bit
+// for bit.  Writes psi; returns the spike.
+template <typename real, bool FORCED>
+__device__ inline bool neuron_step(const DevNet<real> &n, uint32_t b, uint32_t t, uint32_t j, bool live,
+                                   real I, real beta, real &v, real &a, uint8_t &st) {
   uint32_t refr = st & 0x7Fu;
   const real zprev = (st & 0x80u) ? (real)1 : (real)0;
-  const real beta = n.beta_j[j];
   real A = n.v_th;
   if (beta != (real)0) {  // LIF: v_th + 0 * a == v_th
-    real a = n.a[sidx];
     a = n.rho * a + zprev;
-    n.a[sidx] = a;
     A = n.v_th + beta * a;
   }
-  real v = n.v[sidx];
   v = n.alpha * v + I - zprev * A;
   const bool refractory = refr > 0;
   if (refractory) refr -= 1;
@@ -202,63 +162,299 @@ __global__ __launch_bounds__(256) void k_neuron(DevNet<real> n, uint32_t off) {
   z = z && live;
   const real ps = refractory ? (real)0 : surrogate(n, v - A);
   if (z) refr = n.n_ref;
-  n.v[sidx] = v;
-  n.nst[sidx] = (uint8_t)(refr | (z ? 0x80u : 0u));
+  st = (uint8_t)(refr | (z ? 0x80u : 0u));
   n.psi[((size_t)b * (n.Tcap + 1) + t) * n.Jp + j] = ps;
+  return z;
+}
 
+// Spike bitset word of this wavefront's 64 neurons and the spike-time list
+// of each spiking neuron.  Called by whole wavefronts aligned to 64 neurons.
+template <typename real>
+__device__ inline uint64_t publish_bits(const DevNet<real> &n, uint32_t b, uint32_t t, uint32_t j, bool z) {
   const uint64_t word = __ballot(z);
-  const uint32_t lane = lane_id();
-  uint32_t base = 0;
-  if (lane == 0) {
-    n.rec_bits[((size_t)b * (n.Tcap + 1) + t) * n.Jw + (j >> 6)] = word;
-    if (word) {
-      const uint32_t c = (uint32_t)__popcll(word);
-      base = atomicAdd(&n.rec_cnt[(size_t)b * (n.Tcap + 1) + t], c);
-      atomicAdd(&n.cnt[CNT_REC_SPIKES], (unsigned long long)c);
-    }
-  }
-  base = (uint32_t)__shfl((int)base, 0);
+  if (lane_id() == 0) n.rec_bits[((size_t)b * (n.Tcap + 1) + t) * n.Jw + (j >> 6)] = word;
   if (z) {
-    const uint32_t pos = base + (uint32_t)__popcll(word & ((1ull << lane) - 1ull));
-    n.rec_list[((size_t)b * 2 + (t & 1u)) * n.Jp + pos] = j;
     const size_t ci = (size_t)b * n.NS + n.I + j;
     const uint32_t c = n.spk_cnt[ci];
-    n.spk_t[(size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Tcap + c] = (uint16_t)t;
+    n.spk_t[(size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc + c] = (uint16_t)t;
     n.spk_cnt[ci] = c + 1;
+  }
+  return word;
+}
+
+// Barrier of the KT workgroups that simulate one trial.  Thread 0 releases
+// the workgroup's global writes, arrives, and waits for the generation to
+// change.  The wait is bounded: on timeout it flags ERR_BARRIER and returns
+// false, so every wavefront always reaches the end of the kernel.
+__device__ inline bool group_barrier(uint32_t *bar, uint32_t members, uint32_t *err) {
+  __shared__ uint32_t ok_s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1;
+    __threadfence();
+    const uint32_t g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == members) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 24)) {  // far beyond any legitimate wait (about a second)
+          atomicOr(err, ERR_BARRIER);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+    ok_s = ok;
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// Exclusive scan of one value per thread over the block (blockDim <= 1024);
+// returns the prefix and writes the block total to *total.  wsum: LDS [17].
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *wsum, uint32_t *total) {
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
+    if ((int)lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < nw; ++i) {
+      const uint32_t v = wsum[i];
+      wsum[i] = acc;
+      acc += v;
+    }
+    wsum[16] = acc;
+  }
+  __syncthreads();
+  *total = wsum[16];
+  return wsum[w] + inc - x;
+}
+
+// Adds the spikes emitted at step t by inputs and by recurrent neurons of
+// trial b into this tile's LDS ring.  Per chunk of up to blockDim spiking
+// sources: every thread resolves one source to its segment (the part of its
+// target-sorted row inside this tile), a block scan flattens the segments,
+// and consecutive threads take consecutive synapses (coalesced loads, all
+// independent), each adding its weight into the ring slot of its arrival.
+// Only arrivals within the trial are kept.  dlo, dpre: LDS [blockDim];
+// wsum: LDS [17].
+template <typename real>
+__device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
+                                    uint32_t Tb, real *ring, uint32_t *dlo, uint32_t *dpre, uint32_t *wsum) {
+  const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
+  const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
+  const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
+  // written within this kernel (possibly by other workgroups): coherent loads
+  const uint32_t n_rec =
+      t >= 1 ? __hip_atomic_load(&n.rec_cnt[(size_t)b * (n.Tcap + 1) + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+             : 0u;
+  const uint32_t total = n_in + n_rec;
+  const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
+  uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
+  for (uint32_t base = 0; base < total; base += blockDim.x) {
+    const uint32_t m = min(blockDim.x, total - base);
+    uint32_t lo = 0, len = 0;
+    if (threadIdx.x < m) {
+      const uint32_t item = base + threadIdx.x;
+      const uint32_t src = item < n_in ? in_src[in_lo + item]
+                                       : n.I + __hip_atomic_load(&rl[item - n_in], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t *ts = n.tseg + (size_t)src * (n.KT + 1) + k;
+      lo = ts[0];
+      len = ts[1] - lo;
+    }
+    uint32_t nsyn;
+    const uint32_t pre = block_exclusive_scan(len, wsum, &nsyn);
+    dlo[threadIdx.x] = lo;
+    dpre[threadIdx.x] = pre;
+    __syncthreads();
+    // U positions per thread and pass: the segment searches, then all 2U
+    // graph loads, then the LDS additions, so that many loads are in flight
+    constexpr int U = 8;
+    uint32_t top = 1;
+    while (2 * top <= m) top *= 2;
+    for (uint32_t p0 = threadIdx.x; p0 < nsyn; p0 += U * blockDim.x) {
+      uint32_t q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t p = min(p0 + u * blockDim.x, nsyn - 1);
+        uint32_t l = 0;  // largest i < m with dpre[i] <= p
+        for (uint32_t step = top; step > 0; step >>= 1)
+          if (l + step < m && dpre[l + step] <= p) l += step;
+        q[u] = dlo[l] + (p - dpre[l]);
+      }
+      uint32_t pk[U];
+      real w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        pk[u] = n.sm_syn[q[u]];
+        w[u] = n.sm_w[q[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t ta = t + (pk[u] >> 24);
+        if (p0 + u * blockDim.x < nsyn && ta <= Tb)
+          atomicAdd(&ring[(ta % n.R) * n.TS + ((pk[u] & 0xFFFFFFu) - j0)], w[u]);
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Spike delivery for the spikes emitted at step t = ctl[T0] + off: input
-// spikes of that step and recurrent spikes of that step.  One wavefront per
-// spiking source walks its outgoing synapses and adds the weight into the
-// target's ring slot for step t + D (only arrivals within the trial).
-template <typename real>
-__global__ __launch_bounds__(256) void k_deliver(DevNet<real> n, uint32_t off, const uint32_t *const *in_src_pp) {
+// Persistent forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps.  Workgroup
+// (b, k) owns neurons [k*TS, k*TS + TS) of trial b; their delay ring and
+// state stay in LDS for the whole launch.  Per step: neuron update of the
+// tile, spike publication (bitset, spike times, compacted list with one
+// global atomic per workgroup), one barrier among the trial's KT
+// workgroups, delivery of the step's spikes into the tile's ring.
+template <typename real, bool FORCED>
+__global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t KT = n.KT, TS = n.TS;
+  const uint32_t b = blockIdx.x / KT, k = blockIdx.x - b * KT;
+  if (b >= n.ctl[CTL_NTRIALS]) return;
+  const uint32_t Tb = n.T[b];
+  const uint32_t t0 = n.ctl[CTL_T0];
+  if (t0 >= Tb) return;  // the same for every workgroup of the trial
+  const uint32_t j0 = k * TS;
+  const uint32_t nt = min(TS, n.Jp - j0);  // multiple of 64
+  const uint32_t nw = nt >> 6;
+  real *ring = reinterpret_cast<real *>(smem);
+  real *sv = ring + (size_t)n.R * TS;
+  real *sa = sv + TS;
+  real *sb = sa + TS;
+  uint64_t *words = reinterpret_cast<uint64_t *>(sb + TS);
+  uint32_t *woff = reinterpret_cast<uint32_t *>(words + TS / 64);
+  uint32_t *dlo = woff + TS / 64 + 1;
+  uint32_t *dpre = dlo + blockDim.x;
+  uint8_t *sst = reinterpret_cast<uint8_t *>(dpre + blockDim.x);
+  __shared__ uint32_t gbase;
+  __shared__ uint32_t wsum[17];
+
+  const size_t gs = (size_t)b * n.Jp + j0;
+  for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
+    sv[i] = n.v[gs + i];
+    sa[i] = n.a[gs + i];
+    sb[i] = n.beta_j[j0 + i];
+    sst[i] = n.nst[gs + i];
+    for (uint32_t r = 0; r < n.R; ++r) ring[r * TS + i] = n.ring[((size_t)b * n.R + r) * n.Jp + j0 + i];
+  }
+  __syncthreads();
+  if (t0 == 0) {  // inputs emitted at step 0
+    deliver_tile(n, b, k, j0, 0, Tb, ring, dlo, dpre, wsum);
+    __syncthreads();
+  }
+  bool ok = true;
+  const uint32_t t_end = min(t0 + nsteps, Tb);
+  for (uint32_t t = t0 + 1; t <= t_end; ++t) {
+    const uint32_t slot = t % n.R;
+    for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
+      real v = sv[i], a = sa[i];
+      uint8_t st = sst[i];
+      const real I = ring[slot * TS + i];
+      ring[slot * TS + i] = (real)0;
+      const uint32_t j = j0 + i;
+      const bool z = neuron_step<real, FORCED>(n, b, t, j, j < n.J, I, sb[i], v, a, st);
+      sv[i] = v;
+      sa[i] = a;
+      sst[i] = st;
+      const uint64_t word = publish_bits(n, b, t, j, z);
+      if (lane_id() == 0) words[i >> 6] = word;
+    }
+    __syncthreads();
+    // compacted spike list of the tile: one wavefront scans the tile's words
+    if (threadIdx.x < 64) {
+      uint32_t off = 0, tot = 0;
+      for (uint32_t w0 = 0; w0 < nw; w0 += 64) {
+        const uint32_t w = w0 + threadIdx.x;
+        const uint32_t c = w < nw ? (uint32_t)__popcll(words[w]) : 0u;
+        uint32_t inc = c;  // inclusive scan across the wavefront
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
+          if ((int)threadIdx.x >= o) inc += y;
+        }
+        if (w < nw) woff[w] = off + inc - c;
+        off += (uint32_t)__shfl((int)inc, 63);
+      }
+      tot = off;
+      if (threadIdx.x == 0) gbase = tot ? atomicAdd(&n.rec_cnt[(size_t)b * (n.Tcap + 1) + t], tot) : 0u;
+    }
+    __syncthreads();
+    {
+      uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
+      for (uint32_t w = threadIdx.x >> 6; w < nw; w += blockDim.x >> 6) {
+        const uint64_t word = words[w];
+        const uint32_t lane = lane_id();
+        if ((word >> lane) & 1ull)
+          rl[gbase + woff[w] + (uint32_t)__popcll(word & ((1ull << lane) - 1ull))] = j0 + w * 64 + lane;
+      }
+    }
+    if (KT > 1) {
+      if (ok) ok = group_barrier(n.bar + 2 * b, KT, &n.ctl[CTL_ERR]);
+      else __syncthreads();
+    } else {
+      __syncthreads();
+    }
+    if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, dlo, dpre, wsum);
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
+    n.v[gs + i] = sv[i];
+    n.a[gs + i] = sa[i];
+    n.nst[gs + i] = sst[i];
+    for (uint32_t r = 0; r < n.R; ++r) n.ring[((size_t)b * n.R + r) * n.Jp + j0 + i] = ring[r * TS + i];
+  }
+}
+
+// Deterministic per-step neuron update: every target sums its arriving
+// synapses in ascending source order, inputs first (the reference order).
+template <typename real, bool FORCED>
+__global__ __launch_bounds__(256) void k_neuron_gather(DevNet<real> n, uint32_t off) {
   const uint32_t b = blockIdx.y;
   if (b >= n.ctl[CTL_NTRIALS]) return;
   const uint32_t t = n.ctl[CTL_T0] + off;
   const uint32_t Tb = n.T[b];
-  if (t >= Tb) return;
-  const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
-  const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
-  const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
-  const uint32_t n_rec = t >= 1 ? n.rec_cnt[(size_t)b * (n.Tcap + 1) + t] : 0u;
-  const uint32_t total = n_in + n_rec;
-  const uint32_t lane = lane_id();
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-  const uint32_t *in_src = *in_src_pp;
-  const uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
-  real *ring = n.ring + (size_t)b * n.R * n.Jp;
-  for (uint32_t item = wave; item < total; item += nwaves) {
-    const uint32_t src = item < n_in ? in_src[in_lo + item] : n.I + rl[item - n_in];
-    const uint32_t q1 = n.sm_ptr[src + 1];
-    for (uint32_t q = n.sm_ptr[src] + lane; q < q1; q += 64) {
-      const uint32_t pk = n.sm_syn[q];
-      const uint32_t ta = t + (pk >> 24);
-      if (ta <= Tb) atomicAdd(&ring[(size_t)(ta % n.R) * n.Jp + (pk & 0xFFFFFFu)], n.sm_w[q]);
+  if (t == 0 || t > Tb) return;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n.Jp) return;  // whole wavefronts: Jp is a multiple of 64
+  const bool live = j < n.J;
+  const size_t sidx = (size_t)b * n.Jp + j;
+  real I = 0;
+  if (live) {
+    const uint64_t *inb = n.in_bits + (size_t)b * n.Tcap * n.Iw;
+    const uint64_t *rb = n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw;
+    const uint32_t q1 = n.tm_ptr[j + 1];
+    for (uint32_t q = n.tm_ptr[j]; q < q1; ++q) {
+      const uint32_t pk = n.tm_syn[q];
+      const uint32_t src = pk & 0xFFFFFFu;
+      const int s = (int)t - (int)(pk >> 24);
+      bool hit;
+      if (src < n.I) {
+        hit = s >= 0 && ((inb[(size_t)s * n.Iw + (src >> 6)] >> (src & 63u)) & 1ull);
+      } else {
+        const uint32_t r = src - n.I;
+        hit = s >= 1 && ((rb[(size_t)s * n.Jw + (r >> 6)] >> (r & 63u)) & 1ull);
+      }
+      if (hit) I = I + n.tm_w[q];
     }
   }
+  real v = n.v[sidx], a = n.a[sidx];
+  uint8_t st = n.nst[sidx];
+  const bool z = neuron_step<real, FORCED>(n, b, t, j, live, I, n.beta_j[j], v, a, st);
+  n.v[sidx] = v;
+  n.a[sidx] = a;
+  n.nst[sidx] = st;
+  publish_bits(n, b, t, j, z);
 }
 
 __global__ void k_advance(uint32_t *ctl, uint32_t by) {
@@ -278,6 +474,10 @@ __global__ __launch_bounds__(256) void k_readout_sums(DevNet<real> n) {
   const uint32_t lane = lane_id();
   const uint64_t *row = n.rec_bits + ((size_t)b * (n.Tcap + 1) + t) * n.Jw;
   double *out = n.ysum + ((size_t)b * (n.Tcap + 2) + t) * n.K;
+  uint32_t nsp = 0;
+  for (uint32_t w = lane; w < n.Jw; w += 64) nsp += (uint32_t)__popcll(row[w]);
+  for (int o = 32; o > 0; o >>= 1) nsp += (uint32_t)__shfl_down((int)nsp, o);
+  if (lane == 0) n.nspk[(size_t)b * (n.Tcap + 1) + t] = nsp;
   for (uint32_t k0 = 0; k0 < n.K; k0 += 8) {
     double acc[8];
 #pragma unroll
@@ -369,6 +569,9 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   }
   __syncthreads();
   if (tid == 0) {
+    unsigned long long ns = 0;
+    for (uint32_t t = 1; t <= T; ++t) ns += n.nspk[(size_t)b * (n.Tcap + 1) + t];
+    atomicAdd(&n.cnt[CNT_REC_SPIKES], ns);
     n.loss_out[b] = red[0];
     uint32_t best = 0;
     if (n.loss == 1)
@@ -380,36 +583,75 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
 
 // ----------------------------------------------------------------- gradient
 
-// Per (trial, neuron), backward over the trial: learning signal of the
-// filtered errors Lambda^t = sum_k B_jk Ebar_k^t, adjoint recursion of the
-// eligibility vector (FP64), archive phi[b][j][t] = mu^t[0]; then the
-// neuron's output-synapse gradient sum_{spikes u} Ebar_k^u.
+// Per (trial, neuron), backward over the trial in chunks of 16 steps:
+// learning signal of the filtered errors Lambda^t = sum_k B_jk Ebar_k^t, the
+// adjoint recursion of the eligibility vector (FP64) and the archive
+// phi[b][j][t] = mu^t[0]; then the neuron's output-synapse gradient
+// sum over its spikes u of Ebar_k^u.  B rows and the chunk's Ebar rows are
+// read from LDS; phi is transposed through LDS so that each store writes
+// whole 16-step row segments.
 template <typename real>
 __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
+  extern __shared__ __align__(16) unsigned char adj_smem[];
   const uint32_t b = blockIdx.y;
   if (b >= n.ctl[CTL_NTRIALS]) return;
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n.J) return;
+  const uint32_t tid = threadIdx.x, bd = blockDim.x;
+  const uint32_t j = blockIdx.x * bd + tid;
   const uint32_t T = n.T[b], K = n.K;
-  const double beta = (double)n.beta_j[j];
-  const real *fbj = n.fb + (size_t)j * K;
+  const bool live = j < n.J;
+  const bool inrow = j < n.Jp;
+  double *fbl = reinterpret_cast<double *>(adj_smem);   // [K][bd]
+  double *ebl = fbl + (size_t)K * bd;                   // [16][K]
+  real *tile = reinterpret_cast<real *>(ebl + 16 * K);  // [bd][17]
+  for (uint32_t k = 0; k < K; ++k) fbl[k * bd + tid] = live ? (double)n.fb[(size_t)j * K + k] : 0.0;
+  const double beta = live ? (double)n.beta_j[j] : 0.0;
   const double *eb = n.ebar + (size_t)b * (n.Tcap + 2) * K;
-  const real *ps = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
-  real *ph = n.phi + ((size_t)b * n.Jp + j) * n.Tp;
+  const real *ps_col = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
+  const uint32_t wbase = tid & ~63u, lane = tid & 63u;
   double mu0 = 0.0, mu1 = 0.0;
-  for (uint32_t t = T; t >= 1; --t) {
-    double L = 0.0;
-    for (uint32_t k = 0; k < K; ++k) L += (double)fbj[k] * eb[(size_t)t * K + k];
-    const double p = (double)ps[(size_t)t * n.Jp];
-    const double pl = p * L;
-    const double m0 = pl + n.alpha_d * mu0 + p * mu1;
-    const double m1 = -beta * pl + (n.rho_d - p * beta) * mu1;
-    ph[t] = (real)m0;
-    mu0 = m0;
-    mu1 = m1;
+  for (int m = (int)(T / 16); m >= 0; --m) {
+    const uint32_t tb = (uint32_t)m * 16;
+    __syncthreads();
+    for (uint32_t idx = tid; idx < 16 * K; idx += bd) {
+      const uint32_t t = tb + idx / K;
+      ebl[idx] = (t >= 1 && t <= T) ? eb[(size_t)t * K + idx % K] : 0.0;
+    }
+    __syncthreads();
+    real ps[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t t = tb + r;
+      ps[r] = (inrow && t >= 1 && t <= T) ? ps_col[(size_t)t * n.Jp] : (real)0;
+    }
+#pragma unroll
+    for (int r = 15; r >= 0; --r) {
+      const uint32_t t = tb + r;
+      real out = (real)0;
+      if (t >= 1 && t <= T) {
+        double L = 0.0;
+        for (uint32_t k = 0; k < K; ++k) L += fbl[k * bd + tid] * ebl[r * K + k];
+        const double p = (double)ps[r];
+        const double pl = p * L;
+        const double m0 = pl + n.alpha_d * mu0 + p * mu1;
+        const double m1 = -beta * pl + (n.rho_d - p * beta) * mu1;
+        mu0 = m0;
+        mu1 = m1;
+        out = (real)m0;
+      }
+      tile[tid * 17 + r] = out;
+    }
+    __syncthreads();
+    // each store: 4 rows x 16 consecutive steps of this wavefront's 64 rows
+#pragma unroll 4
+    for (uint32_t it = 0; it < 16; ++it) {
+      const uint32_t row = it * 4 + (lane >> 4), r = lane & 15u;
+      const uint32_t jj = blockIdx.x * bd + wbase + row, t = tb + r;
+      if (jj < n.J && t >= 1 && t <= T) n.phi[((size_t)b * n.Jp + jj) * n.Tp + t] = tile[(wbase + row) * 17 + r];
+    }
   }
+  if (!live) return;
   const uint32_t c = n.spk_cnt[(size_t)b * n.NS + n.I + j];
-  const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Tcap;
+  const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
   real *go = n.gout_b + (size_t)b * K * n.Jp + j;
   for (uint32_t k = 0; k < K; ++k) {
     double acc = 0.0;
@@ -418,45 +660,102 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   }
 }
 
-// Event-driven synapse gradient, target-major: one wavefront per target
-// neuron j, one lane per incoming synapse.  For every trial of the batch
-// the lane walks the presynaptic spike-time list of its source; each
-// arrival a = s + D <= T adds phi_j^a.  The per-synapse sum is Kahan-added
-// into the accumulator pair (gs, gc).
+// Event-driven synapse gradient, target-major.  Block (j, c) handles the
+// incoming synapses of target j for the trials of chunk c (at most 8); the
+// target's archive rows phi[b][j][.] of those trials are staged in LDS.  Each
+// lane walks, for its synapse and each trial, the presynaptic spike-time list
+// (8 entries per 16-byte load; the counts and first loads of all trials are
+// issued together); each arrival a = s + D <= T adds phi_j^a (Kahan).  With
+// one chunk the sum goes straight into the accumulator pair (gs, gc);
+// otherwise into partial[c][q] for a fixed-order reduction.
 template <typename real>
-__global__ __launch_bounds__(256) void k_synapse(DevNet<real> n) {
-  const uint32_t lane = lane_id();
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+__device__ inline bool add_arrivals(uint4 v, uint32_t k0, uint32_t cnt, uint32_t D, uint32_t T, const real *ph,
+                                    real &s, real &c, unsigned long long &nev) {
+  const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (uint32_t e = 0; e < 8; ++e) {
+    if (k0 + e >= cnt) return true;
+    const uint32_t a = ((w4[e >> 1] >> ((e & 1u) * 16u)) & 0xFFFFu) + D;
+    if (a > T) return true;
+    kahan_add(s, c, ph[a]);
+    ++nev;
+  }
+  return false;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst, uint32_t nchunk, real *partial) {
+  constexpr uint32_t GB = 8;
+  extern __shared__ __align__(16) unsigned char syn_smem[];
+  real *phl = reinterpret_cast<real *>(syn_smem);   // [ginst][Tp]
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
+  const uint32_t c = blockIdx.x % nchunk, j = blockIdx.x / nchunk;
+  const uint32_t b0 = c * ginst, nb = min(min(ginst, ntr - b0), GB);
+  const uint32_t tid = threadIdx.x;
+  uint32_t Tt[GB];
+#pragma unroll
+  for (uint32_t bi = 0; bi < GB; ++bi) Tt[bi] = bi < nb ? n.T[b0 + bi] : 0u;
+  for (uint32_t bi = 0; bi < nb; ++bi) {
+    const real *src = n.phi + ((size_t)(b0 + bi) * n.Jp + j) * n.Tp;
+    real *dst = phl + bi * n.Tp;
+    const uint32_t T1 = Tt[bi] + 1;
+    for (uint32_t t = tid; t < T1; t += 4 * blockDim.x) {
+      real v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = t + u * blockDim.x < T1 ? src[t + u * blockDim.x] : (real)0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t + u * blockDim.x < T1) dst[t + u * blockDim.x] = v[u];
+    }
+  }
+  __syncthreads();
   unsigned long long nev = 0;
-  for (uint32_t j = wave; j < n.J; j += nwaves) {
-    const uint32_t q1 = n.tm_ptr[j + 1];
-    for (uint32_t q = n.tm_ptr[j] + lane; q < q1; q += 64) {
-      const uint32_t pk = n.tm_syn[q];
-      const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
-      real s = 0, c = 0;
-      for (uint32_t b = 0; b < ntr; ++b) {
-        const uint32_t T = n.T[b];
-        const uint32_t cnt = n.spk_cnt[(size_t)b * n.NS + src];
-        const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)src * n.Tcap;
-        const real *ph = n.phi + ((size_t)b * n.Jp + j) * n.Tp;
-        for (uint32_t k = 0; k < cnt; ++k) {
-          const uint32_t a = (uint32_t)st[k] + D;
-          if (a > T) break;
-          kahan_add(s, c, ph[a]);
-          ++nev;
-        }
-      }
+  const uint32_t q1 = n.tm_ptr[j + 1];
+  for (uint32_t q = n.tm_ptr[j] + tid; q < q1; q += blockDim.x) {
+    const uint32_t pk = n.tm_syn[q];
+    const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
+    uint32_t cnt[GB];
+    uint4 v0[GB];
+    const uint4 *st4[GB];
+#pragma unroll
+    for (uint32_t bi = 0; bi < GB; ++bi) {
+      st4[bi] = reinterpret_cast<const uint4 *>(n.spk_t + (size_t)(b0 + (bi < nb ? bi : 0)) * n.spk_stride +
+                                                (size_t)src * n.Lc);
+      cnt[bi] = bi < nb ? n.spk_cnt[(size_t)(b0 + bi) * n.NS + src] : 0u;
+      v0[bi] = bi < nb ? st4[bi][0] : make_uint4(0, 0, 0, 0);
+    }
+    real s = 0, cc = 0;
+#pragma unroll
+    for (uint32_t bi = 0; bi < GB; ++bi) {
+      if (bi >= nb) break;
+      const real *ph = phl + bi * n.Tp;
+      bool done = add_arrivals(v0[bi], 0, cnt[bi], D, Tt[bi], ph, s, cc, nev);
+      for (uint32_t k0 = 8; k0 < cnt[bi] && !done; k0 += 8)
+        done = add_arrivals(st4[bi][k0 >> 3], k0, cnt[bi], D, Tt[bi], ph, s, cc, nev);
+    }
+    if (nchunk == 1) {
       real gs = n.gs[q], gc = n.gc[q];
       kahan_add(gs, gc, s);
-      kahan_add(gs, gc, c);
+      kahan_add(gs, gc, cc);
       n.gs[q] = gs;
       n.gc[q] = gc;
+    } else {
+      partial[(size_t)c * n.S + q] = s + cc;
     }
   }
   for (int o = 32; o > 0; o >>= 1) nev += __shfl_down(nev, o);
-  if (lane == 0 && nev) atomicAdd(&n.cnt[CNT_EVENTS], nev);
+  if ((tid & 63u) == 0 && nev) atomicAdd(&n.evcnt[blockIdx.x & 63u], nev);
+}
+
+// Fixed-order reduction of the trial-chunk partial sums into (gs, gc).
+template <typename real>
+__global__ __launch_bounds__(256) void k_synapse_reduce(DevNet<real> n, uint32_t nchunk, const real *partial) {
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n.S; q += (uint64_t)gridDim.x * blockDim.x) {
+    real gs = n.gs[q], gc = n.gc[q];
+    for (uint32_t c = 0; c < nchunk; ++c) kahan_add(gs, gc, partial[(size_t)c * n.S + q]);
+    n.gs[q] = gs;
+    n.gc[q] = gc;
+  }
 }
 
 // Output-synapse gradients of the batch's trials, summed in trial order.
@@ -555,23 +854,39 @@ void Launch<real>::stage_forced(const DevNet<real> &n, uint32_t ntr, uint64_t nf
 }
 
 template <typename real>
-void Launch<real>::neuron(const DevNet<real> &n, uint32_t off, bool gather, bool forced, hipStream_t s) {
+void Launch<real>::neuron_gather(const DevNet<real> &n, uint32_t off, bool forced, hipStream_t s) {
   const dim3 grid(cdiv(n.Jp, 256), n.Bcap);
-  if (gather) {
-    if (forced) k_neuron<real, true, true><<<grid, 256, 0, s>>>(n, off);
-    else k_neuron<real, true, false><<<grid, 256, 0, s>>>(n, off);
-  } else {
-    if (forced) k_neuron<real, false, true><<<grid, 256, 0, s>>>(n, off);
-    else k_neuron<real, false, false><<<grid, 256, 0, s>>>(n, off);
-  }
+  if (forced) k_neuron_gather<real, true><<<grid, 256, 0, s>>>(n, off);
+  else k_neuron_gather<real, false><<<grid, 256, 0, s>>>(n, off);
 }
 
 template <typename real>
-void Launch<real>::deliver(const DevNet<real> &n, const Shapes &sh, uint32_t off, hipStream_t s) {
-  // the input-source pointer is read from device memory so that captured
-  // graphs stay valid when a batch brings new device arrays
-  k_deliver<real><<<dim3(sh.deliver_blocks_per_trial, n.Bcap), sh.block, 0, s>>>(
-      n, off, reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS));
+size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R) {
+  const size_t block = TS < 1024 ? TS : 1024;
+  return (size_t)(R + 3) * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 + 2 * block * 4 + TS + 64;
+}
+
+template <typename real>
+hipError_t Launch<real>::allow_smem(size_t smem) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forward_tiled<real, false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forward_tiled<real, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  return e;
+}
+
+template <typename real>
+hipError_t Launch<real>::resident(uint32_t block, size_t smem, int *per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_forward_tiled<real, false>, (int)block, smem);
+}
+
+template <typename real>
+void Launch<real>::forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t block, size_t smem,
+                                 hipStream_t s) {
+  const uint32_t grid = n.Bcap * n.KT;
+  if (forced) k_forward_tiled<real, true><<<grid, block, smem, s>>>(n, nsteps);
+  else k_forward_tiled<real, false><<<grid, block, smem, s>>>(n, nsteps);
 }
 
 template <typename real>
@@ -582,12 +897,17 @@ void Launch<real>::readout(const DevNet<real> &n, hipStream_t s) {
 
 template <typename real>
 void Launch<real>::adjoint(const DevNet<real> &n, hipStream_t s) {
-  k_adjoint<real><<<dim3(cdiv(n.J, 256), n.Bcap), 256, 0, s>>>(n);
+  const uint32_t bd = n.K > 16 ? 64 : 256;
+  const size_t smem = (size_t)n.K * bd * 8 + 16 * (size_t)n.K * 8 + (size_t)bd * 17 * sizeof(real);
+  k_adjoint<real><<<dim3(n.Jp / bd + (n.Jp % bd ? 1 : 0), n.Bcap), bd, smem, s>>>(n);
 }
 
 template <typename real>
-void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, hipStream_t s) {
-  k_synapse<real><<<sh.syn_blocks, sh.block, 0, s>>>(n);
+void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *partial, hipStream_t s) {
+  const uint32_t nchunk = (n_trials + sh.ginst - 1) / sh.ginst;
+  const size_t smem = (size_t)sh.ginst * n.Tp * sizeof(real);
+  k_synapse<real><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial);
+  if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
 }
 
 template <typename real>

@@ -31,7 +31,8 @@ PHASES = ("stage", "forward", "readout", "adjoint", "synapse", "output")
 (EPROP_STATE_W_IN, EPROP_STATE_W_REC, EPROP_STATE_W_OUT, EPROP_STATE_GRAD_IN, EPROP_STATE_GRAD_REC,
  EPROP_STATE_GRAD_OUT, EPROP_STATE_ADAM_M_IN, EPROP_STATE_ADAM_V_IN, EPROP_STATE_ADAM_M_REC,
  EPROP_STATE_ADAM_V_REC, EPROP_STATE_ADAM_M_OUT, EPROP_STATE_ADAM_V_OUT, EPROP_STATE_ADAM_STEP,
- EPROP_STATE_SPIKES, EPROP_STATE_PSI, EPROP_STATE_Y, EPROP_STATE_ERR, EPROP_STATE_V) = range(18)
+ EPROP_STATE_SPIKES, EPROP_STATE_PSI, EPROP_STATE_Y, EPROP_STATE_ERR, EPROP_STATE_V,
+ EPROP_STATE_LAYOUT) = range(19)
 
 EXPORTED = ("eprop_create_network", "eprop_simulate_batch", "eprop_apply_updates", "eprop_read_state",
             "eprop_destroy_network", "eprop_status_string", "eprop_last_error")
@@ -275,6 +276,10 @@ class Network:
             st, need = eprop_read_state(self.h, what, trial, _ptr(buf), buf.nbytes)
             self._check(st)
             return buf[:need // 4].reshape(-1, 2)
+        if what == EPROP_STATE_LAYOUT:
+            buf = np.zeros(8, np.uint64)
+            self._check(eprop_read_state(self.h, what, trial, _ptr(buf), buf.nbytes)[0])
+            return buf
         if what == EPROP_STATE_ADAM_STEP:
             buf = np.zeros(1, np.uint64)
             self._check(eprop_read_state(self.h, what, trial, _ptr(buf), 8)[0])
@@ -283,6 +288,11 @@ class Network:
         st, need = eprop_read_state(self.h, what, trial, _ptr(buf), buf.nbytes)
         self._check(st)
         return buf[:need // 8]
+
+    def layout(self) -> dict:
+        v = [int(x) for x in self.read(EPROP_STATE_LAYOUT)]
+        return dict(zip(("tile_neurons", "tiles", "lanes_per_source", "tile_threads", "synapse_threads",
+                         "synapse_trials", "steps_per_launch", "gather"), v))
 
     def weights(self) -> dict:
         return {"w_in": self.read(EPROP_STATE_W_IN), "w_rec": self.read(EPROP_STATE_W_REC),

@@ -422,14 +422,17 @@ def c3_events(seed: int = SEED_BASE + 3, batch_size: int = 128, iterations: int 
 
 def _large_sparse(name: str, seed: int, n_rec: int, indeg_rec: int, n_in: int, indeg_in: int,
                   rate_in_hz: float, n_steps: int, batch_size: int, gain: float, in_gain: float,
-                  alif_fraction: float, iterations: int, description: str) -> Workload:
+                  alif_fraction: float, iterations: int, description: str, eta: float) -> Workload:
     n_out = 10
     is_alif = np.zeros(n_rec, np.uint8)
     if alif_fraction > 0:
         perm = rng(seed, _P_ALIF).permutation(n_rec)
         is_alif[perm[n_rec - int(round(alif_fraction * n_rec)):]] = 1
+    # gradient descent on a loss summed over T steps and K readouts: the
+    # readout update is coherent over all J neurons, so the stable step scales
+    # like 1 / (J T rate^2 tau_out^2)
     prm = Params(beta_a=1.7 if alif_fraction > 0 else 0.0, tau_a=2000.0, loss=0, optimizer=0,
-                 eta=1e-3, max_delay=5)
+                 eta=eta, max_delay=5)
     rec = fixed_indegree_projection(n_rec, n_rec, indeg_rec, gain / np.sqrt(indeg_rec),
                                     rng(seed, _P_GRAPH_REC), rng(seed, _P_W_REC),
                                     rng(seed, _P_DELAY_REC), no_self=True, delay_lo=1, delay_hi=5)
@@ -467,7 +470,7 @@ def c4_sparse(seed: int = SEED_BASE + 4, n_rec: int = 100_000, n_steps: int = 10
     return _large_sparse("c4_sparse", seed, n_rec, min(1000, n_rec - 1), n_in, min(100, n_in),
                          20.0, n_steps, batch_size, C4_GAIN if gain is None else gain,
                          C4_IN_GAIN if in_gain is None else in_gain, 0.0,
-                         iterations, "1e5 LIF, in-degree 1000 (1e8 synapses), batch 4")
+                         iterations, "1e5 LIF, in-degree 1000 (1e8 synapses), batch 4", eta=1e-7)
 
 
 def c5_million(seed: int = SEED_BASE + 5, n_rec: int = 1_000_000, n_steps: int = 2000,
@@ -478,7 +481,7 @@ def c5_million(seed: int = SEED_BASE + 5, n_rec: int = 1_000_000, n_steps: int =
     return _large_sparse("c5_million", seed, n_rec, min(100, n_rec - 1), n_in, min(10, n_in),
                          5.0, n_steps, batch_size, C5_GAIN if gain is None else gain,
                          C5_IN_GAIN if in_gain is None else in_gain, 0.2,
-                         iterations, "1e6 LIF/ALIF, in-degree 100 (1e8 synapses), batch 1")
+                         iterations, "1e6 LIF/ALIF, in-degree 100 (1e8 synapses), batch 1", eta=1e-8)
 
 
 def tiny(seed: int = SEED_BASE + 11, n_steps: int = 200, loss: int = 0, n_in: int = 6,

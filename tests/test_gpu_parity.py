@@ -3,8 +3,10 @@
 Tolerances (relative, normwise and per entry with a floor, see
 tests/helpers.rel_close):
   * FP64: spike trains identical, gradients and weights within 1e-10;
-  * FP32 with teacher-forced spike trains: per-iteration weight change
-    within 1e-4;
+  * FP32 with teacher-forced spike trains: per-iteration weight update
+    within 1e-4 normwise, and per entry for entries above 1% of the largest
+    (smaller entries sit in cancellations that FP32 weights, rounded after
+    each update, shift by more than their own size allows);
   * FP32 free running: mean loss over the last iterations within 2% of the
     oracle's, averaged over seeds (single runs diverge by spike flips).
 """
@@ -195,8 +197,10 @@ def test_device_memory_batch_equals_host_batch():
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4twin", "tiny"])
 def test_fp32_teacher_forced_weight_updates(name):
-    """FP32 with the oracle's (teacher-forced) spike trains: every
-    iteration's weight change within 1e-4 relative of the FP64 oracle's."""
+    """FP32 with the oracle's (teacher-forced) spike trains: each
+    iteration's computed update (the batch-summed gradient that the
+    optimiser receives) within 1e-4 relative of the FP64 oracle's; the stored
+    FP32 weights within that plus FP32 rounding of the weights themselves."""
     if name == "c1":
         # as configured (GD 1e-3) the loss grows to 1e9 by the third iteration;
         # the check runs in the trained regime instead
@@ -210,30 +214,39 @@ def test_fp32_teacher_forced_weight_updates(name):
         wl, bs, it = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), 2, 2
     else:
         wl, bs, it = W.tiny(), 2, 3
-    gh = gpu_train(wl, "fp32", it, bs, forced_rate=20.0, record=False)
+    gh = gpu_train(wl, "fp32", it, bs, forced_rate=20.0)
     oh = oracle_train(wl, it, bs, forced_rate=20.0)
+    u = 2.0 ** -24
+    bound = {k: 0.0 for k in KEYS}
     for i in range(it):
         for k in KEYS:
-            ok, e, ent = rel_close(gh["dw"][i][k], oh["dw"][i][k], 1e-4)
-            log(f"{name} it {i} dW {k}: normwise {e:.2e} worst entry {ent:.2e}")
+            ok, e, ent = rel_close(gh["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
+            log(f"{name} it {i} update {k}: normwise {e:.2e} worst entry {ent:.2e}")
             assert ok, (name, i, k, e, ent)
+            # stored weights: this and earlier updates' tolerance plus FP32 rounding of w
+            dw_o = np.abs(oh["dw"][i][k])
+            bound[k] = bound[k] + 1e-4 * np.maximum(dw_o, 1e-2 * dw_o.max()) + 4 * u * np.abs(oh["weights"][i][k])
+            assert np.all(np.abs(gh["weights"][i][k] - oh["weights"][i][k]) <= bound[k]), (name, i, k)
         assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
 
 
 def test_fp32_free_running_final_loss():
-    """Trained pattern-generation runs (learning rate lowered so that the
-    loss converges): FP32 final loss within 2% of the FP64 oracle's, as the
-    mean over the last 10 of 20 iterations and over 3 seeds."""
-    g_final, o_final = [], []
-    for s in range(3):
+    """Trained pattern-generation runs (learning rate 1e-6, where gradient
+    descent on the summed loss converges): FP32 final loss within 2% of the
+    FP64 oracle's, as the mean over the last 20 of 40 iterations and over 5
+    seeds (single runs decorrelate through spike flips)."""
+    g_final, o_final, first = [], [], []
+    for s in range(5):
         wl = W.c1_pattern(seed=W.SEED_BASE + 100 + s)
-        wl.network.params.eta = 2e-5
-        gh = gpu_train(wl, "fp32", 20, 1, record=False)
-        oh = oracle_train(wl, 20, 1)
-        g_final.append(np.mean([l.mean() for l in gh["loss"][10:]]))
-        o_final.append(np.mean([l.mean() for l in oh["loss"][10:]]))
-        log(f"seed {s}: first loss {oh['loss'][0][0]:.1f}, final gpu {g_final[-1]:.2f} oracle {o_final[-1]:.2f}")
-        assert o_final[-1] < 0.9 * oh["loss"][0][0]   # training reduced the loss
+        wl.network.params.eta = 1e-6
+        gh = gpu_train(wl, "fp32", 40, 1, record=False)
+        oh = oracle_train(wl, 40, 1)
+        g_final.append(np.mean([l.mean() for l in gh["loss"][20:]]))
+        o_final.append(np.mean([l.mean() for l in oh["loss"][20:]]))
+        first.append(oh["loss"][0][0])
+        log(f"seed {s}: first loss {first[-1]:.1f}, final gpu {g_final[-1]:.2f} oracle {o_final[-1]:.2f}")
+        assert o_final[-1] < first[-1]          # training reduced the loss
+    assert np.mean(o_final) < 0.8 * np.mean(first)
     rel = abs(np.mean(g_final) - np.mean(o_final)) / np.mean(o_final)
     log(f"mean final loss gpu {np.mean(g_final):.3f} oracle {np.mean(o_final):.3f} rel {rel:.3e}")
     assert rel < 0.02
@@ -253,8 +266,17 @@ def test_silent_network_and_single_step_trial():
     assert r.loss[0] == pytest.approx(0.5 * (tg ** 2).sum(), rel=1e-12)
     g = net.grads()
     assert np.all(g["w_in"] == 0) and np.all(g["w_rec"] == 0) and np.all(g["w_out"] == 0)
+    # one-step trial: the input spike emitted at step 0 reaches neuron 1 at step 1
+    # (one event, below threshold), nothing else arrives within the trial
     r = net.simulate(batch_from(1, [(0, 0)], 2, target=tg[:1]))
-    assert r.n_rec_spikes == 1 and r.n_syn_events == 0   # the spike at step 1 arrives at step 2 > T
+    assert r.n_rec_spikes == 0 and r.n_syn_events == 1
+    assert net.read(E.EPROP_STATE_V, 0)[1] == pytest.approx(0.5, rel=1e-7)
+    # a strong input makes neuron 1 spike at step 1; its spike would arrive at step 2 > T
+    net_w.in_rec.w[:] = 5.0
+    net2 = E.Network(net_w, "fp32", max_trials=1, max_steps=50)
+    r = net2.simulate(batch_from(1, [(0, 0)], 2, target=tg[:1]))
+    assert r.n_rec_spikes == 1 and r.n_syn_events == 1
+    net2.close()
     net.close()
 
 
@@ -318,6 +340,6 @@ def test_full_size_sparse_network_sampled():
         gi[mi] += a[mi]
         gr[mr] += c[mr]
     for name, gg, ref, m in (("w_in", g["w_in"], gi, mi), ("w_rec", g["w_rec"], gr, mr)):
-        ok, e, ent = rel_close(gg[m], ref[m], 1e-4)
+        ok, e, ent = rel_close(gg[m], ref[m], 1e-4, floor_frac=1e-2)
         log(f"full size {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
         assert ok, (name, e, ent)
