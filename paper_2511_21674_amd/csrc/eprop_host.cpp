@@ -184,8 +184,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   }
   ok &= dalloc(n, &d.nspk, B * T1);
   ok &= dalloc(n, &d.bar, B * 2);
-  ok &= dalloc(n, &p32, n->S); d.sm_syn = p32;
-  ok &= dalloc(n, &d.sm_w, n->S);
+  ok &= dalloc(n, &d.sm, n->S);
   ok &= dalloc(n, &p32, n->J + 1); d.tm_ptr = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_syn = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_perm = p32;
@@ -258,8 +257,15 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   };
   cp((void *)d.sm_ptr, sm_ptr.data(), sm_ptr.size() * 4);
   if (!n->gather) cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
-  cp((void *)d.sm_syn, sm_syn.data(), sm_syn.size() * 4);
-  { auto o = conv(sm_w); cp(d.sm_w, o.data(), o.size() * sizeof(real)); }
+  {
+    std::vector<eprop::SynRec<real>> rec(sm_syn.size());
+    for (size_t q = 0; q < rec.size(); ++q) {
+      rec[q] = eprop::SynRec<real>{};
+      rec[q].syn = sm_syn[q];
+      rec[q].w = (real)sm_w[q];
+    }
+    cp((void *)d.sm, rec.data(), rec.size() * sizeof(rec[0]));
+  }
   cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
   cp((void *)d.tm_syn, tm_syn.data(), tm_syn.size() * 4);
   cp((void *)d.tm_perm, tm_perm.data(), tm_perm.size() * 4);
@@ -942,14 +948,14 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   switch (what) {
     case EPROP_STATE_W_IN:
     case EPROP_STATE_W_REC: {
-      std::vector<real> w;
       const bool in = what == EPROP_STATE_W_IN;
       if (!dst) { bytes = (in ? n->S_in : n->S_rec) * 8; break; }
-      e = fetch(d.sm_w, n->S, w);
+      std::vector<eprop::SynRec<real>> rec(n->S);
+      if (n->S) e = hipMemcpy(rec.data(), d.sm, n->S * sizeof(rec[0]), hipMemcpyDeviceToHost);
       outd.assign(in ? n->S_in : n->S_rec, 0.0);
       for (uint64_t q = 0; q < n->S && e == hipSuccess; ++q) {
         const uint32_t o = n->sm2caller[q];
-        if ((o < n->S_in) == in) outd[in ? o : o - n->S_in] = (double)w[q];
+        if ((o < n->S_in) == in) outd[in ? o : o - n->S_in] = (double)rec[q].w;
       }
       break;
     }

@@ -2,7 +2,7 @@
 // its kernels.  Shared by eprop_kernels.hip and eprop_host.cpp only.
 //
 // HBM layout (b = trial slot, j = neuron, t = step 1..T, Jp = J padded to 64):
-//   graph, source-major  sm_ptr[NS+1], sm_syn[S] = target | delay << 24, sm_w[S]
+//   graph, source-major  sm_ptr[NS+1], sm[S] = {target | delay << 24, weight} records
 //   graph, target-major  tm_ptr[J+1], tm_syn[S] = source | delay << 24, tm_w[S]
 //                        (sources: inputs 0..I-1, then recurrent I..I+J-1;
 //                        each target's list sorted by source), tm_perm[S]
@@ -32,6 +32,22 @@ enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
 enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_BARRIER = 8u };
 enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_WORDS = 8 };
 
+// One source-major synapse: packed target and delay, and the weight, read
+// together by a single load.
+template <typename real>
+struct SynRec;
+template <>
+struct __align__(8) SynRec<float> {
+  uint32_t syn;
+  float w;
+};
+template <>
+struct __align__(16) SynRec<double> {
+  uint32_t syn;
+  uint32_t pad;
+  double w;
+};
+
 template <typename real>
 struct DevNet {
   // sizes
@@ -47,8 +63,8 @@ struct DevNet {
   real alpha, rho, v_th, sg_gamma, sg_beta;
   double alpha_d, rho_d, kappa_d;
   // graph
-  const uint32_t *sm_ptr, *sm_syn, *tseg;
-  real *sm_w;
+  const uint32_t *sm_ptr, *tseg;
+  SynRec<real> *sm;
   const uint32_t *tm_ptr, *tm_syn, *tm_perm;
   real *tm_w, *gs, *gc, *adam_m, *adam_v;
   const real *beta_j;           // beta_a for ALIF neurons, 0 for LIF [Jp]

@@ -183,32 +183,35 @@ __device__ inline uint64_t publish_bits(const DevNet<real> &n, uint32_t b, uint3
 }
 
 // Barrier of the KT workgroups that simulate one trial.  Thread 0 releases
-// the workgroup's global writes, arrives, and waits for the generation to
-// change.  The wait is bounded: on timeout it flags ERR_BARRIER and returns
-// false, so every wavefront always reaches the end of the kernel.
+// the workgroup's global writes (one agent-scope release fence), arrives,
+// and waits on relaxed coherent loads of the generation (an acquire inside
+// the wait loop would invalidate the L2 on every poll), then acquires once.
+// The wait is bounded: on timeout it flags ERR_BARRIER and returns false, so
+// every wavefront always reaches the end of the kernel.
 __device__ inline bool group_barrier(uint32_t *bar, uint32_t members, uint32_t *err) {
   __shared__ uint32_t ok_s;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ok = 1;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const uint32_t g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == members) {
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1u << 24)) {  // far beyond any legitimate wait (about a second)
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1u << 25)) {  // far beyond any legitimate wait (about a second)
           atomicOr(err, ERR_BARRIER);
           ok = 0;
           break;
         }
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok_s = ok;
   }
   __syncthreads();
@@ -243,14 +246,19 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *wsum, uint
 // Adds the spikes emitted at step t by inputs and by recurrent neurons of
 // trial b into this tile's LDS ring.  Per chunk of up to blockDim spiking
 // sources: every thread resolves one source to its segment (the part of its
-// target-sorted row inside this tile), a block scan flattens the segments,
-// and consecutive threads take consecutive synapses (coalesced loads, all
-// independent), each adding its weight into the ring slot of its arrival.
-// Only arrivals within the trial are kept.  dlo, dpre: LDS [blockDim];
-// wsum: LDS [17].
+// target-sorted row inside this tile); segments are cut into pieces of at
+// most PL synapses, numbered by a block scan, and each source records itself
+// as the owner of its pieces; each thread then takes a piece, issues all of
+// its record loads at once and adds each weight into the ring slot of its
+// arrival (only arrivals within the trial).  dlo, dlen, dpre: LDS
+// [blockDim]; owner: LDS [kOwner]; wsum: LDS [17].
+constexpr uint32_t kPiece = 16;
+constexpr uint32_t kOwner = 4096;
+
 template <typename real>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
-                                    uint32_t Tb, real *ring, uint32_t *dlo, uint32_t *dpre, uint32_t *wsum) {
+                                    uint32_t Tb, real *ring, uint32_t *dlo, uint32_t *dlen, uint32_t *dpre,
+                                    uint16_t *owner, uint32_t *wsum) {
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
@@ -261,6 +269,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   const uint32_t total = n_in + n_rec;
   const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
   uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
+  const uint32_t slot_t = t % n.R;
   for (uint32_t base = 0; base < total; base += blockDim.x) {
     const uint32_t m = min(blockDim.x, total - base);
     uint32_t lo = 0, len = 0;
@@ -273,41 +282,34 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
       lo = ts[0];
       len = ts[1] - lo;
     }
-    uint32_t nsyn;
-    const uint32_t pre = block_exclusive_scan(len, wsum, &nsyn);
+    const uint32_t np = (len + kPiece - 1) / kPiece;
+    uint32_t npieces;
+    const uint32_t pre = block_exclusive_scan(np, wsum, &npieces);
     dlo[threadIdx.x] = lo;
+    dlen[threadIdx.x] = len;
     dpre[threadIdx.x] = pre;
-    __syncthreads();
-    // U positions per thread and pass: the segment searches, then all 2U
-    // graph loads, then the LDS additions, so that many loads are in flight
-    constexpr int U = 8;
-    uint32_t top = 1;
-    while (2 * top <= m) top *= 2;
-    for (uint32_t p0 = threadIdx.x; p0 < nsyn; p0 += U * blockDim.x) {
-      uint32_t q[U];
+    for (uint32_t w0 = 0; w0 < npieces; w0 += kOwner) {
+      const uint32_t w1 = min(npieces, w0 + kOwner);
+      for (uint32_t pc = max(pre, w0); pc < min(pre + np, w1); ++pc) owner[pc - w0] = (uint16_t)threadIdx.x;
+      __syncthreads();
+      for (uint32_t pc = w0 + threadIdx.x; pc < w1; pc += blockDim.x) {
+        const uint32_t i = owner[pc - w0];
+        const uint32_t off = (pc - dpre[i]) * kPiece;
+        const uint32_t q0 = dlo[i] + off;
+        const uint32_t cnt = min(kPiece, dlen[i] - off);
+        SynRec<real> r[kPiece];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t p = min(p0 + u * blockDim.x, nsyn - 1);
-        uint32_t l = 0;  // largest i < m with dpre[i] <= p
-        for (uint32_t step = top; step > 0; step >>= 1)
-          if (l + step < m && dpre[l + step] <= p) l += step;
-        q[u] = dlo[l] + (p - dpre[l]);
-      }
-      uint32_t pk[U];
-      real w[U];
+        for (uint32_t e = 0; e < kPiece; ++e) r[e] = n.sm[q0 + (e < cnt ? e : 0u)];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        pk[u] = n.sm_syn[q[u]];
-        w[u] = n.sm_w[q[u]];
+        for (uint32_t e = 0; e < kPiece; ++e) {
+          const uint32_t d = r[e].syn >> 24;
+          uint32_t slot = slot_t + d;
+          if (slot >= n.R) slot -= n.R;
+          if (e < cnt && t + d <= Tb) atomicAdd(&ring[slot * n.TS + ((r[e].syn & 0xFFFFFFu) - j0)], r[e].w);
+        }
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t ta = t + (pk[u] >> 24);
-        if (p0 + u * blockDim.x < nsyn && ta <= Tb)
-          atomicAdd(&ring[(ta % n.R) * n.TS + ((pk[u] & 0xFFFFFFu) - j0)], w[u]);
-      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -336,8 +338,10 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   uint64_t *words = reinterpret_cast<uint64_t *>(sb + TS);
   uint32_t *woff = reinterpret_cast<uint32_t *>(words + TS / 64);
   uint32_t *dlo = woff + TS / 64 + 1;
-  uint32_t *dpre = dlo + blockDim.x;
-  uint8_t *sst = reinterpret_cast<uint8_t *>(dpre + blockDim.x);
+  uint32_t *dlen = dlo + blockDim.x;
+  uint32_t *dpre = dlen + blockDim.x;
+  uint16_t *owner = reinterpret_cast<uint16_t *>(dpre + blockDim.x);
+  uint8_t *sst = reinterpret_cast<uint8_t *>(owner + kOwner);
   __shared__ uint32_t gbase;
   __shared__ uint32_t wsum[17];
 
@@ -351,7 +355,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile(n, b, k, j0, 0, Tb, ring, dlo, dpre, wsum);
+    deliver_tile(n, b, k, j0, 0, Tb, ring, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
   bool ok = true;
@@ -405,7 +409,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     } else {
       __syncthreads();
     }
-    if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, dlo, dpre, wsum);
+    if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -800,7 +804,7 @@ __global__ __launch_bounds__(256) void k_apply_syn(DevNet<real> n, uint64_t S, d
       n.adam_v[q] = (real)v;
     }
     n.tm_w[q] = (real)w;
-    n.sm_w[n.tm_perm[q]] = (real)w;
+    n.sm[n.tm_perm[q]].w = (real)w;
     n.gs[q] = (real)0;
     n.gc[q] = (real)0;
   }
@@ -863,7 +867,7 @@ void Launch<real>::neuron_gather(const DevNet<real> &n, uint32_t off, bool force
 template <typename real>
 size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R) {
   const size_t block = TS < 1024 ? TS : 1024;
-  return (size_t)(R + 3) * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 + 2 * block * 4 + TS + 64;
+  return (size_t)(R + 3) * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 + 3 * block * 4 + kOwner * 2 + TS + 64;
 }
 
 template <typename real>

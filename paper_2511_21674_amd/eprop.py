@@ -84,6 +84,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP extension not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime under the same soname; loading it
+        # first makes the library bind to that one runtime in this process
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.eprop_create_network.argtypes = [C.POINTER(eprop_config), C.POINTER(eprop_projection),
                                            C.POINTER(eprop_projection), _P, _P,
