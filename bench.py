@@ -56,6 +56,29 @@ def algorithmic_bytes(phase, rs, counts, net, batch_T, n_trials, kt, launches):
     return None
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
+    counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain copy of known size), or None when there is no record
+    for this workload or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    src = os.path.join(ROOT, "paper_2511_21674_amd", "csrc", "eprop_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ": " in line:
+            k, v = line.strip().split(": ", 1)
+            rec[k] = v
+    if not rec.get("kernel", "").startswith(kernel):
+        return None
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return (float(rec["fetch_kib_per_dispatch"]) * float(rec["copy_fetch_factor"])
+            + float(rec["write_kib_per_dispatch"]) * float(rec["copy_write_factor"])) * 1024.0
+
+
 def stage_batches(wl, n, first_iteration):
     from paper_2511_21674_amd import eprop as E
     out = []
@@ -139,6 +162,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
+                         "kernel for scaling hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
@@ -152,6 +178,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}), flush=True)
+        return
     wl = W.WORKLOADS[args.workload]()
     net_w = wl.network
     T = max(int(wl.make_batch(0, 0, 1).n_steps.max()), 1)
@@ -204,6 +240,10 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_ms": round(ms / n_launch, 4), "algorithmic_bytes_per_launch": int(ab / n_launch)}
+    tr = measured_traffic(wl.name, roof["kernel"])
+    if tr is not None:
+        roof["traffic"] = round(tr / 1e9, 3)
+        roof["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     fp64 = None
     if not args.no_fp64:
