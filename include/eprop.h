@@ -250,9 +250,11 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18      /* uint64 [8]: neurons per tile, tiles per trial, lanes per source,
-                                  threads per tile, synapse-kernel threads, trials per synapse
-                                  block, steps per forward launch, gather delivery (0/1) */
+  EPROP_STATE_LAYOUT = 18      /* uint64 [8]: neurons per tile, tiles per trial, bytes per
+                                  delay-ring entry (8: 64-bit fixed point in FP32 or double in
+                                  FP64, 4: 32-bit fixed point in FP32), threads per tile,
+                                  synapse-kernel threads, trials per synapse block, steps per
+                                  forward launch, gather delivery (0/1) */
 } eprop_state_id;
 
 /* Copies one state array to host memory dst (dst_bytes large).  With

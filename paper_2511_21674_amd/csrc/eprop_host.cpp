@@ -177,7 +177,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   bool ok = true;
   d.TS = n->n32.TS ? n->n32.TS : n->n64.TS;
   d.KT = n->n32.KT ? n->n32.KT : n->n64.KT;
-  d.grp = n->n32.grp ? n->n32.grp : n->n64.grp;
+  d.ring_bytes = n->n32.ring_bytes ? n->n32.ring_bytes : n->n64.ring_bytes;
   ok &= dalloc(n, &p32, n->NS + 1); d.sm_ptr = p32;
   if (!n->gather) {
     ok &= dalloc(n, &p32, (size_t)n->NS * (d.KT + 1)); d.tseg = p32;
@@ -209,7 +209,12 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.v, B * n->Jp);
   ok &= dalloc(n, &d.a, B * n->Jp);
   ok &= dalloc(n, &d.nst, B * n->Jp);
-  ok &= dalloc(n, &d.ring, B * n->R * n->Jp);
+  {
+    uint8_t *rp = nullptr;
+    ok &= dalloc(n, &rp, B * n->R * n->Jp * d.ring_bytes);
+    d.ring = rp;
+  }
+  ok &= dalloc(n, &d.l1max, 1);
   ok &= dalloc(n, &d.psi, B * T1 * n->Jp);
   ok &= dalloc(n, &d.phi, B * n->Jp * n->Tp);
   ok &= dalloc(n, &d.rec_bits, B * T1 * n->Jw);
@@ -229,6 +234,15 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.cnt, eprop::CNT_WORDS);
   ok &= dalloc(n, &d.evcnt, 64);
   const uint32_t nchunk_max = (n->Bcap + n->shapes.ginst - 1) / n->shapes.ginst;
+  {
+    // worst case: every record has a header and a partly used last block
+    const size_t recs = (size_t)nchunk_max * n->NS;
+    d.pk_cap = 2 * recs + (B * n->NS * (size_t)d.Lc + 7) / 8 + 8;
+    ok &= d.pk_cap < 0xFFFFFFF0ull;
+    ok &= dalloc(n, &d.pk_off, recs + 1);
+    ok &= dalloc(n, &d.pk_bsum, (recs + eprop::kScanItems - 1) / eprop::kScanItems + 1);
+    ok &= dalloc(n, &d.pk, d.pk_cap * 8);
+  }
   if (nchunk_max > 1) {
     real *part = nullptr;
     ok &= dalloc(n, &part, (size_t)nchunk_max * n->S);
@@ -285,6 +299,11 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   if (e == hipSuccess) e = hipMemset(d.gos, 0, KJ * sizeof(real));
   if (e == hipSuccess) e = hipMemset(d.goc, 0, KJ * sizeof(real));
   if (e == hipSuccess) e = hipMemset(d.cnt, 0, eprop::CNT_WORDS * 8);
+  if (e == hipSuccess) {
+    Launch<real>::input_bound(d, nullptr);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
   if (n->adam && e == hipSuccess) {
     // optimiser state: caller order -> target-major
     std::vector<double> m(n->S, 0.0), v(n->S, 0.0), mo(KJ, 0.0), vo(KJ, 0.0);
@@ -489,39 +508,47 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   // Tiles of the persistent forward kernel: as many neurons per workgroup as
   // LDS allows, but enough tiles to spread the trials over the device; small
   // networks keep a whole trial in one workgroup (no inter-workgroup barrier).
-  uint32_t TS = n->Jp, KT = 1, grp = 1, tile_block = 64;
+  uint32_t TS = n->Jp, KT = 1, tile_block = 64, ring_bytes = 8;
   if (!n->gather) {
-    const size_t rs = n->fp64 ? 8 : 4;
     size_t lds = prop.sharedMemPerBlock;
     if (prop.sharedMemPerBlockOptin > lds) lds = prop.sharedMemPerBlockOptin;
     if (prop.maxSharedMemoryPerMultiProcessor > 0 && lds > prop.maxSharedMemoryPerMultiProcessor)
       lds = prop.maxSharedMemoryPerMultiProcessor;
     const size_t fixed = 1024;  // static LDS of the kernel and slack
-    uint32_t ts_lds = (uint32_t)(((lds - fixed) / ((n->R + 3) * rs + 2)) / 64 * 64);
-    while (ts_lds > 64 && (n->fp64 ? Launch<double>::tile_smem(ts_lds, n->R) : Launch<float>::tile_smem(ts_lds, n->R)) + fixed > lds)
-      ts_lds -= 64;
+    auto smem_of = [&](uint32_t ts, uint32_t rb) {
+      return n->fp64 ? Launch<double>::tile_smem(ts, n->R, rb) : Launch<float>::tile_smem(ts, n->R, rb);
+    };
+    auto ts_max = [&](uint32_t rb) {  // largest tile (multiple of 64) that fits LDS
+      uint32_t ts = 64;
+      while (smem_of(ts + 64, rb) + fixed <= lds) ts += 64;
+      return smem_of(ts, rb) + fixed <= lds ? ts : 0u;
+    };
     const uint32_t cu = std::max(1, prop.multiProcessorCount);
     const uint32_t want = std::max<uint32_t>(1, cu / n->Bcap);
     uint32_t ts_par = round_up((J + want - 1) / want, 64);
     ts_par = std::max<uint32_t>(ts_par, std::min<uint32_t>(n->Jp, 1024));
-    TS = std::min(std::min(ts_lds, ts_par), n->Jp);
-    TS = std::max<uint32_t>(TS, 64);
-    KT = (n->Jp + TS - 1) / TS;
-    tile_block = std::min<uint32_t>(1024, TS);
-    const double avg_seg = (double)S / ((double)NS * KT);
-    grp = 1;
-    while (grp < 64 && grp * 4 < avg_seg) grp *= 2;
-    n->tile_smem = n->fp64 ? Launch<double>::tile_smem(TS, n->R) : Launch<float>::tile_smem(TS, n->R);
+    ts_par = std::min(ts_par, n->Jp);
+    // FP32: exact 64-bit fixed-point ring unless it would force more tiles
+    // than the device spreads the trials over; then 32-bit entries
+    uint32_t ts_lds = ts_max(8);
+    if (!n->fp64 && ts_lds < ts_par) {
+      ring_bytes = 4;
+      ts_lds = ts_max(4);
+    }
     if (ts_lds < 64) {
       g_create_error = "not enough LDS for a tile of 64 neurons";
       delete n;
       return EPROP_ERR_UNSUPPORTED;
     }
+    TS = std::max<uint32_t>(std::min(ts_lds, ts_par), 64);
+    KT = (n->Jp + TS - 1) / TS;
+    tile_block = std::min<uint32_t>(1024, TS);
+    n->tile_smem = smem_of(TS, ring_bytes);
   }
   n->shapes.tile_block = tile_block;
   n->n32.TS = n->n64.TS = TS;
   n->n32.KT = n->n64.KT = KT;
-  n->n32.grp = n->n64.grp = grp;
+  n->n32.ring_bytes = n->n64.ring_bytes = ring_bytes;
   n->blk = std::min<uint32_t>(n->gather ? 50 : 250, n->Tcap);
 
   std::vector<double> beta(n->Jp, 0.0);
@@ -552,11 +579,12 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   }
   hipError_t e = hipSuccess;
   if (!n->gather) {
-    e = n->fp64 ? Launch<double>::allow_smem(n->tile_smem) : Launch<float>::allow_smem(n->tile_smem);
+    const uint32_t rb = n->n32.ring_bytes ? n->n32.ring_bytes : n->n64.ring_bytes;
+    e = n->fp64 ? Launch<double>::allow_smem(n->tile_smem, rb) : Launch<float>::allow_smem(n->tile_smem, rb);
     int per_cu = 0;
     if (e == hipSuccess)
-      e = n->fp64 ? Launch<double>::resident(tile_block, n->tile_smem, &per_cu)
-                  : Launch<float>::resident(tile_block, n->tile_smem, &per_cu);
+      e = n->fp64 ? Launch<double>::resident(tile_block, n->tile_smem, rb, &per_cu)
+                  : Launch<float>::resident(tile_block, n->tile_smem, rb, &per_cu);
     if (e == hipSuccess && (uint64_t)per_cu * prop.multiProcessorCount < KT) {
       g_create_error = "the tiles of one trial cannot be resident together on this device";
       eprop_destroy_network(n);
@@ -783,7 +811,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   MS(d.v, (size_t)ntr * n->Jp * sizeof(real));
   MS(d.a, (size_t)ntr * n->Jp * sizeof(real));
   MS(d.nst, (size_t)ntr * n->Jp);
-  MS(d.ring, (size_t)ntr * n->R * n->Jp * sizeof(real));
+  MS(d.ring, (size_t)ntr * n->R * n->Jp * d.ring_bytes);
   MS(d.in_bits, (size_t)ntr * n->Tcap * n->Iw * 8);
   MS(d.spk_cnt, (size_t)ntr * n->NS * 4);
   MS(d.rec_cnt, (size_t)ntr * T1 * 4);
@@ -851,6 +879,12 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
       set_fail(n, "tile barrier timed out: the workgroups of a trial were not resident together");
       return EPROP_ERR_DEVICE;
     }
+    if (flags & eprop::ERR_INPUT_BOUND) {
+      n->failed = true;
+      set_fail(n, "weights too large for the FP32 fixed-point input accumulator "
+                  "(sum of |w| into one neuron above 2^22)");
+      return EPROP_ERR_NUMERIC;
+    }
     if (flags) {
       set_fail(n, "forced spike out of range");
       return EPROP_ERR_INVALID_ARGUMENT;
@@ -905,6 +939,7 @@ eprop_status apply(eprop_network *n, DevNet<real> &d) {
   const double eta_t = n->cfg.eta * std::sqrt(1.0 - std::pow(b2, step)) / (1.0 - std::pow(b1, step));
   Launch<real>::apply(d, n->S, (double)n->trials_accum, n->cfg.optimizer, n->cfg.eta, eta_t, b1, b2,
                       n->cfg.adam_eps_hat, n->stream);
+  Launch<real>::input_bound(d, n->stream);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
   if (e != hipSuccess) {
@@ -923,7 +958,7 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   const bool per_trial = what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V;
   if (what < 0 || what > EPROP_STATE_LAYOUT) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
-    const uint64_t lay[8] = {d.TS, d.KT, d.grp, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
+    const uint64_t lay[8] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                              n->blk, n->gather ? 1u : 0u};
     if (needed) *needed = sizeof(lay);
     if (!dst) return EPROP_OK;

@@ -10,7 +10,11 @@
 //   gradient sums        gs[S], gc[S] (Kahan pair, target-major), Adam m, v
 //   neuron state         v[b][Jp], a[b][Jp], nst[b][Jp] (refractory count | z << 7)
 //   delay ring           ring[b][R][Jp], R = max_delay + 1 (scatter delivery; held in
-//                        LDS by the tile that owns the targets, saved between launches)
+//                        LDS by the tile that owns the targets, saved between launches;
+//                        FP32: 64-bit (or, where LDS is short, 32-bit) fixed point
+//                        with scale 2^-F; FP64: double)
+//   input bound          l1max: max over targets of the sum of |w| of incoming
+//                        synapses (FP32 bits), which fixes F
 //   tile segments        tseg[src][k], k = 0..KT: first synapse of source src whose
 //                        target lies in tile k (source rows sorted by target)
 //   psi archive          psi[b][t][Jp]          (time-major, written per step)
@@ -29,8 +33,11 @@ namespace eprop {
 // ctl words; the 64-bit device pointer to the batch's input-source array is
 // stored at word CTL_WORDS (byte offset 64)
 enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
-enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_BARRIER = 8u };
+enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_BARRIER = 8u,
+                  ERR_INPUT_BOUND = 16u };
 enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_WORDS = 8 };
+constexpr uint32_t kScanItems = 4096;        // entries per block of the spike-table scan
+constexpr uint32_t kNoRecord = 0xFFFFFFFFu;  // spike-table offset of a source without spikes
 
 // One source-major synapse: packed target and delay, and the weight, read
 // together by a single load.
@@ -48,6 +55,15 @@ struct __align__(16) SynRec<double> {
   double w;
 };
 
+// Element of the delay ring.  FP32: the input current of a step is summed
+// in fixed point, int64_t (F up to 62 fraction bits: every FP32 weight of
+// the network converts exactly, so the sum is exact and is rounded once) or
+// int32_t where 8-byte entries do not fit LDS (F up to 30; each weight is
+// rounded to a multiple of 2^-F).  Integer LDS atomics are an order of
+// magnitude faster than float ones on this GPU, and the sum does not depend
+// on the order of arrival.  F follows from l1max, so no sum can overflow.
+// FP64: plain double.
+
 template <typename real>
 struct DevNet {
   // sizes
@@ -58,7 +74,7 @@ struct DevNet {
   uint32_t n_ref;
   int32_t surrogate, loss;
   uint32_t step_stride;         // batch target/window row length
-  uint32_t TS, KT, grp;         // tile size (neurons), tiles per trial, lanes per source in delivery
+  uint32_t TS, KT;              // tile size (neurons), tiles per trial
   // constants (working precision for the dynamics, FP64 for the backward filters)
   real alpha, rho, v_th, sg_gamma, sg_beta;
   double alpha_d, rho_d, kappa_d;
@@ -74,10 +90,20 @@ struct DevNet {
   // per-slot state
   real *v, *a;
   uint8_t *nst;
-  real *ring, *psi, *phi;
+  void *ring;                   // ring_t [Bcap][R][Jp]
+  uint32_t ring_bytes;          // 8: int64_t (FP32) or double (FP64); 4: int32_t (FP32)
+  real *psi, *phi;
+  uint32_t *l1max;              // [1] bound on |input current| per step (FP32 bits)
   uint64_t *rec_bits, *in_bits, *forced_bits;
   uint32_t *spk_cnt;
   uint16_t *spk_t;
+  // per-source spike table of a batch for the synapse kernel: record (c, i)
+  // of trial chunk c and source i = 16-byte header of 8 uint16 spike counts,
+  // then the spike times of the chunk's trials, trial by trial
+  uint32_t *pk_off;             // [nchunk*NS + 1] record offset in 16-byte units, kNoRecord if empty
+  uint32_t *pk_bsum;            // [scan blocks + 1]
+  uint16_t *pk;                 // [pk_cap * 8]
+  uint64_t pk_cap;
   uint32_t *rec_cnt, *rec_list, *nspk, *bar;
   uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
   double *ysum, *y, *err, *ebar;  // [Bcap][Tcap+2][K]
@@ -115,15 +141,17 @@ struct Launch {
   // persistent tiled forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps
   static void forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t block,
                             size_t smem, hipStream_t s);
-  static size_t tile_smem(uint32_t TS, uint32_t R);
-  static hipError_t allow_smem(size_t smem);
-  static hipError_t resident(uint32_t block, size_t smem, int *per_cu);
+  static size_t tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes);
+  static hipError_t allow_smem(size_t smem, uint32_t ring_bytes);
+  static hipError_t resident(uint32_t block, size_t smem, uint32_t ring_bytes, int *per_cu);
   static void readout(const DevNet<real> &n, hipStream_t s);
   static void adjoint(const DevNet<real> &n, hipStream_t s);
   static void synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *partial, hipStream_t s);
   static void output_reduce(const DevNet<real> &n, hipStream_t s);
   static void apply(const DevNet<real> &n, uint64_t n_syn, double n_trials, int optimizer, double eta,
                     double eta_t, double b1, double b2, double eps_hat, hipStream_t s);
+  // recomputes *l1max from the current weights (after upload and every update)
+  static void input_bound(const DevNet<real> &n, hipStream_t s);
 };
 
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s);

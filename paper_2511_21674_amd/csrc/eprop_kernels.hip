@@ -243,22 +243,68 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *wsum, uint
   return wsum[w] + inc - x;
 }
 
+// Delay-ring arithmetic.  FP32: fixed point with F fraction bits (weights
+// rounded to nearest; the integer sums are exact); FP64: double.
+struct RingScale {
+  float to_fix;    // 2^F
+  float from_fix;  // 2^-F
+};
+
+// F from the bound on |input current| per step: the largest F with
+// l1max * 2^F <= 2^(bits-2) (30 for int32, 62 for int64), so that every
+// partial sum and every rounding excess stays inside the integer.  Below 8
+// fraction bits the bound is reported as an error.
+template <typename A>
+__device__ inline RingScale ring_scale(const uint32_t *l1max, uint32_t *err) {
+  constexpr int top = sizeof(A) == 8 ? 62 : 30;
+  const float l1 = __uint_as_float(*l1max);
+  int F = top;
+  if (l1 > 0.f) F = min(top, top - (int)ceilf(log2f(l1)));
+  if (F < 8) {
+    if (threadIdx.x == 0) atomicOr(err, ERR_INPUT_BOUND);
+    F = max(F, -60);
+  }
+  return RingScale{ldexpf(1.f, F), ldexpf(1.f, -F)};
+}
+
+__device__ inline void ring_add(int32_t *p, float w, const RingScale &sc) {
+  atomicAdd(p, __float2int_rn(w * sc.to_fix));
+}
+__device__ inline void ring_add(int64_t *p, float w, const RingScale &sc) {
+  atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__float2ll_rn(w * sc.to_fix));
+}
+__device__ inline void ring_add(double *p, double w, const RingScale &) { atomicAdd(p, w); }
+__device__ inline float ring_value(int32_t x, const RingScale &sc) { return (float)x * sc.from_fix; }
+__device__ inline float ring_value(int64_t x, const RingScale &sc) { return (float)x * sc.from_fix; }
+__device__ inline double ring_value(double x, const RingScale &) { return x; }
+
 // Adds the spikes emitted at step t by inputs and by recurrent neurons of
 // trial b into this tile's LDS ring.  Per chunk of up to blockDim spiking
 // sources: every thread resolves one source to its segment (the part of its
-// target-sorted row inside this tile); segments are cut into pieces of at
-// most PL synapses, numbered by a block scan, and each source records itself
-// as the owner of its pieces; each thread then takes a piece, issues all of
-// its record loads at once and adds each weight into the ring slot of its
-// arrival (only arrivals within the trial).  dlo, dlen, dpre: LDS
-// [blockDim]; owner: LDS [kOwner]; wsum: LDS [17].
-constexpr uint32_t kPiece = 16;
+// target-sorted row inside this tile); segments are cut into pieces of
+// kPiece synapses, numbered by a block scan, and each source records itself
+// as the owner of its pieces.  A group of kPiece consecutive lanes then
+// takes one piece, one synapse record per lane, so that a wavefront's load
+// covers a few contiguous lines; each group keeps kUnroll pieces in flight
+// before adding the weights into the ring slots of their arrivals (only
+// arrivals within the trial).  dlo, dlen, dpre: LDS [blockDim]; owner: LDS
+// [kOwner]; wsum: LDS [17].
+#ifndef EPROP_PIECE
+#define EPROP_PIECE 8
+#endif
+#ifndef EPROP_UNROLL
+#define EPROP_UNROLL 8
+#endif
+constexpr uint32_t kPiece = EPROP_PIECE;
+constexpr uint32_t kUnroll = EPROP_UNROLL;
 constexpr uint32_t kOwner = 4096;
+static_assert(kPiece == 4 || kPiece == 8 || kPiece == 16 || kPiece == 32 || kPiece == 64, "piece = lanes per group");
 
-template <typename real>
+template <typename real, typename ring_t>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
-                                    uint32_t Tb, real *ring, uint32_t *dlo, uint32_t *dlen, uint32_t *dpre,
-                                    uint16_t *owner, uint32_t *wsum) {
+                                    uint32_t Tb, ring_t *ring, const RingScale &sc,
+                                    uint32_t *dlo, uint32_t *dlen, uint32_t *dpre, uint16_t *owner,
+                                    uint32_t *wsum) {
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
@@ -270,6 +316,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
   uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
   const uint32_t slot_t = t % n.R;
+  const uint32_t sub = threadIdx.x & (kPiece - 1u), grp = threadIdx.x / kPiece, ngrp = blockDim.x / kPiece;
   for (uint32_t base = 0; base < total; base += blockDim.x) {
     const uint32_t m = min(blockDim.x, total - base);
     uint32_t lo = 0, len = 0;
@@ -292,20 +339,32 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
       const uint32_t w1 = min(npieces, w0 + kOwner);
       for (uint32_t pc = max(pre, w0); pc < min(pre + np, w1); ++pc) owner[pc - w0] = (uint16_t)threadIdx.x;
       __syncthreads();
-      for (uint32_t pc = w0 + threadIdx.x; pc < w1; pc += blockDim.x) {
-        const uint32_t i = owner[pc - w0];
-        const uint32_t off = (pc - dpre[i]) * kPiece;
-        const uint32_t q0 = dlo[i] + off;
-        const uint32_t cnt = min(kPiece, dlen[i] - off);
-        SynRec<real> r[kPiece];
+      for (uint32_t pc0 = w0 + grp; pc0 < w1; pc0 += kUnroll * ngrp) {
+        // branch-free address phase, then all loads, then the ring adds: the
+        // loads of a group are in flight together (dead lanes read record 0,
+        // which exists whenever there is a piece)
+        uint32_t idx[kUnroll];
+        uint32_t live = 0;
 #pragma unroll
-        for (uint32_t e = 0; e < kPiece; ++e) r[e] = n.sm[q0 + (e < cnt ? e : 0u)];
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+          const uint32_t pc = pc0 + u * ngrp;
+          const bool inb = pc < w1;
+          const uint32_t i = owner[inb ? pc - w0 : 0u];
+          const uint32_t off = (pc - dpre[i]) * kPiece + sub;
+          const bool ok = inb && off < dlen[i];
+          idx[u] = ok ? dlo[i] + off : 0u;
+          live |= (uint32_t)ok << u;
+        }
+        SynRec<real> r[kUnroll];
 #pragma unroll
-        for (uint32_t e = 0; e < kPiece; ++e) {
-          const uint32_t d = r[e].syn >> 24;
+        for (uint32_t u = 0; u < kUnroll; ++u) r[u] = n.sm[idx[u]];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+          if (!((live >> u) & 1u)) continue;
+          const uint32_t d = r[u].syn >> 24;
           uint32_t slot = slot_t + d;
           if (slot >= n.R) slot -= n.R;
-          if (e < cnt && t + d <= Tb) atomicAdd(&ring[slot * n.TS + ((r[e].syn & 0xFFFFFFu) - j0)], r[e].w);
+          if (t + d <= Tb) ring_add(&ring[slot * n.TS + ((r[u].syn & 0xFFFFFFu) - j0)], r[u].w, sc);
         }
       }
       __syncthreads();
@@ -319,7 +378,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 // tile, spike publication (bitset, spike times, compacted list with one
 // global atomic per workgroup), one barrier among the trial's KT
 // workgroups, delivery of the step's spikes into the tile's ring.
-template <typename real, bool FORCED>
+template <typename real, typename ring_t, bool FORCED>
 __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t KT = n.KT, TS = n.TS;
@@ -331,11 +390,11 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   const uint32_t j0 = k * TS;
   const uint32_t nt = min(TS, n.Jp - j0);  // multiple of 64
   const uint32_t nw = nt >> 6;
-  real *ring = reinterpret_cast<real *>(smem);
-  real *sv = ring + (size_t)n.R * TS;
+  ring_t *ring = reinterpret_cast<ring_t *>(smem);
+  ring_t *gring = static_cast<ring_t *>(n.ring);
+  real *sv = reinterpret_cast<real *>(ring + (size_t)n.R * TS);
   real *sa = sv + TS;
-  real *sb = sa + TS;
-  uint64_t *words = reinterpret_cast<uint64_t *>(sb + TS);
+  uint64_t *words = reinterpret_cast<uint64_t *>(sa + TS);
   uint32_t *woff = reinterpret_cast<uint32_t *>(words + TS / 64);
   uint32_t *dlo = woff + TS / 64 + 1;
   uint32_t *dlen = dlo + blockDim.x;
@@ -344,18 +403,19 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   uint8_t *sst = reinterpret_cast<uint8_t *>(owner + kOwner);
   __shared__ uint32_t gbase;
   __shared__ uint32_t wsum[17];
+  RingScale sc{1.f, 1.f};
+  if constexpr (sizeof(real) == 4) sc = ring_scale<ring_t>(n.l1max, &n.ctl[CTL_ERR]);
 
   const size_t gs = (size_t)b * n.Jp + j0;
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
     sv[i] = n.v[gs + i];
     sa[i] = n.a[gs + i];
-    sb[i] = n.beta_j[j0 + i];
     sst[i] = n.nst[gs + i];
-    for (uint32_t r = 0; r < n.R; ++r) ring[r * TS + i] = n.ring[((size_t)b * n.R + r) * n.Jp + j0 + i];
+    for (uint32_t r = 0; r < n.R; ++r) ring[r * TS + i] = gring[((size_t)b * n.R + r) * n.Jp + j0 + i];
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile(n, b, k, j0, 0, Tb, ring, dlo, dlen, dpre, owner, wsum);
+    deliver_tile(n, b, k, j0, 0, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
   bool ok = true;
@@ -365,10 +425,10 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
       real v = sv[i], a = sa[i];
       uint8_t st = sst[i];
-      const real I = ring[slot * TS + i];
-      ring[slot * TS + i] = (real)0;
+      const real I = ring_value(ring[slot * TS + i], sc);
+      ring[slot * TS + i] = (ring_t)0;
       const uint32_t j = j0 + i;
-      const bool z = neuron_step<real, FORCED>(n, b, t, j, j < n.J, I, sb[i], v, a, st);
+      const bool z = neuron_step<real, FORCED>(n, b, t, j, j < n.J, I, n.beta_j[j], v, a, st);
       sv[i] = v;
       sa[i] = a;
       sst[i] = st;
@@ -409,14 +469,14 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     } else {
       __syncthreads();
     }
-    if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, dlo, dlen, dpre, owner, wsum);
+    if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
     n.v[gs + i] = sv[i];
     n.a[gs + i] = sa[i];
     n.nst[gs + i] = sst[i];
-    for (uint32_t r = 0; r < n.R; ++r) n.ring[((size_t)b * n.R + r) * n.Jp + j0 + i] = ring[r * TS + i];
+    for (uint32_t r = 0; r < n.R; ++r) gring[((size_t)b * n.R + r) * n.Jp + j0 + i] = ring[r * TS + i];
   }
 }
 
@@ -664,45 +724,134 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   }
 }
 
+// Per-source spike table of the batch.  The synapse kernel visits the
+// synapses of a target, whose sources are scattered; keeping all of a
+// source's spike times of a trial chunk in one contiguous record lets a
+// lane fetch them with one or two line reads instead of two per trial.
+// Records are 16-byte aligned, chunk-major and source-minor; their offsets
+// come from a three-kernel exclusive scan of the record sizes.
+template <typename real>
+__device__ inline uint32_t pk_units(const DevNet<real> &n, uint32_t e, uint32_t ginst, uint32_t ntr) {
+  const uint32_t c = e / n.NS, i = e - c * n.NS;
+  const uint32_t b0 = c * ginst;
+  if (b0 >= ntr) return 0;
+  const uint32_t nb = min(ginst, ntr - b0);
+  uint32_t tot = 0;
+  for (uint32_t bi = 0; bi < nb; ++bi) tot += n.spk_cnt[(size_t)(b0 + bi) * n.NS + i];
+  return tot ? 1u + (tot + 7u) / 8u : 0u;
+}
+
+// Block-local exclusive scan of record sizes (kScanItems per block); block
+// totals into pk_bsum.
+template <typename real>
+__global__ __launch_bounds__(1024) void k_pack_scan_local(DevNet<real> n, uint32_t ginst, uint32_t N) {
+  __shared__ uint32_t wsum[17];
+  const uint32_t ntr = n.ctl[CTL_NTRIALS];
+  const uint32_t e0 = blockIdx.x * kScanItems + threadIdx.x * 4;
+  uint32_t sz[4], tsum = 0;
+#pragma unroll
+  for (uint32_t u = 0; u < 4; ++u) {
+    sz[u] = e0 + u < N ? pk_units(n, e0 + u, ginst, ntr) : 0u;
+    tsum += sz[u];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(tsum, wsum, &tot);
+#pragma unroll
+  for (uint32_t u = 0; u < 4; ++u) {
+    if (e0 + u < N) n.pk_off[e0 + u] = sz[u] ? run : kNoRecord;
+    run += sz[u];
+  }
+  if (threadIdx.x == 0) n.pk_bsum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block totals (one block); pk_bsum[nblk] = table size.
+template <typename real>
+__global__ __launch_bounds__(1024) void k_pack_scan_blocks(DevNet<real> n, uint32_t nblk) {
+  __shared__ uint32_t wsum[17];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nblk; base += blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t x = i < nblk ? n.pk_bsum[i] : 0u;
+    uint32_t tot;
+    const uint32_t pre = block_exclusive_scan(x, wsum, &tot);
+    __syncthreads();
+    if (i < nblk) n.pk_bsum[i] = carry + pre;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) n.pk_bsum[nblk] = carry;
+}
+
+// Final offsets, headers (counts of the chunk's trials) and spike times.
+template <typename real>
+__global__ __launch_bounds__(256) void k_pack_fill(DevNet<real> n, uint32_t ginst, uint32_t N) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const uint32_t local = n.pk_off[e];
+  if (local == kNoRecord) return;
+  const uint32_t off = local + n.pk_bsum[e / kScanItems];
+  n.pk_off[e] = off;
+  const uint32_t ntr = n.ctl[CTL_NTRIALS];
+  const uint32_t c = e / n.NS, i = e - c * n.NS;
+  const uint32_t b0 = c * ginst, nb = min(ginst, ntr - b0);
+  uint32_t h[4] = {0, 0, 0, 0};
+  uint16_t *dst = n.pk + (size_t)off * 8 + 8;
+  for (uint32_t bi = 0; bi < nb; ++bi) {
+    const uint32_t cnt = n.spk_cnt[(size_t)(b0 + bi) * n.NS + i];
+    h[bi >> 1] |= cnt << ((bi & 1u) * 16u);
+    const uint16_t *src = n.spk_t + (size_t)(b0 + bi) * n.spk_stride + (size_t)i * n.Lc;
+    for (uint32_t k = 0; k < cnt; ++k) dst[k] = src[k];
+    dst += cnt;
+  }
+  reinterpret_cast<uint4 *>(n.pk)[off] = make_uint4(h[0], h[1], h[2], h[3]);
+}
+
 // Event-driven synapse gradient, target-major.  Block (j, c) handles the
 // incoming synapses of target j for the trials of chunk c (at most 8); the
 // target's archive rows phi[b][j][.] of those trials are staged in LDS.  Each
-// lane walks, for its synapse and each trial, the presynaptic spike-time list
-// (8 entries per 16-byte load; the counts and first loads of all trials are
-// issued together); each arrival a = s + D <= T adds phi_j^a (Kahan).  With
-// one chunk the sum goes straight into the accumulator pair (gs, gc);
-// otherwise into partial[c][q] for a fixed-order reduction.
+// lane takes a synapse, reads its source's record of the spike table (the
+// header and the first blocks of times issued together) and, for every
+// arrival a = s + D <= T_b of every trial, adds phi_j^a (Kahan).  With one
+// chunk the sum goes straight into the accumulator pair (gs, gc); otherwise
+// into partial[c][q] for a fixed-order reduction.
+constexpr uint32_t kPre = 5;  // blocks of 8 spike times loaded with the header
+
 template <typename real>
-__device__ inline bool add_arrivals(uint4 v, uint32_t k0, uint32_t cnt, uint32_t D, uint32_t T, const real *ph,
-                                    real &s, real &c, unsigned long long &nev) {
+__device__ inline void add_block(uint4 v, uint32_t p0, uint32_t total, uint32_t D, const uint4 &h,
+                                 uint32_t &bi, uint32_t &bend, const uint32_t *sT, const real *phl, uint32_t Tp,
+                                 real &s, real &c, unsigned long long &nev) {
   const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+  const uint64_t hlo = ((uint64_t)h.y << 32) | h.x, hhi = ((uint64_t)h.w << 32) | h.z;
 #pragma unroll
   for (uint32_t e = 0; e < 8; ++e) {
-    if (k0 + e >= cnt) return true;
+    const uint32_t p = p0 + e;
+    if (p >= total) return;
+    while (p >= bend) {
+      ++bi;
+      bend += (uint32_t)(((bi < 4 ? hlo : hhi) >> ((bi & 3u) * 16u)) & 0xFFFFu);
+    }
     const uint32_t a = ((w4[e >> 1] >> ((e & 1u) * 16u)) & 0xFFFFu) + D;
-    if (a > T) return true;
-    kahan_add(s, c, ph[a]);
-    ++nev;
+    if (a <= sT[bi]) {
+      kahan_add(s, c, phl[bi * Tp + a]);
+      ++nev;
+    }
   }
-  return false;
 }
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst, uint32_t nchunk, real *partial) {
   constexpr uint32_t GB = 8;
   extern __shared__ __align__(16) unsigned char syn_smem[];
+  __shared__ uint32_t sT[GB];
   real *phl = reinterpret_cast<real *>(syn_smem);   // [ginst][Tp]
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
   const uint32_t c = blockIdx.x % nchunk, j = blockIdx.x / nchunk;
   const uint32_t b0 = c * ginst, nb = min(min(ginst, ntr - b0), GB);
   const uint32_t tid = threadIdx.x;
-  uint32_t Tt[GB];
-#pragma unroll
-  for (uint32_t bi = 0; bi < GB; ++bi) Tt[bi] = bi < nb ? n.T[b0 + bi] : 0u;
+  if (tid < GB) sT[tid] = tid < nb ? n.T[b0 + tid] : 0u;
   for (uint32_t bi = 0; bi < nb; ++bi) {
     const real *src = n.phi + ((size_t)(b0 + bi) * n.Jp + j) * n.Tp;
     real *dst = phl + bi * n.Tp;
-    const uint32_t T1 = Tt[bi] + 1;
+    const uint32_t T1 = n.T[b0 + bi] + 1;
     for (uint32_t t = tid; t < T1; t += 4 * blockDim.x) {
       real v[4];
 #pragma unroll
@@ -714,28 +863,29 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
   }
   __syncthreads();
   unsigned long long nev = 0;
+  const uint4 *pk4 = reinterpret_cast<const uint4 *>(n.pk);
+  const uint32_t *poff = n.pk_off + (size_t)c * n.NS;
   const uint32_t q1 = n.tm_ptr[j + 1];
   for (uint32_t q = n.tm_ptr[j] + tid; q < q1; q += blockDim.x) {
     const uint32_t pk = n.tm_syn[q];
     const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
-    uint32_t cnt[GB];
-    uint4 v0[GB];
-    const uint4 *st4[GB];
-#pragma unroll
-    for (uint32_t bi = 0; bi < GB; ++bi) {
-      st4[bi] = reinterpret_cast<const uint4 *>(n.spk_t + (size_t)(b0 + (bi < nb ? bi : 0)) * n.spk_stride +
-                                                (size_t)src * n.Lc);
-      cnt[bi] = bi < nb ? n.spk_cnt[(size_t)(b0 + bi) * n.NS + src] : 0u;
-      v0[bi] = bi < nb ? st4[bi][0] : make_uint4(0, 0, 0, 0);
-    }
+    const uint32_t o = poff[src];
     real s = 0, cc = 0;
+    if (o != kNoRecord) {
+      // the table has slack beyond its last record, so these loads stay in bounds
+      const uint4 *rec = pk4 + o;
+      uint4 pre[kPre + 1];
 #pragma unroll
-    for (uint32_t bi = 0; bi < GB; ++bi) {
-      if (bi >= nb) break;
-      const real *ph = phl + bi * n.Tp;
-      bool done = add_arrivals(v0[bi], 0, cnt[bi], D, Tt[bi], ph, s, cc, nev);
-      for (uint32_t k0 = 8; k0 < cnt[bi] && !done; k0 += 8)
-        done = add_arrivals(st4[bi][k0 >> 3], k0, cnt[bi], D, Tt[bi], ph, s, cc, nev);
+      for (uint32_t u = 0; u <= kPre; ++u) pre[u] = rec[u];
+      const uint4 h = pre[0];
+      const uint32_t total = (h.x & 0xFFFFu) + (h.x >> 16) + (h.y & 0xFFFFu) + (h.y >> 16) + (h.z & 0xFFFFu) +
+                             (h.z >> 16) + (h.w & 0xFFFFu) + (h.w >> 16);
+      uint32_t bi = 0, bend = h.x & 0xFFFFu;
+#pragma unroll
+      for (uint32_t u = 0; u < kPre; ++u)
+        if (u * 8 < total) add_block(pre[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev);
+      for (uint32_t u = kPre; u * 8 < total; ++u)
+        add_block(rec[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev);
     }
     if (nchunk == 1) {
       real gs = n.gs[q], gc = n.gc[q];
@@ -833,6 +983,25 @@ __global__ __launch_bounds__(256) void k_apply_out(DevNet<real> n, double n_tria
   }
 }
 
+// Bound on the input current of one step: every synapse delivers at most
+// one spike per step, so |I_j^t| <= sum of |w| over j's incoming synapses.
+// One wavefront per target (coalesced over its target-major row); the
+// maximum over targets, slightly enlarged to cover the rounding of the sum,
+// goes to *l1max (positive floats order like their bit patterns).
+template <typename real>
+__global__ __launch_bounds__(256) void k_input_bound(DevNet<real> n) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwv = (gridDim.x * blockDim.x) >> 6;
+  float mx = 0.f;
+  for (uint32_t j = w0; j < n.J; j += nwv) {
+    double acc = 0.0;
+    for (uint32_t q = n.tm_ptr[j] + lane; q < n.tm_ptr[j + 1]; q += 64) acc += fabs((double)n.tm_w[q]);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    mx = fmaxf(mx, (float)(acc * 1.001));
+  }
+  if (lane == 0 && mx > 0.f) atomicMax(n.l1max, __float_as_uint(mx));
+}
+
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 inline uint32_t grid_for(uint64_t work, uint32_t block, uint32_t cap = 8192) {
   const uint32_t g = cdiv(work ? work : 1, block);
@@ -865,32 +1034,53 @@ void Launch<real>::neuron_gather(const DevNet<real> &n, uint32_t off, bool force
 }
 
 template <typename real>
-size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R) {
+size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes) {
   const size_t block = TS < 1024 ? TS : 1024;
-  return (size_t)(R + 3) * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 + 3 * block * 4 + kOwner * 2 + TS + 64;
+  return (size_t)R * TS * ring_bytes + (size_t)2 * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 + 3 * block * 4 +
+         kOwner * 2 + TS + 64;
+}
+
+// The forward kernel of a precision and ring element.
+template <typename real, typename ring_t>
+struct FwdKernels {
+  static const void *get(bool forced) {
+    return forced ? reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, true>)
+                  : reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, false>);
+  }
+  static void launch(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t grid, uint32_t block, size_t smem,
+                     hipStream_t s) {
+    if (forced) k_forward_tiled<real, ring_t, true><<<grid, block, smem, s>>>(n, nsteps);
+    else k_forward_tiled<real, ring_t, false><<<grid, block, smem, s>>>(n, nsteps);
+  }
+};
+
+template <typename real>
+const void *fwd_kernel(uint32_t ring_bytes, bool forced) {
+  if constexpr (sizeof(real) == 8) return FwdKernels<double, double>::get(forced);
+  else return ring_bytes == 8 ? FwdKernels<float, int64_t>::get(forced) : FwdKernels<float, int32_t>::get(forced);
 }
 
 template <typename real>
-hipError_t Launch<real>::allow_smem(size_t smem) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forward_tiled<real, false>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+hipError_t Launch<real>::allow_smem(size_t smem, uint32_t ring_bytes) {
+  hipError_t e = hipFuncSetAttribute(fwd_kernel<real>(ring_bytes, false), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)smem);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forward_tiled<real, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    e = hipFuncSetAttribute(fwd_kernel<real>(ring_bytes, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   return e;
 }
 
 template <typename real>
-hipError_t Launch<real>::resident(uint32_t block, size_t smem, int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_forward_tiled<real, false>, (int)block, smem);
+hipError_t Launch<real>::resident(uint32_t block, size_t smem, uint32_t ring_bytes, int *per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fwd_kernel<real>(ring_bytes, false), (int)block, smem);
 }
 
 template <typename real>
 void Launch<real>::forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t block, size_t smem,
                                  hipStream_t s) {
   const uint32_t grid = n.Bcap * n.KT;
-  if (forced) k_forward_tiled<real, true><<<grid, block, smem, s>>>(n, nsteps);
-  else k_forward_tiled<real, false><<<grid, block, smem, s>>>(n, nsteps);
+  if constexpr (sizeof(real) == 8) FwdKernels<double, double>::launch(n, nsteps, forced, grid, block, smem, s);
+  else if (n.ring_bytes == 8) FwdKernels<float, int64_t>::launch(n, nsteps, forced, grid, block, smem, s);
+  else FwdKernels<float, int32_t>::launch(n, nsteps, forced, grid, block, smem, s);
 }
 
 template <typename real>
@@ -909,6 +1099,10 @@ void Launch<real>::adjoint(const DevNet<real> &n, hipStream_t s) {
 template <typename real>
 void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *partial, hipStream_t s) {
   const uint32_t nchunk = (n_trials + sh.ginst - 1) / sh.ginst;
+  const uint32_t N = nchunk * n.NS, nblk = (N + kScanItems - 1) / kScanItems;
+  k_pack_scan_local<real><<<nblk, 1024, 0, s>>>(n, sh.ginst, N);
+  k_pack_scan_blocks<real><<<1, 1024, 0, s>>>(n, nblk);
+  k_pack_fill<real><<<cdiv(N, 256), 256, 0, s>>>(n, sh.ginst, N);
   const size_t smem = (size_t)sh.ginst * n.Tp * sizeof(real);
   k_synapse<real><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial);
   if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
@@ -924,6 +1118,12 @@ void Launch<real>::apply(const DevNet<real> &n, uint64_t S, double n_trials, int
                          double eta_t, double b1, double b2, double eps, hipStream_t s) {
   if (S > 0) k_apply_syn<real><<<grid_for(S, 256, 16384), 256, 0, s>>>(n, S, n_trials, opt, eta, eta_t, b1, b2, eps);
   k_apply_out<real><<<grid_for((uint64_t)n.K * n.Jp, 256, 2048), 256, 0, s>>>(n, n_trials, opt, eta, eta_t, b1, b2, eps);
+}
+
+template <typename real>
+void Launch<real>::input_bound(const DevNet<real> &n, hipStream_t s) {
+  (void)hipMemsetAsync(n.l1max, 0, sizeof(uint32_t), s);
+  k_input_bound<real><<<grid_for((uint64_t)n.J * 64, 256, 4096), 256, 0, s>>>(n);
 }
 
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s) { k_advance<<<1, 64, 0, s>>>(ctl, by); }

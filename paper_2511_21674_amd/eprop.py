@@ -297,7 +297,7 @@ class Network:
 
     def layout(self) -> dict:
         v = [int(x) for x in self.read(EPROP_STATE_LAYOUT)]
-        return dict(zip(("tile_neurons", "tiles", "lanes_per_source", "tile_threads", "synapse_threads",
+        return dict(zip(("tile_neurons", "tiles", "ring_bytes", "tile_threads", "synapse_threads",
                          "synapse_trials", "steps_per_launch", "gather"), v))
 
     def weights(self) -> dict:
