@@ -183,7 +183,6 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
     ok &= dalloc(n, &p32, (size_t)n->NS * (d.KT + 1)); d.tseg = p32;
   }
   ok &= dalloc(n, &d.nspk, B * T1);
-  ok &= dalloc(n, &d.bar, B * 2);
   ok &= dalloc(n, &d.sm, n->S);
   ok &= dalloc(n, &p32, n->J + 1); d.tm_ptr = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_syn = p32;
@@ -221,8 +220,8 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.in_bits, B * n->Tcap * n->Iw);
   ok &= dalloc(n, &d.spk_cnt, B * n->NS);
   ok &= dalloc(n, &d.spk_t, B * d.spk_stride);
-  ok &= dalloc(n, &d.rec_cnt, B * T1);
-  ok &= dalloc(n, &d.rec_list, B * 2 * n->Jp);
+  ok &= dalloc(n, &d.pub_list, B * 2 * n->Jp);
+  ok &= dalloc(n, &d.pub_cnt, B * 2 * (size_t)d.KT);
   ok &= dalloc(n, &d.in_step_ptr, B * T1);
   ok &= dalloc(n, &d.ysum, B * T2 * n->K);
   ok &= dalloc(n, &d.y, B * T2 * n->K);
@@ -514,7 +513,7 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
     if (prop.sharedMemPerBlockOptin > lds) lds = prop.sharedMemPerBlockOptin;
     if (prop.maxSharedMemoryPerMultiProcessor > 0 && lds > prop.maxSharedMemoryPerMultiProcessor)
       lds = prop.maxSharedMemoryPerMultiProcessor;
-    const size_t fixed = 1024;  // static LDS of the kernel and slack
+    const size_t fixed = 1024 + 4 * 1025;  // static LDS of the kernel (tile count prefix) and slack
     auto smem_of = [&](uint32_t ts, uint32_t rb) {
       return n->fp64 ? Launch<double>::tile_smem(ts, n->R, rb) : Launch<float>::tile_smem(ts, n->R, rb);
     };
@@ -543,6 +542,11 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
     TS = std::max<uint32_t>(std::min(ts_lds, ts_par), 64);
     KT = (n->Jp + TS - 1) / TS;
     tile_block = std::min<uint32_t>(1024, TS);
+    if (KT > tile_block) {  // every tile's count is read by one thread of each tile
+      g_create_error = "too many tiles per trial for the tiled forward kernel";
+      delete n;
+      return EPROP_ERR_UNSUPPORTED;
+    }
     n->tile_smem = smem_of(TS, ring_bytes);
   }
   n->shapes.tile_block = tile_block;
@@ -814,8 +818,10 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   MS(d.ring, (size_t)ntr * n->R * n->Jp * d.ring_bytes);
   MS(d.in_bits, (size_t)ntr * n->Tcap * n->Iw * 8);
   MS(d.spk_cnt, (size_t)ntr * n->NS * 4);
-  MS(d.rec_cnt, (size_t)ntr * T1 * 4);
-  MS(d.bar, (size_t)ntr * 2 * 4);
+  if (!n->gather) {  // tags of an earlier batch must not match
+    MS(d.pub_list, (size_t)ntr * 2 * n->Jp * 8);
+    MS(d.pub_cnt, (size_t)ntr * 2 * d.KT * 8);
+  }
   MS(d.cnt, eprop::CNT_WORDS * 8);
   MS(d.evcnt, 64 * 8);
   if (forced) MS(d.forced_bits, (size_t)ntr * T1 * n->Jw * 8);
@@ -874,9 +880,9 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     if (e != hipSuccess) goto device_error;
     n->last_ntr = ntr;
     n->last_T.assign(b->n_steps, b->n_steps + ntr);
-    if (flags & eprop::ERR_BARRIER) {
+    if (flags & eprop::ERR_SYNC) {
       n->failed = true;
-      set_fail(n, "tile barrier timed out: the workgroups of a trial were not resident together");
+      set_fail(n, "spike exchange between the tiles of a trial timed out");
       return EPROP_ERR_DEVICE;
     }
     if (flags & eprop::ERR_INPUT_BOUND) {

@@ -21,8 +21,9 @@
 //   arrival archive      phi[b][j][t]           (neuron-major, stride Tp)
 //   spike bitsets        rec_bits[b][t][Jw], in_bits[b][s][Iw], forced_bits[b][t][Jw]
 //   spike-time lists     spk_cnt[b][NS], spk_t[b][src*Lc + k] (uint16, ascending)
-//   per-step spikes      rec_cnt[b][t], rec_list[b][t & 1][Jp], nspk[b][t]
-//   tile barriers        bar[b][2] (arrival count, generation)
+//   per-step spikes      pub_list[b][t & 1][Jp] (tile k's spiking neurons of step t at
+//                        k*TS.., each word t << 32 | j), pub_cnt[b][t & 1][KT]
+//                        (t << 32 | count of tile k), nspk[b][t]
 //   readout (FP64)       ysum/pi[b][t][K], y[b][t][K], err[b][t][K], ebar[b][t][K]
 #pragma once
 #include <hip/hip_runtime.h>
@@ -33,7 +34,7 @@ namespace eprop {
 // ctl words; the 64-bit device pointer to the batch's input-source array is
 // stored at word CTL_WORDS (byte offset 64)
 enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
-enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_BARRIER = 8u,
+enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_SYNC = 8u,
                   ERR_INPUT_BOUND = 16u };
 enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_WORDS = 8 };
 constexpr uint32_t kScanItems = 4096;        // entries per block of the spike-table scan
@@ -104,7 +105,8 @@ struct DevNet {
   uint32_t *pk_bsum;            // [scan blocks + 1]
   uint16_t *pk;                 // [pk_cap * 8]
   uint64_t pk_cap;
-  uint32_t *rec_cnt, *rec_list, *nspk, *bar;
+  uint64_t *pub_list, *pub_cnt;
+  uint32_t *nspk;
   uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
   double *ysum, *y, *err, *ebar;  // [Bcap][Tcap+2][K]
   double *loss_out;             // [Bcap]

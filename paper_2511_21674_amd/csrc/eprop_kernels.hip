@@ -182,40 +182,42 @@ __device__ inline uint64_t publish_bits(const DevNet<real> &n, uint32_t b, uint3
   return word;
 }
 
-// Barrier of the KT workgroups that simulate one trial.  Thread 0 releases
-// the workgroup's global writes (one agent-scope release fence), arrives,
-// and waits on relaxed coherent loads of the generation (an acquire inside
-// the wait loop would invalidate the L2 on every poll), then acquires once.
-// The wait is bounded: on timeout it flags ERR_BARRIER and returns false, so
-// every wavefront always reaches the end of the kernel.
-__device__ inline bool group_barrier(uint32_t *bar, uint32_t members, uint32_t *err) {
-  __shared__ uint32_t ok_s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t ok = 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == members) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      uint32_t spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1u << 25)) {  // far beyond any legitimate wait (about a second)
-          atomicOr(err, ERR_BARRIER);
-          ok = 0;
-          break;
-        }
-      }
+// Exchange of the per-step spike lists between the tiles of a trial.  The
+// word of a step-t entry carries t in its upper half, so a reader that sees
+// the tag of step t sees that step's value: only the coherence of single
+// locations is needed (system-scope atomic stores write through and
+// system-scope atomic loads bypass the non-coherent caches), no fence and no
+// barrier.  Double buffering by the parity of t is safe: a tile publishes
+// step t+2 into the buffer of step t only after it has read every tile's
+// step-t+1 list, and every tile publishes step t+1 only after it has read
+// all step-t lists.  Waits are bounded; after the first timeout in the
+// launch every wait returns at once and the batch reports an error.
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr uint32_t kMaxTiles = 1024;  // tiles per trial (at most one per thread of a tile workgroup)
+
+__device__ inline uint64_t load_sys(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline void store_sys(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Low half of the step-t word at p, or 0 on timeout (flag ERR_SYNC).
+__device__ inline uint32_t wait_tag(const uint64_t *p, uint32_t t, uint32_t *err) {
+  uint64_t v = load_sys(p);
+  if ((uint32_t)(v >> 32) == t) return (uint32_t)v;
+  for (uint32_t spins = 0;; ++spins) {
+    // first of all (and every 256 polls) give up if a wait of this batch already failed
+    if ((spins & 255u) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_SYNC))
+      return 0u;
+    if (spins > kSpinLimit) {
+      atomicOr(err, ERR_SYNC);
+      return 0u;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    ok_s = ok;
+    __builtin_amdgcn_s_sleep(1);
+    v = load_sys(p);
+    if ((uint32_t)(v >> 32) == t) return (uint32_t)v;
   }
-  __syncthreads();
-  return ok_s != 0;
 }
 
 // Exclusive scan of one value per thread over the block (blockDim <= 1024);
@@ -305,16 +307,26 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
                                     uint32_t *dlo, uint32_t *dlen, uint32_t *dpre, uint16_t *owner,
                                     uint32_t *wsum) {
+  __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike counts of step t
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
-  // written within this kernel (possibly by other workgroups): coherent loads
-  const uint32_t n_rec =
-      t >= 1 ? __hip_atomic_load(&n.rec_cnt[(size_t)b * (n.Tcap + 1) + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-             : 0u;
+  uint32_t n_rec = 0;
+  const uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
+  if (t >= 1) {  // every tile's count of step t (published by the tiles, possibly still on the way)
+    const uint32_t kk = threadIdx.x;
+    uint32_t c = 0;
+    if (kk < n.KT) {
+      c = wait_tag(n.pub_cnt + ((size_t)b * 2 + (t & 1u)) * n.KT + kk, t, &n.ctl[CTL_ERR]);
+      c = min(c, min(n.TS, n.Jp - kk * n.TS));
+    }
+    const uint32_t pre = block_exclusive_scan(c, wsum, &n_rec);
+    if (kk < n.KT) tpre[kk] = pre;
+    if (kk == 0) tpre[n.KT] = n_rec;
+    __syncthreads();
+  }
   const uint32_t total = n_in + n_rec;
   const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
-  uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
   const uint32_t slot_t = t % n.R;
   const uint32_t sub = threadIdx.x & (kPiece - 1u), grp = threadIdx.x / kPiece, ngrp = blockDim.x / kPiece;
   for (uint32_t base = 0; base < total; base += blockDim.x) {
@@ -322,9 +334,19 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
     uint32_t lo = 0, len = 0;
     if (threadIdx.x < m) {
       const uint32_t item = base + threadIdx.x;
-      const uint32_t src = item < n_in ? in_src[in_lo + item]
-                                       : n.I + __hip_atomic_load(&rl[item - n_in], __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t src;
+      if (item < n_in) {
+        src = in_src[in_lo + item];
+      } else {
+        const uint32_t r = item - n_in;
+        uint32_t lk = 0, hk = n.KT;  // tpre[lk] <= r < tpre[hk]
+        while (hk - lk > 1) {
+          const uint32_t mid = (lk + hk) >> 1;
+          if (tpre[mid] <= r) lk = mid; else hk = mid;
+        }
+        const uint32_t j = wait_tag(pl + (size_t)lk * n.TS + (r - tpre[lk]), t, &n.ctl[CTL_ERR]);
+        src = n.I + min(j, n.J - 1u);
+      }
       const uint32_t *ts = n.tseg + (size_t)src * (n.KT + 1) + k;
       lo = ts[0];
       len = ts[1] - lo;
@@ -375,9 +397,10 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 // Persistent forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps.  Workgroup
 // (b, k) owns neurons [k*TS, k*TS + TS) of trial b; their delay ring and
 // state stay in LDS for the whole launch.  Per step: neuron update of the
-// tile, spike publication (bitset, spike times, compacted list with one
-// global atomic per workgroup), one barrier among the trial's KT
-// workgroups, delivery of the step's spikes into the tile's ring.
+// tile, spike publication (bitset, spike times, the tile's tagged spike list
+// and count), then delivery of all tiles' spikes of the step into the
+// tile's ring, reading each tile's list as soon as its tag shows up.  The
+// KT workgroups of a trial must be resident together (checked on the host).
 template <typename real, typename ring_t, bool FORCED>
 __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -401,7 +424,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   uint32_t *dpre = dlen + blockDim.x;
   uint16_t *owner = reinterpret_cast<uint16_t *>(dpre + blockDim.x);
   uint8_t *sst = reinterpret_cast<uint8_t *>(owner + kOwner);
-  __shared__ uint32_t gbase;
+  __shared__ uint32_t gtot;
   __shared__ uint32_t wsum[17];
   RingScale sc{1.f, 1.f};
   if constexpr (sizeof(real) == 4) sc = ring_scale<ring_t>(n.l1max, &n.ctl[CTL_ERR]);
@@ -418,7 +441,6 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     deliver_tile(n, b, k, j0, 0, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
-  bool ok = true;
   const uint32_t t_end = min(t0 + nsteps, Tb);
   for (uint32_t t = t0 + 1; t <= t_end; ++t) {
     const uint32_t slot = t % n.R;
@@ -451,23 +473,20 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
         off += (uint32_t)__shfl((int)inc, 63);
       }
       tot = off;
-      if (threadIdx.x == 0) gbase = tot ? atomicAdd(&n.rec_cnt[(size_t)b * (n.Tcap + 1) + t], tot) : 0u;
+      if (threadIdx.x == 0) gtot = tot;
     }
     __syncthreads();
-    {
-      uint32_t *rl = n.rec_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
+    {  // publish the tile's spikes of step t: the entries, then the count
+      uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp + j0;
+      const uint64_t tag = (uint64_t)t << 32;
       for (uint32_t w = threadIdx.x >> 6; w < nw; w += blockDim.x >> 6) {
         const uint64_t word = words[w];
         const uint32_t lane = lane_id();
         if ((word >> lane) & 1ull)
-          rl[gbase + woff[w] + (uint32_t)__popcll(word & ((1ull << lane) - 1ull))] = j0 + w * 64 + lane;
+          store_sys(&pl[woff[w] + (uint32_t)__popcll(word & ((1ull << lane) - 1ull))], tag | (j0 + w * 64 + lane));
       }
-    }
-    if (KT > 1) {
-      if (ok) ok = group_barrier(n.bar + 2 * b, KT, &n.ctl[CTL_ERR]);
-      else __syncthreads();
-    } else {
       __syncthreads();
+      if (threadIdx.x == 0) store_sys(&n.pub_cnt[((size_t)b * 2 + (t & 1u)) * KT + k], tag | gtot);
     }
     if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
