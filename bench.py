@@ -29,31 +29,39 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(phase, rs, counts, net, batch_T, n_trials, kt, launches):
-    """Algorithmic HBM bytes of one phase (the per-unit figures are derived
-    in the design doc).  counts: dict of events, rec_spikes, in_spikes."""
-    J, Jp = net.n_rec, (net.n_rec + 63) // 64 * 64
+# Algorithmic bytes per unit of work (FP32): what the method has to move
+# at the least, whatever the implementation.
+B_EVENT = 12            # synaptic event: target index 4 + weight 4 + ring add 4
+B_UPDATE_LIF = 24       # e-prop update fused with its event, LIF target (trace, g, c read and written)
+B_UPDATE_ALIF = 32      # ... ALIF target (adds the adaptation trace)
+B_OUT_EVENT = 20        # recurrent spike to one readout: weight 4 + (g, c) read and written
+B_NEURON_LIF = 34       # neuron-step: v r/w 8, refractory 2, ring slot read+clear 8, history write 8
+B_NEURON_ALIF = 42      #   and history read 8 (ALIF: + a r/w 8)
+B_SOURCE = 16           # spiking source: last spike time and presynaptic trace read and written
+B_FWD_NEURON_LIF = 22   # forward kernel's share of a neuron-step: v 8, refractory 2, ring 8, psi 4
+B_FWD_NEURON_ALIF = 30  #   (ALIF: + a r/w 8)
+
+
+def path_bytes(c, net, n_trials, adam):
+    """Algorithmic bytes of one batch step of the whole path (forward,
+    readout, gradients, optimiser).  c: per-step counts."""
+    n_alif = int(np.count_nonzero(net.is_alif)) if net.is_alif is not None else 0
+    frac_alif = n_alif / net.n_rec
     S = net.in_rec.nnz + net.rec_rec.nnz
-    neuron_steps = n_trials * batch_T * Jp
-    spikes = counts["rec_spikes"] + counts["in_spikes"]
-    if phase == "forward":
-        # per event: packed target+delay (4 B) and weight (rs); per neuron-step:
-        # psi write (rs) and spike bit (1/8 B); per spike: tile offsets (8 B per
-        # tile), list entry written and read per tile (4 B + 4 B per tile), spike
-        # time (2 B); per launch and neuron: state and ring saved and restored.
-        R = 6
-        return (counts["events"] * (4 + rs) + neuron_steps * (rs + 0.125)
-                + spikes * (8 * kt + 4 + 4 * kt + 2)
-                + launches * n_trials * Jp * 2 * ((R + 2) * rs + 1))
-    if phase == "synapse":
-        # per synapse: packed source+delay (4 B), Kahan pair read and written
-        # (4 rs); per trial, neuron and step: archive row read once (rs); per
-        # trial and source: spike count (4 B) and spike times (2 B each).
-        return S * (4 + 4 * rs) + neuron_steps * rs + n_trials * (net.n_in + J) * 4 + spikes * 2
-    if phase == "adjoint":
-        # per trial, neuron and step: psi read and archive written (2 rs)
-        return neuron_steps * 2 * rs
-    return None
+    per_iter = S * (8 * n_trials + 8 + (16 if adam else 0))
+    return (c["events"] * (B_EVENT + B_UPDATE_LIF + frac_alif * (B_UPDATE_ALIF - B_UPDATE_LIF))
+            + c["neuron_steps"] * (B_NEURON_LIF + frac_alif * (B_NEURON_ALIF - B_NEURON_LIF))
+            + c["rec_spikes"] * net.n_out * B_OUT_EVENT
+            + (c["rec_spikes"] + c["in_spikes"]) * B_SOURCE + per_iter)
+
+
+def forward_bytes(c, net):
+    """Algorithmic bytes of the forward kernel (delivery and neuron updates)
+    for one batch step."""
+    n_alif = int(np.count_nonzero(net.is_alif)) if net.is_alif is not None else 0
+    frac_alif = n_alif / net.n_rec
+    return (c["events"] * B_EVENT
+            + c["neuron_steps"] * (B_FWD_NEURON_LIF + frac_alif * (B_FWD_NEURON_ALIF - B_FWD_NEURON_LIF)))
 
 
 def measured_traffic(workload, kernel):
@@ -161,7 +169,7 @@ def main():
     ap.add_argument("--workload", default="c4_sparse")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -201,9 +209,11 @@ def main():
                         stream=E.C.c_void_p(stream.cuda_stream))
         staged = stage_batches(wl, args.warmup + args.steps, 0)
         torch.cuda.synchronize()
+        warm_losses = []
         for i in range(args.warmup):
-            run_staged(net, staged[i])
+            _, wloss = run_staged(net, staged[i])
             net.apply()
+            warm_losses.append(float(wloss.mean()))
         torch.cuda.synchronize()
         tot = {"events": 0, "updates": 0, "rec_spikes": 0, "in_spikes": 0}
         phases = {k: 0.0 for k in E.PHASES}
@@ -225,32 +235,33 @@ def main():
     n_tr = wl.batch_size
     rate_hz = tot["rec_spikes"] / (steps * n_tr * net_w.n_rec * T * net_w.params.dt / 1000.0)
     lay = net.layout()
-    kt = lay["tiles"]
     launches = -(-T // lay["steps_per_launch"])
-    cand = {}
-    for ph in ("forward", "synapse", "adjoint"):
-        ab = algorithmic_bytes(ph, 4, {k: v / steps for k, v in tot.items()}, net_w, T, n_tr, kt, launches)
-        ms = phases[ph] / steps
-        cand[ph] = (ms, ab)
-    dom = max(cand, key=lambda k: cand[k][0])
-    ms, ab = cand[dom]
-    n_launch = launches if dom == "forward" else 1
-    achieved = ab / (ms / 1000.0) / 1e9
-    roof = {"kernel": {"forward": "k_forward_tiled", "synapse": "k_synapse", "adjoint": "k_adjoint"}[dom],
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_ms": round(ms / n_launch, 4), "algorithmic_bytes_per_launch": int(ab / n_launch)}
+    per_step = {k: v / steps for k, v in tot.items()}
+    per_step["neuron_steps"] = float(np.mean([int(staged[args.warmup + i][0].n_steps.sum()) for i in range(steps)])
+                                     * net_w.n_rec)
+    fwd_ms = phases["forward"] / steps
+    fwd_b = forward_bytes(per_step, net_w)
+    achieved = fwd_b / launches / (fwd_ms / launches / 1000.0) / 1e9
+    roof = {"kernel": "k_forward_tiled", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(fwd_ms / launches, 4), "algorithmic_bytes_per_launch": int(fwd_b / launches)}
+    pb = path_bytes(per_step, net_w, n_tr, net_w.params.optimizer == 1)
+    path_roof = {"bytes_per_step": int(pb), "achieved": round(pb / (elapsed / steps) / 1e9, 1), "unit": "GB/s",
+                 "frac": round(pb / (elapsed / steps) / 1e9 / HBM_PEAK_GBS, 4)}
     tr = measured_traffic(wl.name, roof["kernel"])
     if tr is not None:
         roof["traffic"] = round(tr / 1e9, 3)
         roof["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     fp64 = None
-    if not args.no_fp64:
+    if not args.no_fp64 and args.warmup >= 1:
+        # the FP64 plain path (same kernels in double, one trial at a time,
+        # deterministic gather delivery) on the first batch from the same
+        # initial weights as the FP32 run's first (warm-up) batch
         with torch.cuda.stream(stream):
             net64 = E.Network(net_w, "fp64", max_trials=1, max_steps=T, delivery="gather",
                               stream=E.C.c_void_p(stream.cuda_stream))
-            b0 = staged[args.warmup][0]
+            b0 = staged[0][0]
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             ev64, loss64 = 0, []
@@ -262,10 +273,11 @@ def main():
             torch.cuda.synchronize()
             el64 = time.perf_counter() - t1
             net64.close()
-        gpu32_ev_s = tot["events"] / elapsed
+        l64, l32 = float(np.mean(loss64)), warm_losses[0]
         fp64 = {"value": ev64 / el64, "unit": "synaptic events/s", "seconds_per_batch": el64,
-                "speedup_fp32_batched": gpu32_ev_s / (ev64 / el64),
-                "loss_fp64_first_batch": float(np.mean(loss64)), "loss_fp32_first_timed_batch": losses[0]}
+                "speedup_fp32_batched": el64 / (elapsed / steps),
+                "loss_fp64": l64, "loss_fp32": l32, "loss_rel_diff": abs(l32 - l64) / abs(l64),
+                "note": "same batch and initial weights; speedup = FP64 plain seconds per batch / FP32 batched"}
     net.close()
 
     cpu = None
@@ -283,7 +295,7 @@ def main():
            "recurrent_rate_hz": rate_hz,
            "phase_ms_per_step": {k: round(v / steps, 3) for k, v in phases.items()},
            "mean_loss": losses,
-           "layout": lay, "roofline": roof, "cpu_baseline": cpu, "fp64_plain": fp64}
+           "layout": lay, "roofline": roof, "path_roofline": path_roof, "cpu_baseline": cpu, "fp64_plain": fp64}
     print(json.dumps(out), flush=True)
 
 
