@@ -95,6 +95,17 @@ typedef enum { EPROP_DELIVERY_AUTO = 0, EPROP_DELIVERY_SCATTER = 1, EPROP_DELIVE
 
 /* eprop_config.flags */
 #define EPROP_FLAG_NO_GRAPH (1u << 0)   /* launch the step loop kernel by kernel, no captured HIP graph */
+#define EPROP_DETERMINISTIC (1u << 1)   /* bit-reproducible results: FP64 then delivers by gather (FP32
+                                           delivery is deterministic in either mode) */
+#define EPROP_SHARED_WEIGHTS (1u << 2)  /* all trials of a batch use the same weights (always the case;
+                                           accepted for clarity) */
+
+/* Optional device allocator, e.g. a framework's caching allocator: every
+ * device buffer of the handle is taken from dev_alloc (bytes, ctx) and
+ * returned through dev_free (ptr, ctx) by eprop_destroy_network.  Buffers
+ * are at least 256-byte aligned.  NULL dev_alloc = hipMalloc/hipFree. */
+typedef void *(*eprop_dev_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*eprop_dev_free_fn)(void *ptr, void *ctx);
 
 typedef struct {
   uint32_t abi_version;          /* EPROP_ABI_VERSION */
@@ -111,7 +122,16 @@ typedef struct {
   uint32_t max_trials;           /* largest number of trials per eprop_simulate_batch call */
   uint32_t max_steps;            /* largest trial length T, 1..65535 */
   int32_t delivery;              /* eprop_delivery */
-  uint32_t flags;                /* EPROP_FLAG_* */
+  uint32_t flags;                /* EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS */
+  uint32_t d_out;                /* delay of recurrent spikes to the readout (Supplementary, "Delay
+                                    from the recurrent to the output layer"): 0 in this version */
+  uint32_t d_ls;                 /* learning-signal delay: 0 in this version */
+  uint32_t history_steps;        /* per-neuron history capacity in steps; 0 = whole trial.  The
+                                    history always covers the whole trial here, so other values
+                                    must be >= max_steps */
+  eprop_dev_alloc_fn dev_alloc;  /* NULL or the allocator above */
+  eprop_dev_free_fn dev_free;    /* required with dev_alloc */
+  void *alloc_ctx;
 } eprop_config;
 
 /* A projection in CSR-by-source form (host memory, copied by the call):
@@ -159,7 +179,10 @@ typedef enum { EPROP_MEM_HOST = 0, EPROP_MEM_DEVICE = 1 } eprop_memory;
 
 /* eprop_batch.flags */
 #define EPROP_BATCH_TRAIN (1u << 0)    /* accumulate e-prop gradients of these trials */
+#define EPROP_TRAIN EPROP_BATCH_TRAIN
 #define EPROP_BATCH_PROFILE (1u << 1)  /* time each phase with HIP events (phase_ms) */
+#define EPROP_RECORD_SPIKES (1u << 2)  /* keep the batch's spikes for eprop_read_state (always kept) */
+#define EPROP_RECORD_TRACES (1u << 3)  /* keep psi, y, E, L, v for eprop_read_state (always kept) */
 
 /* A batch of independent trials (samples) of uneven lengths, simulated
  * together from zero state with the current weights (Results, "Evidence
@@ -212,7 +235,9 @@ typedef struct {
   uint64_t n_syn_events;         /* input + recurrent deliveries arriving within their trial (TRAIN) */
   uint64_t n_out_events;         /* recurrent spikes x readouts */
   uint64_t n_eprop_updates;      /* arrival evaluations on plastic synapses (TRAIN only) */
-  double device_ms;              /* device time of the whole call (HIP events) */
+  uint64_t n_flush_updates;      /* trial-end evaluations: (synapse, trial) pairs with at least one
+                                    arrival (TRAIN only) */
+  double device_seconds;         /* device time of the whole call (HIP events) */
   double phase_ms[EPROP_N_PHASES];   /* with EPROP_BATCH_PROFILE */
 } eprop_batch_result;
 
@@ -250,11 +275,13 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18      /* uint64 [8]: neurons per tile, tiles per trial, bytes per
+  EPROP_STATE_LAYOUT = 18,     /* uint64 [8]: neurons per tile, tiles per trial, bytes per
                                   delay-ring entry (8: 64-bit fixed point in FP32 or double in
                                   FP64, 4: 32-bit fixed point in FP32), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
                                   forward launch, gather delivery (0/1) */
+  EPROP_STATE_L = 19           /* last batch, trial: double [T_b * J] learning signal
+                                  L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
 } eprop_state_id;
 
 /* Copies one state array to host memory dst (dst_bytes large).  With

@@ -68,15 +68,29 @@ namespace {
 
 void set_fail(eprop_network *n, const std::string &m) { n->err = m; }
 
+void dfree(eprop_network *n, void *p) {
+  if (!p) return;
+  if (n->cfg.dev_free) n->cfg.dev_free(p, n->cfg.alloc_ctx);
+  else (void)hipFree(p);
+}
+
 template <typename T>
 bool dalloc(eprop_network *n, T **p, size_t count) {
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-  if (hipMalloc(reinterpret_cast<void **>(p), bytes) != hipSuccess) {
-    *p = nullptr;
+  void *q = nullptr;
+  if (n->cfg.dev_alloc) {
+    q = n->cfg.dev_alloc(bytes, n->cfg.alloc_ctx);
+    if (q && (reinterpret_cast<uintptr_t>(q) & 255u) != 0) {  // the kernels assume 256-byte alignment
+      n->cfg.dev_free(q, n->cfg.alloc_ctx);
+      q = nullptr;
+    }
+  } else if (hipMalloc(&q, bytes) != hipSuccess) {
+    q = nullptr;
     (void)hipGetLastError();
-    return false;
   }
-  n->allocs.push_back(*p);
+  *p = static_cast<T *>(q);
+  if (!q) return false;
+  n->allocs.push_back(q);
   return true;
 }
 
@@ -87,7 +101,7 @@ bool dgrow(eprop_network *n, T **p, size_t *cap, size_t count) {
   if (*p) {
     auto it = std::find(n->allocs.begin(), n->allocs.end(), (void *)*p);
     if (it != n->allocs.end()) n->allocs.erase(it);
-    (void)hipFree(*p);
+    dfree(n, *p);
     *p = nullptr;
   }
   const size_t want = std::max<size_t>(count, 1024);
@@ -154,6 +168,19 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
   if (c->max_trials < 1) return bad("max_trials must be >= 1");
   if (c->max_steps < 1 || c->max_steps > 65535) return bad("max_steps must be in 1..65535");
   if (c->delivery < EPROP_DELIVERY_AUTO || c->delivery > EPROP_DELIVERY_GATHER) return bad("unknown delivery");
+  if (c->flags & ~(uint32_t)(EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS))
+    return bad("unknown config flag");
+  if ((c->flags & EPROP_DETERMINISTIC) && c->precision == EPROP_FP64 && c->delivery == EPROP_DELIVERY_SCATTER)
+    return bad("FP64 scatter delivery is not deterministic; use gather or AUTO");
+  if ((c->dev_alloc == nullptr) != (c->dev_free == nullptr)) return bad("dev_alloc and dev_free go together");
+  if (c->d_out != 0 || c->d_ls != 0) {
+    msg = "readout and learning-signal delays other than 0 are not supported";
+    return EPROP_ERR_UNSUPPORTED;
+  }
+  if (c->history_steps != 0 && c->history_steps < c->max_steps) {
+    msg = "the history covers whole trials: history_steps must be 0 or >= max_steps";
+    return EPROP_ERR_UNSUPPORTED;
+  }
   return EPROP_OK;
 }
 
@@ -359,7 +386,7 @@ void eprop_destroy_network(eprop_network *net) {
   for (auto &e : net->ev)
     if (e) (void)hipEventDestroy(e);
   if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
-  for (void *p : net->allocs) (void)hipFree(p);
+  for (void *p : net->allocs) dfree(net, p);
   delete net;
 }
 
@@ -908,9 +935,10 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
       res->n_syn_events = events;
       res->n_out_events = cnt[eprop::CNT_REC_SPIKES] * n->K;
       res->n_eprop_updates = train ? events : 0;
+      res->n_flush_updates = train ? cnt[eprop::CNT_FLUSH] : 0;
       float ms = 0;
       (void)hipEventElapsedTime(&ms, n->ev[0], n->ev[7]);
-      res->device_ms = ms;
+      res->device_seconds = ms * 1e-3;
       for (int p = 0; p < EPROP_N_PHASES; ++p) res->phase_ms[p] = 0;
       if (prof) {
         const int upto = train ? 6 : 3;
@@ -961,8 +989,8 @@ eprop_status apply(eprop_network *n, DevNet<real> &d) {
 template <typename real>
 eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t what, uint32_t trial,
                         void *dst, size_t dst_bytes, size_t *needed) {
-  const bool per_trial = what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V;
-  if (what < 0 || what > EPROP_STATE_LAYOUT) return EPROP_ERR_INVALID_ARGUMENT;
+  const bool per_trial = (what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V) || what == EPROP_STATE_L;
+  if (what < 0 || what > EPROP_STATE_L) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
     const uint64_t lay[8] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                              n->blk, n->gather ? 1u : 0u};
@@ -1080,6 +1108,23 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
       outd.resize((size_t)T * n->K);
       const double *src = (what == EPROP_STATE_Y ? d.y : d.err) + ((size_t)trial * (n->Tcap + 2) + 1) * n->K;
       e = hipMemcpy(outd.data(), src, bytes, hipMemcpyDeviceToHost);
+      break;
+    }
+    case EPROP_STATE_L: {  // sum_k B_jk E_k^t in FP64, ascending k
+      bytes = (size_t)T * n->J * 8;
+      if (!dst) break;
+      std::vector<double> err((size_t)T * n->K);
+      std::vector<real> fb;
+      e = hipMemcpy(err.data(), d.err + ((size_t)trial * (n->Tcap + 2) + 1) * n->K, err.size() * 8,
+                    hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = fetch(d.fb, KJ, fb);
+      outd.assign((size_t)T * n->J, 0.0);
+      for (uint32_t t = 0; t < T && e == hipSuccess; ++t)
+        for (uint32_t j = 0; j < n->J; ++j) {
+          double acc = 0.0;
+          for (uint32_t k = 0; k < n->K; ++k) acc += (double)fb[(size_t)j * n->K + k] * err[(size_t)t * n->K + k];
+          outd[(size_t)t * n->J + j] = acc;
+        }
       break;
     }
     case EPROP_STATE_V: {

@@ -36,7 +36,7 @@ namespace eprop {
 enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
 enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_SYNC = 8u,
                   ERR_INPUT_BOUND = 16u };
-enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_WORDS = 8 };
+enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_FLUSH = 2, CNT_WORDS = 8 };
 constexpr uint32_t kScanItems = 4096;        // entries per block of the spike-table scan
 constexpr uint32_t kNoRecord = 0xFFFFFFFFu;  // spike-table offset of a source without spikes
 

@@ -837,7 +837,8 @@ constexpr uint32_t kPre = 5;  // blocks of 8 spike times loaded with the header
 template <typename real>
 __device__ inline void add_block(uint4 v, uint32_t p0, uint32_t total, uint32_t D, const uint4 &h,
                                  uint32_t &bi, uint32_t &bend, const uint32_t *sT, const real *phl, uint32_t Tp,
-                                 real &s, real &c, unsigned long long &nev) {
+                                 real &s, real &c, unsigned long long &nev, uint32_t &lastb,
+                                 unsigned long long &nfl) {
   const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
   const uint64_t hlo = ((uint64_t)h.y << 32) | h.x, hhi = ((uint64_t)h.w << 32) | h.z;
 #pragma unroll
@@ -852,6 +853,10 @@ __device__ inline void add_block(uint4 v, uint32_t p0, uint32_t total, uint32_t 
     if (a <= sT[bi]) {
       kahan_add(s, c, phl[bi * Tp + a]);
       ++nev;
+      if (bi != lastb) {  // first arrival of this trial: the synapse has a trial-end evaluation
+        lastb = bi;
+        ++nfl;
+      }
     }
   }
 }
@@ -881,7 +886,7 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
     }
   }
   __syncthreads();
-  unsigned long long nev = 0;
+  unsigned long long nev = 0, nfl = 0;
   const uint4 *pk4 = reinterpret_cast<const uint4 *>(n.pk);
   const uint32_t *poff = n.pk_off + (size_t)c * n.NS;
   const uint32_t q1 = n.tm_ptr[j + 1];
@@ -899,12 +904,12 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
       const uint4 h = pre[0];
       const uint32_t total = (h.x & 0xFFFFu) + (h.x >> 16) + (h.y & 0xFFFFu) + (h.y >> 16) + (h.z & 0xFFFFu) +
                              (h.z >> 16) + (h.w & 0xFFFFu) + (h.w >> 16);
-      uint32_t bi = 0, bend = h.x & 0xFFFFu;
+      uint32_t bi = 0, bend = h.x & 0xFFFFu, lastb = 0xFFFFFFFFu;
 #pragma unroll
       for (uint32_t u = 0; u < kPre; ++u)
-        if (u * 8 < total) add_block(pre[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev);
+        if (u * 8 < total) add_block(pre[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev, lastb, nfl);
       for (uint32_t u = kPre; u * 8 < total; ++u)
-        add_block(rec[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev);
+        add_block(rec[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev, lastb, nfl);
     }
     if (nchunk == 1) {
       real gs = n.gs[q], gc = n.gc[q];
@@ -916,8 +921,12 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
       partial[(size_t)c * n.S + q] = s + cc;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) nev += __shfl_down(nev, o);
+  for (int o = 32; o > 0; o >>= 1) {
+    nev += __shfl_down(nev, o);
+    nfl += __shfl_down(nfl, o);
+  }
   if ((tid & 63u) == 0 && nev) atomicAdd(&n.evcnt[blockIdx.x & 63u], nev);
+  if ((tid & 63u) == 0 && nfl) atomicAdd(&n.cnt[CNT_FLUSH], nfl);
 }
 
 // Fixed-order reduction of the trial-chunk partial sums into (gs, gc).

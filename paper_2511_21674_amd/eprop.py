@@ -23,21 +23,24 @@ EPROP_ERR_DEVICE, EPROP_ERR_STATE, EPROP_ERR_CAPACITY = -3, -4, -5
 EPROP_ERR_NUMERIC, EPROP_ERR_UNSUPPORTED = -6, -7
 EPROP_FP32, EPROP_FP64 = 0, 1
 EPROP_DELIVERY_AUTO, EPROP_DELIVERY_SCATTER, EPROP_DELIVERY_GATHER = 0, 1, 2
-EPROP_FLAG_NO_GRAPH = 1
+EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS = 1, 2, 4
 EPROP_MEM_HOST, EPROP_MEM_DEVICE = 0, 1
-EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE = 1, 2
+EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE, EPROP_RECORD_SPIKES, EPROP_RECORD_TRACES = 1, 2, 4, 8
+EPROP_TRAIN = EPROP_BATCH_TRAIN
 EPROP_N_PHASES = 8
 PHASES = ("stage", "forward", "readout", "adjoint", "synapse", "output")
 (EPROP_STATE_W_IN, EPROP_STATE_W_REC, EPROP_STATE_W_OUT, EPROP_STATE_GRAD_IN, EPROP_STATE_GRAD_REC,
  EPROP_STATE_GRAD_OUT, EPROP_STATE_ADAM_M_IN, EPROP_STATE_ADAM_V_IN, EPROP_STATE_ADAM_M_REC,
  EPROP_STATE_ADAM_V_REC, EPROP_STATE_ADAM_M_OUT, EPROP_STATE_ADAM_V_OUT, EPROP_STATE_ADAM_STEP,
  EPROP_STATE_SPIKES, EPROP_STATE_PSI, EPROP_STATE_Y, EPROP_STATE_ERR, EPROP_STATE_V,
- EPROP_STATE_LAYOUT) = range(19)
+ EPROP_STATE_LAYOUT, EPROP_STATE_L) = range(20)
 
 EXPORTED = ("eprop_create_network", "eprop_simulate_batch", "eprop_apply_updates", "eprop_read_state",
             "eprop_destroy_network", "eprop_status_string", "eprop_last_error")
 
 _P = C.c_void_p
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class eprop_config(C.Structure):
@@ -49,7 +52,9 @@ class eprop_config(C.Structure):
                 ("loss", C.c_int32), ("optimizer", C.c_int32), ("eta", C.c_double),
                 ("adam_beta1", C.c_double), ("adam_beta2", C.c_double), ("adam_eps_hat", C.c_double),
                 ("max_delay", C.c_uint32), ("max_trials", C.c_uint32), ("max_steps", C.c_uint32),
-                ("delivery", C.c_int32), ("flags", C.c_uint32)]
+                ("delivery", C.c_int32), ("flags", C.c_uint32), ("d_out", C.c_uint32), ("d_ls", C.c_uint32),
+                ("history_steps", C.c_uint32), ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
+                ("alloc_ctx", _P)]
 
 
 class eprop_projection(C.Structure):
@@ -72,7 +77,8 @@ class eprop_batch(C.Structure):
 class eprop_batch_result(C.Structure):
     _fields_ = [("loss", _P), ("predicted", _P), ("n_rec_spikes", C.c_uint64), ("n_in_spikes", C.c_uint64),
                 ("n_syn_events", C.c_uint64), ("n_out_events", C.c_uint64), ("n_eprop_updates", C.c_uint64),
-                ("device_ms", C.c_double), ("phase_ms", C.c_double * EPROP_N_PHASES)]
+                ("n_flush_updates", C.c_uint64), ("device_seconds", C.c_double),
+                ("phase_ms", C.c_double * EPROP_N_PHASES)]
 
 
 _lib = None
@@ -171,15 +177,40 @@ class BatchResult:
     n_syn_events: int
     n_out_events: int
     n_eprop_updates: int
-    device_ms: float
+    n_flush_updates: int
+    device_seconds: float
     phase_ms: dict = field(default_factory=dict)
+
+
+class TorchAllocator:
+    """Device allocator callbacks backed by PyTorch's caching allocator:
+    each library buffer is a uint8 tensor kept alive until the library
+    returns it."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.blocks = {}
+
+        def alloc(nbytes, ctx):
+            t = self._torch.empty(int(nbytes) + 256, dtype=self._torch.uint8, device="cuda")
+            p = (t.data_ptr() + 255) & ~255
+            self.blocks[p] = t
+            return p
+
+        def free(ptr, ctx):
+            self.blocks.pop(ptr, None)
+
+        self.alloc_fn = DEV_ALLOC_FN(alloc)
+        self.free_fn = DEV_FREE_FN(free)
 
 
 class Network:
     """One library handle built from a ``workloads.Network``."""
 
     def __init__(self, wnet, precision: str = "fp32", max_trials: int = 1, max_steps: int = 1000,
-                 delivery: str = "auto", graph: bool = True, stream=None, max_delay: int = None):
+                 delivery: str = "auto", graph: bool = True, stream=None, max_delay: int = None,
+                 torch_alloc: bool = False, deterministic: bool = False):
         p = wnet.params
         self.wnet = wnet
         self._keep = []
@@ -195,7 +226,10 @@ class Network:
                            adam_beta2=p.adam_beta2, adam_eps_hat=p.adam_eps_hat, max_delay=md,
                            max_trials=max_trials, max_steps=max_steps,
                            delivery={"auto": 0, "scatter": 1, "gather": 2}[delivery],
-                           flags=0 if graph else EPROP_FLAG_NO_GRAPH)
+                           flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0))
+        self.allocator = TorchAllocator() if torch_alloc else None
+        if self.allocator is not None:
+            cfg.dev_alloc, cfg.dev_free = self.allocator.alloc_fn, self.allocator.free_fn
         projs = []
         for pr in (wnet.in_rec, wnet.rec_rec):
             arrs = (_c(pr.row_ptr, np.uint64), _c(pr.col, np.uint32), _c(pr.w, np.float64), _c(pr.delay, np.uint8))
@@ -268,7 +302,7 @@ class Network:
         self._check(eprop_simulate_batch(self.h, b, res))
         del keep
         return BatchResult(loss, pred, res.n_rec_spikes, res.n_in_spikes, res.n_syn_events, res.n_out_events,
-                           res.n_eprop_updates, res.device_ms,
+                           res.n_eprop_updates, res.n_flush_updates, res.device_seconds,
                            {k: res.phase_ms[i] for i, k in enumerate(PHASES)} if profile else {})
 
     def apply(self):

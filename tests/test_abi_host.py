@@ -4,6 +4,7 @@ touches a device."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -39,12 +40,44 @@ def test_status_strings():
     assert E.eprop_status_string(12345) == "unknown status"
 
 
-def test_struct_sizes_match_c_layout():
-    # natural alignment on x86-64; a mismatch would shift every later field
-    assert C.sizeof(E.eprop_config) == 176
-    assert C.sizeof(E.eprop_projection) == 48
-    assert C.sizeof(E.eprop_batch) == 120
-    assert C.sizeof(E.eprop_batch_result) == 128
+def test_struct_layout_matches_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the binding equals what a C
+    compiler makes of include/eprop.h."""
+    structs = [E.eprop_config, E.eprop_projection, E.eprop_optimizer_state, E.eprop_batch,
+               E.eprop_batch_result]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "eprop.h"', "int main(void) {"]
+    for st in structs:
+        lines.append(f'  printf("{st.__name__} size %zu\\n", sizeof({st.__name__}));')
+        for name, _ in st._fields_:
+            lines.append(f'  printf("{st.__name__} {name} %zu\\n", offsetof({st.__name__}, {name}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in structs:
+        assert got[(st.__name__, "size")] == C.sizeof(st), st.__name__
+        for name, _ in st._fields_:
+            assert got[(st.__name__, name)] == getattr(st, name).offset, (st.__name__, name)
+
+
+def test_config_rejects_delays_and_short_history():
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, d_out=1)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, d_ls=2)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, history_steps=100)   # max_steps is 200
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, flags=1 << 7)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, precision=E.EPROP_FP64, delivery=1,
+                                      flags=E.EPROP_DETERMINISTIC)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network)
+    cfg.dev_alloc = E.DEV_ALLOC_FN(lambda n, c: None)   # allocator without its free function
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
 
 
 def _parts(wnet, **cfg_over):

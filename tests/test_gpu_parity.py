@@ -343,3 +343,109 @@ def test_full_size_sparse_network_sampled():
         ok, e, ent = rel_close(gg[m], ref[m], 1e-4, floor_frac=1e-2)
         log(f"full size {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
         assert ok, (name, e, ent)
+
+
+# ----------------------------------------------------------------- recordings, counters, allocator
+
+@pytest.mark.parametrize("loss", [0, 1])
+def test_recorded_traces_match_oracle(loss):
+    """FP64: the recorded psi, readout y, error E, learning signal L
+    (eq. final-gradient) and final membrane potential of every trial equal
+    the oracle's recordings."""
+    wl = W.tiny(loss=loss)
+    b = wl.make_batch(0, 0, 2)
+    net = E.Network(wl.network, "fp64", max_trials=2, max_steps=int(b.n_steps.max()))
+    net.simulate(b)
+    on = O.OracleNet(wl.network)
+    for i in range(2):
+        T = int(b.n_steps[i])
+        tr = O.run_trial(on, b, i, 0, trace=True).trace
+        J, K = wl.network.n_rec, wl.network.n_out
+        for what, ref, shape in ((E.EPROP_STATE_PSI, tr["psi"], (T, J)), (E.EPROP_STATE_Y, tr["y"], (T, K)),
+                                 (E.EPROP_STATE_ERR, tr["err"], (T, K)), (E.EPROP_STATE_L, tr["learn"], (T, J))):
+            got = net.read(what, i).reshape(shape)
+            ok, e, ent = rel_close(got, ref, 1e-12)
+            assert ok, (what, i, e, ent)
+        assert rel_close(net.read(E.EPROP_STATE_V, i), tr["v"][T - 1], 1e-12)[0]
+    net.close()
+
+
+def _counts_from_spikes(wnet, b, spikes):
+    """Synaptic events and trial-end evaluations counted on the host from the
+    recorded spike trains and the graph: every delivery that arrives within
+    its trial, and every (synapse, trial) pair with at least one."""
+    events, flushes = 0, 0
+    for i in range(b.n_trials):
+        T = int(b.n_steps[i])
+        lo, hi = int(b.in_ptr[i]), int(b.in_ptr[i + 1])
+        src_times = [(wnet.in_rec, b.in_src[lo:hi], b.in_step[lo:hi]),
+                     (wnet.rec_rec, spikes[i][:, 1], spikes[i][:, 0])]
+        for proj, srcs, steps in src_times:
+            rp = proj.row_ptr.astype(np.int64)
+            per_src = {}
+            for s, t in zip(srcs.tolist(), steps.tolist()):
+                per_src.setdefault(s, []).append(t)
+            for s, ts in per_src.items():
+                d = proj.delay[rp[s]:rp[s + 1]].astype(np.int64)
+                ts = np.asarray(ts, np.int64)
+                arr = ts[None, :] + d[:, None] <= T
+                events += int(arr.sum())
+                flushes += int(arr.any(axis=1).sum())
+    return events, flushes
+
+
+def test_event_and_flush_counters_match_recorded_spikes():
+    """The library's event and trial-end counters equal the counts derived on
+    the host from the recorded spikes and the graph (uneven trials, ALIF)."""
+    wl = W.c2_evidence(batch_size=4)
+    b = wl.make_batch(0, 0, 4)
+    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=int(b.n_steps.max()))
+    r = net.simulate(b, train=True)
+    spikes = [net.read(E.EPROP_STATE_SPIKES, i) for i in range(4)]
+    net.close()
+    ev, fl = _counts_from_spikes(wl.network, b, spikes)
+    assert r.n_rec_spikes == sum(len(s) for s in spikes)
+    assert r.n_syn_events == ev and r.n_eprop_updates == ev
+    assert r.n_flush_updates == fl
+    log(f"c2: {ev} events, {fl} trial-end evaluations")
+
+
+def test_torch_allocator_gives_identical_results():
+    """Device buffers from PyTorch's caching allocator (the optional
+    allocator callbacks) change nothing: FP32 results are bitwise equal."""
+    wl = W.c3_events(batch_size=2)
+    b = wl.make_batch(0, 0, 2)
+    out = []
+    for torch_alloc in (False, True):
+        net = E.Network(wl.network, "fp32", max_trials=2, max_steps=300, torch_alloc=torch_alloc)
+        r = net.simulate(b)
+        net.apply()
+        out.append((r.loss.copy(), net.weights()))
+        if torch_alloc:
+            assert len(net.allocator.blocks) > 10
+        net.close()
+        if torch_alloc:
+            assert len(net.allocator.blocks) == 0
+    assert np.array_equal(out[0][0], out[1][0])
+    for k in KEYS:
+        assert np.array_equal(out[0][1][k], out[1][1][k])
+
+
+def test_fp32_multi_tile_runs_are_deterministic():
+    """FP32 scatter over several tiles per trial (spike lists exchanged
+    between workgroups): input currents are exact fixed-point sums, so two
+    runs agree bit for bit, spikes, losses and gradients."""
+    wl = W.c4_sparse(n_rec=3000, n_steps=300, batch_size=2, n_in=300)
+    b = wl.make_batch(0, 0, 2)
+    runs = []
+    for _ in range(2):
+        net = E.Network(wl.network, "fp32", max_trials=2, max_steps=300)
+        assert net.layout()["tiles"] > 1
+        r = net.simulate(b)
+        runs.append((r.loss.copy(), net.grads(), [net.read(E.EPROP_STATE_SPIKES, i) for i in range(2)]))
+        net.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for i in range(2):
+        assert np.array_equal(runs[0][2][i], runs[1][2][i])
+    for k in KEYS:
+        assert np.array_equal(runs[0][1][k], runs[1][1][k])
