@@ -125,40 +125,80 @@ def run_staged(net, staged, train=True, profile=False):
     return res, loss
 
 
-def cpu_baseline(wl, n_steps_sample):
-    """The FP64 oracle (event-driven gradient) on the first n steps of one
-    trial of the same workload, single thread."""
-    import oracle as O
+def _events_of_trial(net, b, i, z):
+    """Deliveries arriving within trial i, from its input spikes and the
+    recorded recurrent spikes z ([T, J]) (same definition as the library)."""
+    T = int(b.n_steps[i])
+    lo, hi = int(b.in_ptr[i]), int(b.in_ptr[i + 1])
+    ev = 0
+    for proj, spikes in ((net.in_rec, zip(b.in_step[lo:hi].tolist(), b.in_src[lo:hi].tolist())),
+                         (net.rec_rec, [(int(t) + 1, int(j)) for t, j in zip(*np.nonzero(z))])):
+        rp = proj.row_ptr.astype(np.int64)
+        for s, src in spikes:
+            d = proj.delay[rp[src]:rp[src + 1]].astype(np.int64)
+            ev += int(np.count_nonzero(s + d <= T))
+    return ev
+
+
+def _truncated(b, i, T):
+    """Trial i of batch b cut to its first T steps."""
     from paper_2511_21674_amd import workloads as W
-    b = wl.make_batch(0, 0, 1)
-    T = n_steps_sample
-    keep = b.in_step < T
-    lo = int(b.in_ptr[0])
+    lo, hi = int(b.in_ptr[i]), int(b.in_ptr[i + 1])
+    keep = b.in_step[lo:hi] < T
     sb = W.Batch(n_steps=np.array([T], np.uint32), in_ptr=np.array([0, int(keep.sum())], np.uint64),
-                 in_step=b.in_step[keep], in_src=b.in_src[keep])
+                 in_step=b.in_step[lo:hi][keep], in_src=b.in_src[lo:hi][keep])
     if b.target is not None:
-        sb.target = np.ascontiguousarray(b.target[:1, :T])
+        sb.target = np.ascontiguousarray(b.target[i:i + 1, :T])
     if b.label is not None:
-        sb.label = b.label[:1]
+        sb.label = b.label[i:i + 1]
     if b.window is not None:
-        sb.window = np.ascontiguousarray(b.window[:1, :T])
-    on = O.OracleNet(wl.network)
+        sb.window = np.ascontiguousarray(b.window[i:i + 1, :T])
+    return sb
+
+
+def cpu_baseline(wl, n_steps_sample, budget_s=20.0):
+    """The FP64 oracle on one host core.  Networks up to a few thousand
+    neurons: whole trials of the first batch, event-driven gradient (value)
+    and time-driven gradient (beside it), as many trials as fit the time
+    budget.  Larger networks: the first n steps of one trial, event-driven."""
+    import oracle as O
+    net = wl.network
+    on = O.OracleNet(net)
+    b = wl.make_batch(0, 0, wl.batch_size)
+    out = {"unit": "synaptic events/s", "cores": 1, "kind": "oracle"}
+    if net.n_rec <= 5000:
+        res = {}
+        for mode, name in ((2, "event-driven"), (1, "time-driven")):
+            g = O.zero_grads(on)
+            ev, el, done = 0, 0.0, 0
+            for i in range(b.n_trials):
+                if name == "time-driven" and done >= res["event-driven"][2]:
+                    break
+                t0 = time.perf_counter()
+                r = O.run_trial(on, b, i, mode, g, trace=True)
+                el += time.perf_counter() - t0
+                ev += _events_of_trial(net, b, i, r.trace["z"])
+                done += 1
+                if el > budget_s / 2:
+                    break
+            res[name] = (ev, el, done)
+        ev, el, done = res["event-driven"]
+        tev, tel, tdone = res["time-driven"]
+        out.update(value=ev / el, time_driven_value=tev / tel,
+                   sample=f"{done} whole trials of the first batch of the same workload, event-driven gradient "
+                          f"({ev} events, {el:.1f} s); time-driven gradient on {tdone} of them ({tel:.1f} s); "
+                          f"network construction excluded")
+        return out
+    T = min(n_steps_sample, int(b.n_steps[0]))
+    sb = _truncated(b, 0, T)
     g = O.zero_grads(on)
     t0 = time.perf_counter()
     r = O.run_trial(on, sb, 0, 2, g, trace=True)
     el = time.perf_counter() - t0
-    # events: deliveries arriving within the sample (same definition as the GPU)
-    net = wl.network
-    ev = 0
-    for proj, spikes in ((net.in_rec, [(int(s), int(i)) for s, i in zip(sb.in_step, sb.in_src)]),
-                         (net.rec_rec, [(int(t) + 1, int(j)) for t, j in zip(*np.nonzero(r.trace["z"]))])):
-        rp = proj.row_ptr.astype(np.int64)
-        for s, i in spikes:
-            d = proj.delay[rp[i]:rp[i + 1]].astype(np.int64)
-            ev += int(np.count_nonzero(s + d <= T))
-    return {"value": ev / el, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {T} steps of one trial of the same network (event-driven gradient, "
-                      f"{ev} events, {el:.1f} s, network construction excluded)"}
+    ev = _events_of_trial(net, sb, 0, r.trace["z"])
+    out.update(value=ev / el, sample=f"first {T} steps of one trial of the same network (event-driven gradient, "
+                                     f"{ev} events, {el:.1f} s, network construction excluded)")
+    return out
 
 
 def main():
@@ -170,6 +210,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--fp64-iters", type=int, default=1,
+                    help="training iterations of the FP64 plain comparison (<= warmup + steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -254,30 +296,36 @@ def main():
         roof["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     fp64 = None
-    if not args.no_fp64 and args.warmup >= 1:
+    if not args.no_fp64:
         # the FP64 plain path (same kernels in double, one trial at a time,
-        # deterministic gather delivery) on the first batch from the same
-        # initial weights as the FP32 run's first (warm-up) batch
+        # deterministic gather delivery), trained on the same batches from
+        # the same initial weights as the FP32 run's first iterations
+        m = max(1, min(args.fp64_iters, args.warmup + steps))
+        all32 = warm_losses + losses
         with torch.cuda.stream(stream):
             net64 = E.Network(net_w, "fp64", max_trials=1, max_steps=T, delivery="gather",
                               stream=E.C.c_void_p(stream.cuda_stream))
-            b0 = staged[0][0]
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             ev64, loss64 = 0, []
-            for i in range(b0.n_trials):
-                r = net64.simulate(b0.trial(i), train=True)
-                ev64 += r.n_syn_events
-                loss64.append(float(r.loss[0]))
-            net64.apply()
+            for it in range(m):
+                bb = staged[it][0]
+                lt = []
+                for i in range(bb.n_trials):
+                    r = net64.simulate(bb.trial(i), train=True)
+                    ev64 += r.n_syn_events
+                    lt.append(float(r.loss[0]))
+                net64.apply()
+                loss64.append(float(np.mean(lt)))
             torch.cuda.synchronize()
             el64 = time.perf_counter() - t1
             net64.close()
-        l64, l32 = float(np.mean(loss64)), warm_losses[0]
-        fp64 = {"value": ev64 / el64, "unit": "synaptic events/s", "seconds_per_batch": el64,
-                "speedup_fp32_batched": el64 / (elapsed / steps),
-                "loss_fp64": l64, "loss_fp32": l32, "loss_rel_diff": abs(l32 - l64) / abs(l64),
-                "note": "same batch and initial weights; speedup = FP64 plain seconds per batch / FP32 batched"}
+        l64, l32 = loss64[-1], all32[m - 1]
+        fp64 = {"value": ev64 / el64, "unit": "synaptic events/s", "seconds_per_iteration": el64 / m,
+                "iterations": m, "speedup_fp32_batched": (el64 / m) / (elapsed / steps),
+                "loss_fp64": loss64, "loss_fp32": all32[:m], "final_loss_rel_diff": abs(l32 - l64) / abs(l64),
+                "note": "same batches and initial weights; speedup = FP64 plain seconds per iteration / "
+                        "FP32 batched"}
     net.close()
 
     cpu = None

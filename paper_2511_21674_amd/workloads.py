@@ -383,7 +383,7 @@ def c3_events(seed: int = SEED_BASE + 3, batch_size: int = 128, iterations: int 
     recurrence), 10 softmax readouts, learning window = last 30 steps, GD."""
     side, n_classes = 34, 10
     n_in, n_rec, n_out = 2 * side * side, 180, 10
-    prm = Params(loss=1, optimizer=0, eta=5e-3)
+    prm = Params(loss=1, optimizer=0, eta=1e-3)
     net = Network(n_in, n_rec, n_out, np.zeros(n_rec, np.uint8), prm,
                   dense_projection(n_in, n_rec, 1 / np.sqrt(n_in), rng(seed, _P_W_IN)),
                   bernoulli_projection(n_rec, n_rec, 0.1, 1 / np.sqrt(18.0), rng(seed, _P_GRAPH_REC),
@@ -459,7 +459,7 @@ def _large_sparse(name: str, seed: int, n_rec: int, indeg_rec: int, n_in: int, i
 # the configured target (about 10 Hz for the 1e5-neuron network, about 5 Hz for
 # the 1e6-neuron one); measured rates are always reported next to results.
 C4_GAIN, C4_IN_GAIN = 0.5, 0.75
-C5_GAIN, C5_IN_GAIN = 0.5, 1.0
+C5_GAIN, C5_IN_GAIN = 1.1, 1.0
 
 
 def c4_sparse(seed: int = SEED_BASE + 4, n_rec: int = 100_000, n_steps: int = 1000,
