@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--workload", default="c4_sparse")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (the tuner otherwise runs in the first warm-up batch)")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--fp64-iters", type=int, default=1,
                     help="training iterations of the FP64 plain comparison (<= warmup + steps)")
@@ -248,7 +250,7 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         net = E.Network(net_w, "fp32", max_trials=wl.batch_size, max_steps=T,
-                        stream=E.C.c_void_p(stream.cuda_stream))
+                        stream=E.C.c_void_p(stream.cuda_stream), autotune=not args.no_autotune)
         staged = stage_batches(wl, args.warmup + args.steps, 0)
         torch.cuda.synchronize()
         warm_losses = []

@@ -99,6 +99,10 @@ typedef enum { EPROP_DELIVERY_AUTO = 0, EPROP_DELIVERY_SCATTER = 1, EPROP_DELIVE
                                            delivery is deterministic in either mode) */
 #define EPROP_SHARED_WEIGHTS (1u << 2)  /* all trials of a batch use the same weights (always the case;
                                            accepted for clarity) */
+#define EPROP_AUTOTUNE (1u << 3)        /* the first training batch times the candidate launch shapes
+                                           (delivery variant and steps per forward launch, adjoint and
+                                           synapse block sizes) on the batch itself and keeps the
+                                           fastest; results do not depend on the choice */
 
 /* Optional device allocator, e.g. a framework's caching allocator: every
  * device buffer of the handle is taken from dev_alloc (bytes, ctx) and
@@ -275,11 +279,13 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18,     /* uint64 [8]: neurons per tile, tiles per trial, bytes per
+  EPROP_STATE_LAYOUT = 18,     /* uint64 [12]: neurons per tile, tiles per trial, bytes per
                                   delay-ring entry (8: 64-bit fixed point in FP32 or double in
                                   FP64, 4: 32-bit fixed point in FP32), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
-                                  forward launch, gather delivery (0/1) */
+                                  forward launch, gather delivery (0/1), synapses per delivery
+                                  piece, pieces in flight per lane group, adjoint-kernel
+                                  threads, autotuned (0/1) */
   EPROP_STATE_L = 19           /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
 } eprop_state_id;

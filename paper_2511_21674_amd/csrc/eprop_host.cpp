@@ -59,6 +59,8 @@ struct eprop_network {
   uint32_t blk = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipEvent_t ev[EPROP_N_PHASES + 1] = {};
+  hipEvent_t tev[2] = {};           // autotuner timing
+  bool autotune_pending = false, tuned = false;
   // last batch
   uint32_t last_ntr = 0;
   std::vector<uint32_t> last_T;
@@ -168,7 +170,7 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
   if (c->max_trials < 1) return bad("max_trials must be >= 1");
   if (c->max_steps < 1 || c->max_steps > 65535) return bad("max_steps must be in 1..65535");
   if (c->delivery < EPROP_DELIVERY_AUTO || c->delivery > EPROP_DELIVERY_GATHER) return bad("unknown delivery");
-  if (c->flags & ~(uint32_t)(EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS))
+  if (c->flags & ~(uint32_t)(EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS | EPROP_AUTOTUNE))
     return bad("unknown config flag");
   if ((c->flags & EPROP_DETERMINISTIC) && c->precision == EPROP_FP64 && c->delivery == EPROP_DELIVERY_SCATTER)
     return bad("FP64 scatter delivery is not deterministic; use gather or AUTO");
@@ -385,6 +387,8 @@ void eprop_destroy_network(eprop_network *net) {
     if (g) (void)hipGraphExecDestroy(g);
   for (auto &e : net->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &e : net->tev)
+    if (e) (void)hipEventDestroy(e);
   if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
   for (void *p : net->allocs) dfree(net, p);
   delete net;
@@ -514,6 +518,9 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   n->perm = tm_perm;
   n->adam_step = opt ? opt->step : 0;
   n->shapes.block = 256;
+  n->shapes.fwd_variant = 0;
+  n->shapes.adj_block = cfg->n_out > 16 ? 64 : 256;
+  n->autotune_pending = (cfg->flags & EPROP_AUTOTUNE) != 0;
   {
     // synapse kernel: a block per (target, chunk of trials); the chunk's
     // archive rows must fit 16 KB of LDS, and small networks with many
@@ -630,6 +637,8 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&n->cap_stream, hipStreamNonBlocking);
   for (auto &ev : n->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
+  for (auto &ev : n->tev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     g_create_error = std::string("device error during setup: ") + hip_msg(e);
@@ -722,7 +731,7 @@ void record_block(eprop_network *n, DevNet<real> &d, bool forced, hipStream_t s)
   if (n->gather) {
     for (uint32_t o = 1; o <= n->blk; ++o) Launch<real>::neuron_gather(d, o, forced, s);
   } else {
-    Launch<real>::forward_tiled(d, n->blk, forced, n->shapes.tile_block, n->tile_smem, s);
+    Launch<real>::forward_tiled(d, n->blk, forced, n->shapes, n->tile_smem, s);
   }
   eprop::launch_advance(d.ctl, n->blk, s);
 }
@@ -740,6 +749,21 @@ hipError_t ensure_graph(eprop_network *n, DevNet<real> &d, bool forced) {
   e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   return e;
+}
+
+void drop_graphs(eprop_network *n) {
+  for (auto &g : n->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Returns a buffer from dalloc before the handle is destroyed.
+void release(eprop_network *n, void *p) {
+  auto it = std::find(n->allocs.begin(), n->allocs.end(), p);
+  if (it != n->allocs.end()) n->allocs.erase(it);
+  dfree(n, p);
 }
 
 template <typename real>
@@ -836,26 +860,75 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   ctl.w[eprop::CTL_NTRIALS] = ntr;
   ctl.w[eprop::CTL_ERR] = 0;
   ctl.in_src = d.in_src;
-  H2D(d.ctl, &ctl, sizeof(ctl));
-  // per-batch state from zero (trials start from rest)
   const size_t T1 = (size_t)n->Tcap + 1;
-  MS(d.v, (size_t)ntr * n->Jp * sizeof(real));
-  MS(d.a, (size_t)ntr * n->Jp * sizeof(real));
-  MS(d.nst, (size_t)ntr * n->Jp);
-  MS(d.ring, (size_t)ntr * n->R * n->Jp * d.ring_bytes);
-  MS(d.in_bits, (size_t)ntr * n->Tcap * n->Iw * 8);
-  MS(d.spk_cnt, (size_t)ntr * n->NS * 4);
-  if (!n->gather) {  // tags of an earlier batch must not match
-    MS(d.pub_list, (size_t)ntr * 2 * n->Jp * 8);
-    MS(d.pub_cnt, (size_t)ntr * 2 * d.KT * 8);
-  }
-  MS(d.cnt, eprop::CNT_WORDS * 8);
-  MS(d.evcnt, 64 * 8);
-  if (forced) MS(d.forced_bits, (size_t)ntr * T1 * n->Jw * 8);
-  if (e != hipSuccess) goto device_error;
+  // per-batch state from zero (trials start from rest) and staged inputs;
+  // run again by the autotuner before each timed forward pass
+  auto restage = [&]() {
+    H2D(d.ctl, &ctl, sizeof(ctl));
+    MS(d.v, (size_t)ntr * n->Jp * sizeof(real));
+    MS(d.a, (size_t)ntr * n->Jp * sizeof(real));
+    MS(d.nst, (size_t)ntr * n->Jp);
+    MS(d.ring, (size_t)ntr * n->R * n->Jp * d.ring_bytes);
+    MS(d.in_bits, (size_t)ntr * n->Tcap * n->Iw * 8);
+    MS(d.spk_cnt, (size_t)ntr * n->NS * 4);
+    if (!n->gather) {  // tags of an earlier batch must not match
+      MS(d.pub_list, (size_t)ntr * 2 * n->Jp * 8);
+      MS(d.pub_cnt, (size_t)ntr * 2 * d.KT * 8);
+    }
+    MS(d.cnt, eprop::CNT_WORDS * 8);
+    MS(d.evcnt, 64 * 8);
+    if (forced) MS(d.forced_bits, (size_t)ntr * T1 * n->Jw * 8);
+    if (e != hipSuccess) return;
+    Launch<real>::stage_inputs(d, ntr, b->n_in_spikes, dev, s);
+    if (forced) Launch<real>::stage_forced(d, ntr, b->n_forced, s);
+  };
+  // the forward pass in blocks of steps (the tiled kernel delivers step-0 inputs first)
+  auto forward = [&]() {
+    const uint32_t nblk = (t_max + n->blk - 1) / n->blk;
+    if (n->use_graph) {
+      if (e == hipSuccess) e = ensure_graph(n, d, forced);
+      for (uint32_t i = 0; i < nblk && e == hipSuccess; ++i) e = hipGraphLaunch(n->gexec[forced ? 1 : 0], s);
+    } else {
+      for (uint32_t i = 0; i < nblk; ++i) record_block(n, d, forced, s);
+    }
+  };
+  // device time of fn on the stream (best of two runs; setup() first each time)
+  auto timed = [&](auto setup, auto fn) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      setup();
+      if (n->use_graph && e == hipSuccess) e = ensure_graph(n, d, forced);  // instantiate outside the timing
+      if (e == hipSuccess) e = hipEventRecord(n->tev[0], s);
+      fn();
+      if (e == hipSuccess) e = hipEventRecord(n->tev[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(n->tev[1]);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, n->tev[0], n->tev[1]);
+      if (e == hipSuccess && ms < best) best = ms;
+    }
+    return best;
+  };
+  const bool tune = n->autotune_pending && train;
 
-  Launch<real>::stage_inputs(d, ntr, b->n_in_spikes, dev, s);
-  if (forced) Launch<real>::stage_forced(d, ntr, b->n_forced, s);
+  (void)hipEventRecord(n->ev[0], s);
+  // upload
+  H2D(n->d_T, b->n_steps, ntr * 4);
+  if (b->label) H2D(n->d_label, b->label, ntr * 4);
+  if (!dev) {
+    H2D(n->d_in_ptr, in_ptr.data(), in_ptr.size() * 8);
+    H2D(n->d_in_step, b->in_step, b->n_in_spikes * 4);
+    H2D(n->d_in_src, b->in_src, b->n_in_spikes * 4);
+    const size_t nt = (size_t)ntr * b->step_stride;
+    if (b->target) H2D(n->d_target, b->target, nt * n->K * 8);
+    if (b->window) H2D(n->d_window, b->window, nt);
+    if (forced) {
+      H2D(n->d_forced_ptr, f_ptr.data(), f_ptr.size() * 8);
+      H2D(n->d_forced_step, b->forced_step, b->n_forced * 4);
+      H2D(n->d_forced_neuron, b->forced_neuron, b->n_forced * 4);
+    }
+  }
+  restage();
+  if (e != hipSuccess) goto device_error;
   if (dev) {
     uint32_t flags = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flags, d.ctl + eprop::CTL_ERR, 4, hipMemcpyDeviceToHost, s);
@@ -867,25 +940,87 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
       return EPROP_ERR_INVALID_ARGUMENT;
     }
   }
-  if (prof) (void)hipEventRecord(n->ev[1], s);
-
-  // forward in blocks of steps (the tiled kernel delivers step-0 inputs first)
-  {
-    const uint32_t nblk = (t_max + n->blk - 1) / n->blk;
-    if (n->use_graph) {
-      e = ensure_graph(n, d, forced);
-      if (e != hipSuccess) goto device_error;
-      for (uint32_t i = 0; i < nblk && e == hipSuccess; ++i) e = hipGraphLaunch(n->gexec[forced ? 1 : 0], s);
-    } else {
-      for (uint32_t i = 0; i < nblk; ++i) record_block(n, d, forced, s);
+  if (tune && !n->gather) {
+    // Autotuner, part 1: the delivery variant of the forward kernel, then the
+    // steps per launch.  Every candidate simulates this batch from rest; the
+    // results do not depend on the shapes (FP32 sums are exact fixed point).
+    float best = 1e30f;
+    uint32_t bv = n->shapes.fwd_variant, bb = n->blk;
+    for (uint32_t v = 0; v < eprop::kNumFwdVariants && e == hipSuccess; ++v) {
+      n->shapes.fwd_variant = v;
+      drop_graphs(n);
+      const float ms = timed(restage, forward);
+      if (ms < best) { best = ms; bv = v; }
     }
+    n->shapes.fwd_variant = bv;
+    for (uint32_t blk : {125u, 500u, 1000u}) {
+      if (blk > n->Tcap || e != hipSuccess) continue;
+      n->blk = blk;
+      drop_graphs(n);
+      const float ms = timed(restage, forward);
+      if (ms < best) { best = ms; bb = blk; }
+    }
+    n->blk = bb;
+    drop_graphs(n);
+    restage();
+    if (e != hipSuccess) goto device_error;
   }
+  if (prof) (void)hipEventRecord(n->ev[1], s);
+  forward();
+  if (e != hipSuccess) goto device_error;
   if (prof) (void)hipEventRecord(n->ev[2], s);
   Launch<real>::readout(d, s);
   if (prof) (void)hipEventRecord(n->ev[3], s);
   if (train) {
-    Launch<real>::adjoint(d, s);
+    if (tune) {
+      // part 2: threads per block of the adjoint kernel (idempotent)
+      float best = 1e30f;
+      uint32_t bbd = n->shapes.adj_block;
+      for (uint32_t bd : {64u, 128u, 256u}) {
+        if (bd > 64 && n->K > 16) continue;  // LDS of the feedback rows
+        n->shapes.adj_block = bd;
+        const float ms = timed([] {}, [&] { Launch<real>::adjoint(d, n->shapes, s); });
+        if (ms < best) { best = ms; bbd = bd; }
+      }
+      n->shapes.adj_block = bbd;
+    }
+    Launch<real>::adjoint(d, n->shapes, s);
     if (prof) (void)hipEventRecord(n->ev[4], s);
+    if (tune) {
+      // part 3: threads per block of the synapse kernel; the accumulators
+      // are saved before and restored after every trial run
+      void *save = nullptr;
+      const size_t gbytes = n->S * sizeof(real);
+      if (n->S && dalloc(n, reinterpret_cast<uint8_t **>(&save), 2 * gbytes)) {
+        auto keep = [&] {
+          if (e == hipSuccess) e = hipMemcpyAsync(save, d.gs, gbytes, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipMemcpyAsync(static_cast<uint8_t *>(save) + gbytes, d.gc, gbytes,
+                                                  hipMemcpyDeviceToDevice, s);
+        };
+        auto back = [&] {
+          if (e == hipSuccess) e = hipMemcpyAsync(d.gs, save, gbytes, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipMemcpyAsync(d.gc, static_cast<uint8_t *>(save) + gbytes, gbytes,
+                                                  hipMemcpyDeviceToDevice, s);
+        };
+        keep();
+        float best = 1e30f;
+        uint32_t bsb = n->shapes.syn_block;
+        for (uint32_t sb : {64u, 128u, 256u}) {
+          n->shapes.syn_block = sb;
+          const float ms = timed(back, [&] {
+            Launch<real>::synapse(d, n->shapes, ntr, static_cast<real *>(n->partial), s);
+          });
+          if (ms < best) { best = ms; bsb = sb; }
+        }
+        back();
+        n->shapes.syn_block = bsb;
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        release(n, save);
+      }
+      n->autotune_pending = false;
+      n->tuned = true;
+      if (e != hipSuccess) goto device_error;
+    }
     Launch<real>::synapse(d, n->shapes, ntr, static_cast<real *>(n->partial), s);
     if (prof) (void)hipEventRecord(n->ev[5], s);
     Launch<real>::output_reduce(d, s);
@@ -992,8 +1127,10 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   const bool per_trial = (what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V) || what == EPROP_STATE_L;
   if (what < 0 || what > EPROP_STATE_L) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
-    const uint64_t lay[8] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
-                             n->blk, n->gather ? 1u : 0u};
+    const uint64_t lay[12] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
+                              n->blk, n->gather ? 1u : 0u, eprop::fwd_variant_piece(n->shapes.fwd_variant),
+                              eprop::fwd_variant_unroll(n->shapes.fwd_variant), n->shapes.adj_block,
+                              n->tuned ? 1u : 0u};
     if (needed) *needed = sizeof(lay);
     if (!dst) return EPROP_OK;
     if (dst_bytes < sizeof(lay)) return EPROP_ERR_INVALID_ARGUMENT;

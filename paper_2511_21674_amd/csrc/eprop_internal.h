@@ -131,7 +131,12 @@ struct Shapes {
   uint32_t tile_block;          // threads per block of the tiled forward kernel
   uint32_t syn_block;           // threads per block of the synapse kernel
   uint32_t ginst;               // trials per block of the synapse kernel
+  uint32_t fwd_variant;         // delivery variant of the forward kernel (piece size, pieces in flight)
+  uint32_t adj_block;           // threads per block of the adjoint kernel (64, 128 or 256)
 };
+uint32_t fwd_variant_piece(uint32_t v);
+uint32_t fwd_variant_unroll(uint32_t v);
+constexpr uint32_t kNumFwdVariants = 4;
 
 template <typename real>
 struct Launch {
@@ -141,13 +146,13 @@ struct Launch {
   // deterministic per-step neuron update with gather delivery at step ctl[T0] + off
   static void neuron_gather(const DevNet<real> &n, uint32_t off, bool forced, hipStream_t s);
   // persistent tiled forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps
-  static void forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t block,
+  static void forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, const Shapes &sh,
                             size_t smem, hipStream_t s);
   static size_t tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes);
   static hipError_t allow_smem(size_t smem, uint32_t ring_bytes);
   static hipError_t resident(uint32_t block, size_t smem, uint32_t ring_bytes, int *per_cu);
   static void readout(const DevNet<real> &n, hipStream_t s);
-  static void adjoint(const DevNet<real> &n, hipStream_t s);
+  static void adjoint(const DevNet<real> &n, const Shapes &sh, hipStream_t s);
   static void synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *partial, hipStream_t s);
   static void output_reduce(const DevNet<real> &n, hipStream_t s);
   static void apply(const DevNet<real> &n, uint64_t n_syn, double n_trials, int optimizer, double eta,

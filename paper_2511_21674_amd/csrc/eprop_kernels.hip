@@ -284,25 +284,21 @@ __device__ inline double ring_value(double x, const RingScale &) { return x; }
 // trial b into this tile's LDS ring.  Per chunk of up to blockDim spiking
 // sources: every thread resolves one source to its segment (the part of its
 // target-sorted row inside this tile); segments are cut into pieces of
-// kPiece synapses, numbered by a block scan, and each source records itself
-// as the owner of its pieces.  A group of kPiece consecutive lanes then
+// P synapses, numbered by a block scan, and each source records itself
+// as the owner of its pieces.  A group of P consecutive lanes then
 // takes one piece, one synapse record per lane, so that a wavefront's load
-// covers a few contiguous lines; each group keeps kUnroll pieces in flight
+// covers a few contiguous lines; each group keeps U pieces in flight
 // before adding the weights into the ring slots of their arrivals (only
 // arrivals within the trial).  dlo, dlen, dpre: LDS [blockDim]; owner: LDS
 // [kOwner]; wsum: LDS [17].
-#ifndef EPROP_PIECE
-#define EPROP_PIECE 8
-#endif
-#ifndef EPROP_UNROLL
-#define EPROP_UNROLL 8
-#endif
-constexpr uint32_t kPiece = EPROP_PIECE;
-constexpr uint32_t kUnroll = EPROP_UNROLL;
+// [P, U] of the delivery variants the autotuner chooses from; variant 0 is
+// the default.
 constexpr uint32_t kOwner = 4096;
-static_assert(kPiece == 4 || kPiece == 8 || kPiece == 16 || kPiece == 32 || kPiece == 64, "piece = lanes per group");
+constexpr uint32_t kFwdVariants = 4;
+__host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 1 ? 16u : v == 2 ? 4u : v == 3 ? 16u : 8u; }
+__host__ __device__ constexpr uint32_t fwd_unroll(uint32_t v) { return v == 1 ? 4u : v == 2 ? 16u : 8u; }
 
-template <typename real, typename ring_t>
+template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
                                     uint32_t *dlo, uint32_t *dlen, uint32_t *dpre, uint16_t *owner,
@@ -401,8 +397,9 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 // and count), then delivery of all tiles' spikes of the step into the
 // tile's ring, reading each tile's list as soon as its tag shows up.  The
 // KT workgroups of a trial must be resident together (checked on the host).
-template <typename real, typename ring_t, bool FORCED>
+template <typename real, typename ring_t, bool FORCED, uint32_t VAR>
 __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps) {
+  constexpr uint32_t P = fwd_piece(VAR), U = fwd_unroll(VAR);
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t KT = n.KT, TS = n.TS;
   const uint32_t b = blockIdx.x / KT, k = blockIdx.x - b * KT;
@@ -438,7 +435,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile(n, b, k, j0, 0, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
+    deliver_tile<real, ring_t, P, U>(n, b, k, j0, 0, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
   const uint32_t t_end = min(t0 + nsteps, Tb);
@@ -488,7 +485,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       __syncthreads();
       if (threadIdx.x == 0) store_sys(&n.pub_cnt[((size_t)b * 2 + (t & 1u)) * KT + k], tag | gtot);
     }
-    if (t < Tb) deliver_tile(n, b, k, j0, t, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
+    if (t < Tb) deliver_tile<real, ring_t, P, U>(n, b, k, j0, t, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -1068,47 +1065,75 @@ size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes) {
          kOwner * 2 + TS + 64;
 }
 
-// The forward kernel of a precision and ring element.
+// The forward kernels of a precision and ring element, one per delivery variant.
 template <typename real, typename ring_t>
 struct FwdKernels {
-  static const void *get(bool forced) {
-    return forced ? reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, true>)
-                  : reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, false>);
+  template <bool F>
+  static const void *get_v(uint32_t v) {
+    switch (v) {
+      case 1: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 1>);
+      case 2: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 2>);
+      case 3: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 3>);
+      default: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 0>);
+    }
   }
-  static void launch(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t grid, uint32_t block, size_t smem,
-                     hipStream_t s) {
-    if (forced) k_forward_tiled<real, ring_t, true><<<grid, block, smem, s>>>(n, nsteps);
-    else k_forward_tiled<real, ring_t, false><<<grid, block, smem, s>>>(n, nsteps);
+  static const void *get(bool forced, uint32_t v) { return forced ? get_v<true>(v) : get_v<false>(v); }
+  template <bool F>
+  static void launch_v(const DevNet<real> &n, uint32_t nsteps, uint32_t v, uint32_t grid, uint32_t block,
+                       size_t smem, hipStream_t s) {
+    switch (v) {
+      case 1: k_forward_tiled<real, ring_t, F, 1><<<grid, block, smem, s>>>(n, nsteps); break;
+      case 2: k_forward_tiled<real, ring_t, F, 2><<<grid, block, smem, s>>>(n, nsteps); break;
+      case 3: k_forward_tiled<real, ring_t, F, 3><<<grid, block, smem, s>>>(n, nsteps); break;
+      default: k_forward_tiled<real, ring_t, F, 0><<<grid, block, smem, s>>>(n, nsteps); break;
+    }
+  }
+  static void launch(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t v, uint32_t grid, uint32_t block,
+                     size_t smem, hipStream_t s) {
+    if (forced) launch_v<true>(n, nsteps, v, grid, block, smem, s);
+    else launch_v<false>(n, nsteps, v, grid, block, smem, s);
   }
 };
 
 template <typename real>
-const void *fwd_kernel(uint32_t ring_bytes, bool forced) {
-  if constexpr (sizeof(real) == 8) return FwdKernels<double, double>::get(forced);
-  else return ring_bytes == 8 ? FwdKernels<float, int64_t>::get(forced) : FwdKernels<float, int32_t>::get(forced);
+const void *fwd_kernel(uint32_t ring_bytes, bool forced, uint32_t v) {
+  if constexpr (sizeof(real) == 8) return FwdKernels<double, double>::get(forced, v);
+  else return ring_bytes == 8 ? FwdKernels<float, int64_t>::get(forced, v) : FwdKernels<float, int32_t>::get(forced, v);
 }
 
 template <typename real>
 hipError_t Launch<real>::allow_smem(size_t smem, uint32_t ring_bytes) {
-  hipError_t e = hipFuncSetAttribute(fwd_kernel<real>(ring_bytes, false), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)smem);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(fwd_kernel<real>(ring_bytes, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  hipError_t e = hipSuccess;
+  for (uint32_t v = 0; v < kFwdVariants && e == hipSuccess; ++v)
+    for (int f = 0; f < 2 && e == hipSuccess; ++f)
+      e = hipFuncSetAttribute(fwd_kernel<real>(ring_bytes, f == 1, v), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)smem);
   return e;
 }
 
 template <typename real>
 hipError_t Launch<real>::resident(uint32_t block, size_t smem, uint32_t ring_bytes, int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fwd_kernel<real>(ring_bytes, false), (int)block, smem);
+  // the variant with the fewest resident workgroups decides
+  int best = 1 << 30;
+  for (uint32_t v = 0; v < kFwdVariants; ++v) {
+    int pc = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, fwd_kernel<real>(ring_bytes, false, v), (int)block, smem);
+    if (e != hipSuccess) return e;
+    best = pc < best ? pc : best;
+  }
+  *per_cu = best;
+  return hipSuccess;
 }
 
 template <typename real>
-void Launch<real>::forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t block, size_t smem,
+void Launch<real>::forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, const Shapes &sh, size_t smem,
                                  hipStream_t s) {
   const uint32_t grid = n.Bcap * n.KT;
-  if constexpr (sizeof(real) == 8) FwdKernels<double, double>::launch(n, nsteps, forced, grid, block, smem, s);
-  else if (n.ring_bytes == 8) FwdKernels<float, int64_t>::launch(n, nsteps, forced, grid, block, smem, s);
-  else FwdKernels<float, int32_t>::launch(n, nsteps, forced, grid, block, smem, s);
+  const uint32_t v = sh.fwd_variant < kFwdVariants ? sh.fwd_variant : 0u;
+  if constexpr (sizeof(real) == 8) FwdKernels<double, double>::launch(n, nsteps, forced, v, grid, sh.tile_block, smem, s);
+  else if (n.ring_bytes == 8) FwdKernels<float, int64_t>::launch(n, nsteps, forced, v, grid, sh.tile_block, smem, s);
+  else FwdKernels<float, int32_t>::launch(n, nsteps, forced, v, grid, sh.tile_block, smem, s);
 }
 
 template <typename real>
@@ -1118,8 +1143,8 @@ void Launch<real>::readout(const DevNet<real> &n, hipStream_t s) {
 }
 
 template <typename real>
-void Launch<real>::adjoint(const DevNet<real> &n, hipStream_t s) {
-  const uint32_t bd = n.K > 16 ? 64 : 256;
+void Launch<real>::adjoint(const DevNet<real> &n, const Shapes &sh, hipStream_t s) {
+  const uint32_t bd = sh.adj_block;
   const size_t smem = (size_t)n.K * bd * 8 + 16 * (size_t)n.K * 8 + (size_t)bd * 17 * sizeof(real);
   k_adjoint<real><<<dim3(n.Jp / bd + (n.Jp % bd ? 1 : 0), n.Bcap), bd, smem, s>>>(n);
 }
@@ -1155,6 +1180,10 @@ void Launch<real>::input_bound(const DevNet<real> &n, hipStream_t s) {
 }
 
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s) { k_advance<<<1, 64, 0, s>>>(ctl, by); }
+
+uint32_t fwd_variant_piece(uint32_t v) { return fwd_piece(v); }
+uint32_t fwd_variant_unroll(uint32_t v) { return fwd_unroll(v); }
+static_assert(kNumFwdVariants == kFwdVariants, "variant count");
 
 template struct Launch<float>;
 template struct Launch<double>;

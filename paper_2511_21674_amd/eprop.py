@@ -23,7 +23,7 @@ EPROP_ERR_DEVICE, EPROP_ERR_STATE, EPROP_ERR_CAPACITY = -3, -4, -5
 EPROP_ERR_NUMERIC, EPROP_ERR_UNSUPPORTED = -6, -7
 EPROP_FP32, EPROP_FP64 = 0, 1
 EPROP_DELIVERY_AUTO, EPROP_DELIVERY_SCATTER, EPROP_DELIVERY_GATHER = 0, 1, 2
-EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS = 1, 2, 4
+EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS, EPROP_AUTOTUNE = 1, 2, 4, 8
 EPROP_MEM_HOST, EPROP_MEM_DEVICE = 0, 1
 EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE, EPROP_RECORD_SPIKES, EPROP_RECORD_TRACES = 1, 2, 4, 8
 EPROP_TRAIN = EPROP_BATCH_TRAIN
@@ -210,7 +210,7 @@ class Network:
 
     def __init__(self, wnet, precision: str = "fp32", max_trials: int = 1, max_steps: int = 1000,
                  delivery: str = "auto", graph: bool = True, stream=None, max_delay: int = None,
-                 torch_alloc: bool = False, deterministic: bool = False):
+                 torch_alloc: bool = False, deterministic: bool = False, autotune: bool = False):
         p = wnet.params
         self.wnet = wnet
         self._keep = []
@@ -226,7 +226,8 @@ class Network:
                            adam_beta2=p.adam_beta2, adam_eps_hat=p.adam_eps_hat, max_delay=md,
                            max_trials=max_trials, max_steps=max_steps,
                            delivery={"auto": 0, "scatter": 1, "gather": 2}[delivery],
-                           flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0))
+                           flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0)
+                           | (EPROP_AUTOTUNE if autotune else 0))
         self.allocator = TorchAllocator() if torch_alloc else None
         if self.allocator is not None:
             cfg.dev_alloc, cfg.dev_free = self.allocator.alloc_fn, self.allocator.free_fn
@@ -317,7 +318,7 @@ class Network:
             self._check(st)
             return buf[:need // 4].reshape(-1, 2)
         if what == EPROP_STATE_LAYOUT:
-            buf = np.zeros(8, np.uint64)
+            buf = np.zeros(12, np.uint64)
             self._check(eprop_read_state(self.h, what, trial, _ptr(buf), buf.nbytes)[0])
             return buf
         if what == EPROP_STATE_ADAM_STEP:
@@ -332,7 +333,8 @@ class Network:
     def layout(self) -> dict:
         v = [int(x) for x in self.read(EPROP_STATE_LAYOUT)]
         return dict(zip(("tile_neurons", "tiles", "ring_bytes", "tile_threads", "synapse_threads",
-                         "synapse_trials", "steps_per_launch", "gather"), v))
+                         "synapse_trials", "steps_per_launch", "gather", "piece", "pieces_in_flight",
+                         "adjoint_threads", "autotuned"), v))
 
     def weights(self) -> dict:
         return {"w_in": self.read(EPROP_STATE_W_IN), "w_rec": self.read(EPROP_STATE_W_REC),

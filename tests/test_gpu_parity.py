@@ -449,3 +449,31 @@ def test_fp32_multi_tile_runs_are_deterministic():
         assert np.array_equal(runs[0][2][i], runs[1][2][i])
     for k in KEYS:
         assert np.array_equal(runs[0][1][k], runs[1][1][k])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_autotuner_changes_shapes_not_results(precision):
+    """With EPROP_AUTOTUNE the first training batch times the candidate
+    launch shapes and keeps the fastest; two training iterations give the
+    same losses and weights, bit for bit, as the default shapes."""
+    wl = W.c4_sparse(n_rec=3000, n_steps=300, batch_size=2, n_in=300)
+    out = []
+    for autotune in (False, True):
+        net = E.Network(wl.network, precision, max_trials=2, max_steps=300, autotune=autotune)
+        losses = []
+        for it in range(2):
+            r = net.simulate(wl.make_batch(it, 0, 2))
+            net.apply()
+            losses.append(r.loss.copy())
+        lay = net.layout()
+        out.append((losses, net.weights(), lay))
+        net.close()
+    lay = out[1][2]
+    log(f"{precision} tuned layout: {lay}")
+    assert out[0][2]["autotuned"] == 0 and lay["autotuned"] == 1
+    assert lay["piece"] in (4, 8, 16) and lay["adjoint_threads"] in (64, 128, 256)
+    assert lay["synapse_threads"] in (64, 128, 256)
+    for it in range(2):
+        assert np.array_equal(out[0][0][it], out[1][0][it])
+    for k in KEYS:
+        assert np.array_equal(out[0][1][k], out[1][1][k])
