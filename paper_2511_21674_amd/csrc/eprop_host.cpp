@@ -29,7 +29,7 @@ inline uint32_t round_up(uint32_t a, uint32_t m) { return (a + m - 1) / m * m; }
 
 struct eprop_network {
   eprop_config cfg{};
-  uint32_t I = 0, J = 0, K = 0, NS = 0, Jp = 0, Jw = 0, Iw = 0, R = 0, Tcap = 0, Tp = 0, Bcap = 0;
+  uint32_t I = 0, J = 0, K = 0, NS = 0, Jp = 0, Jw = 0, Iw = 0, R = 0, Tcap = 0, Tp = 0, Bcap = 0, Ts = 0;
   uint64_t S_in = 0, S_rec = 0, S = 0;
   bool fp64 = false, gather = false, adam = false, use_graph = true;
   uint32_t n_ref = 0;
@@ -191,7 +191,7 @@ template <typename real>
 bool alloc_state(eprop_network *n, DevNet<real> &d) {
   const size_t B = n->Bcap, T1 = (size_t)n->Tcap + 1, T2 = (size_t)n->Tcap + 2;
   d.I = n->I; d.J = n->J; d.K = n->K; d.NS = n->NS; d.Jp = n->Jp; d.Jw = n->Jw; d.Iw = n->Iw;
-  d.R = n->R; d.Tcap = n->Tcap; d.Tp = n->Tp; d.Bcap = n->Bcap;
+  d.R = n->R; d.Tcap = n->Tcap; d.Tp = n->Tp; d.Bcap = n->Bcap; d.Ts = n->Ts;
   d.Lc = round_up(n->Tcap, 8);
   d.spk_stride = (uint64_t)n->NS * d.Lc;
   d.S = n->S;
@@ -216,6 +216,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &p32, n->J + 1); d.tm_ptr = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_syn = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_perm = p32;
+  ok &= dalloc(n, &p32, (size_t)n->NS * n->R); d.outdeg = p32;
   ok &= dalloc(n, &d.tm_w, n->S);
   ok &= dalloc(n, &d.gs, n->S);
   ok &= dalloc(n, &d.gc, n->S);
@@ -307,6 +308,13 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
       rec[q].w = (real)sm_w[q];
     }
     cp((void *)d.sm, rec.data(), rec.size() * sizeof(rec[0]));
+  }
+  {
+    // out-degree of every source per delay, for the event counts
+    std::vector<uint32_t> od((size_t)n->NS * n->R, 0u);
+    for (uint32_t src = 0; src < n->NS; ++src)
+      for (uint32_t q = sm_ptr[src]; q < sm_ptr[src + 1]; ++q) od[(size_t)src * n->R + (sm_syn[q] >> 24)]++;
+    cp((void *)d.outdeg, od.data(), od.size() * 4);
   }
   cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
   cp((void *)d.tm_syn, tm_syn.data(), tm_syn.size() * 4);
@@ -523,10 +531,18 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   n->autotune_pending = (cfg->flags & EPROP_AUTOTUNE) != 0;
   {
     // synapse kernel: a block per (target, chunk of trials); the chunk's
-    // archive rows must fit 16 KB of LDS, and small networks with many
-    // trials use smaller chunks to fill the device
-    const size_t row = (size_t)n->Tp * (n->fp64 ? 8 : 4);
-    uint32_t g = (uint32_t)std::max<size_t>(1, 16384 / row);
+    // archive rows (Ts entries each, plus a zero tail of R) should fit 16 KB
+    // of LDS and must fit 64 KB; small networks with many trials use smaller
+    // chunks to fill the device
+    const size_t rs = n->fp64 ? 8 : 4;
+    n->Ts = round_up(n->Tcap + n->R, 4);
+    const size_t row = (size_t)n->Ts * rs;
+    if (row + (size_t)n->R * rs > 65536) {
+      g_create_error = "trials longer than the synapse kernel's LDS rows allow (max_steps too large)";
+      delete n;
+      return EPROP_ERR_UNSUPPORTED;
+    }
+    uint32_t g = (uint32_t)std::max<size_t>(1, (16384 - std::min<size_t>(16384, (size_t)n->R * rs)) / row);
     g = std::min<uint32_t>(std::min<uint32_t>(g, n->Bcap), 8);
     const uint64_t par = (uint64_t)n->Bcap * J / 4096;
     g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, par));

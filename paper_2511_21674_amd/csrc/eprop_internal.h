@@ -69,6 +69,7 @@ template <typename real>
 struct DevNet {
   // sizes
   uint32_t I, J, K, NS, Jp, Jw, Iw, R, Tcap, Tp, Bcap;
+  uint32_t Ts;                  // synapse kernel's LDS row per trial: Tcap + R rounded up to 4
   uint64_t spk_stride;          // per-slot size of spk_t (NS * Lc)
   uint32_t Lc;                  // spike-list capacity per source (Tcap rounded up to 8)
   uint64_t S;                   // synapses
@@ -100,7 +101,10 @@ struct DevNet {
   uint16_t *spk_t;
   // per-source spike table of a batch for the synapse kernel: record (c, i)
   // of trial chunk c and source i = 16-byte header of 8 uint16 spike counts,
-  // then the spike times of the chunk's trials, trial by trial
+  // then one uint16 per spike, the LDS index bi * Ts + t of spike time t of
+  // the chunk's trial bi, trial by trial, padded to a multiple of 8 with the
+  // index of a zero entry
+  const uint32_t *outdeg;       // [NS][R] out-degree of each source per delay (index 1..R-1)
   uint32_t *pk_off;             // [nchunk*NS + 1] record offset in 16-byte units, kNoRecord if empty
   uint32_t *pk_bsum;            // [scan blocks + 1]
   uint16_t *pk;                 // [pk_cap * 8]

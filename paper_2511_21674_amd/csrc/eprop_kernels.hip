@@ -797,93 +797,102 @@ __global__ __launch_bounds__(1024) void k_pack_scan_blocks(DevNet<real> n, uint3
   if (threadIdx.x == 0) n.pk_bsum[nblk] = carry;
 }
 
-// Final offsets, headers (counts of the chunk's trials) and spike times.
+// Final offsets, headers (counts of the chunk's trials) and the LDS indices
+// of the spikes.  Also counts, per source, the deliveries that arrive within
+// their trial and the (synapse, trial) pairs with at least one, from the
+// source's out-degree per delay.
 template <typename real>
 __global__ __launch_bounds__(256) void k_pack_fill(DevNet<real> n, uint32_t ginst, uint32_t N) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N) return;
-  const uint32_t local = n.pk_off[e];
-  if (local == kNoRecord) return;
-  const uint32_t off = local + n.pk_bsum[e / kScanItems];
-  n.pk_off[e] = off;
-  const uint32_t ntr = n.ctl[CTL_NTRIALS];
-  const uint32_t c = e / n.NS, i = e - c * n.NS;
-  const uint32_t b0 = c * ginst, nb = min(ginst, ntr - b0);
-  uint32_t h[4] = {0, 0, 0, 0};
-  uint16_t *dst = n.pk + (size_t)off * 8 + 8;
-  for (uint32_t bi = 0; bi < nb; ++bi) {
-    const uint32_t cnt = n.spk_cnt[(size_t)(b0 + bi) * n.NS + i];
-    h[bi >> 1] |= cnt << ((bi & 1u) * 16u);
-    const uint16_t *src = n.spk_t + (size_t)(b0 + bi) * n.spk_stride + (size_t)i * n.Lc;
-    for (uint32_t k = 0; k < cnt; ++k) dst[k] = src[k];
-    dst += cnt;
+  unsigned long long nev = 0, nfl = 0;
+  if (e < N && n.pk_off[e] != kNoRecord) {
+    const uint32_t off = n.pk_off[e] + n.pk_bsum[e / kScanItems];
+    n.pk_off[e] = off;
+    const uint32_t ntr = n.ctl[CTL_NTRIALS];
+    const uint32_t c = e / n.NS, i = e - c * n.NS;
+    const uint32_t b0 = c * ginst, nb = min(ginst, ntr - b0);
+    const uint32_t *od = n.outdeg + (size_t)i * n.R;
+    uint32_t h[4] = {0, 0, 0, 0};
+    uint16_t *dst = n.pk + (size_t)off * 8 + 8;
+    uint32_t tot = 0;
+    for (uint32_t bi = 0; bi < nb; ++bi) {
+      const uint32_t b = b0 + bi, T = n.T[b];
+      const uint32_t cnt = n.spk_cnt[(size_t)b * n.NS + i];
+      h[bi >> 1] |= cnt << ((bi & 1u) * 16u);
+      const uint16_t *src = n.spk_t + (size_t)b * n.spk_stride + (size_t)i * n.Lc;
+      for (uint32_t k = 0; k < cnt; ++k) dst[tot + k] = (uint16_t)(bi * n.Ts + src[k]);
+      tot += cnt;
+      if (cnt == 0) continue;
+      for (uint32_t d = 1; d < n.R; ++d) {
+        const uint32_t deg = od[d];
+        if (deg == 0 || src[0] + d > T) continue;
+        uint32_t m = cnt;  // spikes arriving by step T (times ascending)
+        while (m > 0 && src[m - 1] + d > T) --m;
+        nev += (unsigned long long)deg * m;
+        nfl += deg;
+      }
+    }
+    const uint16_t zero_slot = (uint16_t)(ginst * n.Ts);
+    for (uint32_t k = tot; k < (tot + 7u) / 8u * 8u; ++k) dst[k] = zero_slot;
+    reinterpret_cast<uint4 *>(n.pk)[off] = make_uint4(h[0], h[1], h[2], h[3]);
   }
-  reinterpret_cast<uint4 *>(n.pk)[off] = make_uint4(h[0], h[1], h[2], h[3]);
+  for (int o = 32; o > 0; o >>= 1) {
+    nev += __shfl_down(nev, o);
+    nfl += __shfl_down(nfl, o);
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    if (nev) atomicAdd(&n.evcnt[(blockIdx.x * 4 + (threadIdx.x >> 6)) & 63u], nev);
+    if (nfl) atomicAdd(&n.cnt[CNT_FLUSH], nfl);
+  }
 }
 
 // Event-driven synapse gradient, target-major.  Block (j, c) handles the
-// incoming synapses of target j for the trials of chunk c (at most 8); the
-// target's archive rows phi[b][j][.] of those trials are staged in LDS.  Each
-// lane takes a synapse, reads its source's record of the spike table (the
-// header and the first blocks of times issued together) and, for every
-// arrival a = s + D <= T_b of every trial, adds phi_j^a (Kahan).  With one
-// chunk the sum goes straight into the accumulator pair (gs, gc); otherwise
-// into partial[c][q] for a fixed-order reduction.
-constexpr uint32_t kPre = 5;  // blocks of 8 spike times loaded with the header
+// incoming synapses of target j for the trials of chunk c (at most 8).  The
+// target's archive rows phi[b][j][.] of those trials are staged in LDS, one
+// row of Ts entries per trial that holds phi^t for t = 1..T_b and zeros
+// after it (and a zero tail after the last row), so that an arrival
+// a = s + D beyond its trial reads a zero.  Each lane takes a synapse, reads
+// its source's record of the spike table (the header and the first blocks
+// of LDS indices issued together) and adds phl[index + D] for every element
+// (Kahan); padding elements index the zero tail.  With one chunk the sum
+// goes straight into the accumulator pair (gs, gc); otherwise into
+// partial[c][q] for a fixed-order reduction.
+constexpr uint32_t kPre = 5;  // blocks of 8 spike indices loaded with the header
 
 template <typename real>
-__device__ inline void add_block(uint4 v, uint32_t p0, uint32_t total, uint32_t D, const uint4 &h,
-                                 uint32_t &bi, uint32_t &bend, const uint32_t *sT, const real *phl, uint32_t Tp,
-                                 real &s, real &c, unsigned long long &nev, uint32_t &lastb,
-                                 unsigned long long &nfl) {
+__device__ inline void add_block(uint4 v, const real *base, real &s, real &c) {
   const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-  const uint64_t hlo = ((uint64_t)h.y << 32) | h.x, hhi = ((uint64_t)h.w << 32) | h.z;
 #pragma unroll
-  for (uint32_t e = 0; e < 8; ++e) {
-    const uint32_t p = p0 + e;
-    if (p >= total) return;
-    while (p >= bend) {
-      ++bi;
-      bend += (uint32_t)(((bi < 4 ? hlo : hhi) >> ((bi & 3u) * 16u)) & 0xFFFFu);
-    }
-    const uint32_t a = ((w4[e >> 1] >> ((e & 1u) * 16u)) & 0xFFFFu) + D;
-    if (a <= sT[bi]) {
-      kahan_add(s, c, phl[bi * Tp + a]);
-      ++nev;
-      if (bi != lastb) {  // first arrival of this trial: the synapse has a trial-end evaluation
-        lastb = bi;
-        ++nfl;
-      }
-    }
-  }
+  for (uint32_t e = 0; e < 8; ++e) kahan_add(s, c, base[(w4[e >> 1] >> ((e & 1u) * 16u)) & 0xFFFFu]);
 }
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst, uint32_t nchunk, real *partial) {
   constexpr uint32_t GB = 8;
   extern __shared__ __align__(16) unsigned char syn_smem[];
-  __shared__ uint32_t sT[GB];
-  real *phl = reinterpret_cast<real *>(syn_smem);   // [ginst][Tp]
+  real *phl = reinterpret_cast<real *>(syn_smem);   // [ginst][Ts] + zero tail [R]
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
   const uint32_t c = blockIdx.x % nchunk, j = blockIdx.x / nchunk;
   const uint32_t b0 = c * ginst, nb = min(min(ginst, ntr - b0), GB);
   const uint32_t tid = threadIdx.x;
-  if (tid < GB) sT[tid] = tid < nb ? n.T[b0 + tid] : 0u;
   for (uint32_t bi = 0; bi < nb; ++bi) {
     const real *src = n.phi + ((size_t)(b0 + bi) * n.Jp + j) * n.Tp;
-    real *dst = phl + bi * n.Tp;
-    const uint32_t T1 = n.T[b0 + bi] + 1;
-    for (uint32_t t = tid; t < T1; t += 4 * blockDim.x) {
+    real *dst = phl + bi * n.Ts;
+    const uint32_t T = n.T[b0 + bi];
+    for (uint32_t t = tid; t < n.Ts; t += 4 * blockDim.x) {
       real v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = t + u * blockDim.x < T1 ? src[t + u * blockDim.x] : (real)0;
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t tt = t + u * blockDim.x;
+        v[u] = (tt >= 1 && tt <= T) ? src[tt] : (real)0;
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (t + u * blockDim.x < T1) dst[t + u * blockDim.x] = v[u];
+        if (t + u * blockDim.x < n.Ts) dst[t + u * blockDim.x] = v[u];
     }
   }
+  for (uint32_t t = tid; t < n.R; t += blockDim.x) phl[ginst * n.Ts + t] = (real)0;
   __syncthreads();
-  unsigned long long nev = 0, nfl = 0;
   const uint4 *pk4 = reinterpret_cast<const uint4 *>(n.pk);
   const uint32_t *poff = n.pk_off + (size_t)c * n.NS;
   const uint32_t q1 = n.tm_ptr[j + 1];
@@ -901,12 +910,12 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
       const uint4 h = pre[0];
       const uint32_t total = (h.x & 0xFFFFu) + (h.x >> 16) + (h.y & 0xFFFFu) + (h.y >> 16) + (h.z & 0xFFFFu) +
                              (h.z >> 16) + (h.w & 0xFFFFu) + (h.w >> 16);
-      uint32_t bi = 0, bend = h.x & 0xFFFFu, lastb = 0xFFFFFFFFu;
+      const uint32_t nbk = (total + 7u) >> 3;
+      const real *base = phl + D;
 #pragma unroll
       for (uint32_t u = 0; u < kPre; ++u)
-        if (u * 8 < total) add_block(pre[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev, lastb, nfl);
-      for (uint32_t u = kPre; u * 8 < total; ++u)
-        add_block(rec[u + 1], u * 8, total, D, h, bi, bend, sT, phl, n.Tp, s, cc, nev, lastb, nfl);
+        if (u < nbk) add_block(pre[u + 1], base, s, cc);
+      for (uint32_t u = kPre; u < nbk; ++u) add_block(rec[u + 1], base, s, cc);
     }
     if (nchunk == 1) {
       real gs = n.gs[q], gc = n.gc[q];
@@ -918,12 +927,6 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
       partial[(size_t)c * n.S + q] = s + cc;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    nev += __shfl_down(nev, o);
-    nfl += __shfl_down(nfl, o);
-  }
-  if ((tid & 63u) == 0 && nev) atomicAdd(&n.evcnt[blockIdx.x & 63u], nev);
-  if ((tid & 63u) == 0 && nfl) atomicAdd(&n.cnt[CNT_FLUSH], nfl);
 }
 
 // Fixed-order reduction of the trial-chunk partial sums into (gs, gc).
@@ -1156,7 +1159,7 @@ void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_t
   k_pack_scan_local<real><<<nblk, 1024, 0, s>>>(n, sh.ginst, N);
   k_pack_scan_blocks<real><<<1, 1024, 0, s>>>(n, nblk);
   k_pack_fill<real><<<cdiv(N, 256), 256, 0, s>>>(n, sh.ginst, N);
-  const size_t smem = (size_t)sh.ginst * n.Tp * sizeof(real);
+  const size_t smem = ((size_t)sh.ginst * n.Ts + n.R) * sizeof(real);
   k_synapse<real><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial);
   if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
 }
