@@ -104,7 +104,7 @@ def stage_batches(wl, n, first_iteration):
     return out
 
 
-def run_staged(net, staged, train=True, profile=False):
+def run_staged(net, staged, train=True, profile=False, time_driven=False):
     """simulate_batch on device-resident arrays (no host copies)."""
     from paper_2511_21674_amd import eprop as E
     b, ptrs, _ = staged
@@ -116,7 +116,8 @@ def run_staged(net, staged, train=True, profile=False):
                           else int(b.window.shape[1]),
                           target=ptrs.get("target"), label=label.ctypes.data if label is not None else None,
                           window=ptrs.get("window"),
-                          flags=(E.EPROP_BATCH_TRAIN if train else 0) | (E.EPROP_BATCH_PROFILE if profile else 0))
+                          flags=(E.EPROP_BATCH_TRAIN if train else 0) | (E.EPROP_BATCH_PROFILE if profile else 0)
+                          | (E.EPROP_BATCH_TIME_DRIVEN if time_driven else 0))
     loss = np.zeros(b.n_trials)
     res = E.eprop_batch_result(loss=loss.ctypes.data, predicted=None)
     st = E.eprop_simulate_batch(net.h, batch, res)
@@ -209,6 +210,8 @@ def main():
     ap.add_argument("--workload", default="c4_sparse")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--time-driven", action="store_true",
+                    help="gradient by the time-driven baseline recursion instead of the event-driven path")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (the tuner otherwise runs in the first warm-up batch)")
     ap.add_argument("--cpu-steps", type=int, default=60)
@@ -255,7 +258,7 @@ def main():
         torch.cuda.synchronize()
         warm_losses = []
         for i in range(args.warmup):
-            _, wloss = run_staged(net, staged[i])
+            _, wloss = run_staged(net, staged[i], time_driven=args.time_driven)
             net.apply()
             warm_losses.append(float(wloss.mean()))
         torch.cuda.synchronize()
@@ -264,7 +267,7 @@ def main():
         losses = []
         t0 = time.perf_counter()
         for i in range(args.steps):
-            res, loss = run_staged(net, staged[args.warmup + i], profile=True)
+            res, loss = run_staged(net, staged[args.warmup + i], profile=True, time_driven=args.time_driven)
             net.apply()
             tot["events"] += res.n_syn_events
             tot["updates"] += res.n_eprop_updates
@@ -340,7 +343,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": f"{wl.name}: {wl.description}", "n_rec": net_w.n_rec, "n_in": net_w.n_in,
                       "n_out": net_w.n_out, "synapses": int(net_w.in_rec.nnz + net_w.rec_rec.nnz),
-                      "trials_per_batch": n_tr, "steps_per_trial": T, "delivery": "scatter (LDS tiles)"},
+                      "trials_per_batch": n_tr, "steps_per_trial": T, "delivery": "scatter (LDS tiles)",
+                      "gradient": "time-driven baseline" if args.time_driven else "event-driven"},
            "eprop_updates_per_s": tot["updates"] / elapsed,
            "recurrent_rate_hz": rate_hz,
            "phase_ms_per_step": {k: round(v / steps, 3) for k, v in phases.items()},

@@ -187,6 +187,11 @@ typedef enum { EPROP_MEM_HOST = 0, EPROP_MEM_DEVICE = 1 } eprop_memory;
 #define EPROP_BATCH_PROFILE (1u << 1)  /* time each phase with HIP events (phase_ms) */
 #define EPROP_RECORD_SPIKES (1u << 2)  /* keep the batch's spikes for eprop_read_state (always kept) */
 #define EPROP_RECORD_TRACES (1u << 3)  /* keep psi, y, E, L, v for eprop_read_state (always kept) */
+#define EPROP_BATCH_TIME_DRIVEN (1u << 4)  /* with TRAIN: the gradient by the time-driven recursion of
+                                              Alg. "time-driven gradient computation" (every synapse,
+                                              every step) instead of the event-driven path; the same
+                                              result, kept as the baseline the event-driven path is
+                                              measured against */
 
 /* A batch of independent trials (samples) of uneven lengths, simulated
  * together from zero state with the current weights (Results, "Evidence

@@ -45,6 +45,8 @@ struct eprop_network {
   std::vector<uint32_t> sm2caller;  // internal source-major index -> caller's synapse index
   size_t tile_smem = 0;             // dynamic LDS of the tiled forward kernel
   void *partial = nullptr;          // per trial-chunk synapse sums (large batches)
+  void *Lbuf = nullptr;             // learning signal of the time-driven baseline (allocated on first use)
+  size_t cap_Lbuf = 0;
   uint32_t trials_accum = 0;
   uint64_t adam_step = 0;
   // library-owned staging copies of host-memory batches
@@ -677,6 +679,9 @@ eprop_status check_batch(eprop_network *n, const eprop_batch *b, std::vector<uin
   if (b->n_trials < 1) return bad("n_trials must be >= 1");
   if (b->n_trials > n->Bcap) { msg = "n_trials exceeds max_trials"; return EPROP_ERR_CAPACITY; }
   if (b->memory != EPROP_MEM_HOST && b->memory != EPROP_MEM_DEVICE) return bad("unknown memory kind");
+  if (b->flags & ~(uint32_t)(EPROP_BATCH_TRAIN | EPROP_BATCH_PROFILE | EPROP_RECORD_SPIKES | EPROP_RECORD_TRACES |
+                             EPROP_BATCH_TIME_DRIVEN))
+    return bad("unknown batch flag");
   if (!b->n_steps) return bad("NULL n_steps");
   t_max = 0;
   for (uint32_t i = 0; i < b->n_trials; ++i) {
@@ -797,6 +802,16 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   const bool forced = b->forced_ptr != nullptr;
   const bool train = (b->flags & EPROP_BATCH_TRAIN) != 0;
   const bool prof = (b->flags & EPROP_BATCH_PROFILE) != 0;
+  const bool time_driven = train && (b->flags & EPROP_BATCH_TIME_DRIVEN) != 0;
+  if (time_driven) {
+    const size_t need = (size_t)n->Bcap * (n->Tcap + 1) * n->Jp * sizeof(real);
+    uint8_t *lb = static_cast<uint8_t *>(n->Lbuf);
+    if (!dgrow(n, &lb, &n->cap_Lbuf, need)) {
+      set_fail(n, "out of device memory for the time-driven learning signal");
+      return EPROP_ERR_OUT_OF_MEMORY;
+    }
+    n->Lbuf = lb;
+  }
   hipStream_t s = n->stream;
   hipError_t e = hipSuccess;
   auto H2D = [&](void *dst, const void *src, size_t bytes) {
@@ -924,7 +939,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     }
     return best;
   };
-  const bool tune = n->autotune_pending && train;
+  const bool tune = n->autotune_pending && train && !time_driven;
 
   (void)hipEventRecord(n->ev[0], s);
   // upload
@@ -987,7 +1002,13 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   if (prof) (void)hipEventRecord(n->ev[2], s);
   Launch<real>::readout(d, s);
   if (prof) (void)hipEventRecord(n->ev[3], s);
-  if (train) {
+  if (time_driven) {
+    Launch<real>::time_driven(d, n->shapes, ntr, static_cast<real *>(n->Lbuf), static_cast<real *>(n->partial), s);
+    if (prof) (void)hipEventRecord(n->ev[4], s);
+    if (prof) (void)hipEventRecord(n->ev[5], s);
+    Launch<real>::output_reduce(d, s);
+    if (prof) (void)hipEventRecord(n->ev[6], s);
+  } else if (train) {
     if (tune) {
       // part 2: threads per block of the adjoint kernel (idempotent)
       float best = 1e30f;

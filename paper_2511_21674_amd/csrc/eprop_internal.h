@@ -161,6 +161,9 @@ struct Launch {
   static void output_reduce(const DevNet<real> &n, hipStream_t s);
   static void apply(const DevNet<real> &n, uint64_t n_syn, double n_trials, int optimizer, double eta,
                     double eta_t, double b1, double b2, double eps_hat, hipStream_t s);
+  // the gradient of the batch by the time-driven recursion (baseline); L: [Bcap][Tcap+1][Jp]
+  static void time_driven(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *L, real *partial,
+                          hipStream_t s);
   // recomputes *l1max from the current weights (after upload and every update)
   static void input_bound(const DevNet<real> &n, hipStream_t s);
 };

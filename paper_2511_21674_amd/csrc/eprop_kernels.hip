@@ -929,6 +929,129 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
   }
 }
 
+// ---------------------------------------------------- time-driven baseline
+// The gradient of Alg. 1 ("time-driven gradient computation"), evaluated
+// the way a time-driven simulator does it: every synapse, every step.  Kept
+// as the baseline the event-driven path is measured against; same inputs
+// (spike bitsets, psi archive, error signal) and the same accumulators.
+
+// L_j^t = sum_k B_jk E_k^t (eq. final-gradient), FP64 sum, stored per
+// (trial, step, neuron).
+template <typename real>
+__global__ __launch_bounds__(256) void k_learning_signal(DevNet<real> n, real *L) {
+  const uint32_t ntr = n.ctl[CTL_NTRIALS];
+  const uint64_t per = (uint64_t)(n.Tcap + 1) * n.Jp;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)ntr * per;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = (uint32_t)(i / per);
+    const uint32_t t = (uint32_t)((i % per) / n.Jp), j = (uint32_t)(i % n.Jp);
+    double acc = 0.0;
+    if (j < n.J && t >= 1 && t <= n.T[b]) {
+      const double *E = n.err + ((size_t)b * (n.Tcap + 2) + t) * n.K;
+      for (uint32_t k = 0; k < n.K; ++k) acc += (double)n.fb[(size_t)j * n.K + k] * E[k];
+    }
+    L[i] = (real)acc;
+  }
+}
+
+// One thread per (synapse q, trial chunk c): the eligibility recursion of
+// eq. eligibility-vector-substituted and eq. filtered-eligibility-trace over
+// every step of each trial of the chunk, g += L^t ebar^t (Kahan).  The
+// arrival indicator x^t is the source's spike bit at step t - D.
+template <typename real>
+__global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *L, uint32_t ginst, uint32_t nchunk,
+                                                    real *partial) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long nev = 0, nfl = 0;
+  if (gid < n.S * nchunk) {
+    const uint32_t c = (uint32_t)(gid / n.S);
+    const uint64_t q = gid - (uint64_t)c * n.S;
+    uint32_t lo = 0, hi = n.J;  // target of q: tm_ptr[lo] <= q < tm_ptr[lo + 1]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (n.tm_ptr[mid] <= q) lo = mid; else hi = mid;
+    }
+    const uint32_t j = lo;
+    const uint32_t pk = n.tm_syn[q];
+    const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
+    const bool is_in = src < n.I;
+    const uint32_t si = is_in ? src : src - n.I;
+    const real beta = n.beta_j[j];
+    const real kappa = (real)n.kappa_d;
+    const uint32_t ntr = n.ctl[CTL_NTRIALS];
+    const uint32_t b0 = c * ginst, nb = b0 < ntr ? min(ginst, ntr - b0) : 0u;
+    real s = 0, cc = 0;
+    for (uint32_t bi = 0; bi < nb; ++bi) {
+      const uint32_t b = b0 + bi, T = n.T[b];
+      const real *ps = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
+      const real *Lb = L + (size_t)b * (n.Tcap + 1) * n.Jp + j;
+      real ev = 0, ea = 0, eb = 0, psi_prev = 0;
+      uint32_t arrivals = 0;
+      for (uint32_t t = 1; t <= T; ++t) {
+        uint32_t x = 0;
+        if (t >= D) {
+          const uint32_t se = t - D;  // emission step
+          if (is_in) {
+            x = (uint32_t)(n.in_bits[((size_t)b * n.Tcap + se) * n.Iw + (si >> 6)] >> (si & 63u)) & 1u;
+          } else if (se >= 1) {
+            x = (uint32_t)(n.rec_bits[((size_t)b * (n.Tcap + 1) + se) * n.Jw + (si >> 6)] >> (si & 63u)) & 1u;
+          }
+        }
+        arrivals += x;
+        const real psi_now = ps[(size_t)t * n.Jp];
+        const real ea_new = psi_prev * ev + (n.rho - psi_prev * beta) * ea;
+        const real ev_new = n.alpha * ev + (real)x;
+        eb = kappa * eb + psi_now * (ev_new - beta * ea_new);
+        ev = ev_new;
+        ea = ea_new;
+        psi_prev = psi_now;
+        kahan_add(s, cc, Lb[(size_t)t * n.Jp] * eb);
+      }
+      nev += arrivals;
+      nfl += arrivals ? 1u : 0u;
+    }
+    if (nchunk == 1) {
+      real gs = n.gs[q], gc = n.gc[q];
+      kahan_add(gs, gc, s);
+      kahan_add(gs, gc, cc);
+      n.gs[q] = gs;
+      n.gc[q] = gc;
+    } else {
+      partial[(size_t)c * n.S + q] = s + cc;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    nev += __shfl_down(nev, o);
+    nfl += __shfl_down(nfl, o);
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    if (nev) atomicAdd(&n.evcnt[(blockIdx.x * 4 + (threadIdx.x >> 6)) & 63u], nev);
+    if (nfl) atomicAdd(&n.cnt[CNT_FLUSH], nfl);
+  }
+}
+
+// Output synapses, time-driven: zbar = F_kappa(z_j), g_kj += E_k^t zbar^t,
+// one thread per (trial, readout, neuron), FP64 sum.
+template <typename real>
+__global__ __launch_bounds__(256) void k_td_output(DevNet<real> n) {
+  const uint32_t ntr = n.ctl[CTL_NTRIALS];
+  const uint64_t per = (uint64_t)n.K * n.Jp;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)ntr * per;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = (uint32_t)(i / per), k = (uint32_t)((i % per) / n.Jp), j = (uint32_t)(i % n.Jp);
+    double zb = 0.0, g = 0.0;
+    if (j < n.J) {
+      const uint32_t T = n.T[b];
+      for (uint32_t t = 1; t <= T; ++t) {
+        const uint32_t z = (uint32_t)(n.rec_bits[((size_t)b * (n.Tcap + 1) + t) * n.Jw + (j >> 6)] >> (j & 63u)) & 1u;
+        zb = n.kappa_d * zb + (double)z;
+        g += n.err[((size_t)b * (n.Tcap + 2) + t) * n.K + k] * zb;
+      }
+    }
+    n.gout_b[i] = (real)g;
+  }
+}
+
 // Fixed-order reduction of the trial-chunk partial sums into (gs, gc).
 template <typename real>
 __global__ __launch_bounds__(256) void k_synapse_reduce(DevNet<real> n, uint32_t nchunk, const real *partial) {
@@ -1162,6 +1285,17 @@ void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_t
   const size_t smem = ((size_t)sh.ginst * n.Ts + n.R) * sizeof(real);
   k_synapse<real><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial);
   if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
+}
+
+template <typename real>
+void Launch<real>::time_driven(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *L, real *partial,
+                               hipStream_t s) {
+  const uint32_t nchunk = (n_trials + sh.ginst - 1) / sh.ginst;
+  k_learning_signal<real><<<grid_for((uint64_t)n_trials * (n.Tcap + 1) * n.Jp, 256, 16384), 256, 0, s>>>(n, L);
+  if (n.S > 0)
+    k_td_synapse<real><<<cdiv(n.S * nchunk, 256), 256, 0, s>>>(n, L, sh.ginst, nchunk, partial);
+  if (nchunk > 1 && n.S > 0) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
+  k_td_output<real><<<grid_for((uint64_t)n_trials * n.K * n.Jp, 256, 16384), 256, 0, s>>>(n);
 }
 
 template <typename real>

@@ -26,6 +26,7 @@ EPROP_DELIVERY_AUTO, EPROP_DELIVERY_SCATTER, EPROP_DELIVERY_GATHER = 0, 1, 2
 EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS, EPROP_AUTOTUNE = 1, 2, 4, 8
 EPROP_MEM_HOST, EPROP_MEM_DEVICE = 0, 1
 EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE, EPROP_RECORD_SPIKES, EPROP_RECORD_TRACES = 1, 2, 4, 8
+EPROP_BATCH_TIME_DRIVEN = 16
 EPROP_TRAIN = EPROP_BATCH_TRAIN
 EPROP_N_PHASES = 8
 PHASES = ("stage", "forward", "readout", "adjoint", "synapse", "output")
@@ -265,9 +266,11 @@ class Network:
         if st != EPROP_OK:
             raise EpropError(st, eprop_last_error(self.h))
 
-    def simulate(self, batch, train: bool = True, device: bool = False, profile: bool = False) -> BatchResult:
+    def simulate(self, batch, train: bool = True, device: bool = False, profile: bool = False,
+                 time_driven: bool = False) -> BatchResult:
         """Runs one batch (a ``workloads.Batch``).  device=True places the
-        batch arrays in device memory (torch) before the call."""
+        batch arrays in device memory (torch) before the call; time_driven
+        computes the gradient by the time-driven baseline recursion."""
         ntr = batch.n_trials
         n_steps = _c(batch.n_steps, np.uint32)
         stride = int(n_steps.max())
@@ -296,7 +299,8 @@ class Network:
                         n_forced=int(batch.forced_ptr[-1]) if batch.forced_ptr is not None else 0,
                         forced_ptr=ptrs.get("forced_ptr"), forced_step=ptrs.get("forced_step"),
                         forced_neuron=ptrs.get("forced_neuron"),
-                        flags=(EPROP_BATCH_TRAIN if train else 0) | (EPROP_BATCH_PROFILE if profile else 0))
+                        flags=(EPROP_BATCH_TRAIN if train else 0) | (EPROP_BATCH_PROFILE if profile else 0)
+                        | (EPROP_BATCH_TIME_DRIVEN if time_driven else 0))
         loss = np.zeros(ntr)
         pred = np.zeros(ntr, np.uint32)
         res = eprop_batch_result(loss=_ptr(loss), predicted=_ptr(pred))

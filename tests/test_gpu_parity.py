@@ -477,3 +477,55 @@ def test_autotuner_changes_shapes_not_results(precision):
         assert np.array_equal(out[0][0][it], out[1][0][it])
     for k in KEYS:
         assert np.array_equal(out[0][1][k], out[1][1][k])
+
+
+# ----------------------------------------------------------------- time-driven baseline
+
+def _train_mode(wl, precision, iterations, bs, time_driven, forced_rate=None):
+    T = max(int(wl.make_batch(it, 0, bs).n_steps.max()) for it in range(iterations))
+    net = E.Network(wl.network, precision, max_trials=bs, max_steps=T)
+    out = []
+    for it in range(iterations):
+        b = wl.make_batch(it, 0, bs)
+        if forced_rate:
+            b = W.forced_poisson(b, wl.network.n_rec, forced_rate, wl.network.params.dt, seed=99,
+                                 iteration=it, n_ref=2)
+        r = net.simulate(b, train=True, time_driven=time_driven)
+        out.append((r, net.grads()))
+        net.apply()
+    net.close()
+    return out
+
+
+@pytest.mark.parametrize("name", ["tiny", "c2", "c4twin"])
+def test_time_driven_baseline_fp64_matches_oracle(name):
+    """FP64 time-driven GPU gradient (every synapse, every step) against the
+    oracle's time-driven mode: spike trains identical, gradients within
+    1e-10, event and trial-end counts equal to the event-driven path's."""
+    if name == "tiny":
+        wl, bs, it = W.tiny(), 2, 2
+    elif name == "c2":
+        wl, bs, it = W.c2_evidence(batch_size=3), 3, 2
+    else:
+        wl, bs, it = W.c4_sparse(n_rec=2000, n_steps=150, batch_size=2, n_in=300), 2, 1
+    td = _train_mode(wl, "fp64", it, bs, True)
+    ed = _train_mode(wl, "fp64", it, bs, False)
+    oh = oracle_train(wl, it, bs, grad_mode=1)
+    for i in range(it):
+        for k in KEYS:
+            ok, e, ent = rel_close(td[i][1][k], oh["grads"][i][k], 1e-10)
+            assert ok, (name, i, k, e, ent)
+        assert td[i][0].n_syn_events == ed[i][0].n_syn_events
+        assert td[i][0].n_flush_updates == ed[i][0].n_flush_updates
+        log(f"{name} it {i}: time-driven grads match the oracle, {td[i][0].n_syn_events} events")
+
+
+def test_time_driven_baseline_fp32_teacher_forced():
+    """FP32 time-driven gradient with the oracle's spike trains within 1e-4."""
+    wl = W.c3_events(batch_size=3)
+    td = _train_mode(wl, "fp32", 1, 3, True, forced_rate=20.0)
+    oh = oracle_train(wl, 1, 3, forced_rate=20.0, grad_mode=1)
+    for k in KEYS:
+        ok, e, ent = rel_close(td[0][1][k], oh["grads"][0][k], 1e-4, floor_frac=1e-2)
+        log(f"c3 time-driven fp32 {k}: normwise {e:.2e} worst {ent:.2e}")
+        assert ok, (k, e, ent)
