@@ -47,7 +47,8 @@ class _Net(C.Structure):
                 ("v_th", C.c_double), ("t_ref", C.c_double), ("tau_a", C.c_double),
                 ("beta_a", C.c_double), ("surrogate", C.c_int), ("sg_gamma", C.c_double),
                 ("sg_beta", C.c_double), ("loss", C.c_int), ("inp", _Proj), ("rec", _Proj),
-                ("w_out", C.c_void_p), ("fb", C.c_void_p)]
+                ("w_out", C.c_void_p), ("fb", C.c_void_p), ("d_out", C.c_int), ("d_ls", C.c_int),
+                ("c_reg", C.c_double), ("f_target", C.c_double)]
 
 
 class _Trial(C.Structure):
@@ -125,6 +126,9 @@ class OracleNet:
         s.rec = _Proj(self.n_rec, self.n_rec, int(self.rec_row[-1]), _p(self.rec_row),
                       _p(self.rec_col), _p(self.w_rec), _p(self.rec_delay))
         s.w_out, s.fb = _p(self.w_out), _p(self.fb)
+        s.d_out, s.d_ls = int(getattr(p, "d_out", 0)), int(getattr(p, "d_ls", 0))
+        # target rate in spikes per step (the rate of eq. loss-firing-rate-regularization)
+        s.c_reg, s.f_target = float(getattr(p, "c_reg", 0.0)), float(getattr(p, "f_target_hz", 0.0)) * p.dt / 1000.0
         return s
 
 

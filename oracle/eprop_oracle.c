@@ -170,22 +170,22 @@ static int neuron_step(const orc_net *net, const prep_t *p, int j, double I, dou
   return z;
 }
 
-/* One step of a synapse's e-prop recursion (eq. eligibility-vector-substituted,
- * eq. filtered-eligibility-trace, eq. final-gradient):
+/* One step of a synapse's eligibility (eq. eligibility-vector-substituted,
+ * eq. filtered-eligibility-trace):
  *   eps_a^t = psi^{t-1} eps_v^{t-1} + (rho - psi^{t-1} beta) eps_a^{t-1}
  *   eps_v^t = alpha eps_v^{t-1} + x^t                   (F_alpha of the arrivals)
  *   e^t     = psi^t (eps_v^t - beta eps_a^t)
  *   ebar^t  = kappa ebar^{t-1} + e^t                    (F_kappa)
- *   g      += L^t ebar^t                                                       */
-static void syn_step(const prep_t *p, double x, double psi_prev, double psi_now, double beta,
-                     double L, double *ev, double *ea, double *eb, double *g) {
+ * Returns e^t; the caller pairs ebar^t with the learning signal. */
+static double syn_trace(const prep_t *p, double x, double psi_prev, double psi_now, double beta, double *ev,
+                        double *ea, double *eb) {
   const double ea_new = psi_prev * *ev + (p->rho - psi_prev * beta) * *ea;
   const double ev_new = p->alpha * *ev + x;
   const double e = psi_now * (ev_new - beta * ea_new);
   *eb = p->kappa * *eb + e;
   *ev = ev_new;
   *ea = ea_new;
-  *g += L * *eb;
+  return e;
 }
 
 /* Readout (eq. leaky_integrator), error signal and loss (eq. mean-squared-error
@@ -197,7 +197,7 @@ static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
     for (int j = 0; j < J; ++j)
-      if (sp->zrec[(long)t * J + j]) s = s + net->w_out[(long)k * J + j];
+      if (t - net->d_out >= 1 && sp->zrec[(long)(t - net->d_out) * J + j]) s = s + net->w_out[(long)k * J + j];
     y[k] = p->kappa * y[k] + s;
   }
   const int win = tr->window ? tr->window[t - 1] : 1;
@@ -256,8 +256,13 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
   double *zb = calloc(J, sizeof(double));
   int *apr_o = calloc(J, sizeof(int));
   int *q_src = calloc(ns + 1, sizeof(int));   /* source of each synapse */
+  /* time-driven FIFOs of depth d + 1 (eligibility, filtered eligibility, zbar) */
+  const int dq1 = net->d_out + 1;
+  double *fifo_e = calloc((size_t)(ns + 1) * dq1, sizeof(double)), *fifo_eb = calloc((size_t)(ns + 1) * dq1, sizeof(double));
+  double *fifo_z = calloc((size_t)J * dq1, sizeof(double));
+  double *esum = calloc(ns + 1, sizeof(double)), *creg = calloc(J, sizeof(double));
   if (!v || !a || !refr || !y || !E || !psum || !psi_h || !L_h || !E_h || !ev || !ea || !eb ||
-      !apr || !zb || !apr_o || !q_src)
+      !apr || !zb || !apr_o || !q_src || !fifo_e || !fifo_eb || !fifo_z || !esum || !creg)
     goto done;
   for (int i = 0; i < net->in.n_src; ++i)
     for (unsigned long r = net->in.row_ptr[i]; r < net->in.row_ptr[i + 1]; ++r) q_src[r] = i;
@@ -305,70 +310,104 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
     }
 
     if (grad_mode == 1) {
-      /* Time-driven gradient computation: every synapse, every step. */
+      /* Time-driven gradient computation (Alg. "time-driven gradient
+       * computation"): every synapse, every step.  The eligibility of step t
+       * enters a FIFO of depth d; the one of step t - d leaves it and meets
+       * the learning signal L^t (eq. eprop-approx-final-expanded-subs-
+       * rewritten); with a learning-signal delay d^ls, L^t takes part only
+       * for t <= T - d^ls (eq. eprop-learning-signal-delay).  The static
+       * regularisation term needs the sample's rate and is added at its end
+       * from the sum of the dequeued eligibilities. */
+      const int dq = net->d_out;
+      const double Lon = t <= T - net->d_ls ? 1.0 : 0.0;
       for (long q = 0; q < ns; ++q) {
         const int j = SYN_TGT(q);
         const int kind = q < nin ? 0 : 1;
         const int D = q < nin ? net->in.delay[q] : net->rec.delay[q - nin];
         const double x = spiked(&sp, kind, q_src[q], t - D) ? 1.0 : 0.0;
-        syn_step(&p, x, psi_h[(long)(t - 1) * J + j], psi_h[(long)t * J + j], neuron_beta(net, j),
-                 L_h[(long)t * J + j], &ev[q], &ea[q], &eb[q], SYN_G(q));
-      }
-      /* output synapses: zbar = F_kappa(z_j), g_out += E_k zbar */
-      for (int j = 0; j < J; ++j) {
-        zb[j] = p.kappa * zb[j] + (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);
-        for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E[k] * zb[j];
-      }
-    } else if (grad_mode == 2) {
-      /* Event-driven update: a synapse whose presynaptic spike arrives at t
-       * walks the archived history over its previous interval
-       * [a_prev, t-1], with the arrival counted at the interval's first step. */
-      for (int D = 1; D <= p.max_delay; ++D) {
-        const int s = t - D;
-        for (int kind = 0; kind < 2; ++kind) {
-          const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
-          const long base = kind == 0 ? 0 : nin;
-          for (int i = 0; i < pr->n_src; ++i) {
-            if (!spiked(&sp, kind, i, s)) continue;
-            for (unsigned long r = pr->row_ptr[i]; r < pr->row_ptr[i + 1]; ++r) {
-              if (pr->delay[r] != D) continue;
-              const long q = base + (long)r;
-              const int j = (int)pr->col[r];
-              if (apr[q] > 0)
-                for (int u = apr[q]; u <= t - 1; ++u)
-                  syn_step(&p, u == apr[q] ? 1.0 : 0.0, psi_h[(long)(u - 1) * J + j],
-                           psi_h[(long)u * J + j], neuron_beta(net, j), L_h[(long)u * J + j],
-                           &ev[q], &ea[q], &eb[q], SYN_G(q));
-              apr[q] = t;
-            }
-          }
+        const double e = syn_trace(&p, x, psi_h[(long)(t - 1) * J + j], psi_h[(long)t * J + j], neuron_beta(net, j),
+                                   &ev[q], &ea[q], &eb[q]);
+        fifo_e[q * (dq + 1) + t % (dq + 1)] = e;
+        fifo_eb[q * (dq + 1) + t % (dq + 1)] = eb[q];
+        if (t - dq >= 1) {
+          *SYN_G(q) += Lon * L_h[(long)t * J + j] * fifo_eb[q * (dq + 1) + (t - dq) % (dq + 1)];
+          esum[q] += fifo_e[q * (dq + 1) + (t - dq) % (dq + 1)];
         }
       }
+      /* output synapses: zbar = F_kappa(z_j), g_out += E_k^t zbar^{t-d}
+       * (eq. eprop-output-new-subs-rewritten) */
       for (int j = 0; j < J; ++j) {
-        if (!sp.zrec[(long)t * J + j]) continue;
-        if (apr_o[j] > 0)
-          for (int u = apr_o[j]; u <= t - 1; ++u) {
-            zb[j] = p.kappa * zb[j] + (u == apr_o[j] ? 1.0 : 0.0);
-            for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E_h[(long)u * K + k] * zb[j];
-          }
-        apr_o[j] = t;
+        zb[j] = p.kappa * zb[j] + (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);
+        fifo_z[(long)j * (dq + 1) + t % (dq + 1)] = zb[j];
+        if (t - dq >= 1)
+          for (int k = 0; k < K; ++k)
+            g_out[(long)k * J + j] += E[k] * fifo_z[(long)j * (dq + 1) + (t - dq) % (dq + 1)];
       }
     }
   }
-  if (grad_mode == 2) {
-    /* end of the trial: flush every open interval up to T */
-    for (long q = 0; q < ns; ++q) {
-      if (apr[q] == 0) continue;
-      const int j = SYN_TGT(q);
-      for (int u = apr[q]; u <= T; ++u)
-        syn_step(&p, u == apr[q] ? 1.0 : 0.0, psi_h[(long)(u - 1) * J + j], psi_h[(long)u * J + j],
-                 neuron_beta(net, j), L_h[(long)u * J + j], &ev[q], &ea[q], &eb[q], SYN_G(q));
+
+  /* static firing-rate regularisation (Methods, "Firing rate regularization"):
+   * f_j = (1/T) sum_t z_j^t; loss c/2 sum_j (f_j - f*)^2; per synapse the
+   * gradient adds (c/T)(f_j - f*) times the eligibilities paired in the sum */
+  for (int j = 0; j < J; ++j) {
+    double nz = 0.0;
+    for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
+    const double f = nz / T;
+    creg[j] = net->c_reg / T * (f - net->f_target);
+    loss += 0.5 * net->c_reg * (f - net->f_target) * (f - net->f_target);
+  }
+
+  if (grad_mode == 1) {
+    for (long q = 0; q < ns; ++q) *SYN_G(q) += creg[SYN_TGT(q)] * esum[q];
+  } else if (grad_mode == 2) {
+    /* Event-driven update (Algs. "event-driven weight update" and its
+     * optimized spike-time form), evaluated once the sample is complete, as
+     * the event-driven scheme does (Results, "From time-driven to
+     * event-driven e-prop"): every synapse with at least one arrival walks
+     * the archived history from its first arrival, segment by segment
+     * between arrivals, the arrival counted at its segment's first step;
+     * eligibility e^s pairs with L^{s+d} (s + d <= T - d^ls) and, for the
+     * regularisation, with itself (s <= T - d). */
+    const int dq = net->d_out;
+    for (int kind = 0; kind < 2; ++kind) {
+      const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
+      const long base = kind == 0 ? 0 : nin;
+      for (int i = 0; i < pr->n_src; ++i)
+        for (unsigned long r = pr->row_ptr[i]; r < pr->row_ptr[i + 1]; ++r) {
+          const long q = base + (long)r;
+          const int j = (int)pr->col[r];
+          const int D = pr->delay[r];
+          double evq = 0.0, eaq = 0.0, ebq = 0.0, es = 0.0;
+          int seg = -1;  /* start of the open segment */
+          for (int a = 1; a <= T + 1; ++a) {
+            const int arrival = a <= T && spiked(&sp, kind, i, a - D);
+            if (!arrival && a <= T) continue;
+            if (seg > 0) {
+              for (int u = seg; u <= a - 1; ++u) {
+                const double e = syn_trace(&p, u == seg ? 1.0 : 0.0, psi_h[(long)(u - 1) * J + j],
+                                           psi_h[(long)u * J + j], neuron_beta(net, j), &evq, &eaq, &ebq);
+                if (u + dq <= T - net->d_ls) *SYN_G(q) += L_h[(long)(u + dq) * J + j] * ebq;
+                if (u <= T - dq) es += e;
+              }
+            }
+            seg = a;
+          }
+          *SYN_G(q) += creg[j] * es;
+        }
     }
     for (int j = 0; j < J; ++j) {
-      if (apr_o[j] == 0) continue;
-      for (int u = apr_o[j]; u <= T; ++u) {
-        zb[j] = p.kappa * zb[j] + (u == apr_o[j] ? 1.0 : 0.0);
-        for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E_h[(long)u * K + k] * zb[j];
+      double zbj = 0.0;
+      int seg = -1;
+      for (int u0 = 1; u0 <= T + 1; ++u0) {
+        const int spk = u0 <= T && sp.zrec[(long)u0 * J + j];
+        if (!spk && u0 <= T) continue;
+        if (seg > 0)
+          for (int u = seg; u <= u0 - 1; ++u) {
+            zbj = p.kappa * zbj + (u == seg ? 1.0 : 0.0);
+            if (u + dq <= T)
+              for (int k = 0; k < K; ++k) g_out[(long)k * J + j] += E_h[(long)(u + dq) * K + k] * zbj;
+          }
+        seg = u0;
       }
     }
   }
@@ -386,7 +425,7 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
 done:
   free(v); free(a); free(refr); free(y); free(E); free(psum);
   free(psi_h); free(L_h); free(E_h); free(ev); free(ea); free(eb); free(apr); free(zb); free(apr_o);
-  free(q_src);
+  free(q_src); free(fifo_e); free(fifo_eb); free(fifo_z); free(esum); free(creg);
   spikes_free(&sp);
   prep_free(&p);
   return rc;
@@ -449,12 +488,25 @@ static int dual_run(const orc_net *net, const prep_t *p, const spikes_t *sp_ref,
       dz[(long)t * J + j] = psi * (v[j].d - A.d);
     }
     if (dloss) {
+      /* readout with delay d: y^t = kappa y^{t-1} + W z^{t-d} (eq. leaky_integrator_with_delay) */
       for (int k = 0; k < K; ++k) {
         double s = 0.0;
-        for (int j = 0; j < J; ++j) s += net->w_out[(long)k * J + j] * dz[(long)t * J + j];
+        if (t - net->d_out >= 1)
+          for (int j = 0; j < J; ++j) s += net->w_out[(long)k * J + j] * dz[(long)(t - net->d_out) * J + j];
         y[k].d = p->kappa * y[k].d + s;
         dl += E_rec[(long)(t - 1) * K + k] * y[k].d;
       }
+    }
+  }
+  if (dloss && net->c_reg != 0.0) {
+    /* tangent of the regularisation loss: c (f_j - f*) (1/T) sum_t dz_j^t */
+    for (int j = 0; j < J; ++j) {
+      double nz = 0.0, sd = 0.0;
+      for (int t = 1; t <= T; ++t) {
+        nz += sp_ref->zrec[(long)t * J + j] ? 1.0 : 0.0;
+        sd += dz[(long)t * J + j];
+      }
+      dl += net->c_reg * (nz / T - net->f_target) * sd / T;
     }
   }
   if (dloss) *dloss = dl;
@@ -509,17 +561,26 @@ int orc_bruteforce_eprop(const orc_net *net, const orc_trial *tr, double *g_in, 
       seed_t sd;
       for_each_weight(net, kind, q, &sd);
       rc = dual_run(net, &p, &sp, tr, E_rec, sd, 1, dz, NULL);
-      /* eq. summation-future: sum_t' [sum_k B_jk sum_{t>=t'} E_k^t kappa^(t-t')] e^t' */
-      double g = 0.0;
-      for (int tp = 1; tp <= T; ++tp) {
+      /* eq. summation-future, with the readout delay d
+       * (eq. eprop-approx-final-expanded) and the learning-signal delay d^ls
+       * (eq. eprop-learning-signal-delay):
+       * sum_{t'<=T-d} [sum_k B_jk sum_{t'+d<=t<=T-d^ls} E_k^t kappa^(t-d-t')] e^t',
+       * plus the static regularisation (c/T)(f_j - f*) sum_{t'<=T-d} e^t' */
+      const int d = net->d_out;
+      double g = 0.0, es = 0.0;
+      for (int tp = 1; tp <= T - d; ++tp) {
         double Ls = 0.0;
         for (int k = 0; k < K; ++k) {
           double fut = 0.0;
-          for (int t = tp; t <= T; ++t) fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa, t - tp);
+          for (int t = tp + d; t <= T - net->d_ls; ++t) fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa, t - d - tp);
           Ls += net->fb[(long)sd.tgt * K + k] * fut;
         }
         g += Ls * dz[(long)tp * J + sd.tgt];
+        es += dz[(long)tp * J + sd.tgt];
       }
+      double nz = 0.0;
+      for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + sd.tgt] ? 1.0 : 0.0;
+      g += net->c_reg / T * (nz / T - net->f_target) * es;
       (kind == 0 ? g_in : g_rec)[q] = g;
     }
   }
@@ -578,6 +639,11 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
     readout_step(net, &p, &sp, tr, t, y, E, &loss, psum);
     for (int k = 0; k < K; ++k) E_h[(long)t * K + k] = E[k];
   }
+  for (int j = 0; j < J; ++j) {  /* static rate regularisation of every neuron */
+    double nz = 0.0;
+    for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
+    loss += 0.5 * net->c_reg * (nz / T - net->f_target) * (nz / T - net->f_target);
+  }
   for (int n = 0; n < n_sample && rc == 0; ++n) {
     const int j = targets[n];
     if (j < 0 || j >= J) { rc = -1; break; }
@@ -594,13 +660,19 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
       for (int k = 0; k < K; ++k) Ls = Ls + net->fb[(long)j * K + k] * E_h[(long)t * K + k];
       L_h[t] = Ls;
     }
+    double nz = 0.0;
+    for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
+    const double creg = net->c_reg / T * (nz / T - net->f_target);
     for (long q = p.in_ptr[j]; q < p.in_ptr[j + 1]; ++q) {
       const in_syn *s = &p.syn[q];
-      double ev = 0.0, ea = 0.0, eb = 0.0, g = 0.0;
-      for (int t = 1; t <= T; ++t)
-        syn_step(&p, spiked(&sp, s->kind, s->src, t - s->delay) ? 1.0 : 0.0, psi_h[t - 1], psi_h[t],
-                 neuron_beta(net, j), L_h[t], &ev, &ea, &eb, &g);
-      (s->kind == 0 ? g_in : g_rec)[s->idx] = g;
+      double ev = 0.0, ea = 0.0, eb = 0.0, g = 0.0, es = 0.0;
+      for (int t = 1; t <= T; ++t) {
+        const double e = syn_trace(&p, spiked(&sp, s->kind, s->src, t - s->delay) ? 1.0 : 0.0, psi_h[t - 1],
+                                   psi_h[t], neuron_beta(net, j), &ev, &ea, &eb);
+        if (t + net->d_out <= T - net->d_ls) g += L_h[t + net->d_out] * eb;
+        if (t <= T - net->d_out) es += e;
+      }
+      (s->kind == 0 ? g_in : g_rec)[s->idx] = g + creg * es;
     }
   }
   if (loss_out) *loss_out = loss;

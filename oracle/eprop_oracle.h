@@ -38,6 +38,12 @@ typedef struct {
   orc_proj in, rec;
   const double *w_out;            /* [K*J], row k */
   const double *fb;               /* [J*K], row j */
+  /* generalised delays (Supplementary, "Generalized delays") and static
+   * firing-rate regularisation (Methods, "Firing rate regularization") */
+  int d_out;                      /* delay d from the recurrent to the output layer, >= 0 */
+  int d_ls;                       /* delay d^ls of the learning signal, >= 0 */
+  double c_reg;                   /* regularisation strength c^reg (0 = off) */
+  double f_target;                /* target rate f^*, in spikes per step */
 } orc_net;
 
 typedef struct {

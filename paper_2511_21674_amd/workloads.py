@@ -64,6 +64,10 @@ class Params:
     adam_beta2: float = 0.999
     adam_eps_hat: float = 1e-7
     max_delay: int = 1
+    d_out: int = 0              # delay from the recurrent to the output layer (steps)
+    d_ls: int = 0               # delay of the learning signal (steps)
+    c_reg: float = 0.0          # static firing-rate regularisation strength
+    f_target_hz: float = 0.0    # its target rate
 
 
 @dataclass

@@ -345,3 +345,113 @@ def test_fixed_indegree_graph():
     key = src.astype(np.int64) * p.n_tgt + p.col
     assert np.unique(key).size == key.size
     assert p.delay.min() == 1 and p.delay.max() == 5
+
+
+# ---------------------------------------------------------------- generalised delays, regularisation
+
+def _with(wnet, **params):
+    from dataclasses import replace
+    return replace(wnet, params=replace(wnet.params, **params))
+
+
+def _head(batch, T, shift=0):
+    """Trial 0 of batch cut to its first T steps, target and loss window advanced by shift."""
+    lo, hi = int(batch.in_ptr[0]), int(batch.in_ptr[1])
+    keep = batch.in_step[lo:hi] < T
+    b = W.Batch(n_steps=np.array([T], np.uint32), in_ptr=np.array([0, int(keep.sum())], np.uint64),
+                in_step=batch.in_step[lo:hi][keep], in_src=batch.in_src[lo:hi][keep])
+    b.target = np.ascontiguousarray(batch.target[:1, shift:shift + T])
+    b.window = np.ascontiguousarray(batch.window[:1, shift:shift + T])
+    b.label = batch.label[:1].copy()
+    return b
+
+
+@pytest.mark.parametrize("d,d_ls", [(1, 0), (3, 0), (2, 4), (0, 3)])
+def test_delays_are_a_time_shift(d, d_ls):
+    """Generalised delays (Supplementary, "Generalized delays"): with a readout
+    delay d the readout of step t sees the spikes of step t-d (eq.
+    leaky_integrator_with_delay), so the spike trains, which do not depend on
+    the readout, are those of the network without delays, and the readout is
+    that network's readout d steps later.  Hence the input and recurrent
+    gradient of a T-step trial (eq. eprop-approx-final-expanded-subs-rewritten,
+    with the learning-signal delay of eq. eprop-learning-signal-delay) equals
+    the delay-free gradient of the first T-d-d^ls steps with the target
+    advanced by d; the output gradient (eq. eprop-output-new-subs-rewritten)
+    that of the first T-d steps; and the loss that of the first T-d steps
+    plus the windowed loss of the first d steps, whose readout is still at rest."""
+    wl = W.tiny(loss=0)
+    b = wl.make_batch(0, 0, 1)
+    T = int(b.n_steps[0])
+    on_d = O.OracleNet(_with(wl.network, d_out=d, d_ls=d_ls))
+    gd = O.zero_grads(on_d)
+    rd = O.run_trial(on_d, b, 0, 2, gd)
+    on = O.OracleNet(wl.network)
+    g1 = O.zero_grads(on)
+    O.run_trial(on, _head(b, T - d - d_ls, d), 0, 2, g1)
+    g2 = O.zero_grads(on)
+    r2 = O.run_trial(on, _head(b, T - d, d), 0, 2, g2)
+    for k in ("w_in", "w_rec"):
+        ok, e, ent = rel_close(gd[k], g1[k], 1e-12)
+        assert ok, (k, e, ent)
+    ok, e, ent = rel_close(gd["w_out"], g2["w_out"], 1e-12)
+    assert ok, ("w_out", e, ent)
+    rest = 0.5 * float((b.window[0, :d, None] * b.target[0, :d] ** 2).sum())
+    assert rd.loss == pytest.approx(r2.loss + rest, rel=1e-12)
+    assert np.abs(gd["w_rec"]).max() > 0
+
+
+@pytest.mark.parametrize("d,d_ls,c_reg", [(2, 0, 0.0), (1, 3, 4.0), (3, 2, 4.0)])
+def test_delays_and_regularisation_bruteforce_time_event(d, d_ls, c_reg):
+    """P7 and P10 with generalised delays and static rate regularisation: the
+    dual-number gradient in its future-sum form (eq.
+    eprop-approx-final-expanded with d and the learning-signal delay, plus
+    eq. firing-rate-regularization summed over the paired steps) equals the
+    time-driven FIFO recursion (Alg. time-driven gradient computation) and
+    the event-driven walk over the archived history."""
+    wl = W.tiny(loss=1)
+    on = O.OracleNet(_with(wl.network, d_out=d, d_ls=d_ls, c_reg=c_reg, f_target_hz=20.0))
+    b = wl.make_batch(0, 0, 1)
+    g1, g2 = O.zero_grads(on), O.zero_grads(on)
+    r1 = O.run_trial(on, b, 0, 1, g1)
+    r2 = O.run_trial(on, b, 0, 2, g2)
+    bf = O.bruteforce_eprop(on, b, 0)
+    assert r1.loss == r2.loss
+    for k in ("w_in", "w_rec"):
+        ok, e, ent = rel_close(g1[k], bf[k], 1e-12)
+        assert ok, ("time-driven vs brute force", k, e, ent)
+        ok, e, ent = rel_close(g2[k], g1[k], 1e-12)
+        assert ok, ("event vs time-driven", k, e, ent)
+    ok, e, ent = rel_close(g2["w_out"], g1["w_out"], 1e-12)
+    assert ok, ("w_out", e, ent)
+
+
+def test_rate_regularisation_is_exact_without_recurrence():
+    """Static firing-rate regularisation (eq. loss-firing-rate-regularization,
+    eq. firing-rate-regularization): with W_rec = 0 and B = W_out^T the e-prop
+    gradient, regulariser included, is the exact forward-mode gradient of the
+    loss plus c/2 sum_j (f_j - f*)^2 (as in P8), and the regulariser changes
+    the gradient.  With a readout delay d the loss is that of the plain network
+    plus c/2 sum_j (f_j - f*)^2, f_j the trial's spike count over T."""
+    wl = W.tiny(loss=0)
+    b = wl.make_batch(0, 0, 1)
+    T = int(b.n_steps[0])
+
+    def run(**params):
+        on = O.OracleNet(_with(wl.network, **params))
+        on.w_rec[:] = 0.0
+        on.fb[:] = on.w_out.T
+        g = O.zero_grads(on)
+        r = O.run_trial(on, b, 0, 2, g, trace=True)
+        return on, g, r
+
+    on, g, r = run(c_reg=3.0, f_target_hz=15.0)
+    fm = O.forward_mode_loss_grad(on, b, 0)
+    ok, e, ent = rel_close(g["w_in"], fm["w_in"], 1e-12)
+    assert ok, (e, ent)
+    _, g0, _ = run()
+    assert not rel_close(g0["w_in"], g["w_in"], 1e-3)[0]
+    _, _, rd = run(d_out=2, c_reg=3.0, f_target_hz=15.0)
+    _, _, rd0 = run(d_out=2)
+    f = rd.trace["z"].sum(axis=0) / T
+    reg = 0.5 * 3.0 * float(((f - 15.0 / 1000.0) ** 2).sum())
+    assert rd.loss == pytest.approx(rd0.loss + reg, rel=1e-12)
