@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define EPROP_ABI_VERSION 1u
+#define EPROP_ABI_VERSION 2u
 
 typedef struct eprop_network eprop_network;   /* opaque, owned by the library */
 
@@ -127,12 +127,26 @@ typedef struct {
   uint32_t max_steps;            /* largest trial length T, 1..65535 */
   int32_t delivery;              /* eprop_delivery */
   uint32_t flags;                /* EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS */
-  uint32_t d_out;                /* delay of recurrent spikes to the readout (Supplementary, "Delay
-                                    from the recurrent to the output layer"): 0 in this version */
-  uint32_t d_ls;                 /* learning-signal delay: 0 in this version */
+  uint32_t d_out;                /* delay d in steps of recurrent spikes to the readout, 0..65535
+                                    (Supplementary, "Delay from the recurrent to the output layer":
+                                    y^t integrates W_out z^{t-d}; the recurrent gradient pairs the
+                                    learning signal of step t with the filtered eligibility of step
+                                    t-d, the output gradient E^t with the filtered spikes of t-d) */
+  uint32_t d_ls;                 /* learning-signal delay d^ls in steps, 0..65535 (Supplementary,
+                                    "Generalized delays"): the recurrent and input gradients take the
+                                    learning signals of steps 1+d .. T-d^ls only; the output gradient
+                                    is not affected */
   uint32_t history_steps;        /* per-neuron history capacity in steps; 0 = whole trial.  The
                                     history always covers the whole trial here, so other values
                                     must be >= max_steps */
+  double c_reg;                  /* static firing-rate regularisation coefficient c^reg >= 0
+                                    (eq. loss-firing-rate-regularization, eq. firing-rate-
+                                    regularization); 0 = off.  The rate f_j of a trial is the
+                                    neuron's spike count / T (per step), the loss adds
+                                    c^reg/2 sum_j (f_j - f*)^2 and the recurrent and input gradients
+                                    add c^reg/T (f_j - f*) e_ji^t over steps t <= T - d */
+  double f_target;               /* target rate f* in spikes per second (Hz), >= 0; the regulariser
+                                    uses f_target * dt / 1000 spikes per step */
   eprop_dev_alloc_fn dev_alloc;  /* NULL or the allocator above */
   eprop_dev_free_fn dev_free;    /* required with dev_alloc */
   void *alloc_ctx;

@@ -177,10 +177,9 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
   if ((c->flags & EPROP_DETERMINISTIC) && c->precision == EPROP_FP64 && c->delivery == EPROP_DELIVERY_SCATTER)
     return bad("FP64 scatter delivery is not deterministic; use gather or AUTO");
   if ((c->dev_alloc == nullptr) != (c->dev_free == nullptr)) return bad("dev_alloc and dev_free go together");
-  if (c->d_out != 0 || c->d_ls != 0) {
-    msg = "readout and learning-signal delays other than 0 are not supported";
-    return EPROP_ERR_UNSUPPORTED;
-  }
+  if (c->d_out > 65535 || c->d_ls > 65535) return bad("d_out and d_ls must be in 0..65535");
+  if (!(c->c_reg >= 0) || !is_finite(c->c_reg)) return bad("c_reg must be finite and >= 0");
+  if (!(c->f_target >= 0) || !is_finite(c->f_target)) return bad("f_target must be finite and >= 0");
   if (c->history_steps != 0 && c->history_steps < c->max_steps) {
     msg = "the history covers whole trials: history_steps must be 0 or >= max_steps";
     return EPROP_ERR_UNSUPPORTED;
@@ -203,6 +202,9 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   d.alpha = (real)n->alpha; d.rho = (real)n->rho; d.v_th = (real)n->cfg.v_th;
   d.sg_gamma = (real)n->cfg.sg_gamma; d.sg_beta = (real)n->cfg.sg_beta;
   d.alpha_d = n->alpha; d.rho_d = n->rho; d.kappa_d = n->kappa;
+  d.d_out = n->cfg.d_out; d.d_ls = n->cfg.d_ls;
+  d.c_reg = n->cfg.c_reg;
+  d.f_target = n->cfg.f_target * n->cfg.dt / 1000.0;
   uint32_t *p32;
   real *pr;
   bool ok = true;
@@ -259,6 +261,8 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.y, B * T2 * n->K);
   ok &= dalloc(n, &d.err, B * T2 * n->K);
   ok &= dalloc(n, &d.ebar, B * T2 * n->K);
+  if (n->cfg.d_ls) ok &= dalloc(n, &d.ebo, B * T2 * n->K);
+  else d.ebo = d.ebar;
   ok &= dalloc(n, &d.loss_out, B);
   ok &= dalloc(n, &d.pred_out, B);
   ok &= dalloc(n, &d.ctl, 64);

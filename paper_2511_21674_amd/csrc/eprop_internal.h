@@ -24,7 +24,7 @@
 //   per-step spikes      pub_list[b][t & 1][Jp] (tile k's spiking neurons of step t at
 //                        k*TS.., each word t << 32 | j), pub_cnt[b][t & 1][KT]
 //                        (t << 32 | count of tile k), nspk[b][t]
-//   readout (FP64)       ysum/pi[b][t][K], y[b][t][K], err[b][t][K], ebar[b][t][K]
+//   readout (FP64)       ysum/pi[b][t][K], y[b][t][K], err[b][t][K], ebar[b][t][K], ebo[b][t][K]
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -80,6 +80,8 @@ struct DevNet {
   // constants (working precision for the dynamics, FP64 for the backward filters)
   real alpha, rho, v_th, sg_gamma, sg_beta;
   double alpha_d, rho_d, kappa_d;
+  uint32_t d_out, d_ls;         // readout delay d, learning-signal delay d^ls (steps)
+  double c_reg, f_target;       // rate regulariser coefficient and target rate (spikes per step)
   // graph
   const uint32_t *sm_ptr, *tseg;
   SynRec<real> *sm;
@@ -112,7 +114,11 @@ struct DevNet {
   uint64_t *pub_list, *pub_cnt;
   uint32_t *nspk;
   uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
-  double *ysum, *y, *err, *ebar;  // [Bcap][Tcap+2][K]
+  double *ysum, *y, *err;       // [Bcap][Tcap+2][K]
+  double *ebar;                 // [Bcap][Tcap+2][K] backward-filtered error paired with the
+                                // eligibility of step u: sum_{v=u}^{T-d-d^ls} kappa^{v-u} E^{v+d}
+  double *ebo;                  // the same without the learning-signal cut (upper end T-d), for
+                                // the output gradient; aliases ebar when d^ls = 0
   double *loss_out;             // [Bcap]
   uint32_t *pred_out;           // [Bcap]
   // batch (device pointers)

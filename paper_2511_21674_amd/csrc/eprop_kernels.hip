@@ -581,21 +581,27 @@ __global__ __launch_bounds__(256) void k_readout_sums(DevNet<real> n) {
   }
 }
 
-// Per trial (one block of 256): readout recursion y^t = kappa y^{t-1} + ysum^t,
-// error signal and loss (window-gated), prediction, and the backward filter
-// Ebar^t = E^t + kappa Ebar^{t+1}.  All FP64.
+// Per trial (one block of 256): readout recursion y^t = kappa y^{t-1} +
+// ysum^{t-d} (readout delay d, Supplementary "Delay from the recurrent to the
+// output layer"), error signal and loss (window-gated), the rate
+// regulariser's loss (eq. loss-firing-rate-regularization), prediction, and
+// the backward filters of the error shifted by d: ebar^u = E^{u+d} + kappa
+// ebar^{u+1} up to u = T-d-d^ls (the learning signals the recurrent gradient
+// takes) and ebo^u the same up to u = T-d (output gradient); both 0 beyond.
+// All FP64, fixed summation order.
 template <typename real>
 __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   const uint32_t b = blockIdx.x;
   if (b >= n.ctl[CTL_NTRIALS]) return;
-  const uint32_t T = n.T[b], K = n.K, tid = threadIdx.x;
+  const uint32_t T = n.T[b], K = n.K, tid = threadIdx.x, d = n.d_out;
   const size_t rs = (size_t)(n.Tcap + 2) * K;
   double *ysum = n.ysum + b * rs, *y = n.y + b * rs, *err = n.err + b * rs, *ebar = n.ebar + b * rs;
+  double *ebo = n.ebo + b * rs;
   const double kap = n.kappa_d;
   for (uint32_t k = tid; k < K; k += blockDim.x) {
     double yy = 0.0;
     for (uint32_t t = 1; t <= T; ++t) {
-      yy = kap * yy + ysum[(size_t)t * K + k];
+      yy = kap * yy + (t > d ? ysum[(size_t)(t - d) * K + k] : 0.0);
       y[(size_t)t * K + k] = yy;
     }
   }
@@ -627,6 +633,15 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
       if (win) lp += -(yt[label] - mx - log(se));
     }
   }
+  if (n.c_reg != 0.0) {
+    const uint32_t *cnt = n.spk_cnt + (size_t)b * n.NS + n.I;
+    double rl = 0.0;
+    for (uint32_t j = tid; j < n.J; j += blockDim.x) {
+      const double f = (double)cnt[j] / (double)T - n.f_target;
+      rl += f * f;
+    }
+    lp += 0.5 * n.c_reg * rl;
+  }
   __shared__ double red[256];
   __shared__ double psum[64];
   red[tid] = lp;
@@ -635,11 +650,16 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
+  // last index of each filter (signed: a trial may be shorter than the delays)
+  const int64_t u_out = (int64_t)T - d, u_rec = u_out - (int64_t)n.d_ls;
   for (uint32_t k = tid; k < K; k += blockDim.x) {
-    double eb = 0.0;
-    for (uint32_t t = T; t >= 1; --t) {
-      eb = err[(size_t)t * K + k] + kap * eb;
-      ebar[(size_t)t * K + k] = eb;
+    double eb = 0.0, eo = 0.0;
+    for (int64_t u = T; u >= 1; --u) {
+      const double e = u <= u_out ? err[(size_t)(u + d) * K + k] : 0.0;
+      eo = e + kap * eo;
+      eb = u <= u_rec ? e + kap * eb : 0.0;
+      ebar[(size_t)u * K + k] = eb;
+      if (ebo != ebar) ebo[(size_t)u * K + k] = eo;
     }
     if (n.loss == 1 && k < 64) {
       double s = 0.0;
@@ -664,10 +684,10 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
 // ----------------------------------------------------------------- gradient
 
 // Per (trial, neuron), backward over the trial in chunks of 16 steps:
-// learning signal of the filtered errors Lambda^t = sum_k B_jk Ebar_k^t, the
-// adjoint recursion of the eligibility vector (FP64) and the archive
+// learning signal of the filtered errors Lambda^t = sum_k B_jk Ebar_k^t (plus
+// the rate regulariser's constant for t <= T - d), the adjoint recursion of the eligibility vector (FP64) and the archive
 // phi[b][j][t] = mu^t[0]; then the neuron's output-synapse gradient
-// sum over its spikes u of Ebar_k^u.  B rows and the chunk's Ebar rows are
+// sum over its spikes u of Ebar_k^u (without the learning-signal cut).  B rows and the chunk's Ebar rows are
 // read from LDS; phi is transposed through LDS so that each store writes
 // whole 16-step row segments.
 template <typename real>
@@ -686,6 +706,14 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   for (uint32_t k = 0; k < K; ++k) fbl[k * bd + tid] = live ? (double)n.fb[(size_t)j * K + k] : 0.0;
   const double beta = live ? (double)n.beta_j[j] : 0.0;
   const double *eb = n.ebar + (size_t)b * (n.Tcap + 2) * K;
+  // rate regulariser (eq. firing-rate-regularization): c^reg/T (f_j - f*)
+  // multiplies the eligibility of every step u <= T - d, so it adds to the
+  // adjoint's learning-signal sum there
+  const double creg = (live && n.c_reg != 0.0)
+                          ? n.c_reg / (double)T *
+                                ((double)n.spk_cnt[(size_t)b * n.NS + n.I + j] / (double)T - n.f_target)
+                          : 0.0;
+  const int64_t u_reg = (int64_t)T - n.d_out;
   const real *ps_col = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
   const uint32_t wbase = tid & ~63u, lane = tid & 63u;
   double mu0 = 0.0, mu1 = 0.0;
@@ -710,6 +738,7 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
       if (t >= 1 && t <= T) {
         double L = 0.0;
         for (uint32_t k = 0; k < K; ++k) L += fbl[k * bd + tid] * ebl[r * K + k];
+        if ((int64_t)t <= u_reg) L += creg;
         const double p = (double)ps[r];
         const double pl = p * L;
         const double m0 = pl + n.alpha_d * mu0 + p * mu1;
@@ -733,9 +762,10 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   const uint32_t c = n.spk_cnt[(size_t)b * n.NS + n.I + j];
   const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
   real *go = n.gout_b + (size_t)b * K * n.Jp + j;
+  const double *eo = n.ebo + (size_t)b * (n.Tcap + 2) * K;
   for (uint32_t k = 0; k < K; ++k) {
     double acc = 0.0;
-    for (uint32_t i = 0; i < c; ++i) acc += eb[(size_t)st[i] * K + k];
+    for (uint32_t i = 0; i < c; ++i) acc += eo[(size_t)st[i] * K + k];
     go[(size_t)k * n.Jp] = (real)acc;
   }
 }
@@ -936,7 +966,8 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
 // (spike bitsets, psi archive, error signal) and the same accumulators.
 
 // L_j^t = sum_k B_jk E_k^t (eq. final-gradient), FP64 sum, stored per
-// (trial, step, neuron).
+// (trial, step, neuron) at the step u = t - d whose eligibility it meets
+// (readout delay d), and only for t <= T - d^ls (learning-signal delay).
 template <typename real>
 __global__ __launch_bounds__(256) void k_learning_signal(DevNet<real> n, real *L) {
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
@@ -944,9 +975,10 @@ __global__ __launch_bounds__(256) void k_learning_signal(DevNet<real> n, real *L
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)ntr * per;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t b = (uint32_t)(i / per);
-    const uint32_t t = (uint32_t)((i % per) / n.Jp), j = (uint32_t)(i % n.Jp);
+    const uint32_t u = (uint32_t)((i % per) / n.Jp), j = (uint32_t)(i % n.Jp);
+    const uint64_t t = (uint64_t)u + n.d_out;
     double acc = 0.0;
-    if (j < n.J && t >= 1 && t <= n.T[b]) {
+    if (j < n.J && u >= 1 && t + n.d_ls <= n.T[b]) {
       const double *E = n.err + ((size_t)b * (n.Tcap + 2) + t) * n.K;
       for (uint32_t k = 0; k < n.K; ++k) acc += (double)n.fb[(size_t)j * n.K + k] * E[k];
     }
@@ -956,8 +988,10 @@ __global__ __launch_bounds__(256) void k_learning_signal(DevNet<real> n, real *L
 
 // One thread per (synapse q, trial chunk c): the eligibility recursion of
 // eq. eligibility-vector-substituted and eq. filtered-eligibility-trace over
-// every step of each trial of the chunk, g += L^t ebar^t (Kahan).  The
-// arrival indicator x^t is the source's spike bit at step t - D.
+// every step of each trial of the chunk, g += L^{t+d} ebar^t (Kahan; L as
+// stored by k_learning_signal), plus the rate regulariser c^reg/T (f_j - f*)
+// times the sum of e^t over t <= T - d.  The arrival indicator x^t is the
+// source's spike bit at step t - D.
 template <typename real>
 __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *L, uint32_t ginst, uint32_t nchunk,
                                                     real *partial) {
@@ -985,7 +1019,8 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
       const uint32_t b = b0 + bi, T = n.T[b];
       const real *ps = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
       const real *Lb = L + (size_t)b * (n.Tcap + 1) * n.Jp + j;
-      real ev = 0, ea = 0, eb = 0, psi_prev = 0;
+      real ev = 0, ea = 0, eb = 0, psi_prev = 0, es = 0, ec = 0;
+      const uint32_t t_reg = T > n.d_out ? T - n.d_out : 0u;
       uint32_t arrivals = 0;
       for (uint32_t t = 1; t <= T; ++t) {
         uint32_t x = 0;
@@ -1001,11 +1036,18 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
         const real psi_now = ps[(size_t)t * n.Jp];
         const real ea_new = psi_prev * ev + (n.rho - psi_prev * beta) * ea;
         const real ev_new = n.alpha * ev + (real)x;
-        eb = kappa * eb + psi_now * (ev_new - beta * ea_new);
+        const real e = psi_now * (ev_new - beta * ea_new);
+        eb = kappa * eb + e;
         ev = ev_new;
         ea = ea_new;
         psi_prev = psi_now;
         kahan_add(s, cc, Lb[(size_t)t * n.Jp] * eb);
+        if (t <= t_reg) kahan_add(es, ec, e);
+      }
+      if (n.c_reg != 0.0) {
+        const double creg = n.c_reg / (double)T *
+                            ((double)n.spk_cnt[(size_t)b * n.NS + n.I + j] / (double)T - n.f_target);
+        kahan_add(s, cc, (real)(creg * ((double)es + (double)ec)));
       }
       nev += arrivals;
       nfl += arrivals ? 1u : 0u;
@@ -1030,8 +1072,9 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
   }
 }
 
-// Output synapses, time-driven: zbar = F_kappa(z_j), g_kj += E_k^t zbar^t,
-// one thread per (trial, readout, neuron), FP64 sum.
+// Output synapses, time-driven: zbar = F_kappa(z_j), g_kj += E_k^{t+d}
+// zbar^t over t <= T - d (readout delay d), one thread per (trial, readout,
+// neuron), FP64 sum.
 template <typename real>
 __global__ __launch_bounds__(256) void k_td_output(DevNet<real> n) {
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
@@ -1041,11 +1084,11 @@ __global__ __launch_bounds__(256) void k_td_output(DevNet<real> n) {
     const uint32_t b = (uint32_t)(i / per), k = (uint32_t)((i % per) / n.Jp), j = (uint32_t)(i % n.Jp);
     double zb = 0.0, g = 0.0;
     if (j < n.J) {
-      const uint32_t T = n.T[b];
-      for (uint32_t t = 1; t <= T; ++t) {
+      const uint32_t T = n.T[b], d = n.d_out;
+      for (uint32_t t = 1; t + d <= T; ++t) {
         const uint32_t z = (uint32_t)(n.rec_bits[((size_t)b * (n.Tcap + 1) + t) * n.Jw + (j >> 6)] >> (j & 63u)) & 1u;
         zb = n.kappa_d * zb + (double)z;
-        g += n.err[((size_t)b * (n.Tcap + 2) + t) * n.K + k] * zb;
+        g += n.err[((size_t)b * (n.Tcap + 2) + t + d) * n.K + k] * zb;
       }
     }
     n.gout_b[i] = (real)g;

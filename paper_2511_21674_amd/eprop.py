@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeprop_hip.so")
 
-EPROP_ABI_VERSION = 1
+EPROP_ABI_VERSION = 2
 EPROP_OK, EPROP_ERR_INVALID_ARGUMENT, EPROP_ERR_OUT_OF_MEMORY = 0, -1, -2
 EPROP_ERR_DEVICE, EPROP_ERR_STATE, EPROP_ERR_CAPACITY = -3, -4, -5
 EPROP_ERR_NUMERIC, EPROP_ERR_UNSUPPORTED = -6, -7
@@ -54,7 +54,8 @@ class eprop_config(C.Structure):
                 ("adam_beta1", C.c_double), ("adam_beta2", C.c_double), ("adam_eps_hat", C.c_double),
                 ("max_delay", C.c_uint32), ("max_trials", C.c_uint32), ("max_steps", C.c_uint32),
                 ("delivery", C.c_int32), ("flags", C.c_uint32), ("d_out", C.c_uint32), ("d_ls", C.c_uint32),
-                ("history_steps", C.c_uint32), ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
+                ("history_steps", C.c_uint32), ("c_reg", C.c_double), ("f_target", C.c_double),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
                 ("alloc_ctx", _P)]
 
 
@@ -226,6 +227,8 @@ class Network:
                            loss=p.loss, optimizer=p.optimizer, eta=p.eta, adam_beta1=p.adam_beta1,
                            adam_beta2=p.adam_beta2, adam_eps_hat=p.adam_eps_hat, max_delay=md,
                            max_trials=max_trials, max_steps=max_steps,
+                           d_out=int(getattr(p, "d_out", 0)), d_ls=int(getattr(p, "d_ls", 0)),
+                           c_reg=float(getattr(p, "c_reg", 0.0)), f_target=float(getattr(p, "f_target_hz", 0.0)),
                            delivery={"auto": 0, "scatter": 1, "gather": 2}[delivery],
                            flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0)
                            | (EPROP_AUTOTUNE if autotune else 0))

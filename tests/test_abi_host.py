@@ -63,11 +63,17 @@ def test_struct_layout_matches_the_c_compiler(tmp_path):
             assert got[(st.__name__, name)] == getattr(st, name).offset, (st.__name__, name)
 
 
-def test_config_rejects_delays_and_short_history():
-    cfg, projs, wo, fb, keep = _parts(W.tiny().network, d_out=1)
-    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
-    cfg, projs, wo, fb, keep = _parts(W.tiny().network, d_ls=2)
-    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
+def test_config_rejects_bad_delays_regulariser_and_short_history():
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, d_out=70000)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, d_ls=1 << 20)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, c_reg=-1.0)
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, c_reg=float("nan"))
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, f_target=float("inf"))
+    assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
     cfg, projs, wo, fb, keep = _parts(W.tiny().network, history_steps=100)   # max_steps is 200
     assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
     cfg, projs, wo, fb, keep = _parts(W.tiny().network, flags=1 << 7)

@@ -529,3 +529,61 @@ def test_time_driven_baseline_fp32_teacher_forced():
         ok, e, ent = rel_close(td[0][1][k], oh["grads"][0][k], 1e-4, floor_frac=1e-2)
         log(f"c3 time-driven fp32 {k}: normwise {e:.2e} worst {ent:.2e}")
         assert ok, (k, e, ent)
+
+
+# ----------------------------------------------------------------- generalised delays, rate regulariser
+
+def _delayed(name, d, d_ls, c_reg, f_hz=10.0):
+    if name == "tiny":
+        wl, bs = W.tiny(), 2
+    elif name == "c2":
+        wl, bs = W.c2_evidence(batch_size=3), 3
+    elif name == "c3":
+        wl, bs = W.c3_events(batch_size=3), 3
+    else:
+        wl, bs = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), 2
+    p = wl.network.params
+    p.d_out, p.d_ls, p.c_reg, p.f_target_hz = d, d_ls, c_reg, f_hz
+    return wl, bs
+
+
+@pytest.mark.parametrize("name,d,d_ls,c_reg", [("tiny", 2, 3, 1e5), ("c2", 1, 4, 1e5), ("tiny", 150, 60, 1e5),
+                                               ("tiny", 0, 0, 1e5), ("c2", 3, 0, 0.0)])
+def test_fp64_delays_and_rate_regulariser(name, d, d_ls, c_reg):
+    """Readout delay d, learning-signal delay d^ls (Supplementary, "Generalized
+    delays") and the static rate regulariser (eq. firing-rate-regularization):
+    FP64 event-driven path exact against the oracle (spikes identical, loss,
+    gradients and weights within 1e-10), and the time-driven baseline's
+    gradient against the oracle's time-driven mode.  (150, 60) leaves no
+    learning signal inside a 200-step trial: the recurrent gradient is the
+    regulariser's alone."""
+    wl, bs = _delayed(name, d, d_ls, c_reg)
+    gh = gpu_train(wl, "fp64", 2, bs)
+    oh = oracle_train(wl, 2, bs)
+    assert_fp64_parity(gh, oh, f"{name} d={d} d_ls={d_ls} c_reg={c_reg}")
+    td = _train_mode(wl, "fp64", 2, bs, True)
+    ot = oracle_train(wl, 2, bs, grad_mode=1)
+    for i in range(2):
+        for k in KEYS:
+            ok, e, ent = rel_close(td[i][1][k], ot["grads"][i][k], 1e-10)
+            assert ok, ("time-driven", name, i, k, e, ent)
+
+
+@pytest.mark.parametrize("name", ["c3", "c4twin"])
+def test_fp32_teacher_forced_delays_and_rate_regulariser(name):
+    """FP32 with the oracle's spike trains, d = 2, d^ls = 3, regulariser on:
+    each iteration's update within 1e-4 of the FP64 oracle's (event-driven
+    and time-driven paths)."""
+    wl, bs = _delayed(name, 2, 3, 1e3)
+    gh = gpu_train(wl, "fp32", 2, bs, forced_rate=20.0)
+    oh = oracle_train(wl, 2, bs, forced_rate=20.0)
+    td = _train_mode(wl, "fp32", 1, bs, True, forced_rate=20.0)
+    for i in range(2):
+        for k in KEYS:
+            ok, e, ent = rel_close(gh["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
+            log(f"{name} delays+reg it {i} {k}: normwise {e:.2e} worst entry {ent:.2e}")
+            assert ok, (name, i, k, e, ent)
+        assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
+    for k in KEYS:
+        ok, e, ent = rel_close(td[0][1][k], oh["grads"][0][k], 1e-4, floor_frac=1e-2)
+        assert ok, ("time-driven", name, k, e, ent)
