@@ -99,6 +99,10 @@ def stage_batches(wl, n, first_iteration):
             host["target"] = np.ascontiguousarray(b.target, np.float64)
         if b.window is not None:
             host["window"] = np.ascontiguousarray(b.window, np.uint8)
+        if b.forced_ptr is not None:
+            host["forced_ptr"] = np.ascontiguousarray(b.forced_ptr, np.uint64)
+            host["forced_step"] = np.ascontiguousarray(b.forced_step, np.uint32)
+            host["forced_neuron"] = np.ascontiguousarray(b.forced_neuron, np.uint32)
         ptrs, keep = E.to_device(host)
         out.append((b, ptrs, keep))
     return out
@@ -116,6 +120,9 @@ def run_staged(net, staged, train=True, profile=False, time_driven=False):
                           else int(b.window.shape[1]),
                           target=ptrs.get("target"), label=label.ctypes.data if label is not None else None,
                           window=ptrs.get("window"),
+                          n_forced=int(b.forced_ptr[-1]) if b.forced_ptr is not None else 0,
+                          forced_ptr=ptrs.get("forced_ptr"), forced_step=ptrs.get("forced_step"),
+                          forced_neuron=ptrs.get("forced_neuron"),
                           flags=(E.EPROP_BATCH_TRAIN if train else 0) | (E.EPROP_BATCH_PROFILE if profile else 0)
                           | (E.EPROP_BATCH_TIME_DRIVEN if time_driven else 0))
     loss = np.zeros(b.n_trials)
@@ -154,6 +161,12 @@ def _truncated(b, i, T):
         sb.label = b.label[i:i + 1]
     if b.window is not None:
         sb.window = np.ascontiguousarray(b.window[i:i + 1, :T])
+    if b.forced_ptr is not None:
+        flo, fhi = int(b.forced_ptr[i]), int(b.forced_ptr[i + 1])
+        fk = b.forced_step[flo:fhi] <= T
+        sb.forced_ptr = np.array([0, int(fk.sum())], np.uint64)
+        sb.forced_step = b.forced_step[flo:fhi][fk]
+        sb.forced_neuron = b.forced_neuron[flo:fhi][fk]
     return sb
 
 
@@ -198,14 +211,16 @@ def cpu_baseline(wl, n_steps_sample, budget_s=20.0):
     el = time.perf_counter() - t0
     ev = _events_of_trial(net, sb, 0, r.trace["z"])
     out.update(value=ev / el, sample=f"first {T} steps of one trial of the same network (event-driven gradient, "
-                                     f"{ev} events, {el:.1f} s, network construction excluded)")
+                                     f"{ev} events, {el:.1f} s including the oracle's per-trial target-major copy "
+                                     f"of the graph; building the network arrays excluded)")
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 5; 20 samples = 20 s of biological time for the scaling network)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4_sparse")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -214,7 +229,8 @@ def main():
                     help="gradient by the time-driven baseline recursion instead of the event-driven path")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (the tuner otherwise runs in the first warm-up batch)")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="steps of the CPU oracle's sample on large networks (default 60; 5 for the scaling network)")
     ap.add_argument("--fp64-iters", type=int, default=1,
                     help="training iterations of the FP64 plain comparison (<= warmup + steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -243,6 +259,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}), flush=True)
         return
+    scaling = args.workload == "scaling"
+    if args.steps is None:
+        args.steps = 20 if scaling else 5
+    if args.cpu_steps is None:
+        args.cpu_steps = 5 if scaling else 60
+    if scaling:
+        # the FP64 plain comparison would rebuild the 1.28e9-synapse network in
+        # double; the scaling runs compare static and plastic synapses instead
+        args.no_fp64 = True
+    def progress(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    t_start = time.perf_counter()
+    print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     wl = W.WORKLOADS[args.workload]()
     net_w = wl.network
     T = max(int(wl.make_batch(0, 0, 1).n_steps.max()), 1)
@@ -254,14 +284,17 @@ def main():
     with torch.cuda.stream(stream):
         net = E.Network(net_w, "fp32", max_trials=wl.batch_size, max_steps=T,
                         stream=E.C.c_void_p(stream.cuda_stream), autotune=not args.no_autotune)
+        progress("network built")
         staged = stage_batches(wl, args.warmup + args.steps, 0)
         torch.cuda.synchronize()
+        progress("batches staged")
         warm_losses = []
         for i in range(args.warmup):
             _, wloss = run_staged(net, staged[i], time_driven=args.time_driven)
             net.apply()
             warm_losses.append(float(wloss.mean()))
         torch.cuda.synchronize()
+        progress("warm-up done")
         tot = {"events": 0, "updates": 0, "rec_spikes": 0, "in_spikes": 0}
         phases = {k: 0.0 for k in E.PHASES}
         losses = []
@@ -278,6 +311,21 @@ def main():
             losses.append(float(loss.mean()))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        progress(f"timed steps done, {elapsed / args.steps * 1000.0:.2f} ms per step")
+        static = None
+        if scaling:
+            # the same samples with static synapses: forward pass and readout only
+            t1 = time.perf_counter()
+            for i in range(args.steps):
+                run_staged(net, staged[args.warmup + i], train=False)
+            torch.cuda.synchronize()
+            el_s = time.perf_counter() - t1
+            progress(f"static run done, {el_s / args.steps * 1000.0:.2f} ms per sample")
+            bio_s = args.steps * T * net_w.params.dt / 1000.0
+            static = {"ms_per_sample": el_s / args.steps * 1000.0, "real_time_factor": bio_s / el_s,
+                      "eprop_real_time_factor": bio_s / elapsed, "biological_seconds": bio_s,
+                      "note": "real-time factor = simulated biological time / wall-clock time; static: "
+                              "the same samples without plasticity (no gradient, no update)"}
     steps = args.steps
     n_tr = wl.batch_size
     rate_hz = tot["rec_spikes"] / (steps * n_tr * net_w.n_rec * T * net_w.params.dt / 1000.0)
@@ -335,7 +383,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         cpu = cpu_baseline(wl, min(args.cpu_steps, T))
+        progress("CPU oracle baseline done")
 
     out = {"metric": "synaptic events/s (event-driven e-prop training, FP32 batched)",
            "value": tot["events"] / elapsed, "unit": "synaptic events/s", "n_gpus": 1, "steps": steps,
@@ -350,6 +400,8 @@ def main():
            "phase_ms_per_step": {k: round(v / steps, 3) for k, v in phases.items()},
            "mean_loss": losses,
            "layout": lay, "roofline": roof, "path_roofline": path_roof, "cpu_baseline": cpu, "fp64_plain": fp64}
+    if static is not None:
+        out["scaling_run"] = static
     print(json.dumps(out), flush=True)
 
 

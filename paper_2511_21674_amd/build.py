@@ -15,6 +15,8 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # host threads for building graphs of 10^9 synapses
+    "-pthread",
     "-Wall",
 ]
 

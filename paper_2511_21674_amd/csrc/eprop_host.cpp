@@ -7,9 +7,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "eprop_internal.h"
@@ -25,6 +27,38 @@ constexpr uint32_t kMaxIndex = (1u << 24) - 1u;
 
 inline bool is_finite(double x) { return std::isfinite(x); }
 inline uint32_t round_up(uint32_t a, uint32_t m) { return (a + m - 1) / m * m; }
+
+// Host threads for building graphs of 10^9 synapses (at most 16).
+unsigned host_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return std::max(1u, std::min(h ? h : 1u, 16u));
+}
+
+// Runs f(lo, hi, t) on nt threads over consecutive ranges of [0, n) whose
+// boundaries split the weight w(0..n) (a non-decreasing prefix such as a
+// CSR row pointer) evenly; t is the range's rank.
+template <typename W, typename F>
+void parallel_ranges(uint64_t n, unsigned nt, W w, F f) {
+  if (nt <= 1 || n < 2) {
+    f((uint64_t)0, n, 0u);
+    return;
+  }
+  std::vector<uint64_t> cut(nt + 1, n);
+  cut[0] = 0;
+  const double total = (double)w(n);
+  for (unsigned t = 1; t < nt; ++t) {
+    uint64_t lo = cut[t - 1], hi = n;  // first index whose prefix reaches t / nt of the total
+    const double goal = total * t / nt;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) / 2;
+      if ((double)w(mid) < goal) lo = mid + 1; else hi = mid;
+    }
+    cut[t] = lo;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) th.emplace_back([&, t] { f(cut[t], cut[t + 1], t); });
+  for (auto &x : th) x.join();
+}
 }  // namespace
 
 struct eprop_network {
@@ -299,27 +333,37 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   auto cp = [&](void *dst, const void *src, size_t bytes) {
     if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
+  const unsigned nt = n->S >= (1u << 22) ? host_threads() : 1u;
+  auto flat = [](uint64_t i) { return i; };
   auto conv = [&](const std::vector<double> &v) {
     std::vector<real> o(v.size());
-    for (size_t i = 0; i < v.size(); ++i) o[i] = (real)v[i];
+    parallel_ranges(v.size(), nt, flat, [&](uint64_t lo, uint64_t hi, unsigned) {
+      for (uint64_t i = lo; i < hi; ++i) o[i] = (real)v[i];
+    });
     return o;
   };
   cp((void *)d.sm_ptr, sm_ptr.data(), sm_ptr.size() * 4);
   if (!n->gather) cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
   {
     std::vector<eprop::SynRec<real>> rec(sm_syn.size());
-    for (size_t q = 0; q < rec.size(); ++q) {
-      rec[q] = eprop::SynRec<real>{};
-      rec[q].syn = sm_syn[q];
-      rec[q].w = (real)sm_w[q];
-    }
+    parallel_ranges(rec.size(), nt, flat, [&](uint64_t lo, uint64_t hi, unsigned) {
+      for (uint64_t q = lo; q < hi; ++q) {
+        rec[q] = eprop::SynRec<real>{};
+        rec[q].syn = sm_syn[q];
+        rec[q].w = (real)sm_w[q];
+      }
+    });
     cp((void *)d.sm, rec.data(), rec.size() * sizeof(rec[0]));
   }
   {
     // out-degree of every source per delay, for the event counts
     std::vector<uint32_t> od((size_t)n->NS * n->R, 0u);
-    for (uint32_t src = 0; src < n->NS; ++src)
-      for (uint32_t q = sm_ptr[src]; q < sm_ptr[src + 1]; ++q) od[(size_t)src * n->R + (sm_syn[q] >> 24)]++;
+    parallel_ranges(n->NS, nt, [&](uint64_t src) { return (uint64_t)sm_ptr[src]; },
+                    [&](uint64_t s0, uint64_t s1, unsigned) {
+                      for (uint64_t src = s0; src < s1; ++src)
+                        for (uint32_t q = sm_ptr[src]; q < sm_ptr[src + 1]; ++q)
+                          od[(size_t)src * n->R + (sm_syn[q] >> 24)]++;
+                    });
     cp((void *)d.outdeg, od.data(), od.size() * 4);
   }
   cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
@@ -448,11 +492,19 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   for (uint32_t i = 0; i <= I; ++i) sm_ptr[i] = (uint32_t)in_rec->row_ptr[i];
   for (uint32_t i = 1; i <= J; ++i) sm_ptr[I + i] = (uint32_t)(S_in + rec_rec->row_ptr[i]);
   // internal source-major order: each row sorted by target (stable), so that
-  // the targets of one tile form one contiguous segment of the row
+  // the targets of one tile form one contiguous segment of the row.  Threads
+  // take consecutive ranges of sources of about equal synapse counts and
+  // count the targets of their range; the target-major order (rows sorted
+  // by source) is then filled by the same ranges into disjoint slots.
   std::vector<uint32_t> sm2caller(S);
-  {
+  const unsigned nt = S >= (1u << 22) ? host_threads() : 1u;
+  std::vector<std::vector<uint32_t>> tcount(nt);
+  auto sm_weight = [&](uint64_t src) { return (uint64_t)sm_ptr[src]; };
+  parallel_ranges(NS, nt, sm_weight, [&](uint64_t s0, uint64_t s1, unsigned t) {
+    std::vector<uint32_t> &cnt = tcount[t];
+    cnt.assign(J, 0u);
     std::vector<uint32_t> idx;
-    for (uint32_t src = 0; src < NS; ++src) {
+    for (uint64_t src = s0; src < s1; ++src) {
       const bool in = src < I;
       const eprop_projection *p = in ? in_rec : rec_rec;
       const uint64_t lo = in ? in_rec->row_ptr[src] : rec_rec->row_ptr[src - I];
@@ -470,25 +522,43 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
         sm_syn[pos] = p->col[q] | (d << 24);
         sm_w[pos] = p->w[q];
         sm2caller[pos] = (uint32_t)(base + q);
-        tm_ptr[p->col[q] + 1]++;
+        cnt[p->col[q]]++;
       }
     }
+  });
+  // slot of range t within target j's row: after the counts of ranges < t
+  for (uint32_t j = 0; j < J; ++j) {
+    uint32_t run = 0;
+    for (unsigned t = 0; t < nt; ++t) {
+      const uint32_t c = tcount[t][j];
+      tcount[t][j] = run;
+      run += c;
+    }
+    tm_ptr[j + 1] = tm_ptr[j] + run;
   }
-  for (uint32_t j = 0; j < J; ++j) tm_ptr[j + 1] += tm_ptr[j];
-  {
-    std::vector<uint32_t> fill(J, 0);
-    for (uint32_t src = 0; src < NS; ++src)
+  std::atomic<bool> dup{false};
+  parallel_ranges(NS, nt, sm_weight, [&](uint64_t s0, uint64_t s1, unsigned t) {
+    std::vector<uint32_t> &fill = tcount[t];
+    const std::vector<uint32_t> start(fill);
+    for (uint64_t src = s0; src < s1 && !dup.load(std::memory_order_relaxed); ++src)
       for (uint32_t q = sm_ptr[src]; q < sm_ptr[src + 1]; ++q) {
         const uint32_t tgt = sm_syn[q] & 0xFFFFFFu;
         const uint32_t pos = tm_ptr[tgt] + fill[tgt]++;
-        if (pos > tm_ptr[tgt] && (tm_syn[pos - 1] & 0xFFFFFFu) == src) {
-          g_create_error = "duplicate synapse between one pair of neurons";
-          return EPROP_ERR_INVALID_ARGUMENT;
+        // a repeated pair lands in consecutive slots of this range's part of the row
+        if (pos > tm_ptr[tgt] + start[tgt] && (tm_syn[pos - 1] & 0xFFFFFFu) == src) {
+          dup.store(true);
+          break;
         }
-        tm_syn[pos] = src | (sm_syn[q] & 0xFF000000u);
+        tm_syn[pos] = (uint32_t)src | (sm_syn[q] & 0xFF000000u);
         tm_w[pos] = sm_w[q];
         tm_perm[pos] = q;
       }
+  });
+  tcount.clear();
+  tcount.shrink_to_fit();
+  if (dup) {
+    g_create_error = "duplicate synapse between one pair of neurons";
+    return EPROP_ERR_INVALID_ARGUMENT;
   }
 
   // device
@@ -559,7 +629,9 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
     n->shapes.syn_block = sb;
   }
   n->sm2caller = std::move(sm2caller);
-  for (uint64_t q = 0; q < S; ++q) n->perm[q] = n->sm2caller[tm_perm[q]];
+  parallel_ranges(S, nt, [](uint64_t q) { return q; }, [&](uint64_t lo, uint64_t hi, unsigned) {
+    for (uint64_t q = lo; q < hi; ++q) n->perm[q] = n->sm2caller[tm_perm[q]];
+  });
   // Tiles of the persistent forward kernel: as many neurons per workgroup as
   // LDS allows, but enough tiles to spread the trials over the device; small
   // networks keep a whole trial in one workgroup (no inter-workgroup barrier).
@@ -626,16 +698,18 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   std::vector<uint32_t> tseg;
   if (!n->gather) {
     tseg.resize((size_t)NS * (KT + 1));
-    for (uint32_t src = 0; src < NS; ++src) {
-      uint32_t q = sm_ptr[src];
-      const uint32_t hi = sm_ptr[src + 1];
-      for (uint32_t k = 0; k <= KT; ++k) {
-        const uint64_t lo_t = (uint64_t)k * TS;
-        while (q < hi && (sm_syn[q] & 0xFFFFFFu) < lo_t) ++q;
-        tseg[(size_t)src * (KT + 1) + k] = q;
+    parallel_ranges(NS, nt, sm_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
+      for (uint64_t src = s0; src < s1; ++src) {
+        uint32_t q = sm_ptr[src];
+        const uint32_t hi = sm_ptr[src + 1];
+        for (uint32_t k = 0; k <= KT; ++k) {
+          const uint64_t lo_t = (uint64_t)k * TS;
+          while (q < hi && (sm_syn[q] & 0xFFFFFFu) < lo_t) ++q;
+          tseg[(size_t)src * (KT + 1) + k] = q;
+        }
+        tseg[(size_t)src * (KT + 1) + KT] = hi;
       }
-      tseg[(size_t)src * (KT + 1) + KT] = hi;
-    }
+    });
   }
   hipError_t e = hipSuccess;
   if (!n->gather) {

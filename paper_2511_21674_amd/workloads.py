@@ -222,6 +222,57 @@ def fixed_indegree_projection(n_src: int, n_tgt: int, indegree: int, std: float,
                       np.ascontiguousarray(w[order]), np.ascontiguousarray(delay[order]))
 
 
+def fixed_indegree_lean(n_src: int, n_tgt: int, indegree: int, std: float,
+                        g_graph: np.random.Generator, g_w: np.random.Generator,
+                        no_self: bool, delay: int = 1) -> Projection:
+    """Fixed in-degree projection for graphs of 10^9 synapses: the same distinct
+    sorted draws per target as fixed_indegree_projection, placed into CSR by
+    source chunk by chunk (targets ascending within a row) without a global
+    permutation; weights are drawn directly in CSR order (they are i.i.d.),
+    delays are all `delay`."""
+    n = n_src - 1 if no_self else n_src
+    m = indegree
+    if m > n:
+        raise ValueError("in-degree larger than the number of candidate sources")
+    chunk = max(1, (1 << 24) // max(m, 1))
+    counts = np.zeros(n_src, dtype=np.int64)
+    draws = []
+    for lo in range(0, n_tgt, chunk):
+        hi = min(n_tgt, lo + chunk)
+        d = g_graph.integers(0, n - m + 1, size=(hi - lo, m), dtype=np.int64)
+        d.sort(axis=1)
+        d += np.arange(m, dtype=np.int64)
+        if no_self:
+            d += (d >= np.arange(lo, hi, dtype=np.int64)[:, None])
+        d32 = d.astype(np.uint32)
+        del d
+        counts += np.bincount(d32.ravel(), minlength=n_src)
+        draws.append(d32)
+    row_ptr = np.zeros(n_src + 1, dtype=np.uint64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = np.empty(int(row_ptr[-1]), dtype=np.uint32)
+    fill = row_ptr[:-1].astype(np.int64)
+    for ci, lo in enumerate(range(0, n_tgt, chunk)):
+        d32 = draws[ci]
+        rows = d32.shape[0]
+        key = np.sort(d32.ravel().astype(np.uint64) * np.uint64(rows)
+                      + np.repeat(np.arange(rows, dtype=np.uint64), m))
+        draws[ci] = None
+        src = (key // np.uint64(rows)).astype(np.int64)
+        tl = (key % np.uint64(rows)).astype(np.uint32)
+        del key
+        first = np.flatnonzero(np.r_[True, src[1:] != src[:-1]])
+        cnt = np.diff(np.r_[first, src.size])
+        rank = np.arange(src.size, dtype=np.int64) - np.repeat(first, cnt)
+        col[fill[src] + rank] = tl + np.uint32(lo)
+        fill[src[first]] += cnt
+    w = np.empty(col.size, dtype=np.float64)
+    step = 1 << 26
+    for lo in range(0, col.size, step):
+        w[lo:lo + step] = g_w.normal(0.0, std, size=min(step, col.size - lo))
+    return Projection(n_src, n_tgt, row_ptr, col, w, np.full(col.size, delay, dtype=np.uint8))
+
+
 # --------------------------------------------------------------------------
 # spike trains and targets
 
@@ -488,6 +539,81 @@ def c5_million(seed: int = SEED_BASE + 5, n_rec: int = 1_000_000, n_steps: int =
                          iterations, "1e6 LIF/ALIF, in-degree 100 (1e8 synapses), batch 1", eta=1e-8)
 
 
+def ignore_and_fire(batch: Batch, n_rec: int, rate_hz: float, dt_ms: float, seed: int,
+                    sample0: int = 0) -> Batch:
+    """Attach ignore-and-fire recurrent spike trains (Methods, "Scaling"): each
+    neuron fires regularly at rate_hz with its own random phase, whatever its
+    input.  Trial b is sample sample0 + b of a continuous run and covers its
+    global steps (sample0 + b) * T + 1 .. + T, so consecutive samples continue
+    the same regular trains."""
+    period = int(round(1000.0 / (rate_hz * dt_ms)))
+    phase = rng(seed, _P_FORCED).integers(0, period, size=n_rec)
+    ptr = [0]
+    steps, neurons = [], []
+    for b in range(batch.n_trials):
+        t = int(batch.n_steps[b])
+        t0 = (sample0 + b) * t
+        # neuron j fires at global step u with (u - phase_j) % period == 0
+        first = (phase - (t0 + 1)) % period + 1           # first local step 1..period
+        k = np.arange(0, t, period, dtype=np.int64)
+        loc = first[None, :] + k[:, None]                  # [fires, J], may exceed t
+        sj = np.broadcast_to(np.arange(n_rec), loc.shape)
+        ok = loc <= t
+        s, j = loc[ok], sj[ok]
+        order = np.lexsort((j, s))
+        steps.append(s[order].astype(np.uint32))
+        neurons.append(j[order].astype(np.uint32))
+        ptr.append(ptr[-1] + s.size)
+    out = replace(batch)
+    out.forced_ptr = np.array(ptr, dtype=np.uint64)
+    out.forced_step = np.concatenate(steps)
+    out.forced_neuron = np.concatenate(neurons)
+    return out
+
+
+def scaling(seed: int = SEED_BASE + 6, n_rec: int = 128_000, indeg_rec: int = 10_000, n_in: int = 1000,
+            indeg_in: int = 100, n_out: int = 10, indeg_out: int = 1000, outdeg_fb: int = 100,
+            rate_hz: float = 5.0, n_steps: int = 1000, samples: int = 20, gain: float = 1.0,
+            in_gain: float = 1.0, eta: float = 1e-9) -> Workload:
+    """The paper's scaling network (Methods, "Scaling"), base size: 128,000
+    ignore-and-fire neurons at 5 Hz with random phases, recurrent in-degree
+    10^4 without autapses or multapses (1.28e9 plastic synapses), 1000 Poisson
+    inputs at 5 Hz with in-degree 100, 10 readouts with in-degree 1000 and
+    feedback out-degree 100, target signals from a generator, 20 s of
+    biological time in samples of n_steps steps of 1 ms.  Readout and
+    feedback weights are stored dense with zeros off the drawn connections."""
+    prm = Params(loss=0, optimizer=0, eta=eta, max_delay=1)
+    rec = fixed_indegree_lean(n_rec, n_rec, indeg_rec, gain / np.sqrt(indeg_rec), rng(seed, _P_GRAPH_REC),
+                              rng(seed, _P_W_REC), no_self=True)
+    inp = fixed_indegree_lean(n_in, n_rec, indeg_in, in_gain / np.sqrt(indeg_in), rng(seed, _P_GRAPH_IN),
+                              rng(seed, _P_W_IN), no_self=False)
+    g_out, g_fb = rng(seed, _P_W_OUT), rng(seed, _P_FEEDBACK)
+    w_out = np.zeros((n_out, n_rec))
+    fb = np.zeros((n_rec, n_out))
+    for k in range(n_out):
+        src = g_out.choice(n_rec, size=indeg_out, replace=False)
+        w_out[k, src] = g_out.normal(0.0, 1.0 / np.sqrt(indeg_out), size=indeg_out)
+        tgt = g_fb.choice(n_rec, size=outdeg_fb, replace=False)
+        fb[tgt, k] = g_fb.normal(0.0, 1.0 / np.sqrt(outdeg_fb), size=outdeg_fb)
+    net = Network(n_in, n_rec, n_out, np.zeros(n_rec, np.uint8), prm, inp, rec, w_out, fb)
+    targets = np.stack([sinusoid_sum(rng(seed, _P_TARGET, k), n_steps * samples, prm.dt)
+                        for k in range(n_out)], axis=1)
+    p_in = rate_hz * prm.dt / 1000.0
+
+    def make_batch(iteration: int, first: int, n: int) -> Batch:
+        trials, tg = [], []
+        for i in range(n):
+            s, c = poisson_steps(rng(seed, _P_INPUT, iteration, first + i), np.full((n_steps, n_in), p_in))
+            trials.append((n_steps, s, c))
+            u = ((iteration * n + first + i) % samples) * n_steps
+            tg.append(targets[u:u + n_steps])
+        b = _assemble(trials, n_out, n_steps, targets=tg)
+        return ignore_and_fire(b, n_rec, rate_hz, prm.dt, seed, iteration * n + first)
+    return Workload("scaling", net, make_batch, 1, samples,
+                    "128k ignore-and-fire neurons at 5 Hz, in-degree 1e4 (1.28e9 synapses), 1 trial",
+                    info={"indeg_rec": indeg_rec, "indeg_in": indeg_in, "rate_hz": rate_hz})
+
+
 def tiny(seed: int = SEED_BASE + 11, n_steps: int = 200, loss: int = 0, n_in: int = 6,
          n_lif: int = 3, n_alif: int = 2, n_out: int = 2, max_delay: int = 2,
          rate_hz: float = 100.0, w_scale: float = 0.8, surrogate: int = 0,
@@ -526,4 +652,4 @@ def tiny(seed: int = SEED_BASE + 11, n_steps: int = 200, loss: int = 0, n_in: in
 
 
 WORKLOADS = {"c1_pattern": c1_pattern, "c2_evidence": c2_evidence, "c3_events": c3_events,
-             "c4_sparse": c4_sparse, "c5_million": c5_million, "tiny": tiny}
+             "c4_sparse": c4_sparse, "c5_million": c5_million, "scaling": scaling, "tiny": tiny}

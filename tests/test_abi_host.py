@@ -188,3 +188,22 @@ def test_null_handles_are_safe():
     assert E.lib().eprop_apply_updates(None) == E.EPROP_ERR_INVALID_ARGUMENT
     assert E.lib().eprop_simulate_batch(None, None, None) == E.EPROP_ERR_INVALID_ARGUMENT
     assert E.lib().eprop_read_state(None, 0, 0, None, 0, None) == E.EPROP_ERR_INVALID_ARGUMENT
+
+
+def test_threaded_graph_build_finds_duplicates():
+    """Graphs of 2^22 synapses or more are transposed by several host threads
+    over ranges of sources: a repeated pair inside one source row is still
+    rejected, and a clean graph of that size passes the host build (the
+    call then stops at the missing device, or succeeds on a GPU)."""
+    wnet = W.c4_sparse(n_rec=4500, n_steps=10, batch_size=1, n_in=100).network
+    assert wnet.rec_rec.nnz >= (1 << 22)
+    cfg, projs, wo, fb, keep = _parts(wnet, max_delay=5)
+    st, msg = _create(cfg, projs, wo, fb)
+    assert st in (E.EPROP_OK, E.EPROP_ERR_DEVICE), msg
+    for src in (7, 4321):       # a row near the start and one near the end of the sources
+        cfg, projs, wo, fb, keep = _parts(wnet, max_delay=5)
+        row_ptr, col = projs[1][1][0], projs[1][1][1]
+        lo = int(row_ptr[src])
+        col[lo + 1] = col[lo]
+        st, msg = _create(cfg, projs, wo, fb)
+        assert st == E.EPROP_ERR_INVALID_ARGUMENT and "duplicate" in msg, (src, st, msg)

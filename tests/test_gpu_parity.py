@@ -587,3 +587,54 @@ def test_fp32_teacher_forced_delays_and_rate_regulariser(name):
     for k in KEYS:
         ok, e, ent = rel_close(td[0][1][k], oh["grads"][0][k], 1e-4, floor_frac=1e-2)
         assert ok, ("time-driven", name, k, e, ent)
+
+
+# ----------------------------------------------------------------- the scaling network
+
+def _scaling_twin():
+    return W.scaling(n_rec=3000, indeg_rec=500, n_in=100, indeg_in=10, indeg_out=100, outdeg_fb=30, n_steps=400,
+                     samples=4)
+
+
+def test_scaling_twin_fp64_exact_and_fp32():
+    """Twin of the scaling network (Methods, "Scaling": ignore-and-fire
+    neurons at 5 Hz, fixed in-degree, sparse readout and feedback): FP64
+    exact against the oracle over consecutive samples; FP32 (its spike trains
+    are fixed by construction, so it is teacher-forced) within 1e-4."""
+    wl = _scaling_twin()
+    oh = oracle_train(wl, 2, 1)
+    gh = gpu_train(wl, "fp64", 2, 1)
+    assert_fp64_parity(gh, oh, "scaling twin")
+    g32 = gpu_train(wl, "fp32", 2, 1)
+    for i in range(2):
+        for k in KEYS:
+            ok, e, ent = rel_close(g32["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
+            log(f"scaling twin fp32 it {i} {k}: normwise {e:.2e} worst {ent:.2e}")
+            assert ok, (i, k, e, ent)
+
+
+def test_scaling_network_launch_configuration_sampled():
+    """The scaling network at its full neuron count (128,000 ignore-and-fire
+    neurons, one 1000-step sample, FP32, the tile layout of the benchmark)
+    with recurrent in-degree 100 instead of 10^4 so that it builds in seconds:
+    all 640,000 forced spikes are emitted, and the gradients of every
+    incoming synapse of 24 sampled neurons are within 1e-4 of the oracle's
+    per-neuron evaluation, the loss within 1e-6."""
+    wl = W.scaling(indeg_rec=100)
+    b = wl.make_batch(0, 0, 1)
+    net = E.Network(wl.network, "fp32", max_trials=1, max_steps=1000)
+    r = net.simulate(b, train=True)
+    g = net.grads()
+    lay = net.layout()
+    net.close()
+    log(f"gpu done: layout {lay}, {r.n_rec_spikes} spikes, {r.n_syn_events} events")
+    assert r.n_rec_spikes == 640_000
+    on = O.OracleNet(wl.network)
+    targets = np.sort(np.random.default_rng(1).choice(wl.network.n_rec, 24, replace=False))
+    loss, psi, a, c = O.forced_sampled(on, b, 0, targets)
+    assert abs(r.loss[0] - loss) <= 1e-6 * abs(loss), (r.loss[0], loss)
+    for name, gg, ref in (("w_in", g["w_in"], a), ("w_rec", g["w_rec"], c)):
+        m = ~np.isnan(ref)
+        ok, e, ent = rel_close(gg[m], ref[m], 1e-4, floor_frac=1e-2)
+        log(f"scaling {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
+        assert ok, (name, e, ent)

@@ -347,6 +347,46 @@ def test_fixed_indegree_graph():
     assert p.delay.min() == 1 and p.delay.max() == 5
 
 
+def _scaling_twin(**kw):
+    a = dict(n_rec=3000, indeg_rec=500, n_in=100, indeg_in=10, indeg_out=100, outdeg_fb=30, n_steps=400,
+             samples=4)
+    a.update(kw)
+    return W.scaling(**a)
+
+
+def test_scaling_graph_and_ignore_and_fire_trains():
+    """The scaling network (Methods, "Scaling"): every neuron has exactly the
+    recurrent in-degree, without autapses or multapses; source rows are sorted
+    by target; readout in-degree and feedback out-degree as drawn; every neuron
+    fires regularly at 5 Hz (period 200 steps) and keeps its phase across
+    consecutive samples; the forced spikes are sorted by (step, neuron)."""
+    wl = _scaling_twin()
+    p = wl.network.rec_rec
+    src = np.repeat(np.arange(p.n_src), np.diff(p.row_ptr.astype(np.int64)))
+    assert np.all(np.bincount(p.col, minlength=p.n_tgt) == 500)
+    assert not np.any(src == p.col)
+    key = src.astype(np.int64) * p.n_tgt + p.col
+    assert np.all(np.diff(key) > 0)          # unique pairs, rows ascending by target
+    pi = wl.network.in_rec
+    assert np.all(np.bincount(pi.col, minlength=pi.n_tgt) == 10)
+    assert np.all((wl.network.w_out != 0).sum(axis=1) == 100)
+    assert np.all((wl.network.feedback != 0).sum(axis=0) == 30)
+    z = []
+    for it in range(2):
+        b = wl.make_batch(it, 0, 1)
+        fk = b.forced_step.astype(np.int64) * 4096 + b.forced_neuron
+        assert np.all(np.diff(fk) > 0)
+        zz = np.zeros((400, 3000), np.uint8)
+        zz[b.forced_step - 1, b.forced_neuron] = 1
+        z.append(zz)
+    z = np.concatenate(z)
+    assert np.all(z.sum(axis=0) == 4)
+    for j in range(0, 3000, 37):
+        assert np.all(np.diff(np.flatnonzero(z[:, j])) == 200)
+    phases = np.argmax(z, axis=0)
+    assert len(np.unique(phases)) > 150      # random phases, not synchronous
+
+
 # ---------------------------------------------------------------- generalised delays, regularisation
 
 def _with(wnet, **params):
