@@ -305,8 +305,12 @@ typedef enum {
                                   forward launch, gather delivery (0/1), synapses per delivery
                                   piece, pieces in flight per lane group, adjoint-kernel
                                   threads, autotuned (0/1) */
-  EPROP_STATE_L = 19           /* last batch, trial: double [T_b * J] learning signal
+  EPROP_STATE_L = 19,          /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
+  EPROP_STATE_INPUT_BOUND = 20 /* double [1]: the bound on |input current| of one step used to
+                                  size the FP32 fixed-point delay ring: the largest sum of |w|
+                                  over one target's incoming synapses, with a small margin
+                                  (recomputed by create and by every update) */
 } eprop_state_id;
 
 /* Copies one state array to host memory dst (dst_bytes large).  With

@@ -78,6 +78,8 @@ struct eprop_network {
   std::vector<uint32_t> perm;       // target-major index -> caller's synapse index
   std::vector<uint32_t> sm2caller;  // internal source-major index -> caller's synapse index
   size_t tile_smem = 0;             // dynamic LDS of the tiled forward kernel
+  bool blocked = false;             // weight update as a blocked transposition (k_apply_blk)
+  uint32_t n_ach = 0;               // its blocks
   void *partial = nullptr;          // per trial-chunk synapse sums (large batches)
   void *Lbuf = nullptr;             // learning signal of the time-driven baseline (allocated on first use)
   size_t cap_Lbuf = 0;
@@ -255,7 +257,8 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &p32, n->S); d.tm_syn = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_perm = p32;
   ok &= dalloc(n, &p32, (size_t)n->NS * n->R); d.outdeg = p32;
-  ok &= dalloc(n, &d.tm_w, n->S);
+  if (n->blocked) ok &= dalloc(n, &d.tsum, n->Jp);
+  else ok &= dalloc(n, &d.tm_w, n->S);
   ok &= dalloc(n, &d.gs, n->S);
   ok &= dalloc(n, &d.gc, n->S);
   if (n->adam) {
@@ -369,7 +372,63 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
   cp((void *)d.tm_syn, tm_syn.data(), tm_syn.size() * 4);
   cp((void *)d.tm_perm, tm_perm.data(), tm_perm.size() * 4);
-  { auto o = conv(tm_w); cp(d.tm_w, o.data(), o.size() * sizeof(real)); }
+  if (!n->blocked) {
+    auto o = conv(tm_w);
+    cp(d.tm_w, o.data(), o.size() * sizeof(real));
+  } else {
+    // blocks of the update: per tile, consecutive sources with at most
+    // kApplySyn * 4 bytes of gradients into the tile (and at most kApplySrc
+    // sources), tile-major; then where each target's run of a block's
+    // sources starts in its row
+    const uint32_t KT = d.KT, TS = d.TS;
+    const uint64_t cap = (uint64_t)eprop::kApplySyn * 4 / sizeof(real);
+    std::vector<uint32_t> ach, first(KT + 1, 0);
+    for (uint32_t k = 0; k < KT; ++k) {
+      first[k] = (uint32_t)(ach.size() / 3);
+      uint32_t s0 = 0;
+      uint64_t acc = 0;
+      for (uint32_t src = 0; src < n->NS; ++src) {
+        const uint32_t len = tseg[(size_t)src * (KT + 1) + k + 1] - tseg[(size_t)src * (KT + 1) + k];
+        if (src > s0 && (acc + len > cap || src - s0 >= eprop::kApplySrc)) {
+          if (acc) ach.insert(ach.end(), {k, s0, src});
+          s0 = src;
+          acc = 0;
+        }
+        acc += len;
+      }
+      if (acc) ach.insert(ach.end(), {k, s0, n->NS});
+    }
+    n->n_ach = (uint32_t)(ach.size() / 3);
+    first[KT] = n->n_ach;
+    std::vector<uint32_t> trs((size_t)n->n_ach * TS, 0u);
+    parallel_ranges(KT, nt, flat, [&](uint64_t k0, uint64_t k1, unsigned) {
+      std::vector<uint32_t> cur(TS);
+      for (uint64_t k = k0; k < k1; ++k) {
+        for (uint32_t t = 0; t < TS; ++t) {
+          const uint64_t j = k * TS + t;
+          cur[t] = j < n->J ? tm_ptr[j] : 0u;
+        }
+        for (uint32_t c = first[k]; c < first[k + 1]; ++c) {
+          const uint32_t s1 = ach[3 * (size_t)c + 2];
+          for (uint32_t t = 0; t < TS; ++t) {
+            const uint64_t j = k * TS + t;
+            trs[(size_t)c * TS + t] = cur[t];
+            if (j >= n->J) continue;
+            while (cur[t] < tm_ptr[j + 1] && (tm_syn[cur[t]] & 0xFFFFFFu) < s1) ++cur[t];
+          }
+        }
+      }
+    });
+    uint32_t *pa = nullptr, *pt = nullptr;
+    if (n->n_ach) {
+      if (!dalloc(n, &pa, ach.size()) || !dalloc(n, &pt, trs.size())) return hipErrorOutOfMemory;
+      cp(pa, ach.data(), ach.size() * 4);
+      cp(pt, trs.data(), trs.size() * 4);
+    }
+    d.ach = pa;
+    d.trs = pt;
+    if (e == hipSuccess) e = hipMemset(d.tsum, 0, (size_t)n->Jp * 8);
+  }
   { auto o = conv(beta); cp((void *)d.beta_j, o.data(), o.size() * sizeof(real)); }
   const size_t KJ = (size_t)n->K * n->Jp;
   std::vector<double> wo(KJ, 0.0), fbp(KJ, 0.0);
@@ -386,7 +445,8 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   if (e == hipSuccess) e = hipMemset(d.goc, 0, KJ * sizeof(real));
   if (e == hipSuccess) e = hipMemset(d.cnt, 0, eprop::CNT_WORDS * 8);
   if (e == hipSuccess) {
-    Launch<real>::input_bound(d, nullptr);
+    if (n->blocked) Launch<real>::input_bound_blocked(d, n->n_ach, nullptr);
+    else Launch<real>::input_bound(d, nullptr);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipDeviceSynchronize();
   }
@@ -394,8 +454,11 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     // optimiser state: caller order -> target-major
     std::vector<double> m(n->S, 0.0), v(n->S, 0.0), mo(KJ, 0.0), vo(KJ, 0.0);
     if (opt) {
+      // source-major for the blocked update, target-major otherwise (the
+      // order in which the update kernel visits the synapses)
+      const std::vector<uint32_t> &ord = n->blocked ? n->sm2caller : n->perm;
       for (uint64_t q = 0; q < n->S; ++q) {
-        const uint32_t c = n->perm[q];
+        const uint32_t c = ord[q];
         const double *ms = c < n->S_in ? opt->m_in : opt->m_rec;
         const double *vs = c < n->S_in ? opt->v_in : opt->v_rec;
         const uint64_t o = c < n->S_in ? c : c - n->S_in;
@@ -676,6 +739,11 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
       return EPROP_ERR_UNSUPPORTED;
     }
     n->tile_smem = smem_of(TS, ring_bytes);
+    // blocked transposition for the update where source rows are dense within
+    // a tile (at least 4 synapses per source and tile on average)
+    const size_t blk_lds = n->fp64 ? Launch<double>::apply_blocked_smem(TS) : Launch<float>::apply_blocked_smem(TS);
+    n->blocked = TS <= eprop::kApplyMaxTile && blk_lds <= lds &&
+                 (double)S >= 4.0 * (double)NS * (double)((n->Jp + TS - 1) / TS);
   }
   n->shapes.tile_block = tile_block;
   n->n32.TS = n->n64.TS = TS;
@@ -1221,9 +1289,14 @@ eprop_status apply(eprop_network *n, DevNet<real> &d) {
   const double step = (double)n->adam_step;
   // eq. eta-adam-fast
   const double eta_t = n->cfg.eta * std::sqrt(1.0 - std::pow(b2, step)) / (1.0 - std::pow(b1, step));
-  Launch<real>::apply(d, n->S, (double)n->trials_accum, n->cfg.optimizer, n->cfg.eta, eta_t, b1, b2,
-                      n->cfg.adam_eps_hat, n->stream);
-  Launch<real>::input_bound(d, n->stream);
+  if (!n->blocked) {
+    Launch<real>::apply(d, n->S, (double)n->trials_accum, n->cfg.optimizer, n->cfg.eta, eta_t, b1, b2,
+                        n->cfg.adam_eps_hat, n->stream);
+    Launch<real>::input_bound(d, n->stream);
+  } else {
+    Launch<real>::apply_blocked(d, n->n_ach, n->S, (double)n->trials_accum, n->cfg.optimizer, n->cfg.eta, eta_t,
+                                b1, b2, n->cfg.adam_eps_hat, n->stream);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
   if (e != hipSuccess) {
@@ -1240,7 +1313,7 @@ template <typename real>
 eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t what, uint32_t trial,
                         void *dst, size_t dst_bytes, size_t *needed) {
   const bool per_trial = (what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V) || what == EPROP_STATE_L;
-  if (what < 0 || what > EPROP_STATE_L) return EPROP_ERR_INVALID_ARGUMENT;
+  if (what < 0 || what > EPROP_STATE_INPUT_BOUND) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
     const uint64_t lay[12] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                               n->blk, n->gather ? 1u : 0u, eprop::fwd_variant_piece(n->shapes.fwd_variant),
@@ -1267,6 +1340,15 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   size_t bytes = 0;
   const void *payload = nullptr;
   switch (what) {
+    case EPROP_STATE_INPUT_BOUND: {
+      if (!dst) { bytes = 8; break; }
+      uint32_t bits = 0;
+      e = hipMemcpy(&bits, d.l1max, 4, hipMemcpyDeviceToHost);
+      float f;
+      std::memcpy(&f, &bits, 4);
+      outd.assign(1, (double)f);
+      break;
+    }
     case EPROP_STATE_W_IN:
     case EPROP_STATE_W_REC: {
       const bool in = what == EPROP_STATE_W_IN;
@@ -1296,8 +1378,10 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
         e = fetch(m ? d.adam_m : d.adam_v, n->S, a);
       }
       outd.assign(cnt, 0.0);
+      const bool grad = what == EPROP_STATE_GRAD_IN || what == EPROP_STATE_GRAD_REC;
+      const std::vector<uint32_t> &ord = (grad || !n->blocked) ? n->perm : n->sm2caller;
       for (uint64_t q = 0; q < n->S && e == hipSuccess; ++q) {
-        const uint32_t o = n->perm[q];
+        const uint32_t o = ord[q];
         const bool is_in = o < n->S_in;
         if (is_in != in) continue;
         outd[in ? o : o - n->S_in] = (double)a[q] + (c.empty() ? 0.0 : (double)c[q]);

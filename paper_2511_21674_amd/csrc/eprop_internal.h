@@ -7,7 +7,13 @@
 //                        (sources: inputs 0..I-1, then recurrent I..I+J-1;
 //                        each target's list sorted by source), tm_perm[S]
 //                        (target-major index -> source-major index)
-//   gradient sums        gs[S], gc[S] (Kahan pair, target-major), Adam m, v
+//   gradient sums        gs[S], gc[S] (Kahan pair, target-major), Adam m, v (source-major
+//                        with scatter delivery, target-major with gather delivery)
+//   weight update        (scatter delivery, rows dense within a tile) blocks
+//                        ach[3 * n_ach] = (tile, first source, end source), each at most
+//                        kApplySyn synapses into one tile's targets; trs[n_ach][TS]: where
+//                        each target's run of the block's sources starts in its row;
+//                        tsum[Jp] per-target sum of |w| in fixed point (the input bound)
 //   neuron state         v[b][Jp], a[b][Jp], nst[b][Jp] (refractory count | z << 7)
 //   delay ring           ring[b][R][Jp], R = max_delay + 1 (scatter delivery; held in
 //                        LDS by the tile that owns the targets, saved between launches;
@@ -39,6 +45,11 @@ enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE =
 enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_FLUSH = 2, CNT_WORDS = 8 };
 constexpr uint32_t kScanItems = 4096;        // entries per block of the spike-table scan
 constexpr uint32_t kNoRecord = 0xFFFFFFFFu;  // spike-table offset of a source without spikes
+constexpr uint32_t kApplySyn = 16384;        // synapses per weight-update block (at most, FP32)
+constexpr uint32_t kApplySrc = 2048;         // sources per weight-update block (at most)
+constexpr uint32_t kApplyMaxTile = 8192;     // tile size the blocked update supports
+constexpr double kBoundScale = 65536.0;      // fixed-point scale of the per-target |w| sums
+constexpr double kBoundMaxW = 4194304.0;     // |w| from which the bound saturates (2^22)
 
 // One source-major synapse: packed target and delay, and the weight, read
 // together by a single load.
@@ -86,7 +97,11 @@ struct DevNet {
   const uint32_t *sm_ptr, *tseg;
   SynRec<real> *sm;
   const uint32_t *tm_ptr, *tm_syn, *tm_perm;
-  real *tm_w, *gs, *gc, *adam_m, *adam_v;
+  real *tm_w;                   // target-major weights (gather delivery only)
+  real *gs, *gc, *adam_m, *adam_v;
+  const uint32_t *ach;          // blocked update: blocks (tile, first source, end source)
+  const uint32_t *trs;          // blocked update: [n_ach][TS] start of each target's run
+  unsigned long long *tsum;     // blocked update: [Jp] per-target sum of |w| * kBoundScale
   const real *beta_j;           // beta_a for ALIF neurons, 0 for LIF [Jp]
   real *w_out, *fb;             // [K][Jp], [Jp][K]
   real *gos, *goc, *adam_mo, *adam_vo;   // [K][Jp]
@@ -167,6 +182,13 @@ struct Launch {
   static void output_reduce(const DevNet<real> &n, hipStream_t s);
   static void apply(const DevNet<real> &n, uint64_t n_syn, double n_trials, int optimizer, double eta,
                     double eta_t, double b1, double b2, double eps_hat, hipStream_t s);
+  // the update as a blocked transposition (n_ach blocks of one tile's targets
+  // and a range of sources), which also recomputes *l1max; gs, gc cleared
+  static void apply_blocked(const DevNet<real> &n, uint32_t n_ach, uint64_t n_syn, double n_trials,
+                            int optimizer, double eta, double eta_t, double b1, double b2, double eps_hat,
+                            hipStream_t s);
+  static void input_bound_blocked(const DevNet<real> &n, uint32_t n_ach, hipStream_t s);
+  static size_t apply_blocked_smem(uint32_t TS);   // static + dynamic LDS of one update block
   // the gradient of the batch by the time-driven recursion (baseline); L: [Bcap][Tcap+1][Jp]
   static void time_driven(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *L, real *partial,
                           hipStream_t s);

@@ -14,7 +14,9 @@
 //                           k_adjoint (per-neuron arrival archive phi)
 //                           k_synapse (event-driven synapse gradient)
 //                           k_output_reduce
-//   end of iteration        k_apply_syn, k_apply_out (GD or Adam)
+//   end of iteration        k_apply_blk (scatter delivery, rows dense within a tile)
+//                           or k_apply_syn,
+//                           k_apply_out (GD or Adam)
 //
 // The synapse gradient.  For a synapse (i -> j, delay D) with arrival
 // indicator x^t, e-prop accumulates g = sum_t L_j^t F_kappa(e^t) with
@@ -1182,6 +1184,167 @@ __global__ __launch_bounds__(256) void k_apply_out(DevNet<real> n, double n_tria
 // One wavefront per target (coalesced over its target-major row); the
 // maximum over targets, slightly enlarged to cover the rounding of the sum,
 // goes to *l1max (positive floats order like their bit patterns).
+// Weight update with scatter delivery on networks whose rows are dense
+// within a tile (many synapses per source and tile): an explicit blocked
+// transposition through LDS.  Block c owns the synapses from sources
+// s0..s1-1 into the targets of tile k.  Source rows are sorted by target,
+// so these are one contiguous segment of each source row (tseg); target
+// rows are sorted by source, so they are also one contiguous run of each
+// target row (starting at trs[c][t]).  The block reads the runs' gradients
+// (Kahan pairs) and their source-major positions, puts each averaged
+// gradient into LDS at its place in the block's source-major order, and
+// then updates the source-major weight records segment by segment: both
+// sides of HBM are read and written in runs, with no scattered words.  It
+// also sums |w| per target of the tile in LDS (fixed point, each term
+// rounded up, so the sum bounds the input current of any step) and adds
+// the sums to tsum; k_bound_max turns the largest into *l1max.
+// UPDATE = false only recomputes the bound.
+template <typename real, bool UPDATE>
+__global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_ach, double n_trials, int opt,
+                                                    double eta, double eta_t, double b1, double b2, double eps) {
+  constexpr uint32_t NT = 1024;
+  constexpr uint32_t PER_S = kApplySrc / NT;
+  constexpr uint32_t PER_T = kApplyMaxTile / NT;
+  __shared__ uint32_t pre[kApplySrc + 1];
+  __shared__ uint32_t seg0[kApplySrc];
+  __shared__ uint32_t wsum[17];
+  extern __shared__ __align__(16) unsigned char apl_smem[];
+  const uint32_t TS = n.TS;
+  unsigned long long *tsl = reinterpret_cast<unsigned long long *>(apl_smem);  // [TS]
+  uint32_t *tpre = reinterpret_cast<uint32_t *>(tsl + TS);                     // [TS + 1]
+  uint32_t *tr0 = tpre + TS + 1;                                               // [TS]
+  real *gbuf = reinterpret_cast<real *>(apl_smem + (size_t)TS * 16 + 16);       // [kApplySyn(real)]
+  const uint32_t tid = threadIdx.x, c = blockIdx.x;
+  const uint32_t k = n.ach[3 * c], s0 = n.ach[3 * c + 1], s1 = n.ach[3 * c + 2];
+  const uint32_t nsrc = s1 - s0, j0 = k * TS;
+  const bool last_of_tile = c + 1 >= n_ach || n.ach[3 * (c + 1)] != k;
+  for (uint32_t i = tid; i < TS; i += NT) tsl[i] = 0ull;
+  // source-major side: the segment of each source, scanned
+  uint32_t len[PER_S], lo[PER_S], sum = 0;
+#pragma unroll
+  for (uint32_t u = 0; u < PER_S; ++u) {
+    const uint32_t i = tid * PER_S + u;
+    len[u] = 0;
+    lo[u] = 0;
+    if (i < nsrc) {
+      const uint32_t *ts = n.tseg + (size_t)(s0 + i) * (n.KT + 1) + k;
+      lo[u] = ts[0];
+      len[u] = ts[1] - ts[0];
+    }
+    sum += len[u];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(sum, wsum, &total);
+#pragma unroll
+  for (uint32_t u = 0; u < PER_S; ++u) {
+    const uint32_t i = tid * PER_S + u;
+    if (i < nsrc) {
+      pre[i] = run;
+      seg0[i] = lo[u];
+    }
+    run += len[u];
+  }
+  if (tid == 0) pre[nsrc] = total;
+  if constexpr (UPDATE) {
+    __syncthreads();  // the scan's partial sums are reused below
+    // target-major side: the run of each target, scanned
+    uint32_t tl[PER_T], t0[PER_T], tsum_ = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < PER_T; ++u) {
+      const uint32_t t = tid * PER_T + u, j = j0 + t;
+      tl[u] = 0;
+      t0[u] = 0;
+      if (t < TS && j < n.J) {
+        const uint32_t r0 = n.trs[(size_t)c * TS + t];
+        const uint32_t r1 = last_of_tile ? n.tm_ptr[j + 1] : n.trs[(size_t)(c + 1) * TS + t];
+        t0[u] = r0;
+        tl[u] = r1 - r0;
+      }
+      tsum_ += tl[u];
+    }
+    uint32_t ttot;
+    uint32_t trun = block_exclusive_scan(tsum_, wsum, &ttot);
+#pragma unroll
+    for (uint32_t u = 0; u < PER_T; ++u) {
+      const uint32_t t = tid * PER_T + u;
+      if (t < TS) {
+        tpre[t] = trun;
+        tr0[t] = t0[u];
+      }
+      trun += tl[u];
+    }
+    if (tid == 0) tpre[TS] = ttot;
+    __syncthreads();
+    // gradients in target-major runs -> LDS in the block's source-major order
+    for (uint32_t i = tid; i < ttot; i += NT) {
+      uint32_t a = 0, b = TS;  // tpre[a] <= i < tpre[b]
+      while (b - a > 1) {
+        const uint32_t m = (a + b) >> 1;
+        if (tpre[m] <= i) a = m; else b = m;
+      }
+      const uint32_t q = tr0[a] + (i - tpre[a]);
+      const double G = ((double)n.gs[q] + (double)n.gc[q]) / n_trials;
+      const uint32_t p = n.tm_perm[q];
+      const uint32_t src = (n.tm_syn[q] & 0xFFFFFFu) - s0;
+      const uint32_t local = pre[src] + (p - seg0[src]);
+      if (src < nsrc && local < total) gbuf[local] = (real)G;
+    }
+  }
+  __syncthreads();
+  // source-major side: update the records segment by segment
+  for (uint32_t i = tid; i < total; i += NT) {
+    uint32_t a = 0, b = nsrc;  // pre[a] <= i < pre[b]
+    while (b - a > 1) {
+      const uint32_t m = (a + b) >> 1;
+      if (pre[m] <= i) a = m; else b = m;
+    }
+    const uint32_t q = seg0[a] + (i - pre[a]);
+    const SynRec<real> rec = n.sm[q];
+    double w = (double)rec.w;
+    if constexpr (UPDATE) {
+      const double G = (double)gbuf[i];
+      double m = 0.0, v = 0.0;
+      if (opt == 1) {
+        m = (double)n.adam_m[q];
+        v = (double)n.adam_v[q];
+      }
+      opt_step(w, G, opt, eta, eta_t, b1, b2, eps, m, v);
+      if (opt == 1) {
+        n.adam_m[q] = (real)m;
+        n.adam_v[q] = (real)v;
+      }
+      const real wr = (real)w;
+      n.sm[q].w = wr;
+      w = (double)wr;
+    }
+    const uint32_t t = (rec.syn & 0xFFFFFFu) - j0;
+    const double aw = fabs(w);
+    if (aw < kBoundMaxW) {
+      atomicAdd(&tsl[t], (unsigned long long)ceil(aw * kBoundScale));
+    } else {
+      atomicOr(&n.tsum[j0 + t], 1ull << 63);  // saturated: reported as an out-of-range bound
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < TS && j0 + i < n.Jp; i += NT)
+    if (tsl[i]) atomicAdd(&n.tsum[j0 + i], tsl[i]);
+}
+
+// *l1max = the largest per-target bound (with a margin for the conversion),
+// and tsum cleared for the next update.
+template <typename real>
+__global__ __launch_bounds__(256) void k_bound_max(DevNet<real> n) {
+  float mx = 0.f;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n.J; j += gridDim.x * blockDim.x) {
+    const unsigned long long t = n.tsum[j];
+    n.tsum[j] = 0ull;
+    const float l = (t >> 63) ? 0x1p60f : (float)((double)t / kBoundScale * 1.001);
+    mx = fmaxf(mx, l);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63u) == 0 && mx > 0.f) atomicMax(n.l1max, __float_as_uint(mx));
+}
+
 template <typename real>
 __global__ __launch_bounds__(256) void k_input_bound(DevNet<real> n) {
   const uint32_t lane = threadIdx.x & 63u;
@@ -1351,6 +1514,50 @@ void Launch<real>::apply(const DevNet<real> &n, uint64_t S, double n_trials, int
                          double eta_t, double b1, double b2, double eps, hipStream_t s) {
   if (S > 0) k_apply_syn<real><<<grid_for(S, 256, 16384), 256, 0, s>>>(n, S, n_trials, opt, eta, eta_t, b1, b2, eps);
   k_apply_out<real><<<grid_for((uint64_t)n.K * n.Jp, 256, 2048), 256, 0, s>>>(n, n_trials, opt, eta, eta_t, b1, b2, eps);
+}
+
+// dynamic LDS of k_apply_blk: bound sums, target scan, run starts, and the
+// block's gradients (kApplySyn * 4 bytes: kApplySyn FP32 or half as many FP64)
+static size_t apply_blk_smem(uint32_t TS) { return (size_t)TS * 16 + 16 + (size_t)kApplySyn * 4; }
+
+template <typename real>
+static void launch_apply_blk(const DevNet<real> &n, uint32_t n_ach, bool update, double n_trials, int opt,
+                             double eta, double eta_t, double b1, double b2, double eps, hipStream_t s) {
+  const size_t smem = apply_blk_smem(n.TS);
+  (void)hipMemsetAsync(n.l1max, 0, sizeof(uint32_t), s);
+  if (n_ach) {
+    if (update) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_apply_blk<real, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+      k_apply_blk<real, true><<<n_ach, 1024, smem, s>>>(n, n_ach, n_trials, opt, eta, eta_t, b1, b2, eps);
+    } else {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_apply_blk<real, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+      k_apply_blk<real, false><<<n_ach, 1024, smem, s>>>(n, n_ach, n_trials, opt, eta, eta_t, b1, b2, eps);
+    }
+  }
+  k_bound_max<real><<<grid_for(n.J, 256, 1024), 256, 0, s>>>(n);
+}
+
+template <typename real>
+void Launch<real>::apply_blocked(const DevNet<real> &n, uint32_t n_ach, uint64_t S, double n_trials, int opt,
+                                 double eta, double eta_t, double b1, double b2, double eps, hipStream_t s) {
+  launch_apply_blk(n, n_ach, true, n_trials, opt, eta, eta_t, b1, b2, eps, s);
+  if (S) {
+    (void)hipMemsetAsync(n.gs, 0, S * sizeof(real), s);
+    (void)hipMemsetAsync(n.gc, 0, S * sizeof(real), s);
+  }
+  k_apply_out<real><<<grid_for((uint64_t)n.K * n.Jp, 256, 2048), 256, 0, s>>>(n, n_trials, opt, eta, eta_t, b1, b2, eps);
+}
+
+template <typename real>
+size_t Launch<real>::apply_blocked_smem(uint32_t TS) {
+  return apply_blk_smem(TS) + sizeof(uint32_t) * (2 * kApplySrc + 1 + 17);
+}
+
+template <typename real>
+void Launch<real>::input_bound_blocked(const DevNet<real> &n, uint32_t n_ach, hipStream_t s) {
+  launch_apply_blk(n, n_ach, false, 1.0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, s);
 }
 
 template <typename real>

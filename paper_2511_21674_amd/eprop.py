@@ -34,7 +34,7 @@ PHASES = ("stage", "forward", "readout", "adjoint", "synapse", "output")
  EPROP_STATE_GRAD_OUT, EPROP_STATE_ADAM_M_IN, EPROP_STATE_ADAM_V_IN, EPROP_STATE_ADAM_M_REC,
  EPROP_STATE_ADAM_V_REC, EPROP_STATE_ADAM_M_OUT, EPROP_STATE_ADAM_V_OUT, EPROP_STATE_ADAM_STEP,
  EPROP_STATE_SPIKES, EPROP_STATE_PSI, EPROP_STATE_Y, EPROP_STATE_ERR, EPROP_STATE_V,
- EPROP_STATE_LAYOUT, EPROP_STATE_L) = range(20)
+ EPROP_STATE_LAYOUT, EPROP_STATE_L, EPROP_STATE_INPUT_BOUND) = range(21)
 
 EXPORTED = ("eprop_create_network", "eprop_simulate_batch", "eprop_apply_updates", "eprop_read_state",
             "eprop_destroy_network", "eprop_status_string", "eprop_last_error")

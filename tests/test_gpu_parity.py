@@ -638,3 +638,44 @@ def test_scaling_network_launch_configuration_sampled():
         ok, e, ent = rel_close(gg[m], ref[m], 1e-4, floor_frac=1e-2)
         log(f"scaling {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
         assert ok, (name, e, ent)
+
+
+def test_fp32_adam_state_and_input_bound_after_updates():
+    """Evidence accumulation with Adam (eq. eta-adam-fast, eq. delta-w-adam-fast),
+    FP32, teacher-forced, three iterations: the optimiser's first and second
+    moments read back in the caller's synapse order within 1e-4 of the
+    oracle's, and the weights likewise; the per-target input bound the
+    update recomputes stays above the largest sum of |w| into one target."""
+    wl = W.c2_evidence(batch_size=4)
+    assert wl.network.params.optimizer == 1
+    on = O.OracleNet(wl.network)
+    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=max(int(wl.make_batch(i, 0, 4).n_steps.max())
+                                                                     for i in range(3)))
+    for it in range(3):
+        b = W.forced_poisson(wl.make_batch(it, 0, 4), wl.network.n_rec, 20.0, 1.0, seed=99, iteration=it, n_ref=2)
+        net.simulate(b, train=True)
+        net.apply()
+        g = O.zero_grads(on)
+        for i in range(b.n_trials):
+            O.run_trial(on, b, i, 2, g)
+        O.apply(on, g, b.n_trials)
+    for name, m_id, v_id, key in (("rec", E.EPROP_STATE_ADAM_M_REC, E.EPROP_STATE_ADAM_V_REC, "w_rec"),
+                                  ("in", E.EPROP_STATE_ADAM_M_IN, E.EPROP_STATE_ADAM_V_IN, "w_in")):
+        for sid, ref in ((m_id, on.m[key]), (v_id, on.v[key])):
+            ok, e, ent = rel_close(net.read(sid), ref, 1e-4, floor_frac=1e-2)
+            log(f"adam {name} state {sid}: normwise {e:.2e} worst {ent:.2e}")
+            assert ok, (name, sid, e, ent)
+    w = net.weights()
+    for k in KEYS:
+        ok, e, ent = rel_close(w[k], getattr(on, k), 1e-5)
+        assert ok, (k, e, ent)
+    # the bound: sum of |w| into each target, from the read-back weights
+    pr_in, pr_rec = wl.network.in_rec, wl.network.rec_rec
+    l1 = np.zeros(wl.network.n_rec)
+    np.add.at(l1, pr_in.col, np.abs(w["w_in"]))
+    np.add.at(l1, pr_rec.col, np.abs(w["w_rec"]))
+    bound = float(net.read(E.EPROP_STATE_INPUT_BOUND)[0])
+    net.close()
+    log(f"input bound {bound:.6g}, largest sum of |w| into one target {l1.max():.6g}")
+    indeg = np.bincount(pr_in.col, minlength=wl.network.n_rec) + np.bincount(pr_rec.col, minlength=wl.network.n_rec)
+    assert l1.max() <= bound <= l1.max() * 1.001 * (1 + 1e-6) + indeg.max() * 2.0 ** -16
