@@ -48,7 +48,9 @@ class _Net(C.Structure):
                 ("beta_a", C.c_double), ("surrogate", C.c_int), ("sg_gamma", C.c_double),
                 ("sg_beta", C.c_double), ("loss", C.c_int), ("inp", _Proj), ("rec", _Proj),
                 ("w_out", C.c_void_p), ("fb", C.c_void_p), ("d_out", C.c_int), ("d_ls", C.c_int),
-                ("c_reg", C.c_double), ("f_target", C.c_double)]
+                ("c_reg", C.c_double), ("f_target", C.c_double),
+                ("reset_mode", C.c_int), ("v_reset", C.c_double), ("etrace_filter", C.c_int),
+                ("tau_e", C.c_double), ("reg_mode", C.c_int), ("reg_tau", C.c_double)]
 
 
 class _Trial(C.Structure):
@@ -129,6 +131,9 @@ class OracleNet:
         s.d_out, s.d_ls = int(getattr(p, "d_out", 0)), int(getattr(p, "d_ls", 0))
         # target rate in spikes per step (the rate of eq. loss-firing-rate-regularization)
         s.c_reg, s.f_target = float(getattr(p, "c_reg", 0.0)), float(getattr(p, "f_target_hz", 0.0)) * p.dt / 1000.0
+        s.reset_mode, s.v_reset = int(getattr(p, "reset_mode", 0)), float(getattr(p, "v_reset", 0.0))
+        s.etrace_filter, s.tau_e = int(getattr(p, "etrace_filter", 0)), float(getattr(p, "tau_e", 0.0))
+        s.reg_mode, s.reg_tau = int(getattr(p, "reg_mode", 0)), float(getattr(p, "reg_tau", 0.0))
         return s
 
 

@@ -36,6 +36,8 @@ typedef struct {
 
 typedef struct {
   double alpha, kappa, rho;  /* exact-integration propagators */
+  double kappa_e;            /* the eligibility trace's filter (kappa unless decoupled) */
+  double beta_f;             /* the rate's moving-average factor (eq. ema-rate) */
   int n_ref;
   int max_delay;
   long *in_ptr;              /* [J+1] incoming synapses per target, canonical order */
@@ -56,6 +58,10 @@ static int prep_init(const orc_net *net, prep_t *p) {
   p->alpha = exp(-net->dt / net->tau_m);
   p->kappa = exp(-net->dt / net->tau_out);
   p->rho = exp(-net->dt / net->tau_a);
+  /* Results, "Eligibility trace filter decoupled from output time constant":
+   * F_kappa, F_kappa_e with its own time constant, or no filter */
+  p->kappa_e = net->etrace_filter == 1 ? exp(-net->dt / net->tau_e) : net->etrace_filter == 2 ? 0.0 : p->kappa;
+  p->beta_f = net->reg_mode == 1 ? exp(-net->dt / net->reg_tau) : 0.0;
   p->n_ref = (int)lround(net->t_ref / net->dt);
   p->in_ptr = (long *)calloc((size_t)J + 1, sizeof(long));
   long total = net->in.nnz + net->rec.nnz;
@@ -153,13 +159,16 @@ static double input_current(const orc_net *net, const prep_t *p, const spikes_t 
 }
 
 /* One neuron update at step t (eq. spike-threshold-adaptation, adaptive
- * threshold, eq. lif_update, eq. binary-spike-state-variable, surrogate). */
+ * threshold, eq. lif_update, eq. binary-spike-state-variable, surrogate).
+ * With the full reset of the e-prop+ experiments the membrane restarts
+ * from v_reset after a spike instead of losing the threshold. */
 static int neuron_step(const orc_net *net, const prep_t *p, int j, double I, double zprev,
                        int forced_z, double *v, double *a, int *refr, double *psi) {
   const double beta = neuron_beta(net, j);
   *a = p->rho * *a + zprev;
   const double A = net->v_th + beta * *a;
-  *v = p->alpha * *v + I - zprev * A;
+  if (net->reset_mode == 1) *v = p->alpha * (zprev != 0.0 ? net->v_reset : *v) + I;
+  else *v = p->alpha * *v + I - zprev * A;
   const int refractory = *refr > 0;
   if (refractory) *refr -= 1;
   int z;
@@ -175,14 +184,16 @@ static int neuron_step(const orc_net *net, const prep_t *p, int j, double I, dou
  *   eps_a^t = psi^{t-1} eps_v^{t-1} + (rho - psi^{t-1} beta) eps_a^{t-1}
  *   eps_v^t = alpha eps_v^{t-1} + x^t                   (F_alpha of the arrivals)
  *   e^t     = psi^t (eps_v^t - beta eps_a^t)
- *   ebar^t  = kappa ebar^{t-1} + e^t                    (F_kappa)
+ *   ebar^t  = kappa_e ebar^{t-1} + e^t                  (F_kappa, or the decoupled filter)
+ * With the full reset, dv^t/dv^{t-1} = alpha (1 - z_j^{t-1}), so eps_v
+ * restarts after each postsynaptic spike (zprev = z_j^{t-1}).
  * Returns e^t; the caller pairs ebar^t with the learning signal. */
-static double syn_trace(const prep_t *p, double x, double psi_prev, double psi_now, double beta, double *ev,
-                        double *ea, double *eb) {
+static double syn_trace(const orc_net *net, const prep_t *p, double x, double zprev, double psi_prev, double psi_now,
+                        double beta, double *ev, double *ea, double *eb) {
   const double ea_new = psi_prev * *ev + (p->rho - psi_prev * beta) * *ea;
-  const double ev_new = p->alpha * *ev + x;
+  const double ev_new = (net->reset_mode == 1 && zprev != 0.0 ? 0.0 : p->alpha) * *ev + x;
   const double e = psi_now * (ev_new - beta * ea_new);
-  *eb = p->kappa * *eb + e;
+  *eb = p->kappa_e * *eb + e;
   *ev = ev_new;
   *ea = ea_new;
   return e;
@@ -201,7 +212,18 @@ static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp
     y[k] = p->kappa * y[k] + s;
   }
   const int win = tr->window ? tr->window[t - 1] : 1;
-  if (net->loss == 0) {
+  if (net->loss == 2) {
+    /* eq. temporal-mse on the one-hot label: L = (1/K) sum_t sum_k (y - y*)^2,
+     * E = dL/dy = (2/K)(y - y*); the prediction sums y over the window */
+    for (int k = 0; k < K; ++k) {
+      const double d = y[k] - (k == tr->label ? 1.0 : 0.0);
+      E[k] = win ? 2.0 / K * d : 0.0;
+      if (win) {
+        *loss += d * d / K;
+        psum[k] += y[k];
+      }
+    }
+  } else if (net->loss == 0) {
     for (int k = 0; k < K; ++k) {
       const double d = y[k] - tr->target[(long)(t - 1) * K + k];
       E[k] = win ? d : 0.0;
@@ -225,7 +247,10 @@ static int check_net(const orc_net *net, const orc_trial *tr) {
   if (!net || !tr || net->n_rec < 1 || net->n_out < 1 || net->n_in < 0 || tr->n_steps < 1) return -1;
   if (net->in.n_src != net->n_in || net->rec.n_src != net->n_rec) return -1;
   if (net->loss == 0 && !tr->target) return -1;
-  if (net->loss == 1 && (tr->label < 0 || tr->label >= net->n_out)) return -1;
+  if ((net->loss == 1 || net->loss == 2) && (tr->label < 0 || tr->label >= net->n_out)) return -1;
+  if (net->loss < 0 || net->loss > 2 || net->reset_mode < 0 || net->reset_mode > 1) return -1;
+  if (net->etrace_filter < 0 || net->etrace_filter > 2 || (net->etrace_filter == 1 && !(net->tau_e > 0))) return -1;
+  if (net->reg_mode < 0 || net->reg_mode > 1 || (net->reg_mode == 1 && !(net->reg_tau > 0))) return -1;
   return 0;
 }
 
@@ -261,9 +286,13 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
   double *fifo_e = calloc((size_t)(ns + 1) * dq1, sizeof(double)), *fifo_eb = calloc((size_t)(ns + 1) * dq1, sizeof(double));
   double *fifo_z = calloc((size_t)J * dq1, sizeof(double));
   double *esum = calloc(ns + 1, sizeof(double)), *creg = calloc(J, sizeof(double));
+  /* moving-average rates f_j^t (eq. ema-rate, row t) and, time-driven, each
+   * synapse's G_beta-filtered eligibility (eq. ema-gradient) */
+  double *f_h = calloc((size_t)(T + 1) * J, sizeof(double)), *gh = calloc(ns + 1, sizeof(double));
   if (!v || !a || !refr || !y || !E || !psum || !psi_h || !L_h || !E_h || !ev || !ea || !eb ||
-      !apr || !zb || !apr_o || !q_src || !fifo_e || !fifo_eb || !fifo_z || !esum || !creg)
+      !apr || !zb || !apr_o || !q_src || !fifo_e || !fifo_eb || !fifo_z || !esum || !creg || !f_h || !gh)
     goto done;
+  const int ema = net->reg_mode == 1 && net->c_reg != 0.0;
   for (int i = 0; i < net->in.n_src; ++i)
     for (unsigned long r = net->in.row_ptr[i]; r < net->in.row_ptr[i + 1]; ++r) q_src[r] = i;
   for (int i = 0; i < net->rec.n_src; ++i)
@@ -284,6 +313,7 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
       const int z = neuron_step(net, &p, j, I_t, zprev, fz, &v[j], &a[j], &refr[j], &psi);
       sp.zrec[(long)t * J + j] = (unsigned char)z;
       psi_h[(long)t * J + j] = psi;
+      f_h[(long)t * J + j] = p.beta_f * f_h[(long)(t - 1) * J + j] + (1.0 - p.beta_f) * z;
       if (trace) {
         if (trace->v) trace->v[(long)(t - 1) * J + j] = v[j];
         if (trace->a) trace->a[(long)(t - 1) * J + j] = a[j];
@@ -325,8 +355,14 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
         const int kind = q < nin ? 0 : 1;
         const int D = q < nin ? net->in.delay[q] : net->rec.delay[q - nin];
         const double x = spiked(&sp, kind, q_src[q], t - D) ? 1.0 : 0.0;
-        const double e = syn_trace(&p, x, psi_h[(long)(t - 1) * J + j], psi_h[(long)t * J + j], neuron_beta(net, j),
-                                   &ev[q], &ea[q], &eb[q]);
+        const double e = syn_trace(net, &p, x, sp.zrec[(long)(t - 1) * J + j], psi_h[(long)(t - 1) * J + j],
+                                   psi_h[(long)t * J + j], neuron_beta(net, j), &ev[q], &ea[q], &eb[q]);
+        if (ema) {
+          /* Alg. "time-driven gradient computation", moving-average form:
+           * c (f_j^s - f*) G_beta(e^s) at s = t - d, for s <= T - d */
+          gh[q] = p.beta_f * gh[q] + (1.0 - p.beta_f) * e;
+          if (t <= T - dq) *SYN_G(q) += net->c_reg * (f_h[(long)t * J + j] - net->f_target) * gh[q];
+        }
         fifo_e[q * (dq + 1) + t % (dq + 1)] = e;
         fifo_eb[q * (dq + 1) + t % (dq + 1)] = eb[q];
         if (t - dq >= 1) {
@@ -349,13 +385,20 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
   /* static firing-rate regularisation (Methods, "Firing rate regularization"):
    * f_j = (1/T) sum_t z_j^t; loss c/2 sum_j (f_j - f*)^2; per synapse the
    * gradient adds (c/T)(f_j - f*) times the eligibilities paired in the sum */
-  for (int j = 0; j < J; ++j) {
+  for (int j = 0; j < J && net->reg_mode == 0; ++j) {
     double nz = 0.0;
     for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
     const double f = nz / T;
     creg[j] = net->c_reg / T * (f - net->f_target);
     loss += 0.5 * net->c_reg * (f - net->f_target) * (f - net->f_target);
   }
+  /* moving-average form (eq. sma-loss with the rate of eq. ema-rate):
+   * c/2 sum_t sum_j (f_j^t - f*)^2 */
+  for (int j = 0; j < J && net->reg_mode == 1; ++j)
+    for (int t = 1; t <= T; ++t) {
+      const double df = f_h[(long)t * J + j] - net->f_target;
+      loss += 0.5 * net->c_reg * df * df;
+    }
 
   if (grad_mode == 1) {
     for (long q = 0; q < ns; ++q) *SYN_G(q) += creg[SYN_TGT(q)] * esum[q];
@@ -377,17 +420,22 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
           const long q = base + (long)r;
           const int j = (int)pr->col[r];
           const int D = pr->delay[r];
-          double evq = 0.0, eaq = 0.0, ebq = 0.0, es = 0.0;
+          double evq = 0.0, eaq = 0.0, ebq = 0.0, es = 0.0, ghq = 0.0;
           int seg = -1;  /* start of the open segment */
           for (int a = 1; a <= T + 1; ++a) {
             const int arrival = a <= T && spiked(&sp, kind, i, a - D);
             if (!arrival && a <= T) continue;
             if (seg > 0) {
               for (int u = seg; u <= a - 1; ++u) {
-                const double e = syn_trace(&p, u == seg ? 1.0 : 0.0, psi_h[(long)(u - 1) * J + j],
-                                           psi_h[(long)u * J + j], neuron_beta(net, j), &evq, &eaq, &ebq);
+                const double e = syn_trace(net, &p, u == seg ? 1.0 : 0.0, sp.zrec[(long)(u - 1) * J + j],
+                                           psi_h[(long)(u - 1) * J + j], psi_h[(long)u * J + j], neuron_beta(net, j),
+                                           &evq, &eaq, &ebq);
                 if (u + dq <= T - net->d_ls) *SYN_G(q) += L_h[(long)(u + dq) * J + j] * ebq;
                 if (u <= T - dq) es += e;
+                if (ema) {
+                  ghq = p.beta_f * ghq + (1.0 - p.beta_f) * e;
+                  if (u <= T - dq) *SYN_G(q) += net->c_reg * (f_h[(long)u * J + j] - net->f_target) * ghq;
+                }
               }
             }
             seg = a;
@@ -418,14 +466,14 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
     int best = 0;
     for (int k = 1; k < K; ++k)
       if (psum[k] > psum[best]) best = k;
-    *pred = net->loss == 1 ? best : 0;
+    *pred = net->loss != 0 ? best : 0;
   }
   rc = 0;
   (void)I;
 done:
   free(v); free(a); free(refr); free(y); free(E); free(psum);
   free(psi_h); free(L_h); free(E_h); free(ev); free(ea); free(eb); free(apr); free(zb); free(apr_o);
-  free(q_src); free(fifo_e); free(fifo_eb); free(fifo_z); free(esum); free(creg);
+  free(q_src); free(fifo_e); free(fifo_eb); free(fifo_z); free(esum); free(creg); free(f_h); free(gh);
   spikes_free(&sp);
   prep_free(&p);
   return rc;
@@ -476,9 +524,14 @@ static int dual_run(const orc_net *net, const prep_t *p, const spikes_t *sp_ref,
       dual zprev = {sp_ref->zrec[(long)(t - 1) * J + j] ? 1.0 : 0.0, dz[(long)(t - 1) * J + j]};
       a[j] = dadd(dmul_c(p->rho, a[j]), zprev);                 /* a^t = rho a + z^{t-1} */
       dual A = dadd((dual){net->v_th, 0.0}, dmul_c(beta, a[j]));  /* adaptive threshold */
-      /* v^t = alpha v + I - z^{t-1} A, with the reset term's derivative stopped */
-      dual reset = dstop((dual){zprev.x * A.x, 0.0});
-      v[j] = dsub(dadd(dmul_c(p->alpha, v[j]), I), reset);
+      if (net->reset_mode == 1) {
+        /* full reset: v^t = alpha v_reset + I after a spike, else alpha v + I */
+        v[j] = zprev.x != 0.0 ? dadd((dual){p->alpha * net->v_reset, 0.0}, I) : dadd(dmul_c(p->alpha, v[j]), I);
+      } else {
+        /* v^t = alpha v + I - z^{t-1} A, with the reset term's derivative stopped */
+        dual reset = dstop((dual){zprev.x * A.x, 0.0});
+        v[j] = dsub(dadd(dmul_c(p->alpha, v[j]), I), reset);
+      }
       const int refractory = refr[j] > 0;
       if (refractory) refr[j] -= 1;
       const double psi = refractory ? 0.0 : surrogate(net, v[j].x - A.x);
@@ -498,7 +551,18 @@ static int dual_run(const orc_net *net, const prep_t *p, const spikes_t *sp_ref,
       }
     }
   }
-  if (dloss && net->c_reg != 0.0) {
+  if (dloss && net->c_reg != 0.0 && net->reg_mode == 1) {
+    /* tangent of the moving-average regularisation loss:
+     * sum_t c (f_j^t - f*) df_j^t, with f and df filtered by eq. ema-rate */
+    for (int j = 0; j < J; ++j) {
+      double f = 0.0, df = 0.0;
+      for (int t = 1; t <= T; ++t) {
+        f = p->beta_f * f + (1.0 - p->beta_f) * (sp_ref->zrec[(long)t * J + j] ? 1.0 : 0.0);
+        df = p->beta_f * df + (1.0 - p->beta_f) * dz[(long)t * J + j];
+        dl += net->c_reg * (f - net->f_target) * df;
+      }
+    }
+  } else if (dloss && net->c_reg != 0.0) {
     /* tangent of the regularisation loss: c (f_j - f*) (1/T) sum_t dz_j^t */
     for (int j = 0; j < J; ++j) {
       double nz = 0.0, sd = 0.0;
@@ -572,15 +636,26 @@ int orc_bruteforce_eprop(const orc_net *net, const orc_trial *tr, double *g_in, 
         double Ls = 0.0;
         for (int k = 0; k < K; ++k) {
           double fut = 0.0;
-          for (int t = tp + d; t <= T - net->d_ls; ++t) fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa, t - d - tp);
+          for (int t = tp + d; t <= T - net->d_ls; ++t) fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa_e, t - d - tp);
           Ls += net->fb[(long)sd.tgt * K + k] * fut;
         }
         g += Ls * dz[(long)tp * J + sd.tgt];
         es += dz[(long)tp * J + sd.tgt];
       }
-      double nz = 0.0;
-      for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + sd.tgt] ? 1.0 : 0.0;
-      g += net->c_reg / T * (nz / T - net->f_target) * es;
+      if (net->reg_mode == 1) {
+        /* moving-average regulariser: sum_{s<=T-d} c (f^s - f*) sum_{s'<=s} (1-beta) beta^(s-s') e^s' */
+        double f = 0.0;
+        for (int s2 = 1; s2 <= T - d; ++s2) {
+          f = p.beta_f * f + (1.0 - p.beta_f) * (sp.zrec[(long)s2 * J + sd.tgt] ? 1.0 : 0.0);
+          double G = 0.0;
+          for (int s1 = 1; s1 <= s2; ++s1) G += (1.0 - p.beta_f) * pow(p.beta_f, s2 - s1) * dz[(long)s1 * J + sd.tgt];
+          g += net->c_reg * (f - net->f_target) * G;
+        }
+      } else {
+        double nz = 0.0;
+        for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + sd.tgt] ? 1.0 : 0.0;
+        g += net->c_reg / T * (nz / T - net->f_target) * es;
+      }
       (kind == 0 ? g_in : g_rec)[q] = g;
     }
   }
@@ -639,10 +714,15 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
     readout_step(net, &p, &sp, tr, t, y, E, &loss, psum);
     for (int k = 0; k < K; ++k) E_h[(long)t * K + k] = E[k];
   }
-  for (int j = 0; j < J; ++j) {  /* static rate regularisation of every neuron */
-    double nz = 0.0;
-    for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
-    loss += 0.5 * net->c_reg * (nz / T - net->f_target) * (nz / T - net->f_target);
+  for (int j = 0; j < J; ++j) {  /* rate regularisation of every neuron */
+    double nz = 0.0, f = 0.0;
+    for (int t = 1; t <= T; ++t) {
+      const double z = sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
+      nz += z;
+      f = p.beta_f * f + (1.0 - p.beta_f) * z;
+      if (net->reg_mode == 1) loss += 0.5 * net->c_reg * (f - net->f_target) * (f - net->f_target);
+    }
+    if (net->reg_mode == 0) loss += 0.5 * net->c_reg * (nz / T - net->f_target) * (nz / T - net->f_target);
   }
   for (int n = 0; n < n_sample && rc == 0; ++n) {
     const int j = targets[n];
@@ -662,15 +742,21 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
     }
     double nz = 0.0;
     for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
-    const double creg = net->c_reg / T * (nz / T - net->f_target);
+    const double creg = net->reg_mode == 0 ? net->c_reg / T * (nz / T - net->f_target) : 0.0;
     for (long q = p.in_ptr[j]; q < p.in_ptr[j + 1]; ++q) {
       const in_syn *s = &p.syn[q];
-      double ev = 0.0, ea = 0.0, eb = 0.0, g = 0.0, es = 0.0;
+      double ev = 0.0, ea = 0.0, eb = 0.0, g = 0.0, es = 0.0, gh = 0.0, f = 0.0;
       for (int t = 1; t <= T; ++t) {
-        const double e = syn_trace(&p, spiked(&sp, s->kind, s->src, t - s->delay) ? 1.0 : 0.0, psi_h[t - 1],
-                                   psi_h[t], neuron_beta(net, j), &ev, &ea, &eb);
+        const double e = syn_trace(net, &p, spiked(&sp, s->kind, s->src, t - s->delay) ? 1.0 : 0.0,
+                                   sp.zrec[(long)(t - 1) * J + j], psi_h[t - 1], psi_h[t], neuron_beta(net, j),
+                                   &ev, &ea, &eb);
         if (t + net->d_out <= T - net->d_ls) g += L_h[t + net->d_out] * eb;
         if (t <= T - net->d_out) es += e;
+        if (net->reg_mode == 1 && net->c_reg != 0.0) {
+          f = p.beta_f * f + (1.0 - p.beta_f) * (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);
+          gh = p.beta_f * gh + (1.0 - p.beta_f) * e;
+          if (t <= T - net->d_out) g += net->c_reg * (f - net->f_target) * gh;
+        }
       }
       (s->kind == 0 ? g_in : g_rec)[s->idx] = g + creg * es;
     }

@@ -34,7 +34,8 @@ typedef struct {
   double dt, tau_m, tau_out, v_th, t_ref, tau_a, beta_a;
   int surrogate;                  /* 0 piecewise linear, 1 exponential */
   double sg_gamma, sg_beta;
-  int loss;                       /* 0 mean squared error, 1 softmax cross-entropy */
+  int loss;                       /* 0 mean squared error, 1 softmax cross-entropy, 2 temporal mean
+                                     squared error on the one-hot label (eq. temporal-mse) */
   orc_proj in, rec;
   const double *w_out;            /* [K*J], row k */
   const double *fb;               /* [J*K], row j */
@@ -44,6 +45,15 @@ typedef struct {
   int d_ls;                       /* delay d^ls of the learning signal, >= 0 */
   double c_reg;                   /* regularisation strength c^reg (0 = off) */
   double f_target;                /* target rate f^*, in spikes per step */
+  /* e-prop+ components (Results, "Event-driven e-prop with additional
+   * biological features") */
+  int reset_mode;                 /* 0: subtract the threshold (eq. lif_update); 1: reset to v_reset */
+  double v_reset;
+  int etrace_filter;              /* eligibility filter: 0 F_kappa (tau_out), 1 F_kappa_e (tau_e), 2 none */
+  double tau_e;
+  int reg_mode;                   /* 0 static rate (eq. loss-firing-rate-regularization), 1 exponential
+                                     moving average (eq. ema-rate, eq. ema-gradient) */
+  double reg_tau;                 /* the moving average's time constant: beta = exp(-dt/reg_tau) */
 } orc_net;
 
 typedef struct {
@@ -51,7 +61,7 @@ typedef struct {
   long n_in_spikes;
   const unsigned int *in_step, *in_src;   /* emission steps in [0, T-1] */
   const double *target;                   /* [T*K] (MSE) or NULL */
-  int label;                              /* class (cross-entropy) */
+  int label;                              /* class (cross-entropy, temporal MSE) */
   const unsigned char *window;            /* [T] learning window, NULL = always open */
   int forced;                             /* 1: recurrent spikes replaced by the list below */
   long n_forced;

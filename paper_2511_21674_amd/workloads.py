@@ -57,7 +57,7 @@ class Params:
     surrogate: int = 0          # 0 piecewise linear, 1 exponential
     sg_gamma: float = 0.3 / 0.6  # gamma_original / v_th
     sg_beta: float = 1.0 / 0.6   # 1 / v_th
-    loss: int = 0               # 0 mean squared error, 1 softmax cross-entropy
+    loss: int = 0               # 0 mean squared error, 1 softmax cross-entropy, 2 temporal MSE on the label
     optimizer: int = 0          # 0 gradient descent, 1 Adam
     eta: float = 1e-3
     adam_beta1: float = 0.9
@@ -66,8 +66,14 @@ class Params:
     max_delay: int = 1
     d_out: int = 0              # delay from the recurrent to the output layer (steps)
     d_ls: int = 0               # delay of the learning signal (steps)
-    c_reg: float = 0.0          # static firing-rate regularisation strength
+    c_reg: float = 0.0          # firing-rate regularisation strength
     f_target_hz: float = 0.0    # its target rate
+    reg_mode: int = 0           # 0 static rate over the sample, 1 exponential moving average
+    reg_tau: float = 0.0        # the moving average's time constant (ms)
+    reset_mode: int = 0         # 0 subtract the threshold, 1 reset the membrane to v_reset
+    v_reset: float = 0.0
+    etrace_filter: int = 0      # eligibility filter: 0 tau_out, 1 its own tau_e, 2 none
+    tau_e: float = 0.0
 
 
 @dataclass

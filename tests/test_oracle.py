@@ -495,3 +495,141 @@ def test_rate_regularisation_is_exact_without_recurrence():
     f = rd.trace["z"].sum(axis=0) / T
     reg = 0.5 * 3.0 * float(((f - 15.0 / 1000.0) ** 2).sum())
     assert rd.loss == pytest.approx(rd0.loss + reg, rel=1e-12)
+
+
+# ---------------------------------------------------------------- e-prop+ components
+
+EPROP_PLUS = dict(reset_mode=1, v_reset=-0.2, etrace_filter=1, tau_e=8.0, reg_mode=1, reg_tau=50.0,
+                  c_reg=30.0, f_target_hz=20.0)
+
+
+def test_full_reset_closed_form():
+    """Full reset of the e-prop+ experiments (Methods, "Neuron models"):
+    after a spike the membrane restarts from v_reset, then decays with alpha
+    (eq. lif_update's propagator) until the next input."""
+    alpha = math.exp(-1.0 / 20.0)
+    net = small_net(1, 1, 1, [(0, 0, 2.0, 1)], [], v_th=0.6, t_ref=0.0, reset_mode=1, v_reset=-0.3)
+    r, _, _ = _trace(net, batch_from(12, [(0, 0)], 1))
+    v, z = r.trace["v"][:, 0], r.trace["z"][:, 0]
+    assert v[0] == 2.0 and z[0] == 1
+    expect = -0.3 * alpha ** np.arange(1, 12)
+    assert np.allclose(v[1:], expect, rtol=1e-14, atol=0)
+    assert z[1:].sum() == 0
+
+
+def test_temporal_mse_closed_form_and_output_gradient():
+    """eq. temporal-mse: a silent network keeps y = 0, so the loss is (1/K)
+    times the open window steps (the one-hot target's single 1 per step);
+    the output-weight gradient equals central differences of that loss
+    (P9 for the temporal MSE)."""
+    net = small_net(1, 2, 3, [(0, 0, 0.01, 1)], [], v_th=10.0, loss=2)
+    win = np.r_[np.zeros(10), np.ones(30)].astype(np.uint8)
+    r, _, _ = _trace(net, batch_from(40, [(3, 0)], 3, label=2, window=win))
+    assert r.loss == pytest.approx(30 / 3, rel=1e-15)
+    wl = W.tiny(loss=2)
+    b = wl.make_batch(0, 0, 1)
+    on = O.OracleNet(wl.network)
+    g = O.zero_grads(on)
+    O.run_trial(on, b, 0, 2, g)
+    h = 1e-3
+    fd = np.zeros_like(on.w_out)
+    for k in range(on.n_out):
+        for j in range(on.n_rec):
+            w0 = on.w_out[k, j]
+            on.w_out[k, j] = w0 + h
+            lp = O.run_trial(on, b, 0).loss
+            on.w_out[k, j] = w0 - h
+            lm = O.run_trial(on, b, 0).loss
+            on.w_out[k, j] = w0
+            fd[k, j] = (lp - lm) / (2 * h)
+    ok, e, ent = rel_close(g["w_out"], fd, 1e-8)
+    assert ok, (e, ent)
+
+
+def test_ema_rate_loss_closed_form():
+    """eq. ema-rate: f^t = (1 - beta) sum_{u<=t} beta^(t-u) z^u; the moving-
+    average regulariser's loss is c/2 sum_t sum_j (f_j^t - f*)^2 (added to the
+    task loss)."""
+    wl = W.tiny(loss=0)
+    prm = dict(c_reg=7.0, f_target_hz=30.0, reg_mode=1, reg_tau=40.0)
+    b = wl.make_batch(0, 0, 1)
+    r1, _, _ = _trace(_with(wl.network, **prm), b)
+    r0, _, _ = _trace(wl.network, b)
+    z = r1.trace["z"].astype(float)
+    T = z.shape[0]
+    beta = math.exp(-1.0 / 40.0)
+    w = (1 - beta) * beta ** (np.arange(T)[:, None] - np.arange(T)[None, :])
+    f = np.tril(w) @ z
+    reg = 0.5 * 7.0 * float(((f - 0.03) ** 2).sum())
+    assert r1.loss == pytest.approx(r0.loss + reg, rel=1e-12)
+
+
+@pytest.mark.parametrize("opts", [dict(reset_mode=1, v_reset=-0.2), dict(reg_mode=1, reg_tau=50.0, c_reg=30.0,
+                                                                          f_target_hz=20.0)])
+def test_eprop_plus_components_exact_without_recurrence(opts):
+    """P8 for the e-prop+ components: with W_rec = 0 and B = W_out^T the
+    e-prop gradient is the exact forward-mode gradient.  With the full reset
+    this pins the eligibility's restart after each postsynaptic spike (the
+    local derivative dv^t/dv^{t-1} = alpha (1 - z^{t-1})); with the moving-
+    average regulariser it pins eq. ema-gradient.  Either way the gradient
+    differs from the plain model's."""
+    wl = W.tiny(loss=0)
+    b = wl.make_batch(0, 0, 1)
+
+    def run(**params):
+        on = O.OracleNet(_with(wl.network, **params))
+        on.w_rec[:] = 0.0
+        on.fb[:] = on.w_out.T
+        g = O.zero_grads(on)
+        O.run_trial(on, b, 0, 2, g)
+        return on, g
+
+    on, g = run(**opts)
+    fm = O.forward_mode_loss_grad(on, b, 0)
+    ok, e, ent = rel_close(g["w_in"], fm["w_in"], 1e-12)
+    assert ok, (e, ent)
+    _, g0 = run()
+    assert not rel_close(g0["w_in"], g["w_in"], 1e-3)[0]
+
+
+@pytest.mark.parametrize("loss,extra", [(2, dict()), (0, dict(etrace_filter=2)), (1, dict(d_out=2, d_ls=1)),
+                                        (2, dict(d_out=1, etrace_filter=1, tau_e=80.0))])
+def test_eprop_plus_bruteforce_time_event(loss, extra):
+    """P7/P10 with every e-prop+ component at once (full reset, decoupled or
+    removed eligibility filter, moving-average regulariser, temporal MSE,
+    delays): the dual-number future-sum gradient, the time-driven recursion
+    (Alg. time-driven gradient computation) and the event-driven walk agree."""
+    wl = W.tiny(loss=loss)
+    prm = dict(EPROP_PLUS)
+    prm.update(extra)
+    on = O.OracleNet(_with(wl.network, **prm))
+    b = wl.make_batch(0, 0, 1)
+    g1, g2 = O.zero_grads(on), O.zero_grads(on)
+    r1 = O.run_trial(on, b, 0, 1, g1, trace=True)
+    r2 = O.run_trial(on, b, 0, 2, g2)
+    bf = O.bruteforce_eprop(on, b, 0)
+    assert r1.loss == r2.loss
+    assert r1.trace["z"].sum(axis=0).min() > 0
+    for k in ("w_in", "w_rec"):
+        ok, e, ent = rel_close(g1[k], bf[k], 1e-12)
+        assert ok, ("time-driven vs brute force", k, e, ent)
+        ok, e, ent = rel_close(g2[k], g1[k], 1e-12)
+        assert ok, ("event vs time-driven", k, e, ent)
+    ok, e, ent = rel_close(g2["w_out"], g1["w_out"], 1e-12)
+    assert ok, ("w_out", e, ent)
+
+
+def test_decoupled_filter_with_tau_out_is_the_coupled_filter():
+    """Choosing the decoupled filter with tau_e = tau_out reproduces the
+    coupled filter exactly; tau_e != tau_out changes the gradient."""
+    wl = W.tiny(loss=0)
+    b = wl.make_batch(0, 0, 1)
+    grads = []
+    for prm in (dict(), dict(etrace_filter=1, tau_e=wl.network.params.tau_out), dict(etrace_filter=1, tau_e=5.0)):
+        on = O.OracleNet(_with(wl.network, **prm))
+        g = O.zero_grads(on)
+        O.run_trial(on, b, 0, 2, g)
+        grads.append(g)
+    assert np.array_equal(grads[0]["w_rec"], grads[1]["w_rec"])
+    assert not rel_close(grads[0]["w_rec"], grads[2]["w_rec"], 1e-3)[0]
+    assert np.array_equal(grads[0]["w_out"], grads[2]["w_out"])   # the output gradient keeps F_kappa
