@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define EPROP_ABI_VERSION 2u
+#define EPROP_ABI_VERSION 3u
 
 typedef struct eprop_network eprop_network;   /* opaque, owned by the library */
 
@@ -76,10 +76,35 @@ typedef enum { EPROP_FP32 = 0, EPROP_FP64 = 1 } eprop_precision;
  * psi = gamma exp(-beta |v - A|). */
 typedef enum { EPROP_SG_PIECEWISE_LINEAR = 0, EPROP_SG_EXPONENTIAL = 1 } eprop_surrogate;
 
-/* eq. mean-squared-error (L = 1/2 sum_t sum_k (y - y*)^2) or eq. softmax with
- * eq. cross-entropy-loss (L = -sum_t sum_k pi* log pi), both gated by the
- * learning window. */
-typedef enum { EPROP_LOSS_MSE = 0, EPROP_LOSS_SOFTMAX_CE = 1 } eprop_loss;
+/* eq. mean-squared-error (L = 1/2 sum_t sum_k (y - y*)^2), eq. softmax with
+ * eq. cross-entropy-loss (L = -sum_t sum_k pi* log pi), or the temporal mean
+ * squared error of the e-prop+ classification runs (eq. temporal-mse:
+ * L = (1/K) sum_t sum_k (y - y*)^2 on the one-hot label, error signal
+ * E = (2/K)(y - y*)), all gated by the learning window.  Classification
+ * losses predict the arg max over k of the window's summed pi (CE) or y
+ * (temporal MSE). */
+typedef enum { EPROP_LOSS_MSE = 0, EPROP_LOSS_SOFTMAX_CE = 1, EPROP_LOSS_TEMPORAL_MSE = 2 } eprop_loss;
+
+/* Membrane reset after a spike: subtract the adaptive threshold
+ * (eq. lif_update), or set the membrane to v_reset as in the paper's e-prop+
+ * experiments (Methods, "Neuron models"): v^t = alpha v_reset + I^t after a
+ * spike.  With the full reset the eligibility's membrane component restarts
+ * after each postsynaptic spike (dv^t/dv^{t-1} = alpha (1 - z^{t-1})). */
+typedef enum { EPROP_RESET_SUBTRACT = 0, EPROP_RESET_TO_VALUE = 1 } eprop_reset;
+
+/* Filter of the eligibility trace (Results, "Eligibility trace filter
+ * decoupled from output time constant"): F_kappa with the readout's tau_out
+ * (eq. filtered-eligibility-trace), F_kappa_e with its own tau_e, or none
+ * (ebar = e).  The output-weight gradient always uses F_kappa. */
+typedef enum { EPROP_ETRACE_COUPLED = 0, EPROP_ETRACE_DECOUPLED = 1, EPROP_ETRACE_NONE = 2 } eprop_etrace_filter;
+
+/* Firing-rate regularisation: the static rate over the sample
+ * (eq. loss-firing-rate-regularization, eq. firing-rate-regularization) or
+ * the exponential moving average of e-prop+ (eq. ema-rate, eq. ema-gradient:
+ * f^t = beta f^{t-1} + (1 - beta) z^t, beta = exp(-dt/reg_tau); loss
+ * c^reg/2 sum_t sum_j (f_j^t - f*)^2; the gradient adds
+ * c^reg (f_j^s - f*) G_beta(e^s) for s <= T - d). */
+typedef enum { EPROP_REG_STATIC = 0, EPROP_REG_MOVING_AVERAGE = 1 } eprop_reg_mode;
 
 /* eq. gradient-descent, or Adam in the TensorFlow ordering
  * (eq. eta-adam-fast, eq. delta-w-adam-fast) with one step per iteration. */
@@ -147,6 +172,12 @@ typedef struct {
                                     add c^reg/T (f_j - f*) e_ji^t over steps t <= T - d */
   double f_target;               /* target rate f* in spikes per second (Hz), >= 0; the regulariser
                                     uses f_target * dt / 1000 spikes per step */
+  int32_t reset_mode;            /* eprop_reset */
+  double v_reset;                /* membrane after a spike with EPROP_RESET_TO_VALUE */
+  int32_t etrace_filter;         /* eprop_etrace_filter */
+  double tau_e;                  /* ms, > 0 with EPROP_ETRACE_DECOUPLED */
+  int32_t reg_mode;              /* eprop_reg_mode */
+  double reg_tau;                /* ms, > 0 with EPROP_REG_MOVING_AVERAGE */
   eprop_dev_alloc_fn dev_alloc;  /* NULL or the allocator above */
   eprop_dev_free_fn dev_free;    /* required with dev_alloc */
   void *alloc_ctx;

@@ -81,6 +81,9 @@ def lib():
         L.orc_forced_sampled.argtypes = [C.POINTER(_Net), C.POINTER(_Trial), C.c_int, P, P, P, P,
                                          C.POINTER(C.c_double)]
         L.orc_forced_sampled.restype = C.c_int
+        L.orc_run_online.argtypes = [C.POINTER(_Net), C.c_int, C.POINTER(_Trial), C.c_double, C.c_int, C.c_int,
+                                     P, P, P, P, P, P, P, P]
+        L.orc_run_online.restype = C.c_int
         L.orc_apply.argtypes = [C.c_long, P, P, C.c_double, C.c_int, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.c_long, P, P]
         L.orc_apply.restype = None
@@ -197,6 +200,28 @@ def run_trial(net: OracleNet, batch, b: int, grad_mode: int = 0, grads: dict = N
     if rc != 0:
         raise ValueError("oracle rejected the trial")
     return TrialResult(loss.value, pred.value, rec)
+
+
+def run_online(net: OracleNet, batch, eta: float, cutoff: int = 0, flush: bool = False) -> dict:
+    """e-prop+ update schedule over the batch's trials run back to back as one
+    continuous run (weight update at every arriving spike; see
+    orc_run_online).  The network's weights are trained in place.  Returns
+    the per-sample losses, the recurrent spikes [T_total, J] and the summed
+    gradients that were applied."""
+    keep: list = []
+    ns = net.cstruct()
+    n = batch.n_trials
+    trs = (_Trial * n)(*[_trial_struct(batch, b, keep) for b in range(n)])
+    Tt = int(np.sum(batch.n_steps[:n]))
+    g = zero_grads(net)
+    loss = np.zeros(n)
+    z = np.zeros((Tt, net.n_rec), dtype=np.uint8)
+    rc = lib().orc_run_online(C.byref(ns), n, trs, float(eta), int(cutoff), int(bool(flush)), _p(net.w_in),
+                              _p(net.w_rec), _p(net.w_out), _p(g["w_in"]), _p(g["w_rec"]), _p(g["w_out"]),
+                              _p(loss), _p(z))
+    if rc != 0:
+        raise ValueError("oracle rejected the run")
+    return {"loss": loss, "z": z, "grads": g}
 
 
 def zero_grads(net: OracleNet) -> dict:

@@ -201,9 +201,18 @@ static double syn_trace(const orc_net *net, const prep_t *p, double x, double zp
 
 /* Readout (eq. leaky_integrator), error signal and loss (eq. mean-squared-error
  * or eq. softmax + eq. cross-entropy-loss), window-gated. */
+static void readout_core(const orc_net *net, const prep_t *p, const spikes_t *sp, int t, const double *target_row,
+                         int win, int label, double *y, double *E, double *loss, double *psum);
+
 static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp,
                          const orc_trial *tr, int t, double *y, double *E, double *loss,
                          double *psum) {
+  readout_core(net, p, sp, t, tr->target ? tr->target + (long)(t - 1) * net->n_out : NULL,
+               tr->window ? tr->window[t - 1] : 1, tr->label, y, E, loss, psum);
+}
+
+static void readout_core(const orc_net *net, const prep_t *p, const spikes_t *sp, int t, const double *target_row,
+                         int win, int label, double *y, double *E, double *loss, double *psum) {
   const int J = net->n_rec, K = net->n_out;
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
@@ -211,12 +220,11 @@ static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp
       if (t - net->d_out >= 1 && sp->zrec[(long)(t - net->d_out) * J + j]) s = s + net->w_out[(long)k * J + j];
     y[k] = p->kappa * y[k] + s;
   }
-  const int win = tr->window ? tr->window[t - 1] : 1;
   if (net->loss == 2) {
     /* eq. temporal-mse on the one-hot label: L = (1/K) sum_t sum_k (y - y*)^2,
      * E = dL/dy = (2/K)(y - y*); the prediction sums y over the window */
     for (int k = 0; k < K; ++k) {
-      const double d = y[k] - (k == tr->label ? 1.0 : 0.0);
+      const double d = y[k] - (k == label ? 1.0 : 0.0);
       E[k] = win ? 2.0 / K * d : 0.0;
       if (win) {
         *loss += d * d / K;
@@ -225,7 +233,7 @@ static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp
     }
   } else if (net->loss == 0) {
     for (int k = 0; k < K; ++k) {
-      const double d = y[k] - tr->target[(long)(t - 1) * K + k];
+      const double d = y[k] - target_row[k];
       E[k] = win ? d : 0.0;
       if (win) *loss += 0.5 * d * d;
     }
@@ -236,10 +244,10 @@ static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp
     for (int k = 0; k < K; ++k) se += exp(y[k] - mx);
     for (int k = 0; k < K; ++k) {
       const double pi = exp(y[k] - mx) / se;
-      E[k] = win ? pi - (k == tr->label ? 1.0 : 0.0) : 0.0;
+      E[k] = win ? pi - (k == label ? 1.0 : 0.0) : 0.0;
       if (win) psum[k] += pi;
     }
-    if (win) *loss += -(y[tr->label] - mx - log(se));
+    if (win) *loss += -(y[label] - mx - log(se));
   }
 }
 
@@ -763,6 +771,204 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
   }
   if (loss_out) *loss_out = loss;
   free(y); free(E); free(psum); free(E_h); free(psi_h); free(L_h);
+  spikes_free(&sp);
+  prep_free(&p);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* e-prop+ update schedule: weight updates at every spike over a continuous
+ * run (see the header). */
+
+typedef struct {
+  double ev, ea, eb, gh;   /* eligibility vector, filtered trace, G_beta-filtered trace */
+  int s_done;              /* last eligibility step already used */
+  int last;                /* last arrival at or before s_done (0: none) */
+} online_syn;
+
+/* Advances one synapse (source kind/src, delay D, target j) over the
+ * eligibility steps s_done+1 .. s_new and returns the gradient they carry:
+ * sum_s L_j^{s+d} ebar^s + c (f_j^s - f*) G_beta(e^s) (Alg. "event-driven
+ * weight update", steps of the left-open interval). */
+static double online_walk(const orc_net *net, const prep_t *p, const spikes_t *sp, int kind, int src, int D, int j,
+                          online_syn *st, int s_new, int cutoff, const double *psi_h, const double *L_h,
+                          const double *f_h) {
+  const int J = net->n_rec;
+  const int ema = net->reg_mode == 1 && net->c_reg != 0.0;
+  double g = 0.0;
+  for (int s = st->s_done + 1; s <= s_new; ++s) {
+    const int x = spiked(sp, kind, src, s - D);
+    if (x) st->last = s;
+    if (cutoff > 0 && (st->last == 0 || s - st->last >= cutoff)) {
+      /* beyond the cutoff the traces count as decayed */
+      st->ev = st->ea = st->eb = st->gh = 0.0;
+      continue;
+    }
+    const double e = syn_trace(net, p, x ? 1.0 : 0.0, sp->zrec[(long)(s - 1) * J + j], psi_h[(long)(s - 1) * J + j],
+                               psi_h[(long)s * J + j], neuron_beta(net, j), &st->ev, &st->ea, &st->eb);
+    st->gh = p->beta_f * st->gh + (1.0 - p->beta_f) * e;
+    g += L_h[(long)(s + net->d_out) * J + j] * st->eb;
+    if (ema) g += net->c_reg * (f_h[(long)s * J + j] - net->f_target) * st->gh;
+  }
+  if (s_new > st->s_done) st->s_done = s_new;
+  return g;
+}
+
+/* The readout side: zbar_j^r = kappa zbar_j^{r-1} + z_j^r over r_done+1 ..
+ * r_new, each r adding E_k^{r+d} zbar_j^r to g[k]
+ * (eq. eprop-output-new-subs-rewritten), with the same cutoff rule. */
+static void online_walk_out(const orc_net *net, const prep_t *p, const spikes_t *sp, int j, double *zb, int *r_done,
+                            int *last, int r_new, int cutoff, const double *E_h, double *g) {
+  const int J = net->n_rec, K = net->n_out;
+  for (int r = *r_done + 1; r <= r_new; ++r) {
+    const int x = sp->zrec[(long)r * J + j];
+    if (x) *last = r;
+    if (cutoff > 0 && (*last == 0 || r - *last >= cutoff)) {
+      *zb = 0.0;
+      continue;
+    }
+    *zb = p->kappa * *zb + (x ? 1.0 : 0.0);
+    for (int k = 0; k < K; ++k) g[k] += E_h[(long)(r + net->d_out) * K + k] * *zb;
+  }
+  if (r_new > *r_done) *r_done = r_new;
+}
+
+int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, double eta, int cutoff,
+                   int flush, double *w_in, double *w_rec, double *w_out, double *g_in, double *g_rec,
+                   double *g_out, double *loss_out, unsigned char *z_out) {
+  if (!net0 || !smp || n_samples < 1 || !w_in || !w_rec || !w_out || !loss_out || cutoff < 0) return -1;
+  if (net0->c_reg != 0.0 && net0->reg_mode != 1) return -1;
+  orc_net nt = *net0;  /* the same network, reading the weights being trained */
+  nt.in.w = w_in;
+  nt.rec.w = w_rec;
+  nt.w_out = w_out;
+  const orc_net *net = &nt;
+  long Tt = 0;
+  for (int k = 0; k < n_samples; ++k) {
+    if (check_net(net, &smp[k]) || smp[k].forced != smp[0].forced) return -1;
+    Tt += smp[k].n_steps;
+  }
+  if (Tt > 1000000) return -1;
+  const int T = (int)Tt, I = net->n_in, J = net->n_rec, K = net->n_out;
+  prep_t p;
+  if (prep_init(net, &p)) return -1;
+  /* the run's spike record: sample k's steps are off_k + 1 .. off_k + T_k */
+  spikes_t sp;
+  memset(&sp, 0, sizeof(sp));
+  sp.T = T;
+  sp.I = I;
+  sp.J = J;
+  int *off = calloc((size_t)n_samples + 1, sizeof(int)), *smp_of = calloc((size_t)T + 1, sizeof(int));
+  sp.zin = calloc((size_t)T * (I > 0 ? I : 1), 1);
+  sp.zrec = calloc((size_t)(T + 1) * J, 1);
+  if (smp[0].forced) sp.zforced = calloc((size_t)(T + 1) * J, 1);
+  double *v = calloc(J, sizeof(double)), *a = calloc(J, sizeof(double)), *y = calloc(K, sizeof(double));
+  double *E = calloc(K, sizeof(double)), *psum = calloc(K, sizeof(double)), *gk = calloc(K, sizeof(double));
+  int *refr = calloc(J, sizeof(int));
+  double *psi_h = calloc((size_t)(T + 1) * J, sizeof(double)), *L_h = calloc((size_t)(T + 1) * J, sizeof(double));
+  double *f_h = calloc((size_t)(T + 1) * J, sizeof(double)), *E_h = calloc((size_t)(T + 1) * K, sizeof(double));
+  const long nin = net->in.nnz, ns = net->in.nnz + net->rec.nnz;
+  online_syn *syn = calloc((size_t)ns + 1, sizeof(online_syn));
+  double *zbo = calloc(J, sizeof(double));
+  int *r_done = calloc(J, sizeof(int)), *zlast = calloc(J, sizeof(int));
+  int rc = -1;
+  if (!off || !smp_of || !sp.zin || !sp.zrec || (smp[0].forced && !sp.zforced) || !v || !a || !y || !E || !psum ||
+      !gk || !refr || !psi_h || !L_h || !f_h || !E_h || !syn || !zbo || !r_done || !zlast)
+    goto done;
+  for (int k = 0; k < n_samples; ++k) {
+    off[k + 1] = off[k] + smp[k].n_steps;
+    for (int t = off[k] + 1; t <= off[k + 1]; ++t) smp_of[t] = k;
+    for (long e = 0; e < smp[k].n_in_spikes; ++e) {
+      const unsigned int s0 = smp[k].in_step[e], i = smp[k].in_src[e];
+      if ((int)s0 >= smp[k].n_steps || (int)i >= I) goto done;
+      sp.zin[(long)(off[k] + s0) * I + i] = 1;
+    }
+    for (long e = 0; smp[k].forced && e < smp[k].n_forced; ++e) {
+      const unsigned int t0 = smp[k].forced_step[e], j = smp[k].forced_neuron[e];
+      if (t0 < 1 || (int)t0 > smp[k].n_steps || (int)j >= J) goto done;
+      sp.zforced[(long)(off[k] + t0) * J + j] = 1;
+    }
+  }
+  for (int k = 0; k < n_samples; ++k) loss_out[k] = 0.0;
+  const int d = net->d_out, lag = 1 + net->d_ls + net->d_out;
+  for (int t = 1; t <= T; ++t) {
+    const int k = smp_of[t], lt = t - off[k];
+    const orc_trial *tr = &smp[k];
+    for (int j = 0; j < J; ++j) {
+      /* arrivals at t: update first, then deliver with the new weight
+       * (eq. lif_update's input sums, canonical order) */
+      double I_t = 0.0;
+      for (long q = p.in_ptr[j]; q < p.in_ptr[j + 1]; ++q) {
+        const in_syn *si = &p.syn[q];
+        if (!spiked(&sp, si->kind, si->src, t - si->delay)) continue;
+        const long sq = si->kind == 0 ? si->idx : nin + si->idx;
+        const double g = online_walk(net, &p, &sp, si->kind, si->src, si->delay, j, &syn[sq], t - lag, cutoff, psi_h,
+                                     L_h, f_h);
+        double *w = si->kind == 0 ? &w_in[si->idx] : &w_rec[si->idx];
+        *w = *w - eta * g;
+        if (si->kind == 0 && g_in) g_in[si->idx] += g;
+        if (si->kind == 1 && g_rec) g_rec[si->idx] += g;
+        I_t = I_t + *w;
+      }
+      const double zprev = sp.zrec[(long)(t - 1) * J + j] ? 1.0 : 0.0;
+      const int fz = sp.zforced ? sp.zforced[(long)t * J + j] : -1;
+      double psi;
+      const int z = neuron_step(net, &p, j, I_t, zprev, fz, &v[j], &a[j], &refr[j], &psi);
+      sp.zrec[(long)t * J + j] = (unsigned char)z;
+      psi_h[(long)t * J + j] = psi;
+      f_h[(long)t * J + j] = p.beta_f * f_h[(long)(t - 1) * J + j] + (1.0 - p.beta_f) * z;
+      if (z_out) z_out[(long)(t - 1) * J + j] = (unsigned char)z;
+    }
+    /* readout synapses whose presynaptic spike arrives now */
+    for (int j = 0; j < J && t - d >= 1; ++j) {
+      if (!sp.zrec[(long)(t - d) * J + j]) continue;
+      for (int kk = 0; kk < K; ++kk) gk[kk] = 0.0;
+      online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], t - 1 - d, cutoff, E_h, gk);
+      for (int kk = 0; kk < K; ++kk) {
+        w_out[(long)kk * J + j] -= eta * gk[kk];
+        if (g_out) g_out[(long)kk * J + j] += gk[kk];
+      }
+    }
+    readout_core(net, &p, &sp, t, tr->target ? tr->target + (long)(lt - 1) * K : NULL,
+                 tr->window ? tr->window[lt - 1] : 1, tr->label, y, E, &loss_out[k], psum);
+    for (int kk = 0; kk < K; ++kk) E_h[(long)t * K + kk] = E[kk];
+    for (int j = 0; j < J; ++j) {
+      double Ls = 0.0;
+      for (int kk = 0; kk < K; ++kk) Ls = Ls + net->fb[(long)j * K + kk] * E[kk];
+      L_h[(long)t * J + j] = Ls;
+      if (net->reg_mode == 1 && net->c_reg != 0.0) {
+        const double df = f_h[(long)t * J + j] - net->f_target;
+        loss_out[k] += 0.5 * net->c_reg * df * df;
+      }
+    }
+  }
+  if (flush) {
+    /* as if a spike arrived at every synapse after the last step */
+    for (int kind = 0; kind < 2; ++kind) {
+      const orc_proj *pr = kind == 0 ? &net->in : &net->rec;
+      for (int i = 0; i < pr->n_src; ++i)
+        for (unsigned long r = pr->row_ptr[i]; r < pr->row_ptr[i + 1]; ++r) {
+          const long sq = kind == 0 ? (long)r : nin + (long)r;
+          const double g = online_walk(net, &p, &sp, kind, i, pr->delay[r], (int)pr->col[r], &syn[sq], T + 1 - lag,
+                                       cutoff, psi_h, L_h, f_h);
+          (kind == 0 ? w_in : w_rec)[r] -= eta * g;
+          if (kind == 0 && g_in) g_in[r] += g;
+          if (kind == 1 && g_rec) g_rec[r] += g;
+        }
+    }
+    for (int j = 0; j < J; ++j) {
+      for (int kk = 0; kk < K; ++kk) gk[kk] = 0.0;
+      online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], T - d, cutoff, E_h, gk);
+      for (int kk = 0; kk < K; ++kk) {
+        w_out[(long)kk * J + j] -= eta * gk[kk];
+        if (g_out) g_out[(long)kk * J + j] += gk[kk];
+      }
+    }
+  }
+  rc = 0;
+done:
+  free(off); free(smp_of); free(v); free(a); free(y); free(E); free(psum); free(gk); free(refr);
+  free(psi_h); free(L_h); free(f_h); free(E_h); free(syn); free(zbo); free(r_done); free(zlast);
   spikes_free(&sp);
   prep_free(&p);
   return rc;

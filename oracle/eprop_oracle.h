@@ -107,6 +107,31 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *trial, int n_sample,
                        const int *targets, double *g_in, double *g_rec,
                        double *psi_out, double *loss);
 
+/* e-prop+ update schedule (Results, "Weight updates with every spike";
+ * Alg. "event-driven weight update" applied at every spike): one network
+ * instance runs through n_samples samples back to back, its state (neurons,
+ * readout, synaptic traces, histories) carried from one to the next
+ * (Results, "Continuous dynamics").  A spike arriving at a synapse at step a
+ * first updates the synapse's weight by gradient descent, w -= eta g, with
+ * g the e-prop gradient over the eligibility steps s not yet used whose
+ * learning signal L^{s+d} has reached the neuron, s <= a - 1 - d^ls - d
+ * (plus the moving-average regulariser's c (f^s - f*) G_beta(e^s)); the
+ * spike is then transmitted with the new weight.  A readout synapse j -> k
+ * does the same when z_j arrives at the readout, with E_k^{r+d} zbar_j^r over
+ * r <= a - 1 - d.  With cutoff > 0 an eligibility step s contributes only if
+ * s - (the synapse's last arrival at or before s) < cutoff; beyond that the
+ * traces are taken as zero (eprop_isi_trace_cutoff).  Gradients the run
+ * ends before using are dropped, unless flush is set, which applies them at
+ * the end as if a spike arrived after the last step.
+ * Weights w_in, w_rec, w_out are updated in place (the network's own weight
+ * arrays are not used); g_in, g_rec, g_out, if not NULL, accumulate every
+ * gradient applied; loss [n_samples] gets each sample's loss; z, if not
+ * NULL, the recurrent spikes [T_total*J].  Static rate regularisation and
+ * Adam have no per-spike form here; returns -1 for them. */
+int orc_run_online(const orc_net *net, int n_samples, const orc_trial *samples, double eta, int cutoff,
+                   int flush, double *w_in, double *w_rec, double *w_out, double *g_in, double *g_rec,
+                   double *g_out, double *loss, unsigned char *z);
+
 /* End of iteration: G = g_sum / n_trials, then gradient descent or Adam in
  * the TensorFlow ordering (step = iteration count, starting at 1). */
 void orc_apply(long n, double *w, const double *g_sum, double n_trials, int optimizer,

@@ -197,7 +197,8 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
   if (!(c->t_ref >= 0) || !is_finite(c->t_ref) || std::lround(c->t_ref / c->dt) > 127)
     return bad("t_ref must give 0..127 refractory steps");
   if (c->surrogate != EPROP_SG_PIECEWISE_LINEAR && c->surrogate != EPROP_SG_EXPONENTIAL) return bad("unknown surrogate");
-  if (c->loss != EPROP_LOSS_MSE && c->loss != EPROP_LOSS_SOFTMAX_CE) return bad("unknown loss");
+  if (c->loss != EPROP_LOSS_MSE && c->loss != EPROP_LOSS_SOFTMAX_CE && c->loss != EPROP_LOSS_TEMPORAL_MSE)
+    return bad("unknown loss");
   if (c->optimizer != EPROP_OPT_GD && c->optimizer != EPROP_OPT_ADAM) return bad("unknown optimizer");
   if (!is_finite(c->eta)) return bad("non-finite learning rate");
   if (c->optimizer == EPROP_OPT_ADAM &&
@@ -216,6 +217,15 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
   if (c->d_out > 65535 || c->d_ls > 65535) return bad("d_out and d_ls must be in 0..65535");
   if (!(c->c_reg >= 0) || !is_finite(c->c_reg)) return bad("c_reg must be finite and >= 0");
   if (!(c->f_target >= 0) || !is_finite(c->f_target)) return bad("f_target must be finite and >= 0");
+  if (c->reset_mode != EPROP_RESET_SUBTRACT && c->reset_mode != EPROP_RESET_TO_VALUE) return bad("unknown reset_mode");
+  if (!is_finite(c->v_reset)) return bad("non-finite v_reset");
+  if (c->etrace_filter < EPROP_ETRACE_COUPLED || c->etrace_filter > EPROP_ETRACE_NONE)
+    return bad("unknown etrace_filter");
+  if (c->etrace_filter == EPROP_ETRACE_DECOUPLED && (!(c->tau_e > 0) || !is_finite(c->tau_e)))
+    return bad("tau_e must be finite and > 0 for the decoupled eligibility filter");
+  if (c->reg_mode != EPROP_REG_STATIC && c->reg_mode != EPROP_REG_MOVING_AVERAGE) return bad("unknown reg_mode");
+  if (c->reg_mode == EPROP_REG_MOVING_AVERAGE && (!(c->reg_tau > 0) || !is_finite(c->reg_tau)))
+    return bad("reg_tau must be finite and > 0 for the moving-average regulariser");
   if (c->history_steps != 0 && c->history_steps < c->max_steps) {
     msg = "the history covers whole trials: history_steps must be 0 or >= max_steps";
     return EPROP_ERR_UNSUPPORTED;
@@ -241,6 +251,12 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   d.d_out = n->cfg.d_out; d.d_ls = n->cfg.d_ls;
   d.c_reg = n->cfg.c_reg;
   d.f_target = n->cfg.f_target * n->cfg.dt / 1000.0;
+  d.reset_mode = n->cfg.reset_mode;
+  d.v_reset = (real)n->cfg.v_reset;
+  d.kappa_e_d = n->cfg.etrace_filter == EPROP_ETRACE_DECOUPLED ? std::exp(-n->cfg.dt / n->cfg.tau_e)
+                : n->cfg.etrace_filter == EPROP_ETRACE_NONE ? 0.0 : n->kappa;
+  d.reg_mode = n->cfg.c_reg != 0.0 ? n->cfg.reg_mode : EPROP_REG_STATIC;
+  d.beta_f = n->cfg.reg_mode == EPROP_REG_MOVING_AVERAGE ? std::exp(-n->cfg.dt / n->cfg.reg_tau) : 0.0;
   uint32_t *p32;
   real *pr;
   bool ok = true;
@@ -298,7 +314,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.y, B * T2 * n->K);
   ok &= dalloc(n, &d.err, B * T2 * n->K);
   ok &= dalloc(n, &d.ebar, B * T2 * n->K);
-  if (n->cfg.d_ls) ok &= dalloc(n, &d.ebo, B * T2 * n->K);
+  if (n->cfg.d_ls || n->cfg.etrace_filter != EPROP_ETRACE_COUPLED) ok &= dalloc(n, &d.ebo, B * T2 * n->K);
   else d.ebo = d.ebar;
   ok &= dalloc(n, &d.loss_out, B);
   ok &= dalloc(n, &d.pred_out, B);
@@ -837,8 +853,8 @@ eprop_status check_batch(eprop_network *n, const eprop_batch *b, std::vector<uin
   }
   if (b->step_stride < t_max) return bad("step_stride smaller than the longest trial");
   if (n->cfg.loss == EPROP_LOSS_MSE && !b->target) return bad("MSE needs a target");
-  if (n->cfg.loss == EPROP_LOSS_SOFTMAX_CE) {
-    if (!b->label) return bad("cross-entropy needs labels");
+  if (n->cfg.loss == EPROP_LOSS_SOFTMAX_CE || n->cfg.loss == EPROP_LOSS_TEMPORAL_MSE) {
+    if (!b->label) return bad("classification losses need labels");
     for (uint32_t i = 0; i < b->n_trials; ++i)
       if (b->label[i] >= n->K) return bad("label out of range");
   }
@@ -949,6 +965,10 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   const bool train = (b->flags & EPROP_BATCH_TRAIN) != 0;
   const bool prof = (b->flags & EPROP_BATCH_PROFILE) != 0;
   const bool time_driven = train && (b->flags & EPROP_BATCH_TIME_DRIVEN) != 0;
+  if (time_driven && n->cfg.reg_mode == EPROP_REG_MOVING_AVERAGE && n->cfg.c_reg != 0.0) {
+    set_fail(n, "the time-driven baseline has no moving-average regulariser");
+    return EPROP_ERR_UNSUPPORTED;
+  }
   if (time_driven) {
     const size_t need = (size_t)n->Bcap * (n->Tcap + 1) * n->Jp * sizeof(real);
     uint8_t *lb = static_cast<uint8_t *>(n->Lbuf);

@@ -93,6 +93,11 @@ struct DevNet {
   double alpha_d, rho_d, kappa_d;
   uint32_t d_out, d_ls;         // readout delay d, learning-signal delay d^ls (steps)
   double c_reg, f_target;       // rate regulariser coefficient and target rate (spikes per step)
+  int32_t reset_mode;           // 0 subtract the threshold, 1 reset to v_reset
+  real v_reset;
+  double kappa_e_d;             // the eligibility filter's factor (kappa unless decoupled; 0: none)
+  int32_t reg_mode;             // 0 static rate, 1 moving average (only with c_reg != 0)
+  double beta_f;                // the moving average's factor
   // graph
   const uint32_t *sm_ptr, *tseg;
   SynRec<real> *sm;
@@ -132,8 +137,9 @@ struct DevNet {
   double *ysum, *y, *err;       // [Bcap][Tcap+2][K]
   double *ebar;                 // [Bcap][Tcap+2][K] backward-filtered error paired with the
                                 // eligibility of step u: sum_{v=u}^{T-d-d^ls} kappa^{v-u} E^{v+d}
-  double *ebo;                  // the same without the learning-signal cut (upper end T-d), for
-                                // the output gradient; aliases ebar when d^ls = 0
+  double *ebo;                  // the same with the readout's kappa and without the learning-signal
+                                // cut (upper end T-d), for the output gradient; aliases ebar when
+                                // d^ls = 0 and the eligibility filter is the readout's
   double *loss_out;             // [Bcap]
   uint32_t *pred_out;           // [Bcap]
   // batch (device pointers)

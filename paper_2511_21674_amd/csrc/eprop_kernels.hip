@@ -151,7 +151,8 @@ __device__ inline bool neuron_step(const DevNet<real> &n, uint32_t b, uint32_t t
     a = n.rho * a + zprev;
     A = n.v_th + beta * a;
   }
-  v = n.alpha * v + I - zprev * A;
+  if (n.reset_mode == 1) v = n.alpha * (zprev != (real)0 ? n.v_reset : v) + I;  // full reset to v_reset
+  else v = n.alpha * v + I - zprev * A;
   const bool refractory = refr > 0;
   if (refractory) refr -= 1;
   bool z;
@@ -585,12 +586,13 @@ __global__ __launch_bounds__(256) void k_readout_sums(DevNet<real> n) {
 
 // Per trial (one block of 256): readout recursion y^t = kappa y^{t-1} +
 // ysum^{t-d} (readout delay d, Supplementary "Delay from the recurrent to the
-// output layer"), error signal and loss (window-gated), the rate
-// regulariser's loss (eq. loss-firing-rate-regularization), prediction, and
-// the backward filters of the error shifted by d: ebar^u = E^{u+d} + kappa
-// ebar^{u+1} up to u = T-d-d^ls (the learning signals the recurrent gradient
-// takes) and ebo^u the same up to u = T-d (output gradient); both 0 beyond.
-// All FP64, fixed summation order.
+// output layer"), error signal and loss (window-gated; MSE, cross-entropy
+// or temporal MSE), the rate regulariser's loss (static or moving average),
+// prediction, and the backward filters of the error shifted by d:
+// ebar^u = E^{u+d} + kappa_e ebar^{u+1} up to u = T-d-d^ls (the learning
+// signals the recurrent gradient takes, with the eligibility's filter) and
+// ebo^u with kappa up to u = T-d (output gradient); both 0 beyond.  All
+// FP64, fixed summation order.
 template <typename real>
 __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   const uint32_t b = blockIdx.x;
@@ -609,7 +611,7 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   }
   __syncthreads();
   double lp = 0.0;
-  const uint32_t label = n.loss == 1 ? n.label[b] : 0u;
+  const uint32_t label = n.loss != 0 ? n.label[b] : 0u;
   for (uint32_t t = 1 + tid; t <= T; t += blockDim.x) {
     const bool win = n.window ? n.window[(size_t)b * n.step_stride + t - 1] != 0 : true;
     const double *yt = y + (size_t)t * K;
@@ -620,6 +622,16 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
         const double d = yt[k] - tg[k];
         et[k] = win ? d : 0.0;
         if (win) lp += 0.5 * d * d;
+      }
+    } else if (n.loss == 2) {
+      // eq. temporal-mse on the one-hot label; the window's y rows (kept in
+      // the ysum row, no longer needed) give the prediction
+      double *yw = ysum + (size_t)t * K;
+      for (uint32_t k = 0; k < K; ++k) {
+        const double d = yt[k] - (k == label ? 1.0 : 0.0);
+        et[k] = win ? 2.0 / K * d : 0.0;
+        if (win) lp += d * d / K;
+        yw[k] = win ? yt[k] : 0.0;
       }
     } else {
       double mx = yt[0];
@@ -635,12 +647,38 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
       if (win) lp += -(yt[label] - mx - log(se));
     }
   }
-  if (n.c_reg != 0.0) {
+  if (n.c_reg != 0.0 && n.reg_mode == 0) {
     const uint32_t *cnt = n.spk_cnt + (size_t)b * n.NS + n.I;
     double rl = 0.0;
     for (uint32_t j = tid; j < n.J; j += blockDim.x) {
       const double f = (double)cnt[j] / (double)T - n.f_target;
       rl += f * f;
+    }
+    lp += 0.5 * n.c_reg * rl;
+  } else if (n.c_reg != 0.0) {
+    // moving-average rate (eq. ema-rate): between spikes f decays by beta,
+    // so each inter-spike stretch of the loss c/2 sum_t (f^t - f*)^2 is a
+    // pair of geometric series
+    const double be = n.beta_f, fs = n.f_target;
+    const double g1 = be / (1.0 - be), g2 = be * be / (1.0 - be * be);
+    double rl = 0.0;
+    for (uint32_t j = tid; j < n.J; j += blockDim.x) {
+      const uint32_t c = n.spk_cnt[(size_t)b * n.NS + n.I + j];
+      const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
+      double f = 0.0;
+      uint32_t prev = 0;  // step of f's last value
+      for (uint32_t i = 0; i <= c; ++i) {
+        const uint32_t u = i < c ? (uint32_t)st[i] : T + 1;
+        const double m = (double)(u - prev - 1);  // steps strictly between, f decaying from f
+        // sum_{k=1}^{m} (f be^k - fs)^2
+        const double bm = pow(be, m);
+        rl += f * f * g2 * (1.0 - bm * bm) - 2.0 * f * fs * g1 * (1.0 - bm) + m * fs * fs;
+        if (i < c) {
+          f = be * f * bm + (1.0 - be);
+          rl += (f - fs) * (f - fs);
+          prev = u;
+        }
+      }
     }
     lp += 0.5 * n.c_reg * rl;
   }
@@ -654,16 +692,17 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   }
   // last index of each filter (signed: a trial may be shorter than the delays)
   const int64_t u_out = (int64_t)T - d, u_rec = u_out - (int64_t)n.d_ls;
+  const double kap_e = n.kappa_e_d;
   for (uint32_t k = tid; k < K; k += blockDim.x) {
     double eb = 0.0, eo = 0.0;
     for (int64_t u = T; u >= 1; --u) {
       const double e = u <= u_out ? err[(size_t)(u + d) * K + k] : 0.0;
       eo = e + kap * eo;
-      eb = u <= u_rec ? e + kap * eb : 0.0;
+      eb = u <= u_rec ? e + kap_e * eb : 0.0;
       ebar[(size_t)u * K + k] = eb;
       if (ebo != ebar) ebo[(size_t)u * K + k] = eo;
     }
-    if (n.loss == 1 && k < 64) {
+    if (n.loss != 0 && k < 64) {
       double s = 0.0;
       for (uint32_t t = 1; t <= T; ++t) s += ysum[(size_t)t * K + k];
       psum[k] = s;
@@ -676,7 +715,7 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
     atomicAdd(&n.cnt[CNT_REC_SPIKES], ns);
     n.loss_out[b] = red[0];
     uint32_t best = 0;
-    if (n.loss == 1)
+    if (n.loss != 0)
       for (uint32_t k = 1; k < K && k < 64; ++k)
         if (psum[k] > psum[best]) best = k;
     n.pred_out[b] = best;
@@ -711,13 +750,36 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   // rate regulariser (eq. firing-rate-regularization): c^reg/T (f_j - f*)
   // multiplies the eligibility of every step u <= T - d, so it adds to the
   // adjoint's learning-signal sum there
-  const double creg = (live && n.c_reg != 0.0)
+  const bool ema = n.reg_mode == 1;
+  const double creg = (live && n.c_reg != 0.0 && !ema)
                           ? n.c_reg / (double)T *
                                 ((double)n.spk_cnt[(size_t)b * n.NS + n.I + j] / (double)T - n.f_target)
                           : 0.0;
   const int64_t u_reg = (int64_t)T - n.d_out;
   const real *ps_col = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
   const uint32_t wbase = tid & ~63u, lane = tid & 63u;
+  const uint32_t c = live ? n.spk_cnt[(size_t)b * n.NS + n.I + j] : 0u;
+  const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
+  real *phi_row = n.phi + ((size_t)b * n.Jp + j) * n.Tp;
+  // Moving-average regulariser (eq. ema-gradient): sum_s c (f^s - f*) G_beta(e^s)
+  // over s <= T - d equals sum_s e^s R^s with the backward filter
+  // R^s = c (1 - beta)(f^s - f*) + beta R^{s+1}, added to the learning-signal
+  // sum.  The rate f (eq. ema-rate) is f^u at the neuron's spike steps u and
+  // decays by beta in between; its values at the spikes are computed forward
+  // first and parked in the neuron's archive row at those steps, which the
+  // backward pass overwrites only after it has read them.
+  if (ema && live) {
+    double f = 0.0;
+    uint32_t prev = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+      f = n.beta_f * f * pow(n.beta_f, (double)(st[i] - prev - 1)) + (1.0 - n.beta_f);
+      prev = st[i];
+      phi_row[st[i]] = (real)f;
+    }
+  }
+  int32_t sp_i = (int32_t)c - 1;  // last spike at or before the current step
+  double f_sp = (ema && sp_i >= 0) ? (double)phi_row[st[sp_i]] : 0.0, R = 0.0;
+  const uint64_t *zrow = n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw + (inrow ? (j >> 6) : 0u);
   double mu0 = 0.0, mu1 = 0.0;
   for (int m = (int)(T / 16); m >= 0; --m) {
     const uint32_t tb = (uint32_t)m * 16;
@@ -741,9 +803,21 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
         double L = 0.0;
         for (uint32_t k = 0; k < K; ++k) L += fbl[k * bd + tid] * ebl[r * K + k];
         if ((int64_t)t <= u_reg) L += creg;
+        if (ema) {
+          while (sp_i >= 0 && st[sp_i] > t) {
+            --sp_i;
+            f_sp = sp_i >= 0 ? (double)phi_row[st[sp_i]] : 0.0;
+          }
+          const double f = sp_i >= 0 ? f_sp * pow(n.beta_f, (double)(t - st[sp_i])) : 0.0;
+          R = ((int64_t)t <= u_reg ? n.c_reg * (1.0 - n.beta_f) * (f - n.f_target) : 0.0) + n.beta_f * R;
+          L += R;
+        }
         const double p = (double)ps[r];
         const double pl = p * L;
-        const double m0 = pl + n.alpha_d * mu0 + p * mu1;
+        // with the full reset the membrane's derivative restarts after a
+        // spike of this neuron at step t: alpha (1 - z^t)
+        const bool zt = n.reset_mode == 1 && inrow && ((zrow[(size_t)t * n.Jw] >> (j & 63u)) & 1ull);
+        const double m0 = pl + (zt ? 0.0 : n.alpha_d) * mu0 + p * mu1;
         const double m1 = -beta * pl + (n.rho_d - p * beta) * mu1;
         mu0 = m0;
         mu1 = m1;
@@ -761,8 +835,6 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
     }
   }
   if (!live) return;
-  const uint32_t c = n.spk_cnt[(size_t)b * n.NS + n.I + j];
-  const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
   real *go = n.gout_b + (size_t)b * K * n.Jp + j;
   const double *eo = n.ebo + (size_t)b * (n.Tcap + 2) * K;
   for (uint32_t k = 0; k < K; ++k) {
@@ -1013,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
     const bool is_in = src < n.I;
     const uint32_t si = is_in ? src : src - n.I;
     const real beta = n.beta_j[j];
-    const real kappa = (real)n.kappa_d;
+    const real kappa = (real)n.kappa_e_d;  // the eligibility trace's filter
     const uint32_t ntr = n.ctl[CTL_NTRIALS];
     const uint32_t b0 = c * ginst, nb = b0 < ntr ? min(ginst, ntr - b0) : 0u;
     real s = 0, cc = 0;
@@ -1037,7 +1109,10 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
         arrivals += x;
         const real psi_now = ps[(size_t)t * n.Jp];
         const real ea_new = psi_prev * ev + (n.rho - psi_prev * beta) * ea;
-        const real ev_new = n.alpha * ev + (real)x;
+        // full reset: the membrane component restarts after a spike of j at t - 1
+        const bool zr = n.reset_mode == 1 &&
+                        ((n.rec_bits[((size_t)b * (n.Tcap + 1) + t - 1) * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull);
+        const real ev_new = (zr ? (real)0 : n.alpha) * ev + (real)x;
         const real e = psi_now * (ev_new - beta * ea_new);
         eb = kappa * eb + e;
         ev = ev_new;

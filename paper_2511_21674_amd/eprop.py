@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeprop_hip.so")
 
-EPROP_ABI_VERSION = 2
+EPROP_ABI_VERSION = 3
 EPROP_OK, EPROP_ERR_INVALID_ARGUMENT, EPROP_ERR_OUT_OF_MEMORY = 0, -1, -2
 EPROP_ERR_DEVICE, EPROP_ERR_STATE, EPROP_ERR_CAPACITY = -3, -4, -5
 EPROP_ERR_NUMERIC, EPROP_ERR_UNSUPPORTED = -6, -7
@@ -27,6 +27,10 @@ EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS, EPROP_AUTOTUNE =
 EPROP_MEM_HOST, EPROP_MEM_DEVICE = 0, 1
 EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE, EPROP_RECORD_SPIKES, EPROP_RECORD_TRACES = 1, 2, 4, 8
 EPROP_BATCH_TIME_DRIVEN = 16
+EPROP_LOSS_MSE, EPROP_LOSS_SOFTMAX_CE, EPROP_LOSS_TEMPORAL_MSE = 0, 1, 2
+EPROP_RESET_SUBTRACT, EPROP_RESET_TO_VALUE = 0, 1
+EPROP_ETRACE_COUPLED, EPROP_ETRACE_DECOUPLED, EPROP_ETRACE_NONE = 0, 1, 2
+EPROP_REG_STATIC, EPROP_REG_MOVING_AVERAGE = 0, 1
 EPROP_TRAIN = EPROP_BATCH_TRAIN
 EPROP_N_PHASES = 8
 PHASES = ("stage", "forward", "readout", "adjoint", "synapse", "output")
@@ -55,6 +59,8 @@ class eprop_config(C.Structure):
                 ("max_delay", C.c_uint32), ("max_trials", C.c_uint32), ("max_steps", C.c_uint32),
                 ("delivery", C.c_int32), ("flags", C.c_uint32), ("d_out", C.c_uint32), ("d_ls", C.c_uint32),
                 ("history_steps", C.c_uint32), ("c_reg", C.c_double), ("f_target", C.c_double),
+                ("reset_mode", C.c_int32), ("v_reset", C.c_double), ("etrace_filter", C.c_int32),
+                ("tau_e", C.c_double), ("reg_mode", C.c_int32), ("reg_tau", C.c_double),
                 ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
                 ("alloc_ctx", _P)]
 
@@ -229,6 +235,9 @@ class Network:
                            max_trials=max_trials, max_steps=max_steps,
                            d_out=int(getattr(p, "d_out", 0)), d_ls=int(getattr(p, "d_ls", 0)),
                            c_reg=float(getattr(p, "c_reg", 0.0)), f_target=float(getattr(p, "f_target_hz", 0.0)),
+                           reset_mode=int(getattr(p, "reset_mode", 0)), v_reset=float(getattr(p, "v_reset", 0.0)),
+                           etrace_filter=int(getattr(p, "etrace_filter", 0)), tau_e=float(getattr(p, "tau_e", 0.0)),
+                           reg_mode=int(getattr(p, "reg_mode", 0)), reg_tau=float(getattr(p, "reg_tau", 0.0)),
                            delivery={"auto": 0, "scatter": 1, "gather": 2}[delivery],
                            flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0)
                            | (EPROP_AUTOTUNE if autotune else 0))

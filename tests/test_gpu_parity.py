@@ -679,3 +679,75 @@ def test_fp32_adam_state_and_input_bound_after_updates():
     log(f"input bound {bound:.6g}, largest sum of |w| into one target {l1.max():.6g}")
     indeg = np.bincount(pr_in.col, minlength=wl.network.n_rec) + np.bincount(pr_rec.col, minlength=wl.network.n_rec)
     assert l1.max() <= bound <= l1.max() * 1.001 * (1 + 1e-6) + indeg.max() * 2.0 ** -16
+
+
+# ----------------------------------------------------------------- e-prop+ components
+
+EPROP_PLUS = dict(reset_mode=1, v_reset=-0.2, etrace_filter=1, tau_e=8.0, reg_mode=1, reg_tau=50.0,
+                  c_reg=30.0, f_target_hz=20.0)
+
+
+def _plus(name, **extra):
+    if name == "tiny":
+        wl, bs = W.tiny(loss=2), 2
+    elif name == "c2":
+        wl, bs = W.c2_evidence(batch_size=3), 3
+    elif name == "c3":
+        wl, bs = W.c3_events(batch_size=3), 3
+    else:
+        wl, bs = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), 2
+    p = wl.network.params
+    for k, v in dict(EPROP_PLUS, **extra).items():
+        setattr(p, k, v)
+    if name in ("c2", "c3"):
+        p.loss = 2
+    return wl, bs
+
+
+@pytest.mark.parametrize("name,extra", [("tiny", {}), ("tiny", dict(etrace_filter=2, d_out=1)),
+                                        ("c2", dict(d_out=2, d_ls=1)), ("c4twin", dict(loss=0))])
+def test_fp64_eprop_plus_components(name, extra):
+    """e-prop+ components (Results, "Event-driven e-prop with additional
+    biological features"): full reset to v_reset, decoupled or removed
+    eligibility filter, moving-average rate regulariser, temporal MSE, with
+    delays: FP64 exact against the oracle (spikes identical, loss, gradients
+    and weights within 1e-10)."""
+    wl, bs = _plus(name, **extra)
+    gh = gpu_train(wl, "fp64", 2, bs)
+    oh = oracle_train(wl, 2, bs)
+    assert_fp64_parity(gh, oh, f"e-prop+ {name} {extra}")
+
+
+def test_time_driven_baseline_with_reset_filter_and_temporal_mse():
+    """The time-driven baseline with the full reset, the decoupled filter and
+    the temporal MSE (static regulariser): FP64 within 1e-10 of the oracle's
+    time-driven mode; with the moving-average regulariser it reports
+    EPROP_ERR_UNSUPPORTED."""
+    wl, bs = _plus("tiny", reg_mode=0, c_reg=5.0)
+    td = _train_mode(wl, "fp64", 2, bs, True)
+    oh = oracle_train(wl, 2, bs, grad_mode=1)
+    for i in range(2):
+        for k in KEYS:
+            ok, e, ent = rel_close(td[i][1][k], oh["grads"][i][k], 1e-10)
+            assert ok, (i, k, e, ent)
+    wl, bs = _plus("tiny")
+    net = E.Network(wl.network, "fp64", max_trials=bs, max_steps=200)
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(wl.make_batch(0, 0, bs), train=True, time_driven=True)
+    assert ei.value.status == E.EPROP_ERR_UNSUPPORTED
+    net.close()
+
+
+@pytest.mark.parametrize("name", ["c3", "c4twin"])
+def test_fp32_teacher_forced_eprop_plus_components(name):
+    """FP32 with the oracle's spike trains and every e-prop+ component on:
+    each iteration's update within 1e-4 of the FP64 oracle's."""
+    wl, bs = _plus(name, d_out=1)
+    gh = gpu_train(wl, "fp32", 2, bs, forced_rate=20.0)
+    oh = oracle_train(wl, 2, bs, forced_rate=20.0)
+    for i in range(2):
+        for k in KEYS:
+            ok, e, ent = rel_close(gh["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
+            log(f"{name} e-prop+ it {i} {k}: normwise {e:.2e} worst entry {ent:.2e}")
+            assert ok, (name, i, k, e, ent)
+        assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]

@@ -633,3 +633,161 @@ def test_decoupled_filter_with_tau_out_is_the_coupled_filter():
     assert np.array_equal(grads[0]["w_rec"], grads[1]["w_rec"])
     assert not rel_close(grads[0]["w_rec"], grads[2]["w_rec"], 1e-3)[0]
     assert np.array_equal(grads[0]["w_out"], grads[2]["w_out"])   # the output gradient keeps F_kappa
+
+
+# ---------------------------------------------------------------- e-prop+ update schedule
+
+def _concat(batch):
+    """The batch's trials joined into one trial (inputs shifted, targets and
+    windows concatenated): what a continuous run of them looks like."""
+    n = batch.n_trials
+    Ts = [int(t) for t in batch.n_steps]
+    off = np.r_[0, np.cumsum(Ts)]
+    st, sr, fs, fn = [], [], [], []
+    for b in range(n):
+        lo, hi = int(batch.in_ptr[b]), int(batch.in_ptr[b + 1])
+        st.append(batch.in_step[lo:hi].astype(np.int64) + off[b])
+        sr.append(batch.in_src[lo:hi])
+        if batch.forced_ptr is not None:
+            flo, fhi = int(batch.forced_ptr[b]), int(batch.forced_ptr[b + 1])
+            fs.append(batch.forced_step[flo:fhi].astype(np.int64) + off[b])
+            fn.append(batch.forced_neuron[flo:fhi])
+    T = int(off[-1])
+    c = W.Batch(n_steps=np.array([T], np.uint32), in_ptr=np.array([0, sum(map(len, st))], np.uint64),
+                in_step=np.concatenate(st).astype(np.uint32), in_src=np.concatenate(sr).astype(np.uint32))
+    c.target = np.concatenate([batch.target[b, :Ts[b]] for b in range(n)])[None]
+    c.window = np.concatenate([batch.window[b, :Ts[b]] for b in range(n)])[None]
+    c.label = batch.label[:1].copy()
+    if fs:
+        c.forced_ptr = np.array([0, sum(map(len, fs))], np.uint64)
+        c.forced_step = np.concatenate(fs).astype(np.uint32)
+        c.forced_neuron = np.concatenate(fn).astype(np.uint32)
+    return c
+
+
+@pytest.mark.parametrize("extra", [dict(), dict(d_out=1, d_ls=2), dict(EPROP_PLUS, d_out=2),
+                                   dict(EPROP_PLUS, etrace_filter=2)])
+def test_online_schedule_without_learning_is_the_continuous_gradient(extra):
+    """e-prop+ schedule (Results, "Weight updates with every spike",
+    "Continuous dynamics"): with eta = 0 the weights stay put, so a run of
+    three samples back to back is one long trial; the gradients the
+    per-spike updates apply (with the end flush) add up to the event-driven
+    gradient of that long trial, and the spikes and the summed loss are
+    those of the long trial."""
+    wl = W.tiny(loss=0)
+    prm = dict(extra)
+    prm.pop("loss", None)
+    net = _with(wl.network, **prm) if prm else wl.network
+    b = wl.make_batch(0, 0, 3)
+    on = O.OracleNet(net)
+    r = O.run_online(on, b, 0.0, flush=True)
+    on2 = O.OracleNet(net)
+    g = O.zero_grads(on2)
+    cb = _concat(b)
+    rt = O.run_trial(on2, cb, 0, 2, g, trace=True)
+    assert np.array_equal(r["z"], rt.trace["z"])
+    assert r["loss"].sum() == pytest.approx(rt.loss, rel=1e-12)
+    for k in ("w_in", "w_rec", "w_out"):
+        ok, e, ent = rel_close(r["grads"][k], g[k], 1e-12)
+        assert ok, (k, e, ent)
+    assert np.abs(g["w_rec"]).max() > 0
+
+
+def test_online_cutoff_of_one_step_keeps_only_the_arrival_steps():
+    """eprop_isi_trace_cutoff at its extreme, one step: every trace is
+    dropped right after the step it starts, so each arrival at step a
+    contributes only e^a = psi_j^a (its own eligibility) times L_j^{a+d}; the
+    sum over arrivals, computed from the long trial's recorded psi and L,
+    equals what the per-spike updates apply."""
+    wl = W.tiny(loss=0)
+    net = _with(wl.network, d_out=1)
+    b = wl.make_batch(0, 0, 2)
+    # isolated arrivals only: drop an input spike whose channel also spiked
+    # the step before (recurrent sources are refractory for 2 steps anyway)
+    for i in range(b.n_trials):
+        lo, hi = int(b.in_ptr[i]), int(b.in_ptr[i + 1])
+        prev = {(int(s), int(c)) for s, c in zip(b.in_step[lo:hi], b.in_src[lo:hi])}
+        keep = np.array([(int(s) - 1, int(c)) not in prev for s, c in zip(b.in_step[lo:hi], b.in_src[lo:hi])])
+        b.in_step = np.concatenate([b.in_step[:lo], b.in_step[lo:hi][keep], b.in_step[hi:]])
+        b.in_src = np.concatenate([b.in_src[:lo], b.in_src[lo:hi][keep], b.in_src[hi:]])
+        b.in_ptr[i + 1:] -= np.uint64((~keep).sum())
+    on = O.OracleNet(net)
+    r = O.run_online(on, b, 0.0, cutoff=1, flush=True)
+    on2 = O.OracleNet(net)
+    rt = O.run_trial(on2, _concat(b), 0, 0, None, trace=True)
+    T = rt.trace["z"].shape[0]
+    psi = np.vstack([np.zeros(net.n_rec), rt.trace["psi"]])      # row t = step t
+    L = np.vstack([np.zeros(net.n_rec), rt.trace["learn"], np.zeros((2, net.n_rec))])
+    z = np.vstack([np.zeros(net.n_rec), rt.trace["z"]])
+    cb = _concat(b)
+    zin = np.zeros((T, net.n_in))
+    zin[cb.in_step, cb.in_src] = 1
+    for name, pr, spk in (("w_in", net.in_rec, lambda s, i: zin[s, i] if 0 <= s < T else 0),
+                          ("w_rec", net.rec_rec, lambda s, i: z[s, i] if 1 <= s <= T else 0)):
+        expect = np.zeros(pr.nnz)
+        for i in range(pr.n_src):
+            for q in range(int(pr.row_ptr[i]), int(pr.row_ptr[i + 1])):
+                j, D = int(pr.col[q]), int(pr.delay[q])
+                for a in range(1, T - 1 + 1):          # flush covers s <= T - d - d_ls = T - 1
+                    if spk(a - D, i):
+                        expect[q] += L[a + 1, j] * psi[a, j]
+        ok, e, ent = rel_close(r["grads"][name], expect, 1e-12)
+        assert ok, (name, e, ent)
+
+
+def _single_synapse_online(w0, in_steps, T, eta, target, kappa, alpha, v_th, B, w_out, gamma, sg_beta):
+    """Direct simulation of the e-prop+ schedule for one input synapse onto one
+    LIF neuron read out by one leaky readout (delay d = 1 to the readout,
+    d^ls = 0, subtractive reset, no refractoriness, piecewise-linear
+    surrogate), written out step by step: at an arrival at step a the weight
+    first takes -eta * sum over the not yet used steps s <= a - 2 of
+    L^{s+1} ebar^s, then the arrival adds the new weight to the membrane; the
+    readout weight likewise takes -eta * sum over r <= a - 2 of
+    E^{r+1} zbar^r when the neuron's spike reaches the readout at step a."""
+    w = w0
+    v, y, zprev = 0.0, 0.0, 0
+    z, psi, L, E = [0] * (T + 2), [0.0] * (T + 2), [0.0] * (T + 2), [0.0] * (T + 2)
+    ev = eb = zb = 0.0
+    done = done_out = 0
+    for t in range(1, T + 1):
+        cur = 0.0
+        if (t - 1) in in_steps:                 # emitted at t-1, delay 1
+            for s in range(done + 1, t - 1):    # s <= t - 2
+                x = 1.0 if (s - 1) in in_steps else 0.0
+                ev = alpha * ev + x
+                eb = kappa * eb + psi[s] * ev
+                w -= eta * L[s + 1] * eb
+            done = max(done, t - 2)
+            cur = w
+        v = alpha * v + cur - zprev * v_th
+        zt = 1 if v >= v_th else 0
+        psi[t] = gamma * max(0.0, 1.0 - sg_beta * abs(v - v_th))
+        z[t] = zt
+        if t >= 2 and z[t - 1]:                 # the spike of t-1 reaches the readout
+            for r in range(done_out + 1, t - 1):
+                zb = kappa * zb + z[r]
+                w_out -= eta * E[r + 1] * zb
+            done_out = max(done_out, t - 2)
+        y = kappa * y + (w_out * z[t - 1] if t >= 2 else 0.0)
+        E[t] = y - target[t - 1]
+        L[t] = B * E[t]
+        zprev = zt
+    return w, w_out
+
+
+def test_online_single_synapse_matches_direct_simulation():
+    """The per-spike schedule with learning (eta > 0) on the smallest network,
+    against a direct step-by-step simulation of its definition."""
+    T, eta = 120, 0.05
+    in_steps = {2, 9, 10, 30, 31, 32, 60, 75, 76, 100}
+    target = np.sin(np.arange(1, T + 1) / 9.0)
+    net = small_net(1, 1, 1, [(0, 0, 0.9, 1)], [], w_out=[[0.7]], fb=[[1.3]], v_th=0.6, t_ref=0.0, d_out=1)
+    b = batch_from(T, [(s, 0) for s in sorted(in_steps)], 1, target=target)
+    on = O.OracleNet(net)
+    O.run_online(on, b, eta)
+    p = net.params
+    w, wo = _single_synapse_online(0.9, in_steps, T, eta, target, math.exp(-1 / p.tau_out), math.exp(-1 / p.tau_m),
+                                   p.v_th, 1.3, 0.7, p.sg_gamma, p.sg_beta)
+    assert on.w_in[0] == pytest.approx(w, rel=1e-13, abs=1e-15)
+    assert on.w_out[0, 0] == pytest.approx(wo, rel=1e-13, abs=1e-15)
+    assert abs(w - 0.9) > 1e-3 and abs(wo - 0.7) > 1e-3
