@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define EPROP_ABI_VERSION 3u
+#define EPROP_ABI_VERSION 4u
 
 typedef struct eprop_network eprop_network;   /* opaque, owned by the library */
 
@@ -178,6 +178,10 @@ typedef struct {
   double tau_e;                  /* ms, > 0 with EPROP_ETRACE_DECOUPLED */
   int32_t reg_mode;              /* eprop_reg_mode */
   double reg_tau;                /* ms, > 0 with EPROP_REG_MOVING_AVERAGE */
+  uint32_t isi_cutoff;           /* EPROP_BATCH_ONLINE: eprop_isi_trace_cutoff in steps (Supplementary,
+                                    "History Management"): an eligibility step s counts only if
+                                    s - (the synapse's last arrival at or before s) < isi_cutoff;
+                                    beyond it the traces are taken as decayed.  0 = no cutoff */
   eprop_dev_alloc_fn dev_alloc;  /* NULL or the allocator above */
   eprop_dev_free_fn dev_free;    /* required with dev_alloc */
   void *alloc_ctx;
@@ -237,6 +241,22 @@ typedef enum { EPROP_MEM_HOST = 0, EPROP_MEM_DEVICE = 1 } eprop_memory;
                                               every step) instead of the event-driven path; the same
                                               result, kept as the baseline the event-driven path is
                                               measured against */
+#define EPROP_BATCH_ONLINE (1u << 5)  /* the e-prop+ update schedule (Results, "Weight updates with every
+                                         spike", "Continuous dynamics"): the batch's trials are samples
+                                         run back to back by one network instance from rest, its state
+                                         carried from sample to sample; every presynaptic spike first
+                                         updates its synapse's weight by gradient descent (w -= eta g)
+                                         over the eligibility steps s not yet used whose learning signal
+                                         L^{s+d} has reached the neuron (s <= a - 1 - d^ls - d for an
+                                         arrival at step a), then is delivered with the new weight; a
+                                         readout synapse does the same when its presynaptic spike reaches
+                                         the readout (E^{r+d} zbar^r, r <= a - 1 - d).  Gradients the
+                                         run ends before using are dropped.  Weights change during the
+                                         call; nothing is accumulated for eprop_apply_updates.  Host-
+                                         memory batches, gradient descent, no static rate regulariser;
+                                         the samples' total length must not exceed max_steps.  The loss
+                                         and prediction are reported per sample; the recordings
+                                         (eprop_read_state, trial 0) cover the whole run */
 
 /* A batch of independent trials (samples) of uneven lengths, simulated
  * together from zero state with the current weights (Results, "Evidence

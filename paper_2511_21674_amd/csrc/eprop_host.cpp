@@ -79,6 +79,12 @@ struct eprop_network {
   std::vector<uint32_t> sm2caller;  // internal source-major index -> caller's synapse index
   size_t tile_smem = 0;             // dynamic LDS of the tiled forward kernel
   bool blocked = false;             // weight update as a blocked transposition (k_apply_blk)
+  // e-prop+ schedule (allocated on the first online batch)
+  void *on_syn = nullptr;
+  double *on_Eh = nullptr, *on_y = nullptr, *on_zbo = nullptr, *on_loss = nullptr, *on_psum = nullptr;
+  uint32_t *on_rdone = nullptr, *on_zlast = nullptr, *on_off = nullptr, *on_label = nullptr;
+  void *on_fh = nullptr;
+  size_t cap_on_loss = 0, cap_on_psum = 0, cap_on_off = 0, cap_on_label = 0;
   uint32_t n_ach = 0;               // its blocks
   void *partial = nullptr;          // per trial-chunk synapse sums (large batches)
   void *Lbuf = nullptr;             // learning signal of the time-driven baseline (allocated on first use)
@@ -949,8 +955,19 @@ void release(eprop_network *n, void *p) {
   dfree(n, p);
 }
 
+// The samples of an online batch joined into one run (host arrays).
+struct OnlineCtx {
+  uint32_t n_samples = 0;
+  std::vector<uint32_t> off, label;   // off[c]: steps before sample c
+};
+
 template <typename real>
-eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res) {
+eprop_status run_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res,
+                        const OnlineCtx &oc, bool forced, bool prof, hipError_t &e);
+
+template <typename real>
+eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res,
+                      const OnlineCtx *oc = nullptr) {
   std::string msg;
   std::vector<uint64_t> in_ptr, f_ptr;
   uint32_t t_max = 0;
@@ -1105,7 +1122,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     }
     return best;
   };
-  const bool tune = n->autotune_pending && train && !time_driven;
+  const bool tune = !oc && n->autotune_pending && train && !time_driven;
 
   (void)hipEventRecord(n->ev[0], s);
   // upload
@@ -1136,6 +1153,11 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
                                                  : "spike out of range");
       return EPROP_ERR_INVALID_ARGUMENT;
     }
+  }
+  if (oc) {
+    const eprop_status ost = run_online(n, d, b, res, *oc, forced, prof, e);
+    if (e != hipSuccess) goto device_error;
+    return ost;
   }
   if (tune && !n->gather) {
     // Autotuner, part 1: the delivery variant of the forward kernel, then the
@@ -1300,6 +1322,234 @@ device_error:
   n->failed = true;
   set_fail(n, std::string("device error: ") + hip_msg(e));
   return EPROP_ERR_DEVICE;
+}
+
+// The e-prop+ schedule over one staged run (trial slot 0 holds the joined
+// samples): neuron state, readout and synaptic traces start from rest, the
+// weights move to target-major order for the run and back afterwards.
+template <typename real>
+eprop_status run_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res,
+                        const OnlineCtx &oc, bool forced, bool prof, hipError_t &e) {
+  hipStream_t s = n->stream;
+  const uint32_t T = b->n_steps[0], K = n->K, ns = oc.n_samples;
+  const size_t T1 = (size_t)n->Tcap + 1;
+  const bool ema = n->cfg.reg_mode == EPROP_REG_MOVING_AVERAGE && n->cfg.c_reg != 0.0;
+  bool ok = true;
+  if (!n->on_syn) {
+    uint8_t *p = nullptr;
+    ok = dalloc(n, &p, n->S * sizeof(eprop::OnlineSyn<real>));
+    n->on_syn = p;
+    ok = ok && dalloc(n, &n->on_Eh, T1 * K) && dalloc(n, &n->on_y, K) && dalloc(n, &n->on_zbo, n->Jp) &&
+         dalloc(n, &n->on_rdone, n->Jp) && dalloc(n, &n->on_zlast, n->Jp);
+  }
+  if (ok && ema && !n->on_fh) {
+    real *p = nullptr;
+    ok = dalloc(n, &p, T1 * n->Jp);
+    n->on_fh = p;
+  }
+  if (ok && !d.tm_w) ok = dalloc(n, &d.tm_w, n->S);
+  ok = ok && dgrow(n, &n->on_loss, &n->cap_on_loss, ns) && dgrow(n, &n->on_psum, &n->cap_on_psum, (size_t)ns * K) &&
+       dgrow(n, &n->on_off, &n->cap_on_off, ns + 1) && dgrow(n, &n->on_label, &n->cap_on_label, ns);
+  if (!ok) {
+    set_fail(n, "out of device memory for the online run");
+    return EPROP_ERR_OUT_OF_MEMORY;
+  }
+  auto MS = [&](void *dst, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemsetAsync(dst, 0, bytes, s);
+  };
+  MS(n->on_syn, n->S * sizeof(eprop::OnlineSyn<real>));
+  MS(n->on_Eh, T1 * K * 8);
+  MS(n->on_y, K * 8);
+  MS(n->on_zbo, n->Jp * 8);
+  MS(n->on_rdone, n->Jp * 4);
+  MS(n->on_zlast, n->Jp * 4);
+  if (ema) MS(n->on_fh, n->Jp * sizeof(real));  // f at step 0
+  MS(n->on_loss, ns * 8);
+  MS(n->on_psum, (size_t)ns * K * 8);
+  MS(d.psi, n->Jp * sizeof(real));              // psi and spikes at step 0 of trial slot 0
+  MS(d.rec_bits, n->Jw * 8);
+  if (e == hipSuccess) e = hipMemcpyAsync(n->on_off, oc.off.data(), (ns + 1) * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(n->on_label, oc.label.data(), ns * 4, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return EPROP_ERR_DEVICE;
+  eprop::OnlineRun<real> o{};
+  o.syn = static_cast<eprop::OnlineSyn<real> *>(n->on_syn);
+  o.Eh = n->on_Eh;
+  o.y = n->on_y;
+  o.zbo = n->on_zbo;
+  o.r_done = n->on_rdone;
+  o.zlast = n->on_zlast;
+  o.fh = static_cast<real *>(n->on_fh);
+  o.loss = n->on_loss;
+  o.psum = n->on_psum;
+  o.off = n->on_off;
+  o.label = n->on_label;
+  o.n_samples = ns;
+  o.cutoff = n->cfg.isi_cutoff;
+  o.lag = 1 + n->cfg.d_ls + n->cfg.d_out;
+  o.eta = n->cfg.eta;
+  Launch<real>::online_fill(d, false, s);
+  if (prof) (void)hipEventRecord(n->ev[1], s);
+  for (uint32_t t = 1; t <= T; ++t) Launch<real>::online_step(d, o, t, forced, s);
+  if (prof) (void)hipEventRecord(n->ev[2], s);
+  Launch<real>::online_fill(d, true, s);
+  if (n->blocked) Launch<real>::input_bound_blocked(d, n->n_ach, s);
+  else Launch<real>::input_bound(d, s);
+  (void)hipEventRecord(n->ev[7], s);
+  std::vector<double> loss(ns), psum((size_t)ns * K);
+  unsigned long long cnt[eprop::CNT_WORDS] = {}, ev[64] = {};
+  uint32_t flags = 0;
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(loss.data(), n->on_loss, ns * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(psum.data(), n->on_psum, psum.size() * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(cnt, d.cnt, sizeof(cnt), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ev, d.evcnt, sizeof(ev), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, d.ctl + eprop::CTL_ERR, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return EPROP_ERR_DEVICE;
+  n->last_ntr = 1;
+  n->last_T.assign(1, T);
+  if (flags) {
+    set_fail(n, "forced spike out of range");
+    return EPROP_ERR_INVALID_ARGUMENT;
+  }
+  bool finite_all = true;
+  for (uint32_t c = 0; c < ns; ++c) finite_all = finite_all && std::isfinite(loss[c]);
+  if (res) {
+    if (res->loss) std::memcpy(res->loss, loss.data(), ns * 8);
+    if (res->predicted)
+      for (uint32_t c = 0; c < ns; ++c) {
+        uint32_t best = 0;
+        if (n->cfg.loss != EPROP_LOSS_MSE)
+          for (uint32_t k = 1; k < K; ++k)
+            if (psum[(size_t)c * K + k] > psum[(size_t)c * K + best]) best = k;
+        res->predicted[c] = best;
+      }
+    res->n_rec_spikes = cnt[eprop::CNT_REC_SPIKES];
+    res->n_in_spikes = b->n_in_spikes;
+    unsigned long long events = 0;
+    for (int i = 0; i < 64; ++i) events += ev[i];
+    res->n_syn_events = events;
+    res->n_out_events = cnt[eprop::CNT_REC_SPIKES] * K;
+    res->n_eprop_updates = events;  // one update per arriving spike
+    res->n_flush_updates = 0;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, n->ev[0], n->ev[7]);
+    res->device_seconds = ms * 1e-3;
+    for (int p = 0; p < EPROP_N_PHASES; ++p) res->phase_ms[p] = 0;
+    if (prof) {
+      float m = 0;
+      (void)hipEventElapsedTime(&m, n->ev[0], n->ev[1]);
+      res->phase_ms[0] = m;
+      (void)hipEventElapsedTime(&m, n->ev[1], n->ev[2]);
+      res->phase_ms[1] = m;  // the whole run is the forward phase
+    }
+  }
+  if (!finite_all) {
+    n->failed = true;
+    set_fail(n, "non-finite loss");
+    return EPROP_ERR_NUMERIC;
+  }
+  n->err.clear();
+  return EPROP_OK;
+}
+
+// EPROP_BATCH_ONLINE: validates the samples and joins them into one run.
+template <typename real>
+eprop_status simulate_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res) {
+  auto fail = [&](eprop_status st, const char *m) {
+    set_fail(n, m);
+    return st;
+  };
+  if (b->flags & ~(uint32_t)(EPROP_BATCH_ONLINE | EPROP_BATCH_TRAIN | EPROP_BATCH_PROFILE | EPROP_RECORD_SPIKES |
+                             EPROP_RECORD_TRACES))
+    return fail(EPROP_ERR_INVALID_ARGUMENT, "EPROP_BATCH_ONLINE combines only with TRAIN, PROFILE and RECORD_*");
+  if (b->memory != EPROP_MEM_HOST) return fail(EPROP_ERR_UNSUPPORTED, "the online schedule takes host-memory batches");
+  if (n->cfg.optimizer != EPROP_OPT_GD) return fail(EPROP_ERR_UNSUPPORTED, "the online schedule uses gradient descent");
+  if (n->cfg.c_reg != 0.0 && n->cfg.reg_mode == EPROP_REG_STATIC)
+    return fail(EPROP_ERR_UNSUPPORTED, "the static rate regulariser needs whole samples; use the moving average");
+  if (b->n_trials < 1 || !b->n_steps || !b->in_ptr) return fail(EPROP_ERR_INVALID_ARGUMENT, "empty online batch");
+  const uint32_t ns = b->n_trials;
+  OnlineCtx oc;
+  oc.n_samples = ns;
+  oc.off.assign(ns + 1, 0);
+  oc.label.assign(ns, 0);
+  uint64_t T = 0;
+  for (uint32_t c = 0; c < ns; ++c) {
+    if (b->n_steps[c] < 1) return fail(EPROP_ERR_INVALID_ARGUMENT, "trial with zero steps");
+    T += b->n_steps[c];
+    if (T > n->Tcap) return fail(EPROP_ERR_CAPACITY, "the online run is longer than max_steps");
+    oc.off[c + 1] = (uint32_t)T;
+  }
+  const bool cls = n->cfg.loss != EPROP_LOSS_MSE;
+  if (cls && !b->label) return fail(EPROP_ERR_INVALID_ARGUMENT, "classification losses need labels");
+  if (!cls && !b->target) return fail(EPROP_ERR_INVALID_ARGUMENT, "MSE needs a target");
+  if (b->step_stride < 1) return fail(EPROP_ERR_INVALID_ARGUMENT, "step_stride must be >= 1");
+  for (uint32_t c = 0; c < ns; ++c) {
+    if (b->n_steps[c] > b->step_stride) return fail(EPROP_ERR_INVALID_ARGUMENT, "step_stride smaller than a trial");
+    if (cls) {
+      if (b->label[c] >= n->K) return fail(EPROP_ERR_INVALID_ARGUMENT, "label out of range");
+      oc.label[c] = b->label[c];
+    }
+  }
+  // the joined run: inputs shifted by each sample's offset, targets and
+  // windows laid end to end, forced spikes shifted
+  std::vector<uint64_t> in_ptr(2, 0), f_ptr(2, 0);
+  std::vector<uint32_t> in_step, in_src, f_step, f_neu;
+  in_step.reserve(b->n_in_spikes);
+  in_src.reserve(b->n_in_spikes);
+  for (uint32_t c = 0; c < ns; ++c) {
+    const uint64_t lo = b->in_ptr[c], hi = b->in_ptr[c + 1];
+    if (hi < lo || hi > b->n_in_spikes) return fail(EPROP_ERR_INVALID_ARGUMENT, "in_ptr out of order");
+    for (uint64_t q = lo; q < hi; ++q) {
+      if (b->in_step[q] >= b->n_steps[c]) return fail(EPROP_ERR_INVALID_ARGUMENT, "input spike out of its trial");
+      in_step.push_back(b->in_step[q] + oc.off[c]);
+      in_src.push_back(b->in_src[q]);
+    }
+    if (b->forced_ptr) {
+      for (uint64_t q = b->forced_ptr[c]; q < b->forced_ptr[c + 1]; ++q) {
+        if (b->forced_step[q] < 1 || b->forced_step[q] > b->n_steps[c])
+          return fail(EPROP_ERR_INVALID_ARGUMENT, "forced spike out of range");
+        f_step.push_back(b->forced_step[q] + oc.off[c]);
+        f_neu.push_back(b->forced_neuron[q]);
+      }
+    }
+  }
+  in_ptr[1] = in_step.size();
+  f_ptr[1] = f_step.size();
+  std::vector<double> target;
+  std::vector<uint8_t> window;
+  if (b->target && !cls) {
+    target.resize((size_t)T * n->K);
+    for (uint32_t c = 0; c < ns; ++c)
+      std::memcpy(&target[(size_t)oc.off[c] * n->K], b->target + (size_t)c * b->step_stride * n->K,
+                  (size_t)b->n_steps[c] * n->K * 8);
+  }
+  if (b->window) {
+    window.resize(T);
+    for (uint32_t c = 0; c < ns; ++c)
+      std::memcpy(&window[oc.off[c]], b->window + (size_t)c * b->step_stride, b->n_steps[c]);
+  }
+  const uint32_t T32 = (uint32_t)T, lab0 = oc.label[0];
+  eprop_batch run{};
+  run.n_trials = 1;
+  run.memory = EPROP_MEM_HOST;
+  run.n_steps = &T32;
+  run.n_in_spikes = in_step.size();
+  run.in_ptr = in_ptr.data();
+  run.in_step = in_step.data();
+  run.in_src = in_src.data();
+  run.step_stride = T32;
+  run.target = target.empty() ? nullptr : target.data();
+  run.label = cls ? &lab0 : nullptr;
+  run.window = window.empty() ? nullptr : window.data();
+  if (b->forced_ptr) {
+    run.n_forced = f_step.size();
+    run.forced_ptr = f_ptr.data();
+    run.forced_step = f_step.data();
+    run.forced_neuron = f_neu.data();
+  }
+  run.flags = EPROP_BATCH_TRAIN | (b->flags & EPROP_BATCH_PROFILE);
+  return simulate(n, d, &run, res, &oc);
 }
 
 template <typename real>
@@ -1510,6 +1760,8 @@ extern "C" {
 eprop_status eprop_simulate_batch(eprop_network *net, const eprop_batch *batch, eprop_batch_result *res) {
   if (!net || !batch) return EPROP_ERR_INVALID_ARGUMENT;
   if (net->failed) return EPROP_ERR_STATE;
+  if (batch->flags & EPROP_BATCH_ONLINE)
+    return net->fp64 ? simulate_online(net, net->n64, batch, res) : simulate_online(net, net->n32, batch, res);
   return net->fp64 ? simulate(net, net->n64, batch, res) : simulate(net, net->n32, batch, res);
 }
 

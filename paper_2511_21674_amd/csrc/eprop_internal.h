@@ -156,6 +156,34 @@ struct DevNet {
   unsigned long long *evcnt;    // [64] event counters (spread to avoid one hot atomic)
 };
 
+// e-prop+ update schedule (weight update at every arriving spike, one
+// continuous run): per-synapse state in target-major order, and the run's
+// readout state and histories.
+template <typename real>
+struct OnlineSyn {
+  real ev, ea, eb, gh;          // eligibility vector, filtered trace, G_beta-filtered trace
+  uint32_t s_done;              // last eligibility step used
+  uint32_t last;                // last arrival at or before s_done (0: none)
+};
+
+template <typename real>
+struct OnlineRun {
+  OnlineSyn<real> *syn;         // [S]
+  double *Eh;                   // [T+1][K] error signals of the run
+  double *y;                    // [K] readout state
+  double *zbo;                  // [Jp] zbar of each neuron for its readout synapses
+  uint32_t *r_done, *zlast;     // [Jp] readout synapses: last step used, last spike
+  real *fh;                     // [T+1][Jp] moving-average rates (moving-average regulariser)
+  double *loss;                 // [n_samples]
+  double *psum;                 // [n_samples][K] window sums for the prediction
+  const uint32_t *off;          // [n_samples+1] first step - 1 of each sample
+  const uint32_t *label;        // [n_samples]
+  uint32_t n_samples;
+  uint32_t cutoff;              // eprop_isi_trace_cutoff in steps (0: none)
+  uint32_t lag;                 // 1 + d^ls + d: the learning signal of step s + d is at the neuron at s + lag
+  double eta;
+};
+
 // Launch shapes (chosen on the host; the autotuner may change them)
 struct Shapes {
   uint32_t block;               // threads per block for grid-stride kernels
@@ -200,6 +228,11 @@ struct Launch {
                           hipStream_t s);
   // recomputes *l1max from the current weights (after upload and every update)
   static void input_bound(const DevNet<real> &n, hipStream_t s);
+  // e-prop+ schedule: target-major weights from / to the source-major records,
+  // and one step t of the continuous run (neurons with their synapse updates,
+  // then readout synapses, readout, error and loss)
+  static void online_fill(const DevNet<real> &n, bool to_records, hipStream_t s);
+  static void online_step(const DevNet<real> &n, const OnlineRun<real> &o, uint32_t t, bool forced, hipStream_t s);
 };
 
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s);

@@ -1172,6 +1172,221 @@ __global__ __launch_bounds__(256) void k_td_output(DevNet<real> n) {
   }
 }
 
+// ------------------------------------------------- e-prop+ update schedule
+// One network instance runs its samples back to back (Results, "Continuous
+// dynamics").  Every presynaptic spike first updates its synapse's weight by
+// gradient descent over the eligibility steps whose learning signal has
+// reached the neuron (Results, "Weight updates with every spike"; Alg.
+// "event-driven weight update" evaluated at each spike), then is delivered
+// with the new weight.  A thread per target neuron walks its incoming
+// synapses in target-major order, so the input current sums in the canonical
+// order and each weight has a single writer; weights live in tm_w for the
+// run and are copied to the source-major records afterwards.
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_online_fill(DevNet<real> n, int to_records) {
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n.S; q += (uint64_t)gridDim.x * blockDim.x) {
+    if (to_records) n.sm[n.tm_perm[q]].w = n.tm_w[q];
+    else n.tm_w[q] = n.sm[n.tm_perm[q]].w;
+  }
+}
+
+// Did source src (input or recurrent) emit a spike at step s of the run?
+template <typename real>
+__device__ inline bool online_spiked(const DevNet<real> &n, uint32_t src, int64_t s) {
+  if (src < n.I) return s >= 0 && s < (int64_t)n.Tcap && ((n.in_bits[(size_t)s * n.Iw + (src >> 6)] >> (src & 63u)) & 1ull);
+  const uint32_t r = src - n.I;
+  return s >= 1 && ((n.rec_bits[(size_t)s * n.Jw + (r >> 6)] >> (r & 63u)) & 1ull);
+}
+
+template <typename real, bool FORCED>
+__global__ __launch_bounds__(256) void k_online_neuron(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n.Jp) return;  // whole wavefronts: Jp is a multiple of 64
+  const bool live = j < n.J;
+  const real beta = n.beta_j[j];
+  const bool ema = n.reg_mode == 1;
+  real I = 0;
+  unsigned long long nev = 0;
+  if (live) {
+    const uint32_t q1 = n.tm_ptr[j + 1];
+    for (uint32_t q = n.tm_ptr[j]; q < q1; ++q) {
+      const uint32_t pk = n.tm_syn[q];
+      const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
+      if (!online_spiked(n, src, (int64_t)t - D)) continue;
+      ++nev;
+      OnlineSyn<real> st = o.syn[q];
+      const int64_t s_new = (int64_t)t - o.lag;
+      double g = 0.0;
+      for (int64_t s = (int64_t)st.s_done + 1; s <= s_new; ++s) {
+        const bool x = online_spiked(n, src, s - D);
+        if (x) st.last = (uint32_t)s;
+        if (o.cutoff && (st.last == 0 || (uint64_t)(s - st.last) >= o.cutoff)) {
+          // beyond eprop_isi_trace_cutoff the traces count as decayed
+          st.ev = st.ea = st.eb = st.gh = (real)0;
+          continue;
+        }
+        const bool zr = n.reset_mode == 1 && ((n.rec_bits[(size_t)(s - 1) * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull);
+        const real pp = n.psi[(size_t)(s - 1) * n.Jp + j], pn = n.psi[(size_t)s * n.Jp + j];
+        // eq. eligibility-vector-substituted, eq. filtered-eligibility-trace
+        const real ea_new = pp * st.ev + (n.rho - pp * beta) * st.ea;
+        const real ev_new = (zr ? (real)0 : n.alpha) * st.ev + (x ? (real)1 : (real)0);
+        const real e = pn * (ev_new - beta * ea_new);
+        st.eb = (real)n.kappa_e_d * st.eb + e;
+        st.ev = ev_new;
+        st.ea = ea_new;
+        st.gh = (real)n.beta_f * st.gh + ((real)1 - (real)n.beta_f) * e;
+        // the learning signal L_j^{s+d} = sum_k B_jk E_k^{s+d} (eq. final-gradient)
+        const double *E = o.Eh + (size_t)(s + n.d_out) * n.K;
+        double L = 0.0;
+        for (uint32_t k = 0; k < n.K; ++k) L = L + (double)n.fb[(size_t)j * n.K + k] * E[k];
+        g += L * (double)st.eb;
+        if (ema) g += n.c_reg * ((double)o.fh[(size_t)s * n.Jp + j] - n.f_target) * (double)st.gh;
+      }
+      if (s_new > (int64_t)st.s_done) st.s_done = (uint32_t)s_new;
+      o.syn[q] = st;
+      const real w = (real)((double)n.tm_w[q] - o.eta * g);
+      n.tm_w[q] = w;
+      I = I + w;
+    }
+  }
+  real v = n.v[j], a = n.a[j];
+  uint8_t stt = n.nst[j];
+  const bool z = neuron_step<real, FORCED>(n, 0, t, j, live, I, beta, v, a, stt);
+  n.v[j] = v;
+  n.a[j] = a;
+  n.nst[j] = stt;
+  const uint64_t word = publish_bits(n, 0, t, j, z);
+  if (ema)
+    o.fh[(size_t)t * n.Jp + j] =
+        (real)n.beta_f * o.fh[(size_t)(t - 1) * n.Jp + j] + ((real)1 - (real)n.beta_f) * (z ? (real)1 : (real)0);
+  for (int off = 32; off > 0; off >>= 1) nev += __shfl_down(nev, off);
+  if (lane_id() == 0) {
+    if (nev) atomicAdd(&n.evcnt[(blockIdx.x * 4 + (threadIdx.x >> 6)) & 63u], nev);
+    if (word) atomicAdd(&n.cnt[CNT_REC_SPIKES], (unsigned long long)__popcll(word));
+  }
+}
+
+// One block: the readout synapses of neurons whose spike of step t - d
+// reaches the readout now (gradient E_k^{r+d} zbar_j^r over the steps not
+// yet used, eq. eprop-output-new-subs-rewritten), then the readout
+// (eq. leaky_integrator_with_delay), error signal and loss of step t, FP64.
+template <typename real>
+__global__ __launch_bounds__(256) void k_online_readout(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
+  const uint32_t tid = threadIdx.x, K = n.K, d = n.d_out;
+  __shared__ double red[256];
+  __shared__ uint32_t smp;
+  if (t > d) {
+    const uint64_t *row = n.rec_bits + (size_t)(t - d) * n.Jw;
+    for (uint32_t w = tid; w < n.Jw; w += blockDim.x) {
+      uint64_t word = row[w];
+      while (word) {
+        const uint32_t j = w * 64 + (uint32_t)(__ffsll((unsigned long long)word) - 1);
+        word &= word - 1ull;
+        const int64_t r_new = (int64_t)t - 1 - d;
+        const uint32_t rd0 = o.r_done[j], zl0 = o.zlast[j];
+        const double zb0 = o.zbo[j];
+        uint32_t zl = zl0;
+        double zb = zb0;
+        for (uint32_t k = 0; k < K; ++k) {
+          zl = zl0;
+          zb = zb0;
+          double g = 0.0;
+          for (int64_t r = (int64_t)rd0 + 1; r <= r_new; ++r) {
+            const bool x = (n.rec_bits[(size_t)r * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull;
+            if (x) zl = (uint32_t)r;
+            if (o.cutoff && (zl == 0 || (uint64_t)(r - zl) >= o.cutoff)) {
+              zb = 0.0;
+              continue;
+            }
+            zb = n.kappa_d * zb + (x ? 1.0 : 0.0);
+            g += o.Eh[(size_t)(r + d) * K + k] * zb;
+          }
+          n.w_out[(size_t)k * n.Jp + j] = (real)((double)n.w_out[(size_t)k * n.Jp + j] - o.eta * g);
+        }
+        o.zbo[j] = zb;
+        o.zlast[j] = zl;
+        if (r_new > (int64_t)rd0) o.r_done[j] = (uint32_t)r_new;
+      }
+    }
+  }
+  if (tid == 0) {
+    uint32_t lo = 0, hi = o.n_samples;  // sample c with off[c] < t <= off[c + 1]
+    while (hi - lo > 1) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (o.off[m] < t) lo = m; else hi = m;
+    }
+    smp = lo;
+  }
+  __syncthreads();
+  const uint32_t c = smp;
+  for (uint32_t k = tid; k < K; k += blockDim.x) {
+    double sum = 0.0;
+    if (t > d) {
+      const uint64_t *row = n.rec_bits + (size_t)(t - d) * n.Jw;
+      for (uint32_t w = 0; w < n.Jw; ++w) {
+        uint64_t word = row[w];
+        while (word) {
+          const uint32_t j = w * 64 + (uint32_t)(__ffsll((unsigned long long)word) - 1);
+          word &= word - 1ull;
+          sum = sum + (double)n.w_out[(size_t)k * n.Jp + j];
+        }
+      }
+    }
+    o.y[k] = n.kappa_d * o.y[k] + sum;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const bool win = n.window ? n.window[t - 1] != 0 : true;
+    const uint32_t label = n.loss != 0 ? o.label[c] : 0u;
+    double *E = o.Eh + (size_t)t * K;
+    double lp = 0.0;
+    if (n.loss == 0) {
+      for (uint32_t k = 0; k < K; ++k) {
+        const double dd = o.y[k] - n.target[(size_t)(t - 1) * K + k];
+        E[k] = win ? dd : 0.0;
+        if (win) lp += 0.5 * dd * dd;
+      }
+    } else if (n.loss == 2) {
+      for (uint32_t k = 0; k < K; ++k) {
+        const double dd = o.y[k] - (k == label ? 1.0 : 0.0);
+        E[k] = win ? 2.0 / K * dd : 0.0;
+        if (win) {
+          lp += dd * dd / K;
+          o.psum[(size_t)c * K + k] += o.y[k];
+        }
+      }
+    } else {
+      double mx = o.y[0];
+      for (uint32_t k = 1; k < K; ++k) mx = fmax(mx, o.y[k]);
+      double se = 0.0;
+      for (uint32_t k = 0; k < K; ++k) se += exp(o.y[k] - mx);
+      for (uint32_t k = 0; k < K; ++k) {
+        const double pi = exp(o.y[k] - mx) / se;
+        E[k] = win ? pi - (k == label ? 1.0 : 0.0) : 0.0;
+        if (win) o.psum[(size_t)c * K + k] += pi;
+      }
+      if (win) lp += -(o.y[label] - mx - log(se));
+    }
+    o.loss[c] += lp;
+  }
+  if (n.reg_mode == 1) {
+    // moving-average regulariser's loss of step t (eq. ema-rate)
+    double acc = 0.0;
+    for (uint32_t j = tid; j < n.J; j += blockDim.x) {
+      const double df = (double)o.fh[(size_t)t * n.Jp + j] - n.f_target;
+      acc += df * df;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (uint32_t sz = 128; sz > 0; sz >>= 1) {
+      if (tid < sz) red[tid] += red[tid + sz];
+      __syncthreads();
+    }
+    if (tid == 0) o.loss[c] += 0.5 * n.c_reg * red[0];
+  }
+}
+
 // Fixed-order reduction of the trial-chunk partial sums into (gs, gc).
 template <typename real>
 __global__ __launch_bounds__(256) void k_synapse_reduce(DevNet<real> n, uint32_t nchunk, const real *partial) {
@@ -1623,6 +1838,20 @@ void Launch<real>::apply_blocked(const DevNet<real> &n, uint32_t n_ach, uint64_t
     (void)hipMemsetAsync(n.gc, 0, S * sizeof(real), s);
   }
   k_apply_out<real><<<grid_for((uint64_t)n.K * n.Jp, 256, 2048), 256, 0, s>>>(n, n_trials, opt, eta, eta_t, b1, b2, eps);
+}
+
+template <typename real>
+void Launch<real>::online_fill(const DevNet<real> &n, bool to_records, hipStream_t s) {
+  k_online_fill<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, to_records ? 1 : 0);
+}
+
+template <typename real>
+void Launch<real>::online_step(const DevNet<real> &n, const OnlineRun<real> &o, uint32_t t, bool forced,
+                               hipStream_t s) {
+  const uint32_t blocks = n.Jp / 256 + (n.Jp % 256 ? 1 : 0);
+  if (forced) k_online_neuron<real, true><<<blocks, 256, 0, s>>>(n, o, t);
+  else k_online_neuron<real, false><<<blocks, 256, 0, s>>>(n, o, t);
+  k_online_readout<real><<<1, 256, 0, s>>>(n, o, t);
 }
 
 template <typename real>

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeprop_hip.so")
 
-EPROP_ABI_VERSION = 3
+EPROP_ABI_VERSION = 4
 EPROP_OK, EPROP_ERR_INVALID_ARGUMENT, EPROP_ERR_OUT_OF_MEMORY = 0, -1, -2
 EPROP_ERR_DEVICE, EPROP_ERR_STATE, EPROP_ERR_CAPACITY = -3, -4, -5
 EPROP_ERR_NUMERIC, EPROP_ERR_UNSUPPORTED = -6, -7
@@ -27,6 +27,7 @@ EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS, EPROP_AUTOTUNE =
 EPROP_MEM_HOST, EPROP_MEM_DEVICE = 0, 1
 EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE, EPROP_RECORD_SPIKES, EPROP_RECORD_TRACES = 1, 2, 4, 8
 EPROP_BATCH_TIME_DRIVEN = 16
+EPROP_BATCH_ONLINE = 32
 EPROP_LOSS_MSE, EPROP_LOSS_SOFTMAX_CE, EPROP_LOSS_TEMPORAL_MSE = 0, 1, 2
 EPROP_RESET_SUBTRACT, EPROP_RESET_TO_VALUE = 0, 1
 EPROP_ETRACE_COUPLED, EPROP_ETRACE_DECOUPLED, EPROP_ETRACE_NONE = 0, 1, 2
@@ -61,6 +62,7 @@ class eprop_config(C.Structure):
                 ("history_steps", C.c_uint32), ("c_reg", C.c_double), ("f_target", C.c_double),
                 ("reset_mode", C.c_int32), ("v_reset", C.c_double), ("etrace_filter", C.c_int32),
                 ("tau_e", C.c_double), ("reg_mode", C.c_int32), ("reg_tau", C.c_double),
+                ("isi_cutoff", C.c_uint32),
                 ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
                 ("alloc_ctx", _P)]
 
@@ -238,6 +240,7 @@ class Network:
                            reset_mode=int(getattr(p, "reset_mode", 0)), v_reset=float(getattr(p, "v_reset", 0.0)),
                            etrace_filter=int(getattr(p, "etrace_filter", 0)), tau_e=float(getattr(p, "tau_e", 0.0)),
                            reg_mode=int(getattr(p, "reg_mode", 0)), reg_tau=float(getattr(p, "reg_tau", 0.0)),
+                           isi_cutoff=int(getattr(p, "isi_cutoff", 0)),
                            delivery={"auto": 0, "scatter": 1, "gather": 2}[delivery],
                            flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0)
                            | (EPROP_AUTOTUNE if autotune else 0))
@@ -279,10 +282,12 @@ class Network:
             raise EpropError(st, eprop_last_error(self.h))
 
     def simulate(self, batch, train: bool = True, device: bool = False, profile: bool = False,
-                 time_driven: bool = False) -> BatchResult:
+                 time_driven: bool = False, online: bool = False) -> BatchResult:
         """Runs one batch (a ``workloads.Batch``).  device=True places the
         batch arrays in device memory (torch) before the call; time_driven
-        computes the gradient by the time-driven baseline recursion."""
+        computes the gradient by the time-driven baseline recursion; online
+        runs the trials back to back with the e-prop+ per-spike schedule
+        (EPROP_BATCH_ONLINE)."""
         ntr = batch.n_trials
         n_steps = _c(batch.n_steps, np.uint32)
         stride = int(n_steps.max())
@@ -312,7 +317,7 @@ class Network:
                         forced_ptr=ptrs.get("forced_ptr"), forced_step=ptrs.get("forced_step"),
                         forced_neuron=ptrs.get("forced_neuron"),
                         flags=(EPROP_BATCH_TRAIN if train else 0) | (EPROP_BATCH_PROFILE if profile else 0)
-                        | (EPROP_BATCH_TIME_DRIVEN if time_driven else 0))
+                        | (EPROP_BATCH_TIME_DRIVEN if time_driven else 0) | (EPROP_BATCH_ONLINE if online else 0))
         loss = np.zeros(ntr)
         pred = np.zeros(ntr, np.uint32)
         res = eprop_batch_result(loss=_ptr(loss), predicted=_ptr(pred))

@@ -74,6 +74,7 @@ class Params:
     v_reset: float = 0.0
     etrace_filter: int = 0      # eligibility filter: 0 tau_out, 1 its own tau_e, 2 none
     tau_e: float = 0.0
+    isi_cutoff: int = 0         # e-prop+ schedule: eligibility steps kept after an arrival (0: all)
 
 
 @dataclass

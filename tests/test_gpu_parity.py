@@ -751,3 +751,94 @@ def test_fp32_teacher_forced_eprop_plus_components(name):
             log(f"{name} e-prop+ it {i} {k}: normwise {e:.2e} worst entry {ent:.2e}")
             assert ok, (name, i, k, e, ent)
         assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
+
+
+# ----------------------------------------------------------------- e-prop+ update schedule
+
+def _online_pair(wl, precision, b, eta):
+    """The GPU's and the oracle's online run of the batch's trials back to back."""
+    T = int(b.n_steps.sum())
+    net = E.Network(wl.network, precision, max_trials=1, max_steps=T)
+    w0 = net.weights()
+    r = net.simulate(b, online=True)
+    g = {"loss": r.loss.copy(), "z": net.spikes(0, T), "w": net.weights(), "w0": w0, "events": r.n_syn_events}
+    net.close()
+    on = O.OracleNet(wl.network)
+    o = O.run_online(on, b, eta, cutoff=int(wl.network.params.isi_cutoff))
+    o["w"] = {k: getattr(on, k).copy() for k in KEYS}
+    return g, o
+
+
+@pytest.mark.parametrize("name,extra", [("tiny", {}), ("tiny", dict(d_out=1, d_ls=1)),
+                                        ("tiny", dict(EPROP_PLUS, isi_cutoff=15)),
+                                        ("tiny2", dict(EPROP_PLUS, d_out=2, etrace_filter=2)),
+                                        ("c2", dict(d_out=1, isi_cutoff=40)), ("c4twin", dict(d_out=1))])
+def test_online_schedule_fp64_matches_oracle(name, extra):
+    """e-prop+ update schedule (EPROP_BATCH_ONLINE): the batch's samples run
+    back to back by one network instance, every arriving spike first updating
+    its synapse by gradient descent.  FP64 against the oracle's online run:
+    spike trains identical, per-sample losses within 1e-12 and every weight
+    (input, recurrent, readout) within 1e-10 after the run."""
+    if name == "tiny":
+        wl, b = W.tiny(loss=0), None
+    elif name == "tiny2":
+        wl, b = W.tiny(loss=2), None
+    elif name == "c2":
+        wl, b = W.c2_evidence(batch_size=3), None
+    else:
+        wl, b = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), None
+    p = wl.network.params
+    p.optimizer = 0
+    p.eta = 2e-3 if name != "c4twin" else 1e-5
+    for k, v in extra.items():
+        setattr(p, k, v)
+    if name == "c2":
+        p.loss = 2
+    b = wl.make_batch(0, 0, 3 if name != "c4twin" else 2)
+    g, o = _online_pair(wl, "fp64", b, p.eta)
+    assert np.array_equal(g["z"], o["z"]), "spike trains differ"
+    ok, e, _ = rel_close(g["loss"], o["loss"], 1e-12)
+    assert ok, ("loss", e)
+    for k in KEYS:
+        ok, e, ent = rel_close(g["w"][k], o["w"][k], 1e-10)
+        assert ok, (k, e, ent)
+        assert not np.array_equal(g["w"][k], g["w0"][k]), (k, "weights did not move")
+    log(f"online {name} {extra}: {g['events']} updates, loss {np.round(g['loss'], 3)}")
+
+
+def test_online_schedule_fp32_ignore_and_fire():
+    """FP32 online run of the scaling network's twin (ignore-and-fire spike
+    trains fixed by construction, so FP32 sees the oracle's spikes): the
+    weight changes within 1e-4 of the FP64 oracle's."""
+    wl = _scaling_twin()
+    p = wl.network.params
+    p.eta, p.d_out, p.isi_cutoff = 1e-4, 1, 100
+    b = wl.make_batch(0, 0, 2)
+    g, o = _online_pair(wl, "fp32", b, p.eta)
+    assert np.array_equal(g["z"], o["z"])
+    w0 = {k: getattr(O.OracleNet(wl.network), k) for k in KEYS}
+    for k in KEYS:
+        ok, e, ent = rel_close(g["w"][k] - w0[k], o["w"][k] - w0[k], 1e-4, floor_frac=1e-2)
+        log(f"online fp32 {k}: change normwise {e:.2e} worst {ent:.2e}")
+        assert ok, (k, e, ent)
+
+
+def test_online_schedule_rejects_what_it_does_not_support():
+    wl = W.tiny(loss=0)   # Adam
+    b = wl.make_batch(0, 0, 2)
+    net = E.Network(wl.network, "fp32", max_trials=1, max_steps=400)
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(b, online=True)
+    assert ei.value.status == E.EPROP_ERR_UNSUPPORTED
+    net.close()
+    wl.network.params.optimizer = 0
+    net = E.Network(wl.network, "fp32", max_trials=1, max_steps=300)
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(b, online=True)    # 400 steps > max_steps
+    assert ei.value.status == E.EPROP_ERR_CAPACITY
+    with pytest.raises(E.EpropError) as ei:
+        net.simulate(wl.make_batch(0, 0, 1), online=True, device=True)
+    assert ei.value.status == E.EPROP_ERR_UNSUPPORTED
+    r = net.simulate(wl.make_batch(0, 0, 1), online=True)   # the handle still works
+    assert np.isfinite(r.loss).all()
+    net.close()
