@@ -401,12 +401,16 @@ int orc_run_trial(const orc_net *net, const orc_trial *tr, int grad_mode, double
     loss += 0.5 * net->c_reg * (f - net->f_target) * (f - net->f_target);
   }
   /* moving-average form (eq. sma-loss with the rate of eq. ema-rate):
-   * c/2 sum_t sum_j (f_j^t - f*)^2 */
-  for (int j = 0; j < J && net->reg_mode == 1; ++j)
+   * c/2 sum_j sum_t (f_j^t - f*)^2, each neuron's sum formed first (summing
+   * 10^5 small terms one by one into the total would lose about 1e-11) */
+  for (int j = 0; j < J && net->reg_mode == 1; ++j) {
+    double sj = 0.0;
     for (int t = 1; t <= T; ++t) {
       const double df = f_h[(long)t * J + j] - net->f_target;
-      loss += 0.5 * net->c_reg * df * df;
+      sj += df * df;
     }
+    loss += 0.5 * net->c_reg * sj;
+  }
 
   if (grad_mode == 1) {
     for (long q = 0; q < ns; ++q) *SYN_G(q) += creg[SYN_TGT(q)] * esum[q];
@@ -723,13 +727,14 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
     for (int k = 0; k < K; ++k) E_h[(long)t * K + k] = E[k];
   }
   for (int j = 0; j < J; ++j) {  /* rate regularisation of every neuron */
-    double nz = 0.0, f = 0.0;
+    double nz = 0.0, f = 0.0, sf = 0.0;
     for (int t = 1; t <= T; ++t) {
       const double z = sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
       nz += z;
       f = p.beta_f * f + (1.0 - p.beta_f) * z;
-      if (net->reg_mode == 1) loss += 0.5 * net->c_reg * (f - net->f_target) * (f - net->f_target);
+      sf += (f - net->f_target) * (f - net->f_target);
     }
+    if (net->reg_mode == 1) loss += 0.5 * net->c_reg * sf;
     if (net->reg_mode == 0) loss += 0.5 * net->c_reg * (nz / T - net->f_target) * (nz / T - net->f_target);
   }
   for (int n = 0; n < n_sample && rc == 0; ++n) {
@@ -932,15 +937,15 @@ int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, dou
     readout_core(net, &p, &sp, t, tr->target ? tr->target + (long)(lt - 1) * K : NULL,
                  tr->window ? tr->window[lt - 1] : 1, tr->label, y, E, &loss_out[k], psum);
     for (int kk = 0; kk < K; ++kk) E_h[(long)t * K + kk] = E[kk];
+    double sreg = 0.0;  /* this step's moving-average regulariser, summed before the total */
     for (int j = 0; j < J; ++j) {
       double Ls = 0.0;
       for (int kk = 0; kk < K; ++kk) Ls = Ls + net->fb[(long)j * K + kk] * E[kk];
       L_h[(long)t * J + j] = Ls;
-      if (net->reg_mode == 1 && net->c_reg != 0.0) {
-        const double df = f_h[(long)t * J + j] - net->f_target;
-        loss_out[k] += 0.5 * net->c_reg * df * df;
-      }
+      const double df = f_h[(long)t * J + j] - net->f_target;
+      sreg += df * df;
     }
+    if (net->reg_mode == 1 && net->c_reg != 0.0) loss_out[k] += 0.5 * net->c_reg * sreg;
   }
   if (flush) {
     /* as if a spike arrived at every synapse after the last step */

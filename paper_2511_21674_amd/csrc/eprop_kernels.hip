@@ -656,31 +656,28 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
     }
     lp += 0.5 * n.c_reg * rl;
   } else if (n.c_reg != 0.0) {
-    // moving-average rate (eq. ema-rate): between spikes f decays by beta,
-    // so each inter-spike stretch of the loss c/2 sum_t (f^t - f*)^2 is a
-    // pair of geometric series
+    // moving-average rate (eq. ema-rate) of each neuron, step by step from
+    // its spike times; loss c/2 sum_t (f^t - f*)^2, each neuron's sum first
     const double be = n.beta_f, fs = n.f_target;
-    const double g1 = be / (1.0 - be), g2 = be * be / (1.0 - be * be);
     double rl = 0.0;
     for (uint32_t j = tid; j < n.J; j += blockDim.x) {
       const uint32_t c = n.spk_cnt[(size_t)b * n.NS + n.I + j];
       const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
-      double f = 0.0;
-      uint32_t prev = 0;  // step of f's last value
-      for (uint32_t i = 0; i <= c; ++i) {
-        const uint32_t u = i < c ? (uint32_t)st[i] : T + 1;
-        const double m = (double)(u - prev - 1);  // steps strictly between, f decaying from f
-        // sum_{k=1}^{m} (f be^k - fs)^2
-        const double bm = pow(be, m);
-        rl += f * f * g2 * (1.0 - bm * bm) - 2.0 * f * fs * g1 * (1.0 - bm) + m * fs * fs;
-        if (i < c) {
-          f = be * f * bm + (1.0 - be);
-          rl += (f - fs) * (f - fs);
-          prev = u;
+      double f = 0.0, sj = 0.0;
+      uint32_t i = 0;
+      for (uint32_t t = 1; t <= T; ++t) {
+        double z = 0.0;
+        if (i < c && st[i] == t) {
+          z = 1.0;
+          ++i;
         }
+        f = be * f + (1.0 - be) * z;
+        const double df = f - fs;
+        sj += df * df;
       }
+      rl += 0.5 * n.c_reg * sj;
     }
-    lp += 0.5 * n.c_reg * rl;
+    lp += rl;
   }
   __shared__ double red[256];
   __shared__ double psum[64];
