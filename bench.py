@@ -216,6 +216,53 @@ def cpu_baseline(wl, n_steps_sample, budget_s=20.0):
     return out
 
 
+def bench_online(args, wl, progress):
+    """The e-prop+ schedule: warm-up on one sample, then `steps` samples of the
+    workload run back to back as one continuous run with per-spike updates.
+    The batch is host memory (the schedule joins the samples on the host), so
+    the timed call includes copying its input and forced spikes."""
+    import torch
+    from paper_2511_21674_amd import eprop as E
+    net_w = wl.network
+    net_w.params.optimizer = 0   # the per-spike schedule updates by gradient descent
+    if args.isi_cutoff is not None:
+        net_w.params.isi_cutoff = args.isi_cutoff
+    T = int(wl.make_batch(0, 0, 1).n_steps[0])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        net = E.Network(net_w, "fp32", max_trials=1, max_steps=max(args.steps, 1) * T,
+                        stream=E.C.c_void_p(stream.cuda_stream))
+        progress("network built")
+        warm = wl.make_batch(0, 0, 1)
+        run = wl.make_batch(1, 0, args.steps)
+        net.simulate(warm, online=True)
+        torch.cuda.synchronize()
+        progress("warm-up sample done")
+        t0 = time.perf_counter()
+        r = net.simulate(run, online=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        progress(f"online run done, {elapsed / args.steps * 1000.0:.1f} ms per sample")
+        net.close()
+    bio_s = args.steps * T * net_w.params.dt / 1000.0
+    out = {"metric": "synaptic events/s (e-prop+ per-spike schedule, FP32, one continuous run)",
+           "value": r.n_syn_events / elapsed, "unit": "synaptic events/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": elapsed / args.steps * 1000.0, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"{wl.name}: {wl.description}", "n_rec": net_w.n_rec, "n_in": net_w.n_in,
+                      "n_out": net_w.n_out, "synapses": int(net_w.in_rec.nnz + net_w.rec_rec.nnz),
+                      "samples_per_run": args.steps, "steps_per_sample": T, "isi_cutoff": int(net_w.params.isi_cutoff),
+                      "gradient": "e-prop+ per-spike schedule (walk over each inter-spike interval)"},
+           "eprop_updates_per_s": r.n_eprop_updates / elapsed, "recurrent_rate_hz":
+               r.n_rec_spikes / (args.steps * T * net_w.n_rec * net_w.params.dt / 1000.0),
+           "mean_loss": [float(x) for x in r.loss],
+           "real_time_factor": bio_s / elapsed, "biological_seconds": bio_s,
+           "roofline": None, "cpu_baseline": None,
+           "note": "per-spike updates walk each synapse's inter-spike interval (at most isi_cutoff steps); "
+                   "roofline and CPU baseline are reported for the batched path only"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +274,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--time-driven", action="store_true",
                     help="gradient by the time-driven baseline recursion instead of the event-driven path")
+    ap.add_argument("--online", action="store_true",
+                    help="the e-prop+ schedule: the steps' samples run back to back as one continuous run, every "
+                         "arriving spike updating its synapse (EPROP_BATCH_ONLINE); one warm-up sample first")
+    ap.add_argument("--isi-cutoff", type=int, default=None,
+                    help="with --online: eprop_isi_trace_cutoff in steps (default: the workload's, 0 = none)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (the tuner otherwise runs in the first warm-up batch)")
     ap.add_argument("--cpu-steps", type=int, default=None,
@@ -275,6 +327,8 @@ def main():
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     wl = W.WORKLOADS[args.workload]()
     net_w = wl.network
+    if args.online:
+        return bench_online(args, wl, progress)
     T = max(int(wl.make_batch(0, 0, 1).n_steps.max()), 1)
     if args.workload == "c2_evidence":
         T = 1800
