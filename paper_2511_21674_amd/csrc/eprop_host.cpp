@@ -83,7 +83,7 @@ struct eprop_network {
   void *on_syn = nullptr;
   double *on_Eh = nullptr, *on_y = nullptr, *on_zbo = nullptr, *on_loss = nullptr, *on_psum = nullptr;
   uint32_t *on_rdone = nullptr, *on_zlast = nullptr, *on_off = nullptr, *on_label = nullptr;
-  void *on_fh = nullptr;
+  void *on_fh = nullptr, *on_I = nullptr, *on_L = nullptr;
   size_t cap_on_loss = 0, cap_on_psum = 0, cap_on_off = 0, cap_on_label = 0;
   uint32_t n_ach = 0;               // its blocks
   void *partial = nullptr;          // per trial-chunk synapse sums (large batches)
@@ -1341,6 +1341,10 @@ eprop_status run_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b,
     n->on_syn = p;
     ok = ok && dalloc(n, &n->on_Eh, T1 * K) && dalloc(n, &n->on_y, K) && dalloc(n, &n->on_zbo, n->Jp) &&
          dalloc(n, &n->on_rdone, n->Jp) && dalloc(n, &n->on_zlast, n->Jp);
+    real *pi = nullptr, *pl = nullptr;
+    ok = ok && dalloc(n, &pi, n->Jp) && dalloc(n, &pl, T1 * n->Jp);
+    n->on_I = pi;
+    n->on_L = pl;
   }
   if (ok && ema && !n->on_fh) {
     real *p = nullptr;
@@ -1359,6 +1363,7 @@ eprop_status run_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b,
   };
   MS(n->on_syn, n->S * sizeof(eprop::OnlineSyn<real>));
   MS(n->on_Eh, T1 * K * 8);
+  MS(n->on_L, T1 * n->Jp * sizeof(real));
   MS(n->on_y, K * 8);
   MS(n->on_zbo, n->Jp * 8);
   MS(n->on_rdone, n->Jp * 4);
@@ -1379,6 +1384,8 @@ eprop_status run_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b,
   o.r_done = n->on_rdone;
   o.zlast = n->on_zlast;
   o.fh = static_cast<real *>(n->on_fh);
+  o.Ibuf = static_cast<real *>(n->on_I);
+  o.Lh = static_cast<real *>(n->on_L);
   o.loss = n->on_loss;
   o.psum = n->on_psum;
   o.off = n->on_off;

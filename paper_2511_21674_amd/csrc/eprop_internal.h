@@ -174,6 +174,8 @@ struct OnlineRun {
   double *zbo;                  // [Jp] zbar of each neuron for its readout synapses
   uint32_t *r_done, *zlast;     // [Jp] readout synapses: last step used, last spike
   real *fh;                     // [T+1][Jp] moving-average rates (moving-average regulariser)
+  real *Ibuf;                   // [Jp] input current of the step, from the synapse side
+  real *Lh;                     // [T+1][Jp] learning signals of the run
   double *loss;                 // [n_samples]
   double *psum;                 // [n_samples][K] window sums for the prediction
   const uint32_t *off;          // [n_samples+1] first step - 1 of each sample

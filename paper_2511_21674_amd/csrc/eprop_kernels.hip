@@ -1196,60 +1196,129 @@ __device__ inline bool online_spiked(const DevNet<real> &n, uint32_t src, int64_
   return s >= 1 && ((n.rec_bits[(size_t)s * n.Jw + (r >> 6)] >> (r & 63u)) & 1ull);
 }
 
+// The update walk of one synapse (i -> j, delay D) at an arrival at step t:
+// its eligibility steps s_done+1 .. t - lag (eq. eligibility-vector-
+// substituted, eq. filtered-eligibility-trace, the cutoff rule), each adding
+// L_j^{s+d} ebar^s (the run's learning-signal history) and the
+// moving-average regulariser's c (f_j^s - f*) G_beta(e^s);
+// returns the new weight w - eta g and stores it and the trace state.
+template <typename real>
+__device__ inline real online_update(const DevNet<real> &n, const OnlineRun<real> &o, uint32_t j, uint32_t q,
+                                     uint32_t t, real beta, bool ema) {
+  const uint32_t pk = n.tm_syn[q];
+  const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
+  OnlineSyn<real> st = o.syn[q];
+  const int64_t s_new = (int64_t)t - o.lag;
+  double g = 0.0;
+  real pp = n.psi[(size_t)st.s_done * n.Jp + j];  // psi of the step before the next one
+  for (int64_t s = (int64_t)st.s_done + 1; s <= s_new; ++s) {
+    const bool x = online_spiked(n, src, s - D);
+    const real pn = n.psi[(size_t)s * n.Jp + j];
+    if (x) st.last = (uint32_t)s;
+    if (o.cutoff && (st.last == 0 || (uint64_t)(s - st.last) >= o.cutoff)) {
+      // beyond eprop_isi_trace_cutoff the traces count as decayed
+      st.ev = st.ea = st.eb = st.gh = (real)0;
+      pp = pn;
+      continue;
+    }
+    const bool zr = n.reset_mode == 1 && ((n.rec_bits[(size_t)(s - 1) * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull);
+    const real ea_new = pp * st.ev + (n.rho - pp * beta) * st.ea;
+    const real ev_new = (zr ? (real)0 : n.alpha) * st.ev + (x ? (real)1 : (real)0);
+    const real e = pn * (ev_new - beta * ea_new);
+    st.eb = (real)n.kappa_e_d * st.eb + e;
+    st.ev = ev_new;
+    st.ea = ea_new;
+    st.gh = (real)n.beta_f * st.gh + ((real)1 - (real)n.beta_f) * e;
+    g += (double)o.Lh[(size_t)(s + n.d_out) * n.Jp + j] * (double)st.eb;
+    if (ema) g += n.c_reg * ((double)o.fh[(size_t)s * n.Jp + j] - n.f_target) * (double)st.gh;
+    pp = pn;
+  }
+  if (s_new > (int64_t)st.s_done) st.s_done = (uint32_t)s_new;
+  o.syn[q] = st;
+  const real w = (real)((double)n.tm_w[q] - o.eta * g);
+  n.tm_w[q] = w;
+  return w;
+}
+
+// Position of the r-th set bit of m (r < popcount(m)).
+__device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+  uint32_t pos = 0;
+  for (uint32_t w = 32; w > 0; w >>= 1) {
+    const uint64_t low = m & ((1ull << w) - 1ull);
+    const uint32_t c = (uint32_t)__popcll(low);
+    if (r >= c) {
+      r -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
+// The synapse side of step t: a wavefront per target neuron scans its
+// incoming synapses in target-major order, gathers the ones with an arrival
+// into a list held one per lane (in that order), lets the lanes run their
+// update walks side by side whenever the list is full or the scan ends, and
+// adds the new weights to the input current in list order, so the sum keeps
+// the canonical order.  The current goes to Ibuf for the neuron update.
+template <typename real>
+__global__ __launch_bounds__(256) void k_online_syn(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
+  const uint32_t lane = lane_id();
+  const uint32_t j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= n.J) return;  // whole wavefronts
+  const real beta = n.beta_j[j];
+  const bool ema = n.reg_mode == 1;
+  real I = 0;            // the same in every lane
+  uint32_t cnt = 0;      // arrivals in the list (the same in every lane)
+  uint32_t pend = 0;     // this lane's list entry (lanes < cnt)
+  unsigned long long nev = 0;
+  const uint32_t q0 = n.tm_ptr[j], q1 = n.tm_ptr[j + 1];
+  auto run_list = [&]() {
+    real w = (real)0;
+    if (lane < cnt) w = online_update(n, o, j, pend, t, beta, ema);
+    for (uint32_t l = 0; l < cnt; ++l) I = I + __shfl(w, (int)l);
+    nev += cnt;
+    cnt = 0;
+  };
+  for (uint32_t qb = q0; qb < q1; qb += 64) {
+    const uint32_t q = qb + lane;
+    bool hit = false;
+    if (q < q1) {
+      const uint32_t pk = n.tm_syn[q];
+      hit = online_spiked(n, pk & 0xFFFFFFu, (int64_t)t - (pk >> 24));
+    }
+    const uint64_t m = __ballot(hit);
+    const uint32_t nh = (uint32_t)__popcll(m);
+    if (nh == 0) continue;
+    if (cnt + nh > 64) run_list();
+    // slot cnt + r takes the r-th arrival of this chunk
+    const bool mine = lane >= cnt && lane < cnt + nh;
+    const uint32_t from = mine ? nth_set_bit(m, lane - cnt) : lane;
+    const uint32_t qv = (uint32_t)__shfl((int)q, (int)from);
+    if (mine) pend = qv;
+    cnt += nh;
+  }
+  if (cnt) run_list();
+  if (lane == 0) {
+    o.Ibuf[j] = I;
+    if (nev) atomicAdd(&n.evcnt[(blockIdx.x * 4 + (threadIdx.x >> 6)) & 63u], nev);
+  }
+}
+
+// The neuron side of step t (a thread per neuron): the update with the
+// current gathered by k_online_syn, spikes, rates.
 template <typename real, bool FORCED>
 __global__ __launch_bounds__(256) void k_online_neuron(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n.Jp) return;  // whole wavefronts: Jp is a multiple of 64
   const bool live = j < n.J;
-  const real beta = n.beta_j[j];
   const bool ema = n.reg_mode == 1;
-  real I = 0;
-  unsigned long long nev = 0;
-  if (live) {
-    const uint32_t q1 = n.tm_ptr[j + 1];
-    for (uint32_t q = n.tm_ptr[j]; q < q1; ++q) {
-      const uint32_t pk = n.tm_syn[q];
-      const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
-      if (!online_spiked(n, src, (int64_t)t - D)) continue;
-      ++nev;
-      OnlineSyn<real> st = o.syn[q];
-      const int64_t s_new = (int64_t)t - o.lag;
-      double g = 0.0;
-      for (int64_t s = (int64_t)st.s_done + 1; s <= s_new; ++s) {
-        const bool x = online_spiked(n, src, s - D);
-        if (x) st.last = (uint32_t)s;
-        if (o.cutoff && (st.last == 0 || (uint64_t)(s - st.last) >= o.cutoff)) {
-          // beyond eprop_isi_trace_cutoff the traces count as decayed
-          st.ev = st.ea = st.eb = st.gh = (real)0;
-          continue;
-        }
-        const bool zr = n.reset_mode == 1 && ((n.rec_bits[(size_t)(s - 1) * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull);
-        const real pp = n.psi[(size_t)(s - 1) * n.Jp + j], pn = n.psi[(size_t)s * n.Jp + j];
-        // eq. eligibility-vector-substituted, eq. filtered-eligibility-trace
-        const real ea_new = pp * st.ev + (n.rho - pp * beta) * st.ea;
-        const real ev_new = (zr ? (real)0 : n.alpha) * st.ev + (x ? (real)1 : (real)0);
-        const real e = pn * (ev_new - beta * ea_new);
-        st.eb = (real)n.kappa_e_d * st.eb + e;
-        st.ev = ev_new;
-        st.ea = ea_new;
-        st.gh = (real)n.beta_f * st.gh + ((real)1 - (real)n.beta_f) * e;
-        // the learning signal L_j^{s+d} = sum_k B_jk E_k^{s+d} (eq. final-gradient)
-        const double *E = o.Eh + (size_t)(s + n.d_out) * n.K;
-        double L = 0.0;
-        for (uint32_t k = 0; k < n.K; ++k) L = L + (double)n.fb[(size_t)j * n.K + k] * E[k];
-        g += L * (double)st.eb;
-        if (ema) g += n.c_reg * ((double)o.fh[(size_t)s * n.Jp + j] - n.f_target) * (double)st.gh;
-      }
-      if (s_new > (int64_t)st.s_done) st.s_done = (uint32_t)s_new;
-      o.syn[q] = st;
-      const real w = (real)((double)n.tm_w[q] - o.eta * g);
-      n.tm_w[q] = w;
-      I = I + w;
-    }
-  }
+  const real I = live ? o.Ibuf[j] : (real)0;
   real v = n.v[j], a = n.a[j];
   uint8_t stt = n.nst[j];
-  const bool z = neuron_step<real, FORCED>(n, 0, t, j, live, I, beta, v, a, stt);
+  const bool z = neuron_step<real, FORCED>(n, 0, t, j, live, I, n.beta_j[j], v, a, stt);
   n.v[j] = v;
   n.a[j] = a;
   n.nst[j] = stt;
@@ -1257,11 +1326,19 @@ __global__ __launch_bounds__(256) void k_online_neuron(DevNet<real> n, OnlineRun
   if (ema)
     o.fh[(size_t)t * n.Jp + j] =
         (real)n.beta_f * o.fh[(size_t)(t - 1) * n.Jp + j] + ((real)1 - (real)n.beta_f) * (z ? (real)1 : (real)0);
-  for (int off = 32; off > 0; off >>= 1) nev += __shfl_down(nev, off);
-  if (lane_id() == 0) {
-    if (nev) atomicAdd(&n.evcnt[(blockIdx.x * 4 + (threadIdx.x >> 6)) & 63u], nev);
-    if (word) atomicAdd(&n.cnt[CNT_REC_SPIKES], (unsigned long long)__popcll(word));
-  }
+  if (lane_id() == 0 && word) atomicAdd(&n.cnt[CNT_REC_SPIKES], (unsigned long long)__popcll(word));
+}
+
+// L_j^t = sum_k B_jk E_k^t (eq. final-gradient) of every neuron, FP64 sum in
+// ascending k, kept for the walks of later steps.
+template <typename real>
+__global__ __launch_bounds__(256) void k_online_learn(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n.J) return;
+  const double *E = o.Eh + (size_t)t * n.K;
+  double L = 0.0;
+  for (uint32_t k = 0; k < n.K; ++k) L = L + (double)n.fb[(size_t)j * n.K + k] * E[k];
+  o.Lh[(size_t)t * n.Jp + j] = (real)L;
 }
 
 // One block: the readout synapses of neurons whose spike of step t - d
@@ -1845,10 +1922,12 @@ void Launch<real>::online_fill(const DevNet<real> &n, bool to_records, hipStream
 template <typename real>
 void Launch<real>::online_step(const DevNet<real> &n, const OnlineRun<real> &o, uint32_t t, bool forced,
                                hipStream_t s) {
+  k_online_syn<real><<<(n.J + 3) / 4, 256, 0, s>>>(n, o, t);
   const uint32_t blocks = n.Jp / 256 + (n.Jp % 256 ? 1 : 0);
   if (forced) k_online_neuron<real, true><<<blocks, 256, 0, s>>>(n, o, t);
   else k_online_neuron<real, false><<<blocks, 256, 0, s>>>(n, o, t);
   k_online_readout<real><<<1, 256, 0, s>>>(n, o, t);
+  k_online_learn<real><<<(n.J + 255) / 256, 256, 0, s>>>(n, o, t);
 }
 
 template <typename real>
