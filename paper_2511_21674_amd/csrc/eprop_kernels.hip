@@ -728,7 +728,9 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
 // sum over its spikes u of Ebar_k^u (without the learning-signal cut).  B rows and the chunk's Ebar rows are
 // read from LDS; phi is transposed through LDS so that each store writes
 // whole 16-step row segments.
-template <typename real>
+// PLUS: the full reset or the moving-average regulariser is on (compiled
+// out otherwise, so the plain form keeps its registers).
+template <typename real, bool PLUS>
 __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   extern __shared__ __align__(16) unsigned char adj_smem[];
   const uint32_t b = blockIdx.y;
@@ -747,7 +749,7 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   // rate regulariser (eq. firing-rate-regularization): c^reg/T (f_j - f*)
   // multiplies the eligibility of every step u <= T - d, so it adds to the
   // adjoint's learning-signal sum there
-  const bool ema = n.reg_mode == 1;
+  const bool ema = PLUS && n.reg_mode == 1;
   const double creg = (live && n.c_reg != 0.0 && !ema)
                           ? n.c_reg / (double)T *
                                 ((double)n.spk_cnt[(size_t)b * n.NS + n.I + j] / (double)T - n.f_target)
@@ -765,13 +767,15 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   // decays by beta in between; its values at the spikes are computed forward
   // first and parked in the neuron's archive row at those steps, which the
   // backward pass overwrites only after it has read them.
-  if (ema && live) {
-    double f = 0.0;
-    uint32_t prev = 0;
-    for (uint32_t i = 0; i < c; ++i) {
-      f = n.beta_f * f * pow(n.beta_f, (double)(st[i] - prev - 1)) + (1.0 - n.beta_f);
-      prev = st[i];
-      phi_row[st[i]] = (real)f;
+  if constexpr (PLUS) {
+    if (ema && live) {
+      double f = 0.0;
+      uint32_t prev = 0;
+      for (uint32_t i = 0; i < c; ++i) {
+        f = n.beta_f * f * pow(n.beta_f, (double)(st[i] - prev - 1)) + (1.0 - n.beta_f);
+        prev = st[i];
+        phi_row[st[i]] = (real)f;
+      }
     }
   }
   int32_t sp_i = (int32_t)c - 1;  // last spike at or before the current step
@@ -800,7 +804,7 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
         double L = 0.0;
         for (uint32_t k = 0; k < K; ++k) L += fbl[k * bd + tid] * ebl[r * K + k];
         if ((int64_t)t <= u_reg) L += creg;
-        if (ema) {
+        if (PLUS && ema) {
           while (sp_i >= 0 && st[sp_i] > t) {
             --sp_i;
             f_sp = sp_i >= 0 ? (double)phi_row[st[sp_i]] : 0.0;
@@ -813,7 +817,7 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
         const double pl = p * L;
         // with the full reset the membrane's derivative restarts after a
         // spike of this neuron at step t: alpha (1 - z^t)
-        const bool zt = n.reset_mode == 1 && inrow && ((zrow[(size_t)t * n.Jw] >> (j & 63u)) & 1ull);
+        const bool zt = PLUS && n.reset_mode == 1 && inrow && ((zrow[(size_t)t * n.Jw] >> (j & 63u)) & 1ull);
         const double m0 = pl + (zt ? 0.0 : n.alpha_d) * mu0 + p * mu1;
         const double m1 = -beta * pl + (n.rho_d - p * beta) * mu1;
         mu0 = m0;
@@ -1842,7 +1846,9 @@ template <typename real>
 void Launch<real>::adjoint(const DevNet<real> &n, const Shapes &sh, hipStream_t s) {
   const uint32_t bd = sh.adj_block;
   const size_t smem = (size_t)n.K * bd * 8 + 16 * (size_t)n.K * 8 + (size_t)bd * 17 * sizeof(real);
-  k_adjoint<real><<<dim3(n.Jp / bd + (n.Jp % bd ? 1 : 0), n.Bcap), bd, smem, s>>>(n);
+  const dim3 grid(n.Jp / bd + (n.Jp % bd ? 1 : 0), n.Bcap);
+  if (n.reset_mode == 1 || n.reg_mode == 1) k_adjoint<real, true><<<grid, bd, smem, s>>>(n);
+  else k_adjoint<real, false><<<grid, bd, smem, s>>>(n);
 }
 
 template <typename real>
