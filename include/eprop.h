@@ -126,7 +126,8 @@ typedef enum { EPROP_DELIVERY_AUTO = 0, EPROP_DELIVERY_SCATTER = 1, EPROP_DELIVE
                                            accepted for clarity) */
 #define EPROP_AUTOTUNE (1u << 3)        /* the first training batch times the candidate launch shapes
                                            (delivery variant and steps per forward launch, adjoint and
-                                           synapse block sizes) on the batch itself and keeps the
+                                           synapse block sizes, the synapse kernel's prefetch of spike
+                                           records) on the batch itself and keeps the
                                            fastest; results do not depend on the choice */
 
 /* Optional device allocator, e.g. a framework's caching allocator: every

@@ -689,6 +689,7 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   n->shapes.block = 256;
   n->shapes.fwd_variant = 0;
   n->shapes.adj_block = cfg->n_out > 16 ? 64 : 256;
+  n->shapes.syn_pre = 5;
   n->autotune_pending = (cfg->flags & EPROP_AUTOTUNE) != 0;
   {
     // synapse kernel: a block per (target, chunk of trials); the chunk's
@@ -1212,7 +1213,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     Launch<real>::adjoint(d, n->shapes, s);
     if (prof) (void)hipEventRecord(n->ev[4], s);
     if (tune) {
-      // part 3: threads per block of the synapse kernel; the accumulators
+      // part 3: threads per block and record prefetch depth of the synapse kernel; the accumulators
       // are saved before and restored after every trial run
       void *save = nullptr;
       const size_t gbytes = n->S * sizeof(real);
@@ -1229,16 +1230,19 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
         };
         keep();
         float best = 1e30f;
-        uint32_t bsb = n->shapes.syn_block;
-        for (uint32_t sb : {64u, 128u, 256u}) {
-          n->shapes.syn_block = sb;
-          const float ms = timed(back, [&] {
-            Launch<real>::synapse(d, n->shapes, ntr, static_cast<real *>(n->partial), s);
-          });
-          if (ms < best) { best = ms; bsb = sb; }
-        }
+        uint32_t bsb = n->shapes.syn_block, bpre = n->shapes.syn_pre;
+        for (uint32_t pre : {1u, 2u, 5u})
+          for (uint32_t sb : {64u, 128u, 256u}) {
+            n->shapes.syn_block = sb;
+            n->shapes.syn_pre = pre;
+            const float ms = timed(back, [&] {
+              Launch<real>::synapse(d, n->shapes, ntr, static_cast<real *>(n->partial), s);
+            });
+            if (ms < best) { best = ms; bsb = sb; bpre = pre; }
+          }
         back();
         n->shapes.syn_block = bsb;
+        n->shapes.syn_pre = bpre;
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         release(n, save);
       }

@@ -194,6 +194,7 @@ struct Shapes {
   uint32_t ginst;               // trials per block of the synapse kernel
   uint32_t fwd_variant;         // delivery variant of the forward kernel (piece size, pieces in flight)
   uint32_t adj_block;           // threads per block of the adjoint kernel (64, 128 or 256)
+  uint32_t syn_pre;             // synapse kernel: spike-index blocks loaded with a record's header (1, 2 or 5)
 };
 uint32_t fwd_variant_piece(uint32_t v);
 uint32_t fwd_variant_unroll(uint32_t v);

@@ -962,7 +962,8 @@ __global__ __launch_bounds__(256) void k_pack_fill(DevNet<real> n, uint32_t gins
 // (Kahan); padding elements index the zero tail.  With one chunk the sum
 // goes straight into the accumulator pair (gs, gc); otherwise into
 // partial[c][q] for a fixed-order reduction.
-constexpr uint32_t kPre = 5;  // blocks of 8 spike indices loaded with the header
+// PRE: blocks of 8 spike indices loaded together with a record's header (a
+// shape choice: records of sparse sources hold one or two blocks)
 
 template <typename real>
 __device__ inline void add_block(uint4 v, const real *base, real &s, real &c) {
@@ -971,7 +972,7 @@ __device__ inline void add_block(uint4 v, const real *base, real &s, real &c) {
   for (uint32_t e = 0; e < 8; ++e) kahan_add(s, c, base[(w4[e >> 1] >> ((e & 1u) * 16u)) & 0xFFFFu]);
 }
 
-template <typename real>
+template <typename real, uint32_t PRE>
 __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst, uint32_t nchunk, real *partial) {
   constexpr uint32_t GB = 8;
   extern __shared__ __align__(16) unsigned char syn_smem[];
@@ -1009,18 +1010,18 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
     if (o != kNoRecord) {
       // the table has slack beyond its last record, so these loads stay in bounds
       const uint4 *rec = pk4 + o;
-      uint4 pre[kPre + 1];
+      uint4 pre[PRE + 1];
 #pragma unroll
-      for (uint32_t u = 0; u <= kPre; ++u) pre[u] = rec[u];
+      for (uint32_t u = 0; u <= PRE; ++u) pre[u] = rec[u];
       const uint4 h = pre[0];
       const uint32_t total = (h.x & 0xFFFFu) + (h.x >> 16) + (h.y & 0xFFFFu) + (h.y >> 16) + (h.z & 0xFFFFu) +
                              (h.z >> 16) + (h.w & 0xFFFFu) + (h.w >> 16);
       const uint32_t nbk = (total + 7u) >> 3;
       const real *base = phl + D;
 #pragma unroll
-      for (uint32_t u = 0; u < kPre; ++u)
+      for (uint32_t u = 0; u < PRE; ++u)
         if (u < nbk) add_block(pre[u + 1], base, s, cc);
-      for (uint32_t u = kPre; u < nbk; ++u) add_block(rec[u + 1], base, s, cc);
+      for (uint32_t u = PRE; u < nbk; ++u) add_block(rec[u + 1], base, s, cc);
     }
     if (nchunk == 1) {
       real gs = n.gs[q], gc = n.gc[q];
@@ -1859,7 +1860,11 @@ void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_t
   k_pack_scan_blocks<real><<<1, 1024, 0, s>>>(n, nblk);
   k_pack_fill<real><<<cdiv(N, 256), 256, 0, s>>>(n, sh.ginst, N);
   const size_t smem = ((size_t)sh.ginst * n.Ts + n.R) * sizeof(real);
-  k_synapse<real><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial);
+  switch (sh.syn_pre) {
+    case 1: k_synapse<real, 1><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    case 2: k_synapse<real, 2><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    default: k_synapse<real, 5><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+  }
   if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
 }
 
