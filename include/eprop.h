@@ -350,13 +350,15 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18,     /* uint64 [12]: neurons per tile, tiles per trial, bytes per
+  EPROP_STATE_LAYOUT = 18,     /* uint64 [14]: neurons per tile, tiles per trial, bytes per
                                   delay-ring entry (8: 64-bit fixed point in FP32 or double in
                                   FP64, 4: 32-bit fixed point in FP32), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
                                   forward launch, gather delivery (0/1), synapses per delivery
                                   piece, pieces in flight per lane group, adjoint-kernel
-                                  threads, autotuned (0/1) */
+                                  threads, autotuned (0/1), spiking sources resolved per tile
+                                  thread and round (1 or 2), spike-index blocks the synapse
+                                  kernel loads with a record's header */
   EPROP_STATE_L = 19,          /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
   EPROP_STATE_INPUT_BOUND = 20 /* double [1]: the bound on |input current| of one step used to

@@ -284,20 +284,26 @@ __device__ inline float ring_value(int64_t x, const RingScale &sc) { return (flo
 __device__ inline double ring_value(double x, const RingScale &) { return x; }
 
 // Adds the spikes emitted at step t by inputs and by recurrent neurons of
-// trial b into this tile's LDS ring.  Per chunk of up to blockDim spiking
-// sources: every thread resolves one source to its segment (the part of its
-// target-sorted row inside this tile); segments are cut into pieces of
-// P synapses, numbered by a block scan, and each source records itself
-// as the owner of its pieces.  A group of P consecutive lanes then
-// takes one piece, one synapse record per lane, so that a wavefront's load
-// covers a few contiguous lines; each group keeps U pieces in flight
-// before adding the weights into the ring slots of their arrivals (only
-// arrivals within the trial).  dlo, dlen, dpre: LDS [blockDim]; owner: LDS
-// [kOwner]; wsum: LDS [17].
+// trial b into this tile's LDS ring.  Per chunk of up to rpt * blockDim
+// spiking sources (rpt = n.fwd_rpt, 1 or 2): every thread resolves rpt
+// sources to their segments (the part of each target-sorted row inside this
+// tile); segments are cut into pieces of P synapses, numbered by a block
+// scan, and each source records itself as the owner of its pieces.  A group
+// of P consecutive lanes then takes one piece, one synapse record per lane,
+// so that a wavefront's load covers a few contiguous lines; each group keeps
+// U pieces in flight before adding the weights into the ring slots of their
+// arrivals (only arrivals within the trial).
+// The first E = rpt * blockDim / KT entries of every tile's list are read
+// while the tiles' counts are awaited, so that most recurrent sources of the
+// first chunk are known without a further round trip; an entry whose tag is
+// not yet there is awaited on its own.  They are parked in the owner array,
+// which the first chunk overwrites only after its last read of them.
+// dlo, dlen, dpre: LDS [rpt * blockDim]; owner: LDS [kOwner]; wsum: LDS [17].
 // [P, U] of the delivery variants the autotuner chooses from; variant 0 is
 // the default.
 constexpr uint32_t kOwner = 4096;
 constexpr uint32_t kFwdVariants = 4;
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // a parked list entry that had not arrived
 __host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 1 ? 16u : v == 2 ? 4u : v == 3 ? 16u : 8u; }
 __host__ __device__ constexpr uint32_t fwd_unroll(uint32_t v) { return v == 1 ? 4u : v == 2 ? 16u : 8u; }
 
@@ -307,12 +313,25 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
                                     uint32_t *dlo, uint32_t *dlen, uint32_t *dpre, uint16_t *owner,
                                     uint32_t *wsum) {
   __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike counts of step t
+  static_assert(kOwner * sizeof(uint16_t) >= 2 * kMaxTiles * sizeof(uint32_t), "parked entries fit the owner array");
+  uint32_t *spec = reinterpret_cast<uint32_t *>(owner);  // [E * KT] parked list entries
+  const uint32_t rpt = n.fwd_rpt, span = rpt * blockDim.x;
+  const uint32_t E = span / n.KT;  // >= 1: KT <= blockDim
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
   uint32_t n_rec = 0;
   const uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
-  if (t >= 1) {  // every tile's count of step t (published by the tiles, possibly still on the way)
+  if (t >= 1) {
+    // the first E entries of every tile's list, read ahead of the counts
+    uint64_t ahead[2] = {0ull, 0ull};
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint32_t s = threadIdx.x + u * blockDim.x, tile = s / E, pos = s - tile * E;
+      // (only inside the tile's part of the list buffer)
+      if (u < rpt && tile < n.KT && pos < min(n.TS, n.Jp - tile * n.TS)) ahead[u] = load_sys(pl + (size_t)tile * n.TS + pos);
+    }
+    // every tile's count of step t (published by the tiles, possibly still on the way)
     const uint32_t kk = threadIdx.x;
     uint32_t c = 0;
     if (kk < n.KT) {
@@ -322,20 +341,27 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
     const uint32_t pre = block_exclusive_scan(c, wsum, &n_rec);
     if (kk < n.KT) tpre[kk] = pre;
     if (kk == 0) tpre[n.KT] = n_rec;
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint32_t s = threadIdx.x + u * blockDim.x;
+      if (u < rpt && s / E < n.KT) spec[s] = (uint32_t)(ahead[u] >> 32) == t ? (uint32_t)ahead[u] : kNoEntry;
+    }
     __syncthreads();
   }
   const uint32_t total = n_in + n_rec;
   const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
   const uint32_t slot_t = t % n.R;
   const uint32_t sub = threadIdx.x & (kPiece - 1u), grp = threadIdx.x / kPiece, ngrp = blockDim.x / kPiece;
-  for (uint32_t base = 0; base < total; base += blockDim.x) {
-    const uint32_t m = min(blockDim.x, total - base);
-    uint32_t lo = 0, len = 0;
-    if (threadIdx.x < m) {
-      const uint32_t item = base + threadIdx.x;
-      uint32_t src;
+  for (uint32_t base = 0; base < total; base += span) {
+    uint32_t src[2] = {0u, 0u};
+    bool has[2] = {false, false};
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint32_t item = base + threadIdx.x + u * blockDim.x;
+      if (u >= rpt || item >= total) continue;
+      has[u] = true;
       if (item < n_in) {
-        src = in_src[in_lo + item];
+        src[u] = in_src[in_lo + item];
       } else {
         const uint32_t r = item - n_in;
         uint32_t lk = 0, hk = n.KT;  // tpre[lk] <= r < tpre[hk]
@@ -343,22 +369,38 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
           const uint32_t mid = (lk + hk) >> 1;
           if (tpre[mid] <= r) lk = mid; else hk = mid;
         }
-        const uint32_t j = wait_tag(pl + (size_t)lk * n.TS + (r - tpre[lk]), t, &n.ctl[CTL_ERR]);
-        src = n.I + min(j, n.J - 1u);
+        const uint32_t pos = r - tpre[lk];
+        // parked entries are valid in the first chunk only (the owner array is reused after it)
+        uint32_t j = base == 0 && pos < E ? spec[lk * E + pos] : kNoEntry;
+        if (j == kNoEntry) j = wait_tag(pl + (size_t)lk * n.TS + pos, t, &n.ctl[CTL_ERR]);
+        src[u] = n.I + min(j, n.J - 1u);
       }
-      const uint32_t *ts = n.tseg + (size_t)src * (n.KT + 1) + k;
-      lo = ts[0];
-      len = ts[1] - lo;
     }
-    const uint32_t np = (len + kPiece - 1) / kPiece;
+    uint32_t lo[2] = {0u, 0u}, len[2] = {0u, 0u};
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u)
+      if (has[u]) {
+        const uint32_t *ts = n.tseg + (size_t)src[u] * (n.KT + 1) + k;
+        lo[u] = ts[0];
+        len[u] = ts[1] - lo[u];
+      }
+    const uint32_t np0 = (len[0] + kPiece - 1) / kPiece, np1 = (len[1] + kPiece - 1) / kPiece;
     uint32_t npieces;
-    const uint32_t pre = block_exclusive_scan(np, wsum, &npieces);
-    dlo[threadIdx.x] = lo;
-    dlen[threadIdx.x] = len;
+    const uint32_t pre = block_exclusive_scan(np0 + np1, wsum, &npieces);
+    // (the scan's barrier also ends every read of the parked entries)
+    dlo[threadIdx.x] = lo[0];
+    dlen[threadIdx.x] = len[0];
     dpre[threadIdx.x] = pre;
+    if (rpt > 1) {
+      dlo[threadIdx.x + blockDim.x] = lo[1];
+      dlen[threadIdx.x + blockDim.x] = len[1];
+      dpre[threadIdx.x + blockDim.x] = pre + np0;
+    }
     for (uint32_t w0 = 0; w0 < npieces; w0 += kOwner) {
       const uint32_t w1 = min(npieces, w0 + kOwner);
-      for (uint32_t pc = max(pre, w0); pc < min(pre + np, w1); ++pc) owner[pc - w0] = (uint16_t)threadIdx.x;
+      for (uint32_t pc = max(pre, w0); pc < min(pre + np0, w1); ++pc) owner[pc - w0] = (uint16_t)threadIdx.x;
+      for (uint32_t pc = max(pre + np0, w0); pc < min(pre + np0 + np1, w1); ++pc)
+        owner[pc - w0] = (uint16_t)(threadIdx.x + blockDim.x);
       __syncthreads();
       for (uint32_t pc0 = w0 + grp; pc0 < w1; pc0 += kUnroll * ngrp) {
         // branch-free address phase, then all loads, then the ring adds: the
@@ -419,10 +461,11 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   real *sa = sv + TS;
   uint64_t *words = reinterpret_cast<uint64_t *>(sa + TS);
   uint32_t *woff = reinterpret_cast<uint32_t *>(words + TS / 64);
+  const uint32_t span = n.fwd_rpt * blockDim.x;
   uint32_t *dlo = woff + TS / 64 + 1;
-  uint32_t *dlen = dlo + blockDim.x;
-  uint32_t *dpre = dlen + blockDim.x;
-  uint16_t *owner = reinterpret_cast<uint16_t *>(dpre + blockDim.x);
+  uint32_t *dlen = dlo + span;
+  uint32_t *dpre = dlen + span;
+  uint16_t *owner = reinterpret_cast<uint16_t *>(dpre + span);
   uint8_t *sst = reinterpret_cast<uint8_t *>(owner + kOwner);
   __shared__ uint32_t gtot;
   __shared__ uint32_t wsum[17];
@@ -1760,10 +1803,10 @@ void Launch<real>::neuron_gather(const DevNet<real> &n, uint32_t off, bool force
 }
 
 template <typename real>
-size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes) {
+size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes, uint32_t rpt) {
   const size_t block = TS < 1024 ? TS : 1024;
-  return (size_t)R * TS * ring_bytes + (size_t)2 * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 + 3 * block * 4 +
-         kOwner * 2 + TS + 64;
+  return (size_t)R * TS * ring_bytes + (size_t)2 * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 +
+         3 * block * 4 * rpt + kOwner * 2 + TS + 64;
 }
 
 // The forward kernels of a precision and ring element, one per delivery variant.

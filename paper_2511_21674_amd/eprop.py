@@ -339,7 +339,7 @@ class Network:
             self._check(st)
             return buf[:need // 4].reshape(-1, 2)
         if what == EPROP_STATE_LAYOUT:
-            buf = np.zeros(12, np.uint64)
+            buf = np.zeros(max(need // 8, 1), np.uint64)
             self._check(eprop_read_state(self.h, what, trial, _ptr(buf), buf.nbytes)[0])
             return buf
         if what == EPROP_STATE_ADAM_STEP:
@@ -355,7 +355,7 @@ class Network:
         v = [int(x) for x in self.read(EPROP_STATE_LAYOUT)]
         return dict(zip(("tile_neurons", "tiles", "ring_bytes", "tile_threads", "synapse_threads",
                          "synapse_trials", "steps_per_launch", "gather", "piece", "pieces_in_flight",
-                         "adjoint_threads", "autotuned"), v))
+                         "adjoint_threads", "autotuned", "sources_per_thread", "synapse_prefetch"), v))
 
     def weights(self) -> dict:
         return {"w_in": self.read(EPROP_STATE_W_IN), "w_rec": self.read(EPROP_STATE_W_REC),
