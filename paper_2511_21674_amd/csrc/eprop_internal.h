@@ -109,6 +109,7 @@ struct DevNet {
   const uint32_t *trs;          // blocked update: [n_ach][TS] start of each target's run
   unsigned long long *tsum;     // blocked update: [Jp] per-target sum of |w| * kBoundScale
   const real *beta_j;           // beta_a for ALIF neurons, 0 for LIF [Jp]
+  int32_t any_alif;             // some beta_j is nonzero
   real *w_out, *fb;             // [K][Jp], [Jp][K]
   real *gos, *goc, *adam_mo, *adam_vo;   // [K][Jp]
   real *gout_b;                 // [Bcap][K][Jp]
@@ -203,6 +204,7 @@ constexpr uint32_t kNumFwdVariants = 4;
 
 template <typename real>
 struct Launch {
+  static void rec_lists(const DevNet<real> &n, uint32_t n_trials, hipStream_t s);  // after a tiled forward pass
   static void stage_inputs(const DevNet<real> &n, uint32_t n_trials, uint64_t n_spikes, bool check_order,
                            hipStream_t s);
   static void stage_forced(const DevNet<real> &n, uint32_t n_trials, uint64_t n_forced, hipStream_t s);

@@ -115,6 +115,35 @@ __global__ __launch_bounds__(256) void k_stage_in_lists(DevNet<real> n) {
   n.spk_cnt[(size_t)b * n.NS + i] = c;
 }
 
+// Spike-time lists of the recurrent neurons, ascending, from the bitsets of
+// a finished forward pass (the tiled forward kernel writes only the
+// bitsets, so that a spike costs it no dependent global load).  The bitset
+// word of a step is shared by a wavefront's 64 neurons; 16 steps are loaded
+// at a time.
+template <typename real>
+__global__ __launch_bounds__(256) void k_stage_rec_lists(DevNet<real> n) {
+  const uint32_t b = blockIdx.y;
+  if (b >= n.ctl[CTL_NTRIALS]) return;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n.J) return;
+  const uint32_t T = n.T[b];
+  const uint64_t *bits = n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw + (j >> 6);
+  const uint64_t bit = 1ull << (j & 63u);
+  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
+  uint32_t c = 0, t = 1;
+  for (; t + 15 <= T; t += 16) {
+    uint64_t w[16];
+#pragma unroll
+    for (uint32_t u = 0; u < 16; ++u) w[u] = bits[(size_t)(t + u) * n.Jw];
+#pragma unroll
+    for (uint32_t u = 0; u < 16; ++u)
+      if (w[u] & bit) out[c++] = (uint16_t)(t + u);
+  }
+  for (; t <= T; ++t)
+    if (bits[(size_t)t * n.Jw] & bit) out[c++] = (uint16_t)t;
+  n.spk_cnt[(size_t)b * n.NS + n.I + j] = c;
+}
+
 // Teacher-forced recurrent spikes -> forced_bits[b][t][j].
 template <typename real>
 __global__ __launch_bounds__(256) void k_stage_forced(DevNet<real> n, uint32_t ntr, uint64_t nf) {
@@ -170,13 +199,14 @@ __device__ inline bool neuron_step(const DevNet<real> &n, uint32_t b, uint32_t t
   return z;
 }
 
-// Spike bitset word of this wavefront's 64 neurons and the spike-time list
-// of each spiking neuron.  Called by whole wavefronts aligned to 64 neurons.
-template <typename real>
+// Spike bitset word of this wavefront's 64 neurons and (LISTS) the
+// spike-time list of each spiking neuron.  Called by whole wavefronts aligned
+// to 64 neurons.
+template <typename real, bool LISTS = true>
 __device__ inline uint64_t publish_bits(const DevNet<real> &n, uint32_t b, uint32_t t, uint32_t j, bool z) {
   const uint64_t word = __ballot(z);
   if (lane_id() == 0) n.rec_bits[((size_t)b * (n.Tcap + 1) + t) * n.Jw + (j >> 6)] = word;
-  if (z) {
+  if (LISTS && z) {
     const size_t ci = (size_t)b * n.NS + n.I + j;
     const uint32_t c = n.spk_cnt[ci];
     n.spk_t[(size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc + c] = (uint16_t)t;
@@ -493,11 +523,12 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       const real I = ring_value(ring[slot * TS + i], sc);
       ring[slot * TS + i] = (ring_t)0;
       const uint32_t j = j0 + i;
-      const bool z = neuron_step<real, FORCED>(n, b, t, j, j < n.J, I, n.beta_j[j], v, a, st);
+      const real beta = n.any_alif ? n.beta_j[j] : (real)0;
+      const bool z = neuron_step<real, FORCED>(n, b, t, j, j < n.J, I, beta, v, a, st);
       sv[i] = v;
       sa[i] = a;
       sst[i] = st;
-      const uint64_t word = publish_bits(n, b, t, j, z);
+      const uint64_t word = publish_bits<real, false>(n, b, t, j, z);
       if (lane_id() == 0) words[i >> 6] = word;
     }
     __syncthreads();
@@ -1793,6 +1824,11 @@ void Launch<real>::stage_inputs(const DevNet<real> &n, uint32_t ntr, uint64_t ns
 template <typename real>
 void Launch<real>::stage_forced(const DevNet<real> &n, uint32_t ntr, uint64_t nf, hipStream_t s) {
   if (nf > 0) k_stage_forced<real><<<grid_for(nf, 256), 256, 0, s>>>(n, ntr, nf);
+}
+
+template <typename real>
+void Launch<real>::rec_lists(const DevNet<real> &n, uint32_t ntr, hipStream_t s) {
+  if (n.J > 0) k_stage_rec_lists<real><<<dim3(cdiv(n.J, 256), ntr), 256, 0, s>>>(n);
 }
 
 template <typename real>
