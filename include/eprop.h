@@ -356,9 +356,9 @@ typedef enum {
                                   synapse-kernel threads, trials per synapse block, steps per
                                   forward launch, gather delivery (0/1), synapses per delivery
                                   piece, pieces in flight per lane group, adjoint-kernel
-                                  threads, autotuned (0/1), spiking sources resolved per tile
-                                  thread and round (1 or 2), spike-index blocks the synapse
-                                  kernel loads with a record's header */
+                                  threads, autotuned (0/1), entries of a tile's delivery piece
+                                  table, spike-index blocks the synapse kernel loads with a
+                                  record's header */
   EPROP_STATE_L = 19,          /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
   EPROP_STATE_INPUT_BOUND = 20 /* double [1]: the bound on |input current| of one step used to

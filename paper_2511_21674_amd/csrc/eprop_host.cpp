@@ -722,15 +722,17 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   // Tiles of the persistent forward kernel: as many neurons per workgroup as
   // LDS allows, but enough tiles to spread the trials over the device; small
   // networks keep a whole trial in one workgroup (no inter-workgroup barrier).
-  uint32_t TS = n->Jp, KT = 1, tile_block = 64, ring_bytes = 8, fwd_rpt = 1;
+  uint32_t TS = n->Jp, KT = 1, tile_block = 64, ring_bytes = 8, ptab_cap = 4096;
   if (!n->gather) {
     size_t lds = prop.sharedMemPerBlock;
     if (prop.sharedMemPerBlockOptin > lds) lds = prop.sharedMemPerBlockOptin;
     if (prop.maxSharedMemoryPerMultiProcessor > 0 && lds > prop.maxSharedMemoryPerMultiProcessor)
       lds = prop.maxSharedMemoryPerMultiProcessor;
     const size_t fixed = 1024 + 4 * 1025;  // static LDS of the kernel (tile count prefix) and slack
-    auto smem_of = [&](uint32_t ts, uint32_t rb, uint32_t rpt = 1) {
-      return n->fp64 ? Launch<double>::tile_smem(ts, n->R, rb, rpt) : Launch<float>::tile_smem(ts, n->R, rb, rpt);
+    // the tile size is chosen with a piece table of 2560 entries (20 KB),
+    // which grows to 4096 where LDS has room
+    auto smem_of = [&](uint32_t ts, uint32_t rb, uint32_t cap = 2560) {
+      return n->fp64 ? Launch<double>::tile_smem(ts, n->R, rb, cap) : Launch<float>::tile_smem(ts, n->R, rb, cap);
     };
     auto ts_max = [&](uint32_t rb) {  // largest tile (multiple of 64) that fits LDS
       uint32_t ts = 64;
@@ -762,10 +764,8 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
       delete n;
       return EPROP_ERR_UNSUPPORTED;
     }
-    // two spiking sources per thread and chunk where LDS has room for their
-    // segment tables (one resolve round for up to 2 * tile_block sources)
-    fwd_rpt = smem_of(TS, ring_bytes, 2) + fixed <= lds ? 2u : 1u;
-    n->tile_smem = smem_of(TS, ring_bytes, fwd_rpt);
+    ptab_cap = smem_of(TS, ring_bytes, 4096) + fixed <= lds ? 4096u : 2560u;
+    n->tile_smem = smem_of(TS, ring_bytes, ptab_cap);
     // blocked transposition for the update where source rows are dense within
     // a tile (at least 4 synapses per source and tile on average)
     const size_t blk_lds = n->fp64 ? Launch<double>::apply_blocked_smem(TS) : Launch<float>::apply_blocked_smem(TS);
@@ -776,7 +776,7 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   n->n32.TS = n->n64.TS = TS;
   n->n32.KT = n->n64.KT = KT;
   n->n32.ring_bytes = n->n64.ring_bytes = ring_bytes;
-  n->n32.fwd_rpt = n->n64.fwd_rpt = fwd_rpt;
+  n->n32.ptab_cap = n->n64.ptab_cap = ptab_cap;
   n->blk = std::min<uint32_t>(n->gather ? 50 : 250, n->Tcap);
 
   std::vector<double> beta(n->Jp, 0.0);
@@ -1605,7 +1605,7 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
     const uint64_t lay[14] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                               n->blk, n->gather ? 1u : 0u, eprop::fwd_variant_piece(n->shapes.fwd_variant),
                               eprop::fwd_variant_unroll(n->shapes.fwd_variant), n->shapes.adj_block,
-                              n->tuned ? 1u : 0u, d.fwd_rpt, n->shapes.syn_pre};
+                              n->tuned ? 1u : 0u, d.ptab_cap, n->shapes.syn_pre};
     if (needed) *needed = sizeof(lay);
     if (!dst) return EPROP_OK;
     if (dst_bytes < sizeof(lay)) return EPROP_ERR_INVALID_ARGUMENT;

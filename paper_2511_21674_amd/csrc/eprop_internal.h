@@ -88,7 +88,7 @@ struct DevNet {
   int32_t surrogate, loss;
   uint32_t step_stride;         // batch target/window row length
   uint32_t TS, KT;              // tile size (neurons), tiles per trial
-  uint32_t fwd_rpt;             // spiking sources each thread of a tile resolves per chunk (1 or 2)
+  uint32_t ptab_cap;            // entries of the forward tile's piece table (>= its threads)
   // constants (working precision for the dynamics, FP64 for the backward filters)
   real alpha, rho, v_th, sg_gamma, sg_beta;
   double alpha_d, rho_d, kappa_d;
@@ -213,7 +213,7 @@ struct Launch {
   // persistent tiled forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps
   static void forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, const Shapes &sh,
                             size_t smem, hipStream_t s);
-  static size_t tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes, uint32_t rpt);
+  static size_t tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes, uint32_t ptab_cap);
   static hipError_t allow_smem(size_t smem, uint32_t ring_bytes);
   static hipError_t resident(uint32_t block, size_t smem, uint32_t ring_bytes, int *per_cu);
   static void readout(const DevNet<real> &n, hipStream_t s);

@@ -314,24 +314,24 @@ __device__ inline float ring_value(int64_t x, const RingScale &sc) { return (flo
 __device__ inline double ring_value(double x, const RingScale &) { return x; }
 
 // Adds the spikes emitted at step t by inputs and by recurrent neurons of
-// trial b into this tile's LDS ring.  Per chunk of up to rpt * blockDim
-// spiking sources (rpt = n.fwd_rpt, 1 or 2): every thread resolves rpt
-// sources to their segments (the part of each target-sorted row inside this
-// tile); segments are cut into pieces of P synapses, numbered by a block
-// scan, and each source records itself as the owner of its pieces.  A group
-// of P consecutive lanes then takes one piece, one synapse record per lane,
-// so that a wavefront's load covers a few contiguous lines; each group keeps
-// U pieces in flight before adding the weights into the ring slots of their
-// arrivals (only arrivals within the trial).
-// The first E = rpt * blockDim / KT entries of every tile's list are read
+// trial b into this tile's LDS ring.  Per chunk of up to 2 * blockDim
+// spiking sources: every thread resolves two sources to their segments (the
+// part of each target-sorted row inside this tile); segments are cut into
+// pieces of P synapses, numbered by a block scan, and each source writes the
+// entries of its pieces (first record, record count) into the piece table.
+// A group of P consecutive lanes then takes one piece, one synapse record
+// per lane, so that a wavefront's load covers a few contiguous lines; each
+// group keeps U pieces in flight before adding the weights into the ring
+// slots of their arrivals (only arrivals within the trial).  A lane's
+// address is one LDS read of its piece's entry.
+// The first E = 2 * blockDim / KT entries of every tile's list are read
 // while the tiles' counts are awaited, so that most recurrent sources of the
 // first chunk are known without a further round trip; an entry whose tag is
-// not yet there is awaited on its own.  They are parked in the owner array,
+// not yet there is awaited on its own.  They are parked in the piece table,
 // which the first chunk overwrites only after its last read of them.
-// dlo, dlen, dpre: LDS [rpt * blockDim]; owner: LDS [kOwner]; wsum: LDS [17].
+// ptab: LDS [cap] (cap = n.ptab_cap >= blockDim); wsum: LDS [17].
 // [P, U] of the delivery variants the autotuner chooses from; variant 0 is
 // the default.
-constexpr uint32_t kOwner = 4096;
 constexpr uint32_t kFwdVariants = 4;
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // a parked list entry that had not arrived
 __host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 1 ? 16u : v == 2 ? 4u : v == 3 ? 16u : 8u; }
@@ -340,12 +340,12 @@ __host__ __device__ constexpr uint32_t fwd_unroll(uint32_t v) { return v == 1 ? 
 template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
-                                    uint32_t *dlo, uint32_t *dlen, uint32_t *dpre, uint16_t *owner,
-                                    uint32_t *wsum) {
+                                    uint2 *ptab, uint32_t *wsum) {
   __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike counts of step t
-  static_assert(kOwner * sizeof(uint16_t) >= 2 * kMaxTiles * sizeof(uint32_t), "parked entries fit the owner array");
-  uint32_t *spec = reinterpret_cast<uint32_t *>(owner);  // [E * KT] parked list entries
-  const uint32_t rpt = n.fwd_rpt, span = rpt * blockDim.x;
+  uint32_t *spec = reinterpret_cast<uint32_t *>(ptab);  // [E * KT <= 2 * blockDim] parked list entries
+  const uint32_t cap = n.ptab_cap;
+  constexpr uint32_t rpt = 2;
+  const uint32_t span = rpt * blockDim.x;
   const uint32_t E = span / n.KT;  // >= 1: KT <= blockDim
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
@@ -418,19 +418,16 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
     uint32_t npieces;
     const uint32_t pre = block_exclusive_scan(np0 + np1, wsum, &npieces);
     // (the scan's barrier also ends every read of the parked entries)
-    dlo[threadIdx.x] = lo[0];
-    dlen[threadIdx.x] = len[0];
-    dpre[threadIdx.x] = pre;
-    if (rpt > 1) {
-      dlo[threadIdx.x + blockDim.x] = lo[1];
-      dlen[threadIdx.x + blockDim.x] = len[1];
-      dpre[threadIdx.x + blockDim.x] = pre + np0;
-    }
-    for (uint32_t w0 = 0; w0 < npieces; w0 += kOwner) {
-      const uint32_t w1 = min(npieces, w0 + kOwner);
-      for (uint32_t pc = max(pre, w0); pc < min(pre + np0, w1); ++pc) owner[pc - w0] = (uint16_t)threadIdx.x;
-      for (uint32_t pc = max(pre + np0, w0); pc < min(pre + np0 + np1, w1); ++pc)
-        owner[pc - w0] = (uint16_t)(threadIdx.x + blockDim.x);
+    for (uint32_t w0 = 0; w0 < npieces; w0 += cap) {
+      const uint32_t w1 = min(npieces, w0 + cap);
+#pragma unroll
+      for (uint32_t u = 0; u < 2; ++u) {
+        const uint32_t p0 = u ? pre + np0 : pre, np = u ? np1 : np0;
+        for (uint32_t pc = max(p0, w0); pc < min(p0 + np, w1); ++pc) {
+          const uint32_t off = (pc - p0) * kPiece;
+          ptab[pc - w0] = make_uint2(lo[u] + off, min(kPiece, len[u] - off));
+        }
+      }
       __syncthreads();
       for (uint32_t pc0 = w0 + grp; pc0 < w1; pc0 += kUnroll * ngrp) {
         // branch-free address phase, then all loads, then the ring adds: the
@@ -442,10 +439,9 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
         for (uint32_t u = 0; u < kUnroll; ++u) {
           const uint32_t pc = pc0 + u * ngrp;
           const bool inb = pc < w1;
-          const uint32_t i = owner[inb ? pc - w0 : 0u];
-          const uint32_t off = (pc - dpre[i]) * kPiece + sub;
-          const bool ok = inb && off < dlen[i];
-          idx[u] = ok ? dlo[i] + off : 0u;
+          const uint2 pe = ptab[inb ? pc - w0 : 0u];
+          const bool ok = inb && sub < pe.y;
+          idx[u] = ok ? pe.x + sub : 0u;
           live |= (uint32_t)ok << u;
         }
         SynRec<real> r[kUnroll];
@@ -491,12 +487,8 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   real *sa = sv + TS;
   uint64_t *words = reinterpret_cast<uint64_t *>(sa + TS);
   uint32_t *woff = reinterpret_cast<uint32_t *>(words + TS / 64);
-  const uint32_t span = n.fwd_rpt * blockDim.x;
-  uint32_t *dlo = woff + TS / 64 + 1;
-  uint32_t *dlen = dlo + span;
-  uint32_t *dpre = dlen + span;
-  uint16_t *owner = reinterpret_cast<uint16_t *>(dpre + span);
-  uint8_t *sst = reinterpret_cast<uint8_t *>(owner + kOwner);
+  uint2 *ptab = reinterpret_cast<uint2 *>(woff + ((TS / 64 + 2) & ~1u));  // 8-byte aligned
+  uint8_t *sst = reinterpret_cast<uint8_t *>(ptab + n.ptab_cap);
   __shared__ uint32_t gtot;
   __shared__ uint32_t wsum[17];
   RingScale sc{1.f, 1.f};
@@ -511,7 +503,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile<real, ring_t, P, U>(n, b, k, j0, 0, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
+    deliver_tile<real, ring_t, P, U>(n, b, k, j0, 0, Tb, ring, sc, ptab, wsum);
     __syncthreads();
   }
   const uint32_t t_end = min(t0 + nsteps, Tb);
@@ -562,7 +554,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       __syncthreads();
       if (threadIdx.x == 0) store_sys(&n.pub_cnt[((size_t)b * 2 + (t & 1u)) * KT + k], tag | gtot);
     }
-    if (t < Tb) deliver_tile<real, ring_t, P, U>(n, b, k, j0, t, Tb, ring, sc, dlo, dlen, dpre, owner, wsum);
+    if (t < Tb) deliver_tile<real, ring_t, P, U>(n, b, k, j0, t, Tb, ring, sc, ptab, wsum);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -1839,10 +1831,9 @@ void Launch<real>::neuron_gather(const DevNet<real> &n, uint32_t off, bool force
 }
 
 template <typename real>
-size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes, uint32_t rpt) {
-  const size_t block = TS < 1024 ? TS : 1024;
-  return (size_t)R * TS * ring_bytes + (size_t)2 * TS * sizeof(real) + (size_t)(TS / 64) * 12 + 4 +
-         3 * block * 4 * rpt + kOwner * 2 + TS + 64;
+size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes, uint32_t ptab_cap) {
+  return (size_t)R * TS * ring_bytes + (size_t)2 * TS * sizeof(real) + (size_t)(TS / 64) * 8 +
+         ((TS / 64 + 2) & ~1u) * 4 + (size_t)ptab_cap * 8 + TS + 64;
 }
 
 // The forward kernels of a precision and ring element, one per delivery variant.
