@@ -99,49 +99,65 @@ __global__ __launch_bounds__(256) void k_stage_in_step_ptr(DevNet<real> n) {
   }
 }
 
-// Per-channel input spike-time lists, ascending, from the bitsets.
+// Spike-time lists, ascending, of the 64 sources of one bitset column, by
+// one wavefront: lane l reads the column's word of step t0 + l, and 64
+// ballots turn the 64 x 64 bit block around, so that each lane then holds
+// its source's spikes over those 64 steps.  Steps t_lo .. t_hi - 1; rows
+// are `stride` words apart.  Returns the lane's count (writes only if live).
+__device__ inline uint32_t column_lists(const uint64_t *col, size_t stride, uint32_t t_lo, uint32_t t_hi,
+                                        uint16_t *out, bool live) {
+  const uint32_t lane = lane_id();
+  uint32_t c = 0;
+  for (uint32_t t0 = t_lo; t0 < t_hi; t0 += 64) {
+    const uint32_t t = t0 + lane;
+    const uint64_t w = t < t_hi ? col[(size_t)t * stride] : 0ull;
+    uint64_t mine = 0;
+#pragma unroll 8
+    for (uint32_t nb = 0; nb < 64; ++nb) {
+      const uint64_t m = __ballot((w >> nb) & 1ull);
+      mine = lane == nb ? m : mine;
+    }
+    while (mine) {
+      const uint32_t s = (uint32_t)__ffsll((unsigned long long)mine) - 1u;
+      mine &= mine - 1ull;
+      if (live) out[c] = (uint16_t)(t0 + s);
+      c += 1;
+    }
+  }
+  return live ? c : 0u;
+}
+
+// Per-channel input spike-time lists, ascending, from the bitsets (steps
+// 0 .. T-1); a wavefront per 64 channels.
 template <typename real>
 __global__ __launch_bounds__(256) void k_stage_in_lists(DevNet<real> n) {
   const uint32_t b = blockIdx.y;
   if (b >= n.ctl[CTL_NTRIALS]) return;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n.I) return;
-  const uint32_t T = n.T[b];
-  const uint64_t *bits = n.in_bits + (size_t)b * n.Tcap * n.Iw + (i >> 6);
-  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)i * n.Lc;
-  uint32_t c = 0;
-  for (uint32_t s = 0; s < T; ++s)
-    if ((bits[(size_t)s * n.Iw] >> (i & 63u)) & 1ull) out[c++] = (uint16_t)s;
-  n.spk_cnt[(size_t)b * n.NS + i] = c;
+  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n.Iw) return;  // whole wavefronts
+  const uint32_t i = w * 64 + lane_id();
+  const bool live = i < n.I;
+  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)(live ? i : 0u) * n.Lc;
+  const uint32_t c = column_lists(n.in_bits + (size_t)b * n.Tcap * n.Iw + w, n.Iw, 0, n.T[b], out, live);
+  if (live) n.spk_cnt[(size_t)b * n.NS + i] = c;
 }
 
 // Spike-time lists of the recurrent neurons, ascending, from the bitsets of
-// a finished forward pass (the tiled forward kernel writes only the
-// bitsets, so that a spike costs it no dependent global load).  The bitset
-// word of a step is shared by a wavefront's 64 neurons; 16 steps are loaded
-// at a time.
+// a finished forward pass (steps 1 .. T; the tiled forward kernel writes
+// only the bitsets, so that a spike costs it no dependent global load); a
+// wavefront per 64 neurons.
 template <typename real>
 __global__ __launch_bounds__(256) void k_stage_rec_lists(DevNet<real> n) {
   const uint32_t b = blockIdx.y;
   if (b >= n.ctl[CTL_NTRIALS]) return;
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n.J) return;
-  const uint32_t T = n.T[b];
-  const uint64_t *bits = n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw + (j >> 6);
-  const uint64_t bit = 1ull << (j & 63u);
-  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
-  uint32_t c = 0, t = 1;
-  for (; t + 15 <= T; t += 16) {
-    uint64_t w[16];
-#pragma unroll
-    for (uint32_t u = 0; u < 16; ++u) w[u] = bits[(size_t)(t + u) * n.Jw];
-#pragma unroll
-    for (uint32_t u = 0; u < 16; ++u)
-      if (w[u] & bit) out[c++] = (uint16_t)(t + u);
-  }
-  for (; t <= T; ++t)
-    if (bits[(size_t)t * n.Jw] & bit) out[c++] = (uint16_t)t;
-  n.spk_cnt[(size_t)b * n.NS + n.I + j] = c;
+  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n.Jw) return;  // whole wavefronts
+  const uint32_t j = w * 64 + lane_id();
+  const bool live = j < n.J;
+  uint16_t *out = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + (live ? j : 0u)) * n.Lc;
+  const uint32_t c =
+      column_lists(n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw + w, n.Jw, 1, n.T[b] + 1, out, live);
+  if (live) n.spk_cnt[(size_t)b * n.NS + n.I + j] = c;
 }
 
 // Teacher-forced recurrent spikes -> forced_bits[b][t][j].
@@ -807,7 +823,7 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   const bool live = j < n.J;
   const bool inrow = j < n.Jp;
   double *fbl = reinterpret_cast<double *>(adj_smem);   // [K][bd]
-  double *ebl = fbl + (size_t)K * bd;                   // [16][K]
+  double *ebl = fbl + (size_t)K * bd;                   // [K][16]
   real *tile = reinterpret_cast<real *>(ebl + 16 * K);  // [bd][17]
   for (uint32_t k = 0; k < K; ++k) fbl[k * bd + tid] = live ? (double)n.fb[(size_t)j * K + k] : 0.0;
   const double beta = live ? (double)n.beta_j[j] : 0.0;
@@ -852,8 +868,8 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
     const uint32_t tb = (uint32_t)m * 16;
     __syncthreads();
     for (uint32_t idx = tid; idx < 16 * K; idx += bd) {
-      const uint32_t t = tb + idx / K;
-      ebl[idx] = (t >= 1 && t <= T) ? eb[(size_t)t * K + idx % K] : 0.0;
+      const uint32_t k = idx >> 4, t = tb + (idx & 15u);
+      ebl[idx] = (t >= 1 && t <= T) ? eb[(size_t)t * K + k] : 0.0;
     }
     __syncthreads();
     real ps[16];
@@ -862,13 +878,23 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
       const uint32_t t = tb + r;
       ps[r] = (inrow && t >= 1 && t <= T) ? ps_col[(size_t)t * n.Jp] : (real)0;
     }
+    // Lambda of the chunk's 16 steps: k outer, so each B_jk is read once per
+    // chunk and the 16 error values of k are one broadcast row
+    double lam[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lam[r] = 0.0;
+    for (uint32_t k = 0; k < K; ++k) {
+      const double f = fbl[k * bd + tid];
+      const double *e = ebl + k * 16;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lam[r] = fma(f, e[r], lam[r]);
+    }
 #pragma unroll
     for (int r = 15; r >= 0; --r) {
       const uint32_t t = tb + r;
       real out = (real)0;
       if (t >= 1 && t <= T) {
-        double L = 0.0;
-        for (uint32_t k = 0; k < K; ++k) L += fbl[k * bd + tid] * ebl[r * K + k];
+        double L = lam[r];
         if ((int64_t)t <= u_reg) L += creg;
         if (PLUS && ema) {
           while (sp_i >= 0 && st[sp_i] > t) {
@@ -1810,7 +1836,7 @@ void Launch<real>::stage_inputs(const DevNet<real> &n, uint32_t ntr, uint64_t ns
   if (nsp > 0)
     k_stage_in_bits<real><<<grid_for(nsp, 256), 256, 0, s>>>(n, ntr, nsp, check_order ? 1 : 0);
   k_stage_in_step_ptr<real><<<dim3(cdiv(n.Tcap + 1, 256), n.Bcap), 256, 0, s>>>(n);
-  if (n.I > 0) k_stage_in_lists<real><<<dim3(cdiv(n.I, 256), n.Bcap), 256, 0, s>>>(n);
+  if (n.I > 0) k_stage_in_lists<real><<<dim3(cdiv(n.Iw, 4), n.Bcap), 256, 0, s>>>(n);
 }
 
 template <typename real>
@@ -1820,7 +1846,7 @@ void Launch<real>::stage_forced(const DevNet<real> &n, uint32_t ntr, uint64_t nf
 
 template <typename real>
 void Launch<real>::rec_lists(const DevNet<real> &n, uint32_t ntr, hipStream_t s) {
-  if (n.J > 0) k_stage_rec_lists<real><<<dim3(cdiv(n.J, 256), ntr), 256, 0, s>>>(n);
+  if (n.J > 0) k_stage_rec_lists<real><<<dim3(cdiv(n.Jw, 4), ntr), 256, 0, s>>>(n);
 }
 
 template <typename real>
