@@ -864,20 +864,51 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
   double f_sp = (ema && sp_i >= 0) ? (double)phi_row[st[sp_i]] : 0.0, R = 0.0;
   const uint64_t *zrow = n.rec_bits + (size_t)b * (n.Tcap + 1) * n.Jw + (inrow ? (j >> 6) : 0u);
   double mu0 = 0.0, mu1 = 0.0;
-  for (int m = (int)(T / 16); m >= 0; --m) {
-    const uint32_t tb = (uint32_t)m * 16;
-    __syncthreads();
-    for (uint32_t idx = tid; idx < 16 * K; idx += bd) {
-      const uint32_t k = idx >> 4, t = tb + (idx & 15u);
-      ebl[idx] = (t >= 1 && t <= T) ? eb[(size_t)t * K + k] : 0.0;
-    }
-    __syncthreads();
-    real ps[16];
+  // The psi rows and error values of a chunk are loaded one chunk ahead,
+  // before the archive stores of the current chunk: vector memory operations
+  // complete in order on this GPU, so a load issued after those stores would
+  // wait for them.  (Error values ahead only while they fit 4 per thread.)
+  const bool e_ahead = 16 * K <= 4 * bd;
+  real psn[16];
+  double en[4];
+  // branch-free, with no use of the values until the next chunk: every lane
+  // loads from a clamped, valid address, and what lies outside the trial is
+  // dropped where the values are used
+  const real *ps_safe = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + (inrow ? j : 0u);
+  auto fetch = [&](uint32_t tc) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const uint32_t t = tb + r;
-      ps[r] = (inrow && t >= 1 && t <= T) ? ps_col[(size_t)t * n.Jp] : (real)0;
+      const uint32_t t = tc + r, tt = t < 1 ? 1u : (t > T ? T : t);
+      psn[r] = ps_safe[(size_t)tt * n.Jp];
     }
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t idx = tid + q * bd, k = idx >> 4, t = tc + (idx & 15u);
+      const bool ok = e_ahead && idx < 16 * K && t >= 1 && t <= T;
+      en[q] = eb[ok ? (size_t)t * K + k : 0u];
+    }
+  };
+  fetch((T / 16) * 16);
+  for (int m = (int)(T / 16); m >= 0; --m) {
+    const uint32_t tb = (uint32_t)m * 16;
+    real ps[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ps[r] = psn[r];
+    __syncthreads();
+    if (e_ahead) {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t idx = tid + q * bd, t = tb + (idx & 15u);
+        if (idx < 16 * K) ebl[idx] = (t >= 1 && t <= T) ? en[q] : 0.0;
+      }
+    } else {
+      for (uint32_t idx = tid; idx < 16 * K; idx += bd) {
+        const uint32_t k = idx >> 4, t = tb + (idx & 15u);
+        ebl[idx] = (t >= 1 && t <= T) ? eb[(size_t)t * K + k] : 0.0;
+      }
+    }
+    if (m > 0) fetch(tb - 16);
+    __syncthreads();
     // Lambda of the chunk's 16 steps: k outer, so each B_jk is read once per
     // chunk and the 16 error values of k are one broadcast row
     double lam[16];
