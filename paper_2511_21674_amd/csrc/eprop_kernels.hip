@@ -684,11 +684,25 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   double *ysum = n.ysum + b * rs, *y = n.y + b * rs, *err = n.err + b * rs, *ebar = n.ebar + b * rs;
   double *ebo = n.ebo + b * rs;
   const double kap = n.kappa_d;
+  // the serial scans below take their inputs 16 steps at a time, loaded
+  // before the recursion needs them, so that a step does not wait for memory
   for (uint32_t k = tid; k < K; k += blockDim.x) {
     double yy = 0.0;
-    for (uint32_t t = 1; t <= T; ++t) {
-      yy = kap * yy + (t > d ? ysum[(size_t)(t - d) * K + k] : 0.0);
-      y[(size_t)t * K + k] = yy;
+    for (uint32_t t0 = 1; t0 <= T; t0 += 16) {
+      double in[16];
+#pragma unroll
+      for (uint32_t u = 0; u < 16; ++u) {
+        const uint32_t t = t0 + u;
+        in[u] = (t <= T && t > d) ? ysum[(size_t)(t - d) * K + k] : 0.0;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < 16; ++u) {
+        const uint32_t t = t0 + u;
+        if (t <= T) {
+          yy = kap * yy + in[u];
+          y[(size_t)t * K + k] = yy;
+        }
+      }
     }
   }
   __syncthreads();
@@ -774,24 +788,44 @@ __global__ __launch_bounds__(256) void k_readout_scan(DevNet<real> n) {
   const double kap_e = n.kappa_e_d;
   for (uint32_t k = tid; k < K; k += blockDim.x) {
     double eb = 0.0, eo = 0.0;
-    for (int64_t u = T; u >= 1; --u) {
-      const double e = u <= u_out ? err[(size_t)(u + d) * K + k] : 0.0;
-      eo = e + kap * eo;
-      eb = u <= u_rec ? e + kap_e * eb : 0.0;
-      ebar[(size_t)u * K + k] = eb;
-      if (ebo != ebar) ebo[(size_t)u * K + k] = eo;
+    for (int64_t u0 = T; u0 >= 1; u0 -= 16) {
+      double in[16];
+#pragma unroll
+      for (int64_t q = 0; q < 16; ++q) {
+        const int64_t u = u0 - q;
+        in[q] = (u >= 1 && u <= u_out) ? err[(size_t)(u + d) * K + k] : 0.0;
+      }
+#pragma unroll
+      for (int64_t q = 0; q < 16; ++q) {
+        const int64_t u = u0 - q;
+        if (u >= 1) {
+          const double e = in[q];
+          eo = e + kap * eo;
+          eb = u <= u_rec ? e + kap_e * eb : 0.0;
+          ebar[(size_t)u * K + k] = eb;
+          if (ebo != ebar) ebo[(size_t)u * K + k] = eo;
+        }
+      }
     }
     if (n.loss != 0 && k < 64) {
       double s = 0.0;
-      for (uint32_t t = 1; t <= T; ++t) s += ysum[(size_t)t * K + k];
+      for (uint32_t t0 = 1; t0 <= T; t0 += 16) {
+        double in[16];
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u) in[u] = t0 + u <= T ? ysum[(size_t)(t0 + u) * K + k] : 0.0;
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u) s += in[u];
+      }
       psum[k] = s;
     }
   }
+  {
+    unsigned long long ns = 0;
+    for (uint32_t t = 1 + tid; t <= T; t += blockDim.x) ns += n.nspk[(size_t)b * (n.Tcap + 1) + t];
+    if (ns) atomicAdd(&n.cnt[CNT_REC_SPIKES], ns);
+  }
   __syncthreads();
   if (tid == 0) {
-    unsigned long long ns = 0;
-    for (uint32_t t = 1; t <= T; ++t) ns += n.nspk[(size_t)b * (n.Tcap + 1) + t];
-    atomicAdd(&n.cnt[CNT_REC_SPIKES], ns);
     n.loss_out[b] = red[0];
     uint32_t best = 0;
     if (n.loss != 0)
