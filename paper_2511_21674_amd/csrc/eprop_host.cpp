@@ -422,33 +422,55 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     }
     n->n_ach = (uint32_t)(ach.size() / 3);
     first[KT] = n->n_ach;
+    // and each synapse's place in its block's source-major segments (the
+    // segments of the block's sources into the tile, concatenated in source
+    // order), so that the update reads 2 bytes instead of the synapse's
+    // source and source-major position
     std::vector<uint32_t> trs((size_t)n->n_ach * TS, 0u);
+    std::vector<uint16_t> loc(n->S, 0u);
     parallel_ranges(KT, nt, flat, [&](uint64_t k0, uint64_t k1, unsigned) {
-      std::vector<uint32_t> cur(TS);
+      std::vector<uint32_t> cur(TS), pre, seg0;
       for (uint64_t k = k0; k < k1; ++k) {
         for (uint32_t t = 0; t < TS; ++t) {
           const uint64_t j = k * TS + t;
           cur[t] = j < n->J ? tm_ptr[j] : 0u;
         }
         for (uint32_t c = first[k]; c < first[k + 1]; ++c) {
-          const uint32_t s1 = ach[3 * (size_t)c + 2];
+          const uint32_t s0 = ach[3 * (size_t)c + 1], s1 = ach[3 * (size_t)c + 2];
+          pre.assign(s1 - s0, 0u);
+          seg0.assign(s1 - s0, 0u);
+          uint32_t run = 0;
+          for (uint32_t i = 0; i < s1 - s0; ++i) {
+            const uint32_t *ts = tseg.data() + (size_t)(s0 + i) * (KT + 1) + k;
+            pre[i] = run;
+            seg0[i] = ts[0];
+            run += ts[1] - ts[0];
+          }
           for (uint32_t t = 0; t < TS; ++t) {
             const uint64_t j = k * TS + t;
             trs[(size_t)c * TS + t] = cur[t];
             if (j >= n->J) continue;
-            while (cur[t] < tm_ptr[j + 1] && (tm_syn[cur[t]] & 0xFFFFFFu) < s1) ++cur[t];
+            for (; cur[t] < tm_ptr[j + 1]; ++cur[t]) {
+              const uint32_t q = cur[t], src = tm_syn[q] & 0xFFFFFFu;
+              if (src >= s1) break;
+              loc[q] = (uint16_t)(pre[src - s0] + (tm_perm[q] - seg0[src - s0]));
+            }
           }
         }
       }
     });
     uint32_t *pa = nullptr, *pt = nullptr;
+    uint16_t *pl = nullptr;
     if (n->n_ach) {
-      if (!dalloc(n, &pa, ach.size()) || !dalloc(n, &pt, trs.size())) return hipErrorOutOfMemory;
+      if (!dalloc(n, &pa, ach.size()) || !dalloc(n, &pt, trs.size()) || !dalloc(n, &pl, loc.size()))
+        return hipErrorOutOfMemory;
       cp(pa, ach.data(), ach.size() * 4);
       cp(pt, trs.data(), trs.size() * 4);
+      cp(pl, loc.data(), loc.size() * 2);
     }
     d.ach = pa;
     d.trs = pt;
+    d.tm_loc = pl;
     if (e == hipSuccess) e = hipMemset(d.tsum, 0, (size_t)n->Jp * 8);
   }
   { auto o = conv(beta); cp((void *)d.beta_j, o.data(), o.size() * sizeof(real)); }

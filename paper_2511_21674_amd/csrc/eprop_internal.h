@@ -107,6 +107,7 @@ struct DevNet {
   real *gs, *gc, *adam_m, *adam_v;
   const uint32_t *ach;          // blocked update: blocks (tile, first source, end source)
   const uint32_t *trs;          // blocked update: [n_ach][TS] start of each target's run
+  const uint16_t *tm_loc;       // blocked update: [S] each synapse's place in its block's source-major segments
   unsigned long long *tsum;     // blocked update: [Jp] per-target sum of |w| * kBoundScale
   const real *beta_j;           // beta_a for ALIF neurons, 0 for LIF [Jp]
   int32_t any_alif;             // some beta_j is nonzero

@@ -1810,10 +1810,8 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
       }
       const uint32_t q = tr0[a] + (i - tpre[a]);
       const double G = ((double)n.gs[q] + (double)n.gc[q]) / n_trials;
-      const uint32_t p = n.tm_perm[q];
-      const uint32_t src = (n.tm_syn[q] & 0xFFFFFFu) - s0;
-      const uint32_t local = pre[src] + (p - seg0[src]);
-      if (src < nsrc && local < total) gbuf[local] = (real)G;
+      const uint32_t local = n.tm_loc[q];  // its place in the block's segments (built at create)
+      if (local < total) gbuf[local] = (real)G;
     }
   }
   __syncthreads();
