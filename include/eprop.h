@@ -127,7 +127,8 @@ typedef enum { EPROP_DELIVERY_AUTO = 0, EPROP_DELIVERY_SCATTER = 1, EPROP_DELIVE
 #define EPROP_AUTOTUNE (1u << 3)        /* the first training batch times the candidate launch shapes
                                            (delivery variant and steps per forward launch, adjoint and
                                            synapse block sizes, the synapse kernel's prefetch of spike
-                                           records) on the batch itself and keeps the
+                                           records and synapses per thread at a time) on the batch
+                                           itself and keeps the
                                            fastest; results do not depend on the choice */
 
 /* Optional device allocator, e.g. a framework's caching allocator: every
@@ -350,7 +351,7 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18,     /* uint64 [14]: neurons per tile, tiles per trial, bytes per
+  EPROP_STATE_LAYOUT = 18,     /* uint64 [15]: neurons per tile, tiles per trial, bytes per
                                   delay-ring entry (8: 64-bit fixed point in FP32 or double in
                                   FP64, 4: 32-bit fixed point in FP32), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
@@ -358,7 +359,8 @@ typedef enum {
                                   piece, pieces in flight per lane group, adjoint-kernel
                                   threads, autotuned (0/1), entries of a tile's delivery piece
                                   table, spike-index blocks the synapse kernel loads with a
-                                  record's header */
+                                  record's header, synapses a synapse-kernel thread takes at
+                                  a time */
   EPROP_STATE_L = 19,          /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
   EPROP_STATE_INPUT_BOUND = 20 /* double [1]: the bound on |input current| of one step used to

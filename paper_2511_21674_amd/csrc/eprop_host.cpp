@@ -712,7 +712,7 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
   n->shapes.block = 256;
   n->shapes.fwd_variant = 0;
   n->shapes.adj_block = cfg->n_out > 16 ? 64 : 256;
-  n->shapes.syn_pre = 5;
+  n->shapes.syn_var = 0;
   n->autotune_pending = (cfg->flags & EPROP_AUTOTUNE) != 0;
   {
     // synapse kernel: a block per (target, chunk of trials); the chunk's
@@ -1258,19 +1258,19 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
         };
         keep();
         float best = 1e30f;
-        uint32_t bsb = n->shapes.syn_block, bpre = n->shapes.syn_pre;
-        for (uint32_t pre : {1u, 2u, 5u})
+        uint32_t bsb = n->shapes.syn_block, bvar = n->shapes.syn_var;
+        for (uint32_t var = 0; var < eprop::kNumSynVariants; ++var)
           for (uint32_t sb : {64u, 128u, 256u}) {
             n->shapes.syn_block = sb;
-            n->shapes.syn_pre = pre;
+            n->shapes.syn_var = var;
             const float ms = timed(back, [&] {
               Launch<real>::synapse(d, n->shapes, ntr, static_cast<real *>(n->partial), s);
             });
-            if (ms < best) { best = ms; bsb = sb; bpre = pre; }
+            if (ms < best) { best = ms; bsb = sb; bvar = var; }
           }
         back();
         n->shapes.syn_block = bsb;
-        n->shapes.syn_pre = bpre;
+        n->shapes.syn_var = bvar;
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         release(n, save);
       }
@@ -1624,10 +1624,11 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   const bool per_trial = (what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V) || what == EPROP_STATE_L;
   if (what < 0 || what > EPROP_STATE_INPUT_BOUND) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
-    const uint64_t lay[14] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
+    const uint64_t lay[15] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                               n->blk, n->gather ? 1u : 0u, eprop::fwd_variant_piece(n->shapes.fwd_variant),
                               eprop::fwd_variant_unroll(n->shapes.fwd_variant), n->shapes.adj_block,
-                              n->tuned ? 1u : 0u, d.ptab_cap, n->shapes.syn_pre};
+                              n->tuned ? 1u : 0u, d.ptab_cap, eprop::syn_variant_pre(n->shapes.syn_var),
+                              eprop::syn_variant_batch(n->shapes.syn_var)};
     if (needed) *needed = sizeof(lay);
     if (!dst) return EPROP_OK;
     if (dst_bytes < sizeof(lay)) return EPROP_ERR_INVALID_ARGUMENT;

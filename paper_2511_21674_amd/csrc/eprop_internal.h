@@ -197,10 +197,13 @@ struct Shapes {
   uint32_t ginst;               // trials per block of the synapse kernel
   uint32_t fwd_variant;         // delivery variant of the forward kernel (piece size, pieces in flight)
   uint32_t adj_block;           // threads per block of the adjoint kernel (64, 128 or 256)
-  uint32_t syn_pre;             // synapse kernel: spike-index blocks loaded with a record's header (1, 2 or 5)
+  uint32_t syn_var;             // synapse kernel variant: header prefetch and synapses per thread at a time
 };
 uint32_t fwd_variant_piece(uint32_t v);
 uint32_t fwd_variant_unroll(uint32_t v);
+uint32_t syn_variant_pre(uint32_t v);
+uint32_t syn_variant_batch(uint32_t v);
+constexpr uint32_t kNumSynVariants = 6;
 constexpr uint32_t kNumFwdVariants = 4;
 
 template <typename real>

@@ -1129,7 +1129,15 @@ __device__ inline void add_block(uint4 v, const real *base, real &s, real &c) {
   for (uint32_t e = 0; e < 8; ++e) kahan_add(s, c, base[(w4[e >> 1] >> ((e & 1u) * 16u)) & 0xFFFFu]);
 }
 
-template <typename real, uint32_t PRE>
+// Synapse-kernel variants: spike-index blocks loaded with a record's header
+// (PRE) and synapses a thread takes at a time (B), whose loads are all
+// issued before any of their gradient stores (vector memory operations
+// complete in order, so a load issued after a store waits for it).
+constexpr uint32_t kSynVariants = 6;
+__host__ __device__ constexpr uint32_t syn_pre_of(uint32_t v) { return v == 0 ? 5u : v == 2 || v == 4 ? 2u : 1u; }
+__host__ __device__ constexpr uint32_t syn_batch_of(uint32_t v) { return v == 3 ? 4u : v == 4 || v == 5 ? 2u : 1u; }
+
+template <typename real, uint32_t PRE, uint32_t B>
 __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst, uint32_t nchunk, real *partial) {
   constexpr uint32_t GB = 8;
   extern __shared__ __align__(16) unsigned char syn_smem[];
@@ -1159,35 +1167,59 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
   const uint4 *pk4 = reinterpret_cast<const uint4 *>(n.pk);
   const uint32_t *poff = n.pk_off + (size_t)c * n.NS;
   const uint32_t q1 = n.tm_ptr[j + 1];
-  for (uint32_t q = n.tm_ptr[j] + tid; q < q1; q += blockDim.x) {
-    const uint32_t pk = n.tm_syn[q];
-    const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
-    const uint32_t o = poff[src];
-    real s = 0, cc = 0;
-    if (o != kNoRecord) {
-      // the table has slack beyond its last record, so these loads stay in bounds
-      const uint4 *rec = pk4 + o;
-      uint4 pre[PRE + 1];
+  for (uint32_t q0 = n.tm_ptr[j] + tid; q0 < q1; q0 += B * blockDim.x) {
+    // loads of the thread's B synapses, level by level, from valid addresses
+    // (a synapse beyond the row reads synapse q0; a source without a record
+    // reads record 0: the table has slack beyond its last record, so every
+    // header load stays in bounds)
+    uint32_t pkv[B], ov[B];
 #pragma unroll
-      for (uint32_t u = 0; u <= PRE; ++u) pre[u] = rec[u];
-      const uint4 h = pre[0];
-      const uint32_t total = (h.x & 0xFFFFu) + (h.x >> 16) + (h.y & 0xFFFFu) + (h.y >> 16) + (h.z & 0xFFFFu) +
-                             (h.z >> 16) + (h.w & 0xFFFFu) + (h.w >> 16);
-      const uint32_t nbk = (total + 7u) >> 3;
-      const real *base = phl + D;
-#pragma unroll
-      for (uint32_t u = 0; u < PRE; ++u)
-        if (u < nbk) add_block(pre[u + 1], base, s, cc);
-      for (uint32_t u = PRE; u < nbk; ++u) add_block(rec[u + 1], base, s, cc);
+    for (uint32_t u = 0; u < B; ++u) {
+      const uint32_t q = q0 + u * blockDim.x;
+      pkv[u] = n.tm_syn[q < q1 ? q : q0];
     }
+#pragma unroll
+    for (uint32_t u = 0; u < B; ++u) ov[u] = q0 + u * blockDim.x < q1 ? poff[pkv[u] & 0xFFFFFFu] : kNoRecord;
+    uint4 pre[B][PRE + 1];
+#pragma unroll
+    for (uint32_t u = 0; u < B; ++u) {
+      const uint4 *rec = pk4 + (ov[u] != kNoRecord ? ov[u] : 0u);
+#pragma unroll
+      for (uint32_t v = 0; v <= PRE; ++v) pre[u][v] = rec[v];
+    }
+    real gsv[B], gcv[B];
     if (nchunk == 1) {
-      real gs = n.gs[q], gc = n.gc[q];
-      kahan_add(gs, gc, s);
-      kahan_add(gs, gc, cc);
-      n.gs[q] = gs;
-      n.gc[q] = gc;
-    } else {
-      partial[(size_t)c * n.S + q] = s + cc;
+#pragma unroll
+      for (uint32_t u = 0; u < B; ++u) {
+        const uint32_t q = q0 + u * blockDim.x, qs = q < q1 ? q : q0;
+        gsv[u] = n.gs[qs];
+        gcv[u] = n.gc[qs];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < B; ++u) {
+      const uint32_t q = q0 + u * blockDim.x;
+      if (q >= q1) break;
+      real s = 0, cc = 0;
+      if (ov[u] != kNoRecord) {
+        const uint4 h = pre[u][0];
+        const uint32_t total = (h.x & 0xFFFFu) + (h.x >> 16) + (h.y & 0xFFFFu) + (h.y >> 16) + (h.z & 0xFFFFu) +
+                               (h.z >> 16) + (h.w & 0xFFFFu) + (h.w >> 16);
+        const uint32_t nbk = (total + 7u) >> 3;
+        const real *base = phl + (pkv[u] >> 24);
+#pragma unroll
+        for (uint32_t v = 0; v < PRE; ++v)
+          if (v < nbk) add_block(pre[u][v + 1], base, s, cc);
+        for (uint32_t v = PRE; v < nbk; ++v) add_block(pk4[ov[u] + v + 1], base, s, cc);
+      }
+      if (nchunk == 1) {
+        kahan_add(gsv[u], gcv[u], s);
+        kahan_add(gsv[u], gcv[u], cc);
+        n.gs[q] = gsv[u];
+        n.gc[q] = gcv[u];
+      } else {
+        partial[(size_t)c * n.S + q] = s + cc;
+      }
     }
   }
 }
@@ -2019,10 +2051,14 @@ void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_t
   k_pack_scan_blocks<real><<<1, 1024, 0, s>>>(n, nblk);
   k_pack_fill<real><<<cdiv(N, 256), 256, 0, s>>>(n, sh.ginst, N);
   const size_t smem = ((size_t)sh.ginst * n.Ts + n.R) * sizeof(real);
-  switch (sh.syn_pre) {
-    case 1: k_synapse<real, 1><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
-    case 2: k_synapse<real, 2><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
-    default: k_synapse<real, 5><<<n.J * nchunk, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+  const dim3 grid(n.J * nchunk);
+  switch (sh.syn_var) {
+    case 1: k_synapse<real, syn_pre_of(1), syn_batch_of(1)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    case 2: k_synapse<real, syn_pre_of(2), syn_batch_of(2)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    case 3: k_synapse<real, syn_pre_of(3), syn_batch_of(3)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    case 4: k_synapse<real, syn_pre_of(4), syn_batch_of(4)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    case 5: k_synapse<real, syn_pre_of(5), syn_batch_of(5)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    default: k_synapse<real, syn_pre_of(0), syn_batch_of(0)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
   }
   if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
 }
@@ -2119,6 +2155,9 @@ void Launch<real>::input_bound(const DevNet<real> &n, hipStream_t s) {
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s) { k_advance<<<1, 64, 0, s>>>(ctl, by); }
 
 uint32_t fwd_variant_piece(uint32_t v) { return fwd_piece(v); }
+uint32_t syn_variant_pre(uint32_t v) { return syn_pre_of(v); }
+uint32_t syn_variant_batch(uint32_t v) { return syn_batch_of(v); }
+static_assert(kNumSynVariants == kSynVariants, "synapse variant count");
 uint32_t fwd_variant_unroll(uint32_t v) { return fwd_unroll(v); }
 static_assert(kNumFwdVariants == kFwdVariants, "variant count");
 
