@@ -203,7 +203,7 @@ uint32_t fwd_variant_piece(uint32_t v);
 uint32_t fwd_variant_unroll(uint32_t v);
 uint32_t syn_variant_pre(uint32_t v);
 uint32_t syn_variant_batch(uint32_t v);
-constexpr uint32_t kNumSynVariants = 6;
+constexpr uint32_t kNumSynVariants = 7;
 constexpr uint32_t kNumFwdVariants = 4;
 
 template <typename real>

@@ -1133,9 +1133,11 @@ __device__ inline void add_block(uint4 v, const real *base, real &s, real &c) {
 // (PRE) and synapses a thread takes at a time (B), whose loads are all
 // issued before any of their gradient stores (vector memory operations
 // complete in order, so a load issued after a store waits for it).
-constexpr uint32_t kSynVariants = 6;
+constexpr uint32_t kSynVariants = 7;
 __host__ __device__ constexpr uint32_t syn_pre_of(uint32_t v) { return v == 0 ? 5u : v == 2 || v == 4 ? 2u : 1u; }
-__host__ __device__ constexpr uint32_t syn_batch_of(uint32_t v) { return v == 3 ? 4u : v == 4 || v == 5 ? 2u : 1u; }
+__host__ __device__ constexpr uint32_t syn_batch_of(uint32_t v) {
+  return v == 6 ? 8u : v == 3 ? 4u : v == 4 || v == 5 ? 2u : 1u;
+}
 
 template <typename real, uint32_t PRE, uint32_t B>
 __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst, uint32_t nchunk, real *partial) {
@@ -2058,6 +2060,7 @@ void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_t
     case 3: k_synapse<real, syn_pre_of(3), syn_batch_of(3)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
     case 4: k_synapse<real, syn_pre_of(4), syn_batch_of(4)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
     case 5: k_synapse<real, syn_pre_of(5), syn_batch_of(5)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
+    case 6: k_synapse<real, syn_pre_of(6), syn_batch_of(6)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
     default: k_synapse<real, syn_pre_of(0), syn_batch_of(0)><<<grid, sh.syn_block, smem, s>>>(n, sh.ginst, nchunk, partial); break;
   }
   if (nchunk > 1) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
