@@ -1849,38 +1849,68 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
     }
   }
   __syncthreads();
-  // source-major side: update the records segment by segment
-  for (uint32_t i = tid; i < total; i += NT) {
-    uint32_t a = 0, b = nsrc;  // pre[a] <= i < pre[b]
-    while (b - a > 1) {
-      const uint32_t m = (a + b) >> 1;
-      if (pre[m] <= i) a = m; else b = m;
-    }
-    const uint32_t q = seg0[a] + (i - pre[a]);
-    const SynRec<real> rec = n.sm[q];
-    double w = (double)rec.w;
-    if constexpr (UPDATE) {
-      const double G = (double)gbuf[i];
-      double m = 0.0, v = 0.0;
-      if (opt == 1) {
-        m = (double)n.adam_m[q];
-        v = (double)n.adam_v[q];
+  // source-major side: update the records segment by segment, BU elements
+  // per thread at a time with all their loads issued before their stores
+  // (vector memory operations complete in order, so a load issued after a
+  // store waits for it); an element beyond the block repeats element i0's
+  // address and is not written
+  constexpr uint32_t BU = 4;
+  for (uint32_t i0 = tid; i0 < total; i0 += BU * NT) {
+    uint32_t qv[BU];
+#pragma unroll
+    for (uint32_t u = 0; u < BU; ++u) {
+      const uint32_t i = min(i0 + u * NT, total - 1);
+      uint32_t a = 0, b = nsrc;  // pre[a] <= i < pre[b]
+      while (b - a > 1) {
+        const uint32_t m = (a + b) >> 1;
+        if (pre[m] <= i) a = m; else b = m;
       }
-      opt_step(w, G, opt, eta, eta_t, b1, b2, eps, m, v);
-      if (opt == 1) {
-        n.adam_m[q] = (real)m;
-        n.adam_v[q] = (real)v;
-      }
-      const real wr = (real)w;
-      n.sm[q].w = wr;
-      w = (double)wr;
+      qv[u] = i0 + u * NT < total ? seg0[a] + (i - pre[a]) : 0u;
     }
-    const uint32_t t = (rec.syn & 0xFFFFFFu) - j0;
-    const double aw = fabs(w);
-    if (aw < kBoundMaxW) {
-      atomicAdd(&tsl[t], (unsigned long long)ceil(aw * kBoundScale));
-    } else {
-      atomicOr(&n.tsum[j0 + t], 1ull << 63);  // saturated: reported as an out-of-range bound
+#pragma unroll
+    for (uint32_t u = 1; u < BU; ++u)
+      if (i0 + u * NT >= total) qv[u] = qv[0];
+    SynRec<real> rv[BU];
+    real mv[BU], vv[BU];
+#pragma unroll
+    for (uint32_t u = 0; u < BU; ++u) rv[u] = n.sm[qv[u]];
+    if (UPDATE && opt == 1) {
+#pragma unroll
+      for (uint32_t u = 0; u < BU; ++u) {
+        mv[u] = n.adam_m[qv[u]];
+        vv[u] = n.adam_v[qv[u]];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < BU; ++u) {
+      const uint32_t i = i0 + u * NT;
+      if (i >= total) break;
+      const uint32_t q = qv[u];
+      SynRec<real> rec = rv[u];
+      double w = (double)rec.w;
+      if constexpr (UPDATE) {
+        const double G = (double)gbuf[i];
+        double m = 0.0, v = 0.0;
+        if (opt == 1) {
+          m = (double)mv[u];
+          v = (double)vv[u];
+        }
+        opt_step(w, G, opt, eta, eta_t, b1, b2, eps, m, v);
+        if (opt == 1) {
+          n.adam_m[q] = (real)m;
+          n.adam_v[q] = (real)v;
+        }
+        rec.w = (real)w;
+        n.sm[q] = rec;  // the whole record: full lines rather than masked half-records
+        w = (double)rec.w;
+      }
+      const uint32_t t = (rec.syn & 0xFFFFFFu) - j0;
+      const double aw = fabs(w);
+      if (aw < kBoundMaxW) {
+        atomicAdd(&tsl[t], (unsigned long long)ceil(aw * kBoundScale));
+      } else {
+        atomicOr(&n.tsum[j0 + t], 1ull << 63);  // saturated: reported as an out-of-range bound
+      }
     }
   }
   __syncthreads();
