@@ -1219,6 +1219,9 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   if (prof) (void)hipEventRecord(n->ev[2], s);
   Launch<real>::readout(d, s);
   if (prof) (void)hipEventRecord(n->ev[3], s);
+  // the gradient pairs hold nothing yet after an update (or at start): the
+  // gradient kernels then write them instead of adding to stale contents
+  d.g_fresh = n->trials_accum == 0 ? 1 : 0;
   if (time_driven) {
     Launch<real>::time_driven(d, n->shapes, ntr, static_cast<real *>(n->Lbuf), static_cast<real *>(n->partial), s);
     if (prof) (void)hipEventRecord(n->ev[4], s);
@@ -1681,6 +1684,10 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
       if ((what >= EPROP_STATE_ADAM_M_IN) && !n->adam) { outd.assign(cnt, 0.0); break; }
       std::vector<real> a, c;
       if (what == EPROP_STATE_GRAD_IN || what == EPROP_STATE_GRAD_REC) {
+        if (n->trials_accum == 0) {  // nothing accumulated since the last update
+          outd.assign(cnt, 0.0);
+          break;
+        }
         e = fetch(d.gs, n->S, a);
         if (e == hipSuccess) e = fetch(d.gc, n->S, c);
       } else {

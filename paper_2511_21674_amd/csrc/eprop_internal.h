@@ -105,6 +105,7 @@ struct DevNet {
   const uint32_t *tm_ptr, *tm_syn, *tm_perm;
   real *tm_w;                   // target-major weights (gather delivery only)
   real *gs, *gc, *adam_m, *adam_v;
+  int32_t g_fresh;              // no trial accumulated since the last update: gradient kernels write gs/gc, not add
   const uint32_t *ach;          // blocked update: blocks (tile, first source, end source)
   const uint32_t *trs;          // blocked update: [n_ach][TS] start of each target's run
   const uint16_t *tm_loc;       // blocked update: [S] each synapse's place in its block's source-major segments

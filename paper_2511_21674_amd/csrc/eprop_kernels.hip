@@ -1194,8 +1194,8 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
 #pragma unroll
       for (uint32_t u = 0; u < B; ++u) {
         const uint32_t q = q0 + u * blockDim.x, qs = q < q1 ? q : q0;
-        gsv[u] = n.gs[qs];
-        gcv[u] = n.gc[qs];
+        gsv[u] = n.g_fresh ? (real)0 : n.gs[qs];
+        gcv[u] = n.g_fresh ? (real)0 : n.gc[qs];
       }
     }
 #pragma unroll
@@ -1323,7 +1323,7 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
       nfl += arrivals ? 1u : 0u;
     }
     if (nchunk == 1) {
-      real gs = n.gs[q], gc = n.gc[q];
+      real gs = n.g_fresh ? (real)0 : n.gs[q], gc = n.g_fresh ? (real)0 : n.gc[q];
       kahan_add(gs, gc, s);
       kahan_add(gs, gc, cc);
       n.gs[q] = gs;
@@ -1661,7 +1661,7 @@ __global__ __launch_bounds__(256) void k_online_readout(DevNet<real> n, OnlineRu
 template <typename real>
 __global__ __launch_bounds__(256) void k_synapse_reduce(DevNet<real> n, uint32_t nchunk, const real *partial) {
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n.S; q += (uint64_t)gridDim.x * blockDim.x) {
-    real gs = n.gs[q], gc = n.gc[q];
+    real gs = n.g_fresh ? (real)0 : n.gs[q], gc = n.g_fresh ? (real)0 : n.gc[q];
     for (uint32_t c = 0; c < nchunk; ++c) kahan_add(gs, gc, partial[(size_t)c * n.S + q]);
     n.gs[q] = gs;
     n.gc[q] = gc;
@@ -2145,11 +2145,10 @@ static void launch_apply_blk(const DevNet<real> &n, uint32_t n_ach, bool update,
 template <typename real>
 void Launch<real>::apply_blocked(const DevNet<real> &n, uint32_t n_ach, uint64_t S, double n_trials, int opt,
                                  double eta, double eta_t, double b1, double b2, double eps, hipStream_t s) {
+  // (the gradient pairs are not cleared: the first training batch after an
+  // update writes them instead of adding to them, see g_fresh)
+  (void)S;
   launch_apply_blk(n, n_ach, true, n_trials, opt, eta, eta_t, b1, b2, eps, s);
-  if (S) {
-    (void)hipMemsetAsync(n.gs, 0, S * sizeof(real), s);
-    (void)hipMemsetAsync(n.gc, 0, S * sizeof(real), s);
-  }
   k_apply_out<real><<<grid_for((uint64_t)n.K * n.Jp, 256, 2048), 256, 0, s>>>(n, n_trials, opt, eta, eta_t, b1, b2, eps);
 }
 
