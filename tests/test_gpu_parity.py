@@ -451,6 +451,33 @@ def test_fp32_multi_tile_runs_are_deterministic():
         assert np.array_equal(runs[0][1][k], runs[1][1][k])
 
 
+def test_gradients_restart_after_an_update():
+    """After an update the accumulated gradient reads as zero, and the next
+    training batch's gradient is that batch's alone (the first batch after an
+    update writes the gradient pairs instead of adding to them): checked
+    against the time-driven gradient of the same batch on the same updated
+    weights, in the blocked-update layout."""
+    wl = W.c4_sparse(n_rec=3000, n_steps=300, batch_size=2, n_in=300)
+    b0, b1 = wl.make_batch(0, 0, 2), wl.make_batch(1, 0, 2)
+    grads = []
+    for time_driven in (False, True):
+        net = E.Network(wl.network, "fp32", max_trials=2, max_steps=300)
+        net.simulate(b0)
+        g0 = net.grads()
+        assert all(np.abs(g0[k]).max() > 0 for k in KEYS)
+        net.apply()
+        gz = net.grads()
+        for k in ("w_in", "w_rec"):
+            assert not np.any(gz[k]), k
+        net.simulate(b1, time_driven=time_driven)
+        grads.append(net.grads())
+        net.close()
+    for k in ("w_in", "w_rec"):
+        ok, e, ent = rel_close(grads[0][k], grads[1][k], 1e-4, floor_frac=1e-2)
+        log(f"restart {k}: normwise {e:.2e} worst {ent:.2e}")
+        assert ok, (k, e, ent)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_autotuner_changes_shapes_not_results(precision):
     """With EPROP_AUTOTUNE the first training batch times the candidate
