@@ -282,7 +282,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (the tuner otherwise runs in the first warm-up batch)")
     ap.add_argument("--cpu-steps", type=int, default=None,
-                    help="steps of the CPU oracle's sample on large networks (default 60; 5 for the scaling network)")
+                    help="steps of the CPU oracle's sample on large networks (default 40; 5 for the scaling network)")
     ap.add_argument("--fp64-iters", type=int, default=1,
                     help="training iterations of the FP64 plain comparison (<= warmup + steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -315,7 +315,7 @@ def main():
     if args.steps is None:
         args.steps = 20 if scaling else 5
     if args.cpu_steps is None:
-        args.cpu_steps = 5 if scaling else 60
+        args.cpu_steps = 5 if scaling else 40
     if scaling:
         # the FP64 plain comparison would rebuild the 1.28e9-synapse network in
         # double; the scaling runs compare static and plastic synapses instead
