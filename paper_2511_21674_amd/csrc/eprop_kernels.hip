@@ -1835,17 +1835,36 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
     }
     if (tid == 0) tpre[TS] = ttot;
     __syncthreads();
-    // gradients in target-major runs -> LDS in the block's source-major order
-    for (uint32_t i = tid; i < ttot; i += NT) {
-      uint32_t a = 0, b = TS;  // tpre[a] <= i < tpre[b]
-      while (b - a > 1) {
-        const uint32_t m = (a + b) >> 1;
-        if (tpre[m] <= i) a = m; else b = m;
+    // gradients in target-major runs -> LDS in the block's source-major
+    // order, GB elements per thread at a time so that their loads are in
+    // flight together (an element beyond the runs repeats element i0)
+    constexpr uint32_t GB = 8;
+    for (uint32_t i0 = tid; i0 < ttot; i0 += GB * NT) {
+      uint32_t qv[GB];
+#pragma unroll
+      for (uint32_t u = 0; u < GB; ++u) {
+        const uint32_t i = min(i0 + u * NT, ttot - 1);
+        uint32_t a = 0, b = TS;  // tpre[a] <= i < tpre[b]
+        while (b - a > 1) {
+          const uint32_t m = (a + b) >> 1;
+          if (tpre[m] <= i) a = m; else b = m;
+        }
+        qv[u] = tr0[a] + (i - tpre[a]);
       }
-      const uint32_t q = tr0[a] + (i - tpre[a]);
-      const double G = ((double)n.gs[q] + (double)n.gc[q]) / n_trials;
-      const uint32_t local = n.tm_loc[q];  // its place in the block's segments (built at create)
-      if (local < total) gbuf[local] = (real)G;
+      real gsv[GB], gcv[GB];
+      uint16_t lv[GB];
+#pragma unroll
+      for (uint32_t u = 0; u < GB; ++u) {
+        gsv[u] = n.gs[qv[u]];
+        gcv[u] = n.gc[qv[u]];
+        lv[u] = n.tm_loc[qv[u]];  // its place in the block's segments (built at create)
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < GB; ++u) {
+        const uint32_t local = lv[u];
+        if (i0 + u * NT < ttot && local < total)
+          gbuf[local] = (real)(((double)gsv[u] + (double)gcv[u]) / n_trials);
+      }
     }
   }
   __syncthreads();
