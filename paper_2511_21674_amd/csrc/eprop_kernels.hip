@@ -9,7 +9,8 @@
 //                                      eq. spike-threshold-adaptation, surrogate)
 //                           (k_forward_tiled: persistent, tiles of targets with
 //                            LDS delay rings; k_neuron_gather: deterministic)
-//   after the sample        k_readout_sums, k_readout_scan (eq. leaky_integrator,
+//   after the sample        k_stage_rec_lists (spike-time lists from the bitsets),
+//                           k_readout_sums, k_readout_scan (eq. leaky_integrator,
 //                                      error signal, loss; backward filter of E)
 //                           k_adjoint (per-neuron arrival archive phi)
 //                           k_synapse (event-driven synapse gradient)
@@ -416,7 +417,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
           if (tpre[mid] <= r) lk = mid; else hk = mid;
         }
         const uint32_t pos = r - tpre[lk];
-        // parked entries are valid in the first chunk only (the owner array is reused after it)
+        // parked entries are valid in the first chunk only (the piece table is reused after it)
         uint32_t j = base == 0 && pos < E ? spec[lk * E + pos] : kNoEntry;
         if (j == kNoEntry) j = wait_tag(pl + (size_t)lk * n.TS + pos, t, &n.ctl[CTL_ERR]);
         src[u] = n.I + min(j, n.J - 1u);
