@@ -64,6 +64,18 @@ def forward_bytes(c, net):
             + c["neuron_steps"] * (B_FWD_NEURON_LIF + frac_alif * (B_FWD_NEURON_ALIF - B_FWD_NEURON_LIF)))
 
 
+def kernel_code_hash(path):
+    """SHA-256 of a kernel source with its comments and blank space removed,
+    so that the record of a measurement survives comment-only edits."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    code = "\n".join(line.strip() for line in text.splitlines() if line.strip())
+    return hashlib.sha256(code.encode()).hexdigest()
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
     counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
@@ -81,7 +93,7 @@ def measured_traffic(workload, kernel):
             rec[k] = v
     if not rec.get("kernel", "").startswith(kernel):
         return None
-    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if rec.get("kernel_code_sha256") != kernel_code_hash(src):
         return None
     return (float(rec["fetch_kib_per_dispatch"]) * float(rec["copy_fetch_factor"])
             + float(rec["write_kib_per_dispatch"]) * float(rec["copy_write_factor"])) * 1024.0
