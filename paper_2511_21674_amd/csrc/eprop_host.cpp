@@ -764,7 +764,7 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
     const uint32_t cu = std::max(1, prop.multiProcessorCount);
     const uint32_t want = std::max<uint32_t>(1, cu / n->Bcap);
     uint32_t ts_par = round_up((J + want - 1) / want, 64);
-    ts_par = std::max<uint32_t>(ts_par, std::min<uint32_t>(n->Jp, 1024));
+    ts_par = std::max<uint32_t>(ts_par, std::min<uint32_t>(n->Jp, 512));
     ts_par = std::min(ts_par, n->Jp);
     // FP32: exact 64-bit fixed-point ring unless it would force more tiles
     // than the device spreads the trials over; then 32-bit entries
