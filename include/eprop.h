@@ -339,7 +339,8 @@ typedef enum {
   EPROP_STATE_W_IN = 0,      /* double [nnz_in], caller's synapse order */
   EPROP_STATE_W_REC = 1,     /* double [nnz_rec] */
   EPROP_STATE_W_OUT = 2,     /* double [K*J] */
-  EPROP_STATE_GRAD_IN = 3,   /* double, accumulated gradient sums (not yet averaged) */
+  EPROP_STATE_GRAD_IN = 3,   /* double, accumulated gradient sums (not yet averaged) of the
+                                trials trained since the last eprop_apply_updates (zeros if none) */
   EPROP_STATE_GRAD_REC = 4,
   EPROP_STATE_GRAD_OUT = 5,
   EPROP_STATE_ADAM_M_IN = 6, EPROP_STATE_ADAM_V_IN = 7,
