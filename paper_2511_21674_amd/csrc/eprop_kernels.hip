@@ -872,7 +872,6 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
                                 ((double)n.spk_cnt[(size_t)b * n.NS + n.I + j] / (double)T - n.f_target)
                           : 0.0;
   const int64_t u_reg = (int64_t)T - n.d_out;
-  const real *ps_col = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
   const uint32_t wbase = tid & ~63u, lane = tid & 63u;
   const uint32_t c = live ? n.spk_cnt[(size_t)b * n.NS + n.I + j] : 0u;
   const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
