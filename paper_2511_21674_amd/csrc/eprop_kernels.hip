@@ -330,6 +330,23 @@ __device__ inline float ring_value(int32_t x, const RingScale &sc) { return (flo
 __device__ inline float ring_value(int64_t x, const RingScale &sc) { return (float)x * sc.from_fix; }
 __device__ inline double ring_value(double x, const RingScale &) { return x; }
 
+// Position of the r-th set bit of m (r < popcount(m)).
+__device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+  uint32_t pos = 0;
+  for (uint32_t w = 32; w > 0; w >>= 1) {
+    const uint64_t low = m & ((1ull << w) - 1ull);
+    const uint32_t c = (uint32_t)__popcll(low);
+    if (r >= c) {
+      r -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
 // Adds the spikes emitted at step t by inputs and by recurrent neurons of
 // trial b into this tile's LDS ring.  Per chunk of up to 2 * blockDim
 // spiking sources: every thread resolves two sources to their segments (the
@@ -357,7 +374,8 @@ __host__ __device__ constexpr uint32_t fwd_unroll(uint32_t v) { return v == 1 ? 
 template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
-                                    uint2 *ptab, uint32_t *wsum) {
+                                    uint2 *ptab, uint32_t *wsum, const uint64_t *words, const uint32_t *woff,
+                                    uint32_t nw, uint32_t own) {
   __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike counts of step t
   uint32_t *spec = reinterpret_cast<uint32_t *>(ptab);  // [E * KT <= 2 * blockDim] parked list entries
   const uint32_t cap = n.ptab_cap;
@@ -369,7 +387,11 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
   uint32_t n_rec = 0;
   const uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
-  if (t >= 1) {
+  // a single-tile trial takes its own spikes of the step (own of them) from
+  // its LDS bitset words and their exclusive popcount prefix woff
+  const bool local = n.KT == 1;
+  if (t >= 1 && local) n_rec = own;
+  if (t >= 1 && !local) {
     // the first E entries of every tile's list, read ahead of the counts
     uint64_t ahead[2] = {0ull, 0ull};
 #pragma unroll
@@ -411,6 +433,16 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
         src[u] = in_src[in_lo + item];
       } else {
         const uint32_t r = item - n_in;
+        if (local) {  // the r-th spike: word w with woff[w] <= r < woff[w + 1]
+          uint32_t lw = 0, hw = nw;
+          while (hw - lw > 1) {
+            const uint32_t mid = (lw + hw) >> 1;
+            if (woff[mid] <= r) lw = mid; else hw = mid;
+          }
+          const uint32_t jj = j0 + lw * 64 + nth_set_bit(words[lw], r - woff[lw]);
+          src[u] = n.I + min(jj, n.J - 1u);
+          continue;
+        }
         uint32_t lk = 0, hk = n.KT;  // tpre[lk] <= r < tpre[hk]
         while (hk - lk > 1) {
           const uint32_t mid = (lk + hk) >> 1;
@@ -520,7 +552,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile<real, ring_t, P, U>(n, b, k, j0, 0, Tb, ring, sc, ptab, wsum);
+    deliver_tile<real, ring_t, P, U>(n, b, k, j0, 0, Tb, ring, sc, ptab, wsum, words, woff, 0u, 0u);
     __syncthreads();
   }
   const uint32_t t_end = min(t0 + nsteps, Tb);
@@ -559,7 +591,8 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       if (threadIdx.x == 0) gtot = tot;
     }
     __syncthreads();
-    {  // publish the tile's spikes of step t: the entries, then the count
+    if (KT > 1) {  // publish the tile's spikes of step t: the entries, then the count
+      // (a single-tile trial delivers its spikes from its own LDS bitset)
       uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp + j0;
       const uint64_t tag = (uint64_t)t << 32;
       for (uint32_t w = threadIdx.x >> 6; w < nw; w += blockDim.x >> 6) {
@@ -571,7 +604,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       __syncthreads();
       if (threadIdx.x == 0) store_sys(&n.pub_cnt[((size_t)b * 2 + (t & 1u)) * KT + k], tag | gtot);
     }
-    if (t < Tb) deliver_tile<real, ring_t, P, U>(n, b, k, j0, t, Tb, ring, sc, ptab, wsum);
+    if (t < Tb) deliver_tile<real, ring_t, P, U>(n, b, k, j0, t, Tb, ring, sc, ptab, wsum, words, woff, nw, gtot);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -1434,23 +1467,6 @@ __device__ inline real online_update(const DevNet<real> &n, const OnlineRun<real
   const real w = (real)((double)n.tm_w[q] - o.eta * g);
   n.tm_w[q] = w;
   return w;
-}
-
-// Position of the r-th set bit of m (r < popcount(m)).
-__device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
-  uint32_t pos = 0;
-  for (uint32_t w = 32; w > 0; w >>= 1) {
-    const uint64_t low = m & ((1ull << w) - 1ull);
-    const uint32_t c = (uint32_t)__popcll(low);
-    if (r >= c) {
-      r -= c;
-      m >>= w;
-      pos += w;
-    } else {
-      m = low;
-    }
-  }
-  return pos;
 }
 
 // The synapse side of step t: a wavefront per target neuron scans its
