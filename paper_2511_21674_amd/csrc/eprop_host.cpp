@@ -200,7 +200,8 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
     return bad("dt and time constants must be positive and finite");
   if (!is_finite(c->v_th) || !is_finite(c->beta_a) || !is_finite(c->sg_gamma) || !is_finite(c->sg_beta))
     return bad("non-finite neuron or surrogate parameter");
-  if (!(c->t_ref >= 0) || !is_finite(c->t_ref) || std::lround(c->t_ref / c->dt) > 127)
+  // (compared before rounding: lround of a quotient beyond the long range is unspecified)
+  if (!(c->t_ref >= 0) || !is_finite(c->t_ref) || !(c->t_ref / c->dt < 127.5))
     return bad("t_ref must give 0..127 refractory steps");
   if (c->surrogate != EPROP_SG_PIECEWISE_LINEAR && c->surrogate != EPROP_SG_EXPONENTIAL) return bad("unknown surrogate");
   if (c->loss != EPROP_LOSS_MSE && c->loss != EPROP_LOSS_SOFTMAX_CE && c->loss != EPROP_LOSS_TEMPORAL_MSE)

@@ -128,6 +128,7 @@ def _create(cfg, projs, wo, fb):
     ("max_steps", 70000, E.EPROP_ERR_INVALID_ARGUMENT),
     ("max_trials", 0, E.EPROP_ERR_INVALID_ARGUMENT),
     ("t_ref", 500.0, E.EPROP_ERR_INVALID_ARGUMENT),
+    ("t_ref", 1e300, E.EPROP_ERR_INVALID_ARGUMENT),
     ("surrogate", 5, E.EPROP_ERR_INVALID_ARGUMENT),
     ("delivery", 9, E.EPROP_ERR_INVALID_ARGUMENT),
 ])
