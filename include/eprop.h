@@ -37,8 +37,10 @@
  * EPROP_ERR_INVALID_ARGUMENT, EPROP_ERR_CAPACITY or EPROP_ERR_STATE the
  * handle is unchanged.  After EPROP_ERR_DEVICE or EPROP_ERR_NUMERIC the
  * handle is failed: only eprop_read_state, eprop_last_error and
- * eprop_destroy_network remain usable.  eprop_last_error gives the message
- * of the last failure on a handle.
+ * eprop_destroy_network remain usable.  A host allocation or thread start
+ * that fails inside a call returns EPROP_ERR_OUT_OF_MEMORY; inside
+ * eprop_simulate_batch or eprop_apply_updates it also fails the handle.
+ * eprop_last_error gives the message of the last failure on a handle.
  */
 #ifndef EPROP_H
 #define EPROP_H

@@ -10,6 +10,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -113,6 +115,13 @@ struct eprop_network {
 namespace {
 
 void set_fail(eprop_network *n, const std::string &m) { n->err = m; }
+
+// Message for a host-side exception caught at the ABI (allocation or thread
+// creation failed); such a failure is reported as EPROP_ERR_OUT_OF_MEMORY.
+std::string host_failure(const std::exception &x) {
+  if (dynamic_cast<const std::bad_alloc *>(&x)) return "host allocation failed";
+  return std::string("host resource failure: ") + x.what();
+}
 
 void dfree(eprop_network *n, void *p) {
   if (!p) return;
@@ -561,14 +570,13 @@ void eprop_destroy_network(eprop_network *net) {
   delete net;
 }
 
-eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projection *in_rec,
-                                  const eprop_projection *rec_rec, const double *w_out,
-                                  const double *feedback, const eprop_optimizer_state *opt,
-                                  void *hip_stream, eprop_network **out_net) {
-  g_create_error.clear();
+// The body of eprop_create_network; *partial is the handle under
+// construction, for the caller to release if a host allocation throws.
+static eprop_status create_network(const eprop_config *cfg, const eprop_projection *in_rec,
+                                   const eprop_projection *rec_rec, const double *w_out,
+                                   const double *feedback, const eprop_optimizer_state *opt,
+                                   void *hip_stream, eprop_network **out_net, eprop_network **partial) {
   std::string msg;
-  if (!out_net) { g_create_error = "NULL out_net"; return EPROP_ERR_INVALID_ARGUMENT; }
-  *out_net = nullptr;
   eprop_status st = check_config(cfg, msg);
   if (st == EPROP_OK) st = check_projection(in_rec, cfg->n_in, cfg->n_rec, cfg->max_delay, false, "in_rec", msg);
   if (st == EPROP_OK) st = check_projection(rec_rec, cfg->n_rec, cfg->n_rec, cfg->max_delay, true, "rec_rec", msg);
@@ -690,6 +698,7 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
 
   eprop_network *n = new (std::nothrow) eprop_network();
   if (!n) { g_create_error = "host allocation failed"; return EPROP_ERR_OUT_OF_MEMORY; }
+  *partial = n;
   n->cfg = *cfg;
   n->cfg.is_alif = nullptr;
   n->I = I; n->J = J; n->K = cfg->n_out; n->NS = NS;
@@ -860,8 +869,28 @@ eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projectio
     eprop_destroy_network(n);
     return EPROP_ERR_DEVICE;
   }
+  *partial = nullptr;
   *out_net = n;
   return EPROP_OK;
+}
+
+eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projection *in_rec,
+                                  const eprop_projection *rec_rec, const double *w_out,
+                                  const double *feedback, const eprop_optimizer_state *opt,
+                                  void *hip_stream, eprop_network **out_net) {
+  g_create_error.clear();
+  if (!out_net) { g_create_error = "NULL out_net"; return EPROP_ERR_INVALID_ARGUMENT; }
+  *out_net = nullptr;
+  eprop_network *partial = nullptr;
+  try {
+    return create_network(cfg, in_rec, rec_rec, w_out, feedback, opt, hip_stream, out_net, &partial);
+  } catch (const std::exception &x) {
+    g_create_error = host_failure(x);
+  } catch (...) {
+    g_create_error = "host failure";
+  }
+  if (partial) eprop_destroy_network(partial);
+  return EPROP_ERR_OUT_OF_MEMORY;
 }
 
 }  // extern "C"
@@ -1808,9 +1837,19 @@ extern "C" {
 eprop_status eprop_simulate_batch(eprop_network *net, const eprop_batch *batch, eprop_batch_result *res) {
   if (!net || !batch) return EPROP_ERR_INVALID_ARGUMENT;
   if (net->failed) return EPROP_ERR_STATE;
-  if (batch->flags & EPROP_BATCH_ONLINE)
-    return net->fp64 ? simulate_online(net, net->n64, batch, res) : simulate_online(net, net->n32, batch, res);
-  return net->fp64 ? simulate(net, net->n64, batch, res) : simulate(net, net->n32, batch, res);
+  try {
+    if (batch->flags & EPROP_BATCH_ONLINE)
+      return net->fp64 ? simulate_online(net, net->n64, batch, res) : simulate_online(net, net->n32, batch, res);
+    return net->fp64 ? simulate(net, net->n64, batch, res) : simulate(net, net->n32, batch, res);
+  } catch (const std::exception &x) {
+    set_fail(net, host_failure(x));
+  } catch (...) {
+    set_fail(net, "host failure");
+  }
+  // device work of the batch may be half issued: the handle is failed
+  (void)hipStreamSynchronize(net->stream);
+  net->failed = true;
+  return EPROP_ERR_OUT_OF_MEMORY;
 }
 
 eprop_status eprop_apply_updates(eprop_network *net) {
@@ -1820,14 +1859,28 @@ eprop_status eprop_apply_updates(eprop_network *net) {
     set_fail(net, "no trials trained since the last update");
     return EPROP_ERR_STATE;
   }
-  return net->fp64 ? apply(net, net->n64) : apply(net, net->n32);
+  try {
+    return net->fp64 ? apply(net, net->n64) : apply(net, net->n32);
+  } catch (const std::exception &x) {
+    set_fail(net, host_failure(x));
+  } catch (...) {
+    set_fail(net, "host failure");
+  }
+  (void)hipStreamSynchronize(net->stream);
+  net->failed = true;
+  return EPROP_ERR_OUT_OF_MEMORY;
 }
 
 eprop_status eprop_read_state(const eprop_network *net, int32_t what, uint32_t trial, void *dst,
                               size_t dst_bytes, size_t *bytes_needed) {
   if (!net) return EPROP_ERR_INVALID_ARGUMENT;
-  return net->fp64 ? read_state(net, net->n64, what, trial, dst, dst_bytes, bytes_needed)
-                   : read_state(net, net->n32, what, trial, dst, dst_bytes, bytes_needed);
+  try {
+    return net->fp64 ? read_state(net, net->n64, what, trial, dst, dst_bytes, bytes_needed)
+                     : read_state(net, net->n32, what, trial, dst, dst_bytes, bytes_needed);
+  } catch (...) {
+    // (reading changes nothing on the handle; only the host copy failed)
+    return EPROP_ERR_OUT_OF_MEMORY;
+  }
 }
 
 }  // extern "C"
