@@ -126,6 +126,32 @@ MUTATIONS = [
     ("online_lag_one_short", "the most recent learning signal",
      "const int d = net->d_out, lag = 1 + net->d_ls + net->d_out;",
      "const int d = net->d_out, lag = net->d_ls + net->d_out;"),
+    # the brute-force and forward-mode checkers (dual numbers, eq. summation-future)
+    ("dual_drops_threshold_derivative", "eq. pseudo-derivative through the adaptive threshold",
+     "dz[(long)t * J + j] = psi * (v[j].d - A.d);", "dz[(long)t * J + j] = psi * v[j].d;"),
+    ("dual_reset_not_stopped", "e-prop's reset term without a gradient",
+     "dual reset = dstop((dual){zprev.x * A.x, 0.0});", "dual reset = dmul_c(zprev.x, A);"),
+    ("bruteforce_future_filter_lag", "eq. summation-future",
+     "fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa_e, t - d - tp);",
+     "fut += E_rec[(long)(t - 1) * K + k] * pow(p.kappa_e, t - tp);"),
+    ("forward_mode_readout_delay", "eq. leaky_integrator_with_delay",
+     "for (int j = 0; j < J; ++j) s += net->w_out[(long)k * J + j] * dz[(long)(t - net->d_out) * J + j];",
+     "for (int j = 0; j < J; ++j) s += net->w_out[(long)k * J + j] * dz[(long)t * J + j];"),
+    # the sampled teacher-forced path
+    ("sampled_learning_signal_lag", "eq. eprop-approx-final-expanded-subs-rewritten",
+     "if (t + net->d_out <= T - net->d_ls) g += L_h[t + net->d_out] * eb;",
+     "if (t + net->d_out <= T - net->d_ls) g += L_h[t] * eb;"),
+    ("sampled_regulariser_over_T_twice", "Methods, \"Firing rate regularization\"",
+     "const double creg = net->reg_mode == 0 ? net->c_reg / T * (nz / T - net->f_target) : 0.0;",
+     "const double creg = net->reg_mode == 0 ? net->c_reg / T * (nz / T / T - net->f_target) : 0.0;"),
+    ("sampled_moving_rate_unnormalised", "eq. ema-rate",
+     "f = p.beta_f * f + (1.0 - p.beta_f) * (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);\n          gh",
+     "f = p.beta_f * f + (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);\n          gh"),
+    ("sampled_loss_regulariser_without_half", "eq. sma-loss",
+     "if (net->reg_mode == 1) loss += 0.5 * net->c_reg * sf;", "if (net->reg_mode == 1) loss += net->c_reg * sf;"),
+    ("bruteforce_moving_filter_unnormalised", "eq. ema-gradient",
+     "for (int s1 = 1; s1 <= s2; ++s1) G += (1.0 - p.beta_f) * pow(p.beta_f, s2 - s1) * dz[(long)s1 * J + sd.tgt];",
+     "for (int s1 = 1; s1 <= s2; ++s1) G += pow(p.beta_f, s2 - s1) * dz[(long)s1 * J + sd.tgt];"),
     # optimiser (Methods, "Optimization")
     ("adam_without_second_moment_correction", "eq. eta-adam-fast",
      "const double eta_t = eta * sqrt(1.0 - pow(beta2, (double)step)) / (1.0 - pow(beta1, (double)step));",

@@ -170,12 +170,17 @@ def test_bruteforce_matches_time_and_event_driven(loss, surrogate, forced):
     assert np.array_equal(g1["w_out"], g2["w_out"])
 
 
-@pytest.mark.parametrize("loss", [0, 1])
-def test_eprop_equals_exact_gradient_without_recurrence(loss):
+@pytest.mark.parametrize("loss,d_out", [(0, 0), (1, 0), (0, 2), (1, 3)])
+def test_eprop_equals_exact_gradient_without_recurrence(loss, d_out):
     """P8: with W_rec = 0 and B = W_out^T the e-prop gradient is the exact
     forward-mode gradient of the loss of the surrogate model (eq. replace-wkj-by-bjk
-    is then an identity and no recurrent path is truncated)."""
+    is then an identity and no recurrent path is truncated).  With a readout
+    delay d (eq. leaky_integrator_with_delay) the identity still holds: the
+    learning signal of step t meets the eligibility of step t - d, which is
+    the exact chain through y^t."""
     wl = W.tiny(loss=loss)
+    if d_out:
+        wl = _with_wl(wl, d_out=d_out)
     on = O.OracleNet(wl.network)
     on.w_rec[:] = 0.0
     on.fb[:] = on.w_out.T
@@ -304,23 +309,34 @@ def test_gradient_descent_uses_batch_mean():
     assert np.allclose(on.w_out, w0 - 0.5)
 
 
-def test_forced_sampled_matches_full_run():
+@pytest.mark.parametrize("extra", [{}, dict(d_out=2, d_ls=3, c_reg=1e5, f_target_hz=10.0),
+                                   dict(d_out=1, reg_mode=1, reg_tau=50.0, c_reg=30.0, f_target_hz=20.0)])
+def test_forced_sampled_matches_full_run(extra):
     """The per-neuron teacher-forced evaluation reproduces the full oracle run
-    on the sampled neurons' synapses (basis of the full-size sampled checks)."""
+    on the sampled neurons' synapses (basis of the full-size sampled checks),
+    also with readout and learning-signal delays and either rate regulariser."""
     wl = _twin_c4(n_rec=800, n_steps=100)
+    net = _with(wl.network, **extra) if extra else wl.network
     batch = W.forced_poisson(wl.make_batch(0, 0, 1), wl.network.n_rec, 10.0, 1.0, seed=11, n_ref=2)
-    on = O.OracleNet(wl.network)
+    on = O.OracleNet(net)
     g = O.zero_grads(on)
     r = O.run_trial(on, batch, 0, 1, g, trace=True)
     tg = [0, 17, 799]
     loss, psi, gi, gr = O.forced_sampled(on, batch, 0, tg)
-    assert loss == r.loss
     assert np.array_equal(psi, r.trace["psi"][:, tg].T)
     m = ~np.isnan(gr)
-    assert m.sum() == sum(int((wl.network.rec_rec.col == j).sum()) for j in tg)
-    assert np.array_equal(gr[m], g["w_rec"][m])
     mi = ~np.isnan(gi)
-    assert np.array_equal(gi[mi], g["w_in"][mi])
+    assert m.sum() == sum(int((wl.network.rec_rec.col == j).sum()) for j in tg)
+    if not extra:
+        assert loss == r.loss
+        assert np.array_equal(gr[m], g["w_rec"][m])
+        assert np.array_equal(gi[mi], g["w_in"][mi])
+    else:
+        # the terms are the same; the regulariser's are added in another order
+        assert loss == pytest.approx(r.loss, rel=1e-12)
+        for got, want in ((gr[m], g["w_rec"][m]), (gi[mi], g["w_in"][mi])):
+            ok, e, ent = rel_close(got, want, 1e-12)
+            assert ok, (e, ent)
 
 
 # ---------------------------------------------------------------- generators
@@ -392,6 +408,11 @@ def test_scaling_graph_and_ignore_and_fire_trains():
 def _with(wnet, **params):
     from dataclasses import replace
     return replace(wnet, params=replace(wnet.params, **params))
+
+
+def _with_wl(wl, **params):
+    from dataclasses import replace
+    return replace(wl, network=_with(wl.network, **params))
 
 
 def _head(batch, T, shift=0):
