@@ -123,6 +123,15 @@ MUTATIONS = [
      "if (cutoff > 0 && (st->last == 0 || s - st->last > cutoff)) {"),
     ("online_transmits_old_weight", "update first, then transmit",
      "        *w = *w - eta * g;\n", "        I_t = I_t + *w;\n        *w = *w - eta * g;\n        I_t = I_t - *w;\n"),
+    ("online_signal_without_readout_delay", "Alg. 4 with the readout delay d",
+     "g += L_h[(long)(s + net->d_out) * J + j] * st->eb;", "g += L_h[(long)s * J + j] * st->eb;"),
+    ("online_readout_trace_alpha", "eq. eprop-output-new-subs-rewritten",
+     "*zb = p->kappa * *zb + (x ? 1.0 : 0.0);", "*zb = p->alpha * *zb + (x ? 1.0 : 0.0);"),
+    ("online_flush_stops_one_early", "flush after the last step",
+     "online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], T - d, cutoff, E_h, gk);",
+     "online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], T - d - 1, cutoff, E_h, gk);"),
+    ("online_cutoff_keeps_traces", "inter-spike cutoff",
+     "      st->ev = st->ea = st->eb = st->gh = 0.0;\n", "      st->eb = st->gh = 0.0;\n"),
     ("online_lag_one_short", "the most recent learning signal",
      "const int d = net->d_out, lag = 1 + net->d_ls + net->d_out;",
      "const int d = net->d_out, lag = net->d_ls + net->d_out;"),
