@@ -208,3 +208,24 @@ def test_threaded_graph_build_finds_duplicates():
         col[lo + 1] = col[lo]
         st, msg = _create(cfg, projs, wo, fb)
         assert st == E.EPROP_ERR_INVALID_ARGUMENT and "duplicate" in msg, (src, st, msg)
+
+
+def test_create_error_message_is_per_thread():
+    """eprop_last_error(NULL) gives the last failure of eprop_create_network
+    in the calling thread: a failure in another thread does not replace it."""
+    import threading
+    wnet = W.tiny().network
+    cfg, projs, wo, fb, keep = _parts(wnet, n_out=0)
+    st, msg_main = _create(cfg, projs, wo, fb)
+    assert st == E.EPROP_ERR_INVALID_ARGUMENT and "n_out" in msg_main
+    seen = {}
+
+    def other():
+        cfg2, projs2, wo2, fb2, keep2 = _parts(wnet, max_trials=0)
+        seen["st"], seen["msg"] = _create(cfg2, projs2, wo2, fb2)
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["st"] == E.EPROP_ERR_INVALID_ARGUMENT and "max_trials" in seen["msg"]
+    assert E.eprop_last_error(None) == msg_main
