@@ -7,7 +7,8 @@ tests/test_oracle.py must fail for every one of them; a mistake that
 survives marks a part of the oracle that no pin holds.
 
 Run: python tests/oracle_mutations.py [-j WORKERS] [NAME ...]
-Exit status 0 when every planted mistake is caught.
+Exit status 0 when every planted mistake is caught (the pins are first run
+on an unchanged copy, which must pass).
 
 Not collected by pytest (its name has no test_ prefix): each entry rebuilds
 the oracle and runs the whole pin suite.
@@ -173,20 +174,25 @@ MUTATIONS = [
 
 
 def _copy_tree(dst):
-    shutil.copytree(ROOT, dst, ignore=shutil.ignore_patterns(
-        ".git", "_work", "gpurun_out", "__pycache__", ".pytest_cache", "*.so", "*.so.tmp*"))
+    """The oracle, the pins and the input generators they use; nothing built."""
+    skip = shutil.ignore_patterns("__pycache__", ".pytest_cache", "*.so", "*.so.tmp*")
+    for part in ("oracle", "tests", "paper_2511_21674_amd"):
+        shutil.copytree(os.path.join(ROOT, part), os.path.join(dst, part), ignore=skip)
 
 
 def run_one(entry, base):
+    """Runs the pins on a copy of the oracle with one mistake planted (none
+    for the control entry, whose pins must pass)."""
     name, _, good, bad = entry
     work = os.path.join(base, name)
     _copy_tree(work)
     path = os.path.join(work, SRC)
     src = open(path).read()
-    if src.count(good) != 1:
-        return name, "NOT FOUND (the oracle changed; update this entry)"
-    with open(path, "w") as f:
-        f.write(src.replace(good, bad))
+    if good is not None:
+        if src.count(good) != 1:
+            return name, "NOT FOUND (the oracle changed; update this entry)"
+        with open(path, "w") as f:
+            f.write(src.replace(good, bad))
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-c", "import oracle; oracle.build(force=True)"], cwd=work,
                        capture_output=True, text=True, env=env)
@@ -210,6 +216,11 @@ def main():
     base = tempfile.mkdtemp(prefix="oracle_mut_")
     bad = 0
     try:
+        # control: the copied pins pass on the unchanged oracle
+        name, verdict = run_one(("control", "", None, None), base)
+        if verdict != "SURVIVED":
+            print(f"the pins fail on the unchanged oracle ({verdict}); nothing to check", flush=True)
+            return 2
         with ThreadPoolExecutor(max_workers=max(1, args.j)) as ex:
             for name, verdict in ex.map(lambda m: run_one(m, base), todo):
                 bad += not verdict.startswith("caught")
