@@ -47,6 +47,19 @@ MUTATIONS = [
      "return net->sg_gamma * fmax(0.0, 1.0 - fabs(dv));"),
     ("exponential_without_width", "exponential surrogate",
      "return net->sg_gamma * exp(-net->sg_beta * fabs(dv));", "return net->sg_gamma * exp(-fabs(dv));"),
+    ("membrane_decay_from_tau_out", "exact integration of eq. lif_update",
+     "p->alpha = exp(-net->dt / net->tau_m);", "p->alpha = exp(-net->dt / net->tau_out);"),
+    ("adaptation_decay_from_tau_m", "exact integration of eq. spike-threshold-adaptation",
+     "p->rho = exp(-net->dt / net->tau_a);", "p->rho = exp(-net->dt / net->tau_m);"),
+    ("no_filter_keeps_kappa", "Results, \"Eligibility trace filter decoupled from output time constant\"",
+     "net->etrace_filter == 2 ? 0.0 : p->kappa;", "net->etrace_filter == 2 ? p->kappa : p->kappa;"),
+    ("refractory_steps_truncated", "refractory period in steps",
+     "p->n_ref = (int)lround(net->t_ref / net->dt);", "p->n_ref = (int)(net->t_ref / net->dt) - 1;"),
+    ("recurrent_spike_seen_a_step_late", "a spike of step s reaches a delay-D synapse at s + D",
+     "return (s >= 1 && s <= sp->T) ? sp->zrec[(long)s * sp->J + src] : 0;",
+     "return (s >= 2 && s <= sp->T) ? sp->zrec[(long)(s - 1) * sp->J + src] : 0;"),
+    ("input_spike_steps_shifted", "input emission steps in [0, T-1]",
+     "    sp->zin[(long)s * sp->I + i] = 1;", "    if (s + 1 < (unsigned)sp->T) sp->zin[(long)(s + 1) * sp->I + i] = 1;"),
     ("input_delay_shifted", "eq. lif_update with transmission delays",
      "if (spiked(sp, s->kind, s->src, t - s->delay))",
      "if (spiked(sp, s->kind, s->src, t - s->delay + (s->delay > 1)))"),

@@ -26,9 +26,11 @@ def _trace(net, batch, grad_mode=0):
 
 def test_lif_free_decay_is_exact_exponential():
     """Exact-integration propagator (eq. lif_update, alpha = exp(-dt/tau_m)):
-    after one subthreshold input of weight w arriving at step a, v^t = w e^{-(t-a) dt/tau}."""
+    after one subthreshold input of weight w arriving at step a, v^t = w e^{-(t-a) dt/tau}.
+    The readout and adaptation time constants differ from tau_m, so that
+    only the membrane's own constant gives this decay."""
     w = 0.3
-    net = small_net(1, 1, 1, [(0, 0, w, 1)], [], v_th=10.0)
+    net = small_net(1, 1, 1, [(0, 0, w, 1)], [], v_th=10.0, tau_m=20.0, tau_out=35.0, tau_a=200.0)
     r, _, _ = _trace(net, batch_from(60, [(4, 0)], 1))
     v = r.trace["v"][:, 0]
     t = np.arange(1, 61)
@@ -654,6 +656,26 @@ def test_decoupled_filter_with_tau_out_is_the_coupled_filter():
     assert np.array_equal(grads[0]["w_rec"], grads[1]["w_rec"])
     assert not rel_close(grads[0]["w_rec"], grads[2]["w_rec"], 1e-3)[0]
     assert np.array_equal(grads[0]["w_out"], grads[2]["w_out"])   # the output gradient keeps F_kappa
+
+
+def test_no_filter_is_the_vanishing_filter_limit():
+    """Removing the eligibility filter (Results, "Eligibility trace filter
+    decoupled from output time constant") is the decoupled filter with a
+    vanishing time constant: tau_e = 1e-3 ms gives exp(-dt/tau_e) = 0 in
+    double precision, so both configurations give the same gradient, and it
+    differs from the filtered one."""
+    wl = W.tiny(loss=0)
+    b = wl.make_batch(0, 0, 1)
+    grads = []
+    for prm in (dict(etrace_filter=2), dict(etrace_filter=1, tau_e=1e-3), dict()):
+        on = O.OracleNet(_with(wl.network, **prm))
+        g = O.zero_grads(on)
+        O.run_trial(on, b, 0, 2, g)
+        grads.append(g)
+    assert math.exp(-wl.network.params.dt / 1e-3) == 0.0
+    assert np.array_equal(grads[0]["w_rec"], grads[1]["w_rec"])
+    assert np.array_equal(grads[0]["w_in"], grads[1]["w_in"])
+    assert not rel_close(grads[0]["w_rec"], grads[2]["w_rec"], 1e-3)[0]
 
 
 # ---------------------------------------------------------------- e-prop+ update schedule
