@@ -79,7 +79,9 @@ typedef struct {       /* optional per-step recordings, row t-1; any may be NULL
  * 2: event-driven gradient (intervals between presynaptic arrivals, walked
  * from archived postsynaptic history when the next arrival comes, flushed at
  * the end of the trial).  Gradients are ADDED into g_in [nnz_in],
- * g_rec [nnz_rec] and g_out [K*J].  Returns 0, or -1 on bad input. */
+ * g_rec [nnz_rec] and g_out [K*J].  *pred (classification losses) is the
+ * argmax of the window-summed softmax: parity unpinned, reporting only.
+ * Returns 0, or -1 on bad input. */
 int orc_run_trial(const orc_net *net, const orc_trial *trial, int grad_mode,
                   double *g_in, double *g_rec, double *g_out,
                   orc_trace *trace, double *loss, int *pred);
