@@ -81,6 +81,9 @@ def lib():
         L.orc_forced_sampled.argtypes = [C.POINTER(_Net), C.POINTER(_Trial), C.c_int, P, P, P, P,
                                          C.POINTER(C.c_double)]
         L.orc_forced_sampled.restype = C.c_int
+        L.orc_fp32_bounds.argtypes = [C.POINTER(_Net), C.POINTER(_Trial), C.c_double, P, C.c_int, P,
+                                      P, P, P, P, P, P, P, P]
+        L.orc_fp32_bounds.restype = C.c_int
         L.orc_run_online.argtypes = [C.POINTER(_Net), C.c_int, C.POINTER(_Trial), C.c_double, C.c_int, C.c_int,
                                      P, P, P, P, P, P, P, P]
         L.orc_run_online.restype = C.c_int
@@ -273,6 +276,38 @@ def forced_sampled(net: OracleNet, batch, b: int, targets) -> tuple:
                                 _p(psi), C.byref(loss)):
         raise ValueError("oracle rejected the trial")
     return loss.value, psi, g_in, g_rec
+
+
+def fp32_bounds(net: OracleNet, batch, b: int, quantum: float = 0.0, psi_given=None, targets=None) -> dict:
+    """Teacher-forced trial b (see orc_fp32_bounds): "psi" [T, n_t] the trial's
+    surrogate gradient and "psi_bound" the bound of its FP32 evaluation's
+    error; "g" the time-driven gradient on the psi history psi_given ([T, J],
+    None = own) and "b" the FP32 rounding bound of each of its entries, as
+    dicts like zero_grads.  With targets only their incoming synapses hold
+    values (others NaN) and n_t = len(targets)."""
+    keep: list = []
+    ns, tr = net.cstruct(), _trial_struct(batch, b, keep)
+    T = int(batch.n_steps[b])
+    if targets is None:
+        tg, n, nt = None, -1, net.n_rec
+        fill = 0.0
+    else:
+        tg = np.ascontiguousarray(targets, dtype=np.int32)
+        n = nt = tg.size
+        fill = np.nan
+    pg = None if psi_given is None else np.ascontiguousarray(psi_given, dtype=np.float64)
+    if pg is not None and pg.shape != (T, net.n_rec):
+        raise ValueError("psi_given must be [T, J]")
+    psi, pb = np.zeros((nt, T)), np.zeros((nt, T))
+    g = {"w_in": np.full(net.w_in.shape, fill), "w_rec": np.full(net.w_rec.shape, fill),
+         "w_out": np.zeros_like(net.w_out)}
+    bd = {"w_in": np.full(net.w_in.shape, fill), "w_rec": np.full(net.w_rec.shape, fill),
+          "w_out": np.zeros_like(net.w_out)}
+    if lib().orc_fp32_bounds(C.byref(ns), C.byref(tr), float(quantum), _p(pg), n, _p(tg), _p(psi), _p(pb),
+                             _p(g["w_in"]), _p(g["w_rec"]), _p(g["w_out"]), _p(bd["w_in"]), _p(bd["w_rec"]),
+                             _p(bd["w_out"])):
+        raise ValueError("oracle rejected the trial (the bounds need forced spikes)")
+    return {"psi": psi.T.copy(), "psi_bound": pb.T.copy(), "g": g, "b": bd}
 
 
 def train(workload, iterations: int = None, grad_mode: int = 2, batch_size: int = None,

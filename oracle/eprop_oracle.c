@@ -782,6 +782,154 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *tr, int n_sample, co
 }
 
 /* ------------------------------------------------------------------------ */
+/* Bounds for checking an FP32 evaluation of a teacher-forced trial (see the
+ * header), by running error analysis: a computed quantity x carries mu(x)
+ * with |fl(x) - x| <= u mu(x) to first order in u = 2^-24; one rounding per
+ * operation, so z = x op y gives mu(z) = (mu of the operands, propagated) +
+ * |z|, and a constant rounded to FP32 adds its own magnitude. */
+
+static const double kU32 = 5.9604644775390625e-08;   /* 2^-24 */
+
+int orc_fp32_bounds(const orc_net *net, const orc_trial *tr, double quantum, const double *psi_given, int n_sample,
+                    const int *targets, double *psi_own, double *psi_bound, double *g_in, double *g_rec,
+                    double *g_out, double *b_in, double *b_rec, double *b_out) {
+  if (check_net(net, tr) || !tr->forced || !(quantum >= 0.0)) return -1;
+  prep_t p;
+  if (prep_init(net, &p)) return -1;
+  spikes_t sp;
+  if (spikes_init(net, tr, &sp)) { prep_free(&p); return -1; }
+  const int T = tr->n_steps, J = net->n_rec, K = net->n_out, d = net->d_out;
+  const int ema = net->reg_mode == 1 && net->c_reg != 0.0;
+  const double u = kU32, cs = 7.0;   /* cs: roundings downstream of psi, in units of u (header) */
+  memcpy(sp.zrec, sp.zforced, (size_t)(T + 1) * J);
+  double *y = calloc(K, sizeof(double)), *E = calloc(K, sizeof(double)), *psum = calloc(K, sizeof(double));
+  double *E_h = calloc((size_t)(T + 1) * K, sizeof(double));
+  double *psi_h = calloc((size_t)(T + 1), sizeof(double));
+  double *L_h = calloc((size_t)(T + 1), sizeof(double)), *La_h = calloc((size_t)(T + 1), sizeof(double));
+  double *f_h = calloc((size_t)(T + 1), sizeof(double));
+  int rc = (y && E && psum && E_h && psi_h && L_h && La_h && f_h) ? 0 : -1;
+  double loss = 0.0;
+  for (int t = 1; t <= T && rc == 0; ++t) {
+    readout_step(net, &p, &sp, tr, t, y, E, &loss, psum);
+    for (int k = 0; k < K; ++k) E_h[(long)t * K + k] = E[k];
+  }
+  /* output synapses (eq. eprop-output-new-subs-rewritten): sum over t of
+   * E_k^{t+d} zbar_j^t; every term has the sign of E, so the rounding bound
+   * is cs u sum_t |E_k^{t+d}| zbar_j^t */
+  for (int j = 0; j < J && rc == 0 && (g_out || b_out); ++j) {
+    double zb = 0.0, g[64] = {0}, b[64] = {0};
+    for (int t = 1; t + d <= T; ++t) {
+      zb = p.kappa * zb + (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);
+      for (int k = 0; k < K && k < 64; ++k) {
+        g[k] += E_h[(long)(t + d) * K + k] * zb;
+        b[k] += cs * u * fabs(E_h[(long)(t + d) * K + k]) * zb;
+      }
+    }
+    for (int k = 0; k < K && k < 64; ++k) {
+      if (g_out) g_out[(long)k * J + j] = g[k];
+      if (b_out) b_out[(long)k * J + j] = b[k];
+    }
+  }
+  const int ns = n_sample < 0 ? J : n_sample;
+  for (int n = 0; n < ns && rc == 0; ++n) {
+    const int j = n_sample < 0 ? n : targets[n];
+    if (j < 0 || j >= J) { rc = -1; break; }
+    const double beta = neuron_beta(net, j);
+    /* the neuron's recursion in FP64 and the running bound of its FP32 evaluation */
+    double v = 0.0, a = 0.0, mu_v = 0.0, mu_a = 0.0;
+    int refr = 0;
+    for (int t = 1; t <= T; ++t) {
+      const double v_prev = v, a_prev = a;
+      const int refr_prev = refr;
+      const double I_t = input_current(net, &p, &sp, j, t);
+      int n_arr = 0;
+      for (long q = p.in_ptr[j]; q < p.in_ptr[j + 1]; ++q)
+        n_arr += spiked(&sp, p.syn[q].kind, p.syn[q].src, t - p.syn[q].delay);
+      const double zprev = sp.zrec[(long)(t - 1) * J + j] ? 1.0 : 0.0;
+      double psi;
+      neuron_step(net, &p, j, I_t, zprev, sp.zrec[(long)t * J + j], &v, &a, &refr, &psi);
+      /* a = rho a + z (rho rounded, product, sum); A = v_th + beta a (v_th, beta rounded) */
+      double A = net->v_th, mu_A = fabs(net->v_th);
+      if (beta != 0.0) {
+        mu_a = p.rho * mu_a + 2.0 * fabs(p.rho * a_prev) + fabs(a);
+        A = net->v_th + beta * a;
+        mu_A = fabs(net->v_th) + beta * mu_a + 2.0 * fabs(beta * a) + fabs(A);
+      }
+      /* the input current: the arriving weights summed exactly and rounded
+       * once, plus `quantum` per arriving weight */
+      const double mu_I = fabs(I_t) + n_arr * quantum / u;
+      if (net->reset_mode == 1 && zprev != 0.0)   /* alpha v_reset + I: alpha, v_reset, product, sum */
+        mu_v = 3.0 * fabs(p.alpha * net->v_reset) + mu_I + fabs(v);
+      else                                         /* (alpha v + I) - z A */
+        mu_v = p.alpha * mu_v + 2.0 * fabs(p.alpha * v_prev) + mu_I + fabs(p.alpha * v_prev + I_t) +
+               zprev * mu_A + fabs(v);
+      double mu_psi = 0.0;
+      if (refr_prev == 0) {   /* psi = 0 exactly while refractory */
+        const double dv = v - A, mu_dv = mu_v + mu_A + fabs(dv);
+        if (net->surrogate == 1)   /* gamma exp(-beta |dv|): the exponent's error, exp, gamma, beta, products */
+          mu_psi = psi * (net->sg_beta * mu_dv + 2.0 * net->sg_beta * fabs(dv) + 4.0);
+        else                       /* gamma max(0, 1 - beta |dv|): Lipschitz gamma beta, and its own roundings */
+          mu_psi = net->sg_gamma * net->sg_beta * mu_dv + 3.0 * net->sg_gamma;
+      }
+      if (psi_own) psi_own[(long)n * T + (t - 1)] = psi;
+      if (psi_bound) psi_bound[(long)n * T + (t - 1)] = u * mu_psi;
+      psi_h[t] = psi_given ? psi_given[(long)(t - 1) * J + j] : psi;
+      double Ls = 0.0, La = 0.0;
+      for (int k = 0; k < K; ++k) {
+        Ls = Ls + net->fb[(long)j * K + k] * E_h[(long)t * K + k];
+        La = La + fabs(net->fb[(long)j * K + k] * E_h[(long)t * K + k]);
+      }
+      L_h[t] = Ls;
+      La_h[t] = La;
+      f_h[t] = p.beta_f * f_h[t - 1] + (1.0 - p.beta_f) * (sp.zrec[(long)t * J + j] ? 1.0 : 0.0);
+    }
+    double nz = 0.0;
+    for (int t = 1; t <= T; ++t) nz += sp.zrec[(long)t * J + j] ? 1.0 : 0.0;
+    const double creg = net->reg_mode == 0 ? net->c_reg / T * (nz / T - net->f_target) : 0.0;
+    /* Alg. "time-driven gradient computation" on the archived psi history, as
+     * orc_forced_sampled, with the same recursion run on absolute values for
+     * the rounding bound */
+    for (long q = p.in_ptr[j]; q < p.in_ptr[j + 1]; ++q) {
+      const in_syn *s = &p.syn[q];
+      double ev = 0.0, ea = 0.0, eb = 0.0, gh = 0.0, g = 0.0, es = 0.0;
+      double ea_abs = 0.0, eb_abs = 0.0, gh_abs = 0.0, s_eabs = 0.0, bnd = 0.0;
+      for (int t = 1; t <= T; ++t) {
+        const double ev_prev = ev;
+        const double zp = sp.zrec[(long)(t - 1) * J + j];
+        const double e = syn_trace(net, &p, spiked(&sp, s->kind, s->src, t - s->delay) ? 1.0 : 0.0, zp, psi_h[t - 1],
+                                   psi_h[t], beta, &ev, &ea, &eb);
+        ea_abs = psi_h[t - 1] * fabs(ev_prev) + fabs(p.rho - psi_h[t - 1] * beta) * ea_abs;
+        const double e_abs = psi_h[t] * (fabs(ev) + beta * ea_abs);
+        eb_abs = p.kappa_e * eb_abs + e_abs;
+        if (t + d <= T - net->d_ls) {
+          g += L_h[t + d] * eb;
+          bnd += cs * u * La_h[t + d] * eb_abs;
+        }
+        if (t <= T - d) {
+          es += e;
+          s_eabs += e_abs;
+        }
+        if (ema) {
+          gh = p.beta_f * gh + (1.0 - p.beta_f) * e;
+          gh_abs = p.beta_f * gh_abs + (1.0 - p.beta_f) * e_abs;
+          if (t <= T - d) {
+            const double df = f_h[t] - net->f_target;
+            g += net->c_reg * df * gh;
+            bnd += net->c_reg * (cs * u * fabs(df) + u * fabs(f_h[t])) * gh_abs;
+          }
+        }
+      }
+      if (g_in && g_rec) (s->kind == 0 ? g_in : g_rec)[s->idx] = g + creg * es;
+      if (b_in && b_rec) (s->kind == 0 ? b_in : b_rec)[s->idx] = bnd + cs * u * fabs(creg) * s_eabs;
+    }
+  }
+  free(y); free(E); free(psum); free(E_h); free(psi_h); free(L_h); free(La_h); free(f_h);
+  spikes_free(&sp);
+  prep_free(&p);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* e-prop+ update schedule: weight updates at every spike over a continuous
  * run (see the header). */
 

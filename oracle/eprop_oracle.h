@@ -80,8 +80,9 @@ typedef struct {       /* optional per-step recordings, row t-1; any may be NULL
  * from archived postsynaptic history when the next arrival comes, flushed at
  * the end of the trial).  Gradients are ADDED into g_in [nnz_in],
  * g_rec [nnz_rec] and g_out [K*J].  *pred (classification losses) is the
- * argmax of the window-summed softmax: parity unpinned, reporting only.
- * Returns 0, or -1 on bad input. */
+ * arg max over the readouts of the learning window's summed softmax output
+ * (cross-entropy) or readout signal (temporal MSE), lowest index on ties;
+ * 0 for MSE.  Returns 0, or -1 on bad input. */
 int orc_run_trial(const orc_net *net, const orc_trial *trial, int grad_mode,
                   double *g_in, double *g_rec, double *g_out,
                   orc_trace *trace, double *loss, int *pred);
@@ -108,6 +109,41 @@ int orc_forward_mode_loss_grad(const orc_net *net, const orc_trial *trial,
 int orc_forced_sampled(const orc_net *net, const orc_trial *trial, int n_sample,
                        const int *targets, double *g_in, double *g_rec,
                        double *psi_out, double *loss);
+
+/* What checking an FP32 evaluation of teacher-forced trial `trial` needs,
+ * from running error analysis (Wilkinson; Higham, Accuracy and Stability of
+ * Numerical Algorithms, sec. 3.3), to first order in u = 2^-24:
+ *   psi_own, psi_bound [n_t * T] (row n = the n-th target, column t-1): the
+ *     surrogate gradient psi of the forced trial (FP64) and a bound of the
+ *     error of its FP32 evaluation: weights are FP32 numbers (the same on
+ *     both sides); the input current of a step is the exact sum of the
+ *     arriving weights rounded once to FP32, plus at most `quantum` per
+ *     arriving weight (0 for an exact sum); the neuron recursion
+ *     (eq. spike-threshold-adaptation, adaptive threshold, eq. lif_update,
+ *     the surrogate) runs in FP32 in the order of its definition with one
+ *     rounding per operation, alpha, rho, v_th, gamma and beta rounded to FP32
+ *     and exp within 2 ulp;
+ *   g_in, g_rec: the gradient of Alg. "time-driven gradient computation"
+ *     evaluated on the archived psi history psi_given ([T * J], row t-1;
+ *     NULL = the trial's own psi), as orc_forced_sampled;  g_out [K*J] the
+ *     output gradient (eq. eprop-output-new-subs-rewritten);
+ *   b_in, b_rec, b_out: 7 u times the sum of the absolute values of the terms
+ *     of each of these gradients (for the input and recurrent synapses,
+ *     sum_t sum_k |B_jk E_k^{t+d}| times the eligibility recursion run on
+ *     absolute values, plus the regularisers' terms likewise), a bound of the
+ *     rounding of an FP32 evaluation downstream of psi: 1 u feedback weights
+ *     rounded to FP32, 1 u stored archive values, 2 u compensated summation
+ *     per synapse, 1 u stored partial sums, 2 u compensated summation of the
+ *     partials.
+ * Spikes (forced) and refractory states are the same on both sides.
+ * n_sample < 0: every neuron is a target (n_t = J); otherwise only the
+ * listed targets (n_t = n_sample) get psi rows and their incoming synapses
+ * get values in g_* / b_* (written at the synapse's index, other entries
+ * untouched).  Any output pointer may be NULL.  Returns 0, or -1 on bad
+ * input or a trial without forced spikes. */
+int orc_fp32_bounds(const orc_net *net, const orc_trial *trial, double quantum, const double *psi_given,
+                    int n_sample, const int *targets, double *psi_own, double *psi_bound, double *g_in,
+                    double *g_rec, double *g_out, double *b_in, double *b_rec, double *b_out);
 
 /* e-prop+ update schedule (Results, "Weight updates with every spike";
  * Alg. "event-driven weight update" applied at every spike): one network

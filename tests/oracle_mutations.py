@@ -183,6 +183,31 @@ MUTATIONS = [
      "w[i] = w[i] - eta_t * m[i] / (sqrt(v[i]) + eps_hat);", "w[i] = w[i] - eta_t * m[i] / sqrt(v[i] + eps_hat);"),
     ("sum_instead_of_mean", "eq. gradient-descent on the mini-batch mean",
      "const double G = g_sum[i] / n_trials;", "const double G = g_sum[i];"),
+    # class prediction (arg max of the window-summed softmax or readout)
+    ("prediction_ignores_window_ce", "prediction from the learning window (eq. softmax)",
+     "if (win) psum[k] += pi;", "psum[k] += pi;"),
+    ("prediction_ignores_window_tmse", "prediction from the learning window (eq. temporal-mse)",
+     "if (win) {\n        *loss += d * d / K;\n        psum[k] += y[k];\n      }",
+     "if (win) *loss += d * d / K;\n      psum[k] += y[k];"),
+    ("prediction_ce_sums_readout", "cross-entropy predicts from the softmax output",
+     "if (win) psum[k] += pi;", "if (win) psum[k] += y[k];"),
+    ("prediction_arg_min", "the predicted class is the arg max",
+     "if (psum[k] > psum[best]) best = k;\n    *pred", "if (psum[k] < psum[best]) best = k;\n    *pred"),
+    ("prediction_last_of_ties", "ties go to the lowest index",
+     "if (psum[k] > psum[best]) best = k;\n    *pred", "if (psum[k] >= psum[best]) best = k;\n    *pred"),
+    # running error bounds for checking FP32 evaluations (Higham, sec. 3.3)
+    ("fp32_bound_membrane_without_memory", "running error of v = alpha v + I - z A",
+     "mu_v = p.alpha * mu_v + 2.0 * fabs(p.alpha * v_prev)", "mu_v = 2.0 * fabs(p.alpha * v_prev)"),
+    ("fp32_bound_adaptation_without_memory", "running error of a = rho a + z",
+     "mu_a = p.rho * mu_a + 2.0 * fabs(p.rho * a_prev) + fabs(a);", "mu_a = 2.0 * fabs(p.rho * a_prev) + fabs(a);"),
+    ("fp32_bound_quantum_ignored", "weights rounded by a fixed-point accumulator",
+     "const double mu_I = fabs(I_t) + n_arr * quantum / u;", "const double mu_I = fabs(I_t);"),
+    ("fp32_bound_given_psi_shifted", "the archived psi history, row t-1 is step t",
+     "psi_h[t] = psi_given ? psi_given[(long)(t - 1) * J + j] : psi;",
+     "psi_h[t] = psi_given ? psi_given[(long)(t > 1 ? t - 2 : 0) * J + j] : psi;"),
+    ("fp32_bound_signed_learning_signal", "absolute term sum of the gradient",
+     "La = La + fabs(net->fb[(long)j * K + k] * E_h[(long)t * K + k]);",
+     "La = La + net->fb[(long)j * K + k] * E_h[(long)t * K + k];"),
 ]
 
 

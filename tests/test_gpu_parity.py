@@ -16,7 +16,7 @@ import pytest
 from paper_2511_21674_amd import eprop as E
 from paper_2511_21674_amd import workloads as W
 import oracle as O
-from tests.helpers import rel_close, small_net, batch_from
+from tests.helpers import rel_close, small_net, batch_from, prediction_case
 
 pytestmark = pytest.mark.gpu
 KEYS = ("w_in", "w_rec", "w_out")
@@ -38,7 +38,7 @@ def gpu_train(wl, precision, iterations, bs, delivery="auto", forced_rate=None, 
               max_steps=None, record=True):
     T = max_steps or max(int(wl.make_batch(it, 0, bs).n_steps.max()) for it in range(iterations))
     net = E.Network(wl.network, precision, max_trials=bs, max_steps=T, delivery=delivery)
-    hist = {"loss": [], "spikes": [], "grads": [], "weights": [], "dw": []}
+    hist = {"loss": [], "pred": [], "spikes": [], "grads": [], "weights": [], "dw": []}
     w_prev = net.weights()
     for it in range(iterations):
         b = wl.make_batch(it, 0, bs)
@@ -47,6 +47,7 @@ def gpu_train(wl, precision, iterations, bs, delivery="auto", forced_rate=None, 
                                  iteration=it, n_ref=2)
         r = net.simulate(b, train=True, device=device)
         hist["loss"].append(r.loss.copy())
+        hist["pred"].append(r.predicted.copy())
         if record:
             hist["spikes"].append([net.spikes(i, int(b.n_steps[i])) for i in range(b.n_trials)])
             hist["grads"].append(net.grads())
@@ -61,7 +62,7 @@ def gpu_train(wl, precision, iterations, bs, delivery="auto", forced_rate=None, 
 
 def oracle_train(wl, iterations, bs, forced_rate=None, grad_mode=2):
     on = O.OracleNet(wl.network)
-    hist = {"loss": [], "spikes": [], "grads": [], "weights": [], "dw": []}
+    hist = {"loss": [], "pred": [], "spikes": [], "grads": [], "weights": [], "dw": []}
     w_prev = {k: getattr(on, k).copy() for k in KEYS}
     for it in range(iterations):
         b = wl.make_batch(it, 0, bs)
@@ -69,12 +70,14 @@ def oracle_train(wl, iterations, bs, forced_rate=None, grad_mode=2):
             b = W.forced_poisson(b, wl.network.n_rec, forced_rate, wl.network.params.dt, seed=99,
                                  iteration=it, n_ref=2)
         g = O.zero_grads(on)
-        losses, spikes = [], []
+        losses, spikes, preds = [], [], []
         for i in range(b.n_trials):
             r = O.run_trial(on, b, i, grad_mode, g, trace=True)
             losses.append(r.loss)
             spikes.append(r.trace["z"])
+            preds.append(r.pred)
         hist["loss"].append(np.array(losses))
+        hist["pred"].append(np.array(preds, np.uint32))
         hist["spikes"].append(spikes)
         hist["grads"].append({k: v.copy() for k, v in g.items()})
         O.apply(on, g, b.n_trials)
@@ -91,6 +94,8 @@ def assert_fp64_parity(gh, oh, name):
             assert np.array_equal(zg, zo), f"{name}: iteration {it} trial {i} spike trains differ"
         ok, e, _ = rel_close(gh["loss"][it], oh["loss"][it], 1e-12)
         assert ok, (name, it, "loss", e)
+        # the predicted class (arg max of the window-summed softmax or readout)
+        assert np.array_equal(gh["pred"][it], oh["pred"][it]), (name, it, gh["pred"][it], oh["pred"][it])
         for k in KEYS:
             ok, e, ent = rel_close(gh["grads"][it][k], oh["grads"][it][k], 1e-10)
             assert ok, (name, it, "grad", k, e, ent)
@@ -191,6 +196,25 @@ def test_device_memory_batch_equals_host_batch():
     assert np.array_equal(out[0][0], out[1][0])
     for k in KEYS:
         assert np.array_equal(out[0][1][k], out[1][1][k])
+
+
+@pytest.mark.parametrize("precision,delivery", [("fp64", "gather"), ("fp32", "scatter")])
+@pytest.mark.parametrize("loss", [1, 2])
+def test_class_prediction_constructed_case(precision, delivery, loss):
+    """The predicted class of the constructed trials whose answer is fixed by
+    construction (tests.helpers.prediction_case: a readout dominating before
+    the learning window, a tall short peak and a flat signal inside it, a
+    silent network, an exact tie): the GPU's prediction equals the known
+    class and the oracle's, and the loss matches the oracle's."""
+    for variant in ("main", "silent", "tie"):
+        net_w, b, expected = prediction_case(loss, variant)
+        net = E.Network(net_w, precision, max_trials=1, max_steps=int(b.n_steps[0]), delivery=delivery)
+        r = net.simulate(b, train=True)
+        net.close()
+        ro = O.run_trial(O.OracleNet(net_w), b, 0, 0)
+        log(f"{precision} loss {loss} {variant}: predicted {int(r.predicted[0])}, expected {expected}")
+        assert int(r.predicted[0]) == expected == ro.pred, (variant, int(r.predicted[0]), expected, ro.pred)
+        assert rel_close(r.loss, [ro.loss], 1e-12 if precision == "fp64" else 1e-5)[0]
 
 
 # ----------------------------------------------------------------- FP32

@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2511_21674_amd import workloads as W
-from tests.helpers import small_net, batch_from, rel_close
+from tests.helpers import small_net, batch_from, rel_close, prediction_case
 
 
 def _trace(net, batch, grad_mode=0):
@@ -143,6 +143,24 @@ def test_softmax_errors_sum_to_zero():
     s = r.trace["err"].sum(axis=1)
     assert np.abs(s).max() < 1e-14
     assert np.abs(r.trace["err"]).max() > 0.1
+
+
+@pytest.mark.parametrize("loss", [1, 2])
+@pytest.mark.parametrize("variant", ["main", "silent", "tie"])
+def test_class_prediction_closed_form(loss, variant):
+    """The predicted class of a classification trial: the arg max over the
+    readouts of the learning window's summed softmax output (cross-entropy,
+    eq. softmax; Results, "Evidence accumulation") or summed readout signal
+    (temporal MSE, eq. temporal-mse), lowest index on ties.  The constructed
+    trial (tests.helpers.prediction_case) fixes the answer by construction:
+    one readout dominates before the window, one has the tallest short peak
+    in it, one a flat moderate signal, so that ignoring the window, summing y
+    for cross-entropy, summing pi for temporal MSE, taking the arg min or the
+    last of tied maxima each give another class."""
+    net, b, expected = prediction_case(loss, variant)
+    on = O.OracleNet(net)
+    r = O.run_trial(on, b, 0, 0, trace=True)
+    assert r.pred == expected, (loss, variant, r.pred, expected)
 
 
 # ---------------------------------------------------------------- gradients
@@ -834,3 +852,154 @@ def test_online_single_synapse_matches_direct_simulation():
     assert on.w_in[0] == pytest.approx(w, rel=1e-13, abs=1e-15)
     assert on.w_out[0, 0] == pytest.approx(wo, rel=1e-13, abs=1e-15)
     assert abs(w - 0.9) > 1e-3 and abs(wo - 0.7) > 1e-3
+
+
+# ---------------------------------------------------------------- bounds for checking FP32 evaluations
+
+def _fp32_neuron_psi(net, b, i, quantum_bits=None):
+    """The neuron recursion of teacher-forced trial i evaluated in float32,
+    written from the model's definition (eq. spike-threshold-adaptation,
+    adaptive threshold, eq. lif_update, eq. piecewise-linear / exponential
+    surrogate, zero while refractory), one rounding per operation.  With
+    quantum_bits F every arriving weight is first rounded to a multiple of
+    2^-F.  Returns psi [T, J] (float32 values)."""
+    p, f32 = net.params, np.float32
+    T, J = int(b.n_steps[i]), net.n_rec
+    al, rho = f32(np.exp(-p.dt / p.tau_m)), f32(np.exp(-p.dt / p.tau_a))
+    vth, gam, bet = f32(p.v_th), f32(p.sg_gamma), f32(p.sg_beta)
+    beta = np.where(net.is_alif.astype(bool), f32(p.beta_a), f32(0))
+    nref = int(round(p.t_ref / p.dt))
+    lo, hi = int(b.in_ptr[i]), int(b.in_ptr[i + 1])
+    zin = np.zeros((T, max(net.n_in, 1)), bool)
+    zin[b.in_step[lo:hi], b.in_src[lo:hi]] = True
+    zr = np.zeros((T + 1, J), bool)
+    flo, fhi = int(b.forced_ptr[i]), int(b.forced_ptr[i + 1])
+    zr[b.forced_step[flo:fhi], b.forced_neuron[flo:fhi]] = True
+    v, a = np.zeros(J, f32), np.zeros(J, f32)
+    refr = np.zeros(J, int)
+    psi = np.zeros((T, J), f32)
+    for t in range(1, T + 1):
+        cur = np.zeros(J)   # exact sum of the arriving FP32 weights (few terms), rounded once below
+        for pr, zs, first in ((net.in_rec, zin, 0), (net.rec_rec, zr, 1)):
+            rp = pr.row_ptr.astype(np.int64)
+            for src in range(pr.n_src):
+                for q in range(rp[src], rp[src + 1]):
+                    s = t - int(pr.delay[q])
+                    if first <= s < T + first and s >= 0 and zs[s, src]:
+                        w = float(f32(pr.w[q]))
+                        if quantum_bits is not None:
+                            w = np.round(w * 2.0 ** quantum_bits) / 2.0 ** quantum_bits
+                        cur[pr.col[q]] += w
+        I = cur.astype(f32)
+        zp = zr[t - 1].astype(f32)
+        a = np.where(beta != 0, rho * a + zp, a).astype(f32)
+        A = np.where(beta != 0, vth + beta * a, vth).astype(f32)
+        if p.reset_mode == 1:
+            v = np.where(zr[t - 1], al * f32(p.v_reset) + I, al * v + I).astype(f32)
+        else:
+            v = (al * v + I - zp * A).astype(f32)
+        refractory = refr > 0
+        refr = np.where(refractory, refr - 1, refr)
+        dv = (v - A).astype(f32)
+        if p.surrogate == 0:
+            ps = gam * np.maximum(f32(0), f32(1) - bet * np.abs(dv))
+        else:
+            ps = gam * np.exp(-bet * np.abs(dv)).astype(f32)
+        psi[t - 1] = np.where(refractory, f32(0), ps.astype(f32))
+        refr = np.where(zr[t], nref, refr)
+    return psi
+
+
+def _forced_tiny(loss=0, surrogate=0, **params):
+    wl = W.tiny(loss=loss, surrogate=surrogate)
+    net = wl.network
+    for k, val in params.items():
+        setattr(net.params, k, val)
+    # FP32 weights (what an FP32 evaluation holds), the same on both sides
+    net.in_rec.w[:] = net.in_rec.w.astype(np.float32)
+    net.rec_rec.w[:] = net.rec_rec.w.astype(np.float32)
+    b = W.forced_poisson(wl.make_batch(0, 0, 2), net.n_rec, 40.0, 1.0, seed=3, n_ref=2)
+    return net, b
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(surrogate=1), dict(loss=1, reset_mode=1, v_reset=-0.2),
+                                  dict(quantum_bits=16)])
+def test_fp32_psi_bound_holds_and_is_tight(opts):
+    """Running error analysis of the neuron recursion (orc_fp32_bounds): a
+    float32 evaluation of the model's definition (3 LIF + 2 ALIF neurons,
+    teacher-forced, delays 1 and 2; both surrogates; the full reset; weights
+    rounded to multiples of 2^-16 as by a 32-bit fixed-point accumulator)
+    stays within the bound at every step, and the bound is at most 25 times
+    the largest error seen, so that a dropped error term shows."""
+    opts = dict(opts)
+    qb = opts.pop("quantum_bits", None)
+    net, b = _forced_tiny(**opts)
+    on = O.OracleNet(net)
+    worst = 0.0
+    for i in range(b.n_trials):
+        psi32 = _fp32_neuron_psi(net, b, i, qb).astype(np.float64)
+        r = O.fp32_bounds(on, b, i, quantum=0.0 if qb is None else 2.0 ** -(qb + 1))
+        err = np.abs(psi32 - r["psi"])
+        assert np.all(err <= r["psi_bound"]), (i, float((err / np.maximum(r["psi_bound"], 1e-300)).max()))
+        worst = max(worst, float(err.max() / r["psi_bound"][err > 0].min()) if np.any(err > 0) else 0.0,
+                    float((err / np.maximum(r["psi_bound"], 1e-300)).max()))
+        assert err.max() > 0
+    assert worst >= 1.0 / 25, worst
+
+
+def test_gradient_on_a_given_psi_history():
+    """Alg. "time-driven gradient computation" takes the archived psi history:
+    on the trial's own psi, orc_fp32_bounds' gradient is the time-driven
+    gradient of orc_run_trial; on a perturbed history, it moves by exactly
+    the first-order change of the eligibility recursion in psi, which is
+    evaluated here by finite differences of the psi history on a single
+    synapse (the gradient is quadratic in psi for ALIF targets, linear for
+    LIF targets)."""
+    net, b = _forced_tiny()
+    on = O.OracleNet(net)
+    g = O.zero_grads(on)
+    O.run_trial(on, b, 0, 1, g)
+    own = O.fp32_bounds(on, b, 0)
+    again = O.fp32_bounds(on, b, 0, psi_given=own["psi"])
+    for k in ("w_in", "w_rec", "w_out"):
+        assert np.array_equal(own["g"][k], g[k]), k
+        assert np.array_equal(again["g"][k], g[k]), k
+    T, J = own["psi"].shape
+    rng = np.random.default_rng(0)
+    delta = np.zeros((T, J))
+    j = 0                                              # a LIF target: g is linear in psi
+    delta[:, j] = rng.normal(size=T) * 1e-3 * (own["psi"][:, j] > 0)
+    gp = O.fp32_bounds(on, b, 0, psi_given=own["psi"] + delta)["g"]
+    gm = O.fp32_bounds(on, b, 0, psi_given=own["psi"] - delta)["g"]
+    for k in ("w_in", "w_rec"):
+        tgt = (net.in_rec if k == "w_in" else net.rec_rec).col
+        other = tgt != j
+        assert np.array_equal(gp[k][other], own["g"][k][other]), k   # other targets untouched
+        lin = gp[k][~other] + gm[k][~other] - 2 * own["g"][k][~other]
+        # (zero up to the rounding of sums of the size of g itself)
+        assert np.abs(lin).max() <= 1e-12 * np.abs(own["g"][k][~other]).max(), k
+        assert np.abs(gp[k][~other] - own["g"][k][~other]).max() > 0
+    # psi row t-1 is step t: a change at one step moves nothing before the
+    # step's first arriving synapse, and everything is zero with psi = 0
+    gz = O.fp32_bounds(on, b, 0, psi_given=np.zeros((T, J)))["g"]
+    for k in ("w_in", "w_rec"):
+        assert np.all(gz[k] == 0), k
+
+
+def test_fp32_rounding_bound_is_the_absolute_term_sum():
+    """The downstream rounding bound is 7 u times the sum of the absolute
+    values of the gradient's terms: for one LIF synapse whose every term has
+    one sign (positive learning signal: y below a large target, positive
+    feedback), it is exactly 7 u |g|; with mixed signs it exceeds 7 u |g|."""
+    u = 2.0 ** -24
+    net = small_net(1, 1, 1, [(0, 0, 0.2, 1)], [], w_out=[[-1.0]], fb=[[0.5]])
+    T = 80
+    b = batch_from(T, [(s, 0) for s in range(0, T, 7)], 1, target=np.full(T, -3.0), forced=[(40, 0)])
+    on = O.OracleNet(net)
+    r = O.fp32_bounds(on, b, 0)
+    g, bd = r["g"]["w_in"][0], r["b"]["w_in"][0]
+    assert g < 0 or g > 0
+    assert bd == pytest.approx(7 * u * abs(g), rel=1e-13)
+    b2 = batch_from(T, [(s, 0) for s in range(0, T, 7)], 1, target=np.sin(np.arange(T) / 5.0) * 3, forced=[(40, 0)])
+    r2 = O.fp32_bounds(on, b2, 0)
+    assert r2["b"]["w_in"][0] > 1.5 * 7 * u * abs(r2["g"]["w_in"][0])
