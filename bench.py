@@ -55,6 +55,31 @@ def path_bytes(c, net, n_trials, adam):
             + (c["rec_spikes"] + c["in_spikes"]) * B_SOURCE + per_iter)
 
 
+def design_bytes(c, net, n_trials, adam, blocked, K):
+    """Bytes this design has to move in one batch step, by kernel (the
+    per-unit figures of the kernels' own algorithms rather than the
+    survey's per-synapse trace model, which this design never materialises):
+    forward 12 B per event + 22 B (LIF) / 30 B (ALIF) per neuron-step;
+    spike-time lists 1/8 B per neuron-step + 2 B per spike; readout
+    5 x 8 B per readout and trial-step; adjoint 8 B per neuron-step (psi
+    read, phi written); synapse kernel 20 B per synapse (packed source 4,
+    gradient pair read and written 16) + 4 B per neuron-step (phi staged)
+    + 16 B per source record + 2 B per spike; output reduction
+    8 B per output synapse and trial + 16; update 26 B per synapse blocked
+    (10 B of target-major runs, 16 B records read and written) or 28 B in
+    target-major order, + 16 B with Adam."""
+    S = net.in_rec.nnz + net.rec_rec.nnz
+    ns = c["neuron_steps"]
+    spikes = c["rec_spikes"] + c["in_spikes"]
+    trial_steps = ns / net.n_rec
+    fwd = forward_bytes(c, net)
+    parts = {"forward": fwd, "spike_lists": ns / 8 + 2 * spikes, "readout": 40 * K * trial_steps,
+             "adjoint": 8 * ns, "synapse": 20 * S + 4 * ns + 16 * (net.n_in + net.n_rec) + 2 * spikes,
+             "output": K * net.n_rec * (8 * n_trials + 16),
+             "update": S * ((26 if blocked else 28) + (16 if adam else 0))}
+    return parts
+
+
 def forward_bytes(c, net):
     """Algorithmic bytes of the forward kernel (delivery and neuron updates)
     for one batch step."""
@@ -80,9 +105,25 @@ def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
     counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
     reads for a plain copy of known size), or None when there is no record
-    for this workload or the kernel source changed since it was taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    for this workload or the kernel source changed since it was taken.
+    kernel "step": the bytes of every kernel of one batch step
+    (profiles/hbm_traffic_<workload>_step.md, per-step figures)."""
+    if kernel == "step":
+        rec = _traffic_record(os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_step.md"), "step")
+        if rec is None:
+            return None
+        return (float(rec["fetch_kib_per_step"]) * float(rec["copy_fetch_factor"])
+                + float(rec["write_kib_per_step"]) * float(rec["copy_write_factor"])) * 1024.0
+    rec = _traffic_record(os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md"), kernel)
+    if rec is None:
+        return None
+    return (float(rec["fetch_kib_per_dispatch"]) * float(rec["copy_fetch_factor"])
+            + float(rec["write_kib_per_dispatch"]) * float(rec["copy_write_factor"])) * 1024.0
+
+
+def _traffic_record(path, kernel):
+    """The key: value lines of a committed counter record, if it is for
+    `kernel` and for the kernel source as it is now."""
     src = os.path.join(ROOT, "paper_2511_21674_amd", "csrc", "eprop_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -95,8 +136,7 @@ def measured_traffic(workload, kernel):
         return None
     if rec.get("kernel_code_sha256") != kernel_code_hash(src):
         return None
-    return (float(rec["fetch_kib_per_dispatch"]) * float(rec["copy_fetch_factor"])
-            + float(rec["write_kib_per_dispatch"]) * float(rec["copy_write_factor"])) * 1024.0
+    return rec
 
 
 def stage_batches(wl, n, first_iteration):
@@ -228,6 +268,55 @@ def cpu_baseline(wl, n_steps_sample, budget_s=20.0):
     return out
 
 
+def _oracle_sample(job):
+    """One process of the parallel oracle timing: trial `i` of the first
+    batch, whole (small networks, within the time budget) or its first T
+    steps; returns (events, seconds)."""
+    import oracle as O
+    i, T, budget = job
+    wl = _oracle_sample.workload     # set before the processes are forked
+    net = wl.network
+    on = O.OracleNet(net)
+    b = wl.make_batch(0, 0, wl.batch_size)
+    ev, el = 0, 0.0
+    while i < b.n_trials and el <= budget:
+        sb = _truncated(b, i, min(T, int(b.n_steps[i]))) if T else b.trial(i)
+        g = O.zero_grads(on)
+        t0 = time.perf_counter()
+        r = O.run_trial(on, sb, 0, 2, g, trace=True)
+        el += time.perf_counter() - t0
+        ev += _events_of_trial(net, sb, 0, r.trace["z"])
+        if T:
+            break
+        i += _oracle_sample.stride
+    return ev, el
+
+
+def cpu_parallel(wl, n_steps_sample, budget_s=20.0):
+    """The oracle in P independent processes, P = min(trials per batch, host
+    cores, 16), one trial (or its first steps) each, forked after the
+    workload is built: aggregate events over the wall-clock time."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    P = max(1, min(wl.batch_size, cores, 16))
+    T = 0 if wl.network.n_rec <= 5000 else n_steps_sample
+    _oracle_sample.stride = P
+    _oracle_sample.workload = wl
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        res = pool.map(_oracle_sample, [(i, T, budget_s / 2) for i in range(P)], chunksize=1)
+    wall = time.perf_counter() - t0
+    ev = sum(r[0] for r in res)
+    what = f"the first {T} steps of trials 0..{P - 1}" if T else f"whole trials of the first batch, trial i in process i mod {P}"
+    return {"value": ev / wall, "unit": "synaptic events/s", "cores": P, "kind": "oracle",
+            "sample": f"{what}, event-driven gradient, one process each ({ev} events, {wall:.1f} s wall-clock "
+                      f"including each process's copy of the network; building the network arrays excluded)"}
+
+
 def bench_online(args, wl, progress):
     """The e-prop+ schedule: warm-up on one sample, then `steps` samples of the
     workload run back to back as one continuous run with per-spike updates.
@@ -296,7 +385,13 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="steps of the CPU oracle's sample on large networks (default 40; 5 for the scaling network)")
     ap.add_argument("--fp64-iters", type=int, default=1,
-                    help="training iterations of the FP64 plain comparison (<= warmup + steps)")
+                    help="training iterations of the FP64 plain comparison (<= warmup + steps); its final loss is "
+                         "the mean over the last 10%% of them, compared with the FP32 run's over the same iterations")
+    ap.add_argument("--batch", type=int, default=None, help="trials per batch (default: the workload's)")
+    ap.add_argument("--delivery", choices=("scatter", "gather"), default="scatter",
+                    help="spike delivery of the FP32 run: scatter into LDS delay rings (default) or target-side "
+                         "gather (one kernel per step, every target sums its arriving synapses)")
+    ap.add_argument("--no-cpu-parallel", action="store_true", help="skip the P-process oracle timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -337,7 +432,7 @@ def main():
 
     t_start = time.perf_counter()
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
-    wl = W.WORKLOADS[args.workload]()
+    wl = W.WORKLOADS[args.workload](**({"batch_size": args.batch} if args.batch else {}))
     net_w = wl.network
     if args.online:
         return bench_online(args, wl, progress)
@@ -348,7 +443,7 @@ def main():
           f"synapses={net_w.in_rec.nnz + net_w.rec_rec.nnz} batch={wl.batch_size} T={T}", file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        net = E.Network(net_w, "fp32", max_trials=wl.batch_size, max_steps=T,
+        net = E.Network(net_w, "fp32", max_trials=wl.batch_size, max_steps=T, delivery=args.delivery,
                         stream=E.C.c_void_p(stream.cuda_stream), autotune=not args.no_autotune)
         progress("network built")
         staged = stage_batches(wl, args.warmup + args.steps, 0)
@@ -396,23 +491,42 @@ def main():
     n_tr = wl.batch_size
     rate_hz = tot["rec_spikes"] / (steps * n_tr * net_w.n_rec * T * net_w.params.dt / 1000.0)
     lay = net.layout()
-    launches = -(-T // lay["steps_per_launch"])
+    gather = args.delivery == "gather"
+    # the forward kernel runs once per block of steps (scatter) or once per step (gather)
+    launches = T if gather else -(-T // lay["steps_per_launch"])
     per_step = {k: v / steps for k, v in tot.items()}
     per_step["neuron_steps"] = float(np.mean([int(staged[args.warmup + i][0].n_steps.sum()) for i in range(steps)])
                                      * net_w.n_rec)
     fwd_ms = phases["forward"] / steps
     fwd_b = forward_bytes(per_step, net_w)
     achieved = fwd_b / launches / (fwd_ms / launches / 1000.0) / 1e9
-    roof = {"kernel": "k_forward_tiled", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+    roof = {"kernel": "k_neuron_gather" if gather else "k_forward_tiled", "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_ms": round(fwd_ms / launches, 4), "algorithmic_bytes_per_launch": int(fwd_b / launches)}
+    step_s = elapsed / steps
     pb = path_bytes(per_step, net_w, n_tr, net_w.params.optimizer == 1)
-    path_roof = {"bytes_per_step": int(pb), "achieved": round(pb / (elapsed / steps) / 1e9, 1), "unit": "GB/s",
-                 "frac": round(pb / (elapsed / steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    db = design_bytes(per_step, net_w, n_tr, net_w.params.optimizer == 1, bool(lay["blocked_update"]), net_w.n_out)
+    dsum = sum(db.values())
+    path_roof = {
+        "design": {"bytes_per_step": int(dsum), "achieved": round(dsum / step_s / 1e9, 1), "unit": "GB/s",
+                   "frac": round(dsum / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                   "bytes_by_kernel": {k: int(v) for k, v in db.items()},
+                   "note": "the bytes this design's kernels need (their own algorithms)"},
+        "survey_model": {"bytes_per_step": int(pb), "achieved": round(pb / step_s / 1e9, 1), "unit": "GB/s",
+                         "frac": round(pb / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                         "note": "the survey's per-unit model: 24-32 B of per-synapse trace and gradient traffic "
+                                 "per event, which the archive design never moves; a model, not a measurement"},
+        "measured": None}
     tr = measured_traffic(wl.name, roof["kernel"])
     if tr is not None:
         roof["traffic"] = round(tr / 1e9, 3)
         roof["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    tstep = measured_traffic(wl.name, "step")
+    if tstep is not None:
+        path_roof["measured"] = {"bytes_per_step": int(tstep), "achieved": round(tstep / step_s / 1e9, 1),
+                                 "unit": "GB/s", "frac": round(tstep / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                                 "note": "rocprofv3 FETCH_SIZE + WRITE_SIZE of every kernel of one step, "
+                                         "copy-calibrated"}
 
     fp64 = None
     if not args.no_fp64:
@@ -439,10 +553,16 @@ def main():
             torch.cuda.synchronize()
             el64 = time.perf_counter() - t1
             net64.close()
-        l64, l32 = loss64[-1], all32[m - 1]
+        # final loss: the mean over the last 10% of the compared iterations (at least one)
+        nl = max(1, m // 10)
+        l64, l32 = float(np.mean(loss64[-nl:])), float(np.mean(all32[m - nl:m]))
         fp64 = {"value": ev64 / el64, "unit": "synaptic events/s", "seconds_per_iteration": el64 / m,
                 "iterations": m, "speedup_fp32_batched": (el64 / m) / (elapsed / steps),
-                "loss_fp64": loss64, "loss_fp32": all32[:m], "final_loss_rel_diff": abs(l32 - l64) / abs(l64),
+                "loss_fp64": loss64, "loss_fp32": all32[:m], "final_loss_fp64": l64, "final_loss_fp32": l32,
+                "final_loss_rel_diff": abs(l32 - l64) / abs(l64),
+                "comparison": ("trained: final loss = mean over the last %d of %d training iterations" % (nl, m))
+                if m >= 100 else ("first %d batch(es) from the same initial weights: a forward and gradient "
+                                  "comparison, not a trained run" % m),
                 "note": "same batches and initial weights; speedup = FP64 plain seconds per iteration / "
                         "FP32 batched"}
     net.close()
@@ -452,6 +572,9 @@ def main():
         progress("CPU oracle baseline")
         cpu = cpu_baseline(wl, min(args.cpu_steps, T))
         progress("CPU oracle baseline done")
+        if not args.no_cpu_parallel:
+            cpu["parallel"] = cpu_parallel(wl, min(args.cpu_steps, T))
+            progress("parallel CPU oracle baseline done")
 
     out = {"metric": "synaptic events/s (event-driven e-prop training, FP32 batched)",
            "value": tot["events"] / elapsed, "unit": "synaptic events/s", "n_gpus": 1, "steps": steps,
@@ -459,7 +582,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": f"{wl.name}: {wl.description}", "n_rec": net_w.n_rec, "n_in": net_w.n_in,
                       "n_out": net_w.n_out, "synapses": int(net_w.in_rec.nnz + net_w.rec_rec.nnz),
-                      "trials_per_batch": n_tr, "steps_per_trial": T, "delivery": "scatter (LDS tiles)",
+                      "trials_per_batch": n_tr, "steps_per_trial": T,
+                      "delivery": "gather (target side)" if gather else "scatter (LDS tiles)",
                       "gradient": "time-driven baseline" if args.time_driven else "event-driven"},
            "eprop_updates_per_s": tot["updates"] / elapsed,
            "recurrent_rate_hz": rate_hz,

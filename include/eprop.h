@@ -354,7 +354,7 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18,     /* uint64 [15]: neurons per tile, tiles per trial, bytes per
+  EPROP_STATE_LAYOUT = 18,     /* uint64 [17]: neurons per tile, tiles per trial, bytes per
                                   delay-ring entry (8: 64-bit fixed point in FP32 or double in
                                   FP64, 4: 32-bit fixed point in FP32), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
@@ -363,7 +363,9 @@ typedef enum {
                                   threads, autotuned (0/1), entries of a tile's delivery piece
                                   table, spike-index blocks the synapse kernel loads with a
                                   record's header, synapses a synapse-kernel thread takes at
-                                  a time */
+                                  a time, weight update by tile blocks (1) or in target-major
+                                  order (0), trials per launch of the tiled forward kernel
+                                  (as many as the device keeps resident together) */
   EPROP_STATE_L = 19,          /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
   EPROP_STATE_INPUT_BOUND = 20 /* double [1]: the bound on |input current| of one step used to

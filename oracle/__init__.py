@@ -85,7 +85,7 @@ def lib():
                                       P, P, P, P, P, P, P, P]
         L.orc_fp32_bounds.restype = C.c_int
         L.orc_run_online.argtypes = [C.POINTER(_Net), C.c_int, C.POINTER(_Trial), C.c_double, C.c_int, C.c_int,
-                                     P, P, P, P, P, P, P, P]
+                                     P, P, P, P, P, P, P, P, P, P, P]
         L.orc_run_online.restype = C.c_int
         L.orc_apply.argtypes = [C.c_long, P, P, C.c_double, C.c_int, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.c_long, P, P]
@@ -209,22 +209,24 @@ def run_online(net: OracleNet, batch, eta: float, cutoff: int = 0, flush: bool =
     """e-prop+ update schedule over the batch's trials run back to back as one
     continuous run (weight update at every arriving spike; see
     orc_run_online).  The network's weights are trained in place.  Returns
-    the per-sample losses, the recurrent spikes [T_total, J] and the summed
-    gradients that were applied."""
+    the per-sample losses, the recurrent spikes [T_total, J], the summed
+    gradients that were applied and ("abs") |eta| times the absolute term
+    sums of those gradients."""
     keep: list = []
     ns = net.cstruct()
     n = batch.n_trials
     trs = (_Trial * n)(*[_trial_struct(batch, b, keep) for b in range(n)])
     Tt = int(np.sum(batch.n_steps[:n]))
     g = zero_grads(net)
+    ab = zero_grads(net)
     loss = np.zeros(n)
     z = np.zeros((Tt, net.n_rec), dtype=np.uint8)
     rc = lib().orc_run_online(C.byref(ns), n, trs, float(eta), int(cutoff), int(bool(flush)), _p(net.w_in),
                               _p(net.w_rec), _p(net.w_out), _p(g["w_in"]), _p(g["w_rec"]), _p(g["w_out"]),
-                              _p(loss), _p(z))
+                              _p(loss), _p(z), _p(ab["w_in"]), _p(ab["w_rec"]), _p(ab["w_out"]))
     if rc != 0:
         raise ValueError("oracle rejected the run")
-    return {"loss": loss, "z": z, "grads": g}
+    return {"loss": loss, "z": z, "grads": g, "abs": ab}
 
 
 def zero_grads(net: OracleNet) -> dict:
@@ -281,10 +283,11 @@ def forced_sampled(net: OracleNet, batch, b: int, targets) -> tuple:
 def fp32_bounds(net: OracleNet, batch, b: int, quantum: float = 0.0, psi_given=None, targets=None) -> dict:
     """Teacher-forced trial b (see orc_fp32_bounds): "psi" [T, n_t] the trial's
     surrogate gradient and "psi_bound" the bound of its FP32 evaluation's
-    error; "g" the time-driven gradient on the psi history psi_given ([T, J],
-    None = own) and "b" the FP32 rounding bound of each of its entries, as
-    dicts like zero_grads.  With targets only their incoming synapses hold
-    values (others NaN) and n_t = len(targets)."""
+    error; "g" the time-driven gradient on the psi history psi_given ([T, n_t],
+    the targets' columns; None = own) and "b" the FP32 rounding bound of each
+    of its entries, as dicts like zero_grads.  With targets only their
+    incoming synapses hold values (others NaN) and n_t = len(targets);
+    otherwise n_t = J."""
     keep: list = []
     ns, tr = net.cstruct(), _trial_struct(batch, b, keep)
     T = int(batch.n_steps[b])
@@ -295,9 +298,9 @@ def fp32_bounds(net: OracleNet, batch, b: int, quantum: float = 0.0, psi_given=N
         tg = np.ascontiguousarray(targets, dtype=np.int32)
         n = nt = tg.size
         fill = np.nan
-    pg = None if psi_given is None else np.ascontiguousarray(psi_given, dtype=np.float64)
-    if pg is not None and pg.shape != (T, net.n_rec):
-        raise ValueError("psi_given must be [T, J]")
+    pg = None if psi_given is None else np.ascontiguousarray(np.asarray(psi_given, dtype=np.float64).T)
+    if pg is not None and pg.shape != (nt, T):
+        raise ValueError("psi_given must be [T, n_t] (the targets' columns)")
     psi, pb = np.zeros((nt, T)), np.zeros((nt, T))
     g = {"w_in": np.full(net.w_in.shape, fill), "w_rec": np.full(net.w_rec.shape, fill),
          "w_out": np.zeros_like(net.w_out)}

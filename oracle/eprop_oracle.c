@@ -97,6 +97,7 @@ static int prep_init(const orc_net *net, prep_t *p) {
 typedef struct {
   int T, I, J;
   unsigned char *zin, *zrec, *zforced;
+  int *list;     /* [J] work space: the spiking neurons of one step, ascending */
 } spikes_t;
 
 static int spiked(const spikes_t *sp, int kind, int src, int s) {
@@ -108,6 +109,7 @@ static void spikes_free(spikes_t *sp) {
   free(sp->zin);
   free(sp->zrec);
   free(sp->zforced);
+  free(sp->list);
 }
 
 static int spikes_init(const orc_net *net, const orc_trial *tr, spikes_t *sp) {
@@ -117,7 +119,8 @@ static int spikes_init(const orc_net *net, const orc_trial *tr, spikes_t *sp) {
   sp->J = net->n_rec;
   sp->zin = (unsigned char *)calloc((size_t)sp->T * (sp->I > 0 ? sp->I : 1), 1);
   sp->zrec = (unsigned char *)calloc((size_t)(sp->T + 1) * sp->J, 1);
-  if (!sp->zin || !sp->zrec) { spikes_free(sp); return -1; }
+  sp->list = (int *)calloc((size_t)sp->J, sizeof(int));
+  if (!sp->zin || !sp->zrec || !sp->list) { spikes_free(sp); return -1; }
   for (long e = 0; e < tr->n_in_spikes; ++e) {
     unsigned int s = tr->in_step[e], i = tr->in_src[e];
     if ((int)s >= sp->T || (int)i >= sp->I) { spikes_free(sp); return -1; }
@@ -201,23 +204,28 @@ static double syn_trace(const orc_net *net, const prep_t *p, double x, double zp
 
 /* Readout (eq. leaky_integrator), error signal and loss (eq. mean-squared-error
  * or eq. softmax + eq. cross-entropy-loss), window-gated. */
-static void readout_core(const orc_net *net, const prep_t *p, const spikes_t *sp, int t, const double *target_row,
+static void readout_core(const orc_net *net, const prep_t *p, spikes_t *sp, int t, const double *target_row,
                          int win, int label, double *y, double *E, double *loss, double *psum);
 
-static void readout_step(const orc_net *net, const prep_t *p, const spikes_t *sp,
+static void readout_step(const orc_net *net, const prep_t *p, spikes_t *sp,
                          const orc_trial *tr, int t, double *y, double *E, double *loss,
                          double *psum) {
   readout_core(net, p, sp, t, tr->target ? tr->target + (long)(t - 1) * net->n_out : NULL,
                tr->window ? tr->window[t - 1] : 1, tr->label, y, E, loss, psum);
 }
 
-static void readout_core(const orc_net *net, const prep_t *p, const spikes_t *sp, int t, const double *target_row,
+static void readout_core(const orc_net *net, const prep_t *p, spikes_t *sp, int t, const double *target_row,
                          int win, int label, double *y, double *E, double *loss, double *psum) {
   const int J = net->n_rec, K = net->n_out;
+  /* the neurons whose spike reaches the readout now, ascending: each
+   * readout sums their weights in that order */
+  int n = 0;
+  if (t - net->d_out >= 1)
+    for (int j = 0; j < J; ++j)
+      if (sp->zrec[(long)(t - net->d_out) * J + j]) sp->list[n++] = j;
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
-    for (int j = 0; j < J; ++j)
-      if (t - net->d_out >= 1 && sp->zrec[(long)(t - net->d_out) * J + j]) s = s + net->w_out[(long)k * J + j];
+    for (int i = 0; i < n; ++i) s = s + net->w_out[(long)k * J + sp->list[i]];
     y[k] = p->kappa * y[k] + s;
   }
   if (net->loss == 2) {
@@ -873,7 +881,7 @@ int orc_fp32_bounds(const orc_net *net, const orc_trial *tr, double quantum, con
       }
       if (psi_own) psi_own[(long)n * T + (t - 1)] = psi;
       if (psi_bound) psi_bound[(long)n * T + (t - 1)] = u * mu_psi;
-      psi_h[t] = psi_given ? psi_given[(long)(t - 1) * J + j] : psi;
+      psi_h[t] = psi_given ? psi_given[(long)n * T + (t - 1)] : psi;
       double Ls = 0.0, La = 0.0;
       for (int k = 0; k < K; ++k) {
         Ls = Ls + net->fb[(long)j * K + k] * E_h[(long)t * K + k];
@@ -935,6 +943,7 @@ int orc_fp32_bounds(const orc_net *net, const orc_trial *tr, double quantum, con
 
 typedef struct {
   double ev, ea, eb, gh;   /* eligibility vector, filtered trace, G_beta-filtered trace */
+  double ea_a, eb_a, gh_a; /* the same recursions on the absolute values of their terms */
   int s_done;              /* last eligibility step already used */
   int last;                /* last arrival at or before s_done (0: none) */
 } online_syn;
@@ -945,9 +954,10 @@ typedef struct {
  * weight update", steps of the left-open interval). */
 static double online_walk(const orc_net *net, const prep_t *p, const spikes_t *sp, int kind, int src, int D, int j,
                           online_syn *st, int s_new, int cutoff, const double *psi_h, const double *L_h,
-                          const double *f_h) {
+                          const double *La_h, const double *f_h, double *gabs) {
   const int J = net->n_rec;
   const int ema = net->reg_mode == 1 && net->c_reg != 0.0;
+  const double beta = neuron_beta(net, j);
   double g = 0.0;
   for (int s = st->s_done + 1; s <= s_new; ++s) {
     const int x = spiked(sp, kind, src, s - D);
@@ -955,13 +965,22 @@ static double online_walk(const orc_net *net, const prep_t *p, const spikes_t *s
     if (cutoff > 0 && (st->last == 0 || s - st->last >= cutoff)) {
       /* beyond the cutoff the traces count as decayed */
       st->ev = st->ea = st->eb = st->gh = 0.0;
+      st->ea_a = st->eb_a = st->gh_a = 0.0;
       continue;
     }
-    const double e = syn_trace(net, p, x ? 1.0 : 0.0, sp->zrec[(long)(s - 1) * J + j], psi_h[(long)(s - 1) * J + j],
-                               psi_h[(long)s * J + j], neuron_beta(net, j), &st->ev, &st->ea, &st->eb);
+    const double ev_prev = st->ev, pp = psi_h[(long)(s - 1) * J + j], pn = psi_h[(long)s * J + j];
+    const double e = syn_trace(net, p, x ? 1.0 : 0.0, sp->zrec[(long)(s - 1) * J + j], pp, pn, beta, &st->ev,
+                               &st->ea, &st->eb);
     st->gh = p->beta_f * st->gh + (1.0 - p->beta_f) * e;
     g += L_h[(long)(s + net->d_out) * J + j] * st->eb;
     if (ema) g += net->c_reg * (f_h[(long)s * J + j] - net->f_target) * st->gh;
+    /* the absolute term sum of the same gradient (for bounding an FP32 evaluation) */
+    st->ea_a = pp * fabs(ev_prev) + fabs(p->rho - pp * beta) * st->ea_a;
+    const double e_a = pn * (fabs(st->ev) + beta * st->ea_a);
+    st->eb_a = p->kappa_e * st->eb_a + e_a;
+    st->gh_a = p->beta_f * st->gh_a + (1.0 - p->beta_f) * e_a;
+    *gabs += La_h[(long)(s + net->d_out) * J + j] * st->eb_a;
+    if (ema) *gabs += net->c_reg * (fabs(f_h[(long)s * J + j] - net->f_target) + fabs(f_h[(long)s * J + j])) * st->gh_a;
   }
   if (s_new > st->s_done) st->s_done = s_new;
   return g;
@@ -971,7 +990,7 @@ static double online_walk(const orc_net *net, const prep_t *p, const spikes_t *s
  * r_new, each r adding E_k^{r+d} zbar_j^r to g[k]
  * (eq. eprop-output-new-subs-rewritten), with the same cutoff rule. */
 static void online_walk_out(const orc_net *net, const prep_t *p, const spikes_t *sp, int j, double *zb, int *r_done,
-                            int *last, int r_new, int cutoff, const double *E_h, double *g) {
+                            int *last, int r_new, int cutoff, const double *E_h, double *g, double *gabs) {
   const int J = net->n_rec, K = net->n_out;
   for (int r = *r_done + 1; r <= r_new; ++r) {
     const int x = sp->zrec[(long)r * J + j];
@@ -981,14 +1000,18 @@ static void online_walk_out(const orc_net *net, const prep_t *p, const spikes_t 
       continue;
     }
     *zb = p->kappa * *zb + (x ? 1.0 : 0.0);
-    for (int k = 0; k < K; ++k) g[k] += E_h[(long)(r + net->d_out) * K + k] * *zb;
+    for (int k = 0; k < K; ++k) {
+      g[k] += E_h[(long)(r + net->d_out) * K + k] * *zb;
+      gabs[k] += fabs(E_h[(long)(r + net->d_out) * K + k]) * *zb;
+    }
   }
   if (r_new > *r_done) *r_done = r_new;
 }
 
 int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, double eta, int cutoff,
                    int flush, double *w_in, double *w_rec, double *w_out, double *g_in, double *g_rec,
-                   double *g_out, double *loss_out, unsigned char *z_out) {
+                   double *g_out, double *loss_out, unsigned char *z_out, double *a_in, double *a_rec,
+                   double *a_out) {
   if (!net0 || !smp || n_samples < 1 || !w_in || !w_rec || !w_out || !loss_out || cutoff < 0) return -1;
   if (net0->c_reg != 0.0 && net0->reg_mode != 1) return -1;
   orc_net nt = *net0;  /* the same network, reading the weights being trained */
@@ -1013,20 +1036,23 @@ int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, dou
   sp.J = J;
   int *off = calloc((size_t)n_samples + 1, sizeof(int)), *smp_of = calloc((size_t)T + 1, sizeof(int));
   sp.zin = calloc((size_t)T * (I > 0 ? I : 1), 1);
+  sp.list = calloc((size_t)J, sizeof(int));
   sp.zrec = calloc((size_t)(T + 1) * J, 1);
   if (smp[0].forced) sp.zforced = calloc((size_t)(T + 1) * J, 1);
   double *v = calloc(J, sizeof(double)), *a = calloc(J, sizeof(double)), *y = calloc(K, sizeof(double));
   double *E = calloc(K, sizeof(double)), *psum = calloc(K, sizeof(double)), *gk = calloc(K, sizeof(double));
+  double *gka = calloc(K, sizeof(double));
   int *refr = calloc(J, sizeof(int));
   double *psi_h = calloc((size_t)(T + 1) * J, sizeof(double)), *L_h = calloc((size_t)(T + 1) * J, sizeof(double));
+  double *La_h = calloc((size_t)(T + 1) * J, sizeof(double));   /* sum_k |B_jk E_k^t| */
   double *f_h = calloc((size_t)(T + 1) * J, sizeof(double)), *E_h = calloc((size_t)(T + 1) * K, sizeof(double));
   const long nin = net->in.nnz, ns = net->in.nnz + net->rec.nnz;
   online_syn *syn = calloc((size_t)ns + 1, sizeof(online_syn));
   double *zbo = calloc(J, sizeof(double));
   int *r_done = calloc(J, sizeof(int)), *zlast = calloc(J, sizeof(int));
   int rc = -1;
-  if (!off || !smp_of || !sp.zin || !sp.zrec || (smp[0].forced && !sp.zforced) || !v || !a || !y || !E || !psum ||
-      !gk || !refr || !psi_h || !L_h || !f_h || !E_h || !syn || !zbo || !r_done || !zlast)
+  if (!off || !smp_of || !sp.zin || !sp.list || !sp.zrec || (smp[0].forced && !sp.zforced) || !v || !a || !y || !E || !psum ||
+      !gk || !gka || !refr || !psi_h || !L_h || !La_h || !f_h || !E_h || !syn || !zbo || !r_done || !zlast)
     goto done;
   for (int k = 0; k < n_samples; ++k) {
     off[k + 1] = off[k] + smp[k].n_steps;
@@ -1055,10 +1081,13 @@ int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, dou
         const in_syn *si = &p.syn[q];
         if (!spiked(&sp, si->kind, si->src, t - si->delay)) continue;
         const long sq = si->kind == 0 ? si->idx : nin + si->idx;
+        double ga = 0.0;
         const double g = online_walk(net, &p, &sp, si->kind, si->src, si->delay, j, &syn[sq], t - lag, cutoff, psi_h,
-                                     L_h, f_h);
+                                     L_h, La_h, f_h, &ga);
         double *w = si->kind == 0 ? &w_in[si->idx] : &w_rec[si->idx];
         *w = *w - eta * g;
+        if (si->kind == 0 && a_in) a_in[si->idx] += fabs(eta) * ga;
+        if (si->kind == 1 && a_rec) a_rec[si->idx] += fabs(eta) * ga;
         if (si->kind == 0 && g_in) g_in[si->idx] += g;
         if (si->kind == 1 && g_rec) g_rec[si->idx] += g;
         I_t = I_t + *w;
@@ -1075,11 +1104,12 @@ int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, dou
     /* readout synapses whose presynaptic spike arrives now */
     for (int j = 0; j < J && t - d >= 1; ++j) {
       if (!sp.zrec[(long)(t - d) * J + j]) continue;
-      for (int kk = 0; kk < K; ++kk) gk[kk] = 0.0;
-      online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], t - 1 - d, cutoff, E_h, gk);
+      for (int kk = 0; kk < K; ++kk) gk[kk] = gka[kk] = 0.0;
+      online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], t - 1 - d, cutoff, E_h, gk, gka);
       for (int kk = 0; kk < K; ++kk) {
         w_out[(long)kk * J + j] -= eta * gk[kk];
         if (g_out) g_out[(long)kk * J + j] += gk[kk];
+        if (a_out) a_out[(long)kk * J + j] += fabs(eta) * gka[kk];
       }
     }
     readout_core(net, &p, &sp, t, tr->target ? tr->target + (long)(lt - 1) * K : NULL,
@@ -1087,9 +1117,13 @@ int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, dou
     for (int kk = 0; kk < K; ++kk) E_h[(long)t * K + kk] = E[kk];
     double sreg = 0.0;  /* this step's moving-average regulariser, summed before the total */
     for (int j = 0; j < J; ++j) {
-      double Ls = 0.0;
-      for (int kk = 0; kk < K; ++kk) Ls = Ls + net->fb[(long)j * K + kk] * E[kk];
+      double Ls = 0.0, La = 0.0;
+      for (int kk = 0; kk < K; ++kk) {
+        Ls = Ls + net->fb[(long)j * K + kk] * E[kk];
+        La = La + fabs(net->fb[(long)j * K + kk] * E[kk]);
+      }
       L_h[(long)t * J + j] = Ls;
+      La_h[(long)t * J + j] = La;
       const double df = f_h[(long)t * J + j] - net->f_target;
       sreg += df * df;
     }
@@ -1102,26 +1136,30 @@ int orc_run_online(const orc_net *net0, int n_samples, const orc_trial *smp, dou
       for (int i = 0; i < pr->n_src; ++i)
         for (unsigned long r = pr->row_ptr[i]; r < pr->row_ptr[i + 1]; ++r) {
           const long sq = kind == 0 ? (long)r : nin + (long)r;
+          double ga = 0.0;
           const double g = online_walk(net, &p, &sp, kind, i, pr->delay[r], (int)pr->col[r], &syn[sq], T + 1 - lag,
-                                       cutoff, psi_h, L_h, f_h);
+                                       cutoff, psi_h, L_h, La_h, f_h, &ga);
           (kind == 0 ? w_in : w_rec)[r] -= eta * g;
+          if (a_in && kind == 0) a_in[r] += fabs(eta) * ga;
+          if (a_rec && kind == 1) a_rec[r] += fabs(eta) * ga;
           if (kind == 0 && g_in) g_in[r] += g;
           if (kind == 1 && g_rec) g_rec[r] += g;
         }
     }
     for (int j = 0; j < J; ++j) {
-      for (int kk = 0; kk < K; ++kk) gk[kk] = 0.0;
-      online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], T - d, cutoff, E_h, gk);
+      for (int kk = 0; kk < K; ++kk) gk[kk] = gka[kk] = 0.0;
+      online_walk_out(net, &p, &sp, j, &zbo[j], &r_done[j], &zlast[j], T - d, cutoff, E_h, gk, gka);
       for (int kk = 0; kk < K; ++kk) {
         w_out[(long)kk * J + j] -= eta * gk[kk];
         if (g_out) g_out[(long)kk * J + j] += gk[kk];
+        if (a_out) a_out[(long)kk * J + j] += fabs(eta) * gka[kk];
       }
     }
   }
   rc = 0;
 done:
-  free(off); free(smp_of); free(v); free(a); free(y); free(E); free(psum); free(gk); free(refr);
-  free(psi_h); free(L_h); free(f_h); free(E_h); free(syn); free(zbo); free(r_done); free(zlast);
+  free(off); free(smp_of); free(v); free(a); free(y); free(E); free(psum); free(gk); free(gka); free(refr);
+  free(psi_h); free(L_h); free(La_h); free(f_h); free(E_h); free(syn); free(zbo); free(r_done); free(zlast);
   spikes_free(&sp);
   prep_free(&p);
   return rc;

@@ -124,8 +124,9 @@ int orc_forced_sampled(const orc_net *net, const orc_trial *trial, int n_sample,
  *     rounding per operation, alpha, rho, v_th, gamma and beta rounded to FP32
  *     and exp within 2 ulp;
  *   g_in, g_rec: the gradient of Alg. "time-driven gradient computation"
- *     evaluated on the archived psi history psi_given ([T * J], row t-1;
- *     NULL = the trial's own psi), as orc_forced_sampled;  g_out [K*J] the
+ *     evaluated on the archived psi history psi_given ([n_t * T], laid out
+ *     like psi_own; NULL = the trial's own psi), as orc_forced_sampled;
+ *     g_out [K*J] the
  *     output gradient (eq. eprop-output-new-subs-rewritten);
  *   b_in, b_rec, b_out: 7 u times the sum of the absolute values of the terms
  *     of each of these gradients (for the input and recurrent synapses,
@@ -164,11 +165,15 @@ int orc_fp32_bounds(const orc_net *net, const orc_trial *trial, double quantum, 
  * Weights w_in, w_rec, w_out are updated in place (the network's own weight
  * arrays are not used); g_in, g_rec, g_out, if not NULL, accumulate every
  * gradient applied; loss [n_samples] gets each sample's loss; z, if not
- * NULL, the recurrent spikes [T_total*J].  Static rate regularisation and
- * Adam have no per-spike form here; returns -1 for them. */
+ * NULL, the recurrent spikes [T_total*J]; a_in, a_rec, a_out, if not NULL,
+ * accumulate |eta| times the sum of the absolute values of the terms of
+ * every gradient applied (each eligibility recursion also run on absolute
+ * values, the learning signal as sum_k |B_jk E_k|), the scale of the
+ * rounding of an FP32 evaluation of the run's updates.  Static rate
+ * regularisation and Adam have no per-spike form here; returns -1 for them. */
 int orc_run_online(const orc_net *net, int n_samples, const orc_trial *samples, double eta, int cutoff,
                    int flush, double *w_in, double *w_rec, double *w_out, double *g_in, double *g_rec,
-                   double *g_out, double *loss, unsigned char *z);
+                   double *g_out, double *loss, unsigned char *z, double *a_in, double *a_rec, double *a_out);
 
 /* End of iteration: G = g_sum / n_trials, then gradient descent or Adam in
  * the TensorFlow ordering (step = iteration count, starting at 1). */

@@ -100,7 +100,10 @@ struct eprop_network {
   double *d_target = nullptr;
   uint8_t *d_window = nullptr;
   size_t cap_in_step = 0, cap_in_src = 0, cap_target = 0, cap_window = 0, cap_f_step = 0, cap_f_neuron = 0;
-  bool have_forced_bits = false;
+  // host copies reused by every batch (reserved at create for max_trials)
+  std::vector<uint64_t> h_in_ptr, h_f_ptr;
+  std::vector<double> h_loss;
+  std::vector<uint32_t> h_pred;
   // step loop
   uint32_t blk = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -321,6 +324,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.phi, B * n->Jp * n->Tp);
   ok &= dalloc(n, &d.rec_bits, B * T1 * n->Jw);
   ok &= dalloc(n, &d.in_bits, B * n->Tcap * n->Iw);
+  ok &= dalloc(n, &d.forced_bits, B * T1 * n->Jw);   // teacher-forced spikes (no allocation in a batch call)
   ok &= dalloc(n, &d.spk_cnt, B * n->NS);
   ok &= dalloc(n, &d.spk_t, B * d.spk_stride);
   ok &= dalloc(n, &d.pub_list, B * 2 * n->Jp);
@@ -719,6 +723,11 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
   n->stream = static_cast<hipStream_t>(hip_stream);
   n->perm = tm_perm;
   n->adam_step = opt ? opt->step : 0;
+  n->h_in_ptr.reserve(n->Bcap + 1);
+  n->h_f_ptr.reserve(n->Bcap + 1);
+  n->h_loss.reserve(n->Bcap);
+  n->h_pred.reserve(n->Bcap);
+  n->last_T.reserve(n->Bcap);
   n->shapes.block = 256;
   n->shapes.fwd_variant = 0;
   n->shapes.adj_block = cfg->n_out > 16 ? 64 : 256;
@@ -852,6 +861,9 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
       eprop_destroy_network(n);
       return EPROP_ERR_UNSUPPORTED;
     }
+    // trials per forward launch: as many as are resident together
+    const uint64_t resident_trials = (uint64_t)per_cu * prop.multiProcessorCount / KT;
+    n->shapes.fwd_trials = (uint32_t)std::min<uint64_t>(n->Bcap, std::max<uint64_t>(1, resident_trials));
   }
   if (e == hipSuccess)
     e = n->fp64 ? upload(n, n->n64, sm_ptr, tseg, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
@@ -1027,7 +1039,7 @@ template <typename real>
 eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res,
                       const OnlineCtx *oc = nullptr) {
   std::string msg;
-  std::vector<uint64_t> in_ptr, f_ptr;
+  std::vector<uint64_t> &in_ptr = n->h_in_ptr, &f_ptr = n->h_f_ptr;
   uint32_t t_max = 0;
   eprop_status st = check_batch(n, b, in_ptr, f_ptr, t_max, msg);
   if (st != EPROP_OK) {
@@ -1063,6 +1075,10 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   };
 
   // batch arrays: library copies for host memory, caller's for device memory
+  uint32_t *st_in_step = n->d_in_step, *st_in_src = n->d_in_src, *st_f_step = n->d_forced_step,
+           *st_f_neuron = n->d_forced_neuron;
+  double *st_target = n->d_target;
+  uint8_t *st_window = n->d_window;
   if (!dev) {
     const size_t nt = (size_t)ntr * b->step_stride;
     bool ok = dgrow(n, &n->d_in_step, &n->cap_in_step, b->n_in_spikes) &&
@@ -1076,13 +1092,12 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
       set_fail(n, "out of device memory for the batch");
       return EPROP_ERR_OUT_OF_MEMORY;
     }
-  }
-  if (forced && !n->have_forced_bits) {
-    if (!dalloc(n, &d.forced_bits, (size_t)n->Bcap * (n->Tcap + 1) * n->Jw)) {
-      set_fail(n, "out of device memory for forced spikes");
-      return EPROP_ERR_OUT_OF_MEMORY;
-    }
-    n->have_forced_bits = true;
+    st_in_step = n->d_in_step;
+    st_in_src = n->d_in_src;
+    st_target = n->d_target;
+    st_window = n->d_window;
+    st_f_step = n->d_forced_step;
+    st_f_neuron = n->d_forced_neuron;
   }
   d.T = n->d_T;
   d.label = n->d_label;
@@ -1098,32 +1113,15 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     d.forced_neuron = b->forced_neuron;
   } else {
     d.in_ptr = n->d_in_ptr;
-    d.in_step = n->d_in_step;
-    d.in_src = n->d_in_src;
-    d.target = b->target ? n->d_target : nullptr;
-    d.window = b->window ? n->d_window : nullptr;
+    d.in_step = st_in_step;
+    d.in_src = st_in_src;
+    d.target = b->target ? st_target : nullptr;
+    d.window = b->window ? st_window : nullptr;
     d.forced_ptr = n->d_forced_ptr;
-    d.forced_step = n->d_forced_step;
-    d.forced_neuron = n->d_forced_neuron;
+    d.forced_step = st_f_step;
+    d.forced_neuron = st_f_neuron;
   }
 
-  (void)hipEventRecord(n->ev[0], s);
-  // upload
-  H2D(n->d_T, b->n_steps, ntr * 4);
-  if (b->label) H2D(n->d_label, b->label, ntr * 4);
-  if (!dev) {
-    H2D(n->d_in_ptr, in_ptr.data(), in_ptr.size() * 8);
-    H2D(n->d_in_step, b->in_step, b->n_in_spikes * 4);
-    H2D(n->d_in_src, b->in_src, b->n_in_spikes * 4);
-    const size_t nt = (size_t)ntr * b->step_stride;
-    if (b->target) H2D(n->d_target, b->target, nt * n->K * 8);
-    if (b->window) H2D(n->d_window, b->window, nt);
-    if (forced) {
-      H2D(n->d_forced_ptr, f_ptr.data(), f_ptr.size() * 8);
-      H2D(n->d_forced_step, b->forced_step, b->n_forced * 4);
-      H2D(n->d_forced_neuron, b->forced_neuron, b->n_forced * 4);
-    }
-  }
   struct {
     uint32_t w[eprop::CTL_WORDS];
     const uint32_t *in_src;
@@ -1189,15 +1187,15 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   if (b->label) H2D(n->d_label, b->label, ntr * 4);
   if (!dev) {
     H2D(n->d_in_ptr, in_ptr.data(), in_ptr.size() * 8);
-    H2D(n->d_in_step, b->in_step, b->n_in_spikes * 4);
-    H2D(n->d_in_src, b->in_src, b->n_in_spikes * 4);
+    H2D(st_in_step, b->in_step, b->n_in_spikes * 4);
+    H2D(st_in_src, b->in_src, b->n_in_spikes * 4);
     const size_t nt = (size_t)ntr * b->step_stride;
-    if (b->target) H2D(n->d_target, b->target, nt * n->K * 8);
-    if (b->window) H2D(n->d_window, b->window, nt);
+    if (b->target) H2D(st_target, b->target, nt * n->K * 8);
+    if (b->window) H2D(st_window, b->window, nt);
     if (forced) {
       H2D(n->d_forced_ptr, f_ptr.data(), f_ptr.size() * 8);
-      H2D(n->d_forced_step, b->forced_step, b->n_forced * 4);
-      H2D(n->d_forced_neuron, b->forced_neuron, b->n_forced * 4);
+      H2D(st_f_step, b->forced_step, b->n_forced * 4);
+      H2D(st_f_neuron, b->forced_neuron, b->n_forced * 4);
     }
   }
   restage();
@@ -1318,8 +1316,10 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   }
   (void)hipEventRecord(n->ev[7], s);
   {
-    std::vector<double> loss(ntr);
-    std::vector<uint32_t> pred(ntr);
+    std::vector<double> &loss = n->h_loss;
+    std::vector<uint32_t> &pred = n->h_pred;
+    loss.resize(ntr);
+    pred.resize(ntr);
     unsigned long long cnt[eprop::CNT_WORDS] = {}, ev[64] = {};
     uint32_t flags = 0;
     if (e == hipSuccess) e = hipGetLastError();
@@ -1657,11 +1657,12 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   const bool per_trial = (what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V) || what == EPROP_STATE_L;
   if (what < 0 || what > EPROP_STATE_INPUT_BOUND) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
-    const uint64_t lay[15] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
+    const uint64_t lay[17] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                               n->blk, n->gather ? 1u : 0u, eprop::fwd_variant_piece(n->shapes.fwd_variant),
                               eprop::fwd_variant_unroll(n->shapes.fwd_variant), n->shapes.adj_block,
                               n->tuned ? 1u : 0u, d.ptab_cap, eprop::syn_variant_pre(n->shapes.syn_var),
-                              eprop::syn_variant_batch(n->shapes.syn_var)};
+                              eprop::syn_variant_batch(n->shapes.syn_var), n->blocked ? 1u : 0u,
+                              n->shapes.fwd_trials ? n->shapes.fwd_trials : n->Bcap};
     if (needed) *needed = sizeof(lay);
     if (!dst) return EPROP_OK;
     if (dst_bytes < sizeof(lay)) return EPROP_ERR_INVALID_ARGUMENT;

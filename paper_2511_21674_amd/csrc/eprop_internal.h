@@ -199,6 +199,7 @@ struct Shapes {
   uint32_t fwd_variant;         // delivery variant of the forward kernel (piece size, pieces in flight)
   uint32_t adj_block;           // threads per block of the adjoint kernel (64, 128 or 256)
   uint32_t syn_var;             // synapse kernel variant: header prefetch and synapses per thread at a time
+  uint32_t fwd_trials;          // trials per launch of the tiled forward kernel (all of them resident together)
 };
 uint32_t fwd_variant_piece(uint32_t v);
 uint32_t fwd_variant_unroll(uint32_t v);

@@ -510,19 +510,20 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   }
 }
 
-// Persistent forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps.  Workgroup
-// (b, k) owns neurons [k*TS, k*TS + TS) of trial b; their delay ring and
+// Persistent forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps of trials
+// b0 .. b0 + gridDim.x / KT - 1.  Workgroup (b, k) owns neurons
+// [k*TS, k*TS + TS) of trial b; their delay ring and
 // state stay in LDS for the whole launch.  Per step: neuron update of the
 // tile, spike publication (bitset, spike times, the tile's tagged spike list
 // and count), then delivery of all tiles' spikes of the step into the
 // tile's ring, reading each tile's list as soon as its tag shows up.  The
 // KT workgroups of a trial must be resident together (checked on the host).
 template <typename real, typename ring_t, bool FORCED, uint32_t VAR>
-__global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps) {
+__global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps, uint32_t b0) {
   constexpr uint32_t P = fwd_piece(VAR), U = fwd_unroll(VAR);
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t KT = n.KT, TS = n.TS;
-  const uint32_t b = blockIdx.x / KT, k = blockIdx.x - b * KT;
+  const uint32_t bl = blockIdx.x / KT, k = blockIdx.x - bl * KT, b = b0 + bl;
   if (b >= n.ctl[CTL_NTRIALS]) return;
   const uint32_t Tb = n.T[b];
   const uint32_t t0 = n.ctl[CTL_T0];
@@ -2038,19 +2039,19 @@ struct FwdKernels {
   }
   static const void *get(bool forced, uint32_t v) { return forced ? get_v<true>(v) : get_v<false>(v); }
   template <bool F>
-  static void launch_v(const DevNet<real> &n, uint32_t nsteps, uint32_t v, uint32_t grid, uint32_t block,
-                       size_t smem, hipStream_t s) {
+  static void launch_v(const DevNet<real> &n, uint32_t nsteps, uint32_t b0, uint32_t v, uint32_t grid,
+                       uint32_t block, size_t smem, hipStream_t s) {
     switch (v) {
-      case 1: k_forward_tiled<real, ring_t, F, 1><<<grid, block, smem, s>>>(n, nsteps); break;
-      case 2: k_forward_tiled<real, ring_t, F, 2><<<grid, block, smem, s>>>(n, nsteps); break;
-      case 3: k_forward_tiled<real, ring_t, F, 3><<<grid, block, smem, s>>>(n, nsteps); break;
-      default: k_forward_tiled<real, ring_t, F, 0><<<grid, block, smem, s>>>(n, nsteps); break;
+      case 1: k_forward_tiled<real, ring_t, F, 1><<<grid, block, smem, s>>>(n, nsteps, b0); break;
+      case 2: k_forward_tiled<real, ring_t, F, 2><<<grid, block, smem, s>>>(n, nsteps, b0); break;
+      case 3: k_forward_tiled<real, ring_t, F, 3><<<grid, block, smem, s>>>(n, nsteps, b0); break;
+      default: k_forward_tiled<real, ring_t, F, 0><<<grid, block, smem, s>>>(n, nsteps, b0); break;
     }
   }
-  static void launch(const DevNet<real> &n, uint32_t nsteps, bool forced, uint32_t v, uint32_t grid, uint32_t block,
-                     size_t smem, hipStream_t s) {
-    if (forced) launch_v<true>(n, nsteps, v, grid, block, smem, s);
-    else launch_v<false>(n, nsteps, v, grid, block, smem, s);
+  static void launch(const DevNet<real> &n, uint32_t nsteps, uint32_t b0, bool forced, uint32_t v, uint32_t grid,
+                     uint32_t block, size_t smem, hipStream_t s) {
+    if (forced) launch_v<true>(n, nsteps, b0, v, grid, block, smem, s);
+    else launch_v<false>(n, nsteps, b0, v, grid, block, smem, s);
   }
 };
 
@@ -2085,14 +2086,23 @@ hipError_t Launch<real>::resident(uint32_t block, size_t smem, uint32_t ring_byt
   return hipSuccess;
 }
 
+// The trials' tiles wait for each other within a trial, so every launch holds
+// only as many trials as the device keeps resident together (sh.fwd_trials);
+// larger batches run in consecutive launches of such chunks.
 template <typename real>
 void Launch<real>::forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool forced, const Shapes &sh, size_t smem,
                                  hipStream_t s) {
-  const uint32_t grid = n.Bcap * n.KT;
   const uint32_t v = sh.fwd_variant < kFwdVariants ? sh.fwd_variant : 0u;
-  if constexpr (sizeof(real) == 8) FwdKernels<double, double>::launch(n, nsteps, forced, v, grid, sh.tile_block, smem, s);
-  else if (n.ring_bytes == 8) FwdKernels<float, int64_t>::launch(n, nsteps, forced, v, grid, sh.tile_block, smem, s);
-  else FwdKernels<float, int32_t>::launch(n, nsteps, forced, v, grid, sh.tile_block, smem, s);
+  const uint32_t per = sh.fwd_trials ? sh.fwd_trials : n.Bcap;
+  for (uint32_t b0 = 0; b0 < n.Bcap; b0 += per) {
+    const uint32_t grid = (b0 + per <= n.Bcap ? per : n.Bcap - b0) * n.KT;
+    if constexpr (sizeof(real) == 8)
+      FwdKernels<double, double>::launch(n, nsteps, b0, forced, v, grid, sh.tile_block, smem, s);
+    else if (n.ring_bytes == 8)
+      FwdKernels<float, int64_t>::launch(n, nsteps, b0, forced, v, grid, sh.tile_block, smem, s);
+    else
+      FwdKernels<float, int32_t>::launch(n, nsteps, b0, forced, v, grid, sh.tile_block, smem, s);
+  }
 }
 
 template <typename real>

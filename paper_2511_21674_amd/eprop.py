@@ -355,7 +355,8 @@ class Network:
         v = [int(x) for x in self.read(EPROP_STATE_LAYOUT)]
         return dict(zip(("tile_neurons", "tiles", "ring_bytes", "tile_threads", "synapse_threads",
                          "synapse_trials", "steps_per_launch", "gather", "piece", "pieces_in_flight",
-                         "adjoint_threads", "autotuned", "piece_table", "synapse_prefetch", "synapse_batch"), v))
+                         "adjoint_threads", "autotuned", "piece_table", "synapse_prefetch", "synapse_batch",
+                         "blocked_update", "forward_trials_per_launch"), v))
 
     def weights(self) -> dict:
         return {"w_in": self.read(EPROP_STATE_W_IN), "w_rec": self.read(EPROP_STATE_W_REC),

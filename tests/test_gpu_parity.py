@@ -105,6 +105,184 @@ def assert_fp64_parity(gh, oh, name):
             f"{max(rel_close(gh['grads'][it][k], oh['grads'][it][k], 1)[1] for k in KEYS):.2e}")
 
 
+# ----------------------------------------------------------------- FP32 checks
+
+U32 = 2.0 ** -24
+
+
+def oracle_at(wnet, weights, m=None, v=None, step=0):
+    """The oracle at the GPU's own weights (FP32 values, read back as FP64)
+    and feedback weights rounded to FP32 like the library's copy; optionally
+    the GPU's Adam state (m, v, step) for the optimiser check."""
+    on = O.OracleNet(wnet)
+    on.w_in = np.array(weights["w_in"], dtype=np.float64)
+    on.w_rec = np.array(weights["w_rec"], dtype=np.float64)
+    on.w_out = np.array(weights["w_out"], dtype=np.float64, order="C").reshape(wnet.n_out, wnet.n_rec)
+    on.fb = np.ascontiguousarray(np.asarray(wnet.feedback, np.float64).astype(np.float32).astype(np.float64))
+    if m is not None:
+        on.m = {k: np.array(m[k], dtype=np.float64).reshape(on.m[k].shape) for k in KEYS}
+        on.v = {k: np.array(v[k], dtype=np.float64).reshape(on.v[k].shape) for k in KEYS}
+        on.step = int(step)
+    return on
+
+
+def read_psis(net, b, targets=None):
+    """The recorded surrogate gradients of every trial of the last batch, [T, J]."""
+    J = net.wnet.n_rec
+    out = []
+    for i in range(b.n_trials):
+        T = int(b.n_steps[i])
+        out.append(net.read(E.EPROP_STATE_PSI, i).reshape(T, J))
+    return out
+
+
+def check_fp32_batch(name, wnet, b, psis, G, weights, quantum=0.0, targets=None, downstream=1.0, keys=KEYS):
+    """FP32 gradient of a teacher-forced batch, evaluated by the GPU at
+    `weights` (its own FP32 values), against the FP64 oracle at the same
+    weights (orc_fp32_bounds):
+      (A) normwise: ||G - g|| <= 1e-4 ||g|| for each weight array (the
+          tolerance of the FP32 mode);
+      (C) every recorded psi within the running-error bound of an FP32
+          evaluation of the neuron recursion;
+      (D) every gradient entry within `downstream` times the rounding bound
+          of FP32 arithmetic downstream of psi (7 u times the sum of the
+          absolute values of the entry's terms) of the oracle's gradient on
+          the GPU's own psi history (Alg. "time-driven gradient computation"
+          takes the archived psi).  Together (C) and (D) bound every entry's
+          error against the oracle's own gradient.
+    Returns per-array statistics."""
+    on = oracle_at(wnet, weights)
+    g_own = {k: None for k in keys}
+    g_giv = {k: None for k in keys}
+    bnd = {k: None for k in keys}
+    worst_psi = 0.0
+    for i in range(b.n_trials):
+        own = O.fp32_bounds(on, b, i, quantum, targets=targets)
+        pg = psis[i] if targets is None else psis[i][:, targets]
+        giv = O.fp32_bounds(on, b, i, quantum, psi_given=pg, targets=targets)
+        err = np.abs(pg - own["psi"])
+        bad = err > own["psi_bound"]
+        assert not bad.any(), (name, "psi", i, int(bad.sum()), float(err[bad].max()))
+        if np.any(own["psi_bound"] > 0):
+            worst_psi = max(worst_psi, float((err / np.maximum(own["psi_bound"], 1e-300)).max()))
+        for k in keys:
+            for acc, src in ((g_own, own["g"]), (g_giv, giv["g"]), (bnd, giv["b"])):
+                acc[k] = src[k].copy() if acc[k] is None else acc[k] + src[k]
+    stats = {"psi_err_over_bound": worst_psi}
+    for k in keys:
+        gk = np.asarray(G[k], np.float64).reshape(g_own[k].shape)
+        m = ~np.isnan(g_own[k])
+        a, ref, giv, bd = gk[m], g_own[k][m], g_giv[k][m], bnd[k][m]
+        nrm = np.linalg.norm(ref)
+        nerr = float(np.linalg.norm(a - ref) / nrm) if nrm > 0 else float(np.linalg.norm(a))
+        assert nerr <= 1e-4, (name, k, "normwise", nerr)
+        dev = np.abs(a - giv)
+        lim = downstream * bd + 1e-12 * np.abs(giv).max(initial=0.0)
+        assert np.all(dev <= lim), (name, k, "entry", int((dev > lim).sum()), float((dev / np.maximum(lim, 1e-300)).max()))
+        z21 = np.abs(a - ref) > 1e-4 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max(initial=0.0))
+        stats[k] = {"normwise": nerr, "entry_over_bound": float((dev / np.maximum(lim, 1e-300)).max(initial=0.0)),
+                    "beyond_z21": int(z21.sum()), "n": int(a.size)}
+    log(f"{name}: psi err/bound {worst_psi:.3f}; " + "; ".join(
+        f"{k} normwise {stats[k]['normwise']:.1e}, entry/bound {stats[k]['entry_over_bound']:.3f}, "
+        f"{stats[k]['beyond_z21']} of {stats[k]['n']} beyond 1e-4 x max(|g|, 1e-3 |g|max)" for k in keys))
+    return stats
+
+
+def read_adam(net):
+    ids = {"w_in": (E.EPROP_STATE_ADAM_M_IN, E.EPROP_STATE_ADAM_V_IN),
+           "w_rec": (E.EPROP_STATE_ADAM_M_REC, E.EPROP_STATE_ADAM_V_REC),
+           "w_out": (E.EPROP_STATE_ADAM_M_OUT, E.EPROP_STATE_ADAM_V_OUT)}
+    m = {k: net.read(ids[k][0]) for k in KEYS}
+    v = {k: net.read(ids[k][1]) for k in KEYS}
+    return m, v, int(net.read(E.EPROP_STATE_ADAM_STEP)[0])
+
+
+def check_optimizer(name, wnet, w_before, G, n_trials, w_after, adam_before=None, adam_after=None):
+    """The update given the GPU's own gradient sums G: the oracle's gradient
+    descent or Adam (eq. gradient-descent; eq. eta-adam-fast,
+    eq. delta-w-adam-fast) from the GPU's weights (and Adam state) in FP64.
+    The library may round the averaged gradient to FP32 before the step and
+    stores the weights (and moments) in FP32, so each result is within
+    u |x_exp| plus the change of the oracle's result when G moves by a
+    relative u (evaluated at G (1 - u) and G (1 + u))."""
+    def step(scale):
+        on = oracle_at(wnet, w_before, *adam_before) if adam_before is not None else oracle_at(wnet, w_before)
+        O.apply(on, {k: np.array(G[k], np.float64).reshape(getattr(on, k).shape) * scale for k in KEYS}, n_trials)
+        return on
+    on, lo, hi = step(1.0), step(1.0 - U32), step(1.0 + U32)
+    for k in KEYS:
+        exp = getattr(on, k).ravel()
+        sens = np.maximum(np.abs(getattr(lo, k).ravel() - exp), np.abs(getattr(hi, k).ravel() - exp))
+        got = np.asarray(w_after[k], np.float64).ravel()
+        lim = U32 * np.abs(exp) + 1.01 * sens + 1e-300
+        dev = np.abs(got - exp)
+        assert np.all(dev <= lim), (name, k, float((dev / lim).max()))
+    if adam_after is not None:
+        m1, v1, st = adam_after
+        assert st == on.step, (name, st, on.step)
+        for k in KEYS:
+            for got, exp, e_lo, e_hi in ((m1[k], on.m[k], lo.m[k], hi.m[k]), (v1[k], on.v[k], lo.v[k], hi.v[k])):
+                exp = exp.ravel()
+                sens = np.maximum(np.abs(e_lo.ravel() - exp), np.abs(e_hi.ravel() - exp))
+                lim = U32 * np.abs(exp) + 1.01 * sens + 1e-300
+                assert np.all(np.abs(np.asarray(got).ravel() - exp) <= lim), (name, k)
+
+
+def ring_quantum(net):
+    """The largest rounding of one arriving weight by the delay ring: 0 for
+    64-bit entries (every FP32 weight converts exactly), 2^-(F+1) for 32-bit
+    entries with F = 30 - ceil(log2(input bound)) fraction bits."""
+    if net.layout()["ring_bytes"] != 4:
+        return 0.0
+    import math
+    l1 = float(net.read(E.EPROP_STATE_INPUT_BOUND)[0])
+    F = 30 if l1 <= 0 else min(30, 30 - math.ceil(math.log2(l1)))
+    return 2.0 ** -(F + 1)
+
+
+def fp32_forced_run(name, wl, iterations, bs, rate=20.0, time_driven=False, autotune=False, T=None, max_delay=None,
+                    expect_layout=None):
+    """Teacher-forced FP32 training on the GPU (forced Poisson trains at
+    `rate` Hz, or the batch's own forced trains with rate None); every
+    iteration's gradient is checked against the oracle at the GPU's weights
+    (check_fp32_batch), its loss against the oracle's (identical spikes and
+    FP32 weights, FP64 readout: 1e-12), and its update against the optimiser
+    given that gradient (check_optimizer).  The time-driven baseline's FP32
+    eligibility recursions round at most 5 times per step, so a term that
+    meets the learning signal carries at most 5 T u more than the event-driven
+    path's 7 u: its entry bound is scaled by (7 + 5 T) / 7.  Returns the
+    per-iteration statistics."""
+    wnet = wl.network
+    if T is None:
+        T = max(int(wl.make_batch(it, 0, bs).n_steps.max()) for it in range(iterations))
+    net = E.Network(wnet, "fp32", max_trials=bs, max_steps=T, autotune=autotune, max_delay=max_delay)
+    lay = net.layout()
+    for key, val in (expect_layout or {}).items():
+        assert lay[key] == val, (name, key, lay[key], val)
+    adam = wnet.params.optimizer == 1
+    out = []
+    for it in range(iterations):
+        b = wl.make_batch(it, 0, bs)
+        if rate is not None:
+            b = W.forced_poisson(b, wnet.n_rec, rate, wnet.params.dt, seed=99, iteration=it, n_ref=2)
+        w0 = net.weights()
+        a0 = read_adam(net) if adam else None
+        quantum = ring_quantum(net)
+        r = net.simulate(b, train=True, time_driven=time_driven)
+        G = net.grads()
+        psis = read_psis(net, b)
+        st = check_fp32_batch(f"{name} it {it}", wnet, b, psis, G, w0, quantum=quantum,
+                              downstream=(7.0 + 5.0 * T) / 7.0 if time_driven else 1.0)
+        on = oracle_at(wnet, w0)
+        lo = [O.run_trial(on, b, i, 0).loss for i in range(b.n_trials)]
+        assert rel_close(r.loss, lo, 1e-12)[0], (name, it, "loss")
+        net.apply()
+        check_optimizer(f"{name} it {it}", wnet, w0, G, b.n_trials, net.weights(), a0, read_adam(net) if adam else None)
+        out.append(st)
+    net.close()
+    return out
+
+
 # ----------------------------------------------------------------- FP64: exact reproduction
 
 @pytest.mark.parametrize("loss,surrogate", [(0, 0), (1, 0), (0, 1), (1, 1)])
@@ -221,15 +399,15 @@ def test_class_prediction_constructed_case(precision, delivery, loss):
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4twin", "tiny"])
 def test_fp32_teacher_forced_weight_updates(name):
-    """FP32 with the oracle's (teacher-forced) spike trains: each
-    iteration's computed update (the batch-summed gradient that the
-    optimiser receives) within 1e-4 relative of the FP64 oracle's; the stored
-    FP32 weights within that plus FP32 rounding of the weights themselves."""
+    """FP32 with teacher-forced spike trains, every iteration at the GPU's own
+    weights: the computed update (the batch-summed gradient the optimiser
+    receives) within 1e-4 normwise of the FP64 oracle's, every recorded psi
+    and every gradient entry within its derived FP32 rounding bound
+    (check_fp32_batch), the loss within 1e-12, and the stored weights (and
+    Adam moments, c2) the optimiser's result on that gradient rounded once
+    to FP32."""
     if name == "c1":
-        # as configured (GD 1e-3) the loss grows to 1e9 by the third iteration;
-        # the check runs in the trained regime instead
         wl, bs, it = W.c1_pattern(), 1, 3
-        wl.network.params.eta = 2e-5
     elif name == "c2":
         wl, bs, it = W.c2_evidence(batch_size=4), 4, 2
     elif name == "c3":
@@ -238,41 +416,43 @@ def test_fp32_teacher_forced_weight_updates(name):
         wl, bs, it = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), 2, 2
     else:
         wl, bs, it = W.tiny(), 2, 3
-    gh = gpu_train(wl, "fp32", it, bs, forced_rate=20.0)
-    oh = oracle_train(wl, it, bs, forced_rate=20.0)
-    u = 2.0 ** -24
-    bound = {k: 0.0 for k in KEYS}
-    for i in range(it):
-        for k in KEYS:
-            ok, e, ent = rel_close(gh["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
-            log(f"{name} it {i} update {k}: normwise {e:.2e} worst entry {ent:.2e}")
-            assert ok, (name, i, k, e, ent)
-            # stored weights: this and earlier updates' tolerance plus FP32 rounding of w
-            dw_o = np.abs(oh["dw"][i][k])
-            bound[k] = bound[k] + 1e-4 * np.maximum(dw_o, 1e-2 * dw_o.max()) + 4 * u * np.abs(oh["weights"][i][k])
-            assert np.all(np.abs(gh["weights"][i][k] - oh["weights"][i][k]) <= bound[k]), (name, i, k)
-        assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
+    fp32_forced_run(name, wl, it, bs)
 
 
 def test_fp32_free_running_final_loss():
-    """Trained pattern-generation runs (learning rate 1e-6, where gradient
-    descent on the summed loss converges): FP32 final loss within 2% of the
-    FP64 oracle's, as the mean over the last 20 of 40 iterations and over 5
-    seeds (single runs decorrelate through spike flips)."""
-    g_final, o_final, first = [], [], []
-    for s in range(5):
-        wl = W.c1_pattern(seed=W.SEED_BASE + 100 + s)
-        wl.network.params.eta = 1e-6
-        gh = gpu_train(wl, "fp32", 40, 1, record=False)
-        oh = oracle_train(wl, 40, 1)
-        g_final.append(np.mean([l.mean() for l in gh["loss"][20:]]))
-        o_final.append(np.mean([l.mean() for l in oh["loss"][20:]]))
-        first.append(oh["loss"][0][0])
-        log(f"seed {s}: first loss {first[-1]:.1f}, final gpu {g_final[-1]:.2f} oracle {o_final[-1]:.2f}")
-        assert o_final[-1] < first[-1]          # training reduced the loss
-    assert np.mean(o_final) < 0.8 * np.mean(first)
+    """Free-running FP32 batched training of the evidence-accumulation task
+    (Results, "Evidence accumulation": softmax cross-entropy in the recall
+    window, LIF + ALIF, Adam 5e-3; 32 trials per iteration, 100 iterations,
+    three network seeds) against the FP64 oracle's training of the same
+    batches from the same weights, stored by tests/golden/make_c2_training.py
+    (which calls only the oracle): the oracle's training lowers the loss, and
+    the GPU's final loss -- the mean over the last 10 iterations, averaged
+    over the seeds (reading Z22) -- is within 2% of the oracle's.  Single
+    seeds are logged: free-running runs decorrelate through spike flips."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_training_oracle.json")))
+    it, bs = ref["iterations"], ref["batch"]
+    g_final, o_final = [], []
+    for run in ref["runs"]:
+        wl = W.c2_evidence(seed=run["seed"], batch_size=bs)
+        net = E.Network(wl.network, "fp32", max_trials=bs, max_steps=1800)
+        losses, acc = [], []
+        for i in range(it):
+            b = wl.make_batch(i, 0, bs)
+            r = net.simulate(b, train=True)
+            net.apply()
+            losses.append(float(r.loss.mean()))
+            acc.append(float(np.mean(r.predicted == b.label)))
+        net.close()
+        o = run["mean_loss"]
+        assert np.mean(o[-10:]) < 0.8 * np.mean(o[:10]), "the oracle's training did not lower the loss"
+        g_final.append(np.mean(losses[-10:]))
+        o_final.append(np.mean(o[-10:]))
+        log(f"seed {run['seed']}: loss {np.mean(o[:10]):.1f} -> oracle {o_final[-1]:.2f}, gpu {g_final[-1]:.2f}; "
+            f"accuracy (last 10) oracle {np.mean(run['accuracy'][-10:]):.3f}, gpu {np.mean(acc[-10:]):.3f}")
     rel = abs(np.mean(g_final) - np.mean(o_final)) / np.mean(o_final)
-    log(f"mean final loss gpu {np.mean(g_final):.3f} oracle {np.mean(o_final):.3f} rel {rel:.3e}")
+    log(f"final loss over seeds: gpu {np.mean(g_final):.3f}, oracle {np.mean(o_final):.3f}, relative {rel:.3e}")
     assert rel < 0.02
 
 
@@ -341,32 +521,110 @@ def test_errors_are_reported():
 
 def test_full_size_sparse_network_sampled():
     """1e5 neurons, in-degree 1000, delays 1..5, 4 trials per batch, FP32
-    scatter (the benchmark's launch configuration), teacher-forced at 10 Hz:
-    the gradients of every incoming synapse of 24 sampled neurons, summed
-    over the 4 trials, within 1e-4 of the oracle's per-neuron evaluation, and
-    the per-trial losses within 1e-6."""
+    scatter with the autotuner on (the benchmark's launch configuration: the
+    tuner runs on this first training batch), teacher-forced at 10 Hz: the
+    gradients of every incoming synapse of 24 sampled neurons and of every
+    output synapse, summed over the 4 trials, against the oracle's per-neuron
+    evaluation (check_fp32_batch: 1e-4 normwise, every sampled psi and every
+    entry within its FP32 bound), and the per-trial losses within 1e-12."""
     wl = W.c4_sparse()
     b = W.forced_poisson(wl.make_batch(0, 0, 4), wl.network.n_rec, 10.0, 1.0, seed=7, n_ref=2)
-    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=1000)
+    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=1000, autotune=True)
+    w0 = net.weights()
     r = net.simulate(b, train=True)
-    g = net.grads()
+    lay = net.layout()
+    assert lay["autotuned"] == 1
+    G = net.grads()
+    psis = read_psis(net, b)
     net.close()
-    log(f"gpu done: {r.n_rec_spikes} spikes, {r.n_syn_events} events")
-    on = O.OracleNet(wl.network)
-    rng = np.random.default_rng(0)
-    targets = np.sort(rng.choice(wl.network.n_rec, 24, replace=False))
-    gi = np.zeros_like(on.w_in)
-    gr = np.zeros_like(on.w_rec)
+    log(f"gpu done: {r.n_rec_spikes} spikes, {r.n_syn_events} events, layout {lay}")
+    targets = np.sort(np.random.default_rng(0).choice(wl.network.n_rec, 24, replace=False))
+    check_fp32_batch("full size", wl.network, b, psis, G, w0, targets=targets)
+    on = oracle_at(wl.network, w0)
     for i in range(4):
-        loss, psi, a, c = O.forced_sampled(on, b, i, targets)
-        assert abs(r.loss[i] - loss) <= 1e-6 * abs(loss), (i, r.loss[i], loss)
-        mi, mr = ~np.isnan(a), ~np.isnan(c)
-        gi[mi] += a[mi]
-        gr[mr] += c[mr]
-    for name, gg, ref, m in (("w_in", g["w_in"], gi, mi), ("w_rec", g["w_rec"], gr, mr)):
-        ok, e, ent = rel_close(gg[m], ref[m], 1e-4, floor_frac=1e-2)
-        log(f"full size {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
-        assert ok, (name, e, ent)
+        loss = O.forced_sampled(on, b, i, targets[:1])[0]
+        assert abs(r.loss[i] - loss) <= 1e-12 * abs(loss), (i, r.loss[i], loss)
+
+
+C5_TWIN_RING_STEPS = 40   # delay capacity of the twin's handle (its graph keeps delays 1..5)
+
+
+def _c5_twin():
+    """Twin of the million-neuron network (80/20 LIF/ALIF, fixed in-degree
+    100, delays 1..5, 10 input synapses per neuron at 5 Hz, one trial) at
+    40,000 neurons.  Given a delay capacity of 40 steps, 8-byte ring entries
+    of 512-neuron tiles do not fit LDS, so the handle takes the 32-bit
+    fixed-point ring, as the full network does; rows have under 4 synapses per
+    source and tile, so the update runs in target-major order (k_apply_syn with
+    k_input_bound), also as at full size."""
+    return W.c5_million(n_rec=40_000, n_steps=200, batch_size=1, n_in=1000)
+
+
+def test_c5_twin_fp64_exact():
+    """The twin in FP64 (deterministic gather delivery): spike trains
+    identical to the oracle's, loss, gradients and weights within 1e-10, over
+    two iterations with an update between them."""
+    wl = _c5_twin()
+    assert wl.network.is_alif.sum() == 8000
+    gh = gpu_train(wl, "fp64", 2, 1)
+    oh = oracle_train(wl, 2, 1)
+    assert_fp64_parity(gh, oh, "c5 twin")
+
+
+def test_c5_twin_fp32_ring32_unblocked_alif():
+    """The twin in FP32 with the paths the million-neuron network takes: the
+    32-bit fixed-point delay ring (each arriving weight rounded to 2^-(F+1),
+    part of the psi bound), ALIF neurons in the multi-tile forward kernel,
+    and the target-major update with the input-bound pass.  Teacher-forced,
+    two iterations: each gradient, loss and update checked against the oracle
+    at the GPU's weights (fp32_forced_run); the input bound read back after
+    each update stays above the largest sum of |w| into one target."""
+    wl = _c5_twin()
+    fp32_forced_run("c5 twin", wl, 2, 1, rate=5.0, max_delay=C5_TWIN_RING_STEPS,
+                    expect_layout={"ring_bytes": 4, "blocked_update": 0, "gather": 0})
+    net = E.Network(wl.network, "fp32", max_trials=1, max_steps=200, max_delay=C5_TWIN_RING_STEPS)
+    assert net.layout()["tiles"] > 1
+    for it in range(2):
+        net.simulate(W.forced_poisson(wl.make_batch(it, 0, 1), wl.network.n_rec, 5.0, 1.0, seed=99, iteration=it,
+                                      n_ref=2))
+        net.apply()
+        w = net.weights()
+        l1 = np.zeros(wl.network.n_rec)
+        np.add.at(l1, wl.network.in_rec.col, np.abs(w["w_in"]))
+        np.add.at(l1, wl.network.rec_rec.col, np.abs(w["w_rec"]))
+        bound = float(net.read(E.EPROP_STATE_INPUT_BOUND)[0])
+        assert l1.max() <= bound <= l1.max() * 1.001 * (1 + 1e-6), (it, bound, l1.max())
+    net.close()
+
+
+def test_full_size_million_neuron_network_sampled():
+    """The million-neuron network (10^6 neurons, 20% ALIF, in-degree 100,
+    delays 1..5, one 2000-step trial) in the benchmark's launch configuration
+    (FP32, autotuner on, 32-bit ring, target-major update), teacher-forced at
+    5 Hz: the gradients of every incoming synapse of 24 sampled neurons and of
+    every output synapse against the oracle's per-neuron evaluation
+    (check_fp32_batch), the loss within 1e-12."""
+    wl = W.c5_million()
+    b = W.forced_poisson(wl.make_batch(0, 0, 1), wl.network.n_rec, 5.0, 1.0, seed=7, n_ref=2)
+    net = E.Network(wl.network, "fp32", max_trials=1, max_steps=2000, autotune=True)
+    lay = net.layout()
+    assert lay["ring_bytes"] == 4 and lay["blocked_update"] == 0, lay
+    w0 = net.weights()
+    quantum = ring_quantum(net)
+    r = net.simulate(b, train=True)
+    G = net.grads()
+    psis = read_psis(net, b)
+    lay = net.layout()
+    net.close()
+    assert lay["autotuned"] == 1
+    log(f"gpu done: {r.n_rec_spikes} spikes, {r.n_syn_events} events, layout {lay}")
+    rng = np.random.default_rng(2)
+    alif = np.flatnonzero(wl.network.is_alif)
+    lif = np.flatnonzero(wl.network.is_alif == 0)
+    targets = np.sort(np.concatenate([rng.choice(lif, 16, replace=False), rng.choice(alif, 8, replace=False)]))
+    check_fp32_batch("million", wl.network, b, psis, G, w0, quantum=quantum, targets=targets)
+    loss = O.forced_sampled(oracle_at(wl.network, w0), b, 0, targets[:1])[0]
+    assert abs(r.loss[0] - loss) <= 1e-12 * abs(loss), (r.loss[0], loss)
 
 
 # ----------------------------------------------------------------- recordings, counters, allocator
@@ -475,31 +733,65 @@ def test_fp32_multi_tile_runs_are_deterministic():
         assert np.array_equal(runs[0][1][k], runs[1][1][k])
 
 
+def test_forward_launches_in_chunks_of_resident_trials():
+    """A batch whose tiles do not all fit on the device at once (200 trials
+    of a 3000-neuron network: about 2 tiles of 1500-2400 neurons each, one
+    per CU) runs the forward pass in consecutive launches of as many trials
+    as are resident together, so no trial waits on tiles that are not
+    running; every trial's loss, spikes and the summed gradient equal those
+    of the same trials in batches of 8 (FP32 results do not depend on the
+    batch, the input currents being exact fixed-point sums)."""
+    wl = W.c4_sparse(n_rec=3000, n_steps=60, batch_size=200, n_in=300)
+    big = wl.make_batch(0, 0, 200)
+    net = E.Network(wl.network, "fp32", max_trials=200, max_steps=60)
+    lay = net.layout()
+    log(f"layout {lay}")
+    assert lay["tiles"] > 1 and lay["forward_trials_per_launch"] * lay["tiles"] <= 256 * 8
+    assert lay["forward_trials_per_launch"] < 200
+    r = net.simulate(big)
+    spikes = [net.read(E.EPROP_STATE_SPIKES, i) for i in range(200)]
+    g = net.grads()
+    net.close()
+    net = E.Network(wl.network, "fp32", max_trials=8, max_steps=60)
+    assert net.layout()["forward_trials_per_launch"] == 8
+    for c in range(0, 200, 8):     # no update between the calls: the gradient sums accumulate
+        part = wl.make_batch(0, c, 8)
+        rp = net.simulate(part)
+        assert np.array_equal(rp.loss, r.loss[c:c + 8])
+        for i in range(8):
+            assert np.array_equal(net.read(E.EPROP_STATE_SPIKES, i), spikes[c + i])
+    gsum = net.grads()
+    net.close()
+    for k in KEYS:
+        ok, e, ent = rel_close(g[k], gsum[k], 1e-6)
+        assert ok, (k, e, ent)
+
+
 def test_gradients_restart_after_an_update():
     """After an update the accumulated gradient reads as zero, and the next
     training batch's gradient is that batch's alone (the first batch after an
-    update writes the gradient pairs instead of adding to them): checked
-    against the time-driven gradient of the same batch on the same updated
-    weights, in the blocked-update layout."""
+    update writes the gradient pairs instead of adding to them): the
+    event-driven and the time-driven gradient of the next (teacher-forced)
+    batch, each checked against the oracle at the updated weights
+    (check_fp32_batch), in the blocked-update layout."""
     wl = W.c4_sparse(n_rec=3000, n_steps=300, batch_size=2, n_in=300)
-    b0, b1 = wl.make_batch(0, 0, 2), wl.make_batch(1, 0, 2)
-    grads = []
+    forced = [W.forced_poisson(wl.make_batch(i, 0, 2), wl.network.n_rec, 10.0, 1.0, seed=11, iteration=i, n_ref=2)
+              for i in range(2)]
     for time_driven in (False, True):
         net = E.Network(wl.network, "fp32", max_trials=2, max_steps=300)
-        net.simulate(b0)
+        net.simulate(forced[0])
         g0 = net.grads()
         assert all(np.abs(g0[k]).max() > 0 for k in KEYS)
         net.apply()
         gz = net.grads()
         for k in ("w_in", "w_rec"):
             assert not np.any(gz[k]), k
-        net.simulate(b1, time_driven=time_driven)
-        grads.append(net.grads())
+        w1 = net.weights()
+        net.simulate(forced[1], time_driven=time_driven)
+        check_fp32_batch(f"restart {'time' if time_driven else 'event'}-driven", wl.network, forced[1],
+                         read_psis(net, forced[1]), net.grads(), w1,
+                         downstream=(7.0 + 5.0 * 300) / 7.0 if time_driven else 1.0)
         net.close()
-    for k in ("w_in", "w_rec"):
-        ok, e, ent = rel_close(grads[0][k], grads[1][k], 1e-4, floor_frac=1e-2)
-        log(f"restart {k}: normwise {e:.2e} worst {ent:.2e}")
-        assert ok, (k, e, ent)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -572,14 +864,10 @@ def test_time_driven_baseline_fp64_matches_oracle(name):
 
 
 def test_time_driven_baseline_fp32_teacher_forced():
-    """FP32 time-driven gradient with the oracle's spike trains within 1e-4."""
-    wl = W.c3_events(batch_size=3)
-    td = _train_mode(wl, "fp32", 1, 3, True, forced_rate=20.0)
-    oh = oracle_train(wl, 1, 3, forced_rate=20.0, grad_mode=1)
-    for k in KEYS:
-        ok, e, ent = rel_close(td[0][1][k], oh["grads"][0][k], 1e-4, floor_frac=1e-2)
-        log(f"c3 time-driven fp32 {k}: normwise {e:.2e} worst {ent:.2e}")
-        assert ok, (k, e, ent)
+    """FP32 time-driven gradient with teacher-forced spike trains against the
+    oracle at the GPU's weights (check_fp32_batch with the time-driven
+    recursion's rounding), its loss and its update."""
+    fp32_forced_run("c3 time-driven", W.c3_events(batch_size=3), 1, 3, time_driven=True)
 
 
 # ----------------------------------------------------------------- generalised delays, rate regulariser
@@ -622,22 +910,14 @@ def test_fp64_delays_and_rate_regulariser(name, d, d_ls, c_reg):
 
 @pytest.mark.parametrize("name", ["c3", "c4twin"])
 def test_fp32_teacher_forced_delays_and_rate_regulariser(name):
-    """FP32 with the oracle's spike trains, d = 2, d^ls = 3, regulariser on:
-    each iteration's update within 1e-4 of the FP64 oracle's (event-driven
-    and time-driven paths)."""
+    """FP32 with teacher-forced spike trains, d = 2, d^ls = 3, regulariser on:
+    every iteration's gradient, loss and update checked against the oracle at
+    the GPU's weights (event-driven path, two iterations; time-driven path,
+    one)."""
     wl, bs = _delayed(name, 2, 3, 1e3)
-    gh = gpu_train(wl, "fp32", 2, bs, forced_rate=20.0)
-    oh = oracle_train(wl, 2, bs, forced_rate=20.0)
-    td = _train_mode(wl, "fp32", 1, bs, True, forced_rate=20.0)
-    for i in range(2):
-        for k in KEYS:
-            ok, e, ent = rel_close(gh["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
-            log(f"{name} delays+reg it {i} {k}: normwise {e:.2e} worst entry {ent:.2e}")
-            assert ok, (name, i, k, e, ent)
-        assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
-    for k in KEYS:
-        ok, e, ent = rel_close(td[0][1][k], oh["grads"][0][k], 1e-4, floor_frac=1e-2)
-        assert ok, ("time-driven", name, k, e, ent)
+    fp32_forced_run(f"{name} delays+reg", wl, 2, bs)
+    wl, bs = _delayed(name, 2, 3, 1e3)
+    fp32_forced_run(f"{name} delays+reg time-driven", wl, 1, bs, time_driven=True)
 
 
 # ----------------------------------------------------------------- the scaling network
@@ -651,17 +931,13 @@ def test_scaling_twin_fp64_exact_and_fp32():
     """Twin of the scaling network (Methods, "Scaling": ignore-and-fire
     neurons at 5 Hz, fixed in-degree, sparse readout and feedback): FP64
     exact against the oracle over consecutive samples; FP32 (its spike trains
-    are fixed by construction, so it is teacher-forced) within 1e-4."""
+    are fixed by construction, so it is teacher-forced) checked against the
+    oracle at the GPU's weights every sample (check_fp32_batch)."""
     wl = _scaling_twin()
     oh = oracle_train(wl, 2, 1)
     gh = gpu_train(wl, "fp64", 2, 1)
     assert_fp64_parity(gh, oh, "scaling twin")
-    g32 = gpu_train(wl, "fp32", 2, 1)
-    for i in range(2):
-        for k in KEYS:
-            ok, e, ent = rel_close(g32["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
-            log(f"scaling twin fp32 it {i} {k}: normwise {e:.2e} worst {ent:.2e}")
-            assert ok, (i, k, e, ent)
+    fp32_forced_run("scaling twin", wl, 2, 1, rate=None)
 
 
 def test_scaling_network_launch_configuration_sampled():
@@ -669,57 +945,44 @@ def test_scaling_network_launch_configuration_sampled():
     neurons, one 1000-step sample, FP32, the tile layout of the benchmark)
     with recurrent in-degree 100 instead of 10^4 so that it builds in seconds:
     all 640,000 forced spikes are emitted, and the gradients of every
-    incoming synapse of 24 sampled neurons are within 1e-4 of the oracle's
-    per-neuron evaluation, the loss within 1e-6."""
+    incoming synapse of 24 sampled neurons and of every output synapse are
+    checked against the oracle's per-neuron evaluation (check_fp32_batch),
+    the loss within 1e-12."""
     wl = W.scaling(indeg_rec=100)
     b = wl.make_batch(0, 0, 1)
     net = E.Network(wl.network, "fp32", max_trials=1, max_steps=1000)
+    w0 = net.weights()
     r = net.simulate(b, train=True)
-    g = net.grads()
+    G = net.grads()
+    psis = read_psis(net, b)
     lay = net.layout()
     net.close()
     log(f"gpu done: layout {lay}, {r.n_rec_spikes} spikes, {r.n_syn_events} events")
     assert r.n_rec_spikes == 640_000
-    on = O.OracleNet(wl.network)
     targets = np.sort(np.random.default_rng(1).choice(wl.network.n_rec, 24, replace=False))
-    loss, psi, a, c = O.forced_sampled(on, b, 0, targets)
-    assert abs(r.loss[0] - loss) <= 1e-6 * abs(loss), (r.loss[0], loss)
-    for name, gg, ref in (("w_in", g["w_in"], a), ("w_rec", g["w_rec"], c)):
-        m = ~np.isnan(ref)
-        ok, e, ent = rel_close(gg[m], ref[m], 1e-4, floor_frac=1e-2)
-        log(f"scaling {name}: {m.sum()} synapses, normwise {e:.2e} worst {ent:.2e}")
-        assert ok, (name, e, ent)
+    check_fp32_batch("scaling", wl.network, b, psis, G, w0, targets=targets)
+    loss = O.forced_sampled(oracle_at(wl.network, w0), b, 0, targets[:1])[0]
+    assert abs(r.loss[0] - loss) <= 1e-12 * abs(loss), (r.loss[0], loss)
 
 
 def test_fp32_adam_state_and_input_bound_after_updates():
     """Evidence accumulation with Adam (eq. eta-adam-fast, eq. delta-w-adam-fast),
-    FP32, teacher-forced, three iterations: the optimiser's first and second
-    moments read back in the caller's synapse order within 1e-4 of the
-    oracle's, and the weights likewise; the per-target input bound the
-    update recomputes stays above the largest sum of |w| into one target."""
+    FP32, teacher-forced, three iterations: each iteration's gradient against
+    the oracle at the GPU's weights, and the weights and both moments read
+    back in the caller's synapse order equal to the oracle's Adam step from
+    the GPU's gradient and state, rounded once to FP32 (fp32_forced_run);
+    the per-target input bound the update recomputes stays above the largest
+    sum of |w| into one target."""
     wl = W.c2_evidence(batch_size=4)
     assert wl.network.params.optimizer == 1
-    on = O.OracleNet(wl.network)
-    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=max(int(wl.make_batch(i, 0, 4).n_steps.max())
-                                                                     for i in range(3)))
+    fp32_forced_run("c2 adam", wl, 3, 4)
+    T = max(int(wl.make_batch(i, 0, 4).n_steps.max()) for i in range(3))
+    net = E.Network(wl.network, "fp32", max_trials=4, max_steps=T)
     for it in range(3):
-        b = W.forced_poisson(wl.make_batch(it, 0, 4), wl.network.n_rec, 20.0, 1.0, seed=99, iteration=it, n_ref=2)
-        net.simulate(b, train=True)
+        net.simulate(W.forced_poisson(wl.make_batch(it, 0, 4), wl.network.n_rec, 20.0, 1.0, seed=99, iteration=it,
+                                      n_ref=2), train=True)
         net.apply()
-        g = O.zero_grads(on)
-        for i in range(b.n_trials):
-            O.run_trial(on, b, i, 2, g)
-        O.apply(on, g, b.n_trials)
-    for name, m_id, v_id, key in (("rec", E.EPROP_STATE_ADAM_M_REC, E.EPROP_STATE_ADAM_V_REC, "w_rec"),
-                                  ("in", E.EPROP_STATE_ADAM_M_IN, E.EPROP_STATE_ADAM_V_IN, "w_in")):
-        for sid, ref in ((m_id, on.m[key]), (v_id, on.v[key])):
-            ok, e, ent = rel_close(net.read(sid), ref, 1e-4, floor_frac=1e-2)
-            log(f"adam {name} state {sid}: normwise {e:.2e} worst {ent:.2e}")
-            assert ok, (name, sid, e, ent)
     w = net.weights()
-    for k in KEYS:
-        ok, e, ent = rel_close(w[k], getattr(on, k), 1e-5)
-        assert ok, (k, e, ent)
     # the bound: sum of |w| into each target, from the read-back weights
     pr_in, pr_rec = wl.network.in_rec, wl.network.rec_rec
     l1 = np.zeros(wl.network.n_rec)
@@ -791,17 +1054,12 @@ def test_time_driven_baseline_with_reset_filter_and_temporal_mse():
 
 @pytest.mark.parametrize("name", ["c3", "c4twin"])
 def test_fp32_teacher_forced_eprop_plus_components(name):
-    """FP32 with the oracle's spike trains and every e-prop+ component on:
-    each iteration's update within 1e-4 of the FP64 oracle's."""
+    """FP32 with teacher-forced spike trains and every e-prop+ component on
+    (full reset, decoupled filter, moving-average regulariser, temporal MSE,
+    d = 1): each iteration's gradient, loss and update checked against the
+    oracle at the GPU's weights (fp32_forced_run)."""
     wl, bs = _plus(name, d_out=1)
-    gh = gpu_train(wl, "fp32", 2, bs, forced_rate=20.0)
-    oh = oracle_train(wl, 2, bs, forced_rate=20.0)
-    for i in range(2):
-        for k in KEYS:
-            ok, e, ent = rel_close(gh["grads"][i][k], oh["grads"][i][k], 1e-4, floor_frac=1e-2)
-            log(f"{name} e-prop+ it {i} {k}: normwise {e:.2e} worst entry {ent:.2e}")
-            assert ok, (name, i, k, e, ent)
-        assert rel_close(gh["loss"][i], oh["loss"][i], 1e-4)[0]
+    fp32_forced_run(f"{name} e-prop+", wl, 2, bs)
 
 
 # ----------------------------------------------------------------- e-prop+ update schedule
@@ -814,7 +1072,8 @@ def _online_pair(wl, precision, b, eta):
     r = net.simulate(b, online=True)
     g = {"loss": r.loss.copy(), "z": net.spikes(0, T), "w": net.weights(), "w0": w0, "events": r.n_syn_events}
     net.close()
-    on = O.OracleNet(wl.network)
+    # the oracle starts from the library's initial weights (FP32 values in FP32 mode)
+    on = oracle_at(wl.network, w0) if precision == "fp32" else O.OracleNet(wl.network)
     o = O.run_online(on, b, eta, cutoff=int(wl.network.params.isi_cutoff))
     o["w"] = {k: getattr(on, k).copy() for k in KEYS}
     return g, o
@@ -859,25 +1118,35 @@ def test_online_schedule_fp64_matches_oracle(name, extra):
 
 def test_online_schedule_fp32_ignore_and_fire():
     """FP32 online run of the scaling network's twin (ignore-and-fire spike
-    trains fixed by construction, so FP32 sees the oracle's spikes): the
-    weight changes within 1e-4 of the FP64 oracle's, normwise, and per entry
-    within 1e-4 of max(|change|, 1% of the largest) plus the FP32 rounding of
-    the weight at each of its updates (at most 32 here)."""
+    trains fixed by construction, so FP32 sees the oracle's spikes), both
+    runs from the library's FP32 initial weights: the weight changes within
+    1e-4 of the FP64 oracle's, normwise, and every entry within
+    1e-4 max(|change|, 1e-3 of the largest) plus the FP32 rounding of the
+    weight at each of its updates (at most 32 here) plus (7 + 5 C) u times
+    the absolute term sum of its updates (the oracle's "abs"): the FP32
+    eligibility recursions round at most 5 times per step and restart C
+    (the cutoff) steps after an arrival at the latest, so a term carries at
+    most 5 C u, and the stored learning signal, rates and sums 7 u; the
+    FP32 error of psi (within 0.36 of its running bound, tens of u,
+    wherever the batched tests compare it) is within that margin."""
     wl = _scaling_twin()
     p = wl.network.params
     p.eta, p.d_out, p.isi_cutoff = 1e-4, 1, 100
     b = wl.make_batch(0, 0, 2)
     g, o = _online_pair(wl, "fp32", b, p.eta)
     assert np.array_equal(g["z"], o["z"])
-    w0 = {k: getattr(O.OracleNet(wl.network), k) for k in KEYS}
-    u = 2.0 ** -24
+    w0 = g["w0"]
     for k in KEYS:
-        dg, do = g["w"][k] - w0[k], o["w"][k] - w0[k]
-        ok, e, ent = rel_close(dg, do, 1e-4, floor_frac=1e-2)
+        dg = g["w"][k].ravel() - w0[k].ravel()
+        do = o["w"][k].ravel() - w0[k].ravel()
+        ok, e, ent = rel_close(dg, do, 1e-4)
         log(f"online fp32 {k}: change normwise {e:.2e} worst {ent:.2e}")
         assert e <= 1e-4, (k, e)
-        bound = 1e-4 * np.maximum(np.abs(do), 1e-2 * np.abs(do).max()) + 32 * u * np.abs(o["w"][k])
-        assert np.all(np.abs(dg - do) <= bound), (k, float(np.max(np.abs(dg - do) / bound)))
+        bound = (1e-4 * np.maximum(np.abs(do), 1e-3 * np.abs(do).max()) + 32 * U32 * np.abs(o["w"][k].ravel())
+                 + (7 + 5 * p.isi_cutoff) * U32 * o["abs"][k].ravel())
+        dev = np.abs(dg - do)
+        log(f"online fp32 {k}: entry/bound {float((dev / bound).max()):.3f}")
+        assert np.all(dev <= bound), (k, float(np.max(dev / bound)))
 
 
 def test_online_schedule_rejects_what_it_does_not_support():

@@ -1003,3 +1003,25 @@ def test_fp32_rounding_bound_is_the_absolute_term_sum():
     b2 = batch_from(T, [(s, 0) for s in range(0, T, 7)], 1, target=np.sin(np.arange(T) / 5.0) * 3, forced=[(40, 0)])
     r2 = O.fp32_bounds(on, b2, 0)
     assert r2["b"]["w_in"][0] > 1.5 * 7 * u * abs(r2["g"]["w_in"][0])
+
+
+def test_online_absolute_term_sums():
+    """The online run's absolute term sums (the scale of an FP32 evaluation's
+    rounding): for one LIF synapse whose every gradient term is positive (a
+    readout below a large target, positive feedback), |eta| times the sum
+    over its updates equals the weight's total change exactly; with a target
+    that makes the learning signal change sign it exceeds the change."""
+    net = small_net(1, 1, 1, [(0, 0, 0.2, 1)], [], w_out=[[-1.0]], fb=[[0.5]])
+    T = 120
+    ins = [(s, 0) for s in range(0, T, 9)]
+    for target, same in ((np.full(T, -3.0), True), (np.sin(np.arange(T) / 5.0) * 3, False)):
+        b = batch_from(T, ins, 1, target=target, forced=[(40, 0), (90, 0)])
+        on = O.OracleNet(net)
+        w0 = on.w_in.copy()
+        r = O.run_online(on, b, 1e-3)
+        change = abs(on.w_in[0] - w0[0])
+        assert change > 0
+        if same:
+            assert r["abs"]["w_in"][0] == pytest.approx(change, rel=1e-12)
+        else:
+            assert r["abs"]["w_in"][0] > 1.5 * change
