@@ -223,10 +223,15 @@ typedef struct {
  * opt may be NULL.  hip_stream is a hipStream_t (NULL = default stream)
  * that stays owned by the caller and must outlive the handle.  Device
  * memory is owned by the handle until eprop_destroy_network.
+ * The per-trial archives (psi, the arrival archive, spike bitsets, spike-time
+ * lists and the spike table) hold whole trials: about 12 bytes per neuron
+ * (input or recurrent) and step in FP32, 20 in FP64, times max_trials x
+ * max_steps.
  * Errors: INVALID_ARGUMENT (bad sizes, NULL arrays, delay out of range,
  * duplicate pairs, self-connections, non-finite weights, more than 2^24-1
  * sources or targets, 2^32 or more synapses), UNSUPPORTED (ABI version),
- * OUT_OF_MEMORY, DEVICE (no usable gfx950 device). */
+ * CAPACITY (the archives of max_trials trials of max_steps steps exceed the
+ * device's free memory), OUT_OF_MEMORY, DEVICE (no usable gfx950 device). */
 eprop_status eprop_create_network(const eprop_config *cfg, const eprop_projection *in_rec,
                                   const eprop_projection *rec_rec, const double *w_out,
                                   const double *feedback, const eprop_optimizer_state *opt,

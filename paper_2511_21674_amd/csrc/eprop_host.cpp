@@ -18,6 +18,7 @@
 
 #include "eprop_internal.h"
 
+
 using eprop::DevNet;
 using eprop::Launch;
 using eprop::Shapes;
@@ -81,6 +82,7 @@ struct eprop_network {
   std::vector<uint32_t> sm2caller;  // internal source-major index -> caller's synapse index
   size_t tile_smem = 0;             // dynamic LDS of the tiled forward kernel
   bool blocked = false;             // weight update as a blocked transposition (k_apply_blk)
+  uint64_t dl_words = 0;            // size of the delivery table (4-byte words)
   // e-prop+ schedule (allocated on the first online batch)
   void *on_syn = nullptr;
   double *on_Eh = nullptr, *on_y = nullptr, *on_zbo = nullptr, *on_loss = nullptr, *on_psum = nullptr;
@@ -118,6 +120,17 @@ struct eprop_network {
 namespace {
 
 void set_fail(eprop_network *n, const std::string &m) { n->err = m; }
+
+// Places a delivery-table segment of L synapses (L weights of sz bytes, then
+// L uint16 ring offsets, rounded up to a multiple of sz) at byte cur or
+// later: on the next kDlGrain boundary if it is longer than kDlGrain or
+// would otherwise cross a boundary that it fits between.  Returns the end.
+uint64_t dl_place(uint64_t cur, uint64_t L, uint64_t sz, uint64_t *at) {
+  const uint64_t G = eprop::kDlGrain, z = (L * (sz + 2) + sz - 1) / sz * sz;
+  if (z > 0 && (z > G || cur % G + z > G)) cur = (cur + G - 1) / G * G;
+  *at = cur;
+  return cur + z;
+}
 
 // Message for a host-side exception caught at the ABI (allocation or thread
 // creation failed); such a failure is reported as EPROP_ERR_OUT_OF_MEMORY.
@@ -287,10 +300,11 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
     ok &= dalloc(n, &p32, (size_t)n->NS * (d.KT + 1)); d.tseg = p32;
   }
   ok &= dalloc(n, &d.nspk, B * T1);
-  ok &= dalloc(n, &d.sm, n->S);
   ok &= dalloc(n, &p32, n->J + 1); d.tm_ptr = p32;
   ok &= dalloc(n, &p32, n->S); d.tm_syn = p32;
-  ok &= dalloc(n, &p32, n->S); d.tm_perm = p32;
+  if (!n->gather) {
+    ok &= dalloc(n, &p32, n->S); d.tm_dpos = p32;
+  }
   ok &= dalloc(n, &p32, (size_t)n->NS * n->R); d.outdeg = p32;
   if (n->blocked) ok &= dalloc(n, &d.tsum, n->Jp);
   else ok &= dalloc(n, &d.tm_w, n->S);
@@ -382,17 +396,66 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     return o;
   };
   cp((void *)d.sm_ptr, sm_ptr.data(), sm_ptr.size() * 4);
-  if (!n->gather) cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
-  {
-    std::vector<eprop::SynRec<real>> rec(sm_syn.size());
-    parallel_ranges(rec.size(), nt, flat, [&](uint64_t lo, uint64_t hi, unsigned) {
-      for (uint64_t q = lo; q < hi; ++q) {
-        rec[q] = eprop::SynRec<real>{};
-        rec[q].syn = sm_syn[q];
-        rec[q].w = (real)sm_w[q];
+  if (!n->gather) {
+    cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
+    // delivery table: each source's part starts on a kDlGrain boundary (so
+    // that the parts can be laid out independently); inside it, the
+    // segments of tiles 0..KT-1, each placed by dl_place
+    const uint32_t KT = d.KT, TS = d.TS;
+    const uint64_t NS = n->NS;
+    auto src_weight = [&](uint64_t src) { return (uint64_t)sm_ptr[src]; };
+    std::vector<uint64_t> part(NS + 1, 0);
+    parallel_ranges(NS, nt, src_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
+      for (uint64_t src = s0; src < s1; ++src) {
+        uint64_t cur = 0, at = 0;
+        for (uint32_t k = 0; k < KT; ++k)
+          cur = dl_place(cur, tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k], sizeof(real), &at);
+        part[src] = (cur + eprop::kDlGrain - 1) / eprop::kDlGrain * eprop::kDlGrain;
       }
     });
-    cp((void *)d.sm, rec.data(), rec.size() * sizeof(rec[0]));
+    uint64_t total = 0;
+    for (uint64_t src = 0; src < NS; ++src) {
+      const uint64_t b = part[src];
+      part[src] = total;
+      total += b;
+    }
+    part[NS] = total;
+    if (total / 4 >= (1ull << 31)) return hipErrorInvalidValue;  // (rejected at create)
+    n->dl_words = std::max<uint64_t>(total / 4, 1);
+    std::vector<uint32_t> dlh(n->dl_words, 0u), dpos(n->S, 0u);
+    std::vector<uint2> dsegh((size_t)NS * KT);
+    parallel_ranges(NS, nt, src_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
+      for (uint64_t src = s0; src < s1; ++src) {
+        uint64_t cur = 0, at = 0;
+        for (uint32_t k = 0; k < KT; ++k) {
+          const uint32_t q0 = tseg[src * (KT + 1) + k], L = tseg[src * (KT + 1) + k + 1] - q0;
+          cur = dl_place(cur, L, sizeof(real), &at);
+          const uint32_t word = (uint32_t)((part[src] + at) / 4);
+          dsegh[src * KT + k] = make_uint2(word, L);
+          real *wp = reinterpret_cast<real *>(dlh.data() + word);
+          uint16_t *op = reinterpret_cast<uint16_t *>(wp + L);
+          for (uint32_t i = 0; i < L; ++i) {
+            const uint32_t q = q0 + i, tgt = sm_syn[q] & 0xFFFFFFu, dly = sm_syn[q] >> 24;
+            wp[i] = (real)sm_w[q];
+            op[i] = (uint16_t)(dly * TS + (tgt - k * TS));
+            dpos[q] = word + i * (uint32_t)(sizeof(real) / 4);
+          }
+        }
+      }
+    });
+    uint32_t *pw = nullptr;
+    uint2 *ps = nullptr;
+    if (!dalloc(n, &pw, n->dl_words) || !dalloc(n, &ps, dsegh.size())) return hipErrorOutOfMemory;
+    d.dlw = pw;
+    d.dseg = ps;
+    d.ts_magic = (uint32_t)((1ull << 32) / TS + 1);
+    cp(pw, dlh.data(), dlh.size() * 4);
+    cp(ps, dsegh.data(), dsegh.size() * sizeof(uint2));
+    std::vector<uint32_t> tdp(n->S);
+    parallel_ranges(n->S, nt, flat, [&](uint64_t lo, uint64_t hi, unsigned) {
+      for (uint64_t q = lo; q < hi; ++q) tdp[q] = dpos[tm_perm[q]];
+    });
+    cp((void *)d.tm_dpos, tdp.data(), tdp.size() * 4);
   }
   {
     // out-degree of every source per delay, for the event counts
@@ -407,7 +470,6 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   }
   cp((void *)d.tm_ptr, tm_ptr.data(), tm_ptr.size() * 4);
   cp((void *)d.tm_syn, tm_syn.data(), tm_syn.size() * 4);
-  cp((void *)d.tm_perm, tm_perm.data(), tm_perm.size() * 4);
   if (!n->blocked) {
     auto o = conv(tm_w);
     cp(d.tm_w, o.data(), o.size() * sizeof(real));
@@ -770,9 +832,9 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
     if (prop.maxSharedMemoryPerMultiProcessor > 0 && lds > prop.maxSharedMemoryPerMultiProcessor)
       lds = prop.maxSharedMemoryPerMultiProcessor;
     const size_t fixed = 1024 + 4 * 1025;  // static LDS of the kernel (tile count prefix) and slack
-    // the tile size is chosen with a piece table of 2560 entries (20 KB),
-    // which grows to 4096 where LDS has room
-    auto smem_of = [&](uint32_t ts, uint32_t rb, uint32_t cap = 2560) {
+    // the tile size is chosen with a piece table of 3072 entries (24 KB: at
+    // least 3 per thread), which grows to 4096 where LDS has room
+    auto smem_of = [&](uint32_t ts, uint32_t rb, uint32_t cap = 3072) {
       return n->fp64 ? Launch<double>::tile_smem(ts, n->R, rb, cap) : Launch<float>::tile_smem(ts, n->R, rb, cap);
     };
     auto ts_max = [&](uint32_t rb) {  // largest tile (multiple of 64) that fits LDS
@@ -805,7 +867,16 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
       delete n;
       return EPROP_ERR_UNSUPPORTED;
     }
-    ptab_cap = smem_of(TS, ring_bytes, 4096) + fixed <= lds ? 4096u : 2560u;
+    ptab_cap = smem_of(TS, ring_bytes, 4096) + fixed <= lds ? 4096u : 3072u;
+    // ring offsets d * TS + (target - k * TS) in 16 bits; segment lengths
+    // within the piece entries' 26-bit field
+    uint64_t max_row = 0;
+    for (uint32_t src = 0; src < NS; ++src) max_row = std::max<uint64_t>(max_row, sm_ptr[src + 1] - sm_ptr[src]);
+    if ((uint64_t)n->R * TS > 65536 || max_row * (n->fp64 ? 4 : 2) >= (1ull << 26)) {
+      g_create_error = "delays or rows too long for the delivery table";
+      delete n;
+      return EPROP_ERR_UNSUPPORTED;
+    }
     n->tile_smem = smem_of(TS, ring_bytes, ptab_cap);
     // blocked transposition for the update where source rows are dense within
     // a tile (at least 4 synapses per source and tile on average)
@@ -823,6 +894,23 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
   std::vector<double> beta(n->Jp, 0.0);
   for (uint32_t j = 0; j < J; ++j) beta[j] = (cfg->is_alif && cfg->is_alif[j]) ? cfg->beta_a : 0.0;
 
+  {
+    // The per-trial archives hold whole trials (the gradient of a trial is
+    // formed once it is complete), so they grow as max_trials x max_steps x
+    // neurons: psi and phi, spike bitsets (recurrent, forced, input),
+    // spike-time lists, the per-source spike table and the readout rows.
+    const size_t rs = n->fp64 ? 8 : 4, B = n->Bcap, T1 = (size_t)n->Tcap + 1, Lc = round_up(n->Tcap, 8);
+    const size_t per_trial = T1 * n->Jp * rs + (size_t)n->Jp * n->Tp * rs + 2 * T1 * n->Jw * 8 +
+                             (size_t)n->Tcap * n->Iw * 8 + 2 * (size_t)n->NS * Lc * 2 + 5 * (T1 + 1) * n->K * 8;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && B * per_trial > free_b) {
+      g_create_error = "the trial archives need " + std::to_string(B * per_trial >> 20) + " MiB (" +
+                       std::to_string(per_trial >> 20) + " MiB per trial of max_steps steps) and the device has " +
+                       std::to_string(free_b >> 20) + " MiB free: lower max_trials or max_steps";
+      delete n;
+      return EPROP_ERR_CAPACITY;
+    }
+  }
   bool ok = n->fp64 ? alloc_state(n, n->n64) : alloc_state(n, n->n32);
   ok = ok && dalloc(n, &n->d_T, n->Bcap) && dalloc(n, &n->d_label, n->Bcap) && dalloc(n, &n->d_in_ptr, n->Bcap + 1) &&
        dalloc(n, &n->d_forced_ptr, n->Bcap + 1);
@@ -1697,13 +1785,30 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
     case EPROP_STATE_W_REC: {
       const bool in = what == EPROP_STATE_W_IN;
       if (!dst) { bytes = (in ? n->S_in : n->S_rec) * 8; break; }
-      std::vector<eprop::SynRec<real>> rec(n->S);
-      if (n->S) e = hipMemcpy(rec.data(), d.sm, n->S * sizeof(rec[0]), hipMemcpyDeviceToHost);
       outd.assign(in ? n->S_in : n->S_rec, 0.0);
-      for (uint64_t q = 0; q < n->S && e == hipSuccess; ++q) {
-        const uint32_t o = n->sm2caller[q];
-        if ((o < n->S_in) == in) outd[in ? o : o - n->S_in] = (double)rec[q].w;
+      auto put = [&](uint32_t o, real w) {
+        if ((o < n->S_in) == in) outd[in ? o : o - n->S_in] = (double)w;
+      };
+      if (!n->blocked) {  // target-major weights, kept by every update
+        std::vector<real> w;
+        e = fetch(d.tm_w, n->S, w);
+        for (uint64_t q = 0; q < n->S && e == hipSuccess; ++q) put(n->perm[q], w[q]);
+        break;
       }
+      // the delivery table, segment by segment
+      const uint32_t KT = d.KT;
+      std::vector<uint32_t> dl(n->dl_words), ts((size_t)n->NS * (KT + 1));
+      std::vector<uint2> sg((size_t)n->NS * KT);
+      e = hipMemcpy(dl.data(), d.dlw, dl.size() * 4, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(ts.data(), d.tseg, ts.size() * 4, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(sg.data(), d.dseg, sg.size() * sizeof(uint2), hipMemcpyDeviceToHost);
+      for (uint64_t src = 0; src < n->NS && e == hipSuccess; ++src)
+        for (uint32_t k = 0; k < KT; ++k) {
+          const uint2 g = sg[src * KT + k];
+          const real *w = reinterpret_cast<const real *>(dl.data() + g.x);
+          const uint32_t q0 = ts[src * (KT + 1) + k];
+          for (uint32_t i = 0; i < g.y; ++i) put(n->sm2caller[q0 + i], w[i]);
+        }
       break;
     }
     case EPROP_STATE_GRAD_IN: case EPROP_STATE_GRAD_REC:

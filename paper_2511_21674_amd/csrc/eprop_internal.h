@@ -2,11 +2,19 @@
 // its kernels.  Shared by eprop_kernels.hip and eprop_host.cpp only.
 //
 // HBM layout (b = trial slot, j = neuron, t = step 1..T, Jp = J padded to 64):
-//   graph, source-major  sm_ptr[NS+1], sm[S] = {target | delay << 24, weight} records
+//   graph, source-major  sm_ptr[NS+1] (row of each source, sorted by target)
+//   delivery table       (scatter delivery) dlw: the weights and ring offsets of every
+//                        (source, tile) segment, source by source, tile by tile; a
+//                        segment of L synapses is L weights (real) followed by L uint16
+//                        ring offsets d * TS + (target - k * TS), its size rounded up to
+//                        a multiple of sizeof(real); it starts on a kDlGrain-byte
+//                        boundary if it would otherwise cross one it need not cross
+//                        (so that a delivery reads as few lines as the segment's size
+//                        allows); dseg[src][k] = {word index of the segment, L}
 //   graph, target-major  tm_ptr[J+1], tm_syn[S] = source | delay << 24, tm_w[S]
 //                        (sources: inputs 0..I-1, then recurrent I..I+J-1;
-//                        each target's list sorted by source), tm_perm[S]
-//                        (target-major index -> source-major index)
+//                        each target's list sorted by source), tm_dpos[S]
+//                        (target-major index -> word index of the synapse's weight in dlw)
 //   gradient sums        gs[S], gc[S] (Kahan pair, target-major), Adam m, v (source-major
 //                        with scatter delivery, target-major with gather delivery)
 //   weight update        (scatter delivery, rows dense within a tile) blocks
@@ -51,21 +59,9 @@ constexpr uint32_t kApplyMaxTile = 8192;     // tile size the blocked update sup
 constexpr double kBoundScale = 65536.0;      // fixed-point scale of the per-target |w| sums
 constexpr double kBoundMaxW = 4194304.0;     // |w| from which the bound saturates (2^22)
 
-// One source-major synapse: packed target and delay, and the weight, read
-// together by a single load.
-template <typename real>
-struct SynRec;
-template <>
-struct __align__(8) SynRec<float> {
-  uint32_t syn;
-  float w;
-};
-template <>
-struct __align__(16) SynRec<double> {
-  uint32_t syn;
-  uint32_t pad;
-  double w;
-};
+// Placement unit of the delivery table's segments (bytes): the line a
+// partial read of device memory costs.
+constexpr uint32_t kDlGrain = 128;
 
 // Element of the delay ring.  FP32: the input current of a step is summed
 // in fixed point, int64_t (F up to 62 fraction bits: every FP32 weight of
@@ -101,8 +97,10 @@ struct DevNet {
   double beta_f;                // the moving average's factor
   // graph
   const uint32_t *sm_ptr, *tseg;
-  SynRec<real> *sm;
-  const uint32_t *tm_ptr, *tm_syn, *tm_perm;
+  uint32_t *dlw;                // delivery table (scatter delivery; null with gather delivery)
+  const uint2 *dseg;            // [NS][KT] {word index in dlw, synapse count} of each segment
+  uint32_t ts_magic;            // floor(2^32 / TS) + 1: o / TS == (o * ts_magic) >> 32 for o < 2^16
+  const uint32_t *tm_ptr, *tm_syn, *tm_dpos;
   real *tm_w;                   // target-major weights (gather delivery only)
   real *gs, *gc, *adam_m, *adam_v;
   int32_t g_fresh;              // no trial accumulated since the last update: gradient kernels write gs/gc, not add

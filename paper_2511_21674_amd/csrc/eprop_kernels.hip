@@ -35,6 +35,7 @@
 // The output gradient likewise is sum over the spikes u of j of Ebar_k^u.
 #include "eprop_internal.h"
 
+
 namespace eprop {
 namespace {
 
@@ -349,21 +350,27 @@ __device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
 
 // Adds the spikes emitted at step t by inputs and by recurrent neurons of
 // trial b into this tile's LDS ring.  Per chunk of up to 2 * blockDim
-// spiking sources: every thread resolves two sources to their segments (the
-// part of each target-sorted row inside this tile); segments are cut into
-// pieces of P synapses, numbered by a block scan, and each source writes the
-// entries of its pieces (first record, record count) into the piece table.
-// A group of P consecutive lanes then takes one piece, one synapse record
-// per lane, so that a wavefront's load covers a few contiguous lines; each
-// group keeps U pieces in flight before adding the weights into the ring
-// slots of their arrivals (only arrivals within the trial).  A lane's
-// address is one LDS read of its piece's entry.
-// The first E = 2 * blockDim / KT entries of every tile's list are read
-// while the tiles' counts are awaited, so that most recurrent sources of the
-// first chunk are known without a further round trip; an entry whose tag is
-// not yet there is awaited on its own.  They are parked in the piece table,
-// which the first chunk overwrites only after its last read of them.
-// ptab: LDS [cap] (cap = n.ptab_cap >= blockDim); wsum: LDS [17].
+// spiking sources: every thread resolves two sources to their segments in
+// the delivery table (the synapses of each source into this tile: weights,
+// then ring offsets); segments are cut into pieces of P synapses, numbered
+// by a block scan, and each source writes the entries of its pieces into
+// the piece table.  A group of P consecutive lanes then takes one piece,
+// one synapse per lane, so that a wavefront's loads cover a few contiguous
+// lines; each group keeps U pieces in flight before adding the weights into
+// the ring slots of their arrivals (only arrivals within the trial).  A
+// lane's addresses come from one LDS read of its piece's entry.
+// The segments of the step's input spikes of the first chunk are looked up
+// before anything else (they do not depend on the other tiles).  The first
+// E = 2 * blockDim / KT entries of every tile's list are read while the
+// tiles' counts are awaited, and the segments of those already there are
+// looked up at once, so that most recurrent sources of the first chunk are
+// known without a further round trip; an entry whose tag is not yet there
+// is awaited on its own.  Entries and segments are parked in the piece
+// table, which the first chunk overwrites only after its last read of them.
+// ptab: LDS [cap] (cap = n.ptab_cap >= 3 * blockDim); wsum: LDS [17].
+// Piece entry: x = word index of the piece's first weight, y = synapse count
+// | (distance from that weight to the piece's first ring offset, in uint16
+// units) << 6.
 // [P, U] of the delivery variants the autotuner chooses from; variant 0 is
 // the default.
 constexpr uint32_t kFwdVariants = 4;
@@ -376,15 +383,24 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
                                     uint2 *ptab, uint32_t *wsum, const uint64_t *words, const uint32_t *woff,
                                     uint32_t nw, uint32_t own) {
+  constexpr uint32_t WPR = sizeof(real) / 4;  // words per weight
   __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike counts of step t
-  uint32_t *spec = reinterpret_cast<uint32_t *>(ptab);  // [E * KT <= 2 * blockDim] parked list entries
+  // parked entries [span] and their segments [span] (in the piece table)
+  uint32_t *spec = reinterpret_cast<uint32_t *>(ptab);
+  uint2 *spec_seg = ptab + (n.ptab_cap - blockDim.x * 2);
   const uint32_t cap = n.ptab_cap;
-  constexpr uint32_t rpt = 2;
-  const uint32_t span = rpt * blockDim.x;
+  const uint32_t span = 2 * blockDim.x;
   const uint32_t E = span / n.KT;  // >= 1: KT <= blockDim
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
+  const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
+  uint2 iseg[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
+#pragma unroll
+  for (uint32_t u = 0; u < 2; ++u) {
+    const uint32_t item = threadIdx.x + u * blockDim.x;
+    if (item < n_in) iseg[u] = n.dseg[(size_t)in_src[in_lo + item] * n.KT + k];
+  }
   uint32_t n_rec = 0;
   const uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
   // a single-tile trial takes its own spikes of the step (own of them) from
@@ -398,8 +414,14 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
     for (uint32_t u = 0; u < 2; ++u) {
       const uint32_t s = threadIdx.x + u * blockDim.x, tile = s / E, pos = s - tile * E;
       // (only inside the tile's part of the list buffer)
-      if (u < rpt && tile < n.KT && pos < min(n.TS, n.Jp - tile * n.TS)) ahead[u] = load_sys(pl + (size_t)tile * n.TS + pos);
+      if (tile < n.KT && pos < min(n.TS, n.Jp - tile * n.TS)) ahead[u] = load_sys(pl + (size_t)tile * n.TS + pos);
     }
+    // segments of the entries already there
+    uint2 aseg[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u)
+      if ((uint32_t)(ahead[u] >> 32) == t)
+        aseg[u] = n.dseg[(size_t)(n.I + min((uint32_t)ahead[u], n.J - 1u)) * n.KT + k];
     // every tile's count of step t (published by the tiles, possibly still on the way)
     const uint32_t kk = threadIdx.x;
     uint32_t c = 0;
@@ -413,57 +435,68 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 #pragma unroll
     for (uint32_t u = 0; u < 2; ++u) {
       const uint32_t s = threadIdx.x + u * blockDim.x;
-      if (u < rpt && s / E < n.KT) spec[s] = (uint32_t)(ahead[u] >> 32) == t ? (uint32_t)ahead[u] : kNoEntry;
+      if (s / E < n.KT) {
+        const bool there = (uint32_t)(ahead[u] >> 32) == t;
+        spec[s] = there ? (uint32_t)ahead[u] : kNoEntry;
+        spec_seg[s] = aseg[u];
+      }
     }
     __syncthreads();
   }
   const uint32_t total = n_in + n_rec;
-  const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
-  const uint32_t slot_t = t % n.R;
+  const uint32_t sbase = (t % n.R) * n.TS, RT = n.R * n.TS;
+  // an arrival d steps later lies within the trial iff its ring offset is below lim
+  const uint32_t lim = min(n.R, Tb - t + 1u) * n.TS;
   const uint32_t sub = threadIdx.x & (kPiece - 1u), grp = threadIdx.x / kPiece, ngrp = blockDim.x / kPiece;
   for (uint32_t base = 0; base < total; base += span) {
+    uint2 seg[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
     uint32_t src[2] = {0u, 0u};
-    bool has[2] = {false, false};
+    bool look[2] = {false, false};  // segment still to be looked up
 #pragma unroll
     for (uint32_t u = 0; u < 2; ++u) {
       const uint32_t item = base + threadIdx.x + u * blockDim.x;
-      if (u >= rpt || item >= total) continue;
-      has[u] = true;
+      if (item >= total) continue;
       if (item < n_in) {
-        src[u] = in_src[in_lo + item];
-      } else {
-        const uint32_t r = item - n_in;
-        if (local) {  // the r-th spike: word w with woff[w] <= r < woff[w + 1]
-          uint32_t lw = 0, hw = nw;
-          while (hw - lw > 1) {
-            const uint32_t mid = (lw + hw) >> 1;
-            if (woff[mid] <= r) lw = mid; else hw = mid;
-          }
-          const uint32_t jj = j0 + lw * 64 + nth_set_bit(words[lw], r - woff[lw]);
-          src[u] = n.I + min(jj, n.J - 1u);
-          continue;
+        if (base == 0) {
+          seg[u] = iseg[u];
+        } else {
+          src[u] = in_src[in_lo + item];
+          look[u] = true;
         }
-        uint32_t lk = 0, hk = n.KT;  // tpre[lk] <= r < tpre[hk]
-        while (hk - lk > 1) {
-          const uint32_t mid = (lk + hk) >> 1;
-          if (tpre[mid] <= r) lk = mid; else hk = mid;
-        }
-        const uint32_t pos = r - tpre[lk];
-        // parked entries are valid in the first chunk only (the piece table is reused after it)
-        uint32_t j = base == 0 && pos < E ? spec[lk * E + pos] : kNoEntry;
-        if (j == kNoEntry) j = wait_tag(pl + (size_t)lk * n.TS + pos, t, &n.ctl[CTL_ERR]);
-        src[u] = n.I + min(j, n.J - 1u);
+        continue;
       }
+      const uint32_t r = item - n_in;
+      look[u] = true;
+      if (local) {  // the r-th spike: word w with woff[w] <= r < woff[w + 1]
+        uint32_t lw = 0, hw = nw;
+        while (hw - lw > 1) {
+          const uint32_t mid = (lw + hw) >> 1;
+          if (woff[mid] <= r) lw = mid; else hw = mid;
+        }
+        const uint32_t jj = j0 + lw * 64 + nth_set_bit(words[lw], r - woff[lw]);
+        src[u] = n.I + min(jj, n.J - 1u);
+        continue;
+      }
+      uint32_t lk = 0, hk = n.KT;  // tpre[lk] <= r < tpre[hk]
+      while (hk - lk > 1) {
+        const uint32_t mid = (lk + hk) >> 1;
+        if (tpre[mid] <= r) lk = mid; else hk = mid;
+      }
+      const uint32_t pos = r - tpre[lk];
+      // parked entries are valid in the first chunk only (the piece table is reused after it)
+      uint32_t j = base == 0 && pos < E ? spec[lk * E + pos] : kNoEntry;
+      if (j != kNoEntry) {
+        seg[u] = spec_seg[lk * E + pos];
+        look[u] = false;
+        continue;
+      }
+      j = wait_tag(pl + (size_t)lk * n.TS + pos, t, &n.ctl[CTL_ERR]);
+      src[u] = n.I + min(j, n.J - 1u);
     }
-    uint32_t lo[2] = {0u, 0u}, len[2] = {0u, 0u};
 #pragma unroll
     for (uint32_t u = 0; u < 2; ++u)
-      if (has[u]) {
-        const uint32_t *ts = n.tseg + (size_t)src[u] * (n.KT + 1) + k;
-        lo[u] = ts[0];
-        len[u] = ts[1] - lo[u];
-      }
-    const uint32_t np0 = (len[0] + kPiece - 1) / kPiece, np1 = (len[1] + kPiece - 1) / kPiece;
+      if (look[u]) seg[u] = n.dseg[(size_t)src[u] * n.KT + k];
+    const uint32_t np0 = (seg[0].y + kPiece - 1) / kPiece, np1 = (seg[1].y + kPiece - 1) / kPiece;
     uint32_t npieces;
     const uint32_t pre = block_exclusive_scan(np0 + np1, wsum, &npieces);
     // (the scan's barrier also ends every read of the parked entries)
@@ -472,37 +505,44 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 #pragma unroll
       for (uint32_t u = 0; u < 2; ++u) {
         const uint32_t p0 = u ? pre + np0 : pre, np = u ? np1 : np0;
+        const uint32_t L = seg[u].y;
         for (uint32_t pc = max(p0, w0); pc < min(p0 + np, w1); ++pc) {
           const uint32_t off = (pc - p0) * kPiece;
-          ptab[pc - w0] = make_uint2(lo[u] + off, min(kPiece, len[u] - off));
+          const uint32_t dist = L * (sizeof(real) / 2) - off * (sizeof(real) / 2 - 1);
+          ptab[pc - w0] = make_uint2(seg[u].x + off * WPR, min(kPiece, L - off) | (dist << 6));
         }
       }
       __syncthreads();
       for (uint32_t pc0 = w0 + grp; pc0 < w1; pc0 += kUnroll * ngrp) {
         // branch-free address phase, then all loads, then the ring adds: the
-        // loads of a group are in flight together (dead lanes read record 0,
-        // which exists whenever there is a piece)
-        uint32_t idx[kUnroll];
+        // loads of a group are in flight together (dead lanes read word 0 of
+        // the table, which exists whenever there is a piece)
+        uint32_t wi[kUnroll], oi[kUnroll];
         uint32_t live = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) {
           const uint32_t pc = pc0 + u * ngrp;
           const bool inb = pc < w1;
           const uint2 pe = ptab[inb ? pc - w0 : 0u];
-          const bool ok = inb && sub < pe.y;
-          idx[u] = ok ? pe.x + sub : 0u;
+          const bool ok = inb && sub < (pe.y & 63u);
+          wi[u] = ok ? pe.x + sub * WPR : 0u;
+          oi[u] = ok ? 2u * pe.x + (pe.y >> 6) + sub : 0u;
           live |= (uint32_t)ok << u;
         }
-        SynRec<real> r[kUnroll];
-#pragma unroll
-        for (uint32_t u = 0; u < kUnroll; ++u) r[u] = n.sm[idx[u]];
+        real w[kUnroll];
+        uint32_t o[kUnroll];
+        const uint16_t *o16 = reinterpret_cast<const uint16_t *>(n.dlw);
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) {
-          if (!((live >> u) & 1u)) continue;
-          const uint32_t d = r[u].syn >> 24;
-          uint32_t slot = slot_t + d;
-          if (slot >= n.R) slot -= n.R;
-          if (t + d <= Tb) ring_add(&ring[slot * n.TS + ((r[u].syn & 0xFFFFFFu) - j0)], r[u].w, sc);
+          w[u] = *reinterpret_cast<const real *>(n.dlw + wi[u]);
+          o[u] = o16[oi[u]];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+          if (!((live >> u) & 1u) || o[u] >= lim) continue;
+          uint32_t ri = sbase + o[u];
+          if (ri >= RT) ri -= RT;
+          ring_add(&ring[ri], w[u], sc);
         }
       }
       __syncthreads();
@@ -1408,13 +1448,15 @@ __global__ __launch_bounds__(256) void k_td_output(DevNet<real> n) {
 // with the new weight.  A thread per target neuron walks its incoming
 // synapses in target-major order, so the input current sums in the canonical
 // order and each weight has a single writer; weights live in tm_w for the
-// run and are copied to the source-major records afterwards.
+// run and are copied to the delivery table afterwards (scatter delivery).
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_online_fill(DevNet<real> n, int to_records) {
+  if (!n.dlw) return;  // gather delivery: tm_w is the only copy of the weights
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n.S; q += (uint64_t)gridDim.x * blockDim.x) {
-    if (to_records) n.sm[n.tm_perm[q]].w = n.tm_w[q];
-    else n.tm_w[q] = n.sm[n.tm_perm[q]].w;
+    real *wp = reinterpret_cast<real *>(n.dlw + n.tm_dpos[q]);
+    if (to_records) *wp = n.tm_w[q];
+    else n.tm_w[q] = *wp;
   }
 }
 
@@ -1727,7 +1769,7 @@ __global__ __launch_bounds__(256) void k_apply_syn(DevNet<real> n, uint64_t S, d
       n.adam_v[q] = (real)v;
     }
     n.tm_w[q] = (real)w;
-    n.sm[n.tm_perm[q]].w = (real)w;
+    if (n.dlw) *reinterpret_cast<real *>(n.dlw + n.tm_dpos[q]) = (real)w;
     n.gs[q] = (real)0;
     n.gc[q] = (real)0;
   }
@@ -1765,13 +1807,14 @@ __global__ __launch_bounds__(256) void k_apply_out(DevNet<real> n, double n_tria
 // within a tile (many synapses per source and tile): an explicit blocked
 // transposition through LDS.  Block c owns the synapses from sources
 // s0..s1-1 into the targets of tile k.  Source rows are sorted by target,
-// so these are one contiguous segment of each source row (tseg); target
-// rows are sorted by source, so they are also one contiguous run of each
-// target row (starting at trs[c][t]).  The block reads the runs' gradients
-// (Kahan pairs) and their source-major positions, puts each averaged
-// gradient into LDS at its place in the block's source-major order, and
-// then updates the source-major weight records segment by segment: both
-// sides of HBM are read and written in runs, with no scattered words.  It
+// so these are one contiguous segment of each source row (tseg) and one
+// segment of the delivery table (dseg); target rows are sorted by source,
+// so they are also one contiguous run of each target row (starting at
+// trs[c][t]).  The block reads the runs' gradients (Kahan pairs) and their
+// source-major positions, puts each averaged gradient into LDS at its place
+// in the block's source-major order, and then updates the weights of the
+// delivery table segment by segment: both sides of HBM are read and written
+// in runs, with no scattered words.  It
 // also sums |w| per target of the tile in LDS (fixed point, each term
 // rounded up, so the sum bounds the input current of any step) and adds
 // the sums to tsum; k_bound_max turns the largest into *l1max.
@@ -1782,8 +1825,10 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
   constexpr uint32_t NT = 1024;
   constexpr uint32_t PER_S = kApplySrc / NT;
   constexpr uint32_t PER_T = kApplyMaxTile / NT;
+  constexpr uint32_t WPR = sizeof(real) / 4;  // words per weight
   __shared__ uint32_t pre[kApplySrc + 1];
-  __shared__ uint32_t seg0[kApplySrc];
+  __shared__ uint32_t seg0[kApplySrc];  // first synapse (source-major index) of each source's segment
+  __shared__ uint32_t dw0[kApplySrc];   // word index of each source's segment in the delivery table
   __shared__ uint32_t wsum[17];
   extern __shared__ __align__(16) unsigned char apl_smem[];
   const uint32_t TS = n.TS;
@@ -1797,16 +1842,18 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
   const bool last_of_tile = c + 1 >= n_ach || n.ach[3 * (c + 1)] != k;
   for (uint32_t i = tid; i < TS; i += NT) tsl[i] = 0ull;
   // source-major side: the segment of each source, scanned
-  uint32_t len[PER_S], lo[PER_S], sum = 0;
+  uint32_t len[PER_S], lo[PER_S], dw[PER_S], sum = 0;
 #pragma unroll
   for (uint32_t u = 0; u < PER_S; ++u) {
     const uint32_t i = tid * PER_S + u;
     len[u] = 0;
     lo[u] = 0;
+    dw[u] = 0;
     if (i < nsrc) {
-      const uint32_t *ts = n.tseg + (size_t)(s0 + i) * (n.KT + 1) + k;
-      lo[u] = ts[0];
-      len[u] = ts[1] - ts[0];
+      lo[u] = n.tseg[(size_t)(s0 + i) * (n.KT + 1) + k];
+      const uint2 sg = n.dseg[(size_t)(s0 + i) * n.KT + k];
+      dw[u] = sg.x;
+      len[u] = sg.y;
     }
     sum += len[u];
   }
@@ -1818,6 +1865,7 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
     if (i < nsrc) {
       pre[i] = run;
       seg0[i] = lo[u];
+      dw0[i] = dw[u];
     }
     run += len[u];
   }
@@ -1885,14 +1933,15 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
     }
   }
   __syncthreads();
-  // source-major side: update the records segment by segment, BU elements
+  // source-major side: update the weights segment by segment, BU elements
   // per thread at a time with all their loads issued before their stores
   // (vector memory operations complete in order, so a load issued after a
   // store waits for it); an element beyond the block repeats element i0's
-  // address and is not written
+  // addresses and is not written
   constexpr uint32_t BU = 4;
+  const uint16_t *o16 = reinterpret_cast<const uint16_t *>(n.dlw);
   for (uint32_t i0 = tid; i0 < total; i0 += BU * NT) {
-    uint32_t qv[BU];
+    uint32_t qv[BU], wv[BU], ov[BU];
 #pragma unroll
     for (uint32_t u = 0; u < BU; ++u) {
       const uint32_t i = min(i0 + u * NT, total - 1);
@@ -1901,15 +1950,25 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
         const uint32_t m = (a + b) >> 1;
         if (pre[m] <= i) a = m; else b = m;
       }
-      qv[u] = i0 + u * NT < total ? seg0[a] + (i - pre[a]) : 0u;
+      const uint32_t rel = i - pre[a], L = pre[a + 1] - pre[a];
+      qv[u] = seg0[a] + rel;
+      wv[u] = dw0[a] + rel * WPR;
+      ov[u] = 2 * dw0[a] + L * (sizeof(real) / 2) + rel;
     }
 #pragma unroll
     for (uint32_t u = 1; u < BU; ++u)
-      if (i0 + u * NT >= total) qv[u] = qv[0];
-    SynRec<real> rv[BU];
-    real mv[BU], vv[BU];
+      if (i0 + u * NT >= total) {
+        qv[u] = qv[0];
+        wv[u] = wv[0];
+        ov[u] = ov[0];
+      }
+    real rw[BU], mv[BU], vv[BU];
+    uint32_t ro[BU];
 #pragma unroll
-    for (uint32_t u = 0; u < BU; ++u) rv[u] = n.sm[qv[u]];
+    for (uint32_t u = 0; u < BU; ++u) {
+      rw[u] = *reinterpret_cast<const real *>(n.dlw + wv[u]);
+      ro[u] = o16[ov[u]];
+    }
     if (UPDATE && opt == 1) {
 #pragma unroll
       for (uint32_t u = 0; u < BU; ++u) {
@@ -1922,8 +1981,7 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
       const uint32_t i = i0 + u * NT;
       if (i >= total) break;
       const uint32_t q = qv[u];
-      SynRec<real> rec = rv[u];
-      double w = (double)rec.w;
+      double w = (double)rw[u];
       if constexpr (UPDATE) {
         const double G = (double)gbuf[i];
         double m = 0.0, v = 0.0;
@@ -1936,11 +1994,13 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
           n.adam_m[q] = (real)m;
           n.adam_v[q] = (real)v;
         }
-        rec.w = (real)w;
-        n.sm[q] = rec;  // the whole record: full lines rather than masked half-records
-        w = (double)rec.w;
+        const real wr = (real)w;
+        *reinterpret_cast<real *>(n.dlw + wv[u]) = wr;
+        w = (double)wr;
       }
-      const uint32_t t = (rec.syn & 0xFFFFFFu) - j0;
+      // the target in the tile: the ring offset o = d * TS + t
+      const uint32_t o = ro[u];
+      const uint32_t t = o - TS * (uint32_t)(((uint64_t)o * n.ts_magic) >> 32);
       const double aw = fabs(w);
       if (aw < kBoundMaxW) {
         atomicAdd(&tsl[t], (unsigned long long)ceil(aw * kBoundScale));
@@ -2215,7 +2275,7 @@ void Launch<real>::online_step(const DevNet<real> &n, const OnlineRun<real> &o, 
 
 template <typename real>
 size_t Launch<real>::apply_blocked_smem(uint32_t TS) {
-  return apply_blk_smem(TS) + sizeof(uint32_t) * (2 * kApplySrc + 1 + 17);
+  return apply_blk_smem(TS) + sizeof(uint32_t) * (3 * kApplySrc + 1 + 17);
 }
 
 template <typename real>
