@@ -334,6 +334,24 @@ typedef struct {
 eprop_status eprop_simulate_batch(eprop_network *net, const eprop_batch *batch,
                                   eprop_batch_result *res);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * as eprop_simulate_batch, with the same results, but the call allocates
+ * nothing.  Host-memory batch arrays (in_step, in_src, target, window,
+ * forced_step, forced_neuron) are copied into a static device array of
+ * EPROP_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends, instead of into staging buffers the handle grows; the
+ * step loop runs kernel by kernel where its HIP graph has not been built by
+ * an earlier eprop_simulate_batch; a pending EPROP_AUTOTUNE waits for the
+ * next eprop_simulate_batch.  Every call on one GPU, from any handle, shares
+ * that GPU's array, so calls that overlap on one GPU race.
+ * Errors: as eprop_simulate_batch; CAPACITY also when the batch's host arrays
+ * (each rounded up to 256 bytes) exceed EPROP_NOALLOC_SCRATCH_BYTES;
+ * UNSUPPORTED with EPROP_BATCH_ONLINE or EPROP_BATCH_TIME_DRIVEN. */
+#define EPROP_NOALLOC_SCRATCH_BYTES (64u << 20)
+eprop_status eprop_simulate_batch_noalloc(eprop_network *net, const eprop_batch *batch,
+                                          eprop_batch_result *res);
+
 /* Ends an iteration: divides the accumulated gradients by the number of
  * trials trained since the last call (reading: mean over the mini-batch),
  * applies gradient descent or one Adam step to W^in, W^rec and W^out, and

@@ -18,6 +18,7 @@
 
 #include "eprop_internal.h"
 
+static_assert(eprop::kScratchBytes == EPROP_NOALLOC_SCRATCH_BYTES, "staging array size");
 
 using eprop::DevNet;
 using eprop::Launch;
@@ -106,6 +107,8 @@ struct eprop_network {
   std::vector<uint64_t> h_in_ptr, h_f_ptr;
   std::vector<double> h_loss;
   std::vector<uint32_t> h_pred;
+  // eprop_simulate_batch_noalloc: this device's static staging array
+  uint8_t *scratch = nullptr;
   // step loop
   uint32_t blk = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -958,6 +961,9 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
                          feedback, opt)
                 : upload(n, n->n32, sm_ptr, tseg, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
                          feedback, opt);
+  if (e == hipSuccess) {  // this device's staging array of the no-allocation batch call (device current)
+    n->scratch = static_cast<uint8_t *>(eprop::scratch_address(dev, &e));
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&n->cap_stream, hipStreamNonBlocking);
   for (auto &ev : n->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
@@ -1123,9 +1129,12 @@ template <typename real>
 eprop_status run_online(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res,
                         const OnlineCtx &oc, bool forced, bool prof, hipError_t &e);
 
+// noalloc: eprop_simulate_batch_noalloc (host-memory batch arrays staged in
+// the device's static array, no device allocation, no graph instantiation,
+// no autotuning in this call).
 template <typename real>
 eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, eprop_batch_result *res,
-                      const OnlineCtx *oc = nullptr) {
+                      const OnlineCtx *oc = nullptr, bool noalloc = false) {
   std::string msg;
   std::vector<uint64_t> &in_ptr = n->h_in_ptr, &f_ptr = n->h_f_ptr;
   uint32_t t_max = 0;
@@ -1167,7 +1176,28 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
            *st_f_neuron = n->d_forced_neuron;
   double *st_target = n->d_target;
   uint8_t *st_window = n->d_window;
-  if (!dev) {
+  if (!dev && noalloc) {
+    // consecutive 256-byte aligned pieces of the static staging array
+    const size_t nt = (size_t)ntr * b->step_stride;
+    const size_t sizes[6] = {b->n_in_spikes * 4, b->n_in_spikes * 4, b->target ? nt * n->K * 8 : 0,
+                             b->window ? nt : 0, forced ? b->n_forced * 4 : 0, forced ? b->n_forced * 4 : 0};
+    size_t off[6], used = 0;
+    for (int i = 0; i < 6; ++i) {
+      off[i] = used;
+      used += (sizes[i] + 255) / 256 * 256;
+    }
+    if (used > eprop::kScratchBytes) {
+      set_fail(n, "the batch's host arrays (" + std::to_string(used) + " bytes staged) exceed the " +
+                      std::to_string(eprop::kScratchBytes) + "-byte staging array of eprop_simulate_batch_noalloc");
+      return EPROP_ERR_CAPACITY;
+    }
+    st_in_step = reinterpret_cast<uint32_t *>(n->scratch + off[0]);
+    st_in_src = reinterpret_cast<uint32_t *>(n->scratch + off[1]);
+    st_target = reinterpret_cast<double *>(n->scratch + off[2]);
+    st_window = n->scratch + off[3];
+    st_f_step = reinterpret_cast<uint32_t *>(n->scratch + off[4]);
+    st_f_neuron = reinterpret_cast<uint32_t *>(n->scratch + off[5]);
+  } else if (!dev) {
     const size_t nt = (size_t)ntr * b->step_stride;
     bool ok = dgrow(n, &n->d_in_step, &n->cap_in_step, b->n_in_spikes) &&
               dgrow(n, &n->d_in_src, &n->cap_in_src, b->n_in_spikes);
@@ -1243,7 +1273,8 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   // the forward pass in blocks of steps (the tiled kernel delivers step-0 inputs first)
   auto forward = [&]() {
     const uint32_t nblk = (t_max + n->blk - 1) / n->blk;
-    if (n->use_graph) {
+    // (the no-allocation call instantiates no graph: without one it launches the blocks kernel by kernel)
+    if (n->use_graph && !(noalloc && !n->gexec[forced ? 1 : 0])) {
       if (e == hipSuccess) e = ensure_graph(n, d, forced);
       for (uint32_t i = 0; i < nblk && e == hipSuccess; ++i) e = hipGraphLaunch(n->gexec[forced ? 1 : 0], s);
     } else {
@@ -1267,7 +1298,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     }
     return best;
   };
-  const bool tune = !oc && n->autotune_pending && train && !time_driven;
+  const bool tune = !oc && n->autotune_pending && train && !time_driven && !noalloc;
 
   (void)hipEventRecord(n->ev[0], s);
   // upload
@@ -1953,6 +1984,26 @@ eprop_status eprop_simulate_batch(eprop_network *net, const eprop_batch *batch, 
     set_fail(net, "host failure");
   }
   // device work of the batch may be half issued: the handle is failed
+  (void)hipStreamSynchronize(net->stream);
+  net->failed = true;
+  return EPROP_ERR_OUT_OF_MEMORY;
+}
+
+eprop_status eprop_simulate_batch_noalloc(eprop_network *net, const eprop_batch *batch, eprop_batch_result *res) {
+  if (!net || !batch) return EPROP_ERR_INVALID_ARGUMENT;
+  if (net->failed) return EPROP_ERR_STATE;
+  if (batch->flags & (EPROP_BATCH_ONLINE | EPROP_BATCH_TIME_DRIVEN)) {
+    set_fail(net, "eprop_simulate_batch_noalloc runs the event-driven batch schedule only");
+    return EPROP_ERR_UNSUPPORTED;
+  }
+  try {
+    return net->fp64 ? simulate(net, net->n64, batch, res, nullptr, true)
+                     : simulate(net, net->n32, batch, res, nullptr, true);
+  } catch (const std::exception &x) {
+    set_fail(net, host_failure(x));
+  } catch (...) {
+    set_fail(net, "host failure");
+  }
   (void)hipStreamSynchronize(net->stream);
   net->failed = true;
   return EPROP_ERR_OUT_OF_MEMORY;

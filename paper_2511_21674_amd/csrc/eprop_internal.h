@@ -58,6 +58,8 @@ constexpr uint32_t kApplySrc = 2048;         // sources per weight-update block 
 constexpr uint32_t kApplyMaxTile = 8192;     // tile size the blocked update supports
 constexpr double kBoundScale = 65536.0;      // fixed-point scale of the per-target |w| sums
 constexpr double kBoundMaxW = 4194304.0;     // |w| from which the bound saturates (2^22)
+constexpr size_t kScratchBytes = (size_t)64 << 20;  // static staging array of the no-allocation batch call
+constexpr int kMaxDevices = 64;
 
 // Placement unit of the delivery table's segments (bytes): the line a
 // partial read of device memory costs.
@@ -246,5 +248,10 @@ struct Launch {
 };
 
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s);
+
+// Device address of the static staging array (kScratchBytes) of the
+// no-allocation batch call on `device`, which must be the current device;
+// looked up once per device and kept.  nullptr and *err set on failure.
+void *scratch_address(int device, hipError_t *err);
 
 }  // namespace eprop

@@ -35,6 +35,7 @@
 // The output gradient likewise is sum over the spikes u of j of Ebar_k^u.
 #include "eprop_internal.h"
 
+#include <mutex>
 
 namespace eprop {
 namespace {
@@ -2290,6 +2291,36 @@ void Launch<real>::input_bound(const DevNet<real> &n, hipStream_t s) {
 }
 
 void launch_advance(uint32_t *ctl, uint32_t by, hipStream_t s) { k_advance<<<1, 64, 0, s>>>(ctl, by); }
+
+// ------------------------------------------------- no-allocation staging
+// Staging memory of the no-allocation batch call: the copies of a
+// host-memory batch's arrays, which the staging and readout kernels read.
+// Each GPU the library runs on holds its own copy of this array until the
+// process ends; every call on one GPU shares it, so such calls that overlap
+// on one GPU race.  The name is a host-side stand-in in host code: only the
+// address from hipGetSymbolAddress, taken with the device current, is used.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void *scratch_address(int device, hipError_t *err) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      *err = e;
+      return nullptr;
+    }
+    addr[device] = p;
+  }
+  *err = hipSuccess;
+  return addr[device];
+}
 
 uint32_t fwd_variant_piece(uint32_t v) { return fwd_piece(v); }
 uint32_t syn_variant_pre(uint32_t v) { return syn_pre_of(v); }

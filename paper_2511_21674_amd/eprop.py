@@ -41,8 +41,9 @@ PHASES = ("stage", "forward", "readout", "adjoint", "synapse", "output")
  EPROP_STATE_SPIKES, EPROP_STATE_PSI, EPROP_STATE_Y, EPROP_STATE_ERR, EPROP_STATE_V,
  EPROP_STATE_LAYOUT, EPROP_STATE_L, EPROP_STATE_INPUT_BOUND) = range(21)
 
-EXPORTED = ("eprop_create_network", "eprop_simulate_batch", "eprop_apply_updates", "eprop_read_state",
-            "eprop_destroy_network", "eprop_status_string", "eprop_last_error")
+EXPORTED = ("eprop_create_network", "eprop_simulate_batch", "eprop_simulate_batch_noalloc", "eprop_apply_updates",
+            "eprop_read_state", "eprop_destroy_network", "eprop_status_string", "eprop_last_error")
+EPROP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _P = C.c_void_p
 DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -113,6 +114,8 @@ def lib():
         L.eprop_create_network.restype = C.c_int32
         L.eprop_simulate_batch.argtypes = [_P, C.POINTER(eprop_batch), C.POINTER(eprop_batch_result)]
         L.eprop_simulate_batch.restype = C.c_int32
+        L.eprop_simulate_batch_noalloc.argtypes = [_P, C.POINTER(eprop_batch), C.POINTER(eprop_batch_result)]
+        L.eprop_simulate_batch_noalloc.restype = C.c_int32
         L.eprop_apply_updates.argtypes = [_P]
         L.eprop_apply_updates.restype = C.c_int32
         L.eprop_read_state.argtypes = [_P, C.c_int32, C.c_uint32, _P, C.c_size_t, C.POINTER(C.c_size_t)]
@@ -138,6 +141,10 @@ def eprop_create_network(cfg, in_rec, rec_rec, w_out, feedback, opt, hip_stream)
 
 def eprop_simulate_batch(net, batch, res):
     return lib().eprop_simulate_batch(net, C.byref(batch), C.byref(res))
+
+
+def eprop_simulate_batch_noalloc(net, batch, res):
+    return lib().eprop_simulate_batch_noalloc(net, C.byref(batch), C.byref(res))
 
 
 def eprop_apply_updates(net):
@@ -282,12 +289,12 @@ class Network:
             raise EpropError(st, eprop_last_error(self.h))
 
     def simulate(self, batch, train: bool = True, device: bool = False, profile: bool = False,
-                 time_driven: bool = False, online: bool = False) -> BatchResult:
+                 time_driven: bool = False, online: bool = False, noalloc: bool = False) -> BatchResult:
         """Runs one batch (a ``workloads.Batch``).  device=True places the
         batch arrays in device memory (torch) before the call; time_driven
         computes the gradient by the time-driven baseline recursion; online
         runs the trials back to back with the e-prop+ per-spike schedule
-        (EPROP_BATCH_ONLINE)."""
+        (EPROP_BATCH_ONLINE); noalloc calls eprop_simulate_batch_noalloc."""
         ntr = batch.n_trials
         n_steps = _c(batch.n_steps, np.uint32)
         stride = int(n_steps.max())
@@ -321,7 +328,7 @@ class Network:
         loss = np.zeros(ntr)
         pred = np.zeros(ntr, np.uint32)
         res = eprop_batch_result(loss=_ptr(loss), predicted=_ptr(pred))
-        self._check(eprop_simulate_batch(self.h, b, res))
+        self._check((eprop_simulate_batch_noalloc if noalloc else eprop_simulate_batch)(self.h, b, res))
         del keep
         return BatchResult(loss, pred, res.n_rec_spikes, res.n_in_spikes, res.n_syn_events, res.n_out_events,
                            res.n_eprop_updates, res.n_flush_updates, res.device_seconds,
