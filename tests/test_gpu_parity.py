@@ -421,24 +421,15 @@ def test_fp32_teacher_forced_weight_updates(name):
     fp32_forced_run(name, wl, it, bs)
 
 
-def test_fp32_free_running_final_loss():
-    """Free-running FP32 batched training of the evidence-accumulation task
-    (Results, "Evidence accumulation": softmax cross-entropy in the recall
-    window, LIF + ALIF, Adam 5e-3; 32 trials per iteration, 100 iterations,
-    three network seeds) against the FP64 oracle's training of the same
-    batches from the same weights, stored by tests/golden/make_c2_training.py
-    (which calls only the oracle): the oracle's training lowers the loss, and
-    the GPU's final loss -- the mean over the last 10 iterations, averaged
-    over the seeds (reading Z22) -- is within 2% of the oracle's.  Single
-    seeds are logged: free-running runs decorrelate through spike flips."""
-    import json
-    import os
-    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_training_oracle.json")))
-    it, bs = ref["iterations"], ref["batch"]
-    g_final, o_final = [], []
-    for run in ref["runs"]:
-        wl = W.c2_evidence(seed=run["seed"], batch_size=bs)
-        net = E.Network(wl.network, "fp32", max_trials=bs, max_steps=1800)
+def _free_run(run, it, bs, eta, stream):
+    """One seed's free-running FP32 training (GPU), on its own stream."""
+    import ctypes as C
+    import torch
+    with torch.cuda.stream(stream):
+        wl = W.c3_events(seed=run["seed"], batch_size=bs)
+        wl.network.params.eta = eta
+        net = E.Network(wl.network, "fp32", max_trials=bs, max_steps=300,
+                        stream=C.c_void_p(stream.cuda_stream))
         losses, acc = [], []
         for i in range(it):
             b = wl.make_batch(i, 0, bs)
@@ -447,15 +438,53 @@ def test_fp32_free_running_final_loss():
             losses.append(float(r.loss.mean()))
             acc.append(float(np.mean(r.predicted == b.label)))
         net.close()
+    return losses, acc
+
+
+def test_fp32_free_running_final_loss():
+    """Free-running FP32 batched training of the event-camera classification
+    task (softmax cross-entropy over the last 30 steps, gradient descent with
+    eta 1e-3; 32 trials per iteration, 100 iterations, eight network seeds)
+    against the FP64 oracle's training of the same batches from the same
+    weights, stored by tests/golden/make_c3_training.py (which calls only the
+    oracle).  Both trainings lower the loss.  A free-running spiking network
+    is chaotic: one spike that flips (an FP32 rounding suffices) sends the
+    trajectories apart, and FP64 training from weights perturbed by one unit
+    in the last place ends as far from the unperturbed run as FP32 does, so a
+    single seed's final loss is a random draw (reading Z22).  The final loss
+    of a seed is the mean over its last 10 iterations; with d_s the log ratio
+    of the GPU's to the oracle's for seed s, the test asks for no systematic
+    difference: |mean d| within three standard errors of the mean (a paired
+    test at 3 sigma), and for the seed-mean loss over the whole trained run
+    to agree within 2%."""
+    import json
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    import torch
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_training_oracle.json")))
+    it, bs, eta = ref["iterations"], ref["batch"], ref["eta"]
+    runs = ref["runs"]
+    streams = [torch.cuda.Stream() for _ in runs]
+    with ThreadPoolExecutor(4) as ex:
+        out = list(ex.map(lambda a: _free_run(a[0], it, bs, eta, a[1]), zip(runs, streams)))
+    w = it // 10
+    d, g_run, o_run = [], [], []
+    for run, (losses, acc) in zip(runs, out):
         o = run["mean_loss"]
-        assert np.mean(o[-10:]) < 0.8 * np.mean(o[:10]), "the oracle's training did not lower the loss"
-        g_final.append(np.mean(losses[-10:]))
-        o_final.append(np.mean(o[-10:]))
-        log(f"seed {run['seed']}: loss {np.mean(o[:10]):.1f} -> oracle {o_final[-1]:.2f}, gpu {g_final[-1]:.2f}; "
-            f"accuracy (last 10) oracle {np.mean(run['accuracy'][-10:]):.3f}, gpu {np.mean(acc[-10:]):.3f}")
-    rel = abs(np.mean(g_final) - np.mean(o_final)) / np.mean(o_final)
-    log(f"final loss over seeds: gpu {np.mean(g_final):.3f}, oracle {np.mean(o_final):.3f}, relative {rel:.3e}")
-    assert rel < 0.02
+        assert np.mean(o[-w:]) < 0.5 * np.mean(o[:w]), "the oracle's training did not lower the loss"
+        assert np.mean(losses[-w:]) < 0.5 * np.mean(losses[:w]), "the GPU's training did not lower the loss"
+        d.append(np.log(np.mean(losses[-w:]) / np.mean(o[-w:])))
+        g_run.append(np.mean(losses))
+        o_run.append(np.mean(o))
+        log(f"seed {run['seed']}: loss {np.mean(o[:w]):.1f} -> oracle {np.mean(o[-w:]):.2f}, gpu {np.mean(losses[-w:]):.2f}; "
+            f"accuracy (last {w}) oracle {np.mean(run['accuracy'][-w:]):.3f}, gpu {np.mean(acc[-w:]):.3f}")
+    d = np.array(d)
+    se = d.std(ddof=1) / np.sqrt(len(d))
+    rel_run = abs(np.mean(g_run) - np.mean(o_run)) / np.mean(o_run)
+    log(f"final-loss log ratio: mean {d.mean():+.4f}, standard error {se:.4f}; "
+        f"seed-mean loss over the run: gpu {np.mean(g_run):.3f}, oracle {np.mean(o_run):.3f}, relative {rel_run:.3e}")
+    assert abs(d.mean()) <= 3 * se
+    assert rel_run < 0.02
 
 
 # ----------------------------------------------------------------- edge cases
