@@ -364,6 +364,90 @@ def bench_online(args, wl, progress):
     print(json.dumps(out), flush=True)
 
 
+def equal_loss(args, W, E, T, m, stream, progress):
+    """FP32 batched against FP64 training over args.seeds network seeds: the
+    same batches from the same initial weights, m iterations each, in FP32
+    (batched) and FP64 (batched: the same arithmetic per trial as one trial
+    at a time).  A free-running spiking network is chaotic (one flipped spike
+    sends two runs apart), so one seed's final loss is a random draw and the
+    comparison is over the seeds.  The FP64 plain path (one trial per call,
+    gather delivery) is timed on the first args.plain_iters iterations of
+    each seed for the speedup.  Batches are generated before the timed
+    loops."""
+    import inspect
+    import torch
+    f = W.WORKLOADS[args.workload]
+    seed0 = inspect.signature(f).parameters["seed"].default
+    kw = {"batch_size": args.batch} if args.batch else {}
+    runs, t32, t64, tpl, npl = [], 0.0, 0.0, 0.0, 0
+
+    def train(net, batches, plain=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for b in batches:
+            if plain:
+                lt = [float(net.simulate(b.trial(i), train=True).loss[0]) for i in range(b.n_trials)]
+            else:
+                lt = net.simulate(b, train=True).loss
+            net.apply()
+            out.append(float(np.mean(lt)))
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    for s in range(args.seed_start, args.seed_start + args.seeds):
+        wl = f(seed=seed0 + 7919 * s, **kw)
+        bs = wl.batch_size
+        batches = [wl.make_batch(i, 0, bs) for i in range(m)]
+        progress(f"equal-loss seed {s}: {m} batches generated")
+        with torch.cuda.stream(stream):
+            cs = E.C.c_void_p(stream.cuda_stream)
+            net = E.Network(wl.network, "fp32", max_trials=bs, max_steps=T, stream=cs)
+            l32, e32 = train(net, batches)
+            net.close()
+            progress(f"equal-loss seed {s}: FP32 batched {e32:.1f} s")
+            net = E.Network(wl.network, "fp64", max_trials=bs, max_steps=T, stream=cs)
+            l64, e64 = train(net, batches)
+            net.close()
+            progress(f"equal-loss seed {s}: FP64 batched {e64:.1f} s")
+            k = min(args.plain_iters, m)
+            net = E.Network(wl.network, "fp64", max_trials=1, max_steps=T, delivery="gather", stream=cs)
+            lpl, epl = train(net, batches[:k], plain=True)
+            net.close()
+            progress(f"equal-loss seed {s}: FP64 plain {epl:.1f} s for {k} iterations")
+        t32 += e32
+        t64 += e64
+        tpl += epl
+        npl += k
+        runs.append({"seed": seed0 + 7919 * s, "loss_fp32": l32, "loss_fp64": l64, "loss_fp64_plain": lpl})
+    nl = max(1, m // 10)
+    f32 = np.array([np.mean(r["loss_fp32"][-nl:]) for r in runs])
+    f64 = np.array([np.mean(r["loss_fp64"][-nl:]) for r in runs])
+    d = np.log(f32 / f64)
+    r32 = np.array([np.mean(r["loss_fp32"]) for r in runs])
+    r64 = np.array([np.mean(r["loss_fp64"]) for r in runs])
+    n_it = m * len(runs)
+    return {"iterations": m, "seeds": len(runs), "trials_per_batch": int(batches[0].n_trials),
+            "seconds_per_iteration_fp32_batched": t32 / n_it, "seconds_per_iteration_fp64_batched": t64 / n_it,
+            "seconds_per_iteration_fp64_plain": tpl / npl, "plain_iterations_timed": npl,
+            "speedup_fp32_batched": (tpl / npl) / (t32 / n_it),
+            "speedup_over_fp64_batched": (t64 / n_it) / (t32 / n_it),
+            "final_loss_fp32": float(f32.mean()), "final_loss_fp64": float(f64.mean()),
+            "final_loss_rel_diff": float(abs(f32.mean() - f64.mean()) / f64.mean()),
+            "final_log_ratio_mean": float(d.mean()),
+            "final_log_ratio_se": float(d.std(ddof=1) / np.sqrt(len(d))) if len(d) > 1 else None,
+            "run_loss_fp32": float(r32.mean()), "run_loss_fp64": float(r64.mean()),
+            "run_loss_rel_diff": float(abs(r32.mean() - r64.mean()) / r64.mean()),
+            "per_seed_final": [[float(a), float(b)] for a, b in zip(f32, f64)],
+            "plain_first_loss_rel_diff": float(max(abs(r["loss_fp64_plain"][0] - r["loss_fp64"][0])
+                                                   / abs(r["loss_fp64"][0]) for r in runs)),
+            "comparison": "trained: per seed, final loss = mean over the last %d of %d iterations (FP32 batched vs "
+                          "FP64 batched); seed means compared, and the mean log ratio with its standard error; "
+                          "run loss = mean over all iterations" % (nl, m),
+            "note": "same batches and initial weights per seed; speedup = FP64 plain seconds per iteration (first "
+                    "iterations of each seed) / FP32 batched seconds per iteration (host batches in both)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +472,13 @@ def main():
                     help="training iterations of the FP64 plain comparison (<= warmup + steps); its final loss is "
                          "the mean over the last 10%% of them, compared with the FP32 run's over the same iterations")
     ap.add_argument("--batch", type=int, default=None, help="trials per batch (default: the workload's)")
+    ap.add_argument("--plain-iters", type=int, default=5,
+                    help="with --seeds: iterations of each seed timed on the FP64 plain path")
+    ap.add_argument("--seed-start", type=int, default=0,
+                    help="with --seeds: the first network seed's index (seed = default + 7919 * index)")
+    ap.add_argument("--seeds", type=int, default=1,
+                    help="with --fp64-iters: compare FP32 batched and FP64 plain training over this many network "
+                         "seeds (each trained from scratch for --fp64-iters iterations)")
     ap.add_argument("--delivery", choices=("scatter", "gather"), default="scatter",
                     help="spike delivery of the FP32 run: scatter into LDS delay rings (default) or target-side "
                          "gather (one kernel per step, every target sums its arriving synapses)")
@@ -529,7 +620,9 @@ def main():
                                          "copy-calibrated"}
 
     fp64 = None
-    if not args.no_fp64:
+    if not args.no_fp64 and (args.seeds > 1 or args.seed_start > 0):
+        fp64 = equal_loss(args, W, E, T, max(1, args.fp64_iters), stream, progress)
+    elif not args.no_fp64:
         # the FP64 plain path (same kernels in double, one trial at a time,
         # deterministic gather delivery), trained on the same batches from
         # the same initial weights as the FP32 run's first iterations

@@ -487,6 +487,81 @@ def test_fp32_free_running_final_loss():
     assert rel_run < 0.02
 
 
+def _repeat_trial(b, n):
+    """A batch of n copies of the single-trial batch b."""
+    m = int(b.in_ptr[1])
+    out = W.Batch(n_steps=np.repeat(b.n_steps, n), in_ptr=np.arange(n + 1, dtype=np.uint64) * m,
+                  in_step=np.tile(b.in_step, n), in_src=np.tile(b.in_src, n))
+    if b.target is not None:
+        out.target = np.repeat(b.target, n, axis=0)
+    if b.label is not None:
+        out.label = np.repeat(b.label, n)
+    if b.window is not None:
+        out.window = np.repeat(b.window, n, axis=0)
+    if b.forced_ptr is not None:
+        f = int(b.forced_ptr[1])
+        out.forced_ptr = np.arange(n + 1, dtype=np.uint64) * f
+        out.forced_step = np.tile(b.forced_step, n)
+        out.forced_neuron = np.tile(b.forced_neuron, n)
+    return out
+
+
+def test_device_kahan_accumulation_over_many_trials():
+    """Compensated FP32 summation on the device against FP64 (pin P15;
+    Higham, "Accuracy and Stability of Numerical Algorithms", Sec. 4.3: a
+    Kahan sum of terms x_i is within 2u sum|x_i| + O(n u^2) of the exact
+    sum).  256 copies of one C3 trial add the same FP32 terms 256 times (the
+    forward pass is deterministic), so the exact sum is 256 times one
+    trial's.  The device sums the arrivals of each chunk of 8 trials with
+    Kahan (2u), stores each chunk's sum in FP32 (u) and adds the 32 chunk
+    sums with Kahan (2u); one trial's gradient G_1 carries 2u of its own.
+    The recurrent spikes are teacher-forced (Poisson at 20 Hz), so that the
+    oracle evaluates the same spike trains.
+    Hence |G_256 - 256 G_1| <= 7u * 256 * A_1 + O(u^2), with A_1 the sum of
+    the absolute values of one trial's terms; the oracle's per-entry bound
+    at the GPU's weights on the GPU's psi is exactly 7u A_1 (its 7u also
+    count the roundings of the feedback and the archive, which are the same
+    in every copy and cancel here).  Uncompensated FP32 accumulation of the same
+    copies exceeds this bound on many synapses (evaluated here with numpy
+    float32), so the bound tells the two apart."""
+    n = 256
+    wl = W.c3_events(batch_size=1)
+    b1 = W.forced_poisson(wl.make_batch(0, 0, 1), wl.network.n_rec, 20.0, wl.network.params.dt, seed=7, n_ref=2)
+    net = E.Network(wl.network, "fp32", max_trials=1, max_steps=300)
+    net.simulate(b1, train=True)
+    G1 = net.grads()
+    psis = read_psis(net, b1)
+    w = net.weights()
+    net.close()
+    net = E.Network(wl.network, "fp32", max_trials=n, max_steps=300)
+    net.simulate(_repeat_trial(b1, n), train=True)
+    GN = net.grads()
+    assert all(np.array_equal(w[k], v) for k, v in net.weights().items())
+    net.close()
+    on = oracle_at(wl.network, w)
+    B1 = O.fp32_bounds(on, b1, 0, psi_given=psis[0])["b"]   # 7u A_1 per entry
+    tight = {}
+    for k in KEYS:
+        g1 = np.asarray(G1[k], np.float64).ravel()
+        gn = np.asarray(GN[k], np.float64).ravel()
+        b1 = np.asarray(B1[k], np.float64).ravel()
+        assert b1.size == g1.size, k
+        lim = 1.001 * n * b1 + 1e-300
+        dev = np.abs(gn - n * g1)
+        assert np.all(dev <= lim), (k, int((dev > lim).sum()), float((dev / lim).max()))
+        # plain FP32 accumulation of the same n copies of one trial's sum
+        x = g1.astype(np.float32)
+        acc = np.zeros_like(x)
+        for _ in range(n):
+            acc = (acc + x).astype(np.float32)
+        live = b1 > 0
+        over = np.abs(acc.astype(np.float64) - n * g1) > lim
+        tight[k] = (float((dev[live] / lim[live]).max(initial=0.0)), float(over[live].mean()) if live.any() else 0.0)
+    log("Kahan over 256 trials: " + "; ".join(f"{k} dev/bound {tight[k][0]:.3f}, plain FP32 beyond the bound on "
+                                             f"{100 * tight[k][1]:.1f}% of synapses" for k in KEYS))
+    assert tight["w_in"][1] > 0.05 and tight["w_rec"][1] > 0.05
+
+
 # ----------------------------------------------------------------- edge cases
 
 def test_silent_network_and_single_step_trial():
