@@ -403,16 +403,20 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
     // delivery table: each source's part starts on a kDlGrain boundary (so
     // that the parts can be laid out independently); inside it, the
-    // segments of tiles 0..KT-1, each placed by dl_place
+    // segments of the tiles in tile_rank order, each placed by dl_place
     const uint32_t KT = d.KT, TS = d.TS;
     const uint64_t NS = n->NS;
+    std::vector<uint32_t> by_rank(KT);  // the tile at each place
+    for (uint32_t k = 0; k < KT; ++k) by_rank[eprop::tile_rank(k, KT)] = k;
     auto src_weight = [&](uint64_t src) { return (uint64_t)sm_ptr[src]; };
     std::vector<uint64_t> part(NS + 1, 0);
     parallel_ranges(NS, nt, src_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
       for (uint64_t src = s0; src < s1; ++src) {
         uint64_t cur = 0, at = 0;
-        for (uint32_t k = 0; k < KT; ++k)
+        for (uint32_t r = 0; r < KT; ++r) {
+          const uint32_t k = by_rank[r];
           cur = dl_place(cur, tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k], sizeof(real), &at);
+        }
         part[src] = (cur + eprop::kDlGrain - 1) / eprop::kDlGrain * eprop::kDlGrain;
       }
     });
@@ -430,11 +434,12 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     parallel_ranges(NS, nt, src_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
       for (uint64_t src = s0; src < s1; ++src) {
         uint64_t cur = 0, at = 0;
-        for (uint32_t k = 0; k < KT; ++k) {
+        for (uint32_t r = 0; r < KT; ++r) {
+          const uint32_t k = by_rank[r];
           const uint32_t q0 = tseg[src * (KT + 1) + k], L = tseg[src * (KT + 1) + k + 1] - q0;
           cur = dl_place(cur, L, sizeof(real), &at);
           const uint32_t word = (uint32_t)((part[src] + at) / 4);
-          dsegh[src * KT + k] = make_uint2(word, L);
+          dsegh[src * KT + r] = make_uint2(word, L);
           real *wp = reinterpret_cast<real *>(dlh.data() + word);
           uint16_t *op = reinterpret_cast<uint16_t *>(wp + L);
           for (uint32_t i = 0; i < L; ++i) {
@@ -1835,7 +1840,7 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
       if (e == hipSuccess) e = hipMemcpy(sg.data(), d.dseg, sg.size() * sizeof(uint2), hipMemcpyDeviceToHost);
       for (uint64_t src = 0; src < n->NS && e == hipSuccess; ++src)
         for (uint32_t k = 0; k < KT; ++k) {
-          const uint2 g = sg[src * KT + k];
+          const uint2 g = sg[src * KT + eprop::tile_rank(k, KT)];
           const real *w = reinterpret_cast<const real *>(dl.data() + g.x);
           const uint32_t q0 = ts[src * (KT + 1) + k];
           for (uint32_t i = 0; i < g.y; ++i) put(n->sm2caller[q0 + i], w[i]);

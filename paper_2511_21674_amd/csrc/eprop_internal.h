@@ -10,7 +10,8 @@
 //                        a multiple of sizeof(real); it starts on a kDlGrain-byte
 //                        boundary if it would otherwise cross one it need not cross
 //                        (so that a delivery reads as few lines as the segment's size
-//                        allows); dseg[src][k] = {word index of the segment, L}
+//                        allows); tiles in tile_rank order; dseg[src][tile_rank(k)] =
+//                        {word index of the segment, L}
 //   graph, target-major  tm_ptr[J+1], tm_syn[S] = source | delay << 24, tm_w[S]
 //                        (sources: inputs 0..I-1, then recurrent I..I+J-1;
 //                        each target's list sorted by source), tm_dpos[S]
@@ -64,6 +65,19 @@ constexpr int kMaxDevices = 64;
 // Placement unit of the delivery table's segments (bytes): the line a
 // partial read of device memory costs.
 constexpr uint32_t kDlGrain = 128;
+
+// Order of a source's tile segments in the delivery table and in dseg:
+// tiles grouped by k mod kXcds, since workgroup i of a launch runs on
+// accelerator die i mod kXcds and the tiles of one trial are consecutive
+// workgroups, so each die's tiles read one contiguous stretch of a source's
+// row (and of its segment lookups) through their shared L2.
+constexpr uint32_t kXcds = 8;
+__host__ __device__ inline uint32_t tile_rank(uint32_t k, uint32_t KT) {
+  const uint32_t g = k % kXcds;
+  uint32_t r = k / kXcds;
+  for (uint32_t h = 0; h < g; ++h) r += (KT - h + kXcds - 1) / kXcds;  // tiles of group h
+  return r;
+}
 
 // Element of the delay ring.  FP32: the input current of a step is summed
 // in fixed point, int64_t (F up to 62 fraction bits: every FP32 weight of

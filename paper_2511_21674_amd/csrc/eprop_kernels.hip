@@ -396,11 +396,12 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   const uint64_t in_lo = isp[t], in_hi = isp[t + 1];
   const uint32_t n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
   const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
+  const uint32_t rk = tile_rank(k, n.KT);  // this tile's place in a source's dseg row
   uint2 iseg[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
 #pragma unroll
   for (uint32_t u = 0; u < 2; ++u) {
     const uint32_t item = threadIdx.x + u * blockDim.x;
-    if (item < n_in) iseg[u] = n.dseg[(size_t)in_src[in_lo + item] * n.KT + k];
+    if (item < n_in) iseg[u] = n.dseg[(size_t)in_src[in_lo + item] * n.KT + rk];
   }
   uint32_t n_rec = 0;
   const uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp;
@@ -422,7 +423,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 #pragma unroll
     for (uint32_t u = 0; u < 2; ++u)
       if ((uint32_t)(ahead[u] >> 32) == t)
-        aseg[u] = n.dseg[(size_t)(n.I + min((uint32_t)ahead[u], n.J - 1u)) * n.KT + k];
+        aseg[u] = n.dseg[(size_t)(n.I + min((uint32_t)ahead[u], n.J - 1u)) * n.KT + rk];
     // every tile's count of step t (published by the tiles, possibly still on the way)
     const uint32_t kk = threadIdx.x;
     uint32_t c = 0;
@@ -496,7 +497,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
     }
 #pragma unroll
     for (uint32_t u = 0; u < 2; ++u)
-      if (look[u]) seg[u] = n.dseg[(size_t)src[u] * n.KT + k];
+      if (look[u]) seg[u] = n.dseg[(size_t)src[u] * n.KT + rk];
     const uint32_t np0 = (seg[0].y + kPiece - 1) / kPiece, np1 = (seg[1].y + kPiece - 1) / kPiece;
     uint32_t npieces;
     const uint32_t pre = block_exclusive_scan(np0 + np1, wsum, &npieces);
@@ -1852,7 +1853,7 @@ __global__ __launch_bounds__(1024) void k_apply_blk(DevNet<real> n, uint32_t n_a
     dw[u] = 0;
     if (i < nsrc) {
       lo[u] = n.tseg[(size_t)(s0 + i) * (n.KT + 1) + k];
-      const uint2 sg = n.dseg[(size_t)(s0 + i) * n.KT + k];
+      const uint2 sg = n.dseg[(size_t)(s0 + i) * n.KT + tile_rank(k, n.KT)];
       dw[u] = sg.x;
       len[u] = sg.y;
     }
