@@ -378,8 +378,8 @@ typedef enum {
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
   EPROP_STATE_LAYOUT = 18,     /* uint64 [17]: neurons per tile, tiles per trial, bytes per
-                                  delay-ring entry (8: 64-bit fixed point in FP32 or double in
-                                  FP64, 4: 32-bit fixed point in FP32), threads per tile,
+                                  delay-ring entry (4: 32-bit fixed point in FP32, 8: double in
+                                  FP64), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
                                   forward launch, gather delivery (0/1), synapses per delivery
                                   piece, pieces in flight per lane group, adjoint-kernel

@@ -855,13 +855,11 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
     uint32_t ts_par = round_up((J + want - 1) / want, 64);
     ts_par = std::max<uint32_t>(ts_par, std::min<uint32_t>(n->Jp, 512));
     ts_par = std::min(ts_par, n->Jp);
-    // FP32: exact 64-bit fixed-point ring unless it would force more tiles
-    // than the device spreads the trials over; then 32-bit entries
-    uint32_t ts_lds = ts_max(8);
-    if (!n->fp64 && ts_lds < ts_par) {
-      ring_bytes = 4;
-      ts_lds = ts_max(4);
-    }
+    // FP32: 32-bit fixed-point ring entries (each arrival rounded to half a
+    // quantum, 2^-31 of the input bound: finer than an FP32 running sum of
+    // the same arrivals, whose additions round at 2^-24 of it); FP64: double
+    ring_bytes = n->fp64 ? 8u : 4u;
+    const uint32_t ts_lds = ts_max(ring_bytes);
     if (ts_lds < 64) {
       g_create_error = "not enough LDS for a tile of 64 neurons";
       delete n;
@@ -1159,7 +1157,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     return EPROP_ERR_UNSUPPORTED;
   }
   if (time_driven) {
-    const size_t need = (size_t)n->Bcap * (n->Tcap + 1) * n->Jp * sizeof(real);
+    const size_t need = (size_t)n->Bcap * n->Jp * n->Tp * sizeof(real);  // neuron-major [b][j][Tp]
     uint8_t *lb = static_cast<uint8_t *>(n->Lbuf);
     if (!dgrow(n, &lb, &n->cap_Lbuf, need)) {
       set_fail(n, "out of device memory for the time-driven learning signal");

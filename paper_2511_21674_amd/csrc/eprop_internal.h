@@ -26,8 +26,7 @@
 //   neuron state         v[b][Jp], a[b][Jp], nst[b][Jp] (refractory count | z << 7)
 //   delay ring           ring[b][R][Jp], R = max_delay + 1 (scatter delivery; held in
 //                        LDS by the tile that owns the targets, saved between launches;
-//                        FP32: 64-bit (or, where LDS is short, 32-bit) fixed point
-//                        with scale 2^-F; FP64: double)
+//                        FP32: 32-bit fixed point with scale 2^-F; FP64: double)
 //   input bound          l1max: max over targets of the sum of |w| of incoming
 //                        synapses (FP32 bits), which fixes F
 //   tile segments        tseg[src][k], k = 0..KT: first synapse of source src whose
@@ -80,13 +79,13 @@ __host__ __device__ inline uint32_t tile_rank(uint32_t k, uint32_t KT) {
 }
 
 // Element of the delay ring.  FP32: the input current of a step is summed
-// in fixed point, int64_t (F up to 62 fraction bits: every FP32 weight of
-// the network converts exactly, so the sum is exact and is rounded once) or
-// int32_t where 8-byte entries do not fit LDS (F up to 30; each weight is
-// rounded to a multiple of 2^-F).  Integer LDS atomics are an order of
-// magnitude faster than float ones on this GPU, and the sum does not depend
-// on the order of arrival.  F follows from l1max, so no sum can overflow.
-// FP64: plain double.
+// in 32-bit fixed point (int32_t, F up to 30 fraction bits; each arrival's
+// weight is rounded to a multiple of 2^-F, at most 2^-31 of the input bound
+// off, where an FP32 running sum of the same arrivals would round each
+// addition by up to 2^-24 of it); the integer sum is exact, so it does not
+// depend on the order of arrival.  Integer LDS atomics are an order of
+// magnitude faster than float ones on this GPU.  F follows from l1max, so no
+// sum can overflow.  FP64: plain double.
 
 template <typename real>
 struct DevNet {
@@ -133,7 +132,7 @@ struct DevNet {
   real *v, *a;
   uint8_t *nst;
   void *ring;                   // ring_t [Bcap][R][Jp]
-  uint32_t ring_bytes;          // 8: int64_t (FP32) or double (FP64); 4: int32_t (FP32)
+  uint32_t ring_bytes;          // 4: int32_t (FP32); 8: double (FP64)
   real *psi, *phi;
   uint32_t *l1max;              // [1] bound on |input current| per step (FP32 bits)
   uint64_t *rec_bits, *in_bits, *forced_bits;

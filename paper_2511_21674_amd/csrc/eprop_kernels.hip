@@ -305,12 +305,11 @@ struct RingScale {
 };
 
 // F from the bound on |input current| per step: the largest F with
-// l1max * 2^F <= 2^(bits-2) (30 for int32, 62 for int64), so that every
-// partial sum and every rounding excess stays inside the integer.  Below 8
-// fraction bits the bound is reported as an error.
-template <typename A>
+// l1max * 2^F <= 2^30, so that every partial sum and every rounding excess
+// stays inside the int32 entry.  Below 8 fraction bits the bound is
+// reported as an error.
 __device__ inline RingScale ring_scale(const uint32_t *l1max, uint32_t *err) {
-  constexpr int top = sizeof(A) == 8 ? 62 : 30;
+  constexpr int top = 30;
   const float l1 = __uint_as_float(*l1max);
   int F = top;
   if (l1 > 0.f) F = min(top, top - (int)ceilf(log2f(l1)));
@@ -324,12 +323,8 @@ __device__ inline RingScale ring_scale(const uint32_t *l1max, uint32_t *err) {
 __device__ inline void ring_add(int32_t *p, float w, const RingScale &sc) {
   atomicAdd(p, __float2int_rn(w * sc.to_fix));
 }
-__device__ inline void ring_add(int64_t *p, float w, const RingScale &sc) {
-  atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__float2ll_rn(w * sc.to_fix));
-}
 __device__ inline void ring_add(double *p, double w, const RingScale &) { atomicAdd(p, w); }
 __device__ inline float ring_value(int32_t x, const RingScale &sc) { return (float)x * sc.from_fix; }
-__device__ inline float ring_value(int64_t x, const RingScale &sc) { return (float)x * sc.from_fix; }
 __device__ inline double ring_value(double x, const RingScale &) { return x; }
 
 // Position of the r-th set bit of m (r < popcount(m)).
@@ -584,7 +579,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   __shared__ uint32_t gtot;
   __shared__ uint32_t wsum[17];
   RingScale sc{1.f, 1.f};
-  if constexpr (sizeof(real) == 4) sc = ring_scale<ring_t>(n.l1max, &n.ctl[CTL_ERR]);
+  if constexpr (sizeof(real) == 4) sc = ring_scale(n.l1max, &n.ctl[CTL_ERR]);
 
   const size_t gs = (size_t)b * n.Jp + j0;
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -1314,18 +1309,138 @@ __global__ __launch_bounds__(256) void k_synapse(DevNet<real> n, uint32_t ginst,
 template <typename real>
 __global__ __launch_bounds__(256) void k_learning_signal(DevNet<real> n, real *L) {
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
-  const uint64_t per = (uint64_t)(n.Tcap + 1) * n.Jp;
+  const uint64_t per = (uint64_t)n.Jp * n.Tp;  // neuron-major: L[b][j][u], u < Tp
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)ntr * per;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t b = (uint32_t)(i / per);
-    const uint32_t u = (uint32_t)((i % per) / n.Jp), j = (uint32_t)(i % n.Jp);
+    const uint32_t j = (uint32_t)((i % per) / n.Tp), u = (uint32_t)(i % n.Tp);
     const uint64_t t = (uint64_t)u + n.d_out;
     double acc = 0.0;
-    if (j < n.J && u >= 1 && t + n.d_ls <= n.T[b]) {
+    if (j < n.J && u >= 1 && u <= n.Tcap && t + n.d_ls <= n.T[b]) {
       const double *E = n.err + ((size_t)b * (n.Tcap + 2) + t) * n.K;
       for (uint32_t k = 0; k < n.K; ++k) acc += (double)n.fb[(size_t)j * n.K + k] * E[k];
     }
     L[i] = (real)acc;
+  }
+}
+
+// psi[b][t][j] (time-major, as the forward pass writes it) -> out[b][j][t]
+// (neuron-major, row length Tp), through 64 x 64 LDS tiles.
+template <typename real>
+__global__ __launch_bounds__(256) void k_transpose_psi(DevNet<real> n, real *out) {
+  __shared__ real tile[64][65];
+  const uint32_t b = blockIdx.z;
+  if (b >= n.ctl[CTL_NTRIALS]) return;
+  const uint32_t t0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const uint32_t tx = threadIdx.x & 63u, ty = threadIdx.x >> 6;  // 4 rows per pass
+  for (uint32_t r = ty; r < 64; r += 4) {
+    const uint32_t t = t0 + r, j = j0 + tx;
+    tile[r][tx] = t <= n.Tcap && j < n.Jp ? n.psi[((size_t)b * (n.Tcap + 1) + t) * n.Jp + j] : (real)0;
+  }
+  __syncthreads();
+  for (uint32_t r = ty; r < 64; r += 4) {
+    const uint32_t j = j0 + r, t = t0 + tx;
+    if (j < n.Jp && t < n.Tp) out[((size_t)b * n.Jp + j) * n.Tp + t] = tile[tx][r];
+  }
+}
+
+// The time-driven gradient with one workgroup per (target j, trial chunk
+// c): the target's psi and learning-signal rows of the chunk's trials are
+// staged in LDS once (neuron-major copies), and each thread runs the
+// eligibility recursion of eq. eligibility-vector-substituted and eq.
+// filtered-eligibility-trace for one incoming synapse at a time over every
+// step of every trial of the chunk, with e, ebar in registers; the arrival
+// indicator x^t comes from the source's spike-time list (emission steps,
+// ascending) and the full reset from the target's own.  Sums, counts and
+// the regulariser term as in k_td_synapse.  LDS: 2 * ginst * Tp reals.
+template <typename real>
+__global__ __launch_bounds__(256) void k_td_target(DevNet<real> n, const real *L, const real *psnm, uint32_t ginst,
+                                                   uint32_t nchunk, real *partial) {
+  extern __shared__ __align__(16) unsigned char td_smem[];
+  real *lps = reinterpret_cast<real *>(td_smem);  // [ginst][Tp] psi rows
+  real *lL = lps + (size_t)ginst * n.Tp;          // [ginst][Tp] learning-signal rows
+  const uint32_t j = blockIdx.x, c = blockIdx.y;
+  const uint32_t ntr = n.ctl[CTL_NTRIALS];
+  const uint32_t b0 = c * ginst, nb = b0 < ntr ? min(ginst, ntr - b0) : 0u;
+  if (j >= n.J || nb == 0) return;
+  for (uint32_t bi = 0; bi < nb; ++bi) {
+    const size_t row = ((size_t)(b0 + bi) * n.Jp + j) * n.Tp;
+    for (uint32_t t = threadIdx.x; t < n.Tp; t += blockDim.x) {
+      lps[(size_t)bi * n.Tp + t] = psnm[row + t];
+      lL[(size_t)bi * n.Tp + t] = L[row + t];
+    }
+  }
+  __syncthreads();
+  const real beta = n.beta_j[j];
+  const real kappa = (real)n.kappa_e_d;
+  unsigned long long nev = 0, nfl = 0;
+  const uint32_t q1 = n.tm_ptr[j + 1];
+  for (uint32_t q = n.tm_ptr[j] + threadIdx.x; q < q1; q += blockDim.x) {
+    const uint32_t pk = n.tm_syn[q];
+    const uint32_t src = pk & 0xFFFFFFu, D = pk >> 24;
+    real s = 0, cc = 0;
+    for (uint32_t bi = 0; bi < nb; ++bi) {
+      const uint32_t b = b0 + bi, T = n.T[b];
+      const real *ps = lps + (size_t)bi * n.Tp, *Lb = lL + (size_t)bi * n.Tp;
+      // arrivals: the source's emission steps + D, in order
+      const uint16_t *st = n.spk_t + (size_t)b * n.spk_stride + (size_t)src * n.Lc;
+      const uint32_t cnt = n.spk_cnt[(size_t)b * n.NS + src];
+      uint32_t ci = 0, next = cnt ? (uint32_t)st[0] + D : 0xFFFFFFFFu;
+      // the target's own spikes (full reset: the membrane component restarts after them)
+      const uint16_t *sj = n.spk_t + (size_t)b * n.spk_stride + (size_t)(n.I + j) * n.Lc;
+      const uint32_t cj = n.reset_mode == 1 ? n.spk_cnt[(size_t)b * n.NS + n.I + j] : 0u;
+      uint32_t ri = 0, rnext = cj ? (uint32_t)sj[0] + 1u : 0xFFFFFFFFu;
+      real ev = 0, ea = 0, eb = 0, psi_prev = 0, es = 0, ec = 0;
+      const uint32_t t_reg = T > n.d_out ? T - n.d_out : 0u;
+      uint32_t arrivals = 0;
+      for (uint32_t t = 1; t <= T; ++t) {
+        const bool x = t == next;
+        if (x) {
+          ++ci;
+          next = ci < cnt ? (uint32_t)st[ci] + D : 0xFFFFFFFFu;
+        }
+        const bool zr = t == rnext;
+        if (zr) {
+          ++ri;
+          rnext = ri < cj ? (uint32_t)sj[ri] + 1u : 0xFFFFFFFFu;
+        }
+        arrivals += x ? 1u : 0u;
+        const real psi_now = ps[t];
+        const real ea_new = psi_prev * ev + (n.rho - psi_prev * beta) * ea;
+        const real ev_new = (zr ? (real)0 : n.alpha) * ev + (x ? (real)1 : (real)0);
+        const real e = psi_now * (ev_new - beta * ea_new);
+        eb = kappa * eb + e;
+        ev = ev_new;
+        ea = ea_new;
+        psi_prev = psi_now;
+        kahan_add(s, cc, Lb[t] * eb);
+        if (t <= t_reg) kahan_add(es, ec, e);
+      }
+      if (n.c_reg != 0.0) {
+        const double creg = n.c_reg / (double)T *
+                            ((double)n.spk_cnt[(size_t)b * n.NS + n.I + j] / (double)T - n.f_target);
+        kahan_add(s, cc, (real)(creg * ((double)es + (double)ec)));
+      }
+      nev += arrivals;
+      nfl += arrivals ? 1u : 0u;
+    }
+    if (nchunk == 1) {
+      real gs = n.g_fresh ? (real)0 : n.gs[q], gc = n.g_fresh ? (real)0 : n.gc[q];
+      kahan_add(gs, gc, s);
+      kahan_add(gs, gc, cc);
+      n.gs[q] = gs;
+      n.gc[q] = gc;
+    } else {
+      partial[(size_t)c * n.S + q] = s + cc;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    nev += __shfl_down(nev, o);
+    nfl += __shfl_down(nfl, o);
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    if (nev) atomicAdd(&n.evcnt[((blockIdx.x + blockIdx.y) * 4 + (threadIdx.x >> 6)) & 63u], nev);
+    if (nfl) atomicAdd(&n.cnt[CNT_FLUSH], nfl);
   }
 }
 
@@ -1361,7 +1476,7 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
     for (uint32_t bi = 0; bi < nb; ++bi) {
       const uint32_t b = b0 + bi, T = n.T[b];
       const real *ps = n.psi + (size_t)b * (n.Tcap + 1) * n.Jp + j;
-      const real *Lb = L + (size_t)b * (n.Tcap + 1) * n.Jp + j;
+      const real *Lb = L + ((size_t)b * n.Jp + j) * n.Tp;
       real ev = 0, ea = 0, eb = 0, psi_prev = 0, es = 0, ec = 0;
       const uint32_t t_reg = T > n.d_out ? T - n.d_out : 0u;
       uint32_t arrivals = 0;
@@ -1387,7 +1502,7 @@ __global__ __launch_bounds__(256) void k_td_synapse(DevNet<real> n, const real *
         ev = ev_new;
         ea = ea_new;
         psi_prev = psi_now;
-        kahan_add(s, cc, Lb[(size_t)t * n.Jp] * eb);
+        kahan_add(s, cc, Lb[t] * eb);
         if (t <= t_reg) kahan_add(es, ec, e);
       }
       if (n.c_reg != 0.0) {
@@ -2120,7 +2235,7 @@ struct FwdKernels {
 template <typename real>
 const void *fwd_kernel(uint32_t ring_bytes, bool forced, uint32_t v) {
   if constexpr (sizeof(real) == 8) return FwdKernels<double, double>::get(forced, v);
-  else return ring_bytes == 8 ? FwdKernels<float, int64_t>::get(forced, v) : FwdKernels<float, int32_t>::get(forced, v);
+  else return FwdKernels<float, int32_t>::get(forced, v);
 }
 
 template <typename real>
@@ -2160,8 +2275,6 @@ void Launch<real>::forward_tiled(const DevNet<real> &n, uint32_t nsteps, bool fo
     const uint32_t grid = (b0 + per <= n.Bcap ? per : n.Bcap - b0) * n.KT;
     if constexpr (sizeof(real) == 8)
       FwdKernels<double, double>::launch(n, nsteps, b0, forced, v, grid, sh.tile_block, smem, s);
-    else if (n.ring_bytes == 8)
-      FwdKernels<float, int64_t>::launch(n, nsteps, b0, forced, v, grid, sh.tile_block, smem, s);
     else
       FwdKernels<float, int32_t>::launch(n, nsteps, b0, forced, v, grid, sh.tile_block, smem, s);
   }
@@ -2207,9 +2320,20 @@ template <typename real>
 void Launch<real>::time_driven(const DevNet<real> &n, const Shapes &sh, uint32_t n_trials, real *L, real *partial,
                                hipStream_t s) {
   const uint32_t nchunk = (n_trials + sh.ginst - 1) / sh.ginst;
-  k_learning_signal<real><<<grid_for((uint64_t)n_trials * (n.Tcap + 1) * n.Jp, 256, 16384), 256, 0, s>>>(n, L);
-  if (n.S > 0)
+  k_learning_signal<real><<<grid_for((uint64_t)n_trials * n.Jp * n.Tp, 256, 16384), 256, 0, s>>>(n, L);
+  // one workgroup per target when the chunk's psi and L rows fit LDS
+  const size_t smem = (size_t)2 * sh.ginst * n.Tp * sizeof(real);
+  if (n.S > 0 && smem <= (size_t)160 * 1024) {
+    if (smem > (size_t)64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_td_target<real>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    // psi transposed into the arrival archive's buffer, which the
+    // time-driven gradient does not use
+    k_transpose_psi<real><<<dim3((n.Tp + 63) / 64, (n.Jp + 63) / 64, n_trials), 256, 0, s>>>(n, n.phi);
+    k_td_target<real><<<dim3(n.J, nchunk), 256, smem, s>>>(n, L, n.phi, sh.ginst, nchunk, partial);
+  } else if (n.S > 0) {
     k_td_synapse<real><<<cdiv(n.S * nchunk, 256), 256, 0, s>>>(n, L, sh.ginst, nchunk, partial);
+  }
   if (nchunk > 1 && n.S > 0) k_synapse_reduce<real><<<grid_for(n.S, 256, 16384), 256, 0, s>>>(n, nchunk, partial);
   k_td_output<real><<<grid_for((uint64_t)n_trials * n.K * n.Jp, 256, 16384), 256, 0, s>>>(n);
 }
