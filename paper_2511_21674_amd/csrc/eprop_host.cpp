@@ -559,6 +559,7 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
   }
   { auto o = conv(beta); cp((void *)d.beta_j, o.data(), o.size() * sizeof(real)); }
   d.any_alif = std::any_of(beta.begin(), beta.end(), [](double x) { return x != 0.0; }) ? 1 : 0;
+  d.beta_a = (real)n->cfg.beta_a;
   const size_t KJ = (size_t)n->K * n->Jp;
   std::vector<double> wo(KJ, 0.0), fbp(KJ, 0.0);
   for (uint32_t k = 0; k < n->K; ++k)
@@ -1283,7 +1284,6 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     } else {
       for (uint32_t i = 0; i < nblk; ++i) record_block(n, d, forced, s);
     }
-    if (!n->gather) Launch<real>::rec_lists(d, ntr, s);  // the tiled kernel writes bitsets only
   };
   // device time of fn on the stream (best of two runs; setup() first each time)
   auto timed = [&](auto setup, auto fn) {
@@ -1367,6 +1367,8 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   forward();
   if (e != hipSuccess) goto device_error;
   if (prof) (void)hipEventRecord(n->ev[2], s);
+  // (timed with the readout: the forward phase holds the forward kernel only)
+  if (!n->gather) Launch<real>::rec_lists(d, ntr, s);  // the tiled kernel writes bitsets only
   Launch<real>::readout(d, s);
   if (prof) (void)hipEventRecord(n->ev[3], s);
   // the gradient pairs hold nothing yet after an update (or at start): the

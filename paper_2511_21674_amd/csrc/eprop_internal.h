@@ -124,6 +124,7 @@ struct DevNet {
   const uint16_t *tm_loc;       // blocked update: [S] each synapse's place in its block's source-major segments
   unsigned long long *tsum;     // blocked update: [Jp] per-target sum of |w| * kBoundScale
   const real *beta_j;           // beta_a for ALIF neurons, 0 for LIF [Jp]
+  real beta_a;                  // the ALIF neurons' beta_a
   int32_t any_alif;             // some beta_j is nonzero
   real *w_out, *fb;             // [K][Jp], [Jp][K]
   real *gos, *goc, *adam_mo, *adam_vo;   // [K][Jp]

@@ -371,10 +371,11 @@ __device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
 // the default.
 constexpr uint32_t kFwdVariants = 4;
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // a parked list entry that had not arrived
-__host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 1 ? 16u : v == 2 ? 4u : v == 3 ? 16u : 8u; }
-__host__ __device__ constexpr uint32_t fwd_unroll(uint32_t v) { return v == 1 ? 4u : v == 2 ? 16u : 8u; }
+__host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 2 ? 4u : v == 3 ? 16u : 8u; }
+__host__ __device__ constexpr uint32_t fwd_unroll(uint32_t) { return 8u; }
+__host__ __device__ constexpr uint32_t fwd_rpt(uint32_t v) { return v == 1 || v == 2 ? 5u : 2u; }
 
-template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll>
+template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll, uint32_t kRpt>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
                                     uint2 *ptab, uint32_t *wsum, const uint64_t *words, const uint32_t *woff,
@@ -445,16 +446,23 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   // an arrival d steps later lies within the trial iff its ring offset is below lim
   const uint32_t lim = min(n.R, Tb - t + 1u) * n.TS;
   const uint32_t sub = threadIdx.x & (kPiece - 1u), grp = threadIdx.x / kPiece, ngrp = blockDim.x / kPiece;
-  for (uint32_t base = 0; base < total; base += span) {
-    uint2 seg[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
-    uint32_t src[2] = {0u, 0u};
-    bool look[2] = {false, false};  // segment still to be looked up
+  // chunks of kRpt * blockDim items, kRpt per thread
+  for (uint32_t base = 0; base < total; base += kRpt * blockDim.x) {
+    uint2 seg[kRpt];
+    uint32_t src[kRpt];
+    bool look[kRpt];  // segment still to be looked up
 #pragma unroll
-    for (uint32_t u = 0; u < 2; ++u) {
+    for (uint32_t u = 0; u < kRpt; ++u) {
+      seg[u] = make_uint2(0u, 0u);
+      src[u] = 0u;
+      look[u] = false;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kRpt; ++u) {
       const uint32_t item = base + threadIdx.x + u * blockDim.x;
       if (item >= total) continue;
       if (item < n_in) {
-        if (base == 0) {
+        if (base == 0 && u < 2) {
           seg[u] = iseg[u];
         } else {
           src[u] = in_src[in_lo + item];
@@ -491,23 +499,26 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
       src[u] = n.I + min(j, n.J - 1u);
     }
 #pragma unroll
-    for (uint32_t u = 0; u < 2; ++u)
+    for (uint32_t u = 0; u < kRpt; ++u)
       if (look[u]) seg[u] = n.dseg[(size_t)src[u] * n.KT + rk];
-    const uint32_t np0 = (seg[0].y + kPiece - 1) / kPiece, np1 = (seg[1].y + kPiece - 1) / kPiece;
+    uint32_t np = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kRpt; ++u) np += (seg[u].y + kPiece - 1) / kPiece;
     uint32_t npieces;
-    const uint32_t pre = block_exclusive_scan(np0 + np1, wsum, &npieces);
+    const uint32_t pre = block_exclusive_scan(np, wsum, &npieces);
     // (the scan's barrier also ends every read of the parked entries)
     for (uint32_t w0 = 0; w0 < npieces; w0 += cap) {
       const uint32_t w1 = min(npieces, w0 + cap);
+      uint32_t p0 = pre;
 #pragma unroll
-      for (uint32_t u = 0; u < 2; ++u) {
-        const uint32_t p0 = u ? pre + np0 : pre, np = u ? np1 : np0;
-        const uint32_t L = seg[u].y;
-        for (uint32_t pc = max(p0, w0); pc < min(p0 + np, w1); ++pc) {
+      for (uint32_t u = 0; u < kRpt; ++u) {
+        const uint32_t L = seg[u].y, nq = (L + kPiece - 1) / kPiece;
+        for (uint32_t pc = max(p0, w0); pc < min(p0 + nq, w1); ++pc) {
           const uint32_t off = (pc - p0) * kPiece;
           const uint32_t dist = L * (sizeof(real) / 2) - off * (sizeof(real) / 2 - 1);
           ptab[pc - w0] = make_uint2(seg[u].x + off * WPR, min(kPiece, L - off) | (dist << 6));
         }
+        p0 += nq;
       }
       __syncthreads();
       for (uint32_t pc0 = w0 + grp; pc0 < w1; pc0 += kUnroll * ngrp) {
@@ -557,7 +568,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 // KT workgroups of a trial must be resident together (checked on the host).
 template <typename real, typename ring_t, bool FORCED, uint32_t VAR>
 __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps, uint32_t b0) {
-  constexpr uint32_t P = fwd_piece(VAR), U = fwd_unroll(VAR);
+  constexpr uint32_t P = fwd_piece(VAR), U = fwd_unroll(VAR), RPT = fwd_rpt(VAR);
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t KT = n.KT, TS = n.TS;
   const uint32_t bl = blockIdx.x / KT, k = blockIdx.x - bl * KT, b = b0 + bl;
@@ -576,6 +587,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   uint32_t *woff = reinterpret_cast<uint32_t *>(words + TS / 64);
   uint2 *ptab = reinterpret_cast<uint2 *>(woff + ((TS / 64 + 2) & ~1u));  // 8-byte aligned
   uint8_t *sst = reinterpret_cast<uint8_t *>(ptab + n.ptab_cap);
+  uint64_t *salif = reinterpret_cast<uint64_t *>(sst + TS);  // [TS / 64] ALIF neurons of the tile
   __shared__ uint32_t gtot;
   __shared__ uint32_t wsum[17];
   RingScale sc{1.f, 1.f};
@@ -587,10 +599,12 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     sa[i] = n.a[gs + i];
     sst[i] = n.nst[gs + i];
     for (uint32_t r = 0; r < n.R; ++r) ring[r * TS + i] = gring[((size_t)b * n.R + r) * n.Jp + j0 + i];
+    const uint64_t m = __ballot(n.any_alif && n.beta_j[j0 + i] != (real)0);
+    if (lane_id() == 0) salif[i >> 6] = m;
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile<real, ring_t, P, U>(n, b, k, j0, 0, Tb, ring, sc, ptab, wsum, words, woff, 0u, 0u);
+    deliver_tile<real, ring_t, P, U, RPT>(n, b, k, j0, 0, Tb, ring, sc, ptab, wsum, words, woff, 0u, 0u);
     __syncthreads();
   }
   const uint32_t t_end = min(t0 + nsteps, Tb);
@@ -602,7 +616,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       const real I = ring_value(ring[slot * TS + i], sc);
       ring[slot * TS + i] = (ring_t)0;
       const uint32_t j = j0 + i;
-      const real beta = n.any_alif ? n.beta_j[j] : (real)0;
+      const real beta = (salif[i >> 6] >> (i & 63u)) & 1ull ? n.beta_a : (real)0;
       const bool z = neuron_step<real, FORCED>(n, b, t, j, j < n.J, I, beta, v, a, st);
       sv[i] = v;
       sa[i] = a;
@@ -642,7 +656,7 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       __syncthreads();
       if (threadIdx.x == 0) store_sys(&n.pub_cnt[((size_t)b * 2 + (t & 1u)) * KT + k], tag | gtot);
     }
-    if (t < Tb) deliver_tile<real, ring_t, P, U>(n, b, k, j0, t, Tb, ring, sc, ptab, wsum, words, woff, nw, gtot);
+    if (t < Tb) deliver_tile<real, ring_t, P, U, RPT>(n, b, k, j0, t, Tb, ring, sc, ptab, wsum, words, woff, nw, gtot);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -2199,7 +2213,7 @@ void Launch<real>::neuron_gather(const DevNet<real> &n, uint32_t off, bool force
 template <typename real>
 size_t Launch<real>::tile_smem(uint32_t TS, uint32_t R, uint32_t ring_bytes, uint32_t ptab_cap) {
   return (size_t)R * TS * ring_bytes + (size_t)2 * TS * sizeof(real) + (size_t)(TS / 64) * 8 +
-         ((TS / 64 + 2) & ~1u) * 4 + (size_t)ptab_cap * 8 + TS + 64;
+         ((TS / 64 + 2) & ~1u) * 4 + (size_t)ptab_cap * 8 + TS + (size_t)(TS / 64) * 8 + 64;
 }
 
 // The forward kernels of a precision and ring element, one per delivery variant.
