@@ -482,6 +482,10 @@ def main():
     ap.add_argument("--delivery", choices=("scatter", "gather"), default="scatter",
                     help="spike delivery of the FP32 run: scatter into LDS delay rings (default) or target-side "
                          "gather (one kernel per step, every target sums its arriving synapses)")
+    ap.add_argument("--scatter-form", choices=("auto", "lookup", "queues"), default="auto",
+                    help="scatter delivery by lookup (every tile looks up each spiking source) or through "
+                         "per-tile queues (each spiking neuron's tile bins its synapses by target tile); auto: "
+                         "queues where rows are sparse across tiles, and the autotuner may pick either")
     ap.add_argument("--no-cpu-parallel", action="store_true", help="skip the P-process oracle timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
@@ -535,7 +539,8 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         net = E.Network(net_w, "fp32", max_trials=wl.batch_size, max_steps=T, delivery=args.delivery,
-                        stream=E.C.c_void_p(stream.cuda_stream), autotune=not args.no_autotune)
+                        stream=E.C.c_void_p(stream.cuda_stream), autotune=not args.no_autotune,
+                        scatter_form=args.scatter_form if args.delivery == "scatter" else "auto")
         progress("network built")
         staged = stage_batches(wl, args.warmup + args.steps, 0)
         torch.cuda.synchronize()

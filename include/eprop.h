@@ -132,6 +132,19 @@ typedef enum { EPROP_DELIVERY_AUTO = 0, EPROP_DELIVERY_SCATTER = 1, EPROP_DELIVE
                                            records and synapses per thread at a time) on the batch
                                            itself and keeps the
                                            fastest; results do not depend on the choice */
+/* The two forms of scatter delivery (FP32).  LOOKUP: every tile looks up,
+ * for each source that spiked in the step, the source's synapses into the
+ * tile.  QUEUES: the tile that owns a spiking neuron copies the neuron's
+ * synapses into one queue per target tile, and each tile then reads only
+ * its own queues (device memory: max_trials x 2 x recurrent synapses x 8
+ * bytes, plus small tables).  By default the queues are built where
+ * recurrent rows are sparse across tiles (fewer than 4 synapses per
+ * source and tile on average) and fit in a quarter of the free device
+ * memory, and the autotuner may then pick either form; the flags force
+ * one (QUEUES: EPROP_ERR_CAPACITY if it does not fit; FP32 scatter with
+ * more than one tile per trial only, else EPROP_ERR_UNSUPPORTED). */
+#define EPROP_SCATTER_LOOKUP (1u << 4)
+#define EPROP_SCATTER_QUEUES (1u << 5)
 
 /* Optional device allocator, e.g. a framework's caching allocator: every
  * device buffer of the handle is taken from dev_alloc (bytes, ctx) and
@@ -155,7 +168,8 @@ typedef struct {
   uint32_t max_trials;           /* largest number of trials per eprop_simulate_batch call */
   uint32_t max_steps;            /* largest trial length T, 1..65535 */
   int32_t delivery;              /* eprop_delivery */
-  uint32_t flags;                /* EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS */
+  uint32_t flags;                /* EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS |
+                                    EPROP_AUTOTUNE | EPROP_SCATTER_LOOKUP | EPROP_SCATTER_QUEUES */
   uint32_t d_out;                /* delay d in steps of recurrent spikes to the readout, 0..65535
                                     (Supplementary, "Delay from the recurrent to the output layer":
                                     y^t integrates W_out z^{t-d}; the recurrent gradient pairs the
@@ -377,7 +391,7 @@ typedef enum {
   EPROP_STATE_Y = 15,          /* last batch, trial: double [T_b * K] readout signal */
   EPROP_STATE_ERR = 16,        /* last batch, trial: double [T_b * K] error signal E */
   EPROP_STATE_V = 17,          /* last batch, trial: double [J] membrane potential at T_b */
-  EPROP_STATE_LAYOUT = 18,     /* uint64 [17]: neurons per tile, tiles per trial, bytes per
+  EPROP_STATE_LAYOUT = 18,     /* uint64 [18]: neurons per tile, tiles per trial, bytes per
                                   delay-ring entry (4: 32-bit fixed point in FP32, 8: double in
                                   FP64), threads per tile,
                                   synapse-kernel threads, trials per synapse block, steps per
@@ -388,7 +402,8 @@ typedef enum {
                                   record's header, synapses a synapse-kernel thread takes at
                                   a time, weight update by tile blocks (1) or in target-major
                                   order (0), trials per launch of the tiled forward kernel
-                                  (as many as the device keeps resident together) */
+                                  (as many as the device keeps resident together), scatter
+                                  delivery through per-tile queues (1) or by lookup (0) */
   EPROP_STATE_L = 19,          /* last batch, trial: double [T_b * J] learning signal
                                   L_j^t = sum_k B_jk E_k^t (eq. final-gradient), row t-1 */
   EPROP_STATE_INPUT_BOUND = 20 /* double [1]: the bound on |input current| of one step used to

@@ -83,6 +83,8 @@ struct eprop_network {
   std::vector<uint32_t> sm2caller;  // internal source-major index -> caller's synapse index
   size_t tile_smem = 0;             // dynamic LDS of the tiled forward kernel
   bool blocked = false;             // weight update as a blocked transposition (k_apply_blk)
+  bool queues = false;              // per-tile queues built (FP32 scatter; forward variant kQueueVariant)
+  uint32_t q_since = 0;             // queue step tags used since the queues were last cleared
   uint64_t dl_words = 0;            // size of the delivery table (4-byte words)
   // e-prop+ schedule (allocated on the first online batch)
   void *on_syn = nullptr;
@@ -244,8 +246,11 @@ eprop_status check_config(const eprop_config *c, std::string &msg) {
   if (c->max_trials < 1) return bad("max_trials must be >= 1");
   if (c->max_steps < 1 || c->max_steps > 65535) return bad("max_steps must be in 1..65535");
   if (c->delivery < EPROP_DELIVERY_AUTO || c->delivery > EPROP_DELIVERY_GATHER) return bad("unknown delivery");
-  if (c->flags & ~(uint32_t)(EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS | EPROP_AUTOTUNE))
+  if (c->flags & ~(uint32_t)(EPROP_FLAG_NO_GRAPH | EPROP_DETERMINISTIC | EPROP_SHARED_WEIGHTS | EPROP_AUTOTUNE |
+                             EPROP_SCATTER_LOOKUP | EPROP_SCATTER_QUEUES))
     return bad("unknown config flag");
+  if ((c->flags & EPROP_SCATTER_LOOKUP) && (c->flags & EPROP_SCATTER_QUEUES))
+    return bad("EPROP_SCATTER_LOOKUP and EPROP_SCATTER_QUEUES exclude each other");
   if ((c->flags & EPROP_DETERMINISTIC) && c->precision == EPROP_FP64 && c->delivery == EPROP_DELIVERY_SCATTER)
     return bad("FP64 scatter delivery is not deterministic; use gather or AUTO");
   if ((c->dev_alloc == nullptr) != (c->dev_free == nullptr)) return bad("dev_alloc and dev_free go together");
@@ -377,6 +382,76 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
 }
 
 // Uploads graph, weights and optimiser state (host arrays in double).
+// Tables and buffers of the per-tile queues: every recurrent neuron's
+// non-empty tile segments (q_nzp, q_nz), and the regions of the event
+// buffers, one per (source tile, target tile) pair, sized by the synapses
+// between the two tiles and ordered by target tile, then source tile
+// (q_src row k: the starts of tile k's regions as a source; q_dst row k:
+// those of the regions into tile k).  The buffers start cleared.
+template <typename real>
+hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t> &tseg,
+                         const std::vector<uint2> &dsegh) {
+  const uint32_t KT = d.KT, TS = d.TS, J = n->J, I = n->I;
+  const unsigned nt = n->S >= (1u << 22) ? host_threads() : 1u;
+  auto L_of = [&](uint64_t src, uint32_t k) {
+    return tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k];
+  };
+  std::vector<uint32_t> nzp((size_t)J + 1, 0u);
+  auto flat = [](uint64_t i) { return i; };
+  parallel_ranges(J, nt, flat, [&](uint64_t lo, uint64_t hi, unsigned) {
+    for (uint64_t j = lo; j < hi; ++j) {
+      uint32_t c = 0;
+      for (uint32_t k = 0; k < KT; ++k) c += L_of(I + j, k) > 0;
+      nzp[j + 1] = c;
+    }
+  });
+  for (uint32_t j = 0; j < J; ++j) nzp[j + 1] += nzp[j];
+  std::vector<uint2> nz(std::max<uint32_t>(nzp[J], 1u), make_uint2(0u, 0u));
+  std::vector<uint64_t> rsz((size_t)KT * KT, 0);
+  parallel_ranges(KT, std::min<unsigned>(nt, KT), flat, [&](uint64_t k0, uint64_t k1, unsigned) {
+    for (uint64_t ks = k0; ks < k1; ++ks)
+      for (uint64_t j = ks * TS; j < std::min<uint64_t>(J, (ks + 1) * TS); ++j) {
+        uint32_t at = nzp[j];
+        for (uint32_t kd = 0; kd < KT; ++kd) {
+          const uint32_t L = L_of(I + j, kd);
+          if (L == 0) continue;
+          nz[at++] = make_uint2(dsegh[(I + j) * KT + eprop::tile_rank(kd, KT)].x, L | kd << 16);
+          rsz[ks * KT + kd] += L;
+        }
+      }
+  });
+  std::vector<uint32_t> qsrc((size_t)KT * KT), qdst((size_t)KT * KT);
+  uint64_t acc = 0;
+  for (uint32_t kd = 0; kd < KT; ++kd)
+    for (uint32_t ks = 0; ks < KT; ++ks) {
+      qdst[(size_t)kd * KT + ks] = qsrc[(size_t)ks * KT + kd] = (uint32_t)acc;
+      acc += rsz[(size_t)ks * KT + kd];
+    }
+  if (acc != n->S_rec) return hipErrorInvalidValue;  // every recurrent synapse in exactly one region
+  d.q_len = (uint32_t)std::max<uint64_t>(acc, 1);
+  uint32_t *p_nzp = nullptr, *p_src = nullptr, *p_dst = nullptr;
+  uint2 *p_nz = nullptr;
+  uint64_t *p_ev = nullptr, *p_hdr = nullptr;
+  const size_t kt2 = (size_t)KT * KT, nev = (size_t)n->Bcap * 2 * d.q_len, nhdr = (size_t)n->Bcap * 2 * kt2;
+  if (!dalloc(n, &p_nzp, nzp.size()) || !dalloc(n, &p_nz, nz.size()) || !dalloc(n, &p_src, kt2) ||
+      !dalloc(n, &p_dst, kt2) || !dalloc(n, &p_ev, nev) || !dalloc(n, &p_hdr, nhdr))
+    return hipErrorOutOfMemory;
+  hipError_t e = hipMemcpy(p_nzp, nzp.data(), nzp.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p_nz, nz.data(), nz.size() * sizeof(uint2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p_src, qsrc.data(), kt2 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p_dst, qdst.data(), kt2 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p_ev, 0, nev * 8);
+  if (e == hipSuccess) e = hipMemset(p_hdr, 0, nhdr * 8);
+  d.q_nzp = p_nzp;
+  d.q_nz = p_nz;
+  d.q_src = p_src;
+  d.q_dst = p_dst;
+  d.q_ev = p_ev;
+  d.q_hdr = p_hdr;
+  n->q_since = 0;
+  return e;
+}
+
 template <typename real>
 hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t> &sm_ptr,
                   const std::vector<uint32_t> &tseg,
@@ -464,6 +539,7 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
       for (uint64_t q = lo; q < hi; ++q) tdp[q] = dpos[tm_perm[q]];
     });
     cp((void *)d.tm_dpos, tdp.data(), tdp.size() * 4);
+    if (n->queues && e == hipSuccess) e = upload_queues(n, d, tseg, dsegh);
   }
   {
     // out-degree of every source per delay, for the event counts
@@ -918,6 +994,35 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
       return EPROP_ERR_CAPACITY;
     }
   }
+  {
+    // per-tile queues (FP32 scatter delivery): built where recurrent rows are
+    // sparse across tiles (fewer than 4 synapses per source and tile on
+    // average) and they fit a quarter of the free memory, or when asked for
+    const bool want = (cfg->flags & EPROP_SCATTER_QUEUES) != 0;
+    const bool able = !n->gather && !n->fp64 && KT > 1 && n->S_rec > 0 && n->S_rec < (1ull << 32);
+    if (want && !able) {
+      g_create_error = "EPROP_SCATTER_QUEUES needs FP32 scatter delivery, more than one tile per trial and "
+                       "fewer than 2^32 recurrent synapses";
+      delete n;
+      return EPROP_ERR_UNSUPPORTED;
+    }
+    const bool sparse = (double)n->S_rec < 4.0 * (double)J * (double)KT;
+    if (able && !(cfg->flags & EPROP_SCATTER_LOOKUP) && (want || sparse)) {
+      const size_t kt2 = (size_t)KT * KT;
+      const size_t bytes = (size_t)n->Bcap * 2 * n->S_rec * 8 + n->S_rec * 8 + ((size_t)J + 1) * 4 + 2 * kt2 * 4 +
+                           (size_t)n->Bcap * 2 * kt2 * 8;
+      size_t free_b = 0, total_b = 0;
+      const bool known = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
+      if (want && known && bytes > free_b) {
+        g_create_error = "the per-tile queues need " + std::to_string(bytes >> 20) + " MiB and the device has " +
+                         std::to_string(free_b >> 20) + " MiB free";
+        delete n;
+        return EPROP_ERR_CAPACITY;
+      }
+      n->queues = want || (known && bytes <= free_b / 4);
+    }
+    if (n->queues) n->shapes.fwd_variant = eprop::kQueueVariant;
+  }
   bool ok = n->fp64 ? alloc_state(n, n->n64) : alloc_state(n, n->n32);
   ok = ok && dalloc(n, &n->d_T, n->Bcap) && dalloc(n, &n->d_label, n->Bcap) && dalloc(n, &n->d_in_ptr, n->Bcap + 1) &&
        dalloc(n, &n->d_forced_ptr, n->Bcap + 1);
@@ -1256,6 +1361,15 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
   // per-batch state from zero (trials start from rest) and staged inputs;
   // run again by the autotuner before each timed forward pass
   auto restage = [&]() {
+    if (n->queues) {  // the pass's queue tags CTL_TAG0 + t, none used since the queues were last cleared
+      if ((uint64_t)n->q_since + t_max + 1 > 65535) {
+        MS(d.q_ev, (size_t)n->Bcap * 2 * d.q_len * 8);
+        MS(d.q_hdr, (size_t)n->Bcap * 2 * d.KT * d.KT * 8);
+        n->q_since = 0;
+      }
+      ctl.w[eprop::CTL_TAG0] = n->q_since;
+      n->q_since += t_max;
+    }
     H2D(d.ctl, &ctl, sizeof(ctl));
     MS(d.v, (size_t)ntr * n->Jp * sizeof(real));
     MS(d.a, (size_t)ntr * n->Jp * sizeof(real));
@@ -1345,6 +1459,7 @@ eprop_status simulate(eprop_network *n, DevNet<real> &d, const eprop_batch *b, e
     float best = 1e30f;
     uint32_t bv = n->shapes.fwd_variant, bb = n->blk;
     for (uint32_t v = 0; v < eprop::kNumFwdVariants && e == hipSuccess; ++v) {
+      if (v == eprop::kQueueVariant && !n->queues) continue;
       n->shapes.fwd_variant = v;
       drop_graphs(n);
       const float ms = timed(restage, forward);
@@ -1781,12 +1896,13 @@ eprop_status read_state(const eprop_network *n, const DevNet<real> &d, int32_t w
   const bool per_trial = (what >= EPROP_STATE_SPIKES && what <= EPROP_STATE_V) || what == EPROP_STATE_L;
   if (what < 0 || what > EPROP_STATE_INPUT_BOUND) return EPROP_ERR_INVALID_ARGUMENT;
   if (what == EPROP_STATE_LAYOUT) {
-    const uint64_t lay[17] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
+    const uint64_t lay[18] = {d.TS, d.KT, d.ring_bytes, n->shapes.tile_block, n->shapes.syn_block, n->shapes.ginst,
                               n->blk, n->gather ? 1u : 0u, eprop::fwd_variant_piece(n->shapes.fwd_variant),
                               eprop::fwd_variant_unroll(n->shapes.fwd_variant), n->shapes.adj_block,
                               n->tuned ? 1u : 0u, d.ptab_cap, eprop::syn_variant_pre(n->shapes.syn_var),
                               eprop::syn_variant_batch(n->shapes.syn_var), n->blocked ? 1u : 0u,
-                              n->shapes.fwd_trials ? n->shapes.fwd_trials : n->Bcap};
+                              n->shapes.fwd_trials ? n->shapes.fwd_trials : n->Bcap,
+                              n->shapes.fwd_variant == eprop::kQueueVariant ? 1u : 0u};
     if (needed) *needed = sizeof(lay);
     if (!dst) return EPROP_OK;
     if (dst_bytes < sizeof(lay)) return EPROP_ERR_INVALID_ARGUMENT;

@@ -38,6 +38,14 @@
 //   per-step spikes      pub_list[b][t & 1][Jp] (tile k's spiking neurons of step t at
 //                        k*TS.., each word t << 32 | j), pub_cnt[b][t & 1][KT]
 //                        (t << 32 | count of tile k), nspk[b][t]
+//   per-tile queues      (scatter delivery through queues, FP32) q_nzp[J+1], q_nz[]: for each
+//                        recurrent neuron, its non-empty tile segments {word index in dlw,
+//                        L | target tile << 16}; q_ev[b][t & 1][q_len]: one region per
+//                        (source tile, target tile), as large as the synapses between
+//                        them, regions ordered by target tile, then source tile; q_src[k][kd]
+//                        (= q_dst[kd][k]): where region (k -> kd) starts; an event is
+//                        tag16 << 48 | ring offset << 32 | weight bits; q_hdr[b][t & 1][kd][k]
+//                        = tag << 32 | events of step t in region (k -> kd)
 //   readout (FP64)       ysum/pi[b][t][K], y[b][t][K], err[b][t][K], ebar[b][t][K], ebo[b][t][K]
 #pragma once
 #include <hip/hip_runtime.h>
@@ -47,7 +55,8 @@ namespace eprop {
 
 // ctl words; the 64-bit device pointer to the batch's input-source array is
 // stored at word CTL_WORDS (byte offset 64)
-enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_WORDS = 16 };
+// (CTL_TAG0: the queues' step tags of the batch are CTL_TAG0 + t, all in 1..65535)
+enum : uint32_t { CTL_T0 = 0, CTL_NTRIALS = 1, CTL_ERR = 2, CTL_TAG0 = 3, CTL_WORDS = 16 };
 enum : uint32_t { ERR_INPUT_RANGE = 1u, ERR_INPUT_ORDER = 2u, ERR_FORCED_RANGE = 4u, ERR_SYNC = 8u,
                   ERR_INPUT_BOUND = 16u };
 enum : uint32_t { CNT_EVENTS = 0, CNT_REC_SPIKES = 1, CNT_FLUSH = 2, CNT_WORDS = 8 };
@@ -150,6 +159,11 @@ struct DevNet {
   uint16_t *pk;                 // [pk_cap * 8]
   uint64_t pk_cap;
   uint64_t *pub_list, *pub_cnt;
+  // per-tile queues (null unless built)
+  const uint32_t *q_nzp, *q_src, *q_dst;
+  const uint2 *q_nz;
+  uint64_t *q_ev, *q_hdr;
+  uint32_t q_len;               // events per (trial, parity) buffer: the recurrent synapses
   uint32_t *nspk;
   uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
   double *ysum, *y, *err;       // [Bcap][Tcap+2][K]
@@ -220,7 +234,8 @@ uint32_t fwd_variant_unroll(uint32_t v);
 uint32_t syn_variant_pre(uint32_t v);
 uint32_t syn_variant_batch(uint32_t v);
 constexpr uint32_t kNumSynVariants = 7;
-constexpr uint32_t kNumFwdVariants = 4;
+constexpr uint32_t kNumFwdVariants = 5;
+constexpr uint32_t kQueueVariant = 4;  // the forward variant that delivers through the per-tile queues
 
 template <typename real>
 struct Launch {

@@ -254,6 +254,22 @@ __device__ inline void store_sys(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Queue event at p once its 16-bit tag (bits 48..63) is tag16, or 0 on
+// timeout (flag ERR_SYNC): a zero event adds nothing.
+__device__ inline uint64_t wait_event(const uint64_t *p, uint32_t tag16, uint32_t *err) {
+  for (uint32_t spins = 0;; ++spins) {
+    if ((spins & 255u) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_SYNC))
+      return 0ull;
+    if (spins > kSpinLimit) {
+      atomicOr(err, ERR_SYNC);
+      return 0ull;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    const uint64_t v = load_sys(p);
+    if ((uint32_t)(v >> 48) == tag16) return v;
+  }
+}
+
 // Low half of the step-t word at p, or 0 on timeout (flag ERR_SYNC).
 __device__ inline uint32_t wait_tag(const uint64_t *p, uint32_t t, uint32_t *err) {
   uint64_t v = load_sys(p);
@@ -368,24 +384,27 @@ __device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
 // | (distance from that weight to the piece's first ring offset, in uint16
 // units) << 6.
 // [P, U] of the delivery variants the autotuner chooses from; variant 0 is
-// the default.
-constexpr uint32_t kFwdVariants = 4;
+// the default.  Variant 4 (FP32) delivers the recurrent spikes through the
+// per-tile queues instead (queue_spikes, drain_queues), and this function
+// (kQueue) then delivers only the step's input spikes; its P and U also
+// shape the queue copy.
+constexpr uint32_t kFwdVariants = 5;
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // a parked list entry that had not arrived
-__host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 2 ? 4u : v == 3 ? 16u : 8u; }
+constexpr uint32_t kQueueUnroll = 4;        // queue events a thread holds in flight
+__host__ __device__ constexpr uint32_t fwd_piece(uint32_t v) { return v == 2 || v == 4 ? 4u : v == 3 ? 16u : 8u; }
 __host__ __device__ constexpr uint32_t fwd_unroll(uint32_t) { return 8u; }
 __host__ __device__ constexpr uint32_t fwd_rpt(uint32_t v) { return v == 1 || v == 2 ? 5u : 2u; }
+__host__ __device__ constexpr bool fwd_queue(uint32_t v) { return v == 4; }
 
-template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll, uint32_t kRpt>
+template <typename real, typename ring_t, uint32_t kPiece, uint32_t kUnroll, uint32_t kRpt, bool kQueue>
 __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
                                     uint32_t Tb, ring_t *ring, const RingScale &sc,
-                                    uint2 *ptab, uint32_t *wsum, const uint64_t *words, const uint32_t *woff,
-                                    uint32_t nw, uint32_t own) {
+                                    uint2 *ptab, uint32_t cap, uint32_t *wsum, const uint64_t *words,
+                                    const uint32_t *woff, uint32_t nw, uint32_t own, uint32_t *tpre) {
   constexpr uint32_t WPR = sizeof(real) / 4;  // words per weight
-  __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike counts of step t
   // parked entries [span] and their segments [span] (in the piece table)
   uint32_t *spec = reinterpret_cast<uint32_t *>(ptab);
   uint2 *spec_seg = ptab + (n.ptab_cap - blockDim.x * 2);
-  const uint32_t cap = n.ptab_cap;
   const uint32_t span = 2 * blockDim.x;
   const uint32_t E = span / n.KT;  // >= 1: KT <= blockDim
   const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
@@ -405,7 +424,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   // its LDS bitset words and their exclusive popcount prefix woff
   const bool local = n.KT == 1;
   if (t >= 1 && local) n_rec = own;
-  if (t >= 1 && !local) {
+  if (!kQueue && t >= 1 && !local) {
     // the first E entries of every tile's list, read ahead of the counts
     uint64_t ahead[2] = {0ull, 0ull};
 #pragma unroll
@@ -558,6 +577,197 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
   }
 }
 
+// Recurrent part of a step with queues (FP32): one thread per source tile
+// awaits that tile's count of step t for this tile in q_hdr, a block scan
+// numbers the events, and every thread then takes kQueueUnroll events at a
+// time: all their loads first, then any wait for an event whose tag has not
+// arrived yet, then the ring additions (only arrivals within the trial).
+// tpre: LDS [KT + 1]; qd: LDS [KT] starts of the regions into this tile.
+__device__ inline void drain_queues(const DevNet<float> &n, uint32_t b, uint32_t k, uint32_t t, uint32_t Tb,
+                                    int32_t *ring, const RingScale &sc, uint32_t *wsum, uint32_t *tpre,
+                                    const uint32_t *qd, uint32_t tag) {
+  const uint32_t KT = n.KT, kk = threadIdx.x;
+  const size_t par = (size_t)b * 2 + (t & 1u);
+  const uint64_t *hrow = n.q_hdr + (par * KT + k) * KT;
+  const uint64_t *evq = n.q_ev + par * n.q_len;
+  uint32_t c = 0;
+  if (kk < KT) c = min(wait_tag(hrow + kk, tag, &n.ctl[CTL_ERR]), n.q_len - qd[kk]);
+  uint32_t n_ev;
+  const uint32_t pre = block_exclusive_scan(c, wsum, &n_ev);
+  if (kk < KT) tpre[kk] = pre;
+  if (kk == 0) tpre[KT] = n_ev;
+  __syncthreads();
+  const uint32_t tag16 = tag & 0xFFFFu;
+  const uint32_t sbase = (t % n.R) * n.TS, RT = n.R * n.TS;
+  const uint32_t lim = min(n.R, Tb - t + 1u) * n.TS;
+  for (uint32_t r0 = threadIdx.x; r0 < n_ev; r0 += kQueueUnroll * blockDim.x) {
+    uint32_t ad[kQueueUnroll];
+    uint64_t ev[kQueueUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kQueueUnroll; ++u) {
+      const uint32_t r = r0 + u * blockDim.x;
+      ad[u] = kNoEntry;
+      if (r < n_ev) {
+        uint32_t lk = 0, hk = KT;  // tpre[lk] <= r < tpre[hk]
+        while (hk - lk > 1) {
+          const uint32_t mid = (lk + hk) >> 1;
+          if (tpre[mid] <= r) lk = mid; else hk = mid;
+        }
+        ad[u] = qd[lk] + (r - tpre[lk]);
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kQueueUnroll; ++u) ev[u] = ad[u] != kNoEntry ? load_sys(evq + ad[u]) : 0ull;
+#pragma unroll
+    for (uint32_t u = 0; u < kQueueUnroll; ++u) {
+      if (ad[u] == kNoEntry) continue;
+      if ((uint32_t)(ev[u] >> 48) != tag16) ev[u] = wait_event(evq + ad[u], tag16, &n.ctl[CTL_ERR]);
+      const uint32_t o = (uint32_t)(ev[u] >> 32) & 0xFFFFu;
+      if (o >= lim) continue;
+      uint32_t ri = sbase + o;
+      if (ri >= RT) ri -= RT;
+      ring_add(&ring[ri], __uint_as_float((uint32_t)ev[u]), sc);
+    }
+  }
+}
+
+// Source side of the queues (FP32): after the neuron update of step t, the
+// tile copies the synapses of each of its spiking neurons into the queues
+// of their target tiles, as tagged events.  Per chunk of kQChunk spiking
+// neurons, a thread finds its neuron from the bitset words and their
+// popcount prefix, and a block scan numbers the neurons' non-empty segments
+// (pp, pz).  Per batch of kQueueUnroll * blockDim segments, a thread takes
+// kQueueUnroll of them and reserves each segment's place in the region
+// (this tile -> target tile) with an LDS atomic on that tile's counter
+// (bcnt; cst holds the counters at the start of the batch).  The batch's
+// events are then staged in LDS ordered by target tile (bpl: the batch's
+// prefix over target tiles) and flushed with consecutive lanes on
+// consecutive places of a region, so that the write-through stores of a
+// region's run combine (scattered 8-byte stores would each be a
+// transaction of their own); batches larger than the staging array go in
+// rounds.  Finally the counters go out as the step's q_hdr words and are
+// cleared.  Every event carries its own tag, so a reader that sees a count
+// does not depend on the order in which stores arrive.  The region
+// (k -> kd) holds as many events as there are synapses from the tile's
+// neurons to tile kd, and a neuron spikes at most once per step, so the
+// reservations stay within it.
+// pp, pz: LDS [kQChunk]; stg: LDS [scap]; bcnt, qs, cst: LDS [KT]; bpl: LDS [KT + 1].
+constexpr uint32_t kQChunk = 256;
+__device__ inline void queue_spikes(const DevNet<float> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
+                                    uint32_t tag, const uint64_t *words, const uint32_t *woff, uint32_t nw,
+                                    uint32_t gtot, uint32_t *pp, uint32_t *pz, uint2 *stg, uint32_t scap,
+                                    uint32_t *bcnt, const uint32_t *qs, uint32_t *cst, uint32_t *bpl,
+                                    uint32_t *wsum) {
+  const uint32_t KT = n.KT;
+  const size_t par = (size_t)b * 2 + (t & 1u);
+  uint64_t *evq = n.q_ev + par * n.q_len;
+  const uint64_t hi = (uint64_t)(tag & 0xFFFFu) << 48;
+  const uint16_t *o16 = reinterpret_cast<const uint16_t *>(n.dlw);
+  for (uint32_t c0 = 0; c0 < gtot; c0 += kQChunk) {
+    const uint32_t r = c0 + threadIdx.x;
+    uint32_t np = 0, z0 = 0;
+    if (threadIdx.x < kQChunk && r < gtot) {  // the r-th spike: word lw with woff[lw] <= r < woff[lw + 1]
+      uint32_t lw = 0, hw = nw;
+      while (hw - lw > 1) {
+        const uint32_t mid = (lw + hw) >> 1;
+        if (woff[mid] <= r) lw = mid; else hw = mid;
+      }
+      const uint32_t j = min(j0 + lw * 64 + nth_set_bit(words[lw], r - woff[lw]), n.J - 1u);
+      z0 = n.q_nzp[j];
+      np = n.q_nzp[j + 1] - z0;
+    }
+    uint32_t npairs;
+    const uint32_t pre = block_exclusive_scan(np, wsum, &npairs);
+    if (threadIdx.x < kQChunk) {
+      pp[threadIdx.x] = pre;
+      pz[threadIdx.x] = z0;
+    }
+    for (uint32_t kd = threadIdx.x; kd < KT; kd += blockDim.x) cst[kd] = bcnt[kd];
+    __syncthreads();
+    const uint32_t nown = min(kQChunk, gtot - c0);
+    for (uint32_t s0 = 0; s0 < npairs; s0 += kQueueUnroll * blockDim.x) {
+      uint2 ent[kQueueUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kQueueUnroll; ++u) {
+        const uint32_t p = s0 + u * blockDim.x + threadIdx.x;
+        ent[u] = make_uint2(0u, 0u);
+        if (p < npairs) {
+          uint32_t lo = 0, hs = nown;  // pp[lo] <= p < pp[lo + 1]
+          while (hs - lo > 1) {
+            const uint32_t mid = (lo + hs) >> 1;
+            if (pp[mid] <= p) lo = mid; else hs = mid;
+          }
+          ent[u] = n.q_nz[pz[lo] + (p - pp[lo])];
+        }
+      }
+      // the first two synapses of every segment, loaded before anything waits for them
+      uint32_t w2[kQueueUnroll][2], o2[kQueueUnroll][2];
+#pragma unroll
+      for (uint32_t u = 0; u < kQueueUnroll; ++u) {
+        const uint32_t L = ent[u].y & 0xFFFFu;
+#pragma unroll
+        for (uint32_t i = 0; i < 2; ++i) {
+          w2[u][i] = i < L ? n.dlw[ent[u].x + i] : 0u;
+          o2[u][i] = i < L ? o16[2u * (ent[u].x + L) + i] : 0u;
+        }
+      }
+      uint32_t rel[kQueueUnroll];  // place in the region, relative to the batch's start
+#pragma unroll
+      for (uint32_t u = 0; u < kQueueUnroll; ++u) {
+        const uint32_t L = ent[u].y & 0xFFFFu, kd = ent[u].y >> 16;
+        rel[u] = L ? atomicAdd(&bcnt[kd], L) - cst[kd] : 0u;
+      }
+      __syncthreads();
+      uint32_t cb = 0;
+      if (threadIdx.x < KT) cb = bcnt[threadIdx.x] - cst[threadIdx.x];
+      uint32_t nev;
+      const uint32_t bpre = block_exclusive_scan(cb, wsum, &nev);
+      if (threadIdx.x < KT) bpl[threadIdx.x] = bpre;
+      if (threadIdx.x == 0) bpl[KT] = nev;
+      __syncthreads();
+      uint32_t bp[kQueueUnroll];  // batch position of each segment's first event
+#pragma unroll
+      for (uint32_t u = 0; u < kQueueUnroll; ++u) bp[u] = (ent[u].y & 0xFFFFu) ? bpl[ent[u].y >> 16] + rel[u] : 0u;
+      for (uint32_t r0 = 0; r0 < nev; r0 += scap) {
+        const uint32_t r1 = min(nev, r0 + scap);
+#pragma unroll
+        for (uint32_t u = 0; u < kQueueUnroll; ++u) {
+          const uint32_t L = ent[u].y & 0xFFFFu;
+          const uint32_t i0 = bp[u] < r0 ? r0 - bp[u] : 0u;
+          const uint32_t i1 = min(L, r1 > bp[u] ? r1 - bp[u] : 0u);
+          for (uint32_t i = i0; i < i1; ++i) {
+            uint2 v;
+            if (i < 2) {
+              v = make_uint2(i == 0 ? w2[u][0] : w2[u][1], i == 0 ? o2[u][0] : o2[u][1]);
+            } else {
+              v = make_uint2(n.dlw[ent[u].x + i], o16[2u * (ent[u].x + L) + i]);
+            }
+            stg[bp[u] + i - r0] = v;
+          }
+        }
+        __syncthreads();
+        for (uint32_t e = r0 + threadIdx.x; e < r1; e += blockDim.x) {
+          uint32_t lk = 0, hk = KT;  // bpl[lk] <= e < bpl[hk]
+          while (hk - lk > 1) {
+            const uint32_t mid = (lk + hk) >> 1;
+            if (bpl[mid] <= e) lk = mid; else hk = mid;
+          }
+          const uint2 v = stg[e - r0];
+          store_sys(evq + qs[lk] + cst[lk] + (e - bpl[lk]), hi | (uint64_t)v.y << 32 | v.x);
+        }
+        __syncthreads();
+      }
+      for (uint32_t kd = threadIdx.x; kd < KT; kd += blockDim.x) cst[kd] = bcnt[kd];
+      __syncthreads();
+    }
+  }
+  for (uint32_t kd = threadIdx.x; kd < KT; kd += blockDim.x) {
+    const uint32_t c = bcnt[kd];
+    bcnt[kd] = 0u;
+    store_sys(n.q_hdr + (par * KT + kd) * KT + k, (uint64_t)tag << 32 | c);
+  }
+}
+
 // Persistent forward pass over steps ctl[T0]+1 .. ctl[T0]+nsteps of trials
 // b0 .. b0 + gridDim.x / KT - 1.  Workgroup (b, k) owns neurons
 // [k*TS, k*TS + TS) of trial b; their delay ring and
@@ -569,6 +779,7 @@ __device__ inline void deliver_tile(const DevNet<real> &n, uint32_t b, uint32_t 
 template <typename real, typename ring_t, bool FORCED, uint32_t VAR>
 __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps, uint32_t b0) {
   constexpr uint32_t P = fwd_piece(VAR), U = fwd_unroll(VAR), RPT = fwd_rpt(VAR);
+  constexpr bool Q = fwd_queue(VAR) && sizeof(real) == 4;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t KT = n.KT, TS = n.TS;
   const uint32_t bl = blockIdx.x / KT, k = blockIdx.x - bl * KT, b = b0 + bl;
@@ -590,6 +801,33 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   uint64_t *salif = reinterpret_cast<uint64_t *>(sst + TS);  // [TS / 64] ALIF neurons of the tile
   __shared__ uint32_t gtot;
   __shared__ uint32_t wsum[17];
+  __shared__ uint32_t tpre[kMaxTiles + 1];  // prefix of the tiles' spike (or queue event) counts of a step
+  // queues: the piece table's last 5 * KT + 2 words hold the tile's
+  // per-target-tile counters, region starts (as a source, qs; as a target,
+  // qd) and the source side's batch arrays cst, bpl; the rest serves the
+  // input deliveries' pieces and, on the source side, the chunk arrays pp,
+  // pz [kQChunk] followed by the staging array stg [scap]
+  uint32_t *pu = reinterpret_cast<uint32_t *>(ptab);
+  uint32_t pcap = n.ptab_cap, scap = 0, tag0 = 0;
+  uint32_t *bcnt = nullptr, *qs = nullptr, *qd = nullptr, *cst = nullptr, *bpl = nullptr;
+  uint2 *stg = nullptr;
+  if constexpr (Q) {
+    const uint32_t tail = 5 * KT + 2;
+    bcnt = pu + 2 * n.ptab_cap - tail;
+    qs = bcnt + KT;
+    qd = qs + KT;
+    cst = qd + KT;
+    bpl = cst + KT;
+    pcap = (2 * n.ptab_cap - tail) / 2;
+    scap = (2 * n.ptab_cap - 2 * kQChunk - tail) / 2;
+    stg = reinterpret_cast<uint2 *>(pu + 2 * kQChunk);
+    tag0 = n.ctl[CTL_TAG0];
+    for (uint32_t i = threadIdx.x; i < KT; i += blockDim.x) {
+      bcnt[i] = 0u;
+      qs[i] = n.q_src[(size_t)k * KT + i];
+      qd[i] = n.q_dst[(size_t)k * KT + i];
+    }
+  }
   RingScale sc{1.f, 1.f};
   if constexpr (sizeof(real) == 4) sc = ring_scale(n.l1max, &n.ctl[CTL_ERR]);
 
@@ -604,10 +842,18 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
   }
   __syncthreads();
   if (t0 == 0) {  // inputs emitted at step 0
-    deliver_tile<real, ring_t, P, U, RPT>(n, b, k, j0, 0, Tb, ring, sc, ptab, wsum, words, woff, 0u, 0u);
+    deliver_tile<real, ring_t, P, U, RPT, Q>(n, b, k, j0, 0, Tb, ring, sc, ptab, pcap, wsum, words, woff, 0u, 0u,
+                                             tpre);
     __syncthreads();
   }
   const uint32_t t_end = min(t0 + nsteps, Tb);
+  // with queues, the inputs of a step are delivered during the step before
+  // (while the tile waits for the other tiles' counts), the first here
+  if (Q && t0 + 1 < Tb) {
+    deliver_tile<real, ring_t, P, U, RPT, Q>(n, b, k, j0, t0 + 1, Tb, ring, sc, ptab, pcap, wsum, words, woff, 0u,
+                                             0u, tpre);
+    __syncthreads();
+  }
   for (uint32_t t = t0 + 1; t <= t_end; ++t) {
     const uint32_t slot = t % n.R;
     for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -643,7 +889,16 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       if (threadIdx.x == 0) gtot = tot;
     }
     __syncthreads();
-    if (KT > 1) {  // publish the tile's spikes of step t: the entries, then the count
+    if constexpr (Q) {
+      if (t < Tb) {
+        queue_spikes(n, b, k, j0, t, tag0 + t, words, woff, nw, gtot, pu, pu + kQChunk, stg, scap, bcnt, qs, cst, bpl,
+                     wsum);
+        if (t + 1 < Tb && t + 1 <= t_end)
+          deliver_tile<real, ring_t, P, U, RPT, Q>(n, b, k, j0, t + 1, Tb, ring, sc, ptab, pcap, wsum, words, woff, 0u,
+                                                   0u, tpre);
+        drain_queues(n, b, k, t, Tb, ring, sc, wsum, tpre, qd, tag0 + t);
+      }
+    } else if (KT > 1) {  // publish the tile's spikes of step t: the entries, then the count
       // (a single-tile trial delivers its spikes from its own LDS bitset)
       uint64_t *pl = n.pub_list + ((size_t)b * 2 + (t & 1u)) * n.Jp + j0;
       const uint64_t tag = (uint64_t)t << 32;
@@ -656,7 +911,9 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
       __syncthreads();
       if (threadIdx.x == 0) store_sys(&n.pub_cnt[((size_t)b * 2 + (t & 1u)) * KT + k], tag | gtot);
     }
-    if (t < Tb) deliver_tile<real, ring_t, P, U, RPT>(n, b, k, j0, t, Tb, ring, sc, ptab, wsum, words, woff, nw, gtot);
+    if (!Q && t < Tb)
+      deliver_tile<real, ring_t, P, U, RPT, Q>(n, b, k, j0, t, Tb, ring, sc, ptab, pcap, wsum, words, woff, nw, gtot,
+                                               tpre);
     __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -2225,6 +2482,7 @@ struct FwdKernels {
       case 1: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 1>);
       case 2: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 2>);
       case 3: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 3>);
+      case 4: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 4>);
       default: return reinterpret_cast<const void *>(&k_forward_tiled<real, ring_t, F, 0>);
     }
   }
@@ -2236,6 +2494,7 @@ struct FwdKernels {
       case 1: k_forward_tiled<real, ring_t, F, 1><<<grid, block, smem, s>>>(n, nsteps, b0); break;
       case 2: k_forward_tiled<real, ring_t, F, 2><<<grid, block, smem, s>>>(n, nsteps, b0); break;
       case 3: k_forward_tiled<real, ring_t, F, 3><<<grid, block, smem, s>>>(n, nsteps, b0); break;
+      case 4: k_forward_tiled<real, ring_t, F, 4><<<grid, block, smem, s>>>(n, nsteps, b0); break;
       default: k_forward_tiled<real, ring_t, F, 0><<<grid, block, smem, s>>>(n, nsteps, b0); break;
     }
   }

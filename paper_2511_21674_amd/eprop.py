@@ -24,6 +24,7 @@ EPROP_ERR_NUMERIC, EPROP_ERR_UNSUPPORTED = -6, -7
 EPROP_FP32, EPROP_FP64 = 0, 1
 EPROP_DELIVERY_AUTO, EPROP_DELIVERY_SCATTER, EPROP_DELIVERY_GATHER = 0, 1, 2
 EPROP_FLAG_NO_GRAPH, EPROP_DETERMINISTIC, EPROP_SHARED_WEIGHTS, EPROP_AUTOTUNE = 1, 2, 4, 8
+EPROP_SCATTER_LOOKUP, EPROP_SCATTER_QUEUES = 16, 32
 EPROP_MEM_HOST, EPROP_MEM_DEVICE = 0, 1
 EPROP_BATCH_TRAIN, EPROP_BATCH_PROFILE, EPROP_RECORD_SPIKES, EPROP_RECORD_TRACES = 1, 2, 4, 8
 EPROP_BATCH_TIME_DRIVEN = 16
@@ -227,7 +228,8 @@ class Network:
 
     def __init__(self, wnet, precision: str = "fp32", max_trials: int = 1, max_steps: int = 1000,
                  delivery: str = "auto", graph: bool = True, stream=None, max_delay: int = None,
-                 torch_alloc: bool = False, deterministic: bool = False, autotune: bool = False):
+                 torch_alloc: bool = False, deterministic: bool = False, autotune: bool = False,
+                 scatter_form: str = "auto"):
         p = wnet.params
         self.wnet = wnet
         self._keep = []
@@ -250,7 +252,8 @@ class Network:
                            isi_cutoff=int(getattr(p, "isi_cutoff", 0)),
                            delivery={"auto": 0, "scatter": 1, "gather": 2}[delivery],
                            flags=(0 if graph else EPROP_FLAG_NO_GRAPH) | (EPROP_DETERMINISTIC if deterministic else 0)
-                           | (EPROP_AUTOTUNE if autotune else 0))
+                           | (EPROP_AUTOTUNE if autotune else 0)
+                           | {"auto": 0, "lookup": EPROP_SCATTER_LOOKUP, "queues": EPROP_SCATTER_QUEUES}[scatter_form])
         self.allocator = TorchAllocator() if torch_alloc else None
         if self.allocator is not None:
             cfg.dev_alloc, cfg.dev_free = self.allocator.alloc_fn, self.allocator.free_fn
@@ -363,7 +366,7 @@ class Network:
         return dict(zip(("tile_neurons", "tiles", "ring_bytes", "tile_threads", "synapse_threads",
                          "synapse_trials", "steps_per_launch", "gather", "piece", "pieces_in_flight",
                          "adjoint_threads", "autotuned", "piece_table", "synapse_prefetch", "synapse_batch",
-                         "blocked_update", "forward_trials_per_launch"), v))
+                         "blocked_update", "forward_trials_per_launch", "queues"), v))
 
     def weights(self) -> dict:
         return {"w_in": self.read(EPROP_STATE_W_IN), "w_rec": self.read(EPROP_STATE_W_REC),

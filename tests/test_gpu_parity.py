@@ -687,7 +687,7 @@ def test_c5_twin_fp32_ring32_unblocked_alif():
     each update stays above the largest sum of |w| into one target."""
     wl = _c5_twin()
     fp32_forced_run("c5 twin", wl, 2, 1, rate=5.0, max_delay=C5_TWIN_RING_STEPS,
-                    expect_layout={"ring_bytes": 4, "blocked_update": 0, "gather": 0})
+                    expect_layout={"ring_bytes": 4, "blocked_update": 0, "gather": 0, "queues": 1})
     net = E.Network(wl.network, "fp32", max_trials=1, max_steps=200, max_delay=C5_TWIN_RING_STEPS)
     assert net.layout()["tiles"] > 1
     for it in range(2):
@@ -701,6 +701,97 @@ def test_c5_twin_fp32_ring32_unblocked_alif():
         bound = float(net.read(E.EPROP_STATE_INPUT_BOUND)[0])
         assert l1.max() <= bound <= l1.max() * 1.001 * (1 + 1e-6), (it, bound, l1.max())
     net.close()
+
+
+def _train_form(wl, form, bs, iterations, T, max_delay=None, forced_rate=None):
+    """FP32 training on one handle with the given scatter form: per
+    iteration the losses, every trial's spikes, the gradients and the
+    weights after the update."""
+    net = E.Network(wl.network, "fp32", max_trials=bs, max_steps=T, max_delay=max_delay, scatter_form=form)
+    lay = net.layout()
+    assert lay["queues"] == (1 if form == "queues" else 0) and lay["tiles"] > 1, (form, lay)
+    h = {"loss": [], "spikes": [], "grads": [], "weights": [], "events": 0, "rec_spikes": 0}
+    for it in range(iterations):
+        b = wl.make_batch(it, 0, bs)
+        if forced_rate:
+            b = W.forced_poisson(b, wl.network.n_rec, forced_rate, wl.network.params.dt, seed=17, iteration=it,
+                                 n_ref=2)
+        r = net.simulate(b, train=True)
+        h["events"] += r.n_syn_events
+        h["rec_spikes"] += r.n_rec_spikes
+        h["loss"].append(r.loss.copy())
+        h["spikes"].append([net.read(E.EPROP_STATE_SPIKES, i) for i in range(bs)])
+        h["grads"].append(net.grads())
+        net.apply()
+        h["weights"].append(net.weights())
+    net.close()
+    return h, lay
+
+
+def _assert_same_training(a, b, what):
+    assert a["events"] == b["events"] and a["rec_spikes"] == b["rec_spikes"] > 0, (what, a["events"], b["events"])
+    for it in range(len(a["loss"])):
+        assert np.array_equal(a["loss"][it], b["loss"][it]), (what, it)
+        for i, (sa, sb) in enumerate(zip(a["spikes"][it], b["spikes"][it])):
+            assert np.array_equal(sa, sb), (what, it, i)
+        for k in KEYS:
+            assert np.array_equal(a["grads"][it][k], b["grads"][it][k]), (what, it, k)
+            assert np.array_equal(a["weights"][it][k], b["weights"][it][k]), (what, it, k)
+
+
+@pytest.mark.parametrize("name", ["c5twin", "c4twin"])
+def test_queues_and_lookup_deliver_the_same(name):
+    """Scatter delivery through the per-tile queues (each spiking neuron's
+    tile copies its synapses into one queue per target tile) against
+    delivery by lookup (each tile looks up every spiking source), FP32, free
+    running, three iterations with updates: the input currents are the same
+    fixed-point sums however the arrivals are ordered, so spikes, losses,
+    gradients and weights agree bit for bit.  The lookup form is held to
+    the oracle by the other FP32 tests.  The twin of the million-neuron
+    network takes the queues by default (rows sparse across tiles); the C4
+    twin (rows dense within tiles) forces them."""
+    if name == "c5twin":
+        wl, bs, T, md = _c5_twin(), 1, 200, C5_TWIN_RING_STEPS
+    else:
+        wl, bs, T, md = W.c4_sparse(n_rec=2000, n_steps=200, batch_size=2, n_in=300), 2, 200, None
+    hq, lay = _train_form(wl, "queues", bs, 3, T, md)
+    hl, _ = _train_form(wl, "lookup", bs, 3, T, md)
+    log(f"{name}: {hq['events']} events; queue layout {lay}")
+    if name == "c5twin":
+        net = E.Network(wl.network, "fp32", max_trials=bs, max_steps=T, max_delay=md)
+        assert net.layout()["queues"] == 1
+        net.close()
+    _assert_same_training(hq, hl, name)
+
+
+def test_queue_tags_across_many_batches():
+    """The queues' step tags are 16 bits wide and every forward pass takes
+    fresh ones, so after 65535 steps the library clears the queues and
+    starts over.  Seventy batches of 1000 steps on a handle with the queues
+    forced (four tiles) cross that point; every batch's loss and spike
+    count equal those of a handle delivering by lookup."""
+    wl = W.c4_sparse(n_rec=2048, n_steps=1000, batch_size=1, n_in=200)
+    nets = [E.Network(wl.network, "fp32", max_trials=1, max_steps=1000, scatter_form=f) for f in ("queues", "lookup")]
+    assert nets[0].layout()["queues"] == 1 and nets[0].layout()["tiles"] > 1
+    assert nets[1].layout()["queues"] == 0
+    for it in range(70):
+        b = wl.make_batch(it, 0, 1)
+        rq, rl = nets[0].simulate(b), nets[1].simulate(b)
+        assert rq.n_rec_spikes == rl.n_rec_spikes > 0 and rq.n_syn_events == rl.n_syn_events, it
+        assert np.array_equal(rq.loss, rl.loss), it
+    assert np.array_equal(nets[0].read(E.EPROP_STATE_SPIKES, 0), nets[1].read(E.EPROP_STATE_SPIKES, 0))
+    for net in nets:
+        net.close()
+
+
+def test_queue_form_rejected_where_it_does_not_apply():
+    """EPROP_SCATTER_QUEUES needs FP32 scatter delivery with more than one
+    tile per trial: FP64 and a single-tile network are refused with
+    EPROP_ERR_UNSUPPORTED."""
+    for wl, prec in ((W.c4_sparse(n_rec=2048, n_steps=50, batch_size=1, n_in=100), "fp64"), (W.tiny(), "fp32")):
+        with pytest.raises(E.EpropError) as ex:
+            E.Network(wl.network, prec, max_trials=1, max_steps=50, scatter_form="queues")
+        assert ex.value.status == E.EPROP_ERR_UNSUPPORTED
 
 
 def test_full_size_million_neuron_network_sampled():
