@@ -383,15 +383,19 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
 
 // Uploads graph, weights and optimiser state (host arrays in double).
 // Tables and buffers of the per-tile queues: every recurrent neuron's
-// non-empty tile segments (q_nzp, q_nz), and the regions of the event
-// buffers, one per (source tile, target tile) pair, sized by the synapses
-// between the two tiles and ordered by target tile, then source tile
-// (q_src row k: the starts of tile k's regions as a source; q_dst row k:
-// those of the regions into tile k).  The buffers start cleared.
+// non-empty tile segments (q_nzp, q_nz), then, from q_nz[q_in], one entry
+// per input i and tile k: the segment of i into tile (k - i) mod KT, which
+// tile k copies when i spikes (so an input spike's segments are spread over
+// all tiles); and the regions of the event buffers, one per (source tile,
+// target tile) pair, sized by the synapses the source tile copies into the
+// target tile (those of its own neurons and its input segments), ordered by
+// target tile, then source tile (q_src row k: the starts of tile k's
+// regions as a source; q_dst row k: those of the regions into tile k).  The
+// buffers start cleared.
 template <typename real>
 hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t> &tseg,
                          const std::vector<uint2> &dsegh) {
-  const uint32_t KT = d.KT, TS = d.TS, J = n->J, I = n->I;
+  const uint32_t KT = d.KT, TS = d.TS, J = n->J, I = n->I, NS = n->NS;
   const unsigned nt = n->S >= (1u << 22) ? host_threads() : 1u;
   auto L_of = [&](uint64_t src, uint32_t k) {
     return tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k];
@@ -406,10 +410,12 @@ hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<ui
     }
   });
   for (uint32_t j = 0; j < J; ++j) nzp[j + 1] += nzp[j];
-  std::vector<uint2> nz(std::max<uint32_t>(nzp[J], 1u), make_uint2(0u, 0u));
+  const uint64_t q_in = nzp[J];
+  if (q_in + (uint64_t)I * KT >= (1ull << 32)) return hipErrorInvalidValue;
+  std::vector<uint2> nz(std::max<uint64_t>(q_in + (uint64_t)I * KT, 1), make_uint2(0u, 0u));
   std::vector<uint64_t> rsz((size_t)KT * KT, 0);
   parallel_ranges(KT, std::min<unsigned>(nt, KT), flat, [&](uint64_t k0, uint64_t k1, unsigned) {
-    for (uint64_t ks = k0; ks < k1; ++ks)
+    for (uint64_t ks = k0; ks < k1; ++ks) {
       for (uint64_t j = ks * TS; j < std::min<uint64_t>(J, (ks + 1) * TS); ++j) {
         uint32_t at = nzp[j];
         for (uint32_t kd = 0; kd < KT; ++kd) {
@@ -419,6 +425,12 @@ hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<ui
           rsz[ks * KT + kd] += L;
         }
       }
+      for (uint64_t i = 0; i < I; ++i) {  // input i's segment into tile (ks - i) mod KT
+        const uint32_t kd = (uint32_t)((ks + KT - i % KT) % KT), L = L_of(i, kd);
+        nz[q_in + i * KT + ks] = make_uint2(L ? dsegh[i * KT + eprop::tile_rank(kd, KT)].x : 0u, L | kd << 16);
+        rsz[ks * KT + kd] += L;
+      }
+    }
   });
   std::vector<uint32_t> qsrc((size_t)KT * KT), qdst((size_t)KT * KT);
   uint64_t acc = 0;
@@ -427,7 +439,7 @@ hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<ui
       qdst[(size_t)kd * KT + ks] = qsrc[(size_t)ks * KT + kd] = (uint32_t)acc;
       acc += rsz[(size_t)ks * KT + kd];
     }
-  if (acc != n->S_rec) return hipErrorInvalidValue;  // every recurrent synapse in exactly one region
+  if (acc != n->S) return hipErrorInvalidValue;  // every synapse in exactly one region
   d.q_len = (uint32_t)std::max<uint64_t>(acc, 1);
   uint32_t *p_nzp = nullptr, *p_src = nullptr, *p_dst = nullptr;
   uint2 *p_nz = nullptr;
@@ -444,6 +456,7 @@ hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<ui
   if (e == hipSuccess) e = hipMemset(p_hdr, 0, nhdr * 8);
   d.q_nzp = p_nzp;
   d.q_nz = p_nz;
+  d.q_in = (uint32_t)q_in;
   d.q_src = p_src;
   d.q_dst = p_dst;
   d.q_ev = p_ev;
@@ -999,18 +1012,18 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
     // sparse across tiles (fewer than 4 synapses per source and tile on
     // average) and they fit a quarter of the free memory, or when asked for
     const bool want = (cfg->flags & EPROP_SCATTER_QUEUES) != 0;
-    const bool able = !n->gather && !n->fp64 && KT > 1 && n->S_rec > 0 && n->S_rec < (1ull << 32);
+    const bool able = !n->gather && !n->fp64 && KT > 1 && n->S > 0 && n->S < (1ull << 32);
     if (want && !able) {
       g_create_error = "EPROP_SCATTER_QUEUES needs FP32 scatter delivery, more than one tile per trial and "
-                       "fewer than 2^32 recurrent synapses";
+                       "fewer than 2^32 synapses";
       delete n;
       return EPROP_ERR_UNSUPPORTED;
     }
     const bool sparse = (double)n->S_rec < 4.0 * (double)J * (double)KT;
     if (able && !(cfg->flags & EPROP_SCATTER_LOOKUP) && (want || sparse)) {
       const size_t kt2 = (size_t)KT * KT;
-      const size_t bytes = (size_t)n->Bcap * 2 * n->S_rec * 8 + n->S_rec * 8 + ((size_t)J + 1) * 4 + 2 * kt2 * 4 +
-                           (size_t)n->Bcap * 2 * kt2 * 8;
+      const size_t bytes = (size_t)n->Bcap * 2 * n->S * 8 + (n->S_rec + (size_t)I * KT) * 8 + ((size_t)J + 1) * 4 +
+                           2 * kt2 * 4 + (size_t)n->Bcap * 2 * kt2 * 8;
       size_t free_b = 0, total_b = 0;
       const bool known = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
       if (want && known && bytes > free_b) {

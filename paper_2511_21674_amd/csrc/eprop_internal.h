@@ -40,9 +40,12 @@
 //                        (t << 32 | count of tile k), nspk[b][t]
 //   per-tile queues      (scatter delivery through queues, FP32) q_nzp[J+1], q_nz[]: for each
 //                        recurrent neuron, its non-empty tile segments {word index in dlw,
-//                        L | target tile << 16}; q_ev[b][t & 1][q_len]: one region per
-//                        (source tile, target tile), as large as the synapses between
-//                        them, regions ordered by target tile, then source tile; q_src[k][kd]
+//                        L | target tile << 16}; then q_nz[q_in + i * KT + k]: input i's
+//                        segment into tile (k - i) mod KT, copied by tile k;
+//                        q_ev[b][t & 1][q_len]: one region per (source tile, target
+//                        tile), as large as the synapses the source tile copies into the
+//                        target tile, regions ordered by target tile, then source tile;
+//                        q_src[k][kd]
 //                        (= q_dst[kd][k]): where region (k -> kd) starts; an event is
 //                        tag16 << 48 | ring offset << 32 | weight bits; q_hdr[b][t & 1][kd][k]
 //                        = tag << 32 | events of step t in region (k -> kd)
@@ -163,7 +166,8 @@ struct DevNet {
   const uint32_t *q_nzp, *q_src, *q_dst;
   const uint2 *q_nz;
   uint64_t *q_ev, *q_hdr;
-  uint32_t q_len;               // events per (trial, parity) buffer: the recurrent synapses
+  uint32_t q_len;               // events per (trial, parity) buffer: the synapses
+  uint32_t q_in;                // where the input entries of q_nz start
   uint32_t *nspk;
   uint64_t *in_step_ptr;        // [Bcap][Tcap+1]
   double *ysum, *y, *err;       // [Bcap][Tcap+2][K]

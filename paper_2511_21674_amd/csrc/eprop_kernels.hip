@@ -384,10 +384,9 @@ __device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
 // | (distance from that weight to the piece's first ring offset, in uint16
 // units) << 6.
 // [P, U] of the delivery variants the autotuner chooses from; variant 0 is
-// the default.  Variant 4 (FP32) delivers the recurrent spikes through the
-// per-tile queues instead (queue_spikes, drain_queues), and this function
-// (kQueue) then delivers only the step's input spikes; its P and U also
-// shape the queue copy.
+// the default.  Variant 4 (FP32) delivers the spikes of steps 1.. through
+// the per-tile queues instead (queue_spikes, drain_queues), and this
+// function (kQueue) then delivers only the input spikes of step 0.
 constexpr uint32_t kFwdVariants = 5;
 constexpr uint32_t kNoEntry = 0xFFFFFFFFu;  // a parked list entry that had not arrived
 constexpr uint32_t kQueueUnroll = 4;        // queue events a thread holds in flight
@@ -633,10 +632,13 @@ __device__ inline void drain_queues(const DevNet<float> &n, uint32_t b, uint32_t
 
 // Source side of the queues (FP32): after the neuron update of step t, the
 // tile copies the synapses of each of its spiking neurons into the queues
-// of their target tiles, as tagged events.  Per chunk of kQChunk spiking
-// neurons, a thread finds its neuron from the bitset words and their
-// popcount prefix, and a block scan numbers the neurons' non-empty segments
-// (pp, pz).  Per batch of kQueueUnroll * blockDim segments, a thread takes
+// of their target tiles, as tagged events, and of every input spike of step
+// t the one segment into tile (k - i) mod KT (so each input spike is
+// copied by all tiles together).  Per chunk of kQChunk items (the step's
+// input spikes, then the tile's spikes), a thread takes its input's entry
+// (those of the first chunk loaded before the neuron update: inz, iny) or finds
+// its neuron from the bitset words and their popcount prefix, and a block
+// scan numbers the items' non-empty segments (pp, pz).  Per batch of kQueueUnroll * blockDim segments, a thread takes
 // kQueueUnroll of them and reserves each segment's place in the region
 // (this tile -> target tile) with an LDS atomic on that tile's counter
 // (bcnt; cst holds the counters at the start of the batch).  The batch's
@@ -655,26 +657,35 @@ __device__ inline void drain_queues(const DevNet<float> &n, uint32_t b, uint32_t
 constexpr uint32_t kQChunk = 256;
 __device__ inline void queue_spikes(const DevNet<float> &n, uint32_t b, uint32_t k, uint32_t j0, uint32_t t,
                                     uint32_t tag, const uint64_t *words, const uint32_t *woff, uint32_t nw,
-                                    uint32_t gtot, uint32_t *pp, uint32_t *pz, uint2 *stg, uint32_t scap,
-                                    uint32_t *bcnt, const uint32_t *qs, uint32_t *cst, uint32_t *bpl,
-                                    uint32_t *wsum) {
+                                    uint32_t gtot, uint64_t in_lo, uint32_t n_in, uint32_t inz, uint32_t iny,
+                                    uint32_t *pp,
+                                    uint32_t *pz, uint2 *stg, uint32_t scap, uint32_t *bcnt, const uint32_t *qs,
+                                    uint32_t *cst, uint32_t *bpl, uint32_t *wsum) {
   const uint32_t KT = n.KT;
   const size_t par = (size_t)b * 2 + (t & 1u);
   uint64_t *evq = n.q_ev + par * n.q_len;
   const uint64_t hi = (uint64_t)(tag & 0xFFFFu) << 48;
   const uint16_t *o16 = reinterpret_cast<const uint16_t *>(n.dlw);
-  for (uint32_t c0 = 0; c0 < gtot; c0 += kQChunk) {
+  const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
+  const uint32_t items = n_in + gtot;
+  for (uint32_t c0 = 0; c0 < items; c0 += kQChunk) {
     const uint32_t r = c0 + threadIdx.x;
     uint32_t np = 0, z0 = 0;
-    if (threadIdx.x < kQChunk && r < gtot) {  // the r-th spike: word lw with woff[lw] <= r < woff[lw + 1]
-      uint32_t lw = 0, hw = nw;
-      while (hw - lw > 1) {
-        const uint32_t mid = (lw + hw) >> 1;
-        if (woff[mid] <= r) lw = mid; else hw = mid;
+    if (threadIdx.x < kQChunk && r < items) {
+      if (r >= n_in) {  // the (r - n_in)-th spike: word lw with woff[lw] <= r - n_in < woff[lw + 1]
+        const uint32_t rr = r - n_in;
+        uint32_t lw = 0, hw = nw;
+        while (hw - lw > 1) {
+          const uint32_t mid = (lw + hw) >> 1;
+          if (woff[mid] <= rr) lw = mid; else hw = mid;
+        }
+        const uint32_t j = min(j0 + lw * 64 + nth_set_bit(words[lw], rr - woff[lw]), n.J - 1u);
+        z0 = n.q_nzp[j];
+        np = n.q_nzp[j + 1] - z0;
+      } else {
+        z0 = c0 == 0 ? inz : n.q_in + min(in_src[in_lo + r], n.I - 1u) * KT + k;
+        np = ((c0 == 0 ? iny : n.q_nz[z0].y) & 0xFFFFu) ? 1u : 0u;
       }
-      const uint32_t j = min(j0 + lw * 64 + nth_set_bit(words[lw], r - woff[lw]), n.J - 1u);
-      z0 = n.q_nzp[j];
-      np = n.q_nzp[j + 1] - z0;
     }
     uint32_t npairs;
     const uint32_t pre = block_exclusive_scan(np, wsum, &npairs);
@@ -684,7 +695,7 @@ __device__ inline void queue_spikes(const DevNet<float> &n, uint32_t b, uint32_t
     }
     for (uint32_t kd = threadIdx.x; kd < KT; kd += blockDim.x) cst[kd] = bcnt[kd];
     __syncthreads();
-    const uint32_t nown = min(kQChunk, gtot - c0);
+    const uint32_t nown = min(kQChunk, items - c0);
     for (uint32_t s0 = 0; s0 < npairs; s0 += kQueueUnroll * blockDim.x) {
       uint2 ent[kQueueUnroll];
 #pragma unroll
@@ -847,15 +858,23 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     __syncthreads();
   }
   const uint32_t t_end = min(t0 + nsteps, Tb);
-  // with queues, the inputs of a step are delivered during the step before
-  // (while the tile waits for the other tiles' counts), the first here
-  if (Q && t0 + 1 < Tb) {
-    deliver_tile<real, ring_t, P, U, RPT, Q>(n, b, k, j0, t0 + 1, Tb, ring, sc, ptab, pcap, wsum, words, woff, 0u,
-                                             0u, tpre);
-    __syncthreads();
-  }
   for (uint32_t t = t0 + 1; t <= t_end; ++t) {
     const uint32_t slot = t % n.R;
+    // queues: the step's input spikes, and the entry of the first kQChunk of
+    // them, loaded before the neuron update
+    uint64_t in_lo = 0;
+    uint32_t n_in = 0, inz = 0, iny = 0;
+    if constexpr (Q) {
+      const uint64_t *isp = n.in_step_ptr + (size_t)b * (n.Tcap + 1);
+      in_lo = isp[t];
+      const uint64_t in_hi = t < Tb ? isp[t + 1] : in_lo;
+      n_in = in_hi > in_lo ? (uint32_t)(in_hi - in_lo) : 0u;
+      if (threadIdx.x < min(n_in, kQChunk)) {
+        const uint32_t *in_src = *reinterpret_cast<const uint32_t *const *>(n.ctl + CTL_WORDS);
+        inz = n.q_in + min(in_src[in_lo + threadIdx.x], n.I - 1u) * KT + k;
+        iny = n.q_nz[inz].y;
+      }
+    }
     for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
       real v = sv[i], a = sa[i];
       uint8_t st = sst[i];
@@ -891,11 +910,8 @@ __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t
     __syncthreads();
     if constexpr (Q) {
       if (t < Tb) {
-        queue_spikes(n, b, k, j0, t, tag0 + t, words, woff, nw, gtot, pu, pu + kQChunk, stg, scap, bcnt, qs, cst, bpl,
-                     wsum);
-        if (t + 1 < Tb && t + 1 <= t_end)
-          deliver_tile<real, ring_t, P, U, RPT, Q>(n, b, k, j0, t + 1, Tb, ring, sc, ptab, pcap, wsum, words, woff, 0u,
-                                                   0u, tpre);
+        queue_spikes(n, b, k, j0, t, tag0 + t, words, woff, nw, gtot, in_lo, n_in, inz, iny, pu, pu + kQChunk, stg,
+                     scap, bcnt, qs, cst, bpl, wsum);
         drain_queues(n, b, k, t, Tb, ring, sc, wsum, tpre, qd, tag0 + t);
       }
     } else if (KT > 1) {  // publish the tile's spikes of step t: the entries, then the count
