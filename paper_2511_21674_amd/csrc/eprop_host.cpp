@@ -86,6 +86,7 @@ struct eprop_network {
   bool queues = false;              // per-tile queues built (FP32 scatter; forward variant kQueueVariant)
   uint32_t q_since = 0;             // queue step tags used since the queues were last cleared
   uint64_t dl_words = 0;            // size of the delivery table (4-byte words)
+  bool dl_packed = false;           // its segments packed (the line-aligned placement would exceed 2^31 words)
   // e-prop+ schedule (allocated on the first online batch)
   void *on_syn = nullptr;
   double *on_Eh = nullptr, *on_y = nullptr, *on_zbo = nullptr, *on_loss = nullptr, *on_psum = nullptr;
@@ -129,10 +130,11 @@ void set_fail(eprop_network *n, const std::string &m) { n->err = m; }
 // Places a delivery-table segment of L synapses (L weights of sz bytes, then
 // L uint16 ring offsets, rounded up to a multiple of sz) at byte cur or
 // later: on the next kDlGrain boundary if it is longer than kDlGrain or
-// would otherwise cross a boundary that it fits between.  Returns the end.
-uint64_t dl_place(uint64_t cur, uint64_t L, uint64_t sz, uint64_t *at) {
+// would otherwise cross a boundary that it fits between (unless packed).
+// Returns the end.
+uint64_t dl_place(uint64_t cur, uint64_t L, uint64_t sz, uint64_t *at, bool packed) {
   const uint64_t G = eprop::kDlGrain, z = (L * (sz + 2) + sz - 1) / sz * sz;
-  if (z > 0 && (z > G || cur % G + z > G)) cur = (cur + G - 1) / G * G;
+  if (!packed && z > 0 && (z > G || cur % G + z > G)) cur = (cur + G - 1) / G * G;
   *at = cur;
   return cur + z;
 }
@@ -395,7 +397,7 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
 template <typename real>
 hipError_t upload_queues(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t> &tseg,
                          const std::vector<uint2> &dsegh) {
-  const uint32_t KT = d.KT, TS = d.TS, J = n->J, I = n->I, NS = n->NS;
+  const uint32_t KT = d.KT, TS = d.TS, J = n->J, I = n->I;
   const unsigned nt = n->S >= (1u << 22) ? host_threads() : 1u;
   auto L_of = [&](uint64_t src, uint32_t k) {
     return tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k];
@@ -491,31 +493,47 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
     cp((void *)d.tseg, tseg.data(), tseg.size() * 4);
     // delivery table: each source's part starts on a kDlGrain boundary (so
     // that the parts can be laid out independently); inside it, the
-    // segments of the tiles in tile_rank order, each placed by dl_place
+    // segments of the tiles in tile_rank order, each placed by dl_place.
+    // The kernels index the ring offsets in uint16 units with 32-bit
+    // integers, so the table holds under 2^31 words; where the line-aligned
+    // placement would not fit that (its padding costs up to a third at
+    // segments of 40 synapses, as in the paper's scaling network), the
+    // segments are packed instead.
     const uint32_t KT = d.KT, TS = d.TS;
     const uint64_t NS = n->NS;
     std::vector<uint32_t> by_rank(KT);  // the tile at each place
     for (uint32_t k = 0; k < KT; ++k) by_rank[eprop::tile_rank(k, KT)] = k;
     auto src_weight = [&](uint64_t src) { return (uint64_t)sm_ptr[src]; };
     std::vector<uint64_t> part(NS + 1, 0);
-    parallel_ranges(NS, nt, src_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
-      for (uint64_t src = s0; src < s1; ++src) {
-        uint64_t cur = 0, at = 0;
-        for (uint32_t r = 0; r < KT; ++r) {
-          const uint32_t k = by_rank[r];
-          cur = dl_place(cur, tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k], sizeof(real), &at);
-        }
-        part[src] = (cur + eprop::kDlGrain - 1) / eprop::kDlGrain * eprop::kDlGrain;
-      }
-    });
     uint64_t total = 0;
-    for (uint64_t src = 0; src < NS; ++src) {
-      const uint64_t b = part[src];
-      part[src] = total;
-      total += b;
+    bool packed = false;
+    for (int pass = 0; pass < 2; ++pass) {
+      packed = pass == 1;
+      parallel_ranges(NS, nt, src_weight, [&](uint64_t s0, uint64_t s1, unsigned) {
+        for (uint64_t src = s0; src < s1; ++src) {
+          uint64_t cur = 0, at = 0;
+          for (uint32_t r = 0; r < KT; ++r) {
+            const uint32_t k = by_rank[r];
+            cur = dl_place(cur, tseg[src * (KT + 1) + k + 1] - tseg[src * (KT + 1) + k], sizeof(real), &at, packed);
+          }
+          part[src] = (cur + eprop::kDlGrain - 1) / eprop::kDlGrain * eprop::kDlGrain;
+        }
+      });
+      total = 0;
+      for (uint64_t src = 0; src < NS; ++src) {
+        const uint64_t b = part[src];
+        part[src] = total;
+        total += b;
+      }
+      part[NS] = total;
+      if (total / 4 < (1ull << 31)) break;
     }
-    part[NS] = total;
-    if (total / 4 >= (1ull << 31)) return hipErrorInvalidValue;  // (rejected at create)
+    if (total / 4 >= (1ull << 31)) {
+      g_create_error = "the delivery table needs " + std::to_string(total >> 20) +
+                       " MiB, more than the 8 GiB its 32-bit uint16 indices address";
+      return hipErrorNotSupported;
+    }
+    n->dl_packed = packed;
     n->dl_words = std::max<uint64_t>(total / 4, 1);
     std::vector<uint32_t> dlh(n->dl_words, 0u), dpos(n->S, 0u);
     std::vector<uint2> dsegh((size_t)NS * KT);
@@ -525,7 +543,7 @@ hipError_t upload(eprop_network *n, DevNet<real> &d, const std::vector<uint32_t>
         for (uint32_t r = 0; r < KT; ++r) {
           const uint32_t k = by_rank[r];
           const uint32_t q0 = tseg[src * (KT + 1) + k], L = tseg[src * (KT + 1) + k + 1] - q0;
-          cur = dl_place(cur, L, sizeof(real), &at);
+          cur = dl_place(cur, L, sizeof(real), &at, packed);
           const uint32_t word = (uint32_t)((part[src] + at) / 4);
           dsegh[src * KT + r] = make_uint2(word, L);
           real *wp = reinterpret_cast<real *>(dlh.data() + word);
@@ -1083,6 +1101,10 @@ static eprop_status create_network(const eprop_config *cfg, const eprop_projecti
                          feedback, opt)
                 : upload(n, n->n32, sm_ptr, tseg, sm_syn, sm_w, tm_ptr, tm_syn, tm_perm, tm_w, beta, w_out,
                          feedback, opt);
+  if (e == hipErrorNotSupported && !g_create_error.empty()) {  // a size the tables cannot address
+    eprop_destroy_network(n);
+    return EPROP_ERR_UNSUPPORTED;
+  }
   if (e == hipSuccess) {  // this device's staging array of the no-allocation batch call (device current)
     n->scratch = static_cast<uint8_t *>(eprop::scratch_address(dev, &e));
   }
