@@ -367,12 +367,14 @@ bool alloc_state(eprop_network *n, DevNet<real> &d) {
   ok &= dalloc(n, &d.evcnt, 64);
   const uint32_t nchunk_max = (n->Bcap + n->shapes.ginst - 1) / n->shapes.ginst;
   {
-    // worst case: every record has a header and a partly used last block
+    // worst case: every record has a header and a partly used last block,
+    // rounded up to its size class (under twice its size), the class regions
+    // start on lines, and slack follows for the synapse kernel's prefetch
     const size_t recs = (size_t)nchunk_max * n->NS;
-    d.pk_cap = 2 * recs + (B * n->NS * (size_t)d.Lc + 7) / 8 + 8;
+    d.pk_cap = 3 * (2 * recs + (B * n->NS * (size_t)d.Lc + 7) / 8) + 40;
     ok &= d.pk_cap < 0xFFFFFFF0ull;
     ok &= dalloc(n, &d.pk_off, recs + 1);
-    ok &= dalloc(n, &d.pk_bsum, (recs + eprop::kScanItems - 1) / eprop::kScanItems + 1);
+    ok &= dalloc(n, &d.pk_bsum, ((recs + eprop::kScanItems - 1) / eprop::kScanItems + 1) * 4);
     ok &= dalloc(n, &d.pk, d.pk_cap * 8);
   }
   if (nchunk_max > 1) {

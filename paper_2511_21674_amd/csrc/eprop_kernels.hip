@@ -1363,9 +1363,16 @@ __global__ __launch_bounds__(256) void k_adjoint(DevNet<real> n) {
 // Per-source spike table of the batch.  The synapse kernel visits the
 // synapses of a target, whose sources are scattered; keeping all of a
 // source's spike times of a trial chunk in one contiguous record lets a
-// lane fetch them with one or two line reads instead of two per trial.
-// Records are 16-byte aligned, chunk-major and source-minor; their offsets
-// come from a three-kernel exclusive scan of the record sizes.
+// lane fetch them with one line read instead of two per trial.  A record
+// of u 16-byte units takes 1, 2 or 4 units (u up to 4) or a multiple of 8
+// (u above 4), in a region of the table for its size class, each region
+// starting on a 128-byte line, so that no record crosses a line (a read of
+// a record costs the lines it touches).  Within a class, records are
+// chunk-major and source-minor; their offsets come from a three-kernel
+// exclusive scan of the rounded sizes, one per class.
+__device__ inline uint32_t pk_class(uint32_t u) { return u > 4u ? 0u : u > 2u ? 1u : u > 1u ? 2u : 3u; }
+__device__ inline uint32_t pk_rounded(uint32_t u) { return u > 4u ? (u + 7u) & ~7u : u > 2u ? 4u : u; }
+
 template <typename real>
 __device__ inline uint32_t pk_units(const DevNet<real> &n, uint32_t e, uint32_t ginst, uint32_t ntr) {
   const uint32_t c = e / n.NS, i = e - c * n.NS;
@@ -1377,44 +1384,59 @@ __device__ inline uint32_t pk_units(const DevNet<real> &n, uint32_t e, uint32_t 
   return tot ? 1u + (tot + 7u) / 8u : 0u;
 }
 
-// Block-local exclusive scan of record sizes (kScanItems per block); block
-// totals into pk_bsum.
+// Block-local exclusive scans of the rounded record sizes, per size class
+// (kScanItems records per block): the record's place within its class and
+// block into pk_off, the block's class totals into pk_bsum[block][class].
 template <typename real>
 __global__ __launch_bounds__(1024) void k_pack_scan_local(DevNet<real> n, uint32_t ginst, uint32_t N) {
   __shared__ uint32_t wsum[17];
   const uint32_t ntr = n.ctl[CTL_NTRIALS];
   const uint32_t e0 = blockIdx.x * kScanItems + threadIdx.x * 4;
-  uint32_t sz[4], tsum = 0;
+  uint32_t sz[4];
 #pragma unroll
-  for (uint32_t u = 0; u < 4; ++u) {
-    sz[u] = e0 + u < N ? pk_units(n, e0 + u, ginst, ntr) : 0u;
-    tsum += sz[u];
-  }
-  uint32_t tot;
-  uint32_t run = block_exclusive_scan(tsum, wsum, &tot);
+  for (uint32_t u = 0; u < 4; ++u) sz[u] = e0 + u < N ? pk_units(n, e0 + u, ginst, ntr) : 0u;
+  uint32_t off[4] = {kNoRecord, kNoRecord, kNoRecord, kNoRecord};
+  for (uint32_t c = 0; c < 4; ++c) {
+    uint32_t tsum = 0;
 #pragma unroll
-  for (uint32_t u = 0; u < 4; ++u) {
-    if (e0 + u < N) n.pk_off[e0 + u] = sz[u] ? run : kNoRecord;
-    run += sz[u];
+    for (uint32_t u = 0; u < 4; ++u) tsum += sz[u] && pk_class(sz[u]) == c ? pk_rounded(sz[u]) : 0u;
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(tsum, wsum, &tot);
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u)
+      if (sz[u] && pk_class(sz[u]) == c) {
+        off[u] = run;
+        run += pk_rounded(sz[u]);
+      }
+    if (threadIdx.x == 0) n.pk_bsum[(size_t)blockIdx.x * 4 + c] = tot;
+    __syncthreads();  // (wsum is reused by the next class)
   }
-  if (threadIdx.x == 0) n.pk_bsum[blockIdx.x] = tot;
+#pragma unroll
+  for (uint32_t u = 0; u < 4; ++u)
+    if (e0 + u < N) n.pk_off[e0 + u] = off[u];
 }
 
-// Exclusive scan of the block totals (one block); pk_bsum[nblk] = table size.
+// Exclusive scans of the block totals per class (one block), and the start
+// of each class's region: pk_bsum[nblk][class], classes in order 0..3 (the
+// longest records first), each region on a 128-byte line.
 template <typename real>
 __global__ __launch_bounds__(1024) void k_pack_scan_blocks(DevNet<real> n, uint32_t nblk) {
   __shared__ uint32_t wsum[17];
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < nblk; base += blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t x = i < nblk ? n.pk_bsum[i] : 0u;
-    uint32_t tot;
-    const uint32_t pre = block_exclusive_scan(x, wsum, &tot);
-    __syncthreads();
-    if (i < nblk) n.pk_bsum[i] = carry + pre;
-    carry += tot;
+  uint32_t start = 0;
+  for (uint32_t c = 0; c < 4; ++c) {
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nblk; base += blockDim.x) {
+      const uint32_t i = base + threadIdx.x;
+      const uint32_t x = i < nblk ? n.pk_bsum[(size_t)i * 4 + c] : 0u;
+      uint32_t tot;
+      const uint32_t pre = block_exclusive_scan(x, wsum, &tot);
+      __syncthreads();
+      if (i < nblk) n.pk_bsum[(size_t)i * 4 + c] = carry + pre;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) n.pk_bsum[(size_t)nblk * 4 + c] = start;
+    start = (start + carry + 7u) & ~7u;
   }
-  if (threadIdx.x == 0) n.pk_bsum[nblk] = carry;
 }
 
 // Final offsets, headers (counts of the chunk's trials) and the LDS indices
@@ -1422,13 +1444,14 @@ __global__ __launch_bounds__(1024) void k_pack_scan_blocks(DevNet<real> n, uint3
 // their trial and the (synapse, trial) pairs with at least one, from the
 // source's out-degree per delay.
 template <typename real>
-__global__ __launch_bounds__(256) void k_pack_fill(DevNet<real> n, uint32_t ginst, uint32_t N) {
+__global__ __launch_bounds__(256) void k_pack_fill(DevNet<real> n, uint32_t ginst, uint32_t N, uint32_t nblk) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long nev = 0, nfl = 0;
   if (e < N && n.pk_off[e] != kNoRecord) {
-    const uint32_t off = n.pk_off[e] + n.pk_bsum[e / kScanItems];
-    n.pk_off[e] = off;
     const uint32_t ntr = n.ctl[CTL_NTRIALS];
+    const uint32_t cls = pk_class(pk_units(n, e, ginst, ntr));
+    const uint32_t off = n.pk_off[e] + n.pk_bsum[(size_t)(e / kScanItems) * 4 + cls] + n.pk_bsum[(size_t)nblk * 4 + cls];
+    n.pk_off[e] = off;
     const uint32_t c = e / n.NS, i = e - c * n.NS;
     const uint32_t b0 = c * ginst, nb = min(ginst, ntr - b0);
     const uint32_t *od = n.outdeg + (size_t)i * n.R;
@@ -2590,7 +2613,7 @@ void Launch<real>::synapse(const DevNet<real> &n, const Shapes &sh, uint32_t n_t
   const uint32_t N = nchunk * n.NS, nblk = (N + kScanItems - 1) / kScanItems;
   k_pack_scan_local<real><<<nblk, 1024, 0, s>>>(n, sh.ginst, N);
   k_pack_scan_blocks<real><<<1, 1024, 0, s>>>(n, nblk);
-  k_pack_fill<real><<<cdiv(N, 256), 256, 0, s>>>(n, sh.ginst, N);
+  k_pack_fill<real><<<cdiv(N, 256), 256, 0, s>>>(n, sh.ginst, N, nblk);
   const size_t smem = ((size_t)sh.ginst * n.Ts + n.R) * sizeof(real);
   const dim3 grid(n.J * nchunk);
   switch (sh.syn_var) {
