@@ -309,6 +309,8 @@ def cpu_parallel(wl, n_steps_sample, budget_s=20.0):
     t0 = time.perf_counter()
     with ctx.Pool(P) as pool:
         res = pool.map(_oracle_sample, [(i, T, budget_s / 2) for i in range(P)], chunksize=1)
+        pool.close()
+        pool.join()  # every worker gone before the timing is reported
     wall = time.perf_counter() - t0
     ev = sum(r[0] for r in res)
     what = f"the first {T} steps of trials 0..{P - 1}" if T else f"whole trials of the first batch, trial i in process i mod {P}"

@@ -2027,45 +2027,74 @@ __global__ __launch_bounds__(256) void k_online_learn(DevNet<real> n, OnlineRun<
 // reaches the readout now (gradient E_k^{r+d} zbar_j^r over the steps not
 // yet used, eq. eprop-output-new-subs-rewritten), then the readout
 // (eq. leaky_integrator_with_delay), error signal and loss of step t, FP64.
+// Readout synapses of the neurons whose spike reaches the readout at step t
+// (emitted at t - d): each walks its readout traces over the steps not yet
+// used, r <= t - 1 - d, and takes one gradient-descent step with
+// E^{r+d} zbar^r.  One thread per (spike-bitset word, output k), a block
+// holding whole words, so a neuron's walks for all outputs run side by side;
+// after a barrier (every walk has read the neuron's old trace state), one
+// thread per word walks once more without the error terms and stores the
+// neuron's new state (zbar, last spike, last step used).
+template <typename real>
+__device__ inline void online_out_walk(const DevNet<real> &n, const OnlineRun<real> &o, uint32_t j, int64_t r0,
+                                       int64_t r1, uint32_t &zl, double &zb, uint32_t k, double *g) {
+  const uint32_t K = n.K, d = n.d_out;
+  for (int64_t r = r0; r <= r1; ++r) {
+    const bool x = (n.rec_bits[(size_t)r * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull;
+    if (x) zl = (uint32_t)r;
+    if (o.cutoff && (zl == 0 || (uint64_t)(r - zl) >= o.cutoff)) {
+      zb = 0.0;
+      continue;
+    }
+    zb = n.kappa_d * zb + (x ? 1.0 : 0.0);
+    if (g) *g += o.Eh[(size_t)(r + d) * K + k] * zb;
+  }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_online_out_syn(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
+  const uint32_t K = n.K, d = n.d_out;
+  if (t <= d) return;
+  const uint32_t KB = min(K, blockDim.x), wpb = blockDim.x / KB;
+  const uint32_t wl = threadIdx.x / KB, kk = threadIdx.x - wl * KB;
+  const uint32_t w = blockIdx.x * wpb + wl;
+  const bool on = wl < wpb && w < n.Jw;
+  const uint64_t word0 = on ? n.rec_bits[(size_t)(t - d) * n.Jw + w] : 0ull;
+  const int64_t r_new = (int64_t)t - 1 - d;
+  for (uint64_t word = word0; word;) {
+    const uint32_t j = w * 64 + (uint32_t)(__ffsll((unsigned long long)word) - 1);
+    word &= word - 1ull;
+    const uint32_t rd0 = o.r_done[j], zl0 = o.zlast[j];
+    const double zb0 = o.zbo[j];
+    for (uint32_t k = kk; k < K; k += KB) {
+      uint32_t zl = zl0;
+      double zb = zb0, g = 0.0;
+      online_out_walk(n, o, j, (int64_t)rd0 + 1, r_new, zl, zb, k, &g);
+      n.w_out[(size_t)k * n.Jp + j] = (real)((double)n.w_out[(size_t)k * n.Jp + j] - o.eta * g);
+    }
+  }
+  __syncthreads();
+  if (kk != 0) return;
+  for (uint64_t word = word0; word;) {
+    const uint32_t j = w * 64 + (uint32_t)(__ffsll((unsigned long long)word) - 1);
+    word &= word - 1ull;
+    const uint32_t rd0 = o.r_done[j];
+    uint32_t zl = o.zlast[j];
+    double zb = o.zbo[j];
+    online_out_walk(n, o, j, (int64_t)rd0 + 1, r_new, zl, zb, 0u, (double *)nullptr);
+    o.zbo[j] = zb;
+    o.zlast[j] = zl;
+    if (r_new > (int64_t)rd0) o.r_done[j] = (uint32_t)r_new;
+  }
+}
+
+// Readout state, error signal and loss of step t (one block), after
+// k_online_out_syn has updated the readout weights.
 template <typename real>
 __global__ __launch_bounds__(256) void k_online_readout(DevNet<real> n, OnlineRun<real> o, uint32_t t) {
   const uint32_t tid = threadIdx.x, K = n.K, d = n.d_out;
   __shared__ double red[256];
   __shared__ uint32_t smp;
-  if (t > d) {
-    const uint64_t *row = n.rec_bits + (size_t)(t - d) * n.Jw;
-    for (uint32_t w = tid; w < n.Jw; w += blockDim.x) {
-      uint64_t word = row[w];
-      while (word) {
-        const uint32_t j = w * 64 + (uint32_t)(__ffsll((unsigned long long)word) - 1);
-        word &= word - 1ull;
-        const int64_t r_new = (int64_t)t - 1 - d;
-        const uint32_t rd0 = o.r_done[j], zl0 = o.zlast[j];
-        const double zb0 = o.zbo[j];
-        uint32_t zl = zl0;
-        double zb = zb0;
-        for (uint32_t k = 0; k < K; ++k) {
-          zl = zl0;
-          zb = zb0;
-          double g = 0.0;
-          for (int64_t r = (int64_t)rd0 + 1; r <= r_new; ++r) {
-            const bool x = (n.rec_bits[(size_t)r * n.Jw + (j >> 6)] >> (j & 63u)) & 1ull;
-            if (x) zl = (uint32_t)r;
-            if (o.cutoff && (zl == 0 || (uint64_t)(r - zl) >= o.cutoff)) {
-              zb = 0.0;
-              continue;
-            }
-            zb = n.kappa_d * zb + (x ? 1.0 : 0.0);
-            g += o.Eh[(size_t)(r + d) * K + k] * zb;
-          }
-          n.w_out[(size_t)k * n.Jp + j] = (real)((double)n.w_out[(size_t)k * n.Jp + j] - o.eta * g);
-        }
-        o.zbo[j] = zb;
-        o.zlast[j] = zl;
-        if (r_new > (int64_t)rd0) o.r_done[j] = (uint32_t)r_new;
-      }
-    }
-  }
   if (tid == 0) {
     uint32_t lo = 0, hi = o.n_samples;  // sample c with off[c] < t <= off[c + 1]
     while (hi - lo > 1) {
@@ -2707,6 +2736,8 @@ void Launch<real>::online_step(const DevNet<real> &n, const OnlineRun<real> &o, 
   const uint32_t blocks = n.Jp / 256 + (n.Jp % 256 ? 1 : 0);
   if (forced) k_online_neuron<real, true><<<blocks, 256, 0, s>>>(n, o, t);
   else k_online_neuron<real, false><<<blocks, 256, 0, s>>>(n, o, t);
+  const uint32_t KB = n.K < 256 ? n.K : 256;
+  k_online_out_syn<real><<<(n.Jw + 256 / KB - 1) / (256 / KB), 256, 0, s>>>(n, o, t);
   k_online_readout<real><<<1, 256, 0, s>>>(n, o, t);
   k_online_learn<real><<<(n.J + 255) / 256, 256, 0, s>>>(n, o, t);
 }
