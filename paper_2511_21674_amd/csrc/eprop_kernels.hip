@@ -785,8 +785,11 @@ __device__ inline void queue_spikes(const DevNet<float> &n, uint32_t b, uint32_t
 // state stay in LDS for the whole launch.  Per step: neuron update of the
 // tile, spike publication (bitset, spike times, the tile's tagged spike list
 // and count), then delivery of all tiles' spikes of the step into the
-// tile's ring, reading each tile's list as soon as its tag shows up.  The
-// KT workgroups of a trial must be resident together (checked on the host).
+// tile's ring, reading each tile's list as soon as its tag shows up.  With
+// the queue variant (Q) the tile instead copies its spikes' synapses, and
+// its share of the input spikes', into the per-tile queues, then drains its
+// own queues.  The KT workgroups of a trial must be resident together
+// (checked on the host).
 template <typename real, typename ring_t, bool FORCED, uint32_t VAR>
 __global__ __launch_bounds__(1024) void k_forward_tiled(DevNet<real> n, uint32_t nsteps, uint32_t b0) {
   constexpr uint32_t P = fwd_piece(VAR), U = fwd_unroll(VAR), RPT = fwd_rpt(VAR);
