@@ -34,6 +34,21 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_header_constants_match_the_binding():
+    """Every #define EPROP_* with an integer value in include/eprop.h equals
+    the binding's constant of the same name."""
+    src = open(os.path.join(ROOT, "include", "eprop.h")).read()
+    found = 0
+    for name, val in re.findall(r"#define\s+(EPROP_[A-Z0-9_]+)\s+\(?([0-9]+u?(?:\s*<<\s*[0-9]+)?)\)?", src):
+        if not hasattr(E, name):
+            continue
+        parts = [int(x) for x in val.replace("u", "").split("<<")]  # a literal, or a literal shifted
+        expect = parts[0] << parts[1] if len(parts) == 2 else parts[0]
+        assert getattr(E, name) == expect, (name, getattr(E, name), expect)
+        found += 1
+    assert found >= 6, found
+
+
 def test_status_strings():
     assert E.eprop_status_string(E.EPROP_OK) == "ok"
     assert "invalid" in E.eprop_status_string(E.EPROP_ERR_INVALID_ARGUMENT)
@@ -78,6 +93,10 @@ def test_config_rejects_bad_delays_regulariser_and_short_history():
     assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_UNSUPPORTED
     cfg, projs, wo, fb, keep = _parts(W.tiny().network, flags=1 << 7)
     assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
+    # the two scatter forms exclude each other
+    cfg, projs, wo, fb, keep = _parts(W.tiny().network, flags=E.EPROP_SCATTER_LOOKUP | E.EPROP_SCATTER_QUEUES)
+    st, msg = _create(cfg, projs, wo, fb)
+    assert st == E.EPROP_ERR_INVALID_ARGUMENT and "exclude" in msg, msg
     cfg, projs, wo, fb, keep = _parts(W.tiny().network, precision=E.EPROP_FP64, delivery=1,
                                       flags=E.EPROP_DETERMINISTIC)
     assert _create(cfg, projs, wo, fb)[0] == E.EPROP_ERR_INVALID_ARGUMENT
